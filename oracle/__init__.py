@@ -1,0 +1,225 @@
+"""FP64 CPU oracle for the normal bake -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may import
+this package.  The GPU library never links or calls it, and it imports nothing
+from the GPU package: the two share no code.
+
+The arithmetic lives in ``oracle.c`` (plain C, FP64, OpenMP over rays); this
+module only marshals numpy arrays and chains the steps in the order of the
+paper's bake (Sec. 6.4 "Normal Map Baking"):
+
+1. low-poly smooth vertex normals and per-face tangent frames / reliability;
+2. UV-space rasterisation of the low-poly (texel -> face, barycentrics);
+3. per texel a world position p and the interpolated smooth normal d;
+4. nearest |t| line hit on the high-poly within +-max_dist (brute force over
+   every triangle, or the independent FP64 BVH pinned against it);
+5. barycentric high-poly normal, projection into the tangent frame, neutral
+   (0,0,1) for misses / unreliable / uncovered texels;
+6. chart dilation.
+
+Parity unpinned: none of the paper's own quality numbers (its 50-asset
+benchmark) can be reproduced here; every other function has a pin in
+``tests/test_oracle.py``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import sysconfig
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+ST_MISS, ST_UNREL, ST_UNCOV = -1, -2, -3
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc (FP64, no fast-math, no FP contraction)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+               "-shared", "-Wall", "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        _lib = C.CDLL(_LIB_PATH)
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def set_threads(n: int = 0) -> int:
+    lib = _load()
+    lib.orc_set_threads.restype = C.c_int
+    return lib.orc_set_threads(C.c_int(n))
+
+
+def _call(name, *args):
+    lib = _load()
+    fn = getattr(lib, name)
+    fn.restype = C.c_int
+    rc = fn(*args)
+    if rc != 0:
+        raise ValueError(f"oracle {name} failed ({rc})")
+
+
+def lo_normals(V, F):
+    V = _c(V, np.float32); F = _c(F, np.int32)
+    n = np.zeros((V.shape[0], 3)); ok = np.zeros(V.shape[0], np.uint8)
+    _call("orc_lo_normals", _p(V), C.c_int64(V.shape[0]), _p(F), C.c_int64(F.shape[0]), _p(n), _p(ok))
+    return n, ok.astype(bool)
+
+
+def face_frames(V, F, UV, res, vn_valid=None):
+    V = _c(V, np.float32); F = _c(F, np.int32); UV = _c(UV, np.float32)
+    nf = F.shape[0]
+    T = np.zeros((nf, 3)); B = np.zeros((nf, 3)); h = np.zeros(nf, np.int8); rel = np.zeros(nf, np.uint8)
+    vv = None if vn_valid is None else _c(vn_valid, np.uint8)
+    _call("orc_face_frames", _p(V), C.c_int64(V.shape[0]), _p(F), C.c_int64(nf), _p(UV),
+          C.c_int32(res), _p(vv), _p(T), _p(B), _p(h), _p(rel))
+    return T, B, h, rel.astype(bool)
+
+
+def raster(UV, res):
+    UV = _c(UV, np.float32)
+    face = np.zeros(res * res, np.int32); bary = np.zeros((res * res, 3))
+    _call("orc_raster", _p(UV), C.c_int64(UV.shape[0]), C.c_int32(res), _p(face), _p(bary))
+    return face, bary
+
+
+def rays(V, F, vn, face, bary):
+    V = _c(V, np.float32); F = _c(F, np.int32); vn = _c(vn, np.float64)
+    face = _c(face, np.int32); bary = _c(bary, np.float64)
+    n = face.shape[0]
+    P = np.zeros((n, 3)); D = np.zeros((n, 3)); ok = np.zeros(n, np.uint8)
+    _call("orc_rays", _p(V), _p(F), _p(vn), C.c_int64(n), _p(face), _p(bary), _p(P), _p(D), _p(ok))
+    return P, D, ok.astype(bool)
+
+
+def query(hi_V, hi_F, P, D, max_dist, active=None, method="brute"):
+    """Nearest-|t| two-sided line hit: (id [-1 miss], t, beta[3])."""
+    hi_V = _c(hi_V, np.float32); hi_F = _c(hi_F, np.int32)
+    P = _c(P, np.float64); D = _c(D, np.float64)
+    n = P.shape[0]
+    ids = np.zeros(n, np.int32); t = np.zeros(n); beta = np.zeros((n, 3))
+    act = None if active is None else _c(active, np.uint8)
+    if method == "brute":
+        _call("orc_query_brute", _p(hi_V), _p(hi_F), C.c_int64(hi_F.shape[0]), C.c_int64(n), _p(P),
+              _p(D), _p(act), C.c_double(max_dist), _p(ids), _p(t), _p(beta))
+    elif method == "bvh":
+        _call("orc_query_bvh", _p(hi_V), C.c_int64(hi_V.shape[0]), _p(hi_F), C.c_int64(hi_F.shape[0]),
+              C.c_int64(n), _p(P), _p(D), _p(act), C.c_double(max_dist), _p(ids), _p(t), _p(beta))
+    else:
+        raise ValueError(method)
+    return ids, t, beta
+
+
+def frame_ok(lo_face, D, Tf):
+    lo_face = _c(lo_face, np.int32); D = _c(D, np.float64); Tf = _c(Tf, np.float64)
+    ok = np.zeros(lo_face.shape[0], np.uint8)
+    _call("orc_frame_ok", C.c_int64(lo_face.shape[0]), _p(lo_face), _p(D), _p(Tf), _p(ok))
+    return ok.astype(bool)
+
+
+def encode(hi_F, hi_N, lo_face, D, Tf, hf, beta, status):
+    hi_F = _c(hi_F, np.int32); hi_N = _c(hi_N, np.float32); lo_face = _c(lo_face, np.int32)
+    D = _c(D, np.float64); Tf = _c(Tf, np.float64); hf = _c(hf, np.int8); beta = _c(beta, np.float64)
+    st = _c(status, np.int32).copy()
+    n = lo_face.shape[0]
+    out = np.zeros((n, 3))
+    _call("orc_encode", _p(hi_F), _p(hi_N), C.c_int64(n), _p(lo_face), _p(D), _p(Tf), _p(hf),
+          _p(beta), _p(st), _p(out))
+    return out, st
+
+
+def dilate(map_flat, level, res, passes):
+    m = _c(map_flat, np.float64).copy(); lv = _c(level, np.uint8).copy()
+    _call("orc_dilate", _p(m), _p(lv), C.c_int32(res), C.c_int32(passes))
+    return m, lv
+
+
+def plane_check(hi_V, hi_F, P, D, g):
+    hi_V = _c(hi_V, np.float32); hi_F = _c(hi_F, np.int32)
+    P = _c(P, np.float64); D = _c(D, np.float64); g = _c(g, np.int32)
+    n = g.shape[0]
+    t = np.zeros(n); dl = np.zeros(n)
+    _call("orc_plane_check", _p(hi_V), _p(hi_F), C.c_int64(n), _p(P), _p(D), _p(g), _p(t), _p(dl))
+    return t, dl
+
+
+@dataclass
+class Bake:
+    """Result of an oracle bake; per-texel arrays are flat [res*res(,3)]."""
+    res: int
+    max_dist: float
+    face: np.ndarray        # covering lo face or -1
+    bary: np.ndarray        # [res*res, 3]
+    texels: np.ndarray      # the texels that were baked (covered, possibly sampled)
+    P: np.ndarray           # [n, 3] ray origins for `texels`
+    D: np.ndarray           # [n, 3] ray directions
+    hit: np.ndarray         # [n] query result before encoding (-1 miss), -2 if not traced
+    t: np.ndarray           # [n]
+    beta: np.ndarray        # [n, 3]
+    status: np.ndarray      # [res*res] final status (-3 uncovered; sampled runs: -4 not baked)
+    map_raw: np.ndarray     # [res*res, 3] before dilation
+    map: np.ndarray         # [res*res, 3] after dilation
+    level: np.ndarray       # [res*res] dilation level (0 covered, k filled in pass k, 255 empty)
+
+
+def bake(asset, method="brute", texels=None, dilate_passes=2) -> Bake:
+    """Oracle bake of a whole asset (or of a subset of covered texels)."""
+    hi_V, hi_F, hi_N, lo_V, lo_F, lo_UV = asset.arrays()
+    res, md = int(asset.res), float(asset.max_dist)
+    vn, vn_ok = lo_normals(lo_V, lo_F)
+    Tf, _, hf, rel = face_frames(lo_V, lo_F, lo_UV, res, vn_ok)
+    face, bary = raster(lo_UV, res)
+    covered = np.nonzero(face >= 0)[0]
+    full = texels is None
+    tex = covered if full else np.asarray(texels, dtype=np.int64)
+    if not full and np.any(face[tex] < 0):
+        raise ValueError("sampled texels must be covered")
+    lf = face[tex]
+    P, D, mok = rays(lo_V, lo_F, vn, lf, bary[tex])
+    fok = frame_ok(lf, D, Tf)
+    active = rel[lf] & mok & fok
+    ids, t, beta = query(hi_V, hi_F, P, D, md, active=active, method=method)
+    st = np.where(active, ids, ST_UNREL).astype(np.int32)
+    out, st = encode(hi_F, hi_N, lf, D, Tf, hf, beta, st)
+    ntex = res * res
+    status = np.full(ntex, ST_UNCOV if full else -4, np.int32)
+    status[face < 0] = ST_UNCOV
+    status[tex] = st
+    map_raw = np.zeros((ntex, 3)); map_raw[:, 2] = 1.0
+    map_raw[tex] = out
+    hit = np.where(active, ids, ST_UNREL).astype(np.int32)
+    if full:
+        level = np.where(face >= 0, 0, 255).astype(np.uint8)
+        m, level = dilate(map_raw, level, res, dilate_passes)
+    else:
+        m, level = map_raw.copy(), np.where(face >= 0, 0, 255).astype(np.uint8)
+    return Bake(res, md, face, bary, tex, P, D, hit, t, beta, status, map_raw, m, level)
+
+
+def rgb8(map_flat):
+    """RGB8 encoding c = clamp(floor((x + 1) * 127.5 + 0.5), 0, 255)."""
+    c = np.floor((np.asarray(map_flat, np.float64) + 1.0) * 127.5 + 0.5)
+    return np.clip(c, 0, 255).astype(np.uint8)

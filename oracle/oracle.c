@@ -1,0 +1,583 @@
+/*
+ * FP64 CPU oracle for tangent-space normal baking.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the tests, the smoke check and the benchmark's CPU
+ * baseline do.  It shares no source, header, table or helper with the GPU
+ * library.
+ *
+ * What it computes follows the paper's bake (Sec. 6.4 "Normal Map Baking"):
+ * rasterise the low-poly into its own UV space to get, per valid texel, a
+ * world position, a smooth normal and a tangent frame; find the corresponding
+ * point on the high-poly; interpolate the high-poly smooth normal there with the
+ * hit's barycentric weights; reject far or unreliable correspondences with the
+ * neutral normal (0,0,1); project the hit normal into the texel's tangent frame;
+ * dilate at chart borders.  The correspondence query is a two-sided ray cast
+ * along the interpolated low-poly normal, nearest |t| within +-max_dist, ties to
+ * the lower triangle index (the paper's closest-point query is a different
+ * variant of the same step).
+ *
+ * Everything is plain: brute force over every texel and every triangle,
+ * FP64 arithmetic, no blocking or reordering beyond what the definitions say.
+ * A separate, equally plain FP64 BVH (median split) answers the same query and
+ * is pinned against the brute force.
+ *
+ * Conventions (readings where the paper is silent):
+ *   texel (i, j): centre u = (j + 1/2)/res, v = (i + 1/2)/res, row-major [i][j];
+ *   coverage: corners snapped to 1/256 texel, X = rint(u*res*256); integer edge
+ *     functions at the centre (256j+128, 256i+128); inside iff all >= 0 or all
+ *     <= 0 and their sum != 0; the lowest face index wins an overlap;
+ *   low-poly vertex normal: normalised sum of unnormalised incident face cross
+ *     products (area weighted);
+ *   tangent frame from the snapped UV deltas; per texel Gram-Schmidt against the
+ *     interpolated normal; bitangent = h_f * (d x T');
+ *   status: >= 0 hit id, -1 miss, -2 unreliable, -3 uncovered.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+#define ORC_OK 0
+#define ORC_EINVAL -1
+
+#define ST_MISS -1
+#define ST_UNREL -2
+#define ST_UNCOV -3
+
+typedef struct { double x, y, z; } v3;
+
+static v3 mk(double x, double y, double z) { v3 r = {x, y, z}; return r; }
+static v3 sub(v3 a, v3 b) { return mk(a.x - b.x, a.y - b.y, a.z - b.z); }
+static v3 add(v3 a, v3 b) { return mk(a.x + b.x, a.y + b.y, a.z + b.z); }
+static v3 scl(v3 a, double s) { return mk(a.x * s, a.y * s, a.z * s); }
+static double dot(v3 a, v3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+static v3 cross(v3 a, v3 b) {
+    return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+static double norm(v3 a) { return sqrt(dot(a, a)); }
+static v3 ld3f(const float *p, int64_t i) { return mk(p[3 * i], p[3 * i + 1], p[3 * i + 2]); }
+static v3 ld3d(const double *p, int64_t i) { return mk(p[3 * i], p[3 * i + 1], p[3 * i + 2]); }
+static void st3d(double *p, int64_t i, v3 a) { p[3 * i] = a.x; p[3 * i + 1] = a.y; p[3 * i + 2] = a.z; }
+
+static int64_t floordiv(int64_t a, int64_t b) {  /* b > 0 */
+    int64_t q = a / b;
+    if ((a % b) != 0 && a < 0) q -= 1;
+    return q;
+}
+
+int orc_set_threads(int n) {
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+}
+
+/* ------------------------------------------------------------------------ */
+/* Low-poly smooth normals (G-buffer "smooth normal", Sec. 6.4)              */
+/* ------------------------------------------------------------------------ */
+
+/* n_v = normalise(sum over faces containing v of (V1-V0) x (V2-V0)).
+ * Writes the normalised normal and a validity flag (0 where the sum is 0). */
+int orc_lo_normals(const float *V, int64_t nv, const int32_t *F, int64_t nf,
+                   double *n_out, uint8_t *valid_out) {
+    if (!V || !F || !n_out || nv < 0 || nf < 0) return ORC_EINVAL;
+    double *acc = (double *)calloc((size_t)(3 * (nv > 0 ? nv : 1)), sizeof(double));
+    for (int64_t f = 0; f < nf; ++f) {
+        int32_t a = F[3 * f], b = F[3 * f + 1], c = F[3 * f + 2];
+        if (a < 0 || b < 0 || c < 0 || a >= nv || b >= nv || c >= nv) { free(acc); return ORC_EINVAL; }
+        v3 A = ld3f(V, a), B = ld3f(V, b), C = ld3f(V, c);
+        v3 cr = cross(sub(B, A), sub(C, A));
+        int32_t id[3] = {a, b, c};
+        for (int k = 0; k < 3; ++k) st3d(acc, id[k], add(ld3d(acc, id[k]), cr));
+    }
+    for (int64_t v = 0; v < nv; ++v) {
+        v3 s = ld3d(acc, v);
+        double l = norm(s);
+        if (l > 0) { st3d(n_out, v, scl(s, 1.0 / l)); if (valid_out) valid_out[v] = 1; }
+        else { st3d(n_out, v, mk(0, 0, 0)); if (valid_out) valid_out[v] = 0; }
+    }
+    free(acc);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Per-face tangent frame and UV reliability (Sec. 6.4: tangent/bitangent in */
+/* the G-buffer; UV-reliability filter)                                      */
+/* ------------------------------------------------------------------------ */
+
+static void snap(const float *UV, int64_t f, int k, int32_t res, int64_t *X, int64_t *Y) {
+    double s = (double)res * 256.0;
+    *X = (int64_t)nearbyint((double)UV[6 * f + 2 * k] * s);
+    *Y = (int64_t)nearbyint((double)UV[6 * f + 2 * k + 1] * s);
+}
+
+/* T_f = sgn(det) (e1 dv2 - e2 dv1), B_f = sgn(det) (e2 du1 - e1 du2) with the
+ * snapped integer UV deltas (du, dv) and 3D edges e1 = V1-V0, e2 = V2-V0;
+ * h_f = -1 if ((e1 x e2) x T_f) . B_f < 0 else +1.
+ * reliable = det != 0, e1 x e2 != 0 and all three vertex normals defined. */
+int orc_face_frames(const float *V, int64_t nv, const int32_t *F, int64_t nf,
+                    const float *UV, int32_t res, const uint8_t *vn_valid,
+                    double *T_out, double *B_out, int8_t *h_out, uint8_t *reliable_out) {
+    if (!V || !F || !UV || nv < 0 || nf < 0 || res <= 0) return ORC_EINVAL;
+    for (int64_t f = 0; f < nf; ++f) {
+        int64_t X[3], Y[3];
+        for (int k = 0; k < 3; ++k) snap(UV, f, k, res, &X[k], &Y[k]);
+        int64_t du1 = X[1] - X[0], dv1 = Y[1] - Y[0], du2 = X[2] - X[0], dv2 = Y[2] - Y[0];
+        int64_t det = du1 * dv2 - du2 * dv1;
+        double sg = det > 0 ? 1.0 : (det < 0 ? -1.0 : 0.0);
+        v3 A = ld3f(V, F[3 * f]), B = ld3f(V, F[3 * f + 1]), C = ld3f(V, F[3 * f + 2]);
+        v3 e1 = sub(B, A), e2 = sub(C, A);
+        v3 T = scl(sub(scl(e1, (double)dv2), scl(e2, (double)dv1)), sg);
+        v3 Bt = scl(sub(scl(e2, (double)du1), scl(e1, (double)du2)), sg);
+        v3 n = cross(e1, e2);
+        double hs = dot(cross(n, T), Bt);
+        int ok = det != 0 && (n.x != 0 || n.y != 0 || n.z != 0);
+        if (vn_valid) ok = ok && vn_valid[F[3 * f]] && vn_valid[F[3 * f + 1]] && vn_valid[F[3 * f + 2]];
+        if (T_out) st3d(T_out, f, T);
+        if (B_out) st3d(B_out, f, Bt);
+        if (h_out) h_out[f] = hs < 0 ? -1 : 1;
+        if (reliable_out) reliable_out[f] = (uint8_t)ok;
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* UV-space rasterisation (G-buffer, Sec. 6.4)                               */
+/* ------------------------------------------------------------------------ */
+
+/* face_out[res*res]: covering face or -1; bary_out[res*res*3]: E_k / sum E.
+ * Faces are visited in ascending order and a texel keeps its first cover, so
+ * the lowest face index wins an overlap. */
+int orc_raster(const float *UV, int64_t nf, int32_t res, int32_t *face_out, double *bary_out) {
+    if (!UV || !face_out || nf < 0 || res <= 0) return ORC_EINVAL;
+    int64_t ntex = (int64_t)res * res;
+    for (int64_t t = 0; t < ntex; ++t) {
+        face_out[t] = -1;
+        if (bary_out) { bary_out[3 * t] = bary_out[3 * t + 1] = bary_out[3 * t + 2] = 0; }
+    }
+    for (int64_t f = 0; f < nf; ++f) {
+        int64_t X[3], Y[3];
+        for (int k = 0; k < 3; ++k) snap(UV, f, k, res, &X[k], &Y[k]);
+        int64_t xmin = X[0], xmax = X[0], ymin = Y[0], ymax = Y[0];
+        for (int k = 1; k < 3; ++k) {
+            if (X[k] < xmin) xmin = X[k];
+            if (X[k] > xmax) xmax = X[k];
+            if (Y[k] < ymin) ymin = Y[k];
+            if (Y[k] > ymax) ymax = Y[k];
+        }
+        /* texel centres 256 j + 128 within [xmin, xmax] */
+        int64_t j0 = floordiv(xmin - 128 + 255, 256), j1 = floordiv(xmax - 128, 256);
+        int64_t i0 = floordiv(ymin - 128 + 255, 256), i1 = floordiv(ymax - 128, 256);
+        if (j0 < 0) j0 = 0;
+        if (i0 < 0) i0 = 0;
+        if (j1 > res - 1) j1 = res - 1;
+        if (i1 > res - 1) i1 = res - 1;
+        for (int64_t i = i0; i <= i1; ++i) {
+            for (int64_t j = j0; j <= j1; ++j) {
+                int64_t cx = 256 * j + 128, cy = 256 * i + 128;
+                /* E_k: edge function of the edge opposite corner k */
+                int64_t E0 = (X[2] - X[1]) * (cy - Y[1]) - (Y[2] - Y[1]) * (cx - X[1]);
+                int64_t E1 = (X[0] - X[2]) * (cy - Y[2]) - (Y[0] - Y[2]) * (cx - X[2]);
+                int64_t E2 = (X[1] - X[0]) * (cy - Y[0]) - (Y[1] - Y[0]) * (cx - X[0]);
+                int64_t S = E0 + E1 + E2;
+                int in = (E0 >= 0 && E1 >= 0 && E2 >= 0) || (E0 <= 0 && E1 <= 0 && E2 <= 0);
+                if (!in || S == 0) continue;
+                int64_t t = i * res + j;
+                if (face_out[t] >= 0) continue;
+                face_out[t] = (int32_t)f;
+                if (bary_out) {
+                    bary_out[3 * t] = (double)E0 / (double)S;
+                    bary_out[3 * t + 1] = (double)E1 / (double)S;
+                    bary_out[3 * t + 2] = (double)E2 / (double)S;
+                }
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Rays: world position and interpolated smooth normal per covered texel     */
+/* ------------------------------------------------------------------------ */
+
+/* For texel list (face, b0, b1, b2): p = sum b_k V_k, m = sum b_k n_k,
+ * d = m / |m|.  ok_out = 0 where |m| = 0. */
+int orc_rays(const float *V, const int32_t *F, const double *vn, int64_t n,
+             const int32_t *face, const double *bary, double *p_out, double *d_out, uint8_t *ok_out) {
+    for (int64_t r = 0; r < n; ++r) {
+        int32_t f = face[r];
+        v3 p = mk(0, 0, 0), m = mk(0, 0, 0);
+        for (int k = 0; k < 3; ++k) {
+            int32_t v = F[3 * f + k];
+            double b = bary[3 * r + k];
+            p = add(p, scl(ld3f(V, v), b));
+            m = add(m, scl(ld3d(vn, v), b));
+        }
+        double l = norm(m);
+        st3d(p_out, r, p);
+        if (l > 0) { st3d(d_out, r, scl(m, 1.0 / l)); ok_out[r] = 1; }
+        else { st3d(d_out, r, mk(0, 0, 0)); ok_out[r] = 0; }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* High-poly correspondence: two-sided line / triangle test                 */
+/* ------------------------------------------------------------------------ */
+
+/* Signed volume s(a,b) = d . ((a-p) x (b-p)), always evaluated with the lower
+ * vertex index first and negated for the reversed direction, so two faces that
+ * share an edge see exactly opposite values (watertight in FP64). */
+static double svol(v3 p, v3 d, const float *V, int32_t ia, int32_t ib) {
+    if (ia <= ib) return dot(d, cross(sub(ld3f(V, ia), p), sub(ld3f(V, ib), p)));
+    return -dot(d, cross(sub(ld3f(V, ib), p), sub(ld3f(V, ia), p)));
+}
+
+/* Line p + t d against triangle g.  Hit iff the three volumes share a sign
+ * (zeros allowed) and are not all zero.  beta = (s_bc, s_ca, s_ab) / sum,
+ * q = sum beta_k v_k, t = (q - p) . d.  Returns 1 on a hit. */
+static int tri_hit(v3 p, v3 d, const float *V, const int32_t *F, int64_t g, double *t, double beta[3]) {
+    int32_t a = F[3 * g], b = F[3 * g + 1], c = F[3 * g + 2];
+    double s0 = svol(p, d, V, b, c), s1 = svol(p, d, V, c, a), s2 = svol(p, d, V, a, b);
+    int pos = s0 >= 0 && s1 >= 0 && s2 >= 0;
+    int neg = s0 <= 0 && s1 <= 0 && s2 <= 0;
+    if (!(pos || neg)) return 0;
+    double S = s0 + s1 + s2;
+    if (S == 0) return 0;
+    beta[0] = s0 / S; beta[1] = s1 / S; beta[2] = s2 / S;
+    v3 q = add(add(scl(ld3f(V, a), beta[0]), scl(ld3f(V, b), beta[1])), scl(ld3f(V, c), beta[2]));
+    *t = dot(sub(q, p), d);
+    return 1;
+}
+
+/* (|t|, g) lexicographic order: is (ta, ga) better than (tb, gb)? */
+static int better(double ta, int64_t ga, double tb, int64_t gb) {
+    double a = fabs(ta), b = fabs(tb);
+    return a < b || (a == b && ga < gb);
+}
+
+/* Brute force over every triangle in ascending index order. */
+int orc_query_brute(const float *V, const int32_t *F, int64_t nf, int64_t n, const double *P,
+                    const double *D, const uint8_t *active, double max_dist,
+                    int32_t *id_out, double *t_out, double *beta_out) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < n; ++r) {
+        int32_t best = -1;
+        double bt = 0, bb[3] = {0, 0, 0};
+        if (!active || active[r]) {
+            v3 p = ld3d(P, r), d = ld3d(D, r);
+            for (int64_t g = 0; g < nf; ++g) {
+                double t, beta[3];
+                if (!tri_hit(p, d, V, F, g, &t, beta)) continue;
+                if (fabs(t) > max_dist) continue;
+                if (best < 0 || better(t, g, bt, best)) {
+                    best = (int32_t)g; bt = t; bb[0] = beta[0]; bb[1] = beta[1]; bb[2] = beta[2];
+                }
+            }
+        }
+        id_out[r] = best;
+        if (t_out) t_out[r] = best >= 0 ? bt : 0;
+        if (beta_out) { beta_out[3 * r] = bb[0]; beta_out[3 * r + 1] = bb[1]; beta_out[3 * r + 2] = bb[2]; }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Independent FP64 BVH (median split on the longest centroid axis)          */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double lo[3], hi[3];
+    int64_t left, right;   /* children, or -1 for a leaf */
+    int64_t first, count;  /* triangle range in perm for a leaf */
+} bnode;
+
+typedef struct {
+    bnode *nodes;
+    int64_t nnodes;
+    int64_t *perm;
+} bvh;
+
+static double *g_cent; /* centroid array used by the comparator below */
+static int g_axis;
+static int cmp_cent(const void *a, const void *b) {
+    int64_t ia = *(const int64_t *)a, ib = *(const int64_t *)b;
+    double ca = g_cent[3 * ia + g_axis], cb = g_cent[3 * ib + g_axis];
+    if (ca < cb) return -1;
+    if (ca > cb) return 1;
+    return ia < ib ? -1 : (ia > ib ? 1 : 0);
+}
+
+static int64_t build_rec(bvh *B, const float *V, const int32_t *F, double *cent,
+                         int64_t first, int64_t count) {
+    int64_t me = B->nnodes++;
+    bnode *nd = &B->nodes[me];
+    for (int k = 0; k < 3; ++k) { nd->lo[k] = INFINITY; nd->hi[k] = -INFINITY; }
+    double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = first; i < first + count; ++i) {
+        int64_t g = B->perm[i];
+        for (int c = 0; c < 3; ++c) {
+            int32_t v = F[3 * g + c];
+            for (int k = 0; k < 3; ++k) {
+                double x = V[3 * v + k];
+                if (x < nd->lo[k]) nd->lo[k] = x;
+                if (x > nd->hi[k]) nd->hi[k] = x;
+            }
+        }
+        for (int k = 0; k < 3; ++k) {
+            double x = cent[3 * g + k];
+            if (x < clo[k]) clo[k] = x;
+            if (x > chi[k]) chi[k] = x;
+        }
+    }
+    /* pad outward so the box test can never reject a triangle the exact
+     * triangle test would accept */
+    for (int k = 0; k < 3; ++k) {
+        double pad = 1e-9 * (1.0 + fabs(nd->lo[k]) + fabs(nd->hi[k]));
+        nd->lo[k] -= pad;
+        nd->hi[k] += pad;
+    }
+    if (count <= 4) {
+        nd->left = nd->right = -1;
+        nd->first = first;
+        nd->count = count;
+        return me;
+    }
+    int axis = 0;
+    double ext = chi[0] - clo[0];
+    for (int k = 1; k < 3; ++k) if (chi[k] - clo[k] > ext) { ext = chi[k] - clo[k]; axis = k; }
+    g_cent = cent;
+    g_axis = axis;
+    qsort(B->perm + first, (size_t)count, sizeof(int64_t), cmp_cent);
+    int64_t half = count / 2;
+    int64_t l = build_rec(B, V, F, cent, first, half);
+    int64_t r = build_rec(B, V, F, cent, first + half, count - half);
+    nd = &B->nodes[me];
+    nd->left = l;
+    nd->right = r;
+    nd->first = nd->count = 0;
+    return me;
+}
+
+/* Interval of line parameters t for which p + t d lies in the box, widened
+ * outward by a relative 1e-12.  Returns 0 if empty. */
+static int box_interval(const bnode *nd, v3 p, v3 d, double *t0, double *t1) {
+    double lo = -INFINITY, hi = INFINITY;
+    double pp[3] = {p.x, p.y, p.z}, dd[3] = {d.x, d.y, d.z};
+    for (int k = 0; k < 3; ++k) {
+        if (dd[k] == 0) {
+            if (pp[k] < nd->lo[k] || pp[k] > nd->hi[k]) return 0;
+            continue;
+        }
+        double a = (nd->lo[k] - pp[k]) / dd[k], b = (nd->hi[k] - pp[k]) / dd[k];
+        double mn = a < b ? a : b, mx = a < b ? b : a;
+        mn -= 1e-12 * fabs(mn);
+        mx += 1e-12 * fabs(mx);
+        if (mn > lo) lo = mn;
+        if (mx < hi) hi = mx;
+    }
+    if (lo > hi) return 0;
+    *t0 = lo;
+    *t1 = hi;
+    return 1;
+}
+
+static int32_t bvh_query(const bvh *B, const float *V, const int32_t *F, v3 p, v3 d, double max_dist,
+                         double *t_out, double beta_out[3]) {
+    int64_t stack[256];
+    int sp = 0;
+    stack[sp++] = 0;
+    int32_t best = -1;
+    double bt = 0, bound = max_dist;
+    while (sp > 0) {
+        const bnode *nd = &B->nodes[stack[--sp]];
+        double t0, t1;
+        if (!box_interval(nd, p, d, &t0, &t1)) continue;
+        if (t0 > bound || t1 < -bound) continue; /* strict: equal |t| still visited */
+        if (nd->left < 0) {
+            for (int64_t i = nd->first; i < nd->first + nd->count; ++i) {
+                int64_t g = B->perm[i];
+                double t, beta[3];
+                if (!tri_hit(p, d, V, F, g, &t, beta)) continue;
+                if (fabs(t) > max_dist) continue;
+                if (best < 0 || better(t, g, bt, best)) {
+                    best = (int32_t)g; bt = t;
+                    beta_out[0] = beta[0]; beta_out[1] = beta[1]; beta_out[2] = beta[2];
+                    bound = fabs(t);
+                }
+            }
+        } else {
+            if (sp + 2 > 256) return -100; /* cannot happen for median splits of < 2^60 tris */
+            stack[sp++] = nd->right;
+            stack[sp++] = nd->left;
+        }
+    }
+    *t_out = bt;
+    return best;
+}
+
+int orc_query_bvh(const float *V, int64_t nv, const int32_t *F, int64_t nf, int64_t n, const double *P,
+                  const double *D, const uint8_t *active, double max_dist,
+                  int32_t *id_out, double *t_out, double *beta_out) {
+    (void)nv;
+    bvh B;
+    B.nodes = (bnode *)malloc(sizeof(bnode) * (size_t)(2 * (nf > 0 ? nf : 1)));
+    B.perm = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nf > 0 ? nf : 1));
+    B.nnodes = 0;
+    double *cent = (double *)malloc(sizeof(double) * (size_t)(3 * (nf > 0 ? nf : 1)));
+    for (int64_t g = 0; g < nf; ++g) {
+        B.perm[g] = g;
+        for (int k = 0; k < 3; ++k)
+            cent[3 * g + k] = ((double)V[3 * F[3 * g] + k] + V[3 * F[3 * g + 1] + k] + V[3 * F[3 * g + 2] + k]) / 3.0;
+    }
+    int err = 0;
+    if (nf > 0) build_rec(&B, V, F, cent, 0, nf);
+#pragma omp parallel for schedule(dynamic, 64) reduction(| : err)
+    for (int64_t r = 0; r < n; ++r) {
+        double t = 0, beta[3] = {0, 0, 0};
+        int32_t id = -1;
+        if ((!active || active[r]) && nf > 0) {
+            id = bvh_query(&B, V, F, ld3d(P, r), ld3d(D, r), max_dist, &t, beta);
+            if (id == -100) { err = 1; id = -1; }
+        }
+        id_out[r] = id;
+        if (t_out) t_out[r] = id >= 0 ? t : 0;
+        if (beta_out) { beta_out[3 * r] = beta[0]; beta_out[3 * r + 1] = beta[1]; beta_out[3 * r + 2] = beta[2]; }
+    }
+    free(cent);
+    free(B.perm);
+    free(B.nodes);
+    return err ? ORC_EINVAL : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Encoding in the texel's tangent frame (Sec. 6.4)                          */
+/* ------------------------------------------------------------------------ */
+
+/* For each ray with hit id >= 0: h = sum beta_k N_{g_k}; n = h/|h|;
+ * T' = normalise(T_f - (d.T_f) d); B' = h_f (d x T'); out = (n.T', n.B', n.d).
+ * status_io holds the query result on entry (id or -1) and the final status on
+ * exit; rays already marked unreliable (-2) are left as they are.  Non-hits
+ * get (0,0,1). */
+int orc_encode(const int32_t *hiF, const float *hiN, int64_t n, const int32_t *lo_face,
+               const double *D, const double *Tf, const int8_t *hf, const double *beta,
+               int32_t *status_io, double *out) {
+    for (int64_t r = 0; r < n; ++r) {
+        v3 o = mk(0, 0, 1);
+        int32_t st = status_io[r];
+        if (st >= 0) {
+            v3 d = ld3d(D, r);
+            int32_t f = lo_face[r];
+            v3 T = ld3d(Tf, f);
+            v3 Tp = sub(T, scl(d, dot(d, T)));
+            double lt = norm(Tp);
+            v3 h = mk(0, 0, 0);
+            for (int k = 0; k < 3; ++k) h = add(h, scl(ld3f(hiN, hiF[3 * st + k]), beta[3 * r + k]));
+            double lh = norm(h);
+            if (lt == 0 || lh == 0) {
+                st = ST_UNREL;
+            } else {
+                Tp = scl(Tp, 1.0 / lt);
+                v3 nh = scl(h, 1.0 / lh);
+                v3 Bp = scl(cross(d, Tp), (double)hf[f]);
+                o = mk(dot(nh, Tp), dot(nh, Bp), dot(nh, d));
+            }
+        }
+        status_io[r] = st;
+        st3d(out, r, o);
+    }
+    return ORC_OK;
+}
+
+/* Tangent-frame degeneracy alone (T_f parallel to d), checked before the query. */
+int orc_frame_ok(int64_t n, const int32_t *lo_face, const double *D, const double *Tf, uint8_t *ok_out) {
+    for (int64_t r = 0; r < n; ++r) {
+        v3 d = ld3d(D, r), T = ld3d(Tf, lo_face[r]);
+        v3 Tp = sub(T, scl(d, dot(d, T)));
+        ok_out[r] = norm(Tp) > 0;
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Chart dilation (Sec. 6.4: dilated at UV seams against mip bleed)          */
+/* ------------------------------------------------------------------------ */
+
+/* map [res*res*3], level [res*res]: 0 = has a value before dilation, 255 =
+ * empty.  Pass k (1..passes) fills each still-empty texel with the normalised
+ * sum of its 8 neighbours whose level is < k; a texel with no such neighbour or
+ * a zero sum stays empty.  Neighbour order: rows -1,0,+1, columns -1,0,+1. */
+int orc_dilate(double *map, uint8_t *level, int32_t res, int32_t passes) {
+    if (!map || !level || res <= 0 || passes < 0 || passes > 254) return ORC_EINVAL;
+    for (int k = 1; k <= passes; ++k) {
+        for (int64_t i = 0; i < res; ++i) {
+            for (int64_t j = 0; j < res; ++j) {
+                int64_t t = i * res + j;
+                if (level[t] != 255) continue;
+                v3 s = mk(0, 0, 0);
+                int cnt = 0;
+                for (int di = -1; di <= 1; ++di)
+                    for (int dj = -1; dj <= 1; ++dj) {
+                        if (di == 0 && dj == 0) continue;
+                        int64_t ii = i + di, jj = j + dj;
+                        if (ii < 0 || jj < 0 || ii >= res || jj >= res) continue;
+                        int64_t u = ii * res + jj;
+                        if (level[u] < k) { s = add(s, ld3d(map, u)); ++cnt; }
+                    }
+                if (cnt == 0) continue;
+                double l = norm(s);
+                if (l == 0) continue;
+                st3d(map, t, scl(s, 1.0 / l));
+                level[t] = (uint8_t)k;
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Comparator support: plane crossing and distance to a given triangle       */
+/* ------------------------------------------------------------------------ */
+
+/* Distance from q to segment [a, b]. */
+static double seg_dist(v3 q, v3 a, v3 b) {
+    v3 ab = sub(b, a);
+    double l2 = dot(ab, ab);
+    double s = l2 > 0 ? dot(sub(q, a), ab) / l2 : 0.0;
+    if (s < 0) s = 0;
+    if (s > 1) s = 1;
+    return norm(sub(q, add(a, scl(ab, s))));
+}
+
+/* Distance from a point q lying in the plane of triangle (a,b,c) to the
+ * triangle: 0 if the three sub-triangle orientations against the face normal
+ * agree (q inside or on the border), else the nearest of the three edges. */
+static double in_plane_dist(v3 q, v3 a, v3 b, v3 c) {
+    v3 n = cross(sub(b, a), sub(c, a));
+    double wa = dot(n, cross(sub(b, q), sub(c, q)));
+    double wb = dot(n, cross(sub(c, q), sub(a, q)));
+    double wc = dot(n, cross(sub(a, q), sub(b, q)));
+    if ((wa >= 0 && wb >= 0 && wc >= 0) || (wa <= 0 && wb <= 0 && wc <= 0)) return 0.0;
+    double d0 = seg_dist(q, a, b), d1 = seg_dist(q, b, c), d2 = seg_dist(q, c, a);
+    double m = d0 < d1 ? d0 : d1;
+    return m < d2 ? m : d2;
+}
+
+/* For each (ray, triangle g): t_g = line parameter where p + t d crosses g's
+ * plane (NaN if parallel or degenerate) and delta_g = distance of that crossing
+ * point from the triangle (0 inside). */
+int orc_plane_check(const float *V, const int32_t *F, int64_t n, const double *P, const double *D,
+                    const int32_t *g, double *t_out, double *delta_out) {
+    for (int64_t r = 0; r < n; ++r) {
+        v3 p = ld3d(P, r), d = ld3d(D, r);
+        v3 a = ld3f(V, F[3 * g[r]]), b = ld3f(V, F[3 * g[r] + 1]), c = ld3f(V, F[3 * g[r] + 2]);
+        v3 nn = cross(sub(b, a), sub(c, a));
+        double den = dot(nn, d);
+        if (den == 0) { t_out[r] = NAN; delta_out[r] = INFINITY; continue; }
+        double t = dot(nn, sub(a, p)) / den;
+        v3 q = add(p, scl(d, t));
+        t_out[r] = t;
+        delta_out[r] = in_plane_dist(q, a, b, c);
+    }
+    return ORC_OK;
+}
