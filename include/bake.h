@@ -1,0 +1,171 @@
+/*
+ * bake.h -- C ABI of the MI355X (gfx950) tangent-space normal baker.
+ *
+ * The operation is the paper's normal-map bake (Sec. 6.4 "Normal Map Baking"):
+ * the low-poly mesh is rasterised into its own UV atlas, giving per covered
+ * texel a world position, an interpolated smooth normal and a tangent frame;
+ * a BVH over the high-poly mesh finds the corresponding high-poly point; the
+ * high-poly smooth normal is interpolated there with barycentric weights,
+ * projected into the texel's tangent frame and written to the map; far or
+ * unreliable correspondences get the neutral normal (0,0,1); finally charts
+ * are dilated so mip filtering does not bleed background into them.
+ *
+ * The correspondence query here is a two-sided ray cast from the texel's world
+ * position along its interpolated low-poly normal: the hit with the smallest
+ * |t| for t in [-max_dist, +max_dist], ties to the lower high-poly triangle
+ * index.  (The paper's variant queries the closest surface point and filters
+ * at 1% of the bounding-box diagonal; `max_dist` takes that filter's role.)
+ *
+ * Conventions shared by every entry point:
+ *   - All array pointers are DEVICE pointers (hipMalloc / torch CUDA tensors),
+ *     contiguous, row-major, owned by the caller.  The library never frees them
+ *     and keeps no reference after the call returns.
+ *   - No hidden device allocation: scratch memory is the caller's `workspace`
+ *     (size from bake_workspace_size).  Everything is enqueued asynchronously
+ *     on `stream` (a hipStream_t; NULL = the default stream) and returns
+ *     without synchronising, except bake_query_status / bake_read_counter.
+ *   - Texel (i, j) is row i, column j of a [res][res] image; its centre is
+ *     u = (j + 1/2)/res, v = (i + 1/2)/res.
+ *   - Per-corner UVs are snapped to 1/256 texel; a texel is covered by a face
+ *     when its centre is inside or on the snapped UV triangle (either
+ *     orientation); on overlap the lowest face index wins.
+ *   - Return value: BAKE_OK (0) or a negative BAKE_E_* code; a message is kept
+ *     in a thread-local buffer (bake_last_error).  Argument errors are detected
+ *     on the host before any work is enqueued.
+ */
+#ifndef PAPER_2605_26137_AMD_BAKE_H
+#define PAPER_2605_26137_AMD_BAKE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---------------------------------------------------- */
+#define BAKE_OK 0
+#define BAKE_E_INVALID_ARG -1 /* null pointer, negative count, bad max_dist, ... */
+#define BAKE_E_UNSUPPORTED -2 /* res not a power of two in [1, 16384], size limits */
+#define BAKE_E_WORKSPACE -3   /* workspace missing, too small or misaligned */
+#define BAKE_E_INDEX -4       /* device status word reported bad input data */
+#define BAKE_E_HIP -5         /* a HIP runtime call failed */
+#define BAKE_E_STATE -6       /* backward called without a saved forward */
+
+/* ---- per-texel status written to out_hit ----------------------------- */
+/* >= 0: index of the high-poly triangle that was hit (original hi_F order) */
+#define BAKE_MISS -1       /* no high-poly surface within +-max_dist */
+#define BAKE_UNRELIABLE -2 /* degenerate UV/3D face, zero normal or tangent parallel to the normal */
+#define BAKE_UNCOVERED -3  /* no low-poly face covers the texel centre */
+
+/* ---- device status word bits (bake_query_status) --------------------- */
+#define BAKE_STATUS_LO_INDEX 1u  /* lo_F index outside [0, n_lo_v) */
+#define BAKE_STATUS_HI_INDEX 2u  /* hi_F index outside [0, n_hi_v) */
+#define BAKE_STATUS_BAD_UV 4u    /* UV non-finite or outside [-1, 2]; face skipped */
+#define BAKE_STATUS_NONFINITE 8u /* non-finite vertex position; face/triangle skipped */
+#define BAKE_STATUS_INTERNAL 16u /* internal consistency guard tripped (should never happen) */
+
+/* ---- flags ------------------------------------------------------------ */
+#define BAKE_FLAG_SAVE 1u   /* keep the per-ray state that bake_normals_backward needs */
+#define BAKE_FLAG_TIMING 2u /* record per-stage HIP events (bake_stage_times) */
+
+typedef struct bake_options {
+    int32_t dilate_passes; /* chart dilation passes, 0..64 (default 2)                    */
+    uint32_t flags;        /* BAKE_FLAG_*                                                  */
+    uint8_t *out_rgb8;     /* optional device [res,res,3] u8 map: floor((x+1)*127.5+0.5)   */
+    int32_t trav_block;    /* traversal workgroup size: 64, 128, 256 (0 = tuned default)  */
+    int32_t trav_stack;    /* LDS stack entries per lane: 8, 16, 32 (0 = tuned default)    */
+    int32_t trav_persist;  /* 1 = persistent waves refilling finished lanes, 0 = one ray
+                              per lane, -1 = tuned default                                */
+    int32_t reserved[4];
+} bake_options;
+
+/* Default options: dilate_passes = 2, no flags, no RGB8, tuned traversal. */
+void bake_default_options(bake_options *opt);
+
+/* Workspace bytes needed for a bake of these sizes with these options (NULL =
+ * defaults).  The workspace must be device memory aligned to 256 bytes. */
+int32_t bake_workspace_size(int64_t n_hi_v, int64_t n_hi_f, int64_t n_lo_v, int64_t n_lo_f,
+                            int32_t res, const bake_options *opt, size_t *bytes_out);
+
+/* Forward bake (Sec. 6.4, four stages: UV rasterisation to a G-buffer, BVH
+ * build over the high-poly, per-texel correspondence query with distance and
+ * UV-reliability filters, tangent-space projection and seam dilation).
+ *
+ *   hi_V  [n_hi_v,3] f32  high-poly vertex positions
+ *   hi_F  [n_hi_f,3] i32  high-poly triangles (indices into hi_V)
+ *   hi_N  [n_hi_v,3] f32  high-poly smooth vertex normals (need not be unit)
+ *   lo_V  [n_lo_v,3] f32  low-poly vertex positions
+ *   lo_F  [n_lo_f,3] i32  low-poly triangles
+ *   lo_UV [n_lo_f,3,2] f32 per-corner UVs, nominally in [0,1]
+ *   res   atlas side, a power of two in [1, 16384]
+ *   max_dist  finite, > 0: query range along the ray, both directions
+ *   out_map [res,res,3] f32  tangent-space normal (T', B', N) components
+ *   out_hit [res,res]   i32  hit triangle id or BAKE_MISS/UNRELIABLE/UNCOVERED
+ *
+ * Low-poly vertex normals are not an input: they are the normalised
+ * area-weighted sums of incident face normals.  The per-face tangent comes from
+ * the snapped UV derivatives; per texel it is made orthogonal to the
+ * interpolated normal N, and the bitangent is h_f (N x T') with h_f the face's
+ * UV handedness.  Uncovered texels are (0,0,1) before dilation; dilation fills
+ * them from covered neighbours and leaves their id at BAKE_UNCOVERED.
+ * Bad index data does not fault: offending faces are skipped and a bit is set
+ * in the device status word (bake_query_status). */
+int32_t bake_normals(const float *hi_V, int64_t n_hi_v, const int32_t *hi_F, int64_t n_hi_f,
+                     const float *hi_N, const float *lo_V, int64_t n_lo_v, const int32_t *lo_F,
+                     int64_t n_lo_f, const float *lo_UV, int32_t res, float max_dist,
+                     float *out_map, int32_t *out_hit, const bake_options *opt, void *workspace,
+                     size_t workspace_bytes, void *stream);
+
+/* Backward of L(out_map before dilation) with the hit selection, the texel ->
+ * face assignment and the handedness held fixed: given grad_map = dL/dout_map
+ * [res,res,3], writes dL/dlo_V [n_lo_v,3] and dL/dhi_N [n_hi_v,3] (both
+ * overwritten, not accumulated).  Needs the workspace of a forward call made
+ * with BAKE_FLAG_SAVE on the same inputs, not modified since.  Sums are done in
+ * a fixed order (no floating-point atomics): the result is bitwise
+ * reproducible.  Either gradient pointer may be NULL to skip it. */
+int32_t bake_normals_backward(const float *hi_V, int64_t n_hi_v, const int32_t *hi_F,
+                              int64_t n_hi_f, const float *hi_N, const float *lo_V, int64_t n_lo_v,
+                              const int32_t *lo_F, int64_t n_lo_f, const float *lo_UV, int32_t res,
+                              float max_dist, const float *grad_map, float *grad_lo_V,
+                              float *grad_hi_N, void *workspace, size_t workspace_bytes,
+                              void *stream);
+
+/* Synchronises `stream` and returns the OR of BAKE_STATUS_* bits raised by the
+ * last bake that used `workspace`. */
+int32_t bake_query_status(const void *workspace, void *stream, uint32_t *status_out);
+
+/* Synchronises `stream` and returns a device counter of the last bake that used
+ * `workspace`: which = 0 -> number of covered texels (rays traced). */
+int32_t bake_read_counter(const void *workspace, int32_t which, void *stream, int64_t *value_out);
+
+/* Location of an internal array inside the workspace, for inspection by tests
+ * and tools: which = BAKE_VIEW_*.  Returns byte offset and byte size. */
+#define BAKE_VIEW_RAYS 0     /* [n_rays] {i32 texel, i32 lo face, f32 b1, f32 b2}, face order */
+#define BAKE_VIEW_HITS 1     /* [n_rays] {f32 t, f32 beta1, f32 beta2, i32 id} (FLAG_SAVE)   */
+#define BAKE_VIEW_FACEMAP 2  /* [res*res] i32 covering face or INT32_MAX                      */
+#define BAKE_VIEW_LO_N 3     /* [n_lo_v] {f32 x, y, z, valid}                                 */
+#define BAKE_VIEW_SORTED 4   /* [n_hi_f] {u32 morton key} then [n_hi_f] {u32 tri index}       */
+#define BAKE_VIEW_NODES 5    /* [n_hi_f-1] 64 B BVH nodes: child boxes + child refs            */
+#define BAKE_VIEW_LEAVES 6   /* [n_hi_f] 48 B leaf triangles: 3 vertices + original index      */
+#define BAKE_VIEW_FACE_T 7   /* [n_lo_f] {f32 Tx, Ty, Tz, h}                                   */
+int32_t bake_workspace_view(int64_t n_hi_v, int64_t n_hi_f, int64_t n_lo_v, int64_t n_lo_f,
+                            int32_t res, const bake_options *opt, int32_t which,
+                            size_t *offset_out, size_t *bytes_out);
+
+/* Per-stage GPU times in ms of the last bake on this thread made with
+ * BAKE_FLAG_TIMING (synchronises on those events).  Stages: 0 lo prep,
+ * 1 raster, 2 BVH build, 3 traversal+encode, 4 dilation, 5 whole forward.
+ * Returns the number of stages written. */
+int32_t bake_stage_times(float *ms_out, int32_t n);
+
+/* Thread-local message of the last error on this thread ("" if none). */
+const char *bake_last_error(void);
+
+/* Library version string. */
+const char *bake_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

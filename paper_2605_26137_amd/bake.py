@@ -1,0 +1,240 @@
+"""Python binding of the gfx950 normal baker (libbake.so, C ABI in include/bake.h).
+
+Argument marshalling only: every step of the bake runs in the HIP kernels of
+libbake.so.  PyTorch provides device memory and the stream.  If the library
+is missing, importing works but every call raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbake.so")
+
+BAKE_OK = 0
+BAKE_E_INVALID_ARG = -1
+BAKE_E_UNSUPPORTED = -2
+BAKE_E_WORKSPACE = -3
+BAKE_E_INDEX = -4
+BAKE_E_HIP = -5
+BAKE_E_STATE = -6
+
+BAKE_MISS = -1
+BAKE_UNRELIABLE = -2
+BAKE_UNCOVERED = -3
+
+BAKE_STATUS_LO_INDEX = 1
+BAKE_STATUS_HI_INDEX = 2
+BAKE_STATUS_BAD_UV = 4
+BAKE_STATUS_NONFINITE = 8
+
+BAKE_FLAG_SAVE = 1
+BAKE_FLAG_TIMING = 2
+
+VIEW_RAYS, VIEW_HITS, VIEW_FACEMAP, VIEW_LO_N, VIEW_SORTED, VIEW_NODES, VIEW_LEAVES, VIEW_FACE_T = range(8)
+
+STAGES = ("lo_prep", "raster", "bvh_build", "traverse", "dilate", "forward")
+
+
+class BakeError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"bake error {code}: {msg}")
+        self.code = code
+
+
+class BakeOptions(C.Structure):
+    _fields_ = [
+        ("dilate_passes", C.c_int32),
+        ("flags", C.c_uint32),
+        ("out_rgb8", C.c_void_p),
+        ("trav_block", C.c_int32),
+        ("trav_stack", C.c_int32),
+        ("trav_persist", C.c_int32),
+        ("reserved", C.c_int32 * 4),
+    ]
+
+
+_lib = None
+
+_EXPORTS = {
+    "bake_default_options": (None, [C.c_void_p]),
+    "bake_workspace_size": (C.c_int32, [C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_int32,
+                                        C.c_void_p, C.POINTER(C.c_size_t)]),
+    "bake_normals": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
+                                 C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
+                                 C.c_int32, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_size_t, C.c_void_p]),
+    "bake_normals_backward": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
+                                          C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
+                                          C.c_int32, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.c_void_p, C.c_size_t, C.c_void_p]),
+    "bake_query_status": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_uint32)]),
+    "bake_read_counter": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_int64)]),
+    "bake_workspace_view": (C.c_int32, [C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_int32,
+                                        C.c_void_p, C.c_int32, C.POINTER(C.c_size_t),
+                                        C.POINTER(C.c_size_t)]),
+    "bake_stage_times": (C.c_int32, [C.POINTER(C.c_float), C.c_int32]),
+    "bake_last_error": (C.c_char_p, []),
+    "bake_version": (C.c_char_p, []),
+}
+
+
+def lib():
+    """Load libbake.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2605_26137_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _EXPORTS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc < 0:
+        raise BakeError(rc, lib().bake_last_error().decode())
+    return rc
+
+
+def make_options(dilate_passes=2, save=False, timing=False, rgb8_ptr=0, trav_block=0,
+                 trav_stack=0, trav_persist=-1) -> BakeOptions:
+    o = BakeOptions()
+    lib().bake_default_options(C.byref(o))
+    o.dilate_passes = int(dilate_passes)
+    o.flags = (BAKE_FLAG_SAVE if save else 0) | (BAKE_FLAG_TIMING if timing else 0)
+    o.out_rgb8 = rgb8_ptr or None
+    o.trav_block = int(trav_block)
+    o.trav_stack = int(trav_stack)
+    o.trav_persist = int(trav_persist)
+    return o
+
+
+def workspace_size(n_hi_v, n_hi_f, n_lo_v, n_lo_f, res, opts: Optional[BakeOptions] = None) -> int:
+    b = C.c_size_t(0)
+    _check(lib().bake_workspace_size(int(n_hi_v), int(n_hi_f), int(n_lo_v), int(n_lo_f), int(res),
+                                     C.byref(opts) if opts is not None else None, C.byref(b)))
+    return b.value
+
+
+def workspace_view(n_hi_v, n_hi_f, n_lo_v, n_lo_f, res, which, opts=None):
+    o = C.c_size_t(0)
+    b = C.c_size_t(0)
+    _check(lib().bake_workspace_view(int(n_hi_v), int(n_hi_f), int(n_lo_v), int(n_lo_f), int(res),
+                                     C.byref(opts) if opts is not None else None, int(which),
+                                     C.byref(o), C.byref(b)))
+    return o.value, b.value
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev_tensor(x, dtype, name, shape_tail=None):
+    if not isinstance(x, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor on the GPU")
+    if x.device.type != "cuda":
+        raise ValueError(f"{name} must live on the GPU (got {x.device})")
+    if x.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {x.dtype})")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape_tail is not None and tuple(x.shape[1:]) != tuple(shape_tail):
+        raise ValueError(f"{name} has shape {tuple(x.shape)}, expected [n, {shape_tail}]")
+    return x
+
+
+@dataclass
+class BakeResult:
+    map: torch.Tensor          # [res, res, 3] f32
+    hit: torch.Tensor          # [res, res] i32
+    rgb8: Optional[torch.Tensor]
+    workspace: torch.Tensor
+    opts: BakeOptions
+    sizes: tuple               # (n_hi_v, n_hi_f, n_lo_v, n_lo_f, res)
+
+    def view(self, which, dtype=torch.uint8):
+        o, b = workspace_view(*self.sizes, which, self.opts)
+        return self.workspace[o:o + b].view(dtype)
+
+    def ray_count(self, stream=None) -> int:
+        v = C.c_int64(0)
+        _check(lib().bake_read_counter(_ptr(self.workspace), 0, _stream_handle(stream), C.byref(v)))
+        return v.value
+
+    def status(self, stream=None) -> int:
+        v = C.c_uint32(0)
+        _check(lib().bake_query_status(_ptr(self.workspace), _stream_handle(stream), C.byref(v)))
+        return v.value
+
+
+def bake_normals(hi_V, hi_F, hi_N, lo_V, lo_F, lo_UV, res: int, max_dist: float, *,
+                 dilate_passes: int = 2, rgb8: bool = False, save: bool = False,
+                 timing: bool = False, trav_block: int = 0, trav_stack: int = 0,
+                 trav_persist: int = -1, workspace: Optional[torch.Tensor] = None,
+                 out_map: Optional[torch.Tensor] = None, out_hit: Optional[torch.Tensor] = None,
+                 stream=None) -> BakeResult:
+    """Bake a tangent-space normal map of the high-poly onto the low-poly's UV
+    atlas.  Inputs are GPU tensors: hi_V [Vh,3] f32, hi_F [Fh,3] i32, hi_N [Vh,3]
+    f32, lo_V [Vl,3] f32, lo_F [Fl,3] i32, lo_UV [Fl,3,2] f32."""
+    hi_V = _dev_tensor(hi_V, torch.float32, "hi_V", (3,))
+    hi_F = _dev_tensor(hi_F, torch.int32, "hi_F", (3,))
+    hi_N = _dev_tensor(hi_N, torch.float32, "hi_N", (3,))
+    lo_V = _dev_tensor(lo_V, torch.float32, "lo_V", (3,))
+    lo_F = _dev_tensor(lo_F, torch.int32, "lo_F", (3,))
+    lo_UV = _dev_tensor(lo_UV, torch.float32, "lo_UV", (3, 2))
+    if hi_N.shape[0] != hi_V.shape[0]:
+        raise ValueError("hi_N and hi_V must have the same number of rows")
+    if lo_UV.shape[0] != lo_F.shape[0]:
+        raise ValueError("lo_UV and lo_F must have the same number of rows")
+    dev = hi_V.device
+    sizes = (hi_V.shape[0], hi_F.shape[0], lo_V.shape[0], lo_F.shape[0], int(res))
+    rgb = torch.empty((res, res, 3), dtype=torch.uint8, device=dev) if rgb8 else None
+    opts = make_options(dilate_passes, save, timing, rgb.data_ptr() if rgb is not None else 0,
+                        trav_block, trav_stack, trav_persist)
+    nbytes = workspace_size(*sizes, opts)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    if out_map is None:
+        out_map = torch.empty((res, res, 3), dtype=torch.float32, device=dev)
+    if out_hit is None:
+        out_hit = torch.empty((res, res), dtype=torch.int32, device=dev)
+    _check(lib().bake_normals(
+        _ptr(hi_V), sizes[0], _ptr(hi_F), sizes[1], _ptr(hi_N), _ptr(lo_V), sizes[2], _ptr(lo_F),
+        sizes[3], _ptr(lo_UV), int(res), float(max_dist), _ptr(out_map), _ptr(out_hit),
+        C.byref(opts), _ptr(workspace), workspace.numel(), _stream_handle(stream)))
+    return BakeResult(out_map, out_hit, rgb, workspace, opts, sizes)
+
+
+def stage_times() -> dict:
+    """Per-stage GPU times (ms) of the last bake on this thread made with timing=True."""
+    buf = (C.c_float * len(STAGES))()
+    n = _check(lib().bake_stage_times(buf, len(STAGES)))
+    return {STAGES[k]: float(buf[k]) for k in range(n)}
+
+
+def version() -> str:
+    return lib().bake_version().decode()
+
+
+def to_device(asset, device="cuda"):
+    """numpy Asset arrays -> GPU tensors in the layout the bake expects."""
+    import numpy as np
+    f = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(device)
+    return (f(asset.hi_V, np.float32), f(asset.hi_F, np.int32), f(asset.hi_N, np.float32),
+            f(asset.lo_V, np.float32), f(asset.lo_F, np.int32), f(asset.lo_UV, np.float32))

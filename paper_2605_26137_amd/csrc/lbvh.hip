@@ -1,0 +1,376 @@
+// LBVH build over the high-poly triangles (the paper's "GPU BVH built on the
+// high-poly mesh", Sec. 6.4), after Karras 2012 (binary radix tree over sorted
+// Morton codes):
+//   1. reduction of the triangle-centroid bounds,
+//   2. 30-bit Morton code of each centroid, value = original triangle index,
+//   3. stable LSD radix sort of (code, index), 8-bit digits, LDS-ranked with
+//      wave64 ballots, so equal codes keep ascending index order,
+//   4. Karras hierarchy: every internal node finds its key range and split
+//      from common-prefix lengths (code, extended by the index on equal codes),
+//   5. leaf packing (vertices copied bit-exactly, original index kept) and a
+//      bottom-up refit: per internal node an arrival counter; the second
+//      arriving child unions both boxes and continues upward.  min/max is
+//      exact, so the boxes do not depend on arrival order.
+#include <algorithm>
+#include <utility>
+
+#include "internal.h"
+
+namespace bake {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kSortRounds = 16;
+constexpr int kSortTile = kBlock * kSortRounds;  // 4096 keys per block and pass
+constexpr int kBoundsBlocks = 512;
+
+__device__ __forceinline__ int3 tri_idx(const int32_t* __restrict__ F, int64_t g, int64_t nv,
+                                        bool* bad) {
+    int32_t a = F[3 * g], b = F[3 * g + 1], c = F[3 * g + 2];
+    bool ok = a >= 0 && b >= 0 && c >= 0 && a < nv && b < nv && c < nv;
+    *bad = !ok;
+    if (!ok) a = b = c = 0;  // degenerate stand-in: never hit, never out of bounds
+    return make_int3(a, b, c);
+}
+
+__device__ __forceinline__ float3 ldv(const float* __restrict__ V, int32_t i) {
+    return make_float3(V[3 * (int64_t)i], V[3 * (int64_t)i + 1], V[3 * (int64_t)i + 2]);
+}
+
+__device__ __forceinline__ float3 centroid(const float* __restrict__ V, int3 t) {
+    float3 a = ldv(V, t.x), b = ldv(V, t.y), c = ldv(V, t.z);
+    const float k = 1.0f / 3.0f;
+    return make_float3((a.x + b.x + c.x) * k, (a.y + b.y + c.y) * k, (a.z + b.z + c.z) * k);
+}
+
+// ---------------------------------------------------------------------------
+// 1. centroid bounds
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ void block_minmax6(float v[6], float* out) {
+    __shared__ float red[kBlock / 64][6];
+    int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = wave_min(v[k]);
+#pragma unroll
+    for (int k = 3; k < 6; ++k) v[k] = wave_max(v[k]);
+    if (lane == 0)
+        for (int k = 0; k < 6; ++k) red[wave][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; ++w) {
+            for (int k = 0; k < 3; ++k) v[k] = fminf(v[k], red[w][k]);
+            for (int k = 3; k < 6; ++k) v[k] = fmaxf(v[k], red[w][k]);
+        }
+        for (int k = 0; k < 6; ++k) out[k] = v[k];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void bounds_part_kernel(const float* __restrict__ V, int64_t nv,
+                                                             const int32_t* __restrict__ F, int64_t nf,
+                                                             float* __restrict__ part,
+                                                             uint32_t* __restrict__ status) {
+    float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    bool anybad = false, nonfin = false;
+    for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < nf;
+         g += (int64_t)gridDim.x * kBlock) {
+        bool bad;
+        int3 t = tri_idx(F, g, nv, &bad);
+        anybad |= bad;
+        float3 c = centroid(V, t);
+        if (!(isfinite(c.x) && isfinite(c.y) && isfinite(c.z))) {
+            nonfin = true;
+            continue;
+        }
+        v[0] = fminf(v[0], c.x); v[1] = fminf(v[1], c.y); v[2] = fminf(v[2], c.z);
+        v[3] = fmaxf(v[3], c.x); v[4] = fmaxf(v[4], c.y); v[5] = fmaxf(v[5], c.z);
+    }
+    if (anybad) atomicOr(status, kStHiIndex);
+    if (nonfin) atomicOr(status, kStNonFinite);
+    block_minmax6(v, part + 6 * blockIdx.x);
+}
+
+__global__ __launch_bounds__(kBlock) void bounds_final_kernel(const float* __restrict__ part, int nparts,
+                                                              float* __restrict__ bounds) {
+    float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int i = threadIdx.x; i < nparts; i += kBlock) {
+        for (int k = 0; k < 3; ++k) v[k] = fminf(v[k], part[6 * i + k]);
+        for (int k = 3; k < 6; ++k) v[k] = fmaxf(v[k], part[6 * i + k]);
+    }
+    block_minmax6(v, bounds);
+}
+
+// ---------------------------------------------------------------------------
+// 2. Morton codes
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t spread10(uint32_t x) {
+    // 10 bits -> every third bit of 30
+    x &= 0x3FFu;
+    x = (x | (x << 16)) & 0x030000FFu;
+    x = (x | (x << 8)) & 0x0300F00Fu;
+    x = (x | (x << 4)) & 0x030C30C3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+
+__device__ __forceinline__ uint32_t quant10(float c, float lo, float inv) {
+    float q = (c - lo) * inv * 1024.0f;
+    q = fminf(fmaxf(q, 0.0f), 1023.0f);  // NaN -> 0
+    return (uint32_t)q;
+}
+
+__global__ void morton_kernel(const float* __restrict__ V, int64_t nv, const int32_t* __restrict__ F,
+                              int64_t nf, const float* __restrict__ bounds,
+                              uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nf) return;
+    bool bad;
+    int3 t = tri_idx(F, g, nv, &bad);
+    float3 c = centroid(V, t);
+    float ex = bounds[3] - bounds[0], ey = bounds[4] - bounds[1], ez = bounds[5] - bounds[2];
+    float ix = ex > 0.f ? 1.0f / ex : 0.f, iy = ey > 0.f ? 1.0f / ey : 0.f,
+          iz = ez > 0.f ? 1.0f / ez : 0.f;
+    uint32_t x = quant10(c.x, bounds[0], ix), y = quant10(c.y, bounds[1], iy),
+             z = quant10(c.z, bounds[2], iz);
+    keys[g] = (spread10(x) << 2) | (spread10(y) << 1) | spread10(z);
+    vals[g] = (uint32_t)g;
+}
+
+// ---------------------------------------------------------------------------
+// 3. stable LSD radix sort, 8-bit digits
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __restrict__ keys,
+                                                            int64_t n, int shift, int64_t nb,
+                                                            uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll 4
+    for (int r = 0; r < kSortRounds; ++r) {
+        int64_t i = base + (int64_t)r * kBlock + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+// Element r*256 + tid of the block's tile is ranked among equal digits by
+// (earlier rounds, earlier waves, earlier lanes): a stable order.
+__global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t* __restrict__ kin,
+                                                               const uint32_t* __restrict__ vin,
+                                                               uint32_t* __restrict__ kout,
+                                                               uint32_t* __restrict__ vout, int64_t n,
+                                                               int shift, int64_t nb,
+                                                               const uint32_t* __restrict__ offs) {
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[kBlock / 64][256];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    (void)lane;
+    run[tid] = offs[(int64_t)tid * nb + blockIdx.x];
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortRounds; ++r) {
+        int64_t i = base + (int64_t)r * kBlock + tid;
+        bool valid = i < n;
+        uint32_t key = valid ? kin[i] : 0u, val = valid ? vin[i] : 0u;
+        uint32_t dig = (key >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            bool bit = (dig >> b) & 1u;
+            uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        uint32_t rank = (uint32_t)__popcll(peers & __lanemask_lt());
+        if (valid && rank == 0) wcnt[wave][dig] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = run[dig] + rank;
+            for (int w = 0; w < wave; ++w) pos += wcnt[w][dig];
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) {
+            add += wcnt[w][tid];
+            wcnt[w][tid] = 0;
+        }
+        run[tid] += add;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 4. Karras hierarchy
+// ---------------------------------------------------------------------------
+
+// Common-prefix length of sorted keys i and j, extended by the indices on
+// equal keys; -1 outside [0, n).
+__device__ __forceinline__ int cprefix(const uint32_t* __restrict__ k, int64_t n, int64_t i,
+                                       int64_t j) {
+    if (j < 0 || j >= n) return -1;
+    uint32_t a = k[i], b = k[j];
+    if (a == b) return 32 + __clz((uint32_t)i ^ (uint32_t)j);
+    return __clz(a ^ b);
+}
+
+__global__ void karras_kernel(const uint32_t* __restrict__ keys, int64_t n, BvhNode* __restrict__ nodes,
+                              int32_t* __restrict__ node_parent, int32_t* __restrict__ leaf_parent) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    int d = (cprefix(keys, n, i, i + 1) - cprefix(keys, n, i, i - 1)) >= 0 ? 1 : -1;
+    int dmin = cprefix(keys, n, i, i - d);
+    int64_t lmax = 2;
+    while (cprefix(keys, n, i, i + lmax * d) > dmin) lmax <<= 1;
+    int64_t l = 0;
+    for (int64_t t = lmax >> 1; t >= 1; t >>= 1)
+        if (cprefix(keys, n, i, i + (l + t) * d) > dmin) l += t;
+    int64_t j = i + l * d;
+    int dnode = cprefix(keys, n, i, j);
+    int64_t s = 0, t = l;
+    do {
+        t = (t + 1) >> 1;
+        if (cprefix(keys, n, i, i + (s + t) * d) > dnode) s += t;
+    } while (t > 1);
+    int64_t gamma = i + s * d + (d < 0 ? -1 : 0);
+    int64_t lo = i < j ? i : j, hi = i < j ? j : i;
+    int32_t left = lo == gamma ? ~(int32_t)gamma : (int32_t)gamma;
+    int32_t right = hi == gamma + 1 ? ~(int32_t)(gamma + 1) : (int32_t)(gamma + 1);
+    nodes[i].ref = make_int4(left, right, 0, 0);
+    if (left < 0) leaf_parent[gamma] = (int32_t)(i << 1);
+    else node_parent[gamma] = (int32_t)(i << 1);
+    if (right < 0) leaf_parent[gamma + 1] = (int32_t)((i << 1) | 1);
+    else node_parent[gamma + 1] = (int32_t)((i << 1) | 1);
+    if (i == 0) node_parent[0] = -1;
+}
+
+// ---------------------------------------------------------------------------
+// 5. leaves + refit
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void put_slot(BvhNode* node, int side, const float b[6]) {
+    float* f = reinterpret_cast<float*>(node) + 6 * side;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) f[k] = b[k];
+}
+
+__global__ void leaf_refit_kernel(const float* __restrict__ V, int64_t nv, const int32_t* __restrict__ F,
+                                  int64_t n, const uint32_t* __restrict__ sorted_idx,
+                                  Leaf* __restrict__ leaves, BvhNode* nodes,
+                                  const int32_t* __restrict__ node_parent,
+                                  const int32_t* __restrict__ leaf_parent, uint32_t* cnt,
+                                  uint32_t* __restrict__ status) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    uint32_t g = sorted_idx[k];
+    bool bad;
+    int3 t = tri_idx(F, g, nv, &bad);
+    float3 a = ldv(V, t.x), b = ldv(V, t.y), c = ldv(V, t.z);
+    Leaf lf;
+    lf.a = make_float4(a.x, a.y, a.z, b.x);
+    lf.b = make_float4(b.y, b.z, c.x, c.y);
+    lf.c = make_float4(c.z, __int_as_float((int32_t)g), 0.f, 0.f);
+    leaves[k] = lf;
+    float box[6] = {fminf(fminf(a.x, b.x), c.x), fminf(fminf(a.y, b.y), c.y),
+                    fminf(fminf(a.z, b.z), c.z), fmaxf(fmaxf(a.x, b.x), c.x),
+                    fmaxf(fmaxf(a.y, b.y), c.y), fmaxf(fmaxf(a.z, b.z), c.z)};
+    int32_t pp = n > 1 ? leaf_parent[k] : -1;
+    for (int level = 0; pp >= 0; ++level) {
+        if (level > 2 * kMaxDepth) {  // only a malformed hierarchy gets here
+            atomicOr(status, kStInternal);
+            return;
+        }
+        int32_t p = pp >> 1;
+        int side = pp & 1;
+        put_slot(&nodes[p], side, box);
+        uint32_t old = __hip_atomic_fetch_add(&cnt[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == 0) return;  // the sibling subtree is not finished yet
+        const float* o = reinterpret_cast<const float*>(&nodes[p]) + 6 * (1 - side);
+        float ob[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) ob[q] = __hip_atomic_load(o + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) box[q] = fminf(box[q], ob[q]);
+#pragma unroll
+        for (int q = 3; q < 6; ++q) box[q] = fmaxf(box[q], ob[q]);
+        pp = node_parent[p];
+    }
+}
+
+inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+hipError_t launch_bvh_build(const float* hi_V, int64_t nhv, const int32_t* hi_F, int64_t nhf,
+                            const Layout& L, char* ws, hipStream_t s) {
+    if (nhf <= 0) return hipSuccess;
+    hipError_t e;
+    float* part = (float*)(ws + L.bounds_part);
+    float* bounds = (float*)(ws + L.bounds);
+    uint32_t* k0 = (uint32_t*)(ws + L.keys0);
+    uint32_t* k1 = (uint32_t*)(ws + L.keys1);
+    uint32_t* v0 = (uint32_t*)(ws + L.vals0);
+    uint32_t* v1 = (uint32_t*)(ws + L.vals1);
+    uint32_t* hist = (uint32_t*)(ws + L.hist);
+    BvhNode* nodes = (BvhNode*)(ws + L.nodes);
+    Leaf* leaves = (Leaf*)(ws + L.leaves);
+    int32_t* np = (int32_t*)(ws + L.node_parent);
+    int32_t* lp = (int32_t*)(ws + L.leaf_parent);
+    uint32_t* cnt = (uint32_t*)(ws + L.refit_cnt);
+    uint32_t* status = (uint32_t*)(ws + L.status);
+
+    int parts = (int)std::min<int64_t>(kBoundsBlocks, (nhf + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(bounds_part_kernel, dim3(parts), dim3(kBlock), 0, s, hi_V, nhv, hi_F, nhf,
+                       part, status);
+    hipLaunchKernelGGL(bounds_final_kernel, dim3(1), dim3(kBlock), 0, s, (const float*)part, parts,
+                       bounds);
+    hipLaunchKernelGGL(morton_kernel, dim3(blocks_for(nhf, kBlock)), dim3(kBlock), 0, s, hi_V, nhv,
+                       hi_F, nhf, (const float*)bounds, k0, v0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+
+    int64_t nb = (nhf + kSortTile - 1) / kSortTile;
+    uint32_t* kin = k0; uint32_t* vin = v0; uint32_t* kout = k1; uint32_t* vout = v1;
+    for (int shift = 0; shift < 32; shift += 8) {
+        hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nb), dim3(kBlock), 0, s,
+                           (const uint32_t*)kin, nhf, shift, nb, hist);
+        if ((e = exclusive_scan_u32(hist, hist, 256 * nb, (uint32_t*)(ws + L.scan_tmp), nullptr, s)) !=
+            hipSuccess)
+            return e;
+        hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nb), dim3(kBlock), 0, s,
+                           (const uint32_t*)kin, (const uint32_t*)vin, kout, vout, nhf, shift, nb,
+                           (const uint32_t*)hist);
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+    }
+    // four passes: the sorted arrays are back in keys0 / vals0
+    if (nhf > 1) {
+        hipLaunchKernelGGL(karras_kernel, dim3(blocks_for(nhf - 1, kBlock)), dim3(kBlock), 0, s,
+                           (const uint32_t*)k0, nhf, nodes, np, lp);
+        if ((e = fill_u32(cnt, 0, nhf - 1, s)) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(leaf_refit_kernel, dim3(blocks_for(nhf, kBlock)), dim3(kBlock), 0, s, hi_V,
+                       nhv, hi_F, nhf, (const uint32_t*)v0, leaves, nodes, (const int32_t*)np,
+                       (const int32_t*)lp, cnt, status);
+    return hipGetLastError();
+}
+
+}  // namespace bake

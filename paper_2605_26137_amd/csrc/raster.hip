@@ -1,0 +1,422 @@
+// Low-poly preparation, UV-space rasteriser, uncovered-texel fill, chart
+// dilation and RGB8 encoding.
+//
+// The rasteriser produces the G-buffer of the paper's bake (Sec. 6.4): for
+// every texel centre covered by a low-poly face in UV space, the face and the
+// barycentric weights, from which the world position and the interpolated
+// smooth normal follow.  Coverage is decided exactly in integers: corners are
+// snapped to 1/256 texel (exact in FP32 since res is a power of two) and the
+// three edge functions are evaluated in int64 at the texel centre.
+#include "internal.h"
+
+namespace bake {
+
+namespace {
+
+constexpr uint32_t kFaceReliable = 1u;  // UV det != 0, 3D area != 0, indices and data valid
+constexpr uint32_t kFaceRaster = 2u;    // may cover texels (indices valid, UV in range, det != 0)
+
+__device__ __forceinline__ float3 ld3(const float* p, int64_t i) {
+    return make_float3(p[3 * i], p[3 * i + 1], p[3 * i + 2]);
+}
+__device__ __forceinline__ float3 sub3(float3 a, float3 b) {
+    return make_float3(a.x - b.x, a.y - b.y, a.z - b.z);
+}
+__device__ __forceinline__ float3 cross3(float3 a, float3 b) {
+    return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ bool finite3(float3 a) {
+    return isfinite(a.x) && isfinite(a.y) && isfinite(a.z);
+}
+
+// ---------------------------------------------------------------------------
+// Low-poly preparation
+// ---------------------------------------------------------------------------
+
+// Per face: snapped UV corners, tangent T_f = sgn(det) (e1 dv2 - e2 dv1) and
+// handedness h_f = sign(((e1 x e2) x T_f) . B_f) with B_f = sgn(det)(e2 du1 -
+// e1 du2); reliability flags; vertex degrees for the vertex -> face CSR.
+__global__ void lo_face_kernel(const float* __restrict__ V, int64_t nv, const int32_t* __restrict__ F,
+                               int64_t nf, const float* __restrict__ UV, int32_t res,
+                               float4* __restrict__ face_t, int4* __restrict__ face_uv,
+                               uint32_t* __restrict__ deg, uint32_t* __restrict__ status) {
+    int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    int32_t a = F[3 * f], b = F[3 * f + 1], c = F[3 * f + 2];
+    bool idx_ok = a >= 0 && b >= 0 && c >= 0 && a < nv && b < nv && c < nv;
+    uint32_t st = 0;
+    if (!idx_ok) st |= kStLoIndex;
+    float u[6];
+    bool uv_ok = true;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        u[k] = UV[6 * f + k];
+        uv_ok = uv_ok && isfinite(u[k]) && u[k] >= -1.0f && u[k] <= 2.0f;
+    }
+    if (!uv_ok) st |= kStBadUV;
+    const float sc = (float)res * 256.0f;
+    int32_t X[3], Y[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        X[k] = uv_ok ? (int32_t)rintf(u[2 * k] * sc) : 0;
+        Y[k] = uv_ok ? (int32_t)rintf(u[2 * k + 1] * sc) : 0;
+    }
+    int64_t du1 = X[1] - X[0], dv1 = Y[1] - Y[0], du2 = X[2] - X[0], dv2 = Y[2] - Y[0];
+    int64_t det = du1 * dv2 - du2 * dv1;
+    float sg = det > 0 ? 1.0f : (det < 0 ? -1.0f : 0.0f);
+    float4 T4 = make_float4(0.f, 0.f, 0.f, 1.f);
+    bool rel = false;
+    if (idx_ok) {
+        float3 A = ld3(V, a), B = ld3(V, b), C = ld3(V, c);
+        bool fin = finite3(A) && finite3(B) && finite3(C);
+        if (!fin) st |= kStNonFinite;
+        float3 e1 = sub3(B, A), e2 = sub3(C, A);
+        float fdu1 = (float)du1, fdv1 = (float)dv1, fdu2 = (float)du2, fdv2 = (float)dv2;
+        float3 T = make_float3(sg * (e1.x * fdv2 - e2.x * fdv1), sg * (e1.y * fdv2 - e2.y * fdv1),
+                               sg * (e1.z * fdv2 - e2.z * fdv1));
+        float3 Bt = make_float3(sg * (e2.x * fdu1 - e1.x * fdu2), sg * (e2.y * fdu1 - e1.y * fdu2),
+                                sg * (e2.z * fdu1 - e1.z * fdu2));
+        float3 n = cross3(e1, e2);
+        float hs = dot3(cross3(n, T), Bt);
+        T4 = make_float4(T.x, T.y, T.z, hs < 0.f ? -1.f : 1.f);
+        bool area = n.x != 0.f || n.y != 0.f || n.z != 0.f;
+        rel = fin && uv_ok && det != 0 && area;
+        atomicAdd(&deg[a], 1u);
+        atomicAdd(&deg[b], 1u);
+        atomicAdd(&deg[c], 1u);
+    }
+    uint32_t flags = (rel ? kFaceReliable : 0u) | ((idx_ok && uv_ok && det != 0) ? kFaceRaster : 0u);
+    face_t[f] = T4;
+    face_uv[2 * f] = make_int4(X[0], Y[0], X[1], Y[1]);
+    face_uv[2 * f + 1] = make_int4(X[2], Y[2], (int32_t)flags, 0);
+    if (st) atomicOr(status, st);
+}
+
+__global__ void lo_adj_kernel(const int32_t* __restrict__ F, int64_t nv, int64_t nf,
+                              const uint32_t* __restrict__ off, uint32_t* __restrict__ cur,
+                              int32_t* __restrict__ adj) {
+    int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    int32_t v[3] = {F[3 * f], F[3 * f + 1], F[3 * f + 2]};
+    if (v[0] < 0 || v[1] < 0 || v[2] < 0 || v[0] >= nv || v[1] >= nv || v[2] >= nv) return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        uint32_t slot = atomicAdd(&cur[v[k]], 1u);
+        adj[off[v[k]] + slot] = (int32_t)f;
+    }
+}
+
+// Per vertex: sort its incident faces ascending (fixed summation order, so the
+// result does not depend on the order the adjacency was filled in), then
+// n_v = normalise(sum (V1 - V0) x (V2 - V0)).
+__global__ void lo_normal_kernel(const float* __restrict__ V, int64_t nv, const int32_t* __restrict__ F,
+                                 const uint32_t* __restrict__ off, int32_t* __restrict__ adj,
+                                 float4* __restrict__ lo_n) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv) return;
+    uint32_t b = off[v], e = off[v + 1];
+    for (uint32_t i = b + 1; i < e; ++i) {
+        int32_t x = adj[i];
+        uint32_t j = i;
+        while (j > b && adj[j - 1] > x) {
+            adj[j] = adj[j - 1];
+            --j;
+        }
+        adj[j] = x;
+    }
+    float3 s = make_float3(0.f, 0.f, 0.f);
+    for (uint32_t i = b; i < e; ++i) {
+        int32_t f = adj[i];
+        float3 A = ld3(V, F[3 * f]), B = ld3(V, F[3 * f + 1]), C = ld3(V, F[3 * f + 2]);
+        float3 c = cross3(sub3(B, A), sub3(C, A));
+        s.x += c.x;
+        s.y += c.y;
+        s.z += c.z;
+    }
+    float l2 = dot3(s, s);
+    float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (l2 > 0.f && isfinite(l2)) {
+        float r = 1.0f / sqrtf(l2);
+        out = make_float4(s.x * r, s.y * r, s.z * r, 1.f);
+    }
+    lo_n[v] = out;
+}
+
+// ---------------------------------------------------------------------------
+// Rasteriser: one wave (64 lanes) per face, lanes stride over the face's
+// texel bounding box.
+// ---------------------------------------------------------------------------
+
+struct FaceBox {
+    int32_t X[3], Y[3];
+    int32_t i0, j0, w, h;
+    bool ok;
+};
+
+__device__ __forceinline__ int32_t floor_div256(int32_t x) { return x >> 8; }  // arithmetic shift
+
+__device__ __forceinline__ FaceBox load_face_box(const int4* __restrict__ face_uv, int64_t f,
+                                                 int32_t res) {
+    FaceBox fb;
+    int4 p = face_uv[2 * f], q = face_uv[2 * f + 1];
+    fb.X[0] = p.x; fb.Y[0] = p.y; fb.X[1] = p.z; fb.Y[1] = p.w; fb.X[2] = q.x; fb.Y[2] = q.y;
+    fb.ok = (q.z & kFaceRaster) != 0;
+    int32_t xmin = min(min(fb.X[0], fb.X[1]), fb.X[2]), xmax = max(max(fb.X[0], fb.X[1]), fb.X[2]);
+    int32_t ymin = min(min(fb.Y[0], fb.Y[1]), fb.Y[2]), ymax = max(max(fb.Y[0], fb.Y[1]), fb.Y[2]);
+    // texel centres 256 j + 128 inside [xmin, xmax]
+    int32_t j0 = floor_div256(xmin - 128 + 255), j1 = floor_div256(xmax - 128);
+    int32_t i0 = floor_div256(ymin - 128 + 255), i1 = floor_div256(ymax - 128);
+    j0 = max(j0, 0); i0 = max(i0, 0);
+    j1 = min(j1, res - 1); i1 = min(i1, res - 1);
+    fb.j0 = j0; fb.i0 = i0;
+    fb.w = j1 - j0 + 1; fb.h = i1 - i0 + 1;
+    if (fb.w <= 0 || fb.h <= 0) fb.ok = false;
+    return fb;
+}
+
+// Edge functions of the edges opposite corners 0, 1, 2 at texel (i, j).
+__device__ __forceinline__ bool cover(const FaceBox& fb, int32_t i, int32_t j, int64_t E[3],
+                                      int64_t* S) {
+    int64_t cx = 256 * (int64_t)j + 128, cy = 256 * (int64_t)i + 128;
+    const int32_t* X = fb.X;
+    const int32_t* Y = fb.Y;
+    E[0] = (int64_t)(X[2] - X[1]) * (cy - Y[1]) - (int64_t)(Y[2] - Y[1]) * (cx - X[1]);
+    E[1] = (int64_t)(X[0] - X[2]) * (cy - Y[2]) - (int64_t)(Y[0] - Y[2]) * (cx - X[2]);
+    E[2] = (int64_t)(X[1] - X[0]) * (cy - Y[0]) - (int64_t)(Y[1] - Y[0]) * (cx - X[0]);
+    *S = E[0] + E[1] + E[2];
+    bool in = (E[0] >= 0 && E[1] >= 0 && E[2] >= 0) || (E[0] <= 0 && E[1] <= 0 && E[2] <= 0);
+    return in && *S != 0;
+}
+
+constexpr int kRasterBlock = 256;
+constexpr int kWavesPerBlock = kRasterBlock / 64;
+
+__global__ __launch_bounds__(kRasterBlock) void raster_claim_kernel(const int4* __restrict__ face_uv,
+                                                                    int64_t nf, int32_t res,
+                                                                    uint32_t* __restrict__ facemap) {
+    int64_t f = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    int lane = threadIdx.x & 63;
+    if (f >= nf) return;
+    FaceBox fb = load_face_box(face_uv, f, res);
+    if (!fb.ok) return;
+    int64_t total = (int64_t)fb.w * fb.h;
+    for (int64_t k = lane; k < total; k += 64) {
+        int32_t i = fb.i0 + (int32_t)(k / fb.w), j = fb.j0 + (int32_t)(k % fb.w);
+        int64_t E[3], S;
+        if (cover(fb, i, j, E, &S)) atomicMin(&facemap[(int64_t)i * res + j], (uint32_t)f);
+    }
+}
+
+__global__ __launch_bounds__(kRasterBlock) void raster_count_kernel(const int4* __restrict__ face_uv,
+                                                                    int64_t nf, int32_t res,
+                                                                    const uint32_t* __restrict__ facemap,
+                                                                    uint32_t* __restrict__ cnt) {
+    int64_t f = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    int lane = threadIdx.x & 63;
+    if (f >= nf) return;
+    FaceBox fb = load_face_box(face_uv, f, res);
+    uint32_t c = 0;
+    if (fb.ok) {
+        int64_t total = (int64_t)fb.w * fb.h;
+        for (int64_t k0 = 0; k0 < total; k0 += 64) {
+            int64_t k = k0 + lane;
+            bool win = false;
+            if (k < total) {
+                int32_t i = fb.i0 + (int32_t)(k / fb.w), j = fb.j0 + (int32_t)(k % fb.w);
+                int64_t E[3], S;
+                win = cover(fb, i, j, E, &S) && facemap[(int64_t)i * res + j] == (uint32_t)f;
+            }
+            c += (uint32_t)__popcll(__ballot(win));
+        }
+    }
+    if (lane == 0) cnt[f] = c;
+}
+
+__global__ __launch_bounds__(kRasterBlock) void raster_emit_kernel(const int4* __restrict__ face_uv,
+                                                                   int64_t nf, int32_t res,
+                                                                   const uint32_t* __restrict__ facemap,
+                                                                   const uint32_t* __restrict__ off,
+                                                                   Ray* __restrict__ rays) {
+    int64_t f = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    int lane = threadIdx.x & 63;
+    if (f >= nf) return;
+    FaceBox fb = load_face_box(face_uv, f, res);
+    if (!fb.ok) return;
+    int64_t total = (int64_t)fb.w * fb.h;
+    uint32_t run = off[f];
+    for (int64_t k0 = 0; k0 < total; k0 += 64) {
+        int64_t k = k0 + lane;
+        bool win = false;
+        int64_t E[3] = {0, 0, 0}, S = 1;
+        int32_t i = 0, j = 0;
+        if (k < total) {
+            i = fb.i0 + (int32_t)(k / fb.w);
+            j = fb.j0 + (int32_t)(k % fb.w);
+            win = cover(fb, i, j, E, &S) && facemap[(int64_t)i * res + j] == (uint32_t)f;
+        }
+        uint64_t m = __ballot(win);
+        if (win) {
+            uint32_t r = run + (uint32_t)__popcll(m & __lanemask_lt());
+            Ray ray;
+            ray.texel = i * res + j;
+            ray.face = (int32_t)f;
+            float fs = (float)S;
+            ray.b1 = (float)E[1] / fs;
+            ray.b2 = (float)E[2] / fs;
+            rays[r] = ray;
+        }
+        run += (uint32_t)__popcll(m);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Uncovered texels, dilation, RGB8
+// ---------------------------------------------------------------------------
+
+__global__ void fill_uncovered_kernel(const uint32_t* __restrict__ facemap, int64_t ntex,
+                                      float* __restrict__ map, int32_t* __restrict__ hit,
+                                      uint8_t* __restrict__ level) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntex) return;
+    bool cov = facemap[t] != 0x7FFFFFFFu;
+    level[t] = cov ? 0 : 255;
+    if (!cov) {
+        map[3 * t] = 0.f;
+        map[3 * t + 1] = 0.f;
+        map[3 * t + 2] = 1.f;
+        hit[t] = kUncovered;
+    }
+}
+
+// Pass k: a still-empty texel takes the normalised sum of its 8 neighbours
+// that had a value before this pass (level < k).  Texels written in this pass
+// are never read in it, so the map is updated in place.
+__global__ void dilate_kernel(int32_t res, int pass, float* __restrict__ map,
+                              uint8_t* __restrict__ level) {
+    int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t i = blockIdx.y;
+    if (j >= res) return;
+    int64_t t = (int64_t)i * res + j;
+    if (level[t] != 255) return;
+    float sx = 0.f, sy = 0.f, sz = 0.f;
+    int cnt = 0;
+#pragma unroll
+    for (int di = -1; di <= 1; ++di) {
+#pragma unroll
+        for (int dj = -1; dj <= 1; ++dj) {
+            if (di == 0 && dj == 0) continue;
+            int32_t ii = i + di, jj = j + dj;
+            if (ii < 0 || jj < 0 || ii >= res || jj >= res) continue;
+            int64_t u = (int64_t)ii * res + jj;
+            if (level[u] < pass) {
+                sx += map[3 * u];
+                sy += map[3 * u + 1];
+                sz += map[3 * u + 2];
+                ++cnt;
+            }
+        }
+    }
+    if (cnt == 0) return;
+    float l2 = sx * sx + sy * sy + sz * sz;
+    if (!(l2 > 0.f)) return;
+    float r = 1.0f / sqrtf(l2);
+    map[3 * t] = sx * r;
+    map[3 * t + 1] = sy * r;
+    map[3 * t + 2] = sz * r;
+    level[t] = (uint8_t)pass;
+}
+
+__global__ void rgb8_kernel(const float* __restrict__ map, int64_t n, uint8_t* __restrict__ out) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    float c = floorf((map[k] + 1.0f) * 127.5f + 0.5f);
+    c = fminf(fmaxf(c, 0.0f), 255.0f);
+    out[k] = (uint8_t)c;
+}
+
+inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+hipError_t launch_lo_prep(const float* lo_V, int64_t nlv, const int32_t* lo_F, int64_t nlf,
+                          const float* lo_UV, int32_t res, const Layout& L, char* ws,
+                          hipStream_t s) {
+    uint32_t* deg = (uint32_t*)(ws + L.lo_deg);
+    uint32_t* off = (uint32_t*)(ws + L.lo_off);
+    uint32_t* cur = (uint32_t*)(ws + L.lo_cur);
+    hipError_t e;
+    if ((e = fill_u32(deg, 0, nlv, s)) != hipSuccess) return e;
+    if ((e = fill_u32(cur, 0, nlv, s)) != hipSuccess) return e;
+    if (nlf > 0) {
+        hipLaunchKernelGGL(lo_face_kernel, dim3(blocks_for(nlf, 256)), dim3(256), 0, s, lo_V, nlv,
+                           lo_F, nlf, lo_UV, res, (float4*)(ws + L.face_t), (int4*)(ws + L.face_uv),
+                           deg, (uint32_t*)(ws + L.status));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if ((e = exclusive_scan_u32(deg, off, nlv, (uint32_t*)(ws + L.scan_tmp), off + nlv, s)) !=
+        hipSuccess)
+        return e;
+    if (nlf > 0) {
+        hipLaunchKernelGGL(lo_adj_kernel, dim3(blocks_for(nlf, 256)), dim3(256), 0, s, lo_F, nlv,
+                           nlf, (const uint32_t*)off, cur, (int32_t*)(ws + L.lo_adj));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (nlv > 0) {
+        hipLaunchKernelGGL(lo_normal_kernel, dim3(blocks_for(nlv, 256)), dim3(256), 0, s, lo_V,
+                           nlv, lo_F, (const uint32_t*)off, (int32_t*)(ws + L.lo_adj),
+                           (float4*)(ws + L.lo_n));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_raster(int64_t nlf, int32_t res, const Layout& L, char* ws, hipStream_t s) {
+    uint32_t* facemap = (uint32_t*)(ws + L.facemap);
+    uint32_t* cnt = (uint32_t*)(ws + L.face_cnt);
+    uint32_t* off = (uint32_t*)(ws + L.face_off);
+    uint32_t* counters = (uint32_t*)(ws + L.counters);
+    const int4* fuv = (const int4*)(ws + L.face_uv);
+    hipError_t e;
+    if ((e = fill_u32(facemap, 0x7FFFFFFFu, L.n_texels, s)) != hipSuccess) return e;
+    if (nlf == 0) return fill_u32(counters + kCntRays, 0, 1, s);
+    unsigned g = blocks_for(nlf, kWavesPerBlock);
+    hipLaunchKernelGGL(raster_claim_kernel, dim3(g), dim3(kRasterBlock), 0, s, fuv, nlf, res, facemap);
+    hipLaunchKernelGGL(raster_count_kernel, dim3(g), dim3(kRasterBlock), 0, s, fuv, nlf, res,
+                       (const uint32_t*)facemap, cnt);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = exclusive_scan_u32(cnt, off, nlf, (uint32_t*)(ws + L.scan_tmp), counters + kCntRays,
+                                s)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(raster_emit_kernel, dim3(g), dim3(kRasterBlock), 0, s, fuv, nlf, res,
+                       (const uint32_t*)facemap, (const uint32_t*)off, (Ray*)(ws + L.rays));
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_uncovered(int32_t res, float* out_map, int32_t* out_hit, const Layout& L,
+                                 char* ws, hipStream_t s) {
+    int64_t n = L.n_texels;
+    hipLaunchKernelGGL(fill_uncovered_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s,
+                       (const uint32_t*)(ws + L.facemap), n, out_map, out_hit,
+                       (uint8_t*)(ws + L.level));
+    return hipGetLastError();
+}
+
+hipError_t launch_dilate(int32_t res, int passes, float* out_map, const Layout& L, char* ws,
+                         hipStream_t s) {
+    int bx = res < 256 ? res : 256;
+    dim3 grid((unsigned)((res + bx - 1) / bx), (unsigned)res);
+    for (int k = 1; k <= passes; ++k) {
+        hipLaunchKernelGGL(dilate_kernel, grid, dim3(bx), 0, s, res, k, out_map,
+                           (uint8_t*)(ws + L.level));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_rgb8(int32_t res, const float* out_map, uint8_t* rgb, hipStream_t s) {
+    int64_t n = (int64_t)res * res * 3;
+    hipLaunchKernelGGL(rgb8_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, out_map, n, rgb);
+    return hipGetLastError();
+}
+
+}  // namespace bake

@@ -1,0 +1,434 @@
+// Per-texel correspondence query and tangent-space encoding (Sec. 6.4): for
+// each covered texel, build the ray from the G-buffer (world position and
+// interpolated smooth normal), find the high-poly hit with the smallest |t| in
+// [-max_dist, +max_dist] (ties to the lower original triangle index),
+// interpolate the high-poly normal with the hit's barycentric weights and
+// project it into the texel's tangent frame.
+//
+// Traversal:
+//   * persistent waves; lanes whose ray is finished are refilled from a device
+//     work queue (wave-level compaction after Aila & Laine 2009), so a wave
+//     keeps doing useful work while rays of different lengths finish;
+//   * conservative slab test: near/far planes picked by the sign of the
+//     direction, t widened outward by a relative 1e-6 (after Ize 2013); a zero
+//     direction component yields NaN for a ray lying in a slab plane, which
+//     the NaN-ignoring min3/max3 treat as an unbounded slab;
+//   * pruning is strict (a node is skipped only if its nearest |t| is larger
+//     than the best |t|), so equal-|t| candidates with a lower index are still
+//     found and the result equals a brute-force scan under the same triangle
+//     test, independent of the tree;
+//   * watertight ray/triangle test (Woop, Benthin & Wald 2013): shear to ray
+//     space, edge functions as differences of two rounded products with FP
+//     contraction off, so a shared edge gives exactly opposite values in the
+//     two faces; two-sided, edges inclusive;
+//   * short per-lane stack in LDS, spilling its oldest entries to a per-lane
+//     global area when full (the Karras tree depth is bounded by 62).
+#include "internal.h"
+
+namespace bake {
+
+namespace {
+
+constexpr int32_t kEmpty = INT32_MIN;
+constexpr float kPad = 1e-6f;
+constexpr uint32_t kFaceReliable = 1u;
+
+struct float3x3 {
+    float3 r0, r1, r2;
+};
+
+__device__ __forceinline__ float3 f3(float x, float y, float z) { return make_float3(x, y, z); }
+__device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ float3 cross3(float3 a, float3 b) {
+    return f3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ float3 ld3(const float* p, int64_t i) {
+    return f3(p[3 * i], p[3 * i + 1], p[3 * i + 2]);
+}
+__device__ __forceinline__ float comp(float3 v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
+
+// Edge function of two sheared vertices, as a difference of two rounded
+// products (no FMA): swapping the arguments negates the result exactly.
+__device__ __forceinline__ float edge_fn(float xa, float ya, float xb, float yb) {
+#pragma clang fp contract(off)
+    float p = xa * yb;
+    float q = ya * xb;
+    return p - q;
+}
+
+// Ray state for the slab and triangle tests.
+struct RayT {
+    float3 p;
+    float3 invd;    // 1/d with +inf for a zero component
+    uint32_t sgn;   // bit k set: d_k < 0 (near plane is the box max)
+    float3x3 S;     // rows of the shear: (Ax, Ay, Az) = S (v - p)
+};
+
+__device__ __forceinline__ RayT make_rayt(float3 p, float3 d) {
+    RayT r;
+    r.p = p;
+    r.invd = f3(d.x == 0.f ? INFINITY : 1.0f / d.x, d.y == 0.f ? INFINITY : 1.0f / d.y,
+                d.z == 0.f ? INFINITY : 1.0f / d.z);
+    r.sgn = (d.x < 0.f ? 1u : 0u) | (d.y < 0.f ? 2u : 0u) | (d.z < 0.f ? 4u : 0u);
+    float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
+    int kz = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
+    int kx = kz == 2 ? 0 : kz + 1;
+    int ky = kx == 2 ? 0 : kx + 1;
+    if (comp(d, kz) < 0.f) {
+        int t = kx; kx = ky; ky = t;
+    }
+    float dz = comp(d, kz);
+    float Sx = comp(d, kx) / dz, Sy = comp(d, ky) / dz, Sz = 1.0f / dz;
+    float rx[3] = {0.f, 0.f, 0.f}, ry[3] = {0.f, 0.f, 0.f}, rz[3] = {0.f, 0.f, 0.f};
+    rx[kx] = 1.f; rx[kz] = -Sx;
+    ry[ky] = 1.f; ry[kz] = -Sy;
+    rz[kz] = Sz;
+    r.S.r0 = f3(rx[0], rx[1], rx[2]);
+    r.S.r1 = f3(ry[0], ry[1], ry[2]);
+    r.S.r2 = f3(rz[0], rz[1], rz[2]);
+    return r;
+}
+
+__device__ __forceinline__ float3 shear(const RayT& r, float3 v) {
+    float3 a = f3(v.x - r.p.x, v.y - r.p.y, v.z - r.p.z);
+    return f3(fmaf(r.S.r0.z, a.z, fmaf(r.S.r0.y, a.y, r.S.r0.x * a.x)),
+              fmaf(r.S.r1.z, a.z, fmaf(r.S.r1.y, a.y, r.S.r1.x * a.x)),
+              fmaf(r.S.r2.z, a.z, fmaf(r.S.r2.y, a.y, r.S.r2.x * a.x)));
+}
+
+// Slab test of box [lo, hi]; on overlap with [-best, best] returns true and the
+// smallest |t| of the (widened) overlap in *mint.
+__device__ __forceinline__ bool box_test(const RayT& r, float3 lo, float3 hi, float best,
+                                         float* mint) {
+    float nx = (r.sgn & 1u) ? hi.x : lo.x, fx = (r.sgn & 1u) ? lo.x : hi.x;
+    float ny = (r.sgn & 2u) ? hi.y : lo.y, fy = (r.sgn & 2u) ? lo.y : hi.y;
+    float nz = (r.sgn & 4u) ? hi.z : lo.z, fz = (r.sgn & 4u) ? lo.z : hi.z;
+    float t0x = (nx - r.p.x) * r.invd.x, t1x = (fx - r.p.x) * r.invd.x;
+    float t0y = (ny - r.p.y) * r.invd.y, t1y = (fy - r.p.y) * r.invd.y;
+    float t0z = (nz - r.p.z) * r.invd.z, t1z = (fz - r.p.z) * r.invd.z;
+    float t0 = fmaxf(fmaxf(t0x, t0y), t0z);
+    float t1 = fminf(fminf(t1x, t1y), t1z);
+    // widen outward; a multiply keeps +-inf finite-signed (no inf - inf)
+    t0 = t0 * (t0 > 0.f ? 1.0f - kPad : 1.0f + kPad);
+    t1 = t1 * (t1 > 0.f ? 1.0f + kPad : 1.0f - kPad);
+    t0 = fmaxf(t0, -best);
+    t1 = fminf(t1, best);
+    *mint = t0 > 0.f ? t0 : (t1 < 0.f ? -t1 : 0.f);
+    return t0 <= t1;
+}
+
+// Watertight two-sided test; on a better (|t|, id) hit updates the best.
+__device__ __forceinline__ void tri_test(const RayT& r, const Leaf& L, float max_dist, float* best,
+                                         int32_t* best_id, float* best_t, float* bb1, float* bb2) {
+    float3 v0 = f3(L.a.x, L.a.y, L.a.z), v1 = f3(L.a.w, L.b.x, L.b.y), v2 = f3(L.b.z, L.b.w, L.c.x);
+    int32_t id = __float_as_int(L.c.y);
+    float3 A = shear(r, v0), B = shear(r, v1), C = shear(r, v2);
+    float U = edge_fn(C.x, C.y, B.x, B.y);
+    float V = edge_fn(A.x, A.y, C.x, C.y);
+    float W = edge_fn(B.x, B.y, A.x, A.y);
+    float mn = fminf(fminf(U, V), W), mx = fmaxf(fmaxf(U, V), W);
+    if (mn < 0.f && mx > 0.f) return;
+    float det = U + V + W;
+    if (det == 0.f) return;
+    float T = U * A.z + V * B.z + W * C.z;
+    float t = T / det;
+    float at = fabsf(t);
+    if (!(at <= max_dist)) return;
+    if (at < *best || (at == *best && id < *best_id)) {
+        *best = at;
+        *best_id = id;
+        *best_t = t;
+        *bb1 = V / det;
+        *bb2 = W / det;
+    }
+}
+
+struct TravArgs {
+    const Ray* rays;
+    const uint32_t* nrays;  // device count
+    uint32_t* queue;        // device work queue head
+    const float* lo_V;
+    const int32_t* lo_F;
+    const float4* lo_n;
+    const float4* face_t;
+    const int4* face_uv;
+    const BvhNode* nodes;
+    const Leaf* leaves;
+    int32_t root;  // root ref, or kEmpty when there is no triangle
+    const int32_t* hi_F;
+    int64_t nhv;
+    const float* hi_N;
+    float max_dist;
+    float* out_map;
+    int32_t* out_hit;
+    Hit* hits;           // optional
+    int32_t* spill;      // [kMaxDepth][spill_lanes]
+    int64_t spill_lanes;
+    uint32_t* status;    // device status word
+    int64_t step_cap;    // per-ray safety bound on loop steps
+    int refill_min;      // refill when at least this many lanes are idle (64: whole wave)
+};
+
+template <int BLOCK, int STACK>
+__global__ __launch_bounds__(BLOCK) void traverse_kernel(TravArgs a) {
+    __shared__ int32_t stk[STACK][BLOCK];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int64_t gtid = (int64_t)blockIdx.x * BLOCK + tid;
+    const uint32_t nrays = *a.nrays;
+
+    bool active = false, exhausted = false;
+    uint32_t ridx = 0;
+    int32_t texel = 0, face = 0;
+    RayT R;
+    float3 d = f3(0.f, 0.f, 1.f), Tp = f3(1.f, 0.f, 0.f);
+    float hsign = 1.f;
+    float best = 0.f, best_t = 0.f, bb1 = 0.f, bb2 = 0.f;
+    int32_t best_id = INT32_MAX;
+    int32_t node = kEmpty;
+    int sp = 0, lo = 0;
+    int64_t steps = 0;
+
+    while (true) {
+        // ---- refill idle lanes from the work queue -------------------------
+        uint64_t idle = __ballot(!active);
+        if (!exhausted && (int)__popcll(idle) >= a.refill_min) {
+            int cnt = (int)__popcll(idle);
+            int leader = __ffsll((long long)idle) - 1;
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(a.queue, (uint32_t)cnt);
+            base = __shfl(base, leader, 64);
+            if (base >= nrays) exhausted = true;
+            if (!active) {
+                uint32_t k = base + (uint32_t)__popcll(idle & __lanemask_lt());
+                if (k < nrays) {
+                    ridx = k;
+                    Ray ray = a.rays[k];
+                    texel = ray.texel;
+                    face = ray.face;
+                    float b1 = ray.b1, b2 = ray.b2, b0 = 1.0f - b1 - b2;
+                    int32_t i0 = a.lo_F[3 * face], i1 = a.lo_F[3 * face + 1], i2 = a.lo_F[3 * face + 2];
+                    float3 V0 = ld3(a.lo_V, i0), V1 = ld3(a.lo_V, i1), V2 = ld3(a.lo_V, i2);
+                    float4 n0 = a.lo_n[i0], n1 = a.lo_n[i1], n2 = a.lo_n[i2];
+                    float3 p = f3(b0 * V0.x + b1 * V1.x + b2 * V2.x, b0 * V0.y + b1 * V1.y + b2 * V2.y,
+                                  b0 * V0.z + b1 * V1.z + b2 * V2.z);
+                    float3 m = f3(b0 * n0.x + b1 * n1.x + b2 * n2.x, b0 * n0.y + b1 * n1.y + b2 * n2.y,
+                                  b0 * n0.z + b1 * n1.z + b2 * n2.z);
+                    float4 T4 = a.face_t[face];
+                    uint32_t fl = (uint32_t)a.face_uv[2 * face + 1].z;
+                    bool rel = (fl & kFaceReliable) && n0.w != 0.f && n1.w != 0.f && n2.w != 0.f;
+                    float l2 = dot3(m, m);
+                    rel = rel && l2 > 0.f;
+                    float rl = rel ? 1.0f / sqrtf(l2) : 0.f;
+                    d = f3(m.x * rl, m.y * rl, m.z * rl);
+                    float3 T = f3(T4.x, T4.y, T4.z);
+                    float dt = dot3(d, T);
+                    Tp = f3(T.x - dt * d.x, T.y - dt * d.y, T.z - dt * d.z);
+                    float lt2 = dot3(Tp, Tp);
+                    rel = rel && lt2 > 0.f;
+                    hsign = T4.w;
+                    if (rel) {
+                        float rt = 1.0f / sqrtf(lt2);
+                        Tp = f3(Tp.x * rt, Tp.y * rt, Tp.z * rt);
+                        R = make_rayt(p, d);
+                        best = a.max_dist;
+                        best_id = INT32_MAX;
+                        best_t = 0.f;
+                        bb1 = bb2 = 0.f;
+                        node = a.root;
+                        sp = lo = 0;
+                        steps = 0;
+                        active = node != kEmpty;
+                        if (!active) best_id = INT32_MAX;  // no triangles: a miss
+                    }
+                    if (!active) {
+                        // unreliable (or nothing to hit): finish right away
+                        int32_t st = rel ? kMiss : kUnreliable;
+                        a.out_map[3 * (int64_t)texel] = 0.f;
+                        a.out_map[3 * (int64_t)texel + 1] = 0.f;
+                        a.out_map[3 * (int64_t)texel + 2] = 1.f;
+                        a.out_hit[texel] = st;
+                        if (a.hits) {
+                            Hit h; h.t = 0.f; h.beta1 = 0.f; h.beta2 = 0.f; h.id = st;
+                            a.hits[k] = h;
+                        }
+                    }
+                }
+            }
+        }
+        if (__ballot(active) == 0) {
+            if (exhausted) break;
+            continue;
+        }
+        if (!active) continue;
+
+        // ---- one traversal step -------------------------------------------
+        if (node >= 0) {
+            const BvhNode* nd = a.nodes + node;
+            float4 na = nd->a, nb = nd->b, nc = nd->c;
+            int4 ref = nd->ref;
+            float mL, mR;
+            bool hL = box_test(R, f3(na.x, na.y, na.z), f3(na.w, nb.x, nb.y), best, &mL);
+            bool hR = box_test(R, f3(nb.z, nb.w, nc.x), f3(nc.y, nc.z, nc.w), best, &mR);
+            int32_t next = kEmpty, other = kEmpty;
+            if (hL && hR) {
+                bool rfirst = mR < mL;
+                next = rfirst ? ref.y : ref.x;
+                other = rfirst ? ref.x : ref.y;
+            } else if (hL) {
+                next = ref.x;
+            } else if (hR) {
+                next = ref.y;
+            }
+            if (other != kEmpty) {
+                // push: spill the oldest LDS entry when the LDS part is full.
+                // The tree depth bound keeps lo < kMaxDepth; the check only
+                // guards against a malformed tree.
+                if (sp - lo == STACK) {
+                    if (lo < kMaxDepth) {
+                        a.spill[(int64_t)lo * a.spill_lanes + gtid] = stk[lo & (STACK - 1)][tid];
+                    } else {
+                        atomicOr(a.status, kStInternal);
+                    }
+                    ++lo;
+                }
+                stk[sp & (STACK - 1)][tid] = other;
+                ++sp;
+            }
+            node = next;
+        } else {
+            const Leaf L = a.leaves[~node];
+            tri_test(R, L, a.max_dist, &best, &best_id, &best_t, &bb1, &bb2);
+            node = kEmpty;
+        }
+        if (++steps > a.step_cap) {
+            atomicOr(a.status, kStInternal);
+            node = kEmpty;
+            sp = lo = 0;
+        }
+        if (node == kEmpty) {
+            // pop
+            if (sp > 0) {
+                if (sp == lo) {
+                    --lo;
+                    node = lo < kMaxDepth ? a.spill[(int64_t)lo * a.spill_lanes + gtid] : kEmpty;
+                } else {
+                    node = stk[(sp - 1) & (STACK - 1)][tid];
+                }
+                --sp;
+            }
+        }
+        if (node != kEmpty) continue;
+
+        // ---- finished: interpolate the hi normal and encode -----------------
+        active = false;
+        float3 out = f3(0.f, 0.f, 1.f);
+        int32_t st = kMiss;
+        float beta1 = 0.f, beta2 = 0.f;
+        if (best_id != INT32_MAX) {
+            int32_t g = best_id;
+            int32_t j0 = a.hi_F[3 * (int64_t)g], j1 = a.hi_F[3 * (int64_t)g + 1],
+                    j2 = a.hi_F[3 * (int64_t)g + 2];
+            bool ok = j0 >= 0 && j1 >= 0 && j2 >= 0 && j0 < a.nhv && j1 < a.nhv && j2 < a.nhv;
+            beta1 = bb1;
+            beta2 = bb2;
+            float beta0 = 1.0f - beta1 - beta2;
+            st = kUnreliable;
+            if (ok) {
+                float3 N0 = ld3(a.hi_N, j0), N1 = ld3(a.hi_N, j1), N2 = ld3(a.hi_N, j2);
+                float3 h = f3(beta0 * N0.x + beta1 * N1.x + beta2 * N2.x,
+                              beta0 * N0.y + beta1 * N1.y + beta2 * N2.y,
+                              beta0 * N0.z + beta1 * N1.z + beta2 * N2.z);
+                float lh2 = dot3(h, h);
+                if (lh2 > 0.f && isfinite(lh2)) {
+                    float rh = 1.0f / sqrtf(lh2);
+                    float3 n = f3(h.x * rh, h.y * rh, h.z * rh);
+                    float3 c = cross3(d, Tp);
+                    float3 Bp = f3(hsign * c.x, hsign * c.y, hsign * c.z);
+                    out = f3(dot3(n, Tp), dot3(n, Bp), dot3(n, d));
+                    st = g;
+                }
+            }
+        }
+        a.out_map[3 * (int64_t)texel] = out.x;
+        a.out_map[3 * (int64_t)texel + 1] = out.y;
+        a.out_map[3 * (int64_t)texel + 2] = out.z;
+        a.out_hit[texel] = st;
+        if (a.hits) {
+            Hit h;
+            h.t = best_t;
+            h.beta1 = beta1;
+            h.beta2 = beta2;
+            h.id = st;
+            a.hits[ridx] = h;
+        }
+    }
+}
+
+template <int BLOCK, int STACK>
+hipError_t launch_one(const TravArgs& args, hipStream_t s, int64_t max_lanes) {
+    static int cached_blocks = -1;
+    if (cached_blocks < 0) {
+        int dev = 0, cus = 0, per = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, traverse_kernel<BLOCK, STACK>, BLOCK, 0);
+        if (e != hipSuccess) return e;
+        if (per < 1) per = 1;
+        cached_blocks = cus * per;
+    }
+    int64_t blocks = cached_blocks;
+    int64_t cap = max_lanes / BLOCK;
+    if (blocks > cap) blocks = cap;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL((traverse_kernel<BLOCK, STACK>), dim3((unsigned)blocks), dim3(BLOCK), 0, s, args);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_traverse(const float* lo_V, const int32_t* lo_F, int64_t nlf, const int32_t* hi_F,
+                           int64_t nhv, int64_t nhf, const float* hi_N, float max_dist, float* out_map,
+                           int32_t* out_hit, bool save, const TravConfig& cfg, const Layout& L,
+                           char* ws, hipStream_t s) {
+    (void)nlf;
+    uint32_t* counters = (uint32_t*)(ws + L.counters);
+    hipError_t e = fill_u32(counters + kCntQueue, 0, 1, s);
+    if (e != hipSuccess) return e;
+    TravArgs a;
+    a.rays = (const Ray*)(ws + L.rays);
+    a.nrays = counters + kCntRays;
+    a.queue = counters + kCntQueue;
+    a.lo_V = lo_V;
+    a.lo_F = lo_F;
+    a.lo_n = (const float4*)(ws + L.lo_n);
+    a.face_t = (const float4*)(ws + L.face_t);
+    a.face_uv = (const int4*)(ws + L.face_uv);
+    a.nodes = (const BvhNode*)(ws + L.nodes);
+    a.leaves = (const Leaf*)(ws + L.leaves);
+    a.root = nhf <= 0 ? kEmpty : (nhf == 1 ? ~0 : 0);
+    a.hi_F = hi_F;
+    a.nhv = nhv;
+    a.hi_N = hi_N;
+    a.max_dist = max_dist;
+    a.out_map = out_map;
+    a.out_hit = out_hit;
+    a.hits = save ? (Hit*)(ws + L.hits) : nullptr;
+    a.spill = (int32_t*)(ws + L.spill);
+    a.spill_lanes = L.spill_lanes;
+    a.refill_min = cfg.persist ? 16 : 64;
+    a.status = (uint32_t*)(ws + L.status);
+    a.step_cap = 4 * nhf + 1024;
+    int64_t lanes = L.spill_lanes;
+#define BAKE_TRAV_CASE(B, S) \
+    if (cfg.block == B && cfg.stack == S) return launch_one<B, S>(a, s, lanes);
+    BAKE_TRAV_CASE(64, 8) BAKE_TRAV_CASE(64, 16) BAKE_TRAV_CASE(64, 32)
+    BAKE_TRAV_CASE(128, 8) BAKE_TRAV_CASE(128, 16) BAKE_TRAV_CASE(128, 32)
+    BAKE_TRAV_CASE(256, 8) BAKE_TRAV_CASE(256, 16) BAKE_TRAV_CASE(256, 32)
+#undef BAKE_TRAV_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace bake

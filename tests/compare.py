@@ -1,0 +1,144 @@
+"""GPU-vs-oracle comparator for the normal bake.
+
+Parity rules (what "matches the oracle" means):
+  1. coverage (uncovered status) is bit-identical, and so is the unreliable
+     status decided before the query;
+  2. on covered, reliable texels the hit ids agree on at least 99.9 % of them;
+  3. every id disagreement is a tie: with tau* the oracle's best |t| (inf on a
+     miss), t_g the oracle's FP64 crossing of the GPU triangle's plane along the
+     oracle's ray and delta_g that crossing's distance from the triangle,
+     | |t_g| - tau* | <= 1e-6 max_dist, |t_g| <= max_dist (1 + 1e-6) and
+     delta_g <= 32 ulp_fp32(|q|); a GPU miss against an oracle hit is a tie
+     only when tau* >= (1 - 1e-6) max_dist, and a GPU hit against an oracle
+     miss only when |t_g| is that close to max_dist;
+  4. on same-id texels the angle between the tangent-space vectors is at most
+     0.05 degrees;
+  5. after dilation, uncovered texels agree within 0.05 degrees except next to
+     a tie.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+ANGLE_TOL_DEG = 0.05
+AGREE_MIN = 0.999
+TIE_REL = 1e-6
+DELTA_ULPS = 32
+
+
+def angle_deg(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    c = np.linalg.norm(np.cross(a, b), axis=-1)
+    d = np.einsum("...i,...i->...", a, b)
+    return np.degrees(np.arctan2(c, d))
+
+
+@dataclass
+class Report:
+    n_covered: int = 0
+    n_compared: int = 0
+    agree: float = 1.0
+    n_disagree: int = 0
+    n_ties: int = 0
+    max_angle: float = 0.0
+    p999_angle: float = 0.0
+    mean_angle: float = 0.0
+    max_dilated_angle: float = 0.0
+    failures: list = field(default_factory=list)
+
+    def ok(self):
+        return not self.failures
+
+    def __str__(self):
+        return (f"covered={self.n_covered} compared={self.n_compared} agree={self.agree:.6f} "
+                f"disagree={self.n_disagree} ties={self.n_ties} angle max={self.max_angle:.2e} "
+                f"p99.9={self.p999_angle:.2e} mean={self.mean_angle:.2e} "
+                f"dilated max={self.max_dilated_angle:.2e} failures={self.failures[:5]}")
+
+
+def compare(oracle, asset, ob, gpu_map: np.ndarray, gpu_hit: np.ndarray, check_dilation=True) -> Report:
+    """ob: oracle Bake (full or sampled); gpu_map [res*res,3], gpu_hit [res*res]."""
+    rep = Report()
+    res, md = ob.res, ob.max_dist
+    gm = np.asarray(gpu_map, np.float64).reshape(-1, 3)
+    gh = np.asarray(gpu_hit).reshape(-1).astype(np.int64)
+    cov = ob.face >= 0
+    rep.n_covered = int(cov.sum())
+    # 1. coverage
+    if not np.array_equal(gh == -3, ~cov):
+        bad = np.nonzero((gh == -3) != ~cov)[0]
+        rep.failures.append(f"coverage differs at {bad.size} texels, e.g. {bad[:5].tolist()}")
+        return rep
+    tex = ob.texels
+    oh = ob.hit.astype(np.int64)          # oracle query result per baked texel (-2 untraced)
+    ost = ob.status[tex].astype(np.int64)  # final oracle status
+    g = gh[tex]
+    # the unreliable status must match exactly
+    if not np.array_equal(g == -2, ost == -2):
+        rep.failures.append(f"unreliable status differs at {int(((g == -2) != (ost == -2)).sum())} texels")
+    rel = ost != -2
+    rep.n_compared = int(rel.sum())
+    if rep.n_compared == 0:
+        return rep
+    same = rel & (g == ost)
+    dis = rel & ~same
+    rep.n_disagree = int(dis.sum())
+    rep.agree = float(same.sum()) / rep.n_compared
+    # 3. every disagreement must be a tie
+    tie_mask = np.zeros_like(dis)
+    if rep.n_disagree:
+        idx = np.nonzero(dis)[0]
+        tau = np.where(oh[idx] >= 0, np.abs(ob.t[idx]), np.inf)
+        gg = g[idx]
+        has_g = gg >= 0
+        ok = np.zeros(idx.size, bool)
+        # GPU miss vs oracle hit: oracle hit must sit at the range end
+        ok[~has_g & (gg == -1)] = tau[~has_g & (gg == -1)] >= (1 - TIE_REL) * md
+        if has_g.any():
+            j = idx[has_g]
+            tg, dg = oracle.plane_check(asset.hi_V, asset.hi_F, ob.P[j], ob.D[j], gg[has_g])
+            q = ob.P[j] + tg[:, None] * ob.D[j]
+            ulp = np.spacing(np.linalg.norm(q, axis=1).astype(np.float32)).astype(np.float64)
+            within = (np.abs(tg) <= md * (1 + TIE_REL)) & (dg <= DELTA_ULPS * ulp)
+            t_ok = np.where(np.isfinite(tau[has_g]), np.abs(np.abs(tg) - tau[has_g]) <= TIE_REL * md,
+                            np.abs(tg) >= (1 - TIE_REL) * md)
+            ok[has_g] = within & t_ok
+        tie_mask[idx] = ok
+        rep.n_ties = int(ok.sum())
+        if not ok.all():
+            bad = idx[~ok][:5]
+            rep.failures.append(
+                f"{int((~ok).sum())} non-tie disagreements, e.g. texels {tex[bad].tolist()} "
+                f"gpu {g[bad].tolist()} oracle {ost[bad].tolist()}")
+    if rep.agree < AGREE_MIN:
+        rep.failures.append(f"id agreement {rep.agree:.6f} < {AGREE_MIN}")
+    # 4. angles on same-id texels (hits and neutral results alike)
+    ang = angle_deg(gm[tex][same], ob.map_raw[tex][same])
+    if ang.size:
+        rep.max_angle = float(ang.max())
+        rep.p999_angle = float(np.quantile(ang, 0.999))
+        rep.mean_angle = float(ang.mean())
+        if rep.max_angle > ANGLE_TOL_DEG:
+            rep.failures.append(f"max angle {rep.max_angle:.4f} deg > {ANGLE_TOL_DEG}")
+    # 5. dilated texels (full bakes only)
+    if check_dilation and tex.size == rep.n_covered:
+        unc = np.nonzero(~cov)[0]
+        near_tie = np.zeros(res * res, bool)
+        if rep.n_disagree:
+            t_ids = tex[dis]
+            ii, jj = t_ids // res, t_ids % res
+            for di in range(-3, 4):
+                for dj in range(-3, 4):
+                    a, b = ii + di, jj + dj
+                    m = (a >= 0) & (b >= 0) & (a < res) & (b < res)
+                    near_tie[a[m] * res + b[m]] = True
+        unc = unc[~near_tie[unc]]
+        if unc.size:
+            angd = angle_deg(gm[unc], ob.map[unc])
+            rep.max_dilated_angle = float(angd.max())
+            if rep.max_dilated_angle > ANGLE_TOL_DEG:
+                rep.failures.append(f"dilated max angle {rep.max_dilated_angle:.4f} deg")
+    return rep

@@ -1,0 +1,125 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+function declared in include/bake.h, and rejects bad arguments on the host
+with the documented codes before touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bake.h")
+
+
+@pytest.fixture(scope="module")
+def B():
+    import paper_2605_26137_amd.bake as bake
+    if not os.path.exists(bake.LIB_PATH):
+        from paper_2605_26137_amd import build
+        build.build()
+    bake.lib()
+    return bake
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\**\s*(bake_[a-z_0-9]+)\s*\(", src, re.M)))
+
+
+def test_every_declared_symbol_is_exported(B):
+    names = declared_functions()
+    assert len(names) >= 10, names
+    L = C.CDLL(B.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(B._EXPORTS), set(names) ^ set(B._EXPORTS)
+
+
+def test_version_and_defaults(B):
+    assert "gfx950" in B.version()
+    o = B.make_options()
+    assert o.dilate_passes == 2 and o.flags == 0 and o.trav_persist == -1
+
+
+def test_workspace_size_grows_with_inputs(B):
+    s1 = B.workspace_size(2562, 5120, 42, 80, 128)
+    s2 = B.workspace_size(655362, 1310720, 10242, 20480, 2048)
+    assert 0 < s1 < s2
+    assert s1 % 256 == 0 and s2 % 256 == 0
+    save = B.workspace_size(2562, 5120, 42, 80, 128, B.make_options(save=True))
+    assert save >= s1 + 16 * 128 * 128
+
+
+@pytest.mark.parametrize("res", [0, 3, 100, 32768, -4])
+def test_bad_res_is_unsupported(B, res):
+    with pytest.raises(B.BakeError) as e:
+        B.workspace_size(10, 10, 10, 10, res)
+    assert e.value.code == B.BAKE_E_UNSUPPORTED
+
+
+def test_negative_and_inconsistent_counts(B):
+    for args in [(-1, 1, 1, 1), (1, -1, 1, 1), (0, 5, 3, 1), (3, 1, 0, 4)]:
+        with pytest.raises(B.BakeError) as e:
+            B.workspace_size(*args, 64)
+        assert e.value.code == B.BAKE_E_INVALID_ARG
+
+
+def _call(B, **over):
+    """bake_normals with fake (never dereferenced) device pointers."""
+    fake = C.c_void_p(0x1000)
+    a = dict(hi_V=fake, nhv=3, hi_F=fake, nhf=1, hi_N=fake, lo_V=fake, nlv=3, lo_F=fake, nlf=1,
+             lo_UV=fake, res=16, max_dist=0.1, out_map=fake, out_hit=fake, opt=None,
+             ws=C.c_void_p(0x100000), ws_bytes=1 << 40, stream=None)
+    a.update(over)
+    return B.lib().bake_normals(a["hi_V"], a["nhv"], a["hi_F"], a["nhf"], a["hi_N"], a["lo_V"],
+                                a["nlv"], a["lo_F"], a["nlf"], a["lo_UV"], a["res"], a["max_dist"],
+                                a["out_map"], a["out_hit"], a["opt"], a["ws"], a["ws_bytes"],
+                                a["stream"])
+
+
+@pytest.mark.parametrize("over,code", [
+    (dict(hi_V=None), -1), (dict(hi_N=None), -1), (dict(hi_F=None), -1), (dict(lo_V=None), -1),
+    (dict(lo_F=None), -1), (dict(lo_UV=None), -1), (dict(out_map=None), -1), (dict(out_hit=None), -1),
+    (dict(max_dist=0.0), -1), (dict(max_dist=-1.0), -1), (dict(max_dist=float("inf")), -1),
+    (dict(max_dist=float("nan")), -1), (dict(res=12), -2), (dict(nhv=-2), -1),
+    (dict(ws=None), -3), (dict(ws=C.c_void_p(0x100010)), -3), (dict(ws_bytes=1000), -3),
+])
+def test_host_validation_codes(B, over, code):
+    rc = _call(B, **over)
+    assert rc == code, B.lib().bake_last_error()
+    assert B.lib().bake_last_error()
+
+
+@pytest.mark.parametrize("field,val", [("dilate_passes", -1), ("dilate_passes", 65), ("flags", 64),
+                                       ("trav_block", 96), ("trav_stack", 12), ("trav_persist", 2)])
+def test_bad_options(B, field, val):
+    o = B.make_options()
+    setattr(o, field, val)
+    rc = _call(B, opt=C.byref(o))
+    assert rc == B.BAKE_E_INVALID_ARG
+
+
+def test_backward_requires_saved_state_and_stage_times_require_timing(B):
+    buf = (C.c_float * 6)()
+    assert B.lib().bake_stage_times(buf, 6) == B.BAKE_E_STATE
+
+
+def test_workspace_views(B):
+    o, b = B.workspace_view(2562, 5120, 42, 80, 128, B.VIEW_RAYS)
+    assert o % 256 == 0 and b == 16 * 128 * 128
+    with pytest.raises(B.BakeError):
+        B.workspace_view(2562, 5120, 42, 80, 128, B.VIEW_HITS)
+    o2, _ = B.workspace_view(2562, 5120, 42, 80, 128, B.VIEW_HITS, B.make_options(save=True))
+    assert o2 % 256 == 0
+
+
+def test_product_does_not_reach_the_oracle():
+    """The GPU package never imports the oracle (no CPU fallback path)."""
+    pkg = os.path.join(ROOT, "paper_2605_26137_amd")
+    for dp, _, fs in os.walk(pkg):
+        for f in fs:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dp, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
+                assert "liboracle" not in txt, f
