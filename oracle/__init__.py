@@ -11,8 +11,12 @@ paper's bake (Sec. 6.4 "Normal Map Baking"):
 1. low-poly smooth vertex normals and per-face tangent frames / reliability;
 2. UV-space rasterisation of the low-poly (texel -> face, barycentrics);
 3. per texel a world position p and the interpolated smooth normal d;
-4. nearest |t| line hit on the high-poly within +-max_dist (brute force over
-   every triangle, or the independent FP64 BVH pinned against it);
+4. nearest line hit on the high-poly within +-max_dist (brute force over
+   every triangle, or the independent FP64 BVH pinned against it).  A triangle
+   is hit when the crossing's barycentric weights are all >= -EDGE_EPS; the
+   winner minimises (floor(|t| / w), index) with w = max_dist * 2^-20, so a
+   line through a shared edge or vertex, or two surfaces at the same distance,
+   resolve to the lower triangle index robustly;
 5. barycentric high-poly normal, projection into the tangent frame, neutral
    (0,0,1) for misses / unreliable / uncovered texels;
 6. chart dilation.
@@ -158,12 +162,22 @@ def dilate(map_flat, level, res, passes):
 
 
 def plane_check(hi_V, hi_F, P, D, g):
+    """Per (ray, triangle): plane crossing t, distance of the crossing from the
+    triangle, smallest barycentric weight of the crossing."""
     hi_V = _c(hi_V, np.float32); hi_F = _c(hi_F, np.int32)
     P = _c(P, np.float64); D = _c(D, np.float64); g = _c(g, np.int32)
     n = g.shape[0]
-    t = np.zeros(n); dl = np.zeros(n)
-    _call("orc_plane_check", _p(hi_V), _p(hi_F), C.c_int64(n), _p(P), _p(D), _p(g), _p(t), _p(dl))
-    return t, dl
+    t = np.zeros(n); dl = np.zeros(n); bm = np.zeros(n)
+    _call("orc_plane_check", _p(hi_V), _p(hi_F), C.c_int64(n), _p(P), _p(D), _p(g), _p(t), _p(dl), _p(bm))
+    return t, dl, bm
+
+
+EDGE_EPS = 1.0 / 1024.0   # relative edge tolerance of the hit rule (barycentric units)
+T_QUANT_BITS = 20         # distance quantum w = max_dist * 2^-20
+
+
+def t_quantum(max_dist):
+    return max_dist * 2.0 ** -T_QUANT_BITS
 
 
 @dataclass

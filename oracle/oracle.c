@@ -31,7 +31,13 @@
  *     products (area weighted);
  *   tangent frame from the snapped UV deltas; per texel Gram-Schmidt against the
  *     interpolated normal; bitangent = h_f * (d x T');
- *   status: >= 0 hit id, -1 miss, -2 unreliable, -3 uncovered.
+ *   status: >= 0 hit id, -1 miss, -2 unreliable, -3 uncovered;
+ *   hit rule: a triangle is hit when the line crosses its plane at barycentric
+ *     weights all >= -EDGE_EPS (a relative edge tolerance, so a line grazing a
+ *     shared edge or vertex hits every face there); among hits with |t| <=
+ *     max_dist the winner minimises (floor(|t| / w), index) with the distance
+ *     quantum w = max_dist * 2^-20, so hits whose distances agree to within
+ *     the quantum resolve to the lower triangle index.
  */
 #include <math.h>
 #include <stdint.h>
@@ -41,6 +47,10 @@
 
 #define ORC_OK 0
 #define ORC_EINVAL -1
+
+/* relative edge tolerance (in barycentric units) and distance quantum */
+#define EDGE_EPS (1.0 / 1024.0)
+#define T_QUANT_BITS 20
 
 #define ST_MISS -1
 #define ST_UNREL -2
@@ -233,26 +243,30 @@ static double svol(v3 p, v3 d, const float *V, int32_t ia, int32_t ib) {
     return -dot(d, cross(sub(ld3f(V, ib), p), sub(ld3f(V, ia), p)));
 }
 
-/* Line p + t d against triangle g.  Hit iff the three volumes share a sign
- * (zeros allowed) and are not all zero.  beta = (s_bc, s_ca, s_ab) / sum,
+/* Line p + t d against triangle g.  With the three volumes s_k and their sum
+ * S != 0, the plane crossing has barycentric weights beta = (s_bc, s_ca,
+ * s_ab) / S; the triangle is hit iff every weight is >= -EDGE_EPS.
  * q = sum beta_k v_k, t = (q - p) . d.  Returns 1 on a hit. */
 static int tri_hit(v3 p, v3 d, const float *V, const int32_t *F, int64_t g, double *t, double beta[3]) {
     int32_t a = F[3 * g], b = F[3 * g + 1], c = F[3 * g + 2];
     double s0 = svol(p, d, V, b, c), s1 = svol(p, d, V, c, a), s2 = svol(p, d, V, a, b);
-    int pos = s0 >= 0 && s1 >= 0 && s2 >= 0;
-    int neg = s0 <= 0 && s1 <= 0 && s2 <= 0;
-    if (!(pos || neg)) return 0;
     double S = s0 + s1 + s2;
     if (S == 0) return 0;
     beta[0] = s0 / S; beta[1] = s1 / S; beta[2] = s2 / S;
+    if (beta[0] < -EDGE_EPS || beta[1] < -EDGE_EPS || beta[2] < -EDGE_EPS) return 0;
     v3 q = add(add(scl(ld3f(V, a), beta[0]), scl(ld3f(V, b), beta[1])), scl(ld3f(V, c), beta[2]));
     *t = dot(sub(q, p), d);
     return 1;
 }
 
-/* (|t|, g) lexicographic order: is (ta, ga) better than (tb, gb)? */
-static int better(double ta, int64_t ga, double tb, int64_t gb) {
-    double a = fabs(ta), b = fabs(tb);
+/* Distance key: floor(|t| / w) with w = max_dist * 2^-T_QUANT_BITS. */
+static int64_t tkey(double t, double max_dist) {
+    return (int64_t)floor(fabs(t) * ldexp(1.0, T_QUANT_BITS) / max_dist);
+}
+
+/* (key, g) lexicographic order: is (ta, ga) better than (tb, gb)? */
+static int better(double ta, int64_t ga, double tb, int64_t gb, double max_dist) {
+    int64_t a = tkey(ta, max_dist), b = tkey(tb, max_dist);
     return a < b || (a == b && ga < gb);
 }
 
@@ -270,7 +284,7 @@ int orc_query_brute(const float *V, const int32_t *F, int64_t nf, int64_t n, con
                 double t, beta[3];
                 if (!tri_hit(p, d, V, F, g, &t, beta)) continue;
                 if (fabs(t) > max_dist) continue;
-                if (best < 0 || better(t, g, bt, best)) {
+                if (best < 0 || better(t, g, bt, best, max_dist)) {
                     best = (int32_t)g; bt = t; bb[0] = beta[0]; bb[1] = beta[1]; bb[2] = beta[2];
                 }
             }
@@ -330,10 +344,11 @@ static int64_t build_rec(bvh *B, const float *V, const int32_t *F, double *cent,
             if (x > chi[k]) chi[k] = x;
         }
     }
-    /* pad outward so the box test can never reject a triangle the exact
-     * triangle test would accept */
+    /* pad outward so the box test can never reject a triangle the triangle
+     * test would accept: with weights >= -EDGE_EPS the crossing lies in the
+     * triangle scaled by (1 + 3 EDGE_EPS) about its centroid */
     for (int k = 0; k < 3; ++k) {
-        double pad = 1e-9 * (1.0 + fabs(nd->lo[k]) + fabs(nd->hi[k]));
+        double pad = 3.0 * EDGE_EPS * (nd->hi[k] - nd->lo[k]) + 1e-9 * (1.0 + fabs(nd->lo[k]) + fabs(nd->hi[k]));
         nd->lo[k] -= pad;
         nd->hi[k] += pad;
     }
@@ -388,22 +403,24 @@ static int32_t bvh_query(const bvh *B, const float *V, const int32_t *F, v3 p, v
     int sp = 0;
     stack[sp++] = 0;
     int32_t best = -1;
-    double bt = 0, bound = max_dist;
+    double bt = 0, bound = max_dist * (1.0 + 1e-12);
+    const double w = max_dist * ldexp(1.0, -T_QUANT_BITS);
     while (sp > 0) {
         const bnode *nd = &B->nodes[stack[--sp]];
         double t0, t1;
         if (!box_interval(nd, p, d, &t0, &t1)) continue;
-        if (t0 > bound || t1 < -bound) continue; /* strict: equal |t| still visited */
+        if (t0 > bound || t1 < -bound) continue; /* a node reaching the best key's bin is visited */
         if (nd->left < 0) {
             for (int64_t i = nd->first; i < nd->first + nd->count; ++i) {
                 int64_t g = B->perm[i];
                 double t, beta[3];
                 if (!tri_hit(p, d, V, F, g, &t, beta)) continue;
                 if (fabs(t) > max_dist) continue;
-                if (best < 0 || better(t, g, bt, best)) {
+                if (best < 0 || better(t, g, bt, best, max_dist)) {
                     best = (int32_t)g; bt = t;
                     beta_out[0] = beta[0]; beta_out[1] = beta[1]; beta_out[2] = beta[2];
-                    bound = fabs(t);
+                    /* upper end of the best key's bin, widened */
+                    bound = (double)(tkey(t, max_dist) + 1) * w * (1.0 + 1e-12);
                 }
             }
         } else {
@@ -564,20 +581,30 @@ static double in_plane_dist(v3 q, v3 a, v3 b, v3 c) {
 }
 
 /* For each (ray, triangle g): t_g = line parameter where p + t d crosses g's
- * plane (NaN if parallel or degenerate) and delta_g = distance of that crossing
- * point from the triangle (0 inside). */
+ * plane (NaN if parallel or degenerate), delta_g = distance of that crossing
+ * point from the triangle (0 inside) and bmin_g = the smallest barycentric
+ * weight of the crossing (the quantity the hit rule thresholds). */
 int orc_plane_check(const float *V, const int32_t *F, int64_t n, const double *P, const double *D,
-                    const int32_t *g, double *t_out, double *delta_out) {
+                    const int32_t *g, double *t_out, double *delta_out, double *bmin_out) {
     for (int64_t r = 0; r < n; ++r) {
         v3 p = ld3d(P, r), d = ld3d(D, r);
         v3 a = ld3f(V, F[3 * g[r]]), b = ld3f(V, F[3 * g[r] + 1]), c = ld3f(V, F[3 * g[r] + 2]);
         v3 nn = cross(sub(b, a), sub(c, a));
         double den = dot(nn, d);
-        if (den == 0) { t_out[r] = NAN; delta_out[r] = INFINITY; continue; }
+        if (den == 0) { t_out[r] = NAN; delta_out[r] = INFINITY; if (bmin_out) bmin_out[r] = -INFINITY; continue; }
         double t = dot(nn, sub(a, p)) / den;
         v3 q = add(p, scl(d, t));
         t_out[r] = t;
         delta_out[r] = in_plane_dist(q, a, b, c);
+        if (bmin_out) {
+            int32_t ia = F[3 * g[r]], ib = F[3 * g[r] + 1], ic = F[3 * g[r] + 2];
+            double s0 = svol(p, d, V, ib, ic), s1 = svol(p, d, V, ic, ia), s2 = svol(p, d, V, ia, ib);
+            double S = s0 + s1 + s2;
+            double m = s0 / S;
+            if (s1 / S < m) m = s1 / S;
+            if (s2 / S < m) m = s2 / S;
+            bmin_out[r] = S != 0 ? m : -INFINITY;
+        }
     }
     return ORC_OK;
 }

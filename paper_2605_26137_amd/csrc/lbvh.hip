@@ -24,6 +24,7 @@ constexpr int kBlock = 256;
 constexpr int kSortRounds = 16;
 constexpr int kSortTile = kBlock * kSortRounds;  // 4096 keys per block and pass
 constexpr int kBoundsBlocks = 512;
+constexpr float kLeafEps = 1.0f / 1024.0f;  // edge tolerance of the hit rule (traverse.hip)
 
 __device__ __forceinline__ int3 tri_idx(const int32_t* __restrict__ F, int64_t g, int64_t nv,
                                         bool* bad) {
@@ -293,6 +294,17 @@ __global__ void leaf_refit_kernel(const float* __restrict__ V, int64_t nv, const
     float box[6] = {fminf(fminf(a.x, b.x), c.x), fminf(fminf(a.y, b.y), c.y),
                     fminf(fminf(a.z, b.z), c.z), fmaxf(fmaxf(a.x, b.x), c.x),
                     fmaxf(fmaxf(a.y, b.y), c.y), fmaxf(fmaxf(a.z, b.z), c.z)};
+    // The hit rule accepts crossings with barycentric weights down to
+    // -kLeafEps, i.e. inside the triangle scaled by (1 + 3 kLeafEps) about its
+    // centroid: widen the box by 4 kLeafEps of its extent (3 plus rounding
+    // margin) and a few ulps of its coordinates.
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        float ext = box[q + 3] - box[q];
+        float pad = 4.0f * kLeafEps * ext + 4.76837158e-7f * fmaxf(fabsf(box[q]), fabsf(box[q + 3]));
+        box[q] -= pad;
+        box[q + 3] += pad;
+    }
     int32_t pp = n > 1 ? leaf_parent[k] : -1;
     for (int level = 0; pp >= 0; ++level) {
         if (level > 2 * kMaxDepth) {  // only a malformed hierarchy gets here

@@ -13,14 +13,18 @@
 //     direction, t widened outward by a relative 1e-6 (after Ize 2013); a zero
 //     direction component yields NaN for a ray lying in a slab plane, which
 //     the NaN-ignoring min3/max3 treat as an unbounded slab;
-//   * pruning is strict (a node is skipped only if its nearest |t| is larger
-//     than the best |t|), so equal-|t| candidates with a lower index are still
-//     found and the result equals a brute-force scan under the same triangle
-//     test, independent of the tree;
+//   * hit rule: a triangle is hit when the crossing's barycentric weights are
+//     all >= -kEdgeEps (relative edge tolerance) and |t| <= max_dist; the
+//     winner minimises (floor(|t| / w), index) with the quantum w = max_dist
+//     2^-20, so a ray through a shared edge or vertex, or two surfaces at the
+//     same distance, resolve to the lower index instead of to rounding noise;
+//   * pruning keeps every node whose nearest |t| reaches the best key's bin,
+//     so the result equals a brute-force scan under the same triangle test,
+//     independent of the tree and of the visiting order;
 //   * watertight ray/triangle test (Woop, Benthin & Wald 2013): shear to ray
 //     space, edge functions as differences of two rounded products with FP
 //     contraction off, so a shared edge gives exactly opposite values in the
-//     two faces; two-sided, edges inclusive;
+//     two faces; two-sided;
 //   * short per-lane stack in LDS, spilling its oldest entries to a per-lane
 //     global area when full (the Karras tree depth is bounded by 62).
 #include "internal.h"
@@ -31,6 +35,8 @@ namespace {
 
 constexpr int32_t kEmpty = INT32_MIN;
 constexpr float kPad = 1e-6f;
+constexpr float kEdgeEps = 1.0f / 1024.0f;   // must match the leaf-box widening in lbvh.hip
+constexpr float kQuantScale = 1048576.0f;    // 2^20: distance quantum w = max_dist / 2^20
 constexpr uint32_t kFaceReliable = 1u;
 
 struct float3x3 {
@@ -96,9 +102,9 @@ __device__ __forceinline__ float3 shear(const RayT& r, float3 v) {
               fmaf(r.S.r2.z, a.z, fmaf(r.S.r2.y, a.y, r.S.r2.x * a.x)));
 }
 
-// Slab test of box [lo, hi]; on overlap with [-best, best] returns true and the
-// smallest |t| of the (widened) overlap in *mint.
-__device__ __forceinline__ bool box_test(const RayT& r, float3 lo, float3 hi, float best,
+// Slab test of box [lo, hi]; on overlap with [-bound, bound] returns true and
+// the smallest |t| of the (widened) overlap in *mint.
+__device__ __forceinline__ bool box_test(const RayT& r, float3 lo, float3 hi, float bound,
                                          float* mint) {
     float nx = (r.sgn & 1u) ? hi.x : lo.x, fx = (r.sgn & 1u) ? lo.x : hi.x;
     float ny = (r.sgn & 2u) ? hi.y : lo.y, fy = (r.sgn & 2u) ? lo.y : hi.y;
@@ -111,35 +117,46 @@ __device__ __forceinline__ bool box_test(const RayT& r, float3 lo, float3 hi, fl
     // widen outward; a multiply keeps +-inf finite-signed (no inf - inf)
     t0 = t0 * (t0 > 0.f ? 1.0f - kPad : 1.0f + kPad);
     t1 = t1 * (t1 > 0.f ? 1.0f + kPad : 1.0f - kPad);
-    t0 = fmaxf(t0, -best);
-    t1 = fminf(t1, best);
+    t0 = fmaxf(t0, -bound);
+    t1 = fminf(t1, bound);
     *mint = t0 > 0.f ? t0 : (t1 < 0.f ? -t1 : 0.f);
     return t0 <= t1;
 }
 
-// Watertight two-sided test; on a better (|t|, id) hit updates the best.
-__device__ __forceinline__ void tri_test(const RayT& r, const Leaf& L, float max_dist, float* best,
-                                         int32_t* best_id, float* best_t, float* bb1, float* bb2) {
+struct Best {
+    uint32_t key;   // floor(|t| / w), 0xFFFFFFFF before the first hit
+    int32_t id;     // INT32_MAX before the first hit
+    float t, b1, b2;
+    float bound;    // prune nodes whose nearest |t| exceeds this
+};
+
+// Watertight two-sided test; on a better (key, id) hit updates the best.
+__device__ __forceinline__ void tri_test(const RayT& r, const Leaf& L, float max_dist, float inv_w,
+                                         float w, Best* b) {
     float3 v0 = f3(L.a.x, L.a.y, L.a.z), v1 = f3(L.a.w, L.b.x, L.b.y), v2 = f3(L.b.z, L.b.w, L.c.x);
     int32_t id = __float_as_int(L.c.y);
     float3 A = shear(r, v0), B = shear(r, v1), C = shear(r, v2);
     float U = edge_fn(C.x, C.y, B.x, B.y);
     float V = edge_fn(A.x, A.y, C.x, C.y);
     float W = edge_fn(B.x, B.y, A.x, A.y);
-    float mn = fminf(fminf(U, V), W), mx = fmaxf(fmaxf(U, V), W);
-    if (mn < 0.f && mx > 0.f) return;
     float det = U + V + W;
     if (det == 0.f) return;
+    if (det < 0.f) {
+        U = -U; V = -V; W = -W; det = -det;
+    }
+    if (fminf(fminf(U, V), W) < -kEdgeEps * det) return;
     float T = U * A.z + V * B.z + W * C.z;
     float t = T / det;
     float at = fabsf(t);
     if (!(at <= max_dist)) return;
-    if (at < *best || (at == *best && id < *best_id)) {
-        *best = at;
-        *best_id = id;
-        *best_t = t;
-        *bb1 = V / det;
-        *bb2 = W / det;
+    uint32_t key = (uint32_t)(at * inv_w);
+    if (key < b->key || (key == b->key && id < b->id)) {
+        b->key = key;
+        b->id = id;
+        b->t = t;
+        b->b1 = V / det;
+        b->b2 = W / det;
+        b->bound = (float)(key + 1u) * w * (1.0f + kPad);
     }
 }
 
@@ -183,8 +200,11 @@ __global__ __launch_bounds__(BLOCK) void traverse_kernel(TravArgs a) {
     RayT R;
     float3 d = f3(0.f, 0.f, 1.f), Tp = f3(1.f, 0.f, 0.f);
     float hsign = 1.f;
-    float best = 0.f, best_t = 0.f, bb1 = 0.f, bb2 = 0.f;
-    int32_t best_id = INT32_MAX;
+    const float w = a.max_dist / kQuantScale;   // exact: power-of-two scaling
+    const float inv_w = kQuantScale / a.max_dist;
+    Best best;
+    best.key = 0xFFFFFFFFu; best.id = INT32_MAX; best.t = best.b1 = best.b2 = 0.f;
+    best.bound = a.max_dist;
     int32_t node = kEmpty;
     int sp = 0, lo = 0;
     int64_t steps = 0;
@@ -231,15 +251,14 @@ __global__ __launch_bounds__(BLOCK) void traverse_kernel(TravArgs a) {
                         float rt = 1.0f / sqrtf(lt2);
                         Tp = f3(Tp.x * rt, Tp.y * rt, Tp.z * rt);
                         R = make_rayt(p, d);
-                        best = a.max_dist;
-                        best_id = INT32_MAX;
-                        best_t = 0.f;
-                        bb1 = bb2 = 0.f;
+                        best.key = 0xFFFFFFFFu;
+                        best.id = INT32_MAX;
+                        best.t = best.b1 = best.b2 = 0.f;
+                        best.bound = a.max_dist * (1.0f + kPad);
                         node = a.root;
                         sp = lo = 0;
                         steps = 0;
                         active = node != kEmpty;
-                        if (!active) best_id = INT32_MAX;  // no triangles: a miss
                     }
                     if (!active) {
                         // unreliable (or nothing to hit): finish right away
@@ -268,8 +287,8 @@ __global__ __launch_bounds__(BLOCK) void traverse_kernel(TravArgs a) {
             float4 na = nd->a, nb = nd->b, nc = nd->c;
             int4 ref = nd->ref;
             float mL, mR;
-            bool hL = box_test(R, f3(na.x, na.y, na.z), f3(na.w, nb.x, nb.y), best, &mL);
-            bool hR = box_test(R, f3(nb.z, nb.w, nc.x), f3(nc.y, nc.z, nc.w), best, &mR);
+            bool hL = box_test(R, f3(na.x, na.y, na.z), f3(na.w, nb.x, nb.y), best.bound, &mL);
+            bool hR = box_test(R, f3(nb.z, nb.w, nc.x), f3(nc.y, nc.z, nc.w), best.bound, &mR);
             int32_t next = kEmpty, other = kEmpty;
             if (hL && hR) {
                 bool rfirst = mR < mL;
@@ -298,7 +317,7 @@ __global__ __launch_bounds__(BLOCK) void traverse_kernel(TravArgs a) {
             node = next;
         } else {
             const Leaf L = a.leaves[~node];
-            tri_test(R, L, a.max_dist, &best, &best_id, &best_t, &bb1, &bb2);
+            tri_test(R, L, a.max_dist, inv_w, w, &best);
             node = kEmpty;
         }
         if (++steps > a.step_cap) {
@@ -325,13 +344,13 @@ __global__ __launch_bounds__(BLOCK) void traverse_kernel(TravArgs a) {
         float3 out = f3(0.f, 0.f, 1.f);
         int32_t st = kMiss;
         float beta1 = 0.f, beta2 = 0.f;
-        if (best_id != INT32_MAX) {
-            int32_t g = best_id;
+        if (best.id != INT32_MAX) {
+            int32_t g = best.id;
             int32_t j0 = a.hi_F[3 * (int64_t)g], j1 = a.hi_F[3 * (int64_t)g + 1],
                     j2 = a.hi_F[3 * (int64_t)g + 2];
             bool ok = j0 >= 0 && j1 >= 0 && j2 >= 0 && j0 < a.nhv && j1 < a.nhv && j2 < a.nhv;
-            beta1 = bb1;
-            beta2 = bb2;
+            beta1 = best.b1;
+            beta2 = best.b2;
             float beta0 = 1.0f - beta1 - beta2;
             st = kUnreliable;
             if (ok) {
@@ -356,7 +375,7 @@ __global__ __launch_bounds__(BLOCK) void traverse_kernel(TravArgs a) {
         a.out_hit[texel] = st;
         if (a.hits) {
             Hit h;
-            h.t = best_t;
+            h.t = best.t;
             h.beta1 = beta1;
             h.beta2 = beta2;
             h.id = st;

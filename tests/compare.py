@@ -2,15 +2,16 @@
 
 Parity rules (what "matches the oracle" means):
   1. coverage (uncovered status) is bit-identical, and so is the unreliable
-     status decided before the query;
+     status;
   2. on covered, reliable texels the hit ids agree on at least 99.9 % of them;
-  3. every id disagreement is a tie: with tau* the oracle's best |t| (inf on a
-     miss), t_g the oracle's FP64 crossing of the GPU triangle's plane along the
-     oracle's ray and delta_g that crossing's distance from the triangle,
-     | |t_g| - tau* | <= 1e-6 max_dist, |t_g| <= max_dist (1 + 1e-6) and
-     delta_g <= 32 ulp_fp32(|q|); a GPU miss against an oracle hit is a tie
-     only when tau* >= (1 - 1e-6) max_dist, and a GPU hit against an oracle
-     miss only when |t_g| is that close to max_dist;
+  3. every id disagreement is a tie of the hit rule, checked in FP64 along the
+     oracle's ray: the GPU's triangle g must be a candidate within the FP32
+     noise of the rule (smallest barycentric weight of its plane crossing >=
+     -EDGE_EPS - 1e-4, |t_g| <= max_dist (1 + 1e-6)) and its distance must be
+     within two quanta w = max_dist 2^-20 (about 1e-6 max_dist each) of the
+     oracle's best |t|; a GPU miss against an oracle hit, or the reverse, is a
+     tie only at the range end (|t| within 1e-6 max_dist of max_dist) or at the
+     edge-tolerance boundary (weight within 1e-4 of -EDGE_EPS);
   4. on same-id texels the angle between the tangent-space vectors is at most
      0.05 degrees;
   5. after dilation, uncovered texels agree within 0.05 degrees except next to
@@ -25,7 +26,8 @@ import numpy as np
 ANGLE_TOL_DEG = 0.05
 AGREE_MIN = 0.999
 TIE_REL = 1e-6
-DELTA_ULPS = 32
+EDGE_EPS = 1.0 / 1024.0   # the hit rule's edge tolerance (barycentric units)
+BARY_SLACK = 1e-4         # FP32 noise allowance on barycentric weights
 
 
 def angle_deg(a: np.ndarray, b: np.ndarray) -> np.ndarray:
@@ -90,22 +92,31 @@ def compare(oracle, asset, ob, gpu_map: np.ndarray, gpu_hit: np.ndarray, check_d
     # 3. every disagreement must be a tie
     tie_mask = np.zeros_like(dis)
     if rep.n_disagree:
+        w = md * 2.0 ** -20
         idx = np.nonzero(dis)[0]
-        tau = np.where(oh[idx] >= 0, np.abs(ob.t[idx]), np.inf)
+        o_has = oh[idx] >= 0
+        tau = np.where(o_has, np.abs(ob.t[idx]), np.inf)
         gg = g[idx]
         has_g = gg >= 0
         ok = np.zeros(idx.size, bool)
-        # GPU miss vs oracle hit: oracle hit must sit at the range end
-        ok[~has_g & (gg == -1)] = tau[~has_g & (gg == -1)] >= (1 - TIE_REL) * md
+        at_end = lambda x: np.abs(x) >= (1 - TIE_REL) * md
+        # is the oracle's own pick at the edge-tolerance boundary?
+        o_edge = np.zeros(idx.size, bool)
+        if o_has.any():
+            j = idx[o_has]
+            _, _, bmo = oracle.plane_check(asset.hi_V, asset.hi_F, ob.P[j], ob.D[j], oh[j])
+            o_edge[o_has] = np.abs(bmo + EDGE_EPS) <= BARY_SLACK
+        # GPU miss against an oracle hit
+        gm_ = ~has_g & (gg == -1)
+        ok[gm_] = at_end(tau[gm_]) | o_edge[gm_]
         if has_g.any():
             j = idx[has_g]
-            tg, dg = oracle.plane_check(asset.hi_V, asset.hi_F, ob.P[j], ob.D[j], gg[has_g])
-            q = ob.P[j] + tg[:, None] * ob.D[j]
-            ulp = np.spacing(np.linalg.norm(q, axis=1).astype(np.float32)).astype(np.float64)
-            within = (np.abs(tg) <= md * (1 + TIE_REL)) & (dg <= DELTA_ULPS * ulp)
-            t_ok = np.where(np.isfinite(tau[has_g]), np.abs(np.abs(tg) - tau[has_g]) <= TIE_REL * md,
-                            np.abs(tg) >= (1 - TIE_REL) * md)
-            ok[has_g] = within & t_ok
+            tg, _, bm = oracle.plane_check(asset.hi_V, asset.hi_F, ob.P[j], ob.D[j], gg[has_g])
+            cand = (bm >= -EDGE_EPS - BARY_SLACK) & (np.abs(tg) <= md * (1 + TIE_REL))
+            fin = np.isfinite(tau[has_g])
+            t_ok = np.where(fin, np.abs(np.abs(tg) - tau[has_g]) <= 2 * w,
+                            at_end(tg) | (np.abs(bm + EDGE_EPS) <= BARY_SLACK))
+            ok[has_g] = cand & (t_ok | o_edge[has_g])
         tie_mask[idx] = ok
         rep.n_ties = int(ok.sum())
         if not ok.all():
