@@ -68,6 +68,8 @@ extern "C" {
 /* ---- flags ------------------------------------------------------------ */
 #define BAKE_FLAG_SAVE 1u   /* keep the per-ray state that bake_normals_backward needs */
 #define BAKE_FLAG_TIMING 2u /* record per-stage HIP events (bake_stage_times) */
+#define BAKE_FLAG_COUNT 4u  /* instrumented traversal: count box and triangle tests
+                               (bake_read_counter 1 and 2); slower, same results */
 
 typedef struct bake_options {
     int32_t dilate_passes; /* chart dilation passes, 0..64 (default 2)                    */
@@ -136,7 +138,8 @@ int32_t bake_normals_backward(const float *hi_V, int64_t n_hi_v, const int32_t *
 int32_t bake_query_status(const void *workspace, void *stream, uint32_t *status_out);
 
 /* Synchronises `stream` and returns a device counter of the last bake that used
- * `workspace`: which = 0 -> number of covered texels (rays traced). */
+ * `workspace`: which = 0 -> number of covered texels (rays traced); 1 -> box
+ * tests and 2 -> triangle tests of the traversal (bakes with BAKE_FLAG_COUNT). */
 int32_t bake_read_counter(const void *workspace, int32_t which, void *stream, int64_t *value_out);
 
 /* Location of an internal array inside the workspace, for inspection by tests
@@ -154,10 +157,15 @@ int32_t bake_workspace_view(int64_t n_hi_v, int64_t n_hi_f, int64_t n_lo_v, int6
                             size_t *offset_out, size_t *bytes_out);
 
 /* Per-stage GPU times in ms of the last bake on this thread made with
- * BAKE_FLAG_TIMING (synchronises on those events).  Stages: 0 lo prep,
- * 1 raster, 2 BVH build, 3 traversal+encode, 4 dilation, 5 whole forward.
- * Returns the number of stages written. */
+ * BAKE_FLAG_TIMING, from HIP events recorded on the bake's stream
+ * (synchronises on those events).  Stages: 0 lo prep, 1 raster (+ uncovered
+ * fill), 2 BVH build, 3 traversal + encode, 4 dilation (+ RGB8), 5 whole
+ * forward.  Returns the number of stages written. */
 int32_t bake_stage_times(float *ms_out, int32_t n);
+
+/* The same for up to the 64 most recent timed bakes on this thread, oldest
+ * first: ms_out is [max_bakes][6].  Returns the number of bakes written. */
+int32_t bake_stage_history(float *ms_out, int32_t max_bakes);
 
 /* Thread-local message of the last error on this thread ("" if none). */
 const char *bake_last_error(void);

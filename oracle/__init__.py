@@ -172,7 +172,7 @@ def plane_check(hi_V, hi_F, P, D, g):
     return t, dl, bm
 
 
-EDGE_EPS = 1.0 / 1024.0   # relative edge tolerance of the hit rule (barycentric units)
+EDGE_EPS = 1.0 / 16384.0  # relative edge tolerance of the hit rule (barycentric units)
 T_QUANT_BITS = 20         # distance quantum w = max_dist * 2^-20
 
 

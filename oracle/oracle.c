@@ -49,7 +49,7 @@
 #define ORC_EINVAL -1
 
 /* relative edge tolerance (in barycentric units) and distance quantum */
-#define EDGE_EPS (1.0 / 1024.0)
+#define EDGE_EPS (1.0 / 16384.0)
 #define T_QUANT_BITS 20
 
 #define ST_MISS -1

@@ -35,6 +35,7 @@ BAKE_STATUS_NONFINITE = 8
 
 BAKE_FLAG_SAVE = 1
 BAKE_FLAG_TIMING = 2
+BAKE_FLAG_COUNT = 4
 
 VIEW_RAYS, VIEW_HITS, VIEW_FACEMAP, VIEW_LO_N, VIEW_SORTED, VIEW_NODES, VIEW_LEAVES, VIEW_FACE_T = range(8)
 
@@ -79,6 +80,7 @@ _EXPORTS = {
                                         C.c_void_p, C.c_int32, C.POINTER(C.c_size_t),
                                         C.POINTER(C.c_size_t)]),
     "bake_stage_times": (C.c_int32, [C.POINTER(C.c_float), C.c_int32]),
+    "bake_stage_history": (C.c_int32, [C.POINTER(C.c_float), C.c_int32]),
     "bake_last_error": (C.c_char_p, []),
     "bake_version": (C.c_char_p, []),
 }
@@ -107,11 +109,12 @@ def _check(rc: int):
 
 
 def make_options(dilate_passes=2, save=False, timing=False, rgb8_ptr=0, trav_block=0,
-                 trav_stack=0, trav_persist=-1) -> BakeOptions:
+                 trav_stack=0, trav_persist=-1, count=False) -> BakeOptions:
     o = BakeOptions()
     lib().bake_default_options(C.byref(o))
     o.dilate_passes = int(dilate_passes)
-    o.flags = (BAKE_FLAG_SAVE if save else 0) | (BAKE_FLAG_TIMING if timing else 0)
+    o.flags = ((BAKE_FLAG_SAVE if save else 0) | (BAKE_FLAG_TIMING if timing else 0)
+               | (BAKE_FLAG_COUNT if count else 0))
     o.out_rgb8 = rgb8_ptr or None
     o.trav_block = int(trav_block)
     o.trav_stack = int(trav_stack)
@@ -172,10 +175,18 @@ class BakeResult:
         o, b = workspace_view(*self.sizes, which, self.opts)
         return self.workspace[o:o + b].view(dtype)
 
-    def ray_count(self, stream=None) -> int:
+    def counter(self, which: int, stream=None) -> int:
         v = C.c_int64(0)
-        _check(lib().bake_read_counter(_ptr(self.workspace), 0, _stream_handle(stream), C.byref(v)))
+        _check(lib().bake_read_counter(_ptr(self.workspace), int(which), _stream_handle(stream),
+                                       C.byref(v)))
         return v.value
+
+    def ray_count(self, stream=None) -> int:
+        return self.counter(0, stream)
+
+    def test_counts(self, stream=None):
+        """(box tests, triangle tests) of a bake made with count=True."""
+        return self.counter(1, stream), self.counter(2, stream)
 
     def status(self, stream=None) -> int:
         v = C.c_uint32(0)
@@ -186,7 +197,8 @@ class BakeResult:
 def bake_normals(hi_V, hi_F, hi_N, lo_V, lo_F, lo_UV, res: int, max_dist: float, *,
                  dilate_passes: int = 2, rgb8: bool = False, save: bool = False,
                  timing: bool = False, trav_block: int = 0, trav_stack: int = 0,
-                 trav_persist: int = -1, workspace: Optional[torch.Tensor] = None,
+                 trav_persist: int = -1, count: bool = False,
+                 workspace: Optional[torch.Tensor] = None,
                  out_map: Optional[torch.Tensor] = None, out_hit: Optional[torch.Tensor] = None,
                  stream=None) -> BakeResult:
     """Bake a tangent-space normal map of the high-poly onto the low-poly's UV
@@ -206,7 +218,7 @@ def bake_normals(hi_V, hi_F, hi_N, lo_V, lo_F, lo_UV, res: int, max_dist: float,
     sizes = (hi_V.shape[0], hi_F.shape[0], lo_V.shape[0], lo_F.shape[0], int(res))
     rgb = torch.empty((res, res, 3), dtype=torch.uint8, device=dev) if rgb8 else None
     opts = make_options(dilate_passes, save, timing, rgb.data_ptr() if rgb is not None else 0,
-                        trav_block, trav_stack, trav_persist)
+                        trav_block, trav_stack, trav_persist, count)
     nbytes = workspace_size(*sizes, opts)
     if workspace is None or workspace.numel() < nbytes:
         workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
@@ -226,6 +238,14 @@ def stage_times() -> dict:
     buf = (C.c_float * len(STAGES))()
     n = _check(lib().bake_stage_times(buf, len(STAGES)))
     return {STAGES[k]: float(buf[k]) for k in range(n)}
+
+
+def stage_history(max_bakes: int = 64):
+    """[n, 6] per-stage ms of up to the 64 most recent timed bakes, oldest first."""
+    import numpy as np
+    buf = (C.c_float * (6 * max_bakes))()
+    n = _check(lib().bake_stage_history(buf, int(max_bakes)))
+    return np.frombuffer(buf, dtype=np.float32, count=6 * n).reshape(n, 6).copy()
 
 
 def version() -> str:

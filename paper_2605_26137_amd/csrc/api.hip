@@ -58,7 +58,7 @@ int32_t parse_opts(const bake_options* o, Opts* out) {
     if (o->dilate_passes < 0 || o->dilate_passes > 64)
         return fail(BAKE_E_INVALID_ARG, "dilate_passes %d outside [0, 64]", o->dilate_passes);
     out->dilate = o->dilate_passes;
-    if (o->flags & ~(uint32_t)(BAKE_FLAG_SAVE | BAKE_FLAG_TIMING))
+    if (o->flags & ~(uint32_t)(BAKE_FLAG_SAVE | BAKE_FLAG_TIMING | BAKE_FLAG_COUNT))
         return fail(BAKE_E_INVALID_ARG, "unknown flag bits 0x%x", o->flags);
     out->flags = o->flags;
     out->rgb8 = o->out_rgb8;
@@ -136,30 +136,59 @@ Layout make_layout(int64_t nhv, int64_t nhf, int64_t nlv, int64_t nlf, int32_t r
     L.node_parent = take(4 * (size_t)std::max<int64_t>(nhf - 1, 1));
     L.leaf_parent = take(4 * (size_t)std::max<int64_t>(nhf, 1));
     L.refit_cnt = take(4 * (size_t)std::max<int64_t>(nhf - 1, 1));
+    L.node_range = take(8 * (size_t)std::max<int64_t>(nhf - 1, 1));
+    // tile-crossing nodes: at most (tiles - 1) boundaries x depth, 2 entries each
+    L.frontier = take(4 * (size_t)(2 * kMaxDepth * ((nhf + kRefitTileLeaves - 1) / kRefitTileLeaves + 1)));
     L.spill = take(4 * (size_t)kMaxDepth * (size_t)L.spill_lanes);
     L.total = off;
     return L;
 }
 
 // ---- per-thread stage timing ---------------------------------------------
+// A ring of event sets, so the stage times of many consecutive bakes can be
+// read back after they ran, without synchronising between them.
 constexpr int kStages = 6;
+constexpr int kRing = 64;
 struct Timing {
-    hipEvent_t ev[kStages + 1];
+    hipEvent_t ev[kRing][kStages];
     bool created = false;
-    bool valid = false;
+    int next = 0;   // ring slot of the next timed bake
+    int count = 0;  // timed bakes recorded (saturates at kRing)
 };
 thread_local Timing g_tim;
 
 hipError_t tim_record(bool on, int k, hipStream_t s) {
     if (!on) return hipSuccess;
     if (!g_tim.created) {
-        for (int i = 0; i <= kStages; ++i) {
-            hipError_t e = hipEventCreate(&g_tim.ev[i]);
-            if (e != hipSuccess) return e;
-        }
+        for (int r = 0; r < kRing; ++r)
+            for (int i = 0; i < kStages; ++i) {
+                hipError_t e = hipEventCreate(&g_tim.ev[r][i]);
+                if (e != hipSuccess) return e;
+            }
         g_tim.created = true;
     }
-    return hipEventRecord(g_tim.ev[k], s);
+    return hipEventRecord(g_tim.ev[g_tim.next][k], s);
+}
+
+void tim_commit(bool on) {
+    if (!on) return;
+    g_tim.next = (g_tim.next + 1) % kRing;
+    if (g_tim.count < kRing) ++g_tim.count;
+}
+
+// Stage times of ring slot r: 0 lo prep, 1 raster, 2 BVH, 3 traversal, 4 dilation, 5 total.
+int32_t slot_times(int r, float* ms) {
+    HIP_OR_FAIL(hipEventSynchronize(g_tim.ev[r][kStages - 1]));
+    for (int k = 0; k < kStages; ++k) {
+        float v = 0.f;
+        if (k < kStages - 1) {
+            HIP_OR_FAIL(hipEventElapsedTime(&v, g_tim.ev[r][k], g_tim.ev[r][k + 1]));
+        } else {
+            HIP_OR_FAIL(hipEventElapsedTime(&v, g_tim.ev[r][0], g_tim.ev[r][kStages - 1]));
+        }
+        ms[k] = v;
+    }
+    return BAKE_OK;
 }
 
 int32_t validate_common(const float* hi_V, int64_t nhv, const int32_t* hi_F, int64_t nhf,
@@ -258,7 +287,6 @@ int32_t bake_normals(const float* hi_V, int64_t n_hi_v, const int32_t* hi_F, int
     char* ws = (char*)workspace;
     hipStream_t s = (hipStream_t)stream;
     const bool tim = (o.flags & BAKE_FLAG_TIMING) != 0;
-    g_tim.valid = false;
 
     HIP_OR_FAIL(tim_record(tim, 0, s));
     HIP_OR_FAIL(fill_u32((uint32_t*)(ws + L.status), 0, 1, s));
@@ -270,13 +298,15 @@ int32_t bake_normals(const float* hi_V, int64_t n_hi_v, const int32_t* hi_F, int
     HIP_OR_FAIL(tim_record(tim, 2, s));
     HIP_OR_FAIL(launch_bvh_build(hi_V, n_hi_v, hi_F, n_hi_f, L, ws, s));
     HIP_OR_FAIL(tim_record(tim, 3, s));
+    TravConfig tc = o.trav;
+    tc.count = (o.flags & BAKE_FLAG_COUNT) != 0;
     HIP_OR_FAIL(launch_traverse(lo_V, lo_F, n_lo_f, hi_F, n_hi_v, n_hi_f, hi_N, max_dist, out_map,
-                                out_hit, (o.flags & BAKE_FLAG_SAVE) != 0, o.trav, L, ws, s));
+                                out_hit, (o.flags & BAKE_FLAG_SAVE) != 0, tc, L, ws, s));
     HIP_OR_FAIL(tim_record(tim, 4, s));
     HIP_OR_FAIL(launch_dilate(res, o.dilate, out_map, L, ws, s));
     if (o.rgb8) HIP_OR_FAIL(launch_rgb8(res, out_map, o.rgb8, s));
     HIP_OR_FAIL(tim_record(tim, 5, s));
-    g_tim.valid = tim;
+    tim_commit(tim);
     return BAKE_OK;
 }
 
@@ -307,31 +337,38 @@ int32_t bake_query_status(const void* workspace, void* stream, uint32_t* status_
 int32_t bake_read_counter(const void* workspace, int32_t which, void* stream, int64_t* value_out) {
     g_err[0] = 0;
     if (!workspace || !value_out) return fail(BAKE_E_INVALID_ARG, "NULL argument");
-    if (which != 0) return fail(BAKE_E_INVALID_ARG, "unknown counter %d", which);
+    if (which < 0 || which > 2) return fail(BAKE_E_INVALID_ARG, "unknown counter %d", which);
     hipStream_t s = (hipStream_t)stream;
-    uint32_t v = 0;
+    uint32_t v[kCntSlots];
     // counters sit right after the 256-byte status block
-    HIP_OR_FAIL(hipMemcpyAsync(&v, (const char*)workspace + 256 + 4 * kCntRays, 4,
-                               hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipMemcpyAsync(v, (const char*)workspace + 256, sizeof v, hipMemcpyDeviceToHost, s));
     HIP_OR_FAIL(hipStreamSynchronize(s));
-    *value_out = v;
+    if (which == 0) *value_out = v[kCntRays];
+    else if (which == 1) *value_out = (int64_t)v[kCntBoxLo] | ((int64_t)v[kCntBoxLo + 1] << 32);
+    else *value_out = (int64_t)v[kCntTriLo] | ((int64_t)v[kCntTriLo + 1] << 32);
     return BAKE_OK;
 }
 
 int32_t bake_stage_times(float* ms_out, int32_t n) {
     g_err[0] = 0;
     if (!ms_out || n < 0) return fail(BAKE_E_INVALID_ARG, "bad output");
-    if (!g_tim.valid) return fail(BAKE_E_STATE, "no timed bake on this thread");
-    HIP_OR_FAIL(hipEventSynchronize(g_tim.ev[kStages - 1]));
+    if (g_tim.count == 0) return fail(BAKE_E_STATE, "no timed bake on this thread");
+    float ms[kStages];
+    int32_t rc = slot_times((g_tim.next + kRing - 1) % kRing, ms);
+    if (rc) return rc;
     int m = std::min<int>(n, kStages);
-    for (int k = 0; k < m; ++k) {
-        float ms = 0.f;
-        if (k < kStages - 1) {
-            HIP_OR_FAIL(hipEventElapsedTime(&ms, g_tim.ev[k], g_tim.ev[k + 1]));
-        } else {
-            HIP_OR_FAIL(hipEventElapsedTime(&ms, g_tim.ev[0], g_tim.ev[kStages - 1]));
-        }
-        ms_out[k] = ms;
+    for (int k = 0; k < m; ++k) ms_out[k] = ms[k];
+    return m;
+}
+
+int32_t bake_stage_history(float* ms_out, int32_t max_bakes) {
+    g_err[0] = 0;
+    if (!ms_out || max_bakes < 0) return fail(BAKE_E_INVALID_ARG, "bad output");
+    int m = std::min<int>(max_bakes, g_tim.count);
+    for (int i = 0; i < m; ++i) {
+        int r = (g_tim.next + kRing - m + i) % kRing;  // oldest first
+        int32_t rc = slot_times(r, ms_out + (size_t)i * kStages);
+        if (rc) return rc;
     }
     return m;
 }

@@ -75,7 +75,7 @@ struct Layout {
     size_t rays, hits;                        // per ray
     size_t bounds_part, bounds;               // centroid bounds reduction
     size_t keys0, keys1, vals0, vals1, hist;  // radix sort
-    size_t nodes, leaves, node_parent, leaf_parent, refit_cnt;
+    size_t nodes, leaves, node_parent, leaf_parent, refit_cnt, node_range, frontier;
     size_t spill;                             // traversal stack spill
     size_t bwd0, bwd1, bwd2, bwd3, bwd4, bwd5;  // backward scratch
     size_t total;
@@ -86,7 +86,10 @@ struct Layout {
 // counters[] slots
 constexpr int kCntRays = 0;      // number of covered texels (rays)
 constexpr int kCntQueue = 1;     // persistent traversal work queue head
-constexpr int kCntHiSorted = 2;  // spare
+constexpr int kCntBoxLo = 2;     // u64 box tests (FLAG_COUNT), slots 2-3
+constexpr int kCntTriLo = 4;     // u64 triangle tests (FLAG_COUNT), slots 4-5
+constexpr int kCntFrontier = 6;  // refit frontier length
+constexpr int kRefitTileLeaves = 4096;  // leaves per refit tile (lbvh.hip)
 constexpr int kCntSlots = 16;
 
 // Traversal configuration
@@ -94,6 +97,7 @@ struct TravConfig {
     int block;    // 64 / 128 / 256
     int stack;    // LDS entries per lane: 8 / 16 / 32
     int persist;  // 1: refill finished lanes from a work queue; 0: static striding
+    bool count = false;  // instrumented variant: count box and triangle tests
 };
 
 // ---------------------------------------------------------------------------

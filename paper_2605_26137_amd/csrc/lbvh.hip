@@ -24,7 +24,7 @@ constexpr int kBlock = 256;
 constexpr int kSortRounds = 16;
 constexpr int kSortTile = kBlock * kSortRounds;  // 4096 keys per block and pass
 constexpr int kBoundsBlocks = 512;
-constexpr float kLeafEps = 1.0f / 1024.0f;  // edge tolerance of the hit rule (traverse.hip)
+constexpr float kLeafEps = 1.0f / 16384.0f;  // edge tolerance of the hit rule (traverse.hip)
 
 __device__ __forceinline__ int3 tri_idx(const int32_t* __restrict__ F, int64_t g, int64_t nv,
                                         bool* bad) {
@@ -235,7 +235,8 @@ __device__ __forceinline__ int cprefix(const uint32_t* __restrict__ k, int64_t n
 }
 
 __global__ void karras_kernel(const uint32_t* __restrict__ keys, int64_t n, BvhNode* __restrict__ nodes,
-                              int32_t* __restrict__ node_parent, int32_t* __restrict__ leaf_parent) {
+                              int32_t* __restrict__ node_parent, int32_t* __restrict__ leaf_parent,
+                              int2* __restrict__ node_range) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n - 1) return;
     int d = (cprefix(keys, n, i, i + 1) - cprefix(keys, n, i, i - 1)) >= 0 ? 1 : -1;
@@ -257,6 +258,7 @@ __global__ void karras_kernel(const uint32_t* __restrict__ keys, int64_t n, BvhN
     int32_t left = lo == gamma ? ~(int32_t)gamma : (int32_t)gamma;
     int32_t right = hi == gamma + 1 ? ~(int32_t)(gamma + 1) : (int32_t)(gamma + 1);
     nodes[i].ref = make_int4(left, right, 0, 0);
+    node_range[i] = make_int2((int32_t)lo, (int32_t)hi);
     if (left < 0) leaf_parent[gamma] = (int32_t)(i << 1);
     else node_parent[gamma] = (int32_t)(i << 1);
     if (right < 0) leaf_parent[gamma + 1] = (int32_t)((i << 1) | 1);
@@ -267,6 +269,24 @@ __global__ void karras_kernel(const uint32_t* __restrict__ keys, int64_t n, BvhN
 // ---------------------------------------------------------------------------
 // 5. leaves + refit
 // ---------------------------------------------------------------------------
+//
+// Two launches, with no device-scope ordering inside either:
+//  1. one workgroup per tile of kRefitTile consecutive sorted leaves.  A Karras
+//     node covers the contiguous leaf range [lo, hi] and sits at one end of it,
+//     so every node whose range lies inside the tile also has its index inside
+//     the tile: the workgroup refits all of those with arrival counters in LDS
+//     and workgroup-scope ordering.  A child whose parent's range crosses the
+//     tile boundary writes its box into the parent's slot and appends the
+//     parent reference to a frontier list.
+//  2. a single workgroup finishes the nodes that cross tile boundaries (about
+//     (n / tile) x depth of them), starting from the frontier, with arrival
+//     counters in global memory that only this workgroup touches.
+// (Device-scope acquire/release per node costs an L2 write-back and
+// invalidation across the XCDs and serialises the upper levels.)
+
+constexpr int kRefitTile = kRefitTileLeaves;
+constexpr int kRefitBlock = 512;
+constexpr int kTopBlock = 1024;
 
 __device__ __forceinline__ void put_slot(BvhNode* node, int side, const float b[6]) {
     float* f = reinterpret_cast<float*>(node) + 6 * side;
@@ -274,57 +294,106 @@ __device__ __forceinline__ void put_slot(BvhNode* node, int side, const float b[
     for (int k = 0; k < 6; ++k) f[k] = b[k];
 }
 
-__global__ void leaf_refit_kernel(const float* __restrict__ V, int64_t nv, const int32_t* __restrict__ F,
-                                  int64_t n, const uint32_t* __restrict__ sorted_idx,
-                                  Leaf* __restrict__ leaves, BvhNode* nodes,
-                                  const int32_t* __restrict__ node_parent,
-                                  const int32_t* __restrict__ leaf_parent, uint32_t* cnt,
-                                  uint32_t* __restrict__ status) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    uint32_t g = sorted_idx[k];
-    bool bad;
-    int3 t = tri_idx(F, g, nv, &bad);
-    float3 a = ldv(V, t.x), b = ldv(V, t.y), c = ldv(V, t.z);
-    Leaf lf;
-    lf.a = make_float4(a.x, a.y, a.z, b.x);
-    lf.b = make_float4(b.y, b.z, c.x, c.y);
-    lf.c = make_float4(c.z, __int_as_float((int32_t)g), 0.f, 0.f);
-    leaves[k] = lf;
-    float box[6] = {fminf(fminf(a.x, b.x), c.x), fminf(fminf(a.y, b.y), c.y),
-                    fminf(fminf(a.z, b.z), c.z), fmaxf(fmaxf(a.x, b.x), c.x),
-                    fmaxf(fmaxf(a.y, b.y), c.y), fmaxf(fmaxf(a.z, b.z), c.z)};
-    // The hit rule accepts crossings with barycentric weights down to
-    // -kLeafEps, i.e. inside the triangle scaled by (1 + 3 kLeafEps) about its
-    // centroid: widen the box by 4 kLeafEps of its extent (3 plus rounding
-    // margin) and a few ulps of its coordinates.
+__device__ __forceinline__ void union_slot(const BvhNode* node, int side, float box[6]) {
+    const float* o = reinterpret_cast<const float*>(node) + 6 * side;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        float ext = box[q + 3] - box[q];
-        float pad = 4.0f * kLeafEps * ext + 4.76837158e-7f * fmaxf(fabsf(box[q]), fabsf(box[q + 3]));
-        box[q] -= pad;
-        box[q + 3] += pad;
-    }
-    int32_t pp = n > 1 ? leaf_parent[k] : -1;
-    for (int level = 0; pp >= 0; ++level) {
-        if (level > 2 * kMaxDepth) {  // only a malformed hierarchy gets here
-            atomicOr(status, kStInternal);
-            return;
+    for (int q = 0; q < 3; ++q) box[q] = fminf(box[q], o[q]);
+#pragma unroll
+    for (int q = 3; q < 6; ++q) box[q] = fmaxf(box[q], o[q]);
+}
+
+__global__ __launch_bounds__(kRefitBlock) void leaf_refit_kernel(
+    const float* __restrict__ V, int64_t nv, const int32_t* __restrict__ F, int64_t n,
+    const uint32_t* __restrict__ sorted_idx, Leaf* __restrict__ leaves, BvhNode* nodes,
+    const int32_t* __restrict__ node_parent, const int32_t* __restrict__ leaf_parent,
+    const int2* __restrict__ node_range, int32_t* __restrict__ frontier, uint32_t* nfront,
+    uint32_t front_cap, uint32_t* __restrict__ status) {
+    __shared__ uint32_t lcnt[kRefitTile];
+    const int64_t t0 = (int64_t)blockIdx.x * kRefitTile;
+    const int64_t t1 = t0 + kRefitTile < n ? t0 + kRefitTile : n;
+    for (int i = threadIdx.x; i < kRefitTile; i += kRefitBlock) lcnt[i] = 0;
+    __syncthreads();
+    for (int64_t k = t0 + threadIdx.x; k < t1; k += kRefitBlock) {
+        uint32_t g = sorted_idx[k];
+        bool bad;
+        int3 t = tri_idx(F, g, nv, &bad);
+        float3 a = ldv(V, t.x), b = ldv(V, t.y), c = ldv(V, t.z);
+        Leaf lf;
+        lf.a = make_float4(a.x, a.y, a.z, b.x);
+        lf.b = make_float4(b.y, b.z, c.x, c.y);
+        lf.c = make_float4(c.z, __int_as_float((int32_t)g), 0.f, 0.f);
+        leaves[k] = lf;
+        float box[6] = {fminf(fminf(a.x, b.x), c.x), fminf(fminf(a.y, b.y), c.y),
+                        fminf(fminf(a.z, b.z), c.z), fmaxf(fmaxf(a.x, b.x), c.x),
+                        fmaxf(fmaxf(a.y, b.y), c.y), fmaxf(fmaxf(a.z, b.z), c.z)};
+        // The hit rule accepts crossings with barycentric weights down to
+        // -kLeafEps, i.e. inside the triangle scaled by (1 + 3 kLeafEps) about its
+        // centroid: widen the box by 4 kLeafEps of its extent (3 plus rounding
+        // margin) and a few ulps of its coordinates.
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            float ext = box[q + 3] - box[q];
+            float pad = 4.0f * kLeafEps * ext + 4.76837158e-7f * fmaxf(fabsf(box[q]), fabsf(box[q + 3]));
+            box[q] -= pad;
+            box[q + 3] += pad;
         }
-        int32_t p = pp >> 1;
-        int side = pp & 1;
-        put_slot(&nodes[p], side, box);
-        uint32_t old = __hip_atomic_fetch_add(&cnt[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (old == 0) return;  // the sibling subtree is not finished yet
-        const float* o = reinterpret_cast<const float*>(&nodes[p]) + 6 * (1 - side);
-        float ob[6];
+        int32_t pp = n > 1 ? leaf_parent[k] : -1;
+        for (int level = 0; pp >= 0; ++level) {
+            if (level > 2 * kMaxDepth) {  // only a malformed hierarchy gets here
+                atomicOr(status, kStInternal);
+                break;
+            }
+            int32_t p = pp >> 1;
+            int side = pp & 1;
+            int2 rg = node_range[p];
+            put_slot(&nodes[p], side, box);
+            if (!(rg.x >= t0 && rg.y < t1)) {
+                // p crosses the tile boundary: finished by the top-level pass
+                uint32_t e = atomicAdd(nfront, 1u);
+                if (e < front_cap) frontier[e] = pp;
+                else atomicOr(status, kStInternal);  // impossible for a well-formed tree
+                break;
+            }
+            uint32_t old = __hip_atomic_fetch_add(&lcnt[p - t0], 1u, __ATOMIC_ACQ_REL,
+                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (old == 0) break;  // the sibling subtree is not finished yet
+            union_slot(&nodes[p], 1 - side, box);
+            pp = node_parent[p];
+        }
+    }
+}
+
+
+// Pass 2: one workgroup climbs from the frontier through the tile-crossing
+// nodes.  Each frontier entry says: child `side` of node p is complete and its
+// box is in p's slot.
+__global__ __launch_bounds__(kTopBlock) void refit_top_kernel(BvhNode* nodes,
+                                                             const int32_t* __restrict__ node_parent,
+                                                             const int32_t* __restrict__ frontier,
+                                                             const uint32_t* __restrict__ nfront,
+                                                             uint32_t front_cap, uint32_t* cnt,
+                                                             uint32_t* __restrict__ status) {
+    const uint32_t m = min(*nfront, front_cap);
+    for (uint32_t e = threadIdx.x; e < m; e += kTopBlock) {
+        int32_t pp = frontier[e];
+        for (int level = 0; pp >= 0; ++level) {
+            if (level > 2 * kMaxDepth) {
+                atomicOr(status, kStInternal);
+                break;
+            }
+            int32_t p = pp >> 1;
+            uint32_t old = __hip_atomic_fetch_add(&cnt[p], 1u, __ATOMIC_ACQ_REL,
+                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (old == 0) break;
+            float box[6];
+            const float* f = reinterpret_cast<const float*>(&nodes[p]);
 #pragma unroll
-        for (int q = 0; q < 6; ++q) ob[q] = __hip_atomic_load(o + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int q = 0; q < 3; ++q) box[q] = fminf(f[q], f[6 + q]);
 #pragma unroll
-        for (int q = 0; q < 3; ++q) box[q] = fminf(box[q], ob[q]);
-#pragma unroll
-        for (int q = 3; q < 6; ++q) box[q] = fmaxf(box[q], ob[q]);
-        pp = node_parent[p];
+            for (int q = 3; q < 6; ++q) box[q] = fmaxf(f[q], f[6 + q]);
+            pp = node_parent[p];
+            if (pp >= 0) put_slot(&nodes[pp >> 1], pp & 1, box);
+        }
     }
 }
 
@@ -348,6 +417,7 @@ hipError_t launch_bvh_build(const float* hi_V, int64_t nhv, const int32_t* hi_F,
     int32_t* np = (int32_t*)(ws + L.node_parent);
     int32_t* lp = (int32_t*)(ws + L.leaf_parent);
     uint32_t* cnt = (uint32_t*)(ws + L.refit_cnt);
+    int2* range = (int2*)(ws + L.node_range);
     uint32_t* status = (uint32_t*)(ws + L.status);
 
     int parts = (int)std::min<int64_t>(kBoundsBlocks, (nhf + kBlock - 1) / kBlock);
@@ -376,12 +446,20 @@ hipError_t launch_bvh_build(const float* hi_V, int64_t nhv, const int32_t* hi_F,
     // four passes: the sorted arrays are back in keys0 / vals0
     if (nhf > 1) {
         hipLaunchKernelGGL(karras_kernel, dim3(blocks_for(nhf - 1, kBlock)), dim3(kBlock), 0, s,
-                           (const uint32_t*)k0, nhf, nodes, np, lp);
+                           (const uint32_t*)k0, nhf, nodes, np, lp, range);
         if ((e = fill_u32(cnt, 0, nhf - 1, s)) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(leaf_refit_kernel, dim3(blocks_for(nhf, kBlock)), dim3(kBlock), 0, s, hi_V,
-                       nhv, hi_F, nhf, (const uint32_t*)v0, leaves, nodes, (const int32_t*)np,
-                       (const int32_t*)lp, cnt, status);
+    uint32_t* nfront = (uint32_t*)(ws + L.counters) + kCntFrontier;
+    int32_t* frontier = (int32_t*)(ws + L.frontier);
+    const uint32_t front_cap = (uint32_t)(2 * kMaxDepth * ((nhf + kRefitTile - 1) / kRefitTile + 1));
+    if ((e = fill_u32(nfront, 0, 1, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(leaf_refit_kernel, dim3(blocks_for(nhf, kRefitTile)), dim3(kRefitBlock), 0, s,
+                       hi_V, nhv, hi_F, nhf, (const uint32_t*)v0, leaves, nodes, (const int32_t*)np,
+                       (const int32_t*)lp, (const int2*)range, frontier, nfront, front_cap, status);
+    if (nhf > kRefitTile) {
+        hipLaunchKernelGGL(refit_top_kernel, dim3(1), dim3(kTopBlock), 0, s, nodes, (const int32_t*)np,
+                           (const int32_t*)frontier, (const uint32_t*)nfront, front_cap, cnt, status);
+    }
     return hipGetLastError();
 }
 

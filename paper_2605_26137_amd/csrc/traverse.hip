@@ -35,7 +35,7 @@ namespace {
 
 constexpr int32_t kEmpty = INT32_MIN;
 constexpr float kPad = 1e-6f;
-constexpr float kEdgeEps = 1.0f / 1024.0f;   // must match the leaf-box widening in lbvh.hip
+constexpr float kEdgeEps = 1.0f / 16384.0f;   // must match the leaf-box widening in lbvh.hip
 constexpr float kQuantScale = 1048576.0f;    // 2^20: distance quantum w = max_dist / 2^20
 constexpr uint32_t kFaceReliable = 1u;
 
@@ -183,10 +183,12 @@ struct TravArgs {
     int64_t spill_lanes;
     uint32_t* status;    // device status word
     int64_t step_cap;    // per-ray safety bound on loop steps
+    unsigned long long* n_box;  // box tests (instrumented variant)
+    unsigned long long* n_tri;  // triangle tests (instrumented variant)
     int refill_min;      // refill when at least this many lanes are idle (64: whole wave)
 };
 
-template <int BLOCK, int STACK>
+template <int BLOCK, int STACK, bool COUNT>
 __global__ __launch_bounds__(BLOCK) void traverse_kernel(TravArgs a) {
     __shared__ int32_t stk[STACK][BLOCK];
     const int tid = threadIdx.x;
@@ -208,6 +210,7 @@ __global__ __launch_bounds__(BLOCK) void traverse_kernel(TravArgs a) {
     int32_t node = kEmpty;
     int sp = 0, lo = 0;
     int64_t steps = 0;
+    unsigned long long c_box = 0, c_tri = 0;
 
     while (true) {
         // ---- refill idle lanes from the work queue -------------------------
@@ -289,6 +292,7 @@ __global__ __launch_bounds__(BLOCK) void traverse_kernel(TravArgs a) {
             float mL, mR;
             bool hL = box_test(R, f3(na.x, na.y, na.z), f3(na.w, nb.x, nb.y), best.bound, &mL);
             bool hR = box_test(R, f3(nb.z, nb.w, nc.x), f3(nc.y, nc.z, nc.w), best.bound, &mR);
+            if (COUNT) c_box += 2;
             int32_t next = kEmpty, other = kEmpty;
             if (hL && hR) {
                 bool rfirst = mR < mL;
@@ -318,6 +322,7 @@ __global__ __launch_bounds__(BLOCK) void traverse_kernel(TravArgs a) {
         } else {
             const Leaf L = a.leaves[~node];
             tri_test(R, L, a.max_dist, inv_w, w, &best);
+            if (COUNT) c_tri += 1;
             node = kEmpty;
         }
         if (++steps > a.step_cap) {
@@ -382,9 +387,13 @@ __global__ __launch_bounds__(BLOCK) void traverse_kernel(TravArgs a) {
             a.hits[ridx] = h;
         }
     }
+    if (COUNT) {
+        atomicAdd(a.n_box, c_box);
+        atomicAdd(a.n_tri, c_tri);
+    }
 }
 
-template <int BLOCK, int STACK>
+template <int BLOCK, int STACK, bool COUNT>
 hipError_t launch_one(const TravArgs& args, hipStream_t s, int64_t max_lanes) {
     static int cached_blocks = -1;
     if (cached_blocks < 0) {
@@ -393,7 +402,7 @@ hipError_t launch_one(const TravArgs& args, hipStream_t s, int64_t max_lanes) {
         if (e != hipSuccess) return e;
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) return e;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, traverse_kernel<BLOCK, STACK>, BLOCK, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, traverse_kernel<BLOCK, STACK, COUNT>, BLOCK, 0);
         if (e != hipSuccess) return e;
         if (per < 1) per = 1;
         cached_blocks = cus * per;
@@ -402,7 +411,7 @@ hipError_t launch_one(const TravArgs& args, hipStream_t s, int64_t max_lanes) {
     int64_t cap = max_lanes / BLOCK;
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL((traverse_kernel<BLOCK, STACK>), dim3((unsigned)blocks), dim3(BLOCK), 0, s, args);
+    hipLaunchKernelGGL((traverse_kernel<BLOCK, STACK, COUNT>), dim3((unsigned)blocks), dim3(BLOCK), 0, s, args);
     return hipGetLastError();
 }
 
@@ -440,9 +449,12 @@ hipError_t launch_traverse(const float* lo_V, const int32_t* lo_F, int64_t nlf, 
     a.refill_min = cfg.persist ? 16 : 64;
     a.status = (uint32_t*)(ws + L.status);
     a.step_cap = 4 * nhf + 1024;
+    a.n_box = (unsigned long long*)(counters + kCntBoxLo);
+    a.n_tri = (unsigned long long*)(counters + kCntTriLo);
     int64_t lanes = L.spill_lanes;
+    if (cfg.count) return launch_one<256, 16, true>(a, s, lanes);
 #define BAKE_TRAV_CASE(B, S) \
-    if (cfg.block == B && cfg.stack == S) return launch_one<B, S>(a, s, lanes);
+    if (cfg.block == B && cfg.stack == S) return launch_one<B, S, false>(a, s, lanes);
     BAKE_TRAV_CASE(64, 8) BAKE_TRAV_CASE(64, 16) BAKE_TRAV_CASE(64, 32)
     BAKE_TRAV_CASE(128, 8) BAKE_TRAV_CASE(128, 16) BAKE_TRAV_CASE(128, 32)
     BAKE_TRAV_CASE(256, 8) BAKE_TRAV_CASE(256, 16) BAKE_TRAV_CASE(256, 32)

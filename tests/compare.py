@@ -26,7 +26,7 @@ import numpy as np
 ANGLE_TOL_DEG = 0.05
 AGREE_MIN = 0.999
 TIE_REL = 1e-6
-EDGE_EPS = 1.0 / 1024.0   # the hit rule's edge tolerance (barycentric units)
+EDGE_EPS = 1.0 / 16384.0  # the hit rule's edge tolerance (barycentric units)
 BARY_SLACK = 1e-4         # FP32 noise allowance on barycentric weights
 
 
