@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--trav-block", type=int, default=0)
     ap.add_argument("--trav-stack", type=int, default=0)
     ap.add_argument("--trav-persist", type=int, default=-1)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run device-to-device copies of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build bakes on a single device "
@@ -114,6 +116,17 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        # a plain copy kernel of known size: the reference for scaling the
+        # FETCH_SIZE / WRITE_SIZE counters into bytes
+        n = args.calibrate_copy << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n, "copies": 3}), flush=True)
+        return
     print(f"[bench] {B.version()} on {torch.cuda.get_device_name(0)}", file=sys.stderr, flush=True)
     asset = make_config(2)
     t = B.to_device(asset, dev)

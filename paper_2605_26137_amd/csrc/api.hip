@@ -53,7 +53,7 @@ int32_t parse_opts(const bake_options* o, Opts* out) {
     out->rgb8 = nullptr;
     out->trav.block = 256;
     out->trav.stack = 16;
-    out->trav.persist = 1;
+    out->trav.persist = 0;
     if (!o) return BAKE_OK;
     if (o->dilate_passes < 0 || o->dilate_passes > 64)
         return fail(BAKE_E_INVALID_ARG, "dilate_passes %d outside [0, 64]", o->dilate_passes);
@@ -137,8 +137,8 @@ Layout make_layout(int64_t nhv, int64_t nhf, int64_t nlv, int64_t nlf, int32_t r
     L.leaf_parent = take(4 * (size_t)std::max<int64_t>(nhf, 1));
     L.refit_cnt = take(4 * (size_t)std::max<int64_t>(nhf - 1, 1));
     L.node_range = take(8 * (size_t)std::max<int64_t>(nhf - 1, 1));
-    // tile-crossing nodes: at most (tiles - 1) boundaries x depth, 2 entries each
-    L.frontier = take(4 * (size_t)(2 * kMaxDepth * ((nhf + kRefitTileLeaves - 1) / kRefitTileLeaves + 1)));
+    L.frontier = take(4 * (size_t)treelet_cap(nhf));
+    L.treelets = take(16 * (size_t)treelet_cap(nhf));
     L.spill = take(4 * (size_t)kMaxDepth * (size_t)L.spill_lanes);
     L.total = off;
     return L;

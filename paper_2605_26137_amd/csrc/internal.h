@@ -75,7 +75,7 @@ struct Layout {
     size_t rays, hits;                        // per ray
     size_t bounds_part, bounds;               // centroid bounds reduction
     size_t keys0, keys1, vals0, vals1, hist;  // radix sort
-    size_t nodes, leaves, node_parent, leaf_parent, refit_cnt, node_range, frontier;
+    size_t nodes, leaves, node_parent, leaf_parent, refit_cnt, node_range, frontier, treelets;
     size_t spill;                             // traversal stack spill
     size_t bwd0, bwd1, bwd2, bwd3, bwd4, bwd5;  // backward scratch
     size_t total;
@@ -89,7 +89,15 @@ constexpr int kCntQueue = 1;     // persistent traversal work queue head
 constexpr int kCntBoxLo = 2;     // u64 box tests (FLAG_COUNT), slots 2-3
 constexpr int kCntTriLo = 4;     // u64 triangle tests (FLAG_COUNT), slots 4-5
 constexpr int kCntFrontier = 6;  // refit frontier length
-constexpr int kRefitTileLeaves = 4096;  // leaves per refit tile (lbvh.hip)
+constexpr int kCntTreelets = 7;  // number of refit treelets
+
+// Capacity of the treelet list and of the refit frontier.  Treelet roots are
+// the small children of the nodes with more than 2048 leaves ("big" nodes).
+// Big nodes whose children are both small cover disjoint ranges of > 2048
+// leaves, so there are fewer than n / 2048 of them, and every big node lies
+// on the root path (at most 62 nodes) of one of them: fewer than 62 n / 2048
+// + 62 big nodes, one more treelet than big nodes.
+inline int64_t treelet_cap(int64_t n) { return n / 32 + 2 * kMaxDepth + 16; }
 constexpr int kCntSlots = 16;
 
 // Traversal configuration

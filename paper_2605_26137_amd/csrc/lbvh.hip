@@ -270,22 +270,23 @@ __global__ void karras_kernel(const uint32_t* __restrict__ keys, int64_t n, BvhN
 // 5. leaves + refit
 // ---------------------------------------------------------------------------
 //
-// Two launches, with no device-scope ordering inside either:
-//  1. one workgroup per tile of kRefitTile consecutive sorted leaves.  A Karras
-//     node covers the contiguous leaf range [lo, hi] and sits at one end of it,
-//     so every node whose range lies inside the tile also has its index inside
-//     the tile: the workgroup refits all of those with arrival counters in LDS
-//     and workgroup-scope ordering.  A child whose parent's range crosses the
-//     tile boundary writes its box into the parent's slot and appends the
-//     parent reference to a frontier list.
-//  2. a single workgroup finishes the nodes that cross tile boundaries (about
-//     (n / tile) x depth of them), starting from the frontier, with arrival
-//     counters in global memory that only this workgroup touches.
-// (Device-scope acquire/release per node costs an L2 write-back and
-// invalidation across the XCDs and serialises the upper levels.)
+// The refit avoids device-scope ordering per node (an acquire/release at
+// device scope costs an L2 write-back and invalidation across the XCDs, and
+// chains of them serialise the upper levels):
+//  a. leaf packing: one thread per sorted leaf;
+//  b. treelets: the maximal subtrees with at most kTreelet leaves.  A Karras
+//     node covers a contiguous leaf range [lo, hi] and its index lies in that
+//     range, so a treelet's internal nodes have indices in [lo, hi] too;
+//  c. one workgroup per treelet loads the parent links of [lo, hi] into LDS
+//     and refits bottom-up with LDS arrival counters, keeping the first
+//     arrival's box in LDS; the completing thread of a node writes both child
+//     boxes to the node.  The treelet root's box goes to its parent's slot and
+//     the parent is appended to a frontier;
+//  d. one workgroup finishes the few nodes above the treelets from the
+//     frontier (global counters that only this workgroup touches).
 
-constexpr int kRefitTile = kRefitTileLeaves;
-constexpr int kRefitBlock = 512;
+constexpr int kTreelet = 2048;
+constexpr int kRefitBlock = 256;
 constexpr int kTopBlock = 1024;
 
 __device__ __forceinline__ void put_slot(BvhNode* node, int side, const float b[6]) {
@@ -294,78 +295,139 @@ __device__ __forceinline__ void put_slot(BvhNode* node, int side, const float b[
     for (int k = 0; k < 6; ++k) f[k] = b[k];
 }
 
-__device__ __forceinline__ void union_slot(const BvhNode* node, int side, float box[6]) {
-    const float* o = reinterpret_cast<const float*>(node) + 6 * side;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) box[q] = fminf(box[q], o[q]);
-#pragma unroll
-    for (int q = 3; q < 6; ++q) box[q] = fmaxf(box[q], o[q]);
+__global__ void leaf_pack_kernel(const float* __restrict__ V, int64_t nv, const int32_t* __restrict__ F,
+                                 int64_t n, const uint32_t* __restrict__ sorted_idx,
+                                 Leaf* __restrict__ leaves) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    uint32_t g = sorted_idx[k];
+    bool bad;
+    int3 t = tri_idx(F, g, nv, &bad);
+    float3 a = ldv(V, t.x), b = ldv(V, t.y), c = ldv(V, t.z);
+    Leaf lf;
+    lf.a = make_float4(a.x, a.y, a.z, b.x);
+    lf.b = make_float4(b.y, b.z, c.x, c.y);
+    lf.c = make_float4(c.z, __int_as_float((int32_t)g), 0.f, 0.f);
+    leaves[k] = lf;
 }
 
-__global__ __launch_bounds__(kRefitBlock) void leaf_refit_kernel(
-    const float* __restrict__ V, int64_t nv, const int32_t* __restrict__ F, int64_t n,
-    const uint32_t* __restrict__ sorted_idx, Leaf* __restrict__ leaves, BvhNode* nodes,
-    const int32_t* __restrict__ node_parent, const int32_t* __restrict__ leaf_parent,
-    const int2* __restrict__ node_range, int32_t* __restrict__ frontier, uint32_t* nfront,
-    uint32_t front_cap, uint32_t* __restrict__ status) {
-    __shared__ uint32_t lcnt[kRefitTile];
-    const int64_t t0 = (int64_t)blockIdx.x * kRefitTile;
-    const int64_t t1 = t0 + kRefitTile < n ? t0 + kRefitTile : n;
-    for (int i = threadIdx.x; i < kRefitTile; i += kRefitBlock) lcnt[i] = 0;
-    __syncthreads();
-    for (int64_t k = t0 + threadIdx.x; k < t1; k += kRefitBlock) {
-        uint32_t g = sorted_idx[k];
-        bool bad;
-        int3 t = tri_idx(F, g, nv, &bad);
-        float3 a = ldv(V, t.x), b = ldv(V, t.y), c = ldv(V, t.z);
-        Leaf lf;
-        lf.a = make_float4(a.x, a.y, a.z, b.x);
-        lf.b = make_float4(b.y, b.z, c.x, c.y);
-        lf.c = make_float4(c.z, __int_as_float((int32_t)g), 0.f, 0.f);
-        leaves[k] = lf;
-        float box[6] = {fminf(fminf(a.x, b.x), c.x), fminf(fminf(a.y, b.y), c.y),
-                        fminf(fminf(a.z, b.z), c.z), fmaxf(fmaxf(a.x, b.x), c.x),
-                        fmaxf(fmaxf(a.y, b.y), c.y), fmaxf(fmaxf(a.z, b.z), c.z)};
-        // The hit rule accepts crossings with barycentric weights down to
-        // -kLeafEps, i.e. inside the triangle scaled by (1 + 3 kLeafEps) about its
-        // centroid: widen the box by 4 kLeafEps of its extent (3 plus rounding
-        // margin) and a few ulps of its coordinates.
+// Box of a leaf triangle, widened for the hit rule's edge tolerance: weights
+// down to -kLeafEps put the crossing inside the triangle scaled by (1 + 3
+// kLeafEps) about its centroid; widen by 4 kLeafEps of the extent (3 plus
+// rounding margin) and a few ulps of the coordinates.
+__device__ __forceinline__ void leaf_box(const Leaf& L, float box[6]) {
+    float ax = L.a.x, ay = L.a.y, az = L.a.z, bx = L.a.w, by = L.b.x, bz = L.b.y;
+    float cx = L.b.z, cy = L.b.w, cz = L.c.x;
+    box[0] = fminf(fminf(ax, bx), cx); box[1] = fminf(fminf(ay, by), cy); box[2] = fminf(fminf(az, bz), cz);
+    box[3] = fmaxf(fmaxf(ax, bx), cx); box[4] = fmaxf(fmaxf(ay, by), cy); box[5] = fmaxf(fmaxf(az, bz), cz);
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            float ext = box[q + 3] - box[q];
-            float pad = 4.0f * kLeafEps * ext + 4.76837158e-7f * fmaxf(fabsf(box[q]), fabsf(box[q + 3]));
-            box[q] -= pad;
-            box[q + 3] += pad;
-        }
-        int32_t pp = n > 1 ? leaf_parent[k] : -1;
-        for (int level = 0; pp >= 0; ++level) {
-            if (level > 2 * kMaxDepth) {  // only a malformed hierarchy gets here
-                atomicOr(status, kStInternal);
-                break;
-            }
-            int32_t p = pp >> 1;
-            int side = pp & 1;
-            int2 rg = node_range[p];
-            put_slot(&nodes[p], side, box);
-            if (!(rg.x >= t0 && rg.y < t1)) {
-                // p crosses the tile boundary: finished by the top-level pass
-                uint32_t e = atomicAdd(nfront, 1u);
-                if (e < front_cap) frontier[e] = pp;
-                else atomicOr(status, kStInternal);  // impossible for a well-formed tree
-                break;
-            }
-            uint32_t old = __hip_atomic_fetch_add(&lcnt[p - t0], 1u, __ATOMIC_ACQ_REL,
-                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (old == 0) break;  // the sibling subtree is not finished yet
-            union_slot(&nodes[p], 1 - side, box);
-            pp = node_parent[p];
-        }
+    for (int q = 0; q < 3; ++q) {
+        float ext = box[q + 3] - box[q];
+        float pad = 4.0f * kLeafEps * ext + 4.76837158e-7f * fmaxf(fabsf(box[q]), fabsf(box[q + 3]));
+        box[q] -= pad;
+        box[q + 3] += pad;
     }
 }
 
+// Treelet roots: nodes (internal i < n-1, or leaf ~k) of at most kTreelet
+// leaves whose parent has more (or that are the root).
+__global__ void treelet_find_kernel(int64_t n, const int2* __restrict__ node_range,
+                                    const int32_t* __restrict__ node_parent,
+                                    const int32_t* __restrict__ leaf_parent, int4* __restrict__ list,
+                                    uint32_t* __restrict__ count, uint32_t cap, uint32_t* __restrict__ status) {
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= 2 * n - 1) return;
+    int32_t ref, lo, hi, pp;
+    if (x < n - 1) {
+        int2 r = node_range[x];
+        ref = (int32_t)x; lo = r.x; hi = r.y;
+        pp = node_parent[x];
+    } else {
+        int32_t k = (int32_t)(x - (n - 1));
+        ref = ~k; lo = hi = k;
+        pp = n > 1 ? leaf_parent[k] : -1;
+    }
+    if (hi - lo + 1 > kTreelet) return;
+    if (pp >= 0) {
+        int2 pr = node_range[pp >> 1];
+        if (pr.y - pr.x + 1 <= kTreelet) return;
+    }
+    uint32_t e = atomicAdd(count, 1u);
+    if (e < cap) list[e] = make_int4(ref, lo, hi, pp);
+    else atomicOr(status, kStInternal);
+}
 
-// Pass 2: one workgroup climbs from the frontier through the tile-crossing
-// nodes.  Each frontier entry says: child `side` of node p is complete and its
+__global__ __launch_bounds__(kRefitBlock) void treelet_refit_kernel(
+    int64_t n, const Leaf* __restrict__ leaves, BvhNode* __restrict__ nodes,
+    const int32_t* __restrict__ node_parent, const int32_t* __restrict__ leaf_parent,
+    const int4* __restrict__ list, const uint32_t* __restrict__ count, uint32_t cap,
+    int32_t* __restrict__ frontier, uint32_t* __restrict__ nfront, uint32_t front_cap,
+    uint32_t* __restrict__ status) {
+    __shared__ int32_t s_np[kTreelet];      // parent link of internal node lo + i
+    __shared__ int32_t s_lp[kTreelet];      // parent link of leaf lo + i
+    __shared__ uint32_t s_cnt[kTreelet];    // arrivals at internal node lo + i
+    __shared__ float s_box[kTreelet][6];    // first arrival's box at internal node lo + i
+    const uint32_t m = min(*count, cap);
+    for (uint32_t tl = blockIdx.x; tl < m; tl += gridDim.x) {
+        const int4 T = list[tl];
+        const int32_t ref = T.x, lo = T.y, hi = T.z, rootpp = T.w;
+        const int32_t sz = hi - lo + 1;
+        for (int i = threadIdx.x; i < sz; i += kRefitBlock) {
+            s_np[i] = (lo + i < n - 1) ? node_parent[lo + i] : -1;
+            s_lp[i] = n > 1 ? leaf_parent[lo + i] : -1;
+            s_cnt[i] = 0;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < sz; i += kRefitBlock) {
+            float box[6];
+            leaf_box(leaves[lo + i], box);
+            int32_t cur = ~(lo + i);   // node whose box is in `box`
+            int32_t pp = s_lp[i];
+            for (int level = 0;; ++level) {
+                if (cur == ref) {
+                    // treelet complete: hand its box to the node above
+                    if (rootpp >= 0) {
+                        put_slot(&nodes[rootpp >> 1], rootpp & 1, box);
+                        uint32_t e = atomicAdd(nfront, 1u);
+                        if (e < front_cap) frontier[e] = rootpp;
+                        else atomicOr(status, kStInternal);
+                    }
+                    break;
+                }
+                if (level > 2 * kMaxDepth || pp < 0) {  // only a malformed hierarchy gets here
+                    atomicOr(status, kStInternal);
+                    break;
+                }
+                const int32_t p = pp >> 1, side = pp & 1, li = p - lo;
+                if (li < 0 || li >= sz) {  // only a malformed hierarchy gets here
+                    atomicOr(status, kStInternal);
+                    break;
+                }
+                // first arrival leaves its box in LDS; LDS-only ordering
+#pragma unroll
+                for (int q = 0; q < 6; ++q) s_box[li][q] = box[q];
+                uint32_t old = __hip_atomic_fetch_add(&s_cnt[li], 1u, __ATOMIC_ACQ_REL,
+                                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (old == 0) break;
+                float sib[6];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) sib[q] = s_box[li][q];
+                put_slot(&nodes[p], side, box);
+                put_slot(&nodes[p], 1 - side, sib);
+#pragma unroll
+                for (int q = 0; q < 3; ++q) box[q] = fminf(box[q], sib[q]);
+#pragma unroll
+                for (int q = 3; q < 6; ++q) box[q] = fmaxf(box[q], sib[q]);
+                cur = p;
+                pp = s_np[li];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Top pass: one workgroup climbs from the frontier through the nodes above
+// the treelets.  Each frontier entry says: child `side` of node p is complete and its
 // box is in p's slot.
 __global__ __launch_bounds__(kTopBlock) void refit_top_kernel(BvhNode* nodes,
                                                              const int32_t* __restrict__ node_parent,
@@ -449,14 +511,25 @@ hipError_t launch_bvh_build(const float* hi_V, int64_t nhv, const int32_t* hi_F,
                            (const uint32_t*)k0, nhf, nodes, np, lp, range);
         if ((e = fill_u32(cnt, 0, nhf - 1, s)) != hipSuccess) return e;
     }
-    uint32_t* nfront = (uint32_t*)(ws + L.counters) + kCntFrontier;
+    uint32_t* counters = (uint32_t*)(ws + L.counters);
+    uint32_t* nfront = counters + kCntFrontier;
+    uint32_t* ntl = counters + kCntTreelets;
     int32_t* frontier = (int32_t*)(ws + L.frontier);
-    const uint32_t front_cap = (uint32_t)(2 * kMaxDepth * ((nhf + kRefitTile - 1) / kRefitTile + 1));
-    if ((e = fill_u32(nfront, 0, 1, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(leaf_refit_kernel, dim3(blocks_for(nhf, kRefitTile)), dim3(kRefitBlock), 0, s,
-                       hi_V, nhv, hi_F, nhf, (const uint32_t*)v0, leaves, nodes, (const int32_t*)np,
-                       (const int32_t*)lp, (const int2*)range, frontier, nfront, front_cap, status);
-    if (nhf > kRefitTile) {
+    int4* tlist = (int4*)(ws + L.treelets);
+    const uint32_t tcap = (uint32_t)treelet_cap(nhf);
+    const uint32_t front_cap = tcap;
+    if ((e = fill_u32(nfront, 0, 2, s)) != hipSuccess) return e;  // frontier + treelet counts
+    hipLaunchKernelGGL(leaf_pack_kernel, dim3(blocks_for(nhf, kBlock)), dim3(kBlock), 0, s, hi_V, nhv,
+                       hi_F, nhf, (const uint32_t*)v0, leaves);
+    hipLaunchKernelGGL(treelet_find_kernel, dim3(blocks_for(2 * nhf - 1, kBlock)), dim3(kBlock), 0, s,
+                       nhf, (const int2*)range, (const int32_t*)np, (const int32_t*)lp, tlist, ntl, tcap,
+                       status);
+    if (nhf > 1) {
+        int grid = (int)std::min<int64_t>(2048, (nhf + kTreelet / 2 - 1) / (kTreelet / 2) + 1);
+        hipLaunchKernelGGL(treelet_refit_kernel, dim3(grid), dim3(kRefitBlock), 0, s, nhf,
+                           (const Leaf*)leaves, nodes, (const int32_t*)np, (const int32_t*)lp,
+                           (const int4*)tlist, (const uint32_t*)ntl, tcap, frontier, nfront, front_cap,
+                           status);
         hipLaunchKernelGGL(refit_top_kernel, dim3(1), dim3(kTopBlock), 0, s, nodes, (const int32_t*)np,
                            (const int32_t*)frontier, (const uint32_t*)nfront, front_cap, cnt, status);
     }
