@@ -278,10 +278,10 @@ __global__ void karras_kernel(const uint32_t* __restrict__ keys, int64_t n, BvhN
 //     node covers a contiguous leaf range [lo, hi] and its index lies in that
 //     range, so a treelet's internal nodes have indices in [lo, hi] too;
 //  c. one workgroup per treelet loads the parent links of [lo, hi] into LDS
-//     and refits bottom-up with LDS arrival counters, keeping the first
-//     arrival's box in LDS; the completing thread of a node writes both child
-//     boxes to the node.  The treelet root's box goes to its parent's slot and
-//     the parent is appended to a frontier;
+//     and refits bottom-up: each child writes its box into its slot of the
+//     parent node, then counts its arrival in LDS; the second arrival reads
+//     the sibling's slot and continues.  The treelet root's box goes to its
+//     parent's slot and the parent is appended to a frontier;
 //  d. one workgroup finishes the few nodes above the treelets from the
 //     frontier (global counters that only this workgroup touches).
 
@@ -358,7 +358,7 @@ __global__ void treelet_find_kernel(int64_t n, const int2* __restrict__ node_ran
 }
 
 __global__ __launch_bounds__(kRefitBlock) void treelet_refit_kernel(
-    int64_t n, const Leaf* __restrict__ leaves, BvhNode* __restrict__ nodes,
+    int64_t n, const Leaf* __restrict__ leaves, BvhNode* nodes,
     const int32_t* __restrict__ node_parent, const int32_t* __restrict__ leaf_parent,
     const int4* __restrict__ list, const uint32_t* __restrict__ count, uint32_t cap,
     int32_t* __restrict__ frontier, uint32_t* __restrict__ nfront, uint32_t front_cap,
@@ -366,7 +366,6 @@ __global__ __launch_bounds__(kRefitBlock) void treelet_refit_kernel(
     __shared__ int32_t s_np[kTreelet];      // parent link of internal node lo + i
     __shared__ int32_t s_lp[kTreelet];      // parent link of leaf lo + i
     __shared__ uint32_t s_cnt[kTreelet];    // arrivals at internal node lo + i
-    __shared__ float s_box[kTreelet][6];    // first arrival's box at internal node lo + i
     const uint32_t m = min(*count, cap);
     for (uint32_t tl = blockIdx.x; tl < m; tl += gridDim.x) {
         const int4 T = list[tl];
@@ -403,17 +402,13 @@ __global__ __launch_bounds__(kRefitBlock) void treelet_refit_kernel(
                     atomicOr(status, kStInternal);
                     break;
                 }
-                // first arrival leaves its box in LDS; LDS-only ordering
-#pragma unroll
-                for (int q = 0; q < 6; ++q) s_box[li][q] = box[q];
+                // each child writes its own slot of p; the second arrival
+                // (workgroup-scope acquire on the LDS counter) reads the other
+                put_slot(&nodes[p], side, box);
                 uint32_t old = __hip_atomic_fetch_add(&s_cnt[li], 1u, __ATOMIC_ACQ_REL,
                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
                 if (old == 0) break;
-                float sib[6];
-#pragma unroll
-                for (int q = 0; q < 6; ++q) sib[q] = s_box[li][q];
-                put_slot(&nodes[p], side, box);
-                put_slot(&nodes[p], 1 - side, sib);
+                const float* sib = reinterpret_cast<const float*>(&nodes[p]) + 6 * (1 - side);
 #pragma unroll
                 for (int q = 0; q < 3; ++q) box[q] = fminf(box[q], sib[q]);
 #pragma unroll
