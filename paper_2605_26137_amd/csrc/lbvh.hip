@@ -278,10 +278,11 @@ __global__ void karras_kernel(const uint32_t* __restrict__ keys, int64_t n, BvhN
 //     node covers a contiguous leaf range [lo, hi] and its index lies in that
 //     range, so a treelet's internal nodes have indices in [lo, hi] too;
 //  c. one workgroup per treelet loads the parent links of [lo, hi] into LDS
-//     and refits bottom-up: each child writes its box into its slot of the
-//     parent node, then counts its arrival in LDS; the second arrival reads
-//     the sibling's slot and continues.  The treelet root's box goes to its
-//     parent's slot and the parent is appended to a frontier;
+//     and refits bottom-up: each child leaves its box in its own LDS slot of
+//     the parent (one slot per side) and counts its arrival in LDS; the second
+//     arrival reads the sibling's slot, writes the node and continues.  The
+//     treelet root's box goes to its parent's slot and the parent is appended
+//     to a frontier;
 //  d. one workgroup finishes the few nodes above the treelets from the
 //     frontier (global counters that only this workgroup touches).
 
@@ -366,6 +367,7 @@ __global__ __launch_bounds__(kRefitBlock) void treelet_refit_kernel(
     __shared__ int32_t s_np[kTreelet];      // parent link of internal node lo + i
     __shared__ int32_t s_lp[kTreelet];      // parent link of leaf lo + i
     __shared__ uint32_t s_cnt[kTreelet];    // arrivals at internal node lo + i
+    __shared__ float s_box[kTreelet][2][6]; // child boxes of internal node lo + i, by side
     const uint32_t m = min(*count, cap);
     for (uint32_t tl = blockIdx.x; tl < m; tl += gridDim.x) {
         const int4 T = list[tl];
@@ -402,13 +404,19 @@ __global__ __launch_bounds__(kRefitBlock) void treelet_refit_kernel(
                     atomicOr(status, kStInternal);
                     break;
                 }
-                // each child writes its own slot of p; the second arrival
-                // (workgroup-scope acquire on the LDS counter) reads the other
-                put_slot(&nodes[p], side, box);
+                // each child leaves its box in its own LDS slot of p and
+                // counts its arrival; the second arrival (workgroup-scope
+                // acquire) reads the other slot and writes the node out
+#pragma unroll
+                for (int q = 0; q < 6; ++q) s_box[li][side][q] = box[q];
                 uint32_t old = __hip_atomic_fetch_add(&s_cnt[li], 1u, __ATOMIC_ACQ_REL,
                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
                 if (old == 0) break;
-                const float* sib = reinterpret_cast<const float*>(&nodes[p]) + 6 * (1 - side);
+                float sib[6];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) sib[q] = s_box[li][1 - side][q];
+                put_slot(&nodes[p], side, box);
+                put_slot(&nodes[p], 1 - side, sib);
 #pragma unroll
                 for (int q = 0; q < 3; ++q) box[q] = fminf(box[q], sib[q]);
 #pragma unroll

@@ -5,10 +5,13 @@
 // interpolate the high-poly normal with the hit's barycentric weights and
 // project it into the texel's tangent frame.
 //
-// Traversal:
-//   * persistent waves; lanes whose ray is finished are refilled from a device
-//     work queue (wave-level compaction after Aila & Laine 2009), so a wave
-//     keeps doing useful work while rays of different lengths finish;
+// Traversal (two launch shapes, same per-ray arithmetic and results):
+//   * wave batches (default): persistent waves take 64 consecutive rays of the
+//     face-ordered ray list from a device work queue, trace them together in a
+//     tight loop and encode when the whole batch is done: neighbouring texels
+//     of one face walk nearly the same nodes;
+//   * lane refill: lanes whose ray finished are refilled from the queue while
+//     the rest continue (wave-level compaction after Aila & Laine 2009);
 //   * conservative slab test: near/far planes picked by the sign of the
 //     direction, t widened outward by a relative 1e-6 (after Ize 2013); a zero
 //     direction component yields NaN for a ray lying in a slab plane, which
@@ -27,6 +30,8 @@
 //     two faces; two-sided;
 //   * short per-lane stack in LDS, spilling its oldest entries to a per-lane
 //     global area when full (the Karras tree depth is bounded by 62).
+#include <algorithm>
+
 #include "internal.h"
 
 namespace bake {
@@ -114,12 +119,14 @@ __device__ __forceinline__ bool box_test(const RayT& r, float3 lo, float3 hi, fl
     float t0z = (nz - r.p.z) * r.invd.z, t1z = (fz - r.p.z) * r.invd.z;
     float t0 = fmaxf(fmaxf(t0x, t0y), t0z);
     float t1 = fminf(fminf(t1x, t1y), t1z);
-    // widen outward; a multiply keeps +-inf finite-signed (no inf - inf)
-    t0 = t0 * (t0 > 0.f ? 1.0f - kPad : 1.0f + kPad);
-    t1 = t1 * (t1 > 0.f ? 1.0f + kPad : 1.0f - kPad);
+    // widen outward by a relative kPad (one fma each).  An infinite end turns
+    // into NaN here, which the NaN-ignoring clamps below replace by the bound:
+    // the box is kept, never wrongly culled.
+    t0 = fmaf(-kPad, fabsf(t0), t0);
+    t1 = fmaf(kPad, fabsf(t1), t1);
     t0 = fmaxf(t0, -bound);
     t1 = fminf(t1, bound);
-    *mint = t0 > 0.f ? t0 : (t1 < 0.f ? -t1 : 0.f);
+    *mint = fmaxf(fmaxf(t0, -t1), 0.f);  // nearest |t| of [t0, t1]
     return t0 <= t1;
 }
 
@@ -146,7 +153,8 @@ __device__ __forceinline__ void tri_test(const RayT& r, const Leaf& L, float max
     }
     if (fminf(fminf(U, V), W) < -kEdgeEps * det) return;
     float T = U * A.z + V * B.z + W * C.z;
-    float t = T / det;
+    float rdet = 1.0f / det;
+    float t = T * rdet;
     float at = fabsf(t);
     if (!(at <= max_dist)) return;
     uint32_t key = (uint32_t)(at * inv_w);
@@ -154,8 +162,8 @@ __device__ __forceinline__ void tri_test(const RayT& r, const Leaf& L, float max
         b->key = key;
         b->id = id;
         b->t = t;
-        b->b1 = V / det;
-        b->b2 = W / det;
+        b->b1 = V * rdet;
+        b->b2 = W * rdet;
         b->bound = (float)(key + 1u) * w * (1.0f + kPad);
     }
 }
@@ -182,40 +190,258 @@ struct TravArgs {
     int32_t* spill;      // [kMaxDepth][spill_lanes]
     int64_t spill_lanes;
     uint32_t* status;    // device status word
-    int64_t step_cap;    // per-ray safety bound on loop steps
+    int32_t step_cap;    // per-ray safety bound on loop steps
     unsigned long long* n_box;  // box tests (instrumented variant)
     unsigned long long* n_tri;  // triangle tests (instrumented variant)
-    int refill_min;      // refill when at least this many lanes are idle (64: whole wave)
 };
 
+// Ray setup from the G-buffer record: world position p, interpolated smooth
+// normal d, tangent T' orthogonalised against d, UV handedness.  rel = false
+// when the face or the frame is degenerate (the texel is unreliable).
+struct RaySetup {
+    float3 p, d, Tp;
+    float hsign;
+    int32_t texel;
+    bool rel;
+};
+
+__device__ __forceinline__ RaySetup setup_ray(const TravArgs& a, const Ray& ray) {
+    RaySetup r;
+    r.texel = ray.texel;
+    const int32_t face = ray.face;
+    float b1 = ray.b1, b2 = ray.b2, b0 = 1.0f - b1 - b2;
+    int32_t i0 = a.lo_F[3 * face], i1 = a.lo_F[3 * face + 1], i2 = a.lo_F[3 * face + 2];
+    float3 V0 = ld3(a.lo_V, i0), V1 = ld3(a.lo_V, i1), V2 = ld3(a.lo_V, i2);
+    float4 n0 = a.lo_n[i0], n1 = a.lo_n[i1], n2 = a.lo_n[i2];
+    r.p = f3(b0 * V0.x + b1 * V1.x + b2 * V2.x, b0 * V0.y + b1 * V1.y + b2 * V2.y,
+             b0 * V0.z + b1 * V1.z + b2 * V2.z);
+    float3 m = f3(b0 * n0.x + b1 * n1.x + b2 * n2.x, b0 * n0.y + b1 * n1.y + b2 * n2.y,
+                  b0 * n0.z + b1 * n1.z + b2 * n2.z);
+    float4 T4 = a.face_t[face];
+    uint32_t fl = (uint32_t)a.face_uv[2 * face + 1].z;
+    bool rel = (fl & kFaceReliable) && n0.w != 0.f && n1.w != 0.f && n2.w != 0.f;
+    float l2 = dot3(m, m);
+    rel = rel && l2 > 0.f;
+    float rl = rel ? 1.0f / sqrtf(l2) : 0.f;
+    r.d = f3(m.x * rl, m.y * rl, m.z * rl);
+    float3 T = f3(T4.x, T4.y, T4.z);
+    float dt = dot3(r.d, T);
+    float3 Tp = f3(T.x - dt * r.d.x, T.y - dt * r.d.y, T.z - dt * r.d.z);
+    float lt2 = dot3(Tp, Tp);
+    rel = rel && lt2 > 0.f;
+    float rt = rel ? 1.0f / sqrtf(lt2) : 0.f;
+    r.Tp = f3(Tp.x * rt, Tp.y * rt, Tp.z * rt);
+    r.hsign = T4.w;
+    r.rel = rel;
+    return r;
+}
+
+// Interpolate the hit's high-poly normal, project it into (T', B', d) and
+// write the texel; unreliable and missed rays get (0,0,1).
+__device__ __forceinline__ void finish_ray(const TravArgs& a, uint32_t ridx, const RaySetup& rs,
+                                           const Best& best) {
+    float3 out = f3(0.f, 0.f, 1.f);
+    int32_t st = rs.rel ? kMiss : kUnreliable;
+    float beta1 = 0.f, beta2 = 0.f, tt = 0.f;
+    if (rs.rel && best.id != INT32_MAX) {
+        int32_t g = best.id;
+        int32_t j0 = a.hi_F[3 * (int64_t)g], j1 = a.hi_F[3 * (int64_t)g + 1],
+                j2 = a.hi_F[3 * (int64_t)g + 2];
+        bool ok = j0 >= 0 && j1 >= 0 && j2 >= 0 && j0 < a.nhv && j1 < a.nhv && j2 < a.nhv;
+        beta1 = best.b1;
+        beta2 = best.b2;
+        tt = best.t;
+        float beta0 = 1.0f - beta1 - beta2;
+        st = kUnreliable;
+        if (ok) {
+            float3 N0 = ld3(a.hi_N, j0), N1 = ld3(a.hi_N, j1), N2 = ld3(a.hi_N, j2);
+            float3 h = f3(beta0 * N0.x + beta1 * N1.x + beta2 * N2.x,
+                          beta0 * N0.y + beta1 * N1.y + beta2 * N2.y,
+                          beta0 * N0.z + beta1 * N1.z + beta2 * N2.z);
+            float lh2 = dot3(h, h);
+            if (lh2 > 0.f && isfinite(lh2)) {
+                float rh = 1.0f / sqrtf(lh2);
+                float3 n = f3(h.x * rh, h.y * rh, h.z * rh);
+                float3 c = cross3(rs.d, rs.Tp);
+                float3 Bp = f3(rs.hsign * c.x, rs.hsign * c.y, rs.hsign * c.z);
+                out = f3(dot3(n, rs.Tp), dot3(n, Bp), dot3(n, rs.d));
+                st = g;
+            }
+        }
+    }
+    const int64_t t = rs.texel;
+    a.out_map[3 * t] = out.x;
+    a.out_map[3 * t + 1] = out.y;
+    a.out_map[3 * t + 2] = out.z;
+    a.out_hit[t] = st;
+    if (a.hits) {
+        Hit h;
+        h.t = tt;
+        h.beta1 = beta1;
+        h.beta2 = beta2;
+        h.id = st;
+        a.hits[ridx] = h;
+    }
+}
+
+// Per-lane short stack: entries [lo, sp) in LDS (ring of STACK), older ones
+// spilled to a per-lane column of global memory.
+template <int BLOCK, int STACK>
+struct LaneStack {
+    int32_t (*lds)[BLOCK];
+    int32_t* spill;
+    int64_t stride, col;
+    int sp, lo;
+
+    __device__ __forceinline__ void push(int32_t x, int tid, uint32_t* status) {
+        if (sp - lo == STACK) {
+            // the tree depth bound keeps lo < kMaxDepth; the check only
+            // guards against a malformed tree
+            if (lo < kMaxDepth) spill[(int64_t)lo * stride + col] = lds[lo & (STACK - 1)][tid];
+            else atomicOr(status, kStInternal);
+            ++lo;
+        }
+        lds[sp & (STACK - 1)][tid] = x;
+        ++sp;
+    }
+    __device__ __forceinline__ int32_t pop(int tid) {
+        if (sp == 0) return kEmpty;
+        --sp;
+        if (sp < lo) {
+            lo = sp;
+            return lo < kMaxDepth ? spill[(int64_t)lo * stride + col] : kEmpty;
+        }
+        return lds[sp & (STACK - 1)][tid];
+    }
+};
+
+// One traversal step of a lane: an internal node (test both child boxes, go to
+// the nearer hit, push the other) or a leaf (triangle test), then pop when the
+// lane has nowhere to go.  Returns the next node (kEmpty: the ray is done).
 template <int BLOCK, int STACK, bool COUNT>
-__global__ __launch_bounds__(BLOCK) void traverse_kernel(TravArgs a) {
+__device__ __forceinline__ int32_t trav_step(const TravArgs& a, int32_t node, const RayT& R,
+                                             Best& best, LaneStack<BLOCK, STACK>& st, int tid,
+                                             float inv_w, float w, unsigned long long& c_box,
+                                             unsigned long long& c_tri) {
+    if (node >= 0) {
+        const BvhNode* nd = a.nodes + node;
+        float4 na = nd->a, nb = nd->b, nc = nd->c;
+        int4 ref = nd->ref;
+        float mL, mR;
+        bool hL = box_test(R, f3(na.x, na.y, na.z), f3(na.w, nb.x, nb.y), best.bound, &mL);
+        bool hR = box_test(R, f3(nb.z, nb.w, nc.x), f3(nc.y, nc.z, nc.w), best.bound, &mR);
+        if (COUNT) c_box += 2;
+        int32_t next = kEmpty;
+        if (hL && hR) {
+            bool rfirst = mR < mL;
+            next = rfirst ? ref.y : ref.x;
+            st.push(rfirst ? ref.x : ref.y, tid, a.status);
+        } else if (hL) {
+            next = ref.x;
+        } else if (hR) {
+            next = ref.y;
+        }
+        node = next;
+    } else {
+        const Leaf L = a.leaves[~node];
+        tri_test(R, L, a.max_dist, inv_w, w, &best);
+        if (COUNT) c_tri += 1;
+        node = kEmpty;
+    }
+    if (node == kEmpty) node = st.pop(tid);
+    return node;
+}
+
+__device__ __forceinline__ void reset_best(Best& b, float max_dist) {
+    b.key = 0xFFFFFFFFu;
+    b.id = INT32_MAX;
+    b.t = b.b1 = b.b2 = 0.f;
+    b.bound = max_dist * (1.0f + kPad);
+}
+
+// Wave batches: each wave takes 64 consecutive rays, traces them together and
+// encodes once all 64 are done.
+template <int BLOCK, int STACK, bool COUNT>
+__global__ __launch_bounds__(BLOCK) void traverse_batch_kernel(TravArgs a) {
     __shared__ int32_t stk[STACK][BLOCK];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int64_t gtid = (int64_t)blockIdx.x * BLOCK + tid;
     const uint32_t nrays = *a.nrays;
+    const float w = a.max_dist / kQuantScale;  // exact: power-of-two scaling
+    const float inv_w = kQuantScale / a.max_dist;
+    LaneStack<BLOCK, STACK> st;
+    st.lds = stk;
+    st.spill = a.spill;
+    st.stride = a.spill_lanes;
+    st.col = (int64_t)blockIdx.x * BLOCK + tid;
+    unsigned long long c_box = 0, c_tri = 0;
+    for (;;) {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(a.queue, 64u);
+        base = __shfl(base, 0, 64);
+        if (base >= nrays) break;
+        const uint32_t k = base + lane;
+        RaySetup rs;
+        rs.rel = false;
+        int32_t node = kEmpty;
+        Best best;
+        reset_best(best, a.max_dist);
+        RayT R;
+        if (k < nrays) {
+            rs = setup_ray(a, a.rays[k]);
+            if (rs.rel) {
+                R = make_rayt(rs.p, rs.d);
+                node = a.root;
+            }
+        }
+        st.sp = st.lo = 0;
+        int32_t steps = 0;
+        while (__ballot(node != kEmpty)) {
+            if (node != kEmpty) {
+                node = trav_step<BLOCK, STACK, COUNT>(a, node, R, best, st, tid, inv_w, w, c_box, c_tri);
+                if (++steps > a.step_cap) {
+                    atomicOr(a.status, kStInternal);
+                    node = kEmpty;
+                }
+            }
+        }
+        if (k < nrays) finish_ray(a, k, rs, best);
+    }
+    if (COUNT) {
+        atomicAdd(a.n_box, c_box);
+        atomicAdd(a.n_tri, c_tri);
+    }
+}
 
+// Lane refill: idle lanes take new rays from the queue when at least 16 of
+// the wave are idle; the rest keep traversing.
+template <int BLOCK, int STACK, bool COUNT>
+__global__ __launch_bounds__(BLOCK) void traverse_refill_kernel(TravArgs a) {
+    __shared__ int32_t stk[STACK][BLOCK];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const uint32_t nrays = *a.nrays;
+    const float w = a.max_dist / kQuantScale;
+    const float inv_w = kQuantScale / a.max_dist;
+    LaneStack<BLOCK, STACK> st;
+    st.lds = stk;
+    st.spill = a.spill;
+    st.stride = a.spill_lanes;
+    st.col = (int64_t)blockIdx.x * BLOCK + tid;
+    st.sp = st.lo = 0;
     bool active = false, exhausted = false;
     uint32_t ridx = 0;
-    int32_t texel = 0, face = 0;
+    RaySetup rs;
+    rs.rel = false;
     RayT R;
-    float3 d = f3(0.f, 0.f, 1.f), Tp = f3(1.f, 0.f, 0.f);
-    float hsign = 1.f;
-    const float w = a.max_dist / kQuantScale;   // exact: power-of-two scaling
-    const float inv_w = kQuantScale / a.max_dist;
     Best best;
-    best.key = 0xFFFFFFFFu; best.id = INT32_MAX; best.t = best.b1 = best.b2 = 0.f;
-    best.bound = a.max_dist;
+    reset_best(best, a.max_dist);
     int32_t node = kEmpty;
-    int sp = 0, lo = 0;
-    int64_t steps = 0;
+    int32_t steps = 0;
     unsigned long long c_box = 0, c_tri = 0;
-
-    while (true) {
-        // ---- refill idle lanes from the work queue -------------------------
+    for (;;) {
         uint64_t idle = __ballot(!active);
-        if (!exhausted && (int)__popcll(idle) >= a.refill_min) {
+        if (!exhausted && (int)__popcll(idle) >= 16) {
             int cnt = (int)__popcll(idle);
             int leader = __ffsll((long long)idle) - 1;
             uint32_t base = 0;
@@ -226,55 +452,14 @@ __global__ __launch_bounds__(BLOCK) void traverse_kernel(TravArgs a) {
                 uint32_t k = base + (uint32_t)__popcll(idle & __lanemask_lt());
                 if (k < nrays) {
                     ridx = k;
-                    Ray ray = a.rays[k];
-                    texel = ray.texel;
-                    face = ray.face;
-                    float b1 = ray.b1, b2 = ray.b2, b0 = 1.0f - b1 - b2;
-                    int32_t i0 = a.lo_F[3 * face], i1 = a.lo_F[3 * face + 1], i2 = a.lo_F[3 * face + 2];
-                    float3 V0 = ld3(a.lo_V, i0), V1 = ld3(a.lo_V, i1), V2 = ld3(a.lo_V, i2);
-                    float4 n0 = a.lo_n[i0], n1 = a.lo_n[i1], n2 = a.lo_n[i2];
-                    float3 p = f3(b0 * V0.x + b1 * V1.x + b2 * V2.x, b0 * V0.y + b1 * V1.y + b2 * V2.y,
-                                  b0 * V0.z + b1 * V1.z + b2 * V2.z);
-                    float3 m = f3(b0 * n0.x + b1 * n1.x + b2 * n2.x, b0 * n0.y + b1 * n1.y + b2 * n2.y,
-                                  b0 * n0.z + b1 * n1.z + b2 * n2.z);
-                    float4 T4 = a.face_t[face];
-                    uint32_t fl = (uint32_t)a.face_uv[2 * face + 1].z;
-                    bool rel = (fl & kFaceReliable) && n0.w != 0.f && n1.w != 0.f && n2.w != 0.f;
-                    float l2 = dot3(m, m);
-                    rel = rel && l2 > 0.f;
-                    float rl = rel ? 1.0f / sqrtf(l2) : 0.f;
-                    d = f3(m.x * rl, m.y * rl, m.z * rl);
-                    float3 T = f3(T4.x, T4.y, T4.z);
-                    float dt = dot3(d, T);
-                    Tp = f3(T.x - dt * d.x, T.y - dt * d.y, T.z - dt * d.z);
-                    float lt2 = dot3(Tp, Tp);
-                    rel = rel && lt2 > 0.f;
-                    hsign = T4.w;
-                    if (rel) {
-                        float rt = 1.0f / sqrtf(lt2);
-                        Tp = f3(Tp.x * rt, Tp.y * rt, Tp.z * rt);
-                        R = make_rayt(p, d);
-                        best.key = 0xFFFFFFFFu;
-                        best.id = INT32_MAX;
-                        best.t = best.b1 = best.b2 = 0.f;
-                        best.bound = a.max_dist * (1.0f + kPad);
-                        node = a.root;
-                        sp = lo = 0;
-                        steps = 0;
-                        active = node != kEmpty;
-                    }
-                    if (!active) {
-                        // unreliable (or nothing to hit): finish right away
-                        int32_t st = rel ? kMiss : kUnreliable;
-                        a.out_map[3 * (int64_t)texel] = 0.f;
-                        a.out_map[3 * (int64_t)texel + 1] = 0.f;
-                        a.out_map[3 * (int64_t)texel + 2] = 1.f;
-                        a.out_hit[texel] = st;
-                        if (a.hits) {
-                            Hit h; h.t = 0.f; h.beta1 = 0.f; h.beta2 = 0.f; h.id = st;
-                            a.hits[k] = h;
-                        }
-                    }
+                    rs = setup_ray(a, a.rays[k]);
+                    reset_best(best, a.max_dist);
+                    node = rs.rel ? a.root : kEmpty;
+                    st.sp = st.lo = 0;
+                    steps = 0;
+                    if (rs.rel) R = make_rayt(rs.p, rs.d);
+                    active = node != kEmpty;
+                    if (!active) finish_ray(a, k, rs, best);
                 }
             }
         }
@@ -283,109 +468,14 @@ __global__ __launch_bounds__(BLOCK) void traverse_kernel(TravArgs a) {
             continue;
         }
         if (!active) continue;
-
-        // ---- one traversal step -------------------------------------------
-        if (node >= 0) {
-            const BvhNode* nd = a.nodes + node;
-            float4 na = nd->a, nb = nd->b, nc = nd->c;
-            int4 ref = nd->ref;
-            float mL, mR;
-            bool hL = box_test(R, f3(na.x, na.y, na.z), f3(na.w, nb.x, nb.y), best.bound, &mL);
-            bool hR = box_test(R, f3(nb.z, nb.w, nc.x), f3(nc.y, nc.z, nc.w), best.bound, &mR);
-            if (COUNT) c_box += 2;
-            int32_t next = kEmpty, other = kEmpty;
-            if (hL && hR) {
-                bool rfirst = mR < mL;
-                next = rfirst ? ref.y : ref.x;
-                other = rfirst ? ref.x : ref.y;
-            } else if (hL) {
-                next = ref.x;
-            } else if (hR) {
-                next = ref.y;
-            }
-            if (other != kEmpty) {
-                // push: spill the oldest LDS entry when the LDS part is full.
-                // The tree depth bound keeps lo < kMaxDepth; the check only
-                // guards against a malformed tree.
-                if (sp - lo == STACK) {
-                    if (lo < kMaxDepth) {
-                        a.spill[(int64_t)lo * a.spill_lanes + gtid] = stk[lo & (STACK - 1)][tid];
-                    } else {
-                        atomicOr(a.status, kStInternal);
-                    }
-                    ++lo;
-                }
-                stk[sp & (STACK - 1)][tid] = other;
-                ++sp;
-            }
-            node = next;
-        } else {
-            const Leaf L = a.leaves[~node];
-            tri_test(R, L, a.max_dist, inv_w, w, &best);
-            if (COUNT) c_tri += 1;
-            node = kEmpty;
-        }
+        node = trav_step<BLOCK, STACK, COUNT>(a, node, R, best, st, tid, inv_w, w, c_box, c_tri);
         if (++steps > a.step_cap) {
             atomicOr(a.status, kStInternal);
             node = kEmpty;
-            sp = lo = 0;
-        }
-        if (node == kEmpty) {
-            // pop
-            if (sp > 0) {
-                if (sp == lo) {
-                    --lo;
-                    node = lo < kMaxDepth ? a.spill[(int64_t)lo * a.spill_lanes + gtid] : kEmpty;
-                } else {
-                    node = stk[(sp - 1) & (STACK - 1)][tid];
-                }
-                --sp;
-            }
         }
         if (node != kEmpty) continue;
-
-        // ---- finished: interpolate the hi normal and encode -----------------
         active = false;
-        float3 out = f3(0.f, 0.f, 1.f);
-        int32_t st = kMiss;
-        float beta1 = 0.f, beta2 = 0.f;
-        if (best.id != INT32_MAX) {
-            int32_t g = best.id;
-            int32_t j0 = a.hi_F[3 * (int64_t)g], j1 = a.hi_F[3 * (int64_t)g + 1],
-                    j2 = a.hi_F[3 * (int64_t)g + 2];
-            bool ok = j0 >= 0 && j1 >= 0 && j2 >= 0 && j0 < a.nhv && j1 < a.nhv && j2 < a.nhv;
-            beta1 = best.b1;
-            beta2 = best.b2;
-            float beta0 = 1.0f - beta1 - beta2;
-            st = kUnreliable;
-            if (ok) {
-                float3 N0 = ld3(a.hi_N, j0), N1 = ld3(a.hi_N, j1), N2 = ld3(a.hi_N, j2);
-                float3 h = f3(beta0 * N0.x + beta1 * N1.x + beta2 * N2.x,
-                              beta0 * N0.y + beta1 * N1.y + beta2 * N2.y,
-                              beta0 * N0.z + beta1 * N1.z + beta2 * N2.z);
-                float lh2 = dot3(h, h);
-                if (lh2 > 0.f && isfinite(lh2)) {
-                    float rh = 1.0f / sqrtf(lh2);
-                    float3 n = f3(h.x * rh, h.y * rh, h.z * rh);
-                    float3 c = cross3(d, Tp);
-                    float3 Bp = f3(hsign * c.x, hsign * c.y, hsign * c.z);
-                    out = f3(dot3(n, Tp), dot3(n, Bp), dot3(n, d));
-                    st = g;
-                }
-            }
-        }
-        a.out_map[3 * (int64_t)texel] = out.x;
-        a.out_map[3 * (int64_t)texel + 1] = out.y;
-        a.out_map[3 * (int64_t)texel + 2] = out.z;
-        a.out_hit[texel] = st;
-        if (a.hits) {
-            Hit h;
-            h.t = best.t;
-            h.beta1 = beta1;
-            h.beta2 = beta2;
-            h.id = st;
-            a.hits[ridx] = h;
-        }
+        finish_ray(a, ridx, rs, best);
     }
     if (COUNT) {
         atomicAdd(a.n_box, c_box);
@@ -393,16 +483,17 @@ __global__ __launch_bounds__(BLOCK) void traverse_kernel(TravArgs a) {
     }
 }
 
-template <int BLOCK, int STACK, bool COUNT>
+template <int BLOCK, int STACK, bool COUNT, bool REFILL>
 hipError_t launch_one(const TravArgs& args, hipStream_t s, int64_t max_lanes) {
     static int cached_blocks = -1;
+    auto kern = REFILL ? traverse_refill_kernel<BLOCK, STACK, COUNT> : traverse_batch_kernel<BLOCK, STACK, COUNT>;
     if (cached_blocks < 0) {
         int dev = 0, cus = 0, per = 0;
         hipError_t e = hipGetDevice(&dev);
         if (e != hipSuccess) return e;
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) return e;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, traverse_kernel<BLOCK, STACK, COUNT>, BLOCK, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, BLOCK, 0);
         if (e != hipSuccess) return e;
         if (per < 1) per = 1;
         cached_blocks = cus * per;
@@ -411,7 +502,7 @@ hipError_t launch_one(const TravArgs& args, hipStream_t s, int64_t max_lanes) {
     int64_t cap = max_lanes / BLOCK;
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL((traverse_kernel<BLOCK, STACK, COUNT>), dim3((unsigned)blocks), dim3(BLOCK), 0, s, args);
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(BLOCK), 0, s, args);
     return hipGetLastError();
 }
 
@@ -446,15 +537,19 @@ hipError_t launch_traverse(const float* lo_V, const int32_t* lo_F, int64_t nlf, 
     a.hits = save ? (Hit*)(ws + L.hits) : nullptr;
     a.spill = (int32_t*)(ws + L.spill);
     a.spill_lanes = L.spill_lanes;
-    a.refill_min = cfg.persist ? 16 : 64;
     a.status = (uint32_t*)(ws + L.status);
-    a.step_cap = 4 * nhf + 1024;
+    a.step_cap = (int32_t)std::min<int64_t>(4 * nhf + 1024, INT32_MAX);
     a.n_box = (unsigned long long*)(counters + kCntBoxLo);
     a.n_tri = (unsigned long long*)(counters + kCntTriLo);
     int64_t lanes = L.spill_lanes;
-    if (cfg.count) return launch_one<256, 16, true>(a, s, lanes);
-#define BAKE_TRAV_CASE(B, S) \
-    if (cfg.block == B && cfg.stack == S) return launch_one<B, S, false>(a, s, lanes);
+    if (cfg.count) {
+        return cfg.persist ? launch_one<256, 16, true, true>(a, s, lanes)
+                           : launch_one<256, 16, true, false>(a, s, lanes);
+    }
+#define BAKE_TRAV_CASE(B, S)                                                         \
+    if (cfg.block == B && cfg.stack == S)                                            \
+        return cfg.persist ? launch_one<B, S, false, true>(a, s, lanes)              \
+                           : launch_one<B, S, false, false>(a, s, lanes);
     BAKE_TRAV_CASE(64, 8) BAKE_TRAV_CASE(64, 16) BAKE_TRAV_CASE(64, 32)
     BAKE_TRAV_CASE(128, 8) BAKE_TRAV_CASE(128, 16) BAKE_TRAV_CASE(128, 32)
     BAKE_TRAV_CASE(256, 8) BAKE_TRAV_CASE(256, 16) BAKE_TRAV_CASE(256, 32)

@@ -103,6 +103,52 @@ __global__ __launch_bounds__(kScanBlock) void scan_down_kernel(const uint32_t* i
     }
 }
 
+// Single workgroup of 1024 threads for small arrays: tiles of 8192 values,
+// each thread owning 8 consecutive ones, scanned through wave shuffles and
+// LDS, with a running carry between tiles.
+constexpr int kSmallBlock = 1024;
+constexpr int kSmallItems = 8;
+__global__ __launch_bounds__(kSmallBlock) void scan_small_kernel(const uint32_t* in, uint32_t* out,
+                                                                 int64_t n, uint32_t* total) {
+    __shared__ uint32_t lw[kSmallBlock / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t carry = 0;
+    for (int64_t tile = 0; tile < n; tile += (int64_t)kSmallBlock * kSmallItems) {
+        const int64_t b = tile + (int64_t)threadIdx.x * kSmallItems;
+        uint32_t v[kSmallItems];
+        uint32_t acc = 0;
+#pragma unroll
+        for (int k = 0; k < kSmallItems; ++k) {
+            v[k] = b + k < n ? in[b + k] : 0u;
+            acc += v[k];
+        }
+        uint32_t x = acc;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) lw[wave] = x;
+        __syncthreads();
+        uint32_t base = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < kSmallBlock / 64; ++w) {
+            uint32_t t = lw[w];
+            if (w < wave) base += t;
+            tot += t;
+        }
+        __syncthreads();
+        uint32_t run = carry + base + x - acc;
+#pragma unroll
+        for (int k = 0; k < kSmallItems; ++k) {
+            if (b + k < n) out[b + k] = run;
+            run += v[k];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
 int grid_for(int64_t n, int block) {
     int64_t g = (n + block - 1) / block;
     if (g < 1) g = 1;
@@ -131,6 +177,10 @@ hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint
     if (n <= 0) {
         if (total) return fill_u32(total, 0, 1, s);
         return hipSuccess;
+    }
+    if (n <= (int64_t)kSmallBlock * kSmallItems * 16) {
+        hipLaunchKernelGGL(scan_small_kernel, dim3(1), dim3(kSmallBlock), 0, s, in, out, n, total);
+        return hipGetLastError();
     }
     int64_t nb = (n + kScanTile - 1) / kScanTile;
     hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, n, tmp);
