@@ -237,3 +237,48 @@ def rgb8(map_flat):
     """RGB8 encoding c = clamp(floor((x + 1) * 127.5 + 0.5), 0, 255)."""
     c = np.floor((np.asarray(map_flat, np.float64) + 1.0) * 127.5 + 0.5)
     return np.clip(c, 0, 255).astype(np.uint8)
+
+
+def _frozen_args(asset, face, bary, g, hf):
+    return (_c(asset.lo_V, np.float32), _c(asset.lo_F, np.int32), _c(asset.lo_UV, np.float32),
+            _c(asset.hi_V, np.float32), _c(asset.hi_F, np.int32), _c(asset.hi_N, np.float32),
+            _c(face, np.int32), _c(bary, np.float64), _c(g, np.int32), _c(hf, np.int8))
+
+
+def frozen_forward(asset, face, bary, g, hf):
+    """Per-ray output with the texel's lo face and barycentrics, the hit
+    triangle g and the handedness held fixed: (out [n,3], (t, beta1, beta2) [n,3])."""
+    loV, loF, UV, hiV, hiF, hiN, face, bary, g, hf = _frozen_args(asset, face, bary, g, hf)
+    n = face.shape[0]
+    out = np.zeros((n, 3)); tb = np.zeros((n, 3))
+    _call("orc_frozen_forward", _p(loV), C.c_int64(loV.shape[0]), _p(loF), C.c_int64(loF.shape[0]),
+          _p(UV), C.c_int32(asset.res), _p(hiV), _p(hiF), _p(hiN), C.c_int64(n), _p(face), _p(bary),
+          _p(g), _p(hf), _p(out), _p(tb))
+    return out, tb
+
+
+def adjoint(asset, face, bary, g, hf, grad_out):
+    """FP64 reverse mode of frozen_forward: given d(loss)/d(out) per ray,
+    returns (d loss / d lo_V [Vl,3], d loss / d hi_N [Vh,3])."""
+    loV, loF, UV, hiV, hiF, hiN, face, bary, g, hf = _frozen_args(asset, face, bary, g, hf)
+    go = _c(grad_out, np.float64)
+    glo = np.zeros((loV.shape[0], 3)); ghi = np.zeros((hiV.shape[0], 3))
+    _call("orc_adjoint", _p(loV), C.c_int64(loV.shape[0]), _p(loF), C.c_int64(loF.shape[0]), _p(UV),
+          C.c_int32(asset.res), _p(hiV), C.c_int64(hiV.shape[0]), _p(hiF), _p(hiN),
+          C.c_int64(face.shape[0]), _p(face), _p(bary), _p(g), _p(hf), _p(go), _p(glo), _p(ghi))
+    return glo, ghi
+
+
+def bake_adjoint(asset, ob, grad_map):
+    """Adjoint of a whole bake's pre-dilation map: the hit texels of the oracle
+    bake `ob` carry grad_map [res*res,3]; misses, unreliable and uncovered
+    texels are constant and carry none."""
+    hit = ob.hit >= 0
+    st = ob.status[ob.texels]
+    hit &= st >= 0
+    tex = ob.texels[hit]
+    face = ob.face[tex]
+    _, ok = lo_normals(asset.lo_V, asset.lo_F)
+    _, _, hf, _ = face_frames(asset.lo_V, asset.lo_F, asset.lo_UV, asset.res, ok)
+    gm = np.asarray(grad_map, np.float64).reshape(-1, 3)[tex]
+    return adjoint(asset, face, ob.bary[tex], ob.hit[hit], hf[face], gm)

@@ -608,3 +608,185 @@ int orc_plane_check(const float *V, const int32_t *F, int64_t n, const double *P
     }
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Frozen-selection forward and its adjoint (backward of a map loss)         */
+/* ------------------------------------------------------------------------ */
+/*
+ * With the texel -> low-poly face assignment, its barycentrics b, the hit
+ * triangle g and the handedness h_f held fixed, each texel's output is a
+ * smooth function of the low-poly positions lo_V (through p, the vertex
+ * normals and T_f) and of the three high-poly normals of g:
+ *   n_v = s_v/|s_v|, s_v = sum_{faces at v} (V1-V0) x (V2-V0)
+ *   p = sum b_k V_k,  m = sum b_k n_k,  d = m/|m|
+ *   p + t d = A + beta1 (B-A) + beta2 (C-A)      (crossing of g's plane)
+ *   h = beta0 N0 + beta1 N1 + beta2 N2,  n = h/|h|
+ *   T~ = T_f - (d.T_f) d, T' = T~/|T~|, B' = h_f (d x T')
+ *   out = (n.T', n.B', n.d)
+ * The adjoint walks the same chain backwards, in FP64, summing in ray order.
+ */
+
+static void lo_vertex_sums(const float *V, int64_t nv, const int32_t *F, int64_t nf, double *s) {
+    for (int64_t i = 0; i < 3 * nv; ++i) s[i] = 0;
+    for (int64_t f = 0; f < nf; ++f) {
+        v3 A = ld3f(V, F[3 * f]), B = ld3f(V, F[3 * f + 1]), C = ld3f(V, F[3 * f + 2]);
+        v3 c = cross(sub(B, A), sub(C, A));
+        for (int k = 0; k < 3; ++k) st3d(s, F[3 * f + k], add(ld3d(s, F[3 * f + k]), c));
+    }
+}
+
+/* T_f from the snapped UV deltas (same definition as orc_face_frames). */
+static v3 face_tangent(const float *V, const int32_t *F, const float *UV, int32_t res, int64_t f,
+                       double *c1, double *c2) {
+    int64_t X[3], Y[3];
+    for (int k = 0; k < 3; ++k) snap(UV, f, k, res, &X[k], &Y[k]);
+    int64_t du1 = X[1] - X[0], dv1 = Y[1] - Y[0], du2 = X[2] - X[0], dv2 = Y[2] - Y[0];
+    int64_t det = du1 * dv2 - du2 * dv1;
+    double sg = det > 0 ? 1.0 : (det < 0 ? -1.0 : 0.0);
+    /* T_f = c1 e1 + c2 e2 */
+    *c1 = sg * (double)dv2;
+    *c2 = -sg * (double)dv1;
+    v3 A = ld3f(V, F[3 * f]), B = ld3f(V, F[3 * f + 1]), C = ld3f(V, F[3 * f + 2]);
+    return add(scl(sub(B, A), *c1), scl(sub(C, A), *c2));
+}
+
+/* Solve [a | b | c] x = r by Cramer's rule. */
+static v3 solve3(v3 a, v3 b, v3 c, v3 r) {
+    double D = dot(a, cross(b, c));
+    return mk(dot(r, cross(b, c)) / D, dot(a, cross(r, c)) / D, dot(a, cross(b, r)) / D);
+}
+
+/* Per-ray forward state shared by the frozen forward and the adjoint. */
+typedef struct {
+    v3 p, m, d, Tf, Tt, Tp, Bp, h, n;
+    double lm, lt, lh, t, b1, b2, c1, c2;
+    v3 A, e1, e2, N[3];
+    int32_t lv[3], hv[3];
+} rstate;
+
+static void ray_forward(const float *loV, const int32_t *loF, const double *nrm, const float *UV,
+                        int32_t res, const float *hiV, const int32_t *hiF, const float *hiN,
+                        int32_t face, const double *bary, int32_t g, int8_t hf, rstate *S) {
+    for (int k = 0; k < 3; ++k) { S->lv[k] = loF[3 * face + k]; S->hv[k] = hiF[3 * g + k]; }
+    S->p = mk(0, 0, 0); S->m = mk(0, 0, 0);
+    for (int k = 0; k < 3; ++k) {
+        S->p = add(S->p, scl(ld3f(loV, S->lv[k]), bary[k]));
+        S->m = add(S->m, scl(ld3d(nrm, S->lv[k]), bary[k]));
+    }
+    S->lm = norm(S->m);
+    S->d = scl(S->m, 1.0 / S->lm);
+    S->A = ld3f(hiV, S->hv[0]);
+    S->e1 = sub(ld3f(hiV, S->hv[1]), S->A);
+    S->e2 = sub(ld3f(hiV, S->hv[2]), S->A);
+    v3 x = solve3(scl(S->d, -1.0), S->e1, S->e2, sub(S->p, S->A));
+    S->t = x.x; S->b1 = x.y; S->b2 = x.z;
+    double b0 = 1.0 - S->b1 - S->b2;
+    for (int k = 0; k < 3; ++k) S->N[k] = ld3f(hiN, S->hv[k]);
+    S->h = add(add(scl(S->N[0], b0), scl(S->N[1], S->b1)), scl(S->N[2], S->b2));
+    S->lh = norm(S->h);
+    S->n = scl(S->h, 1.0 / S->lh);
+    S->Tf = face_tangent(loV, loF, UV, res, face, &S->c1, &S->c2);
+    S->Tt = sub(S->Tf, scl(S->d, dot(S->d, S->Tf)));
+    S->lt = norm(S->Tt);
+    S->Tp = scl(S->Tt, 1.0 / S->lt);
+    S->Bp = scl(cross(S->d, S->Tp), (double)hf);
+}
+
+int orc_frozen_forward(const float *loV, int64_t nlv, const int32_t *loF, int64_t nlf, const float *UV,
+                       int32_t res, const float *hiV, const int32_t *hiF, const float *hiN, int64_t n,
+                       const int32_t *face, const double *bary, const int32_t *g, const int8_t *hf,
+                       double *out, double *tb_out) {
+    double *s = (double *)malloc(sizeof(double) * (size_t)(3 * (nlv > 0 ? nlv : 1)));
+    double *nrm = (double *)malloc(sizeof(double) * (size_t)(3 * (nlv > 0 ? nlv : 1)));
+    lo_vertex_sums(loV, nlv, loF, nlf, s);
+    for (int64_t v = 0; v < nlv; ++v) st3d(nrm, v, scl(ld3d(s, v), 1.0 / norm(ld3d(s, v))));
+    for (int64_t r = 0; r < n; ++r) {
+        rstate S;
+        ray_forward(loV, loF, nrm, UV, res, hiV, hiF, hiN, face[r], bary + 3 * r, g[r], hf[r], &S);
+        st3d(out, r, mk(dot(S.n, S.Tp), dot(S.n, S.Bp), dot(S.n, S.d)));
+        if (tb_out) { tb_out[3 * r] = S.t; tb_out[3 * r + 1] = S.b1; tb_out[3 * r + 2] = S.b2; }
+    }
+    free(nrm);
+    free(s);
+    return ORC_OK;
+}
+
+int orc_adjoint(const float *loV, int64_t nlv, const int32_t *loF, int64_t nlf, const float *UV,
+                int32_t res, const float *hiV, int64_t nhv, const int32_t *hiF, const float *hiN, int64_t n,
+                const int32_t *face, const double *bary, const int32_t *g, const int8_t *hf,
+                const double *gout, double *gloV, double *ghiN) {
+    double *s = (double *)malloc(sizeof(double) * (size_t)(3 * (nlv > 0 ? nlv : 1)));
+    double *nrm = (double *)malloc(sizeof(double) * (size_t)(3 * (nlv > 0 ? nlv : 1)));
+    double *nbar = (double *)calloc((size_t)(3 * (nlv > 0 ? nlv : 1)), sizeof(double));
+    lo_vertex_sums(loV, nlv, loF, nlf, s);
+    for (int64_t v = 0; v < nlv; ++v) st3d(nrm, v, scl(ld3d(s, v), 1.0 / norm(ld3d(s, v))));
+    for (int64_t i = 0; i < 3 * nlv; ++i) gloV[i] = 0;
+    for (int64_t i = 0; i < 3 * nhv; ++i) ghiN[i] = 0;
+    for (int64_t r = 0; r < n; ++r) {
+        rstate S;
+        ray_forward(loV, loF, nrm, UV, res, hiV, hiF, hiN, face[r], bary + 3 * r, g[r], hf[r], &S);
+        v3 o = ld3d(gout, r);
+        double H = (double)hf[r];
+        /* out = (n.T', n.B', n.d), B' = H (d x T') */
+        v3 nb = add(add(scl(S.Tp, o.x), scl(S.Bp, o.y)), scl(S.d, o.z));
+        v3 Tpb = add(scl(S.n, o.x), scl(cross(S.n, S.d), o.y * H));
+        v3 db = add(scl(S.n, o.z), scl(cross(S.Tp, S.n), o.y * H));
+        /* T' = T~/|T~| */
+        v3 Ttb = scl(sub(Tpb, scl(S.Tp, dot(Tpb, S.Tp))), 1.0 / S.lt);
+        /* T~ = T_f - (d.T_f) d */
+        v3 Tfb = sub(Ttb, scl(S.d, dot(S.d, Ttb)));
+        db = sub(db, add(scl(Ttb, dot(S.d, S.Tf)), scl(S.Tf, dot(S.d, Ttb))));
+        /* n = h/|h| */
+        v3 hb = scl(sub(nb, scl(S.n, dot(nb, S.n))), 1.0 / S.lh);
+        double beta[3] = {1.0 - S.b1 - S.b2, S.b1, S.b2};
+        for (int k = 0; k < 3; ++k) st3d(ghiN, S.hv[k], add(ld3d(ghiN, S.hv[k]), scl(hb, beta[k])));
+        double b1b = dot(hb, sub(S.N[1], S.N[0])), b2b = dot(hb, sub(S.N[2], S.N[0]));
+        /* [-d | e1 | e2] (t, b1, b2) = p - A: w = M^-T (0, b1b, b2b) */
+        v3 md = scl(S.d, -1.0);
+        /* M^T w = xbar: rows of M^T are -d, e1, e2 */
+        v3 w;
+        {
+            /* solve M^T w = xb with M^T = [md; e1; e2] (rows) */
+            v3 r0 = md, r1 = S.e1, r2 = S.e2;
+            /* columns of M^T are (r0.x, r1.x, r2.x) etc.; Cramer on the transposed system */
+            v3 c0 = mk(r0.x, r1.x, r2.x), c1 = mk(r0.y, r1.y, r2.y), c2 = mk(r0.z, r1.z, r2.z);
+            w = solve3(c0, c1, c2, mk(0.0, b1b, b2b));
+        }
+        v3 pb = w;
+        db = add(db, scl(w, S.t));
+        /* d = m/|m| */
+        v3 mb = scl(sub(db, scl(S.d, dot(db, S.d))), 1.0 / S.lm);
+        const double *bk = bary + 3 * r;
+        for (int k = 0; k < 3; ++k) {
+            int32_t v = S.lv[k];
+            st3d(gloV, v, add(ld3d(gloV, v), scl(pb, bk[k])));
+            st3d(nbar, v, add(ld3d(nbar, v), scl(mb, bk[k])));
+        }
+        /* T_f = c1 (V1 - V0) + c2 (V2 - V0) */
+        v3 e1b = scl(Tfb, S.c1), e2b = scl(Tfb, S.c2);
+        st3d(gloV, S.lv[1], add(ld3d(gloV, S.lv[1]), e1b));
+        st3d(gloV, S.lv[2], add(ld3d(gloV, S.lv[2]), e2b));
+        st3d(gloV, S.lv[0], sub(ld3d(gloV, S.lv[0]), add(e1b, e2b)));
+    }
+    /* n_v = s_v/|s_v|, s_v = sum of face cross products */
+    double *sb = (double *)calloc((size_t)(3 * (nlv > 0 ? nlv : 1)), sizeof(double));
+    for (int64_t v = 0; v < nlv; ++v) {
+        v3 nv = ld3d(nrm, v), nbv = ld3d(nbar, v);
+        st3d(sb, v, scl(sub(nbv, scl(nv, dot(nbv, nv))), 1.0 / norm(ld3d(s, v))));
+    }
+    for (int64_t f = 0; f < nlf; ++f) {
+        int32_t a = loF[3 * f], b = loF[3 * f + 1], c = loF[3 * f + 2];
+        v3 cb = add(add(ld3d(sb, a), ld3d(sb, b)), ld3d(sb, c));
+        v3 A = ld3f(loV, a), B = ld3f(loV, b), C = ld3f(loV, c);
+        v3 e1 = sub(B, A), e2 = sub(C, A);
+        v3 e1b = cross(e2, cb), e2b = cross(cb, e1);
+        st3d(gloV, b, add(ld3d(gloV, b), e1b));
+        st3d(gloV, c, add(ld3d(gloV, c), e2b));
+        st3d(gloV, a, sub(ld3d(gloV, a), add(e1b, e2b)));
+    }
+    free(sb);
+    free(nbar);
+    free(nrm);
+    free(s);
+    return ORC_OK;
+}
