@@ -122,16 +122,28 @@ int32_t bake_normals(const float *hi_V, int64_t n_hi_v, const int32_t *hi_F, int
 /* Backward of L(out_map before dilation) with the hit selection, the texel ->
  * face assignment and the handedness held fixed: given grad_map = dL/dout_map
  * [res,res,3], writes dL/dlo_V [n_lo_v,3] and dL/dhi_N [n_hi_v,3] (both
- * overwritten, not accumulated).  Needs the workspace of a forward call made
- * with BAKE_FLAG_SAVE on the same inputs, not modified since.  Sums are done in
- * a fixed order (no floating-point atomics): the result is bitwise
- * reproducible.  Either gradient pointer may be NULL to skip it. */
+ * overwritten, not accumulated).  Only texels with a hit carry gradient;
+ * misses, unreliable, uncovered and dilated texels are constants.  (The paper
+ * has no backward pass; this differentiates its bake as defined above.)
+ * Needs the workspace of the last forward call made with BAKE_FLAG_SAVE on the
+ * same inputs on this thread, not modified since (else BAKE_E_STATE); the
+ * workspace size is the one of that forward.  Sums are done in a fixed order
+ * (no floating-point atomics): the result is bitwise reproducible.  Either
+ * gradient pointer may be NULL to skip it. */
 int32_t bake_normals_backward(const float *hi_V, int64_t n_hi_v, const int32_t *hi_F,
                               int64_t n_hi_f, const float *hi_N, const float *lo_V, int64_t n_lo_v,
                               const int32_t *lo_F, int64_t n_lo_f, const float *lo_UV, int32_t res,
                               float max_dist, const float *grad_map, float *grad_lo_V,
                               float *grad_hi_N, void *workspace, size_t workspace_bytes,
                               void *stream);
+
+/* Squared-error map loss, a helper for training-style use of the backward:
+ * loss_out[0] = sum_i (map[i] - target[i])^2 and, if grad_out is not NULL,
+ * grad_out[i] = 2 (map[i] - target[i]), over n floats (n = res*res*3 for a map).
+ * Device pointers; the sum is reduced in a fixed order (deterministic).
+ * scratch: device memory of at least 4 * (ceil(n / 256) + 1) bytes. */
+int32_t bake_sq_loss(const float *map, const float *target, int64_t n, float *grad_out,
+                     float *loss_out, void *scratch, size_t scratch_bytes, void *stream);
 
 /* Synchronises `stream` and returns the OR of BAKE_STATUS_* bits raised by the
  * last bake that used `workspace`. */

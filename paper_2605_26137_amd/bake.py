@@ -74,6 +74,8 @@ _EXPORTS = {
                                           C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                                           C.c_int32, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p,
                                           C.c_void_p, C.c_size_t, C.c_void_p]),
+    "bake_sq_loss": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_size_t, C.c_void_p]),
     "bake_query_status": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_uint32)]),
     "bake_read_counter": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_int64)]),
     "bake_workspace_view": (C.c_int32, [C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_int32,
@@ -230,7 +232,69 @@ def bake_normals(hi_V, hi_F, hi_N, lo_V, lo_F, lo_UV, res: int, max_dist: float,
         _ptr(hi_V), sizes[0], _ptr(hi_F), sizes[1], _ptr(hi_N), _ptr(lo_V), sizes[2], _ptr(lo_F),
         sizes[3], _ptr(lo_UV), int(res), float(max_dist), _ptr(out_map), _ptr(out_hit),
         C.byref(opts), _ptr(workspace), workspace.numel(), _stream_handle(stream)))
-    return BakeResult(out_map, out_hit, rgb, workspace, opts, sizes)
+    r = BakeResult(out_map, out_hit, rgb, workspace, opts, sizes)
+    r.max_dist = float(max_dist)
+    return r
+
+
+def bake_normals_backward(result: BakeResult, inputs, grad_map, need_lo=True, need_hi=True,
+                          stream=None):
+    """Gradients of a loss on the pre-dilation map w.r.t. lo_V and hi_N, for a
+    forward `result` made with save=True on the same `inputs` (the six tensors
+    given to bake_normals, same order).  Returns (grad_lo_V, grad_hi_N); an
+    entry is None when not requested."""
+    hi_V, hi_F, hi_N, lo_V, lo_F, lo_UV = inputs
+    res = result.sizes[4]
+    g = _dev_tensor(grad_map.contiguous(), torch.float32, "grad_map")
+    if tuple(g.shape) != (res, res, 3):
+        raise ValueError(f"grad_map must be [{res},{res},3]")
+    glo = torch.empty_like(lo_V) if need_lo else None
+    ghi = torch.empty_like(hi_N) if need_hi else None
+    _check(lib().bake_normals_backward(
+        _ptr(hi_V), hi_V.shape[0], _ptr(hi_F), hi_F.shape[0], _ptr(hi_N), _ptr(lo_V), lo_V.shape[0],
+        _ptr(lo_F), lo_F.shape[0], _ptr(lo_UV), int(res), float(result.max_dist), _ptr(g), _ptr(glo),
+        _ptr(ghi), _ptr(result.workspace), result.workspace.numel(), _stream_handle(stream)))
+    return glo, ghi
+
+
+def sq_loss(map_, target, want_grad=True, stream=None):
+    """(sum (map - target)^2 as a 1-element tensor, 2 (map - target) or None)."""
+    m = _dev_tensor(map_.contiguous(), torch.float32, "map")
+    t = _dev_tensor(target.contiguous(), torch.float32, "target")
+    if m.shape != t.shape:
+        raise ValueError("map and target shapes differ")
+    n = m.numel()
+    loss = torch.empty(1, dtype=torch.float32, device=m.device)
+    grad = torch.empty_like(m) if want_grad else None
+    scratch = torch.empty(4 * ((n + 255) // 256 + 1), dtype=torch.uint8, device=m.device)
+    _check(lib().bake_sq_loss(_ptr(m), _ptr(t), n, _ptr(grad), _ptr(loss), _ptr(scratch),
+                              scratch.numel(), _stream_handle(stream)))
+    return loss, grad
+
+
+class BakeNormals(torch.autograd.Function):
+    """Differentiable bake: map = BakeNormals.apply(lo_V, hi_N, hi_V, hi_F, lo_F,
+    lo_UV, res, max_dist[, dilate_passes]).  Gradients flow to lo_V and hi_N
+    with the hit selection held fixed; the hit-id map is returned as a second,
+    non-differentiable output.  dilate_passes defaults to 0 so that every
+    differentiable texel is a traced one."""
+
+    @staticmethod
+    def forward(ctx, lo_V, hi_N, hi_V, hi_F, lo_F, lo_UV, res, max_dist, dilate_passes=0):
+        r = bake_normals(hi_V, hi_F, hi_N, lo_V, lo_F, lo_UV, res, max_dist,
+                         dilate_passes=dilate_passes, save=True)
+        r.max_dist = float(max_dist)
+        ctx.result = r
+        ctx.inputs = (hi_V, hi_F, hi_N, lo_V, lo_F, lo_UV)
+        ctx.mark_non_differentiable(r.hit)
+        return r.map, r.hit
+
+    @staticmethod
+    def backward(ctx, grad_map, grad_hit):
+        glo, ghi = bake_normals_backward(ctx.result, ctx.inputs, grad_map,
+                                         need_lo=ctx.needs_input_grad[0],
+                                         need_hi=ctx.needs_input_grad[1])
+        return glo, ghi, None, None, None, None, None, None, None
 
 
 def stage_times() -> dict:

@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "../../include/bake.h"
 #include "internal.h"
@@ -104,6 +105,7 @@ Layout make_layout(int64_t nhv, int64_t nhf, int64_t nlv, int64_t nlf, int32_t r
     L.max_rays = L.n_texels;
     L.sort_blocks = (nhf + 4095) / 4096;
     int64_t scan_n = std::max<int64_t>(std::max<int64_t>(nlv, nlf), 256 * L.sort_blocks);
+    if (flags & BAKE_FLAG_SAVE) scan_n = std::max<int64_t>(scan_n, radix_hist_elems(3 * L.max_rays));
     L.scan_tmp_n = scan_tmp_elems(scan_n) + 1;
     int64_t lanes = std::min<int64_t>(std::max<int64_t>(L.max_rays, 256), kMaxLanes);
     L.spill_lanes = (lanes + 255) / 256 * 256;
@@ -140,8 +142,62 @@ Layout make_layout(int64_t nhv, int64_t nhf, int64_t nlv, int64_t nlf, int32_t r
     L.frontier = take(4 * (size_t)treelet_cap(nhf));
     L.treelets = take(16 * (size_t)treelet_cap(nhf));
     L.spill = take(4 * (size_t)kMaxDepth * (size_t)L.spill_lanes);
+    if (flags & BAKE_FLAG_SAVE) {
+        const size_t items = 3 * (size_t)L.max_rays;
+        L.bwd_ray = take(48 * (size_t)L.max_rays);
+        L.bwd_k0 = take(4 * items);
+        L.bwd_v0 = take(4 * items);
+        L.bwd_k1 = take(4 * items);
+        L.bwd_v1 = take(4 * items);
+        L.bwd_hist = take(4 * (size_t)radix_hist_elems((int64_t)items));
+        L.bwd_face1 = take(72 * (size_t)nlf);
+        L.bwd_face2 = take(36 * (size_t)nlf);
+        L.bwd_sbar = take(12 * (size_t)nlv);
+        L.bwd_vbar = take(12 * (size_t)nlv);
+    }
     L.total = off;
     return L;
+}
+
+// ---- forwards that saved their state (for the backward pass) ---------------
+// Host-side record of the last saved forwards, keyed by workspace, so a
+// backward call can check it matches a saved forward of the same sizes.  It
+// is process-wide (autograd may run the backward on another thread).
+struct Saved {
+    const void* ws;
+    int64_t nhv, nhf, nlv, nlf;
+    int32_t res;
+};
+constexpr int kSavedSlots = 64;
+std::mutex g_saved_mu;
+Saved g_saved[kSavedSlots];
+int g_saved_next = 0;
+
+void remember_saved(const void* ws, int64_t nhv, int64_t nhf, int64_t nlv, int64_t nlf, int32_t res) {
+    std::lock_guard<std::mutex> lk(g_saved_mu);
+    for (int i = 0; i < kSavedSlots; ++i)
+        if (g_saved[i].ws == ws) {
+            g_saved[i] = Saved{ws, nhv, nhf, nlv, nlf, res};
+            return;
+        }
+    g_saved[g_saved_next] = Saved{ws, nhv, nhf, nlv, nlf, res};
+    g_saved_next = (g_saved_next + 1) % kSavedSlots;
+}
+
+void forget_saved(const void* ws) {
+    std::lock_guard<std::mutex> lk(g_saved_mu);
+    for (int i = 0; i < kSavedSlots; ++i)
+        if (g_saved[i].ws == ws) g_saved[i].ws = nullptr;
+}
+
+bool was_saved(const void* ws, int64_t nhv, int64_t nhf, int64_t nlv, int64_t nlf, int32_t res) {
+    std::lock_guard<std::mutex> lk(g_saved_mu);
+    for (int i = 0; i < kSavedSlots; ++i) {
+        const Saved& v = g_saved[i];
+        if (v.ws == ws && ws != nullptr)
+            return v.nhv == nhv && v.nhf == nhf && v.nlv == nlv && v.nlf == nlf && v.res == res;
+    }
+    return false;
 }
 
 // ---- per-thread stage timing ---------------------------------------------
@@ -307,6 +363,8 @@ int32_t bake_normals(const float* hi_V, int64_t n_hi_v, const int32_t* hi_F, int
     if (o.rgb8) HIP_OR_FAIL(launch_rgb8(res, out_map, o.rgb8, s));
     HIP_OR_FAIL(tim_record(tim, 5, s));
     tim_commit(tim);
+    if (o.flags & BAKE_FLAG_SAVE) remember_saved(workspace, n_hi_v, n_hi_f, n_lo_v, n_lo_f, res);
+    else forget_saved(workspace);
     return BAKE_OK;
 }
 
@@ -317,10 +375,31 @@ int32_t bake_normals_backward(const float* hi_V, int64_t n_hi_v, const int32_t* 
                               float* grad_hi_N, void* workspace, size_t workspace_bytes,
                               void* stream) {
     g_err[0] = 0;
-    (void)hi_V; (void)n_hi_v; (void)hi_F; (void)n_hi_f; (void)hi_N; (void)lo_V; (void)n_lo_v;
-    (void)lo_F; (void)n_lo_f; (void)lo_UV; (void)res; (void)max_dist; (void)grad_map;
-    (void)grad_lo_V; (void)grad_hi_N; (void)workspace; (void)workspace_bytes; (void)stream;
-    return fail(BAKE_E_UNSUPPORTED, "backward not built yet");
+    int32_t rc = validate_common(hi_V, n_hi_v, hi_F, n_hi_f, hi_N, lo_V, n_lo_v, lo_F, n_lo_f, lo_UV,
+                                 res, max_dist);
+    if (rc) return rc;
+    if (!grad_map) return fail(BAKE_E_INVALID_ARG, "grad_map is NULL");
+    Layout L = make_layout(n_hi_v, n_hi_f, n_lo_v, n_lo_f, res, BAKE_FLAG_SAVE);
+    if ((rc = check_workspace(workspace, workspace_bytes, L))) return rc;
+    if (!was_saved(workspace, n_hi_v, n_hi_f, n_lo_v, n_lo_f, res))
+        return fail(BAKE_E_STATE,
+                    "no forward bake with BAKE_FLAG_SAVE and these sizes used this workspace");
+    if (!grad_lo_V && !grad_hi_N) return BAKE_OK;
+    HIP_OR_FAIL(launch_backward(hi_V, hi_F, n_hi_v, hi_N, lo_V, lo_F, n_lo_v, n_lo_f, grad_map, grad_lo_V,
+                                grad_hi_N, L, (char*)workspace, (hipStream_t)stream));
+    return BAKE_OK;
+}
+
+int32_t bake_sq_loss(const float* map, const float* target, int64_t n, float* grad_out, float* loss_out,
+                     void* scratch, size_t scratch_bytes, void* stream) {
+    g_err[0] = 0;
+    if (n < 0) return fail(BAKE_E_INVALID_ARG, "negative count");
+    if ((n > 0 && (!map || !target)) || !loss_out) return fail(BAKE_E_INVALID_ARG, "NULL argument");
+    const size_t need = 4 * (size_t)((n + 255) / 256 + 1);
+    if (!scratch || scratch_bytes < need)
+        return fail(BAKE_E_WORKSPACE, "scratch has %zu bytes, needs %zu", scratch_bytes, need);
+    HIP_OR_FAIL(launch_sq_loss(map, target, n, grad_out, loss_out, (float*)scratch, (hipStream_t)stream));
+    return BAKE_OK;
 }
 
 int32_t bake_query_status(const void* workspace, void* stream, uint32_t* status_out) {

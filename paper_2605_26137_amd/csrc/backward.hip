@@ -1,0 +1,389 @@
+// Backward of a loss on the baked map (pre-dilation), with the texel -> face
+// assignment, the barycentrics, the hit triangle and the UV handedness held
+// fixed.  Differentiable inputs: low-poly positions lo_V (through the texel
+// position p, the area-weighted vertex normals and the face tangent T_f) and
+// the high-poly normals hi_N (through the interpolated hit normal).
+//
+// Per ray (forward):  p = sum b_k V_k,  m = sum b_k n_k,  d = m/|m|;
+//   p + t d = A + beta1 (B - A) + beta2 (C - A) on the hit triangle's plane;
+//   h = sum beta_k N_k, n = h/|h|;  T~ = T_f - (d.T_f) d, T' = T~/|T~|,
+//   B' = h_f (d x T');  out = (n.T', n.B', n.d).
+// The adjoint walks this chain backwards per ray, then reduces:
+//   * low-poly: rays are contiguous per face in the ray list, so one wave per
+//     face sums its rays (lane-strided, then a fixed shuffle tree); vertices
+//     gather their faces through the ascending vertex -> face adjacency, the
+//     normalisation and the face cross products are differentiated, and a
+//     second gather finishes dL/dlo_V;
+//   * high-poly: each hit ray contributes beta_k h_bar to the three vertices
+//     of its triangle; the (vertex, ray*3 + corner) pairs are radix-sorted
+//     stably and each vertex sums its run in ray order.
+// No floating-point atomics: the result is bitwise reproducible.
+#include <algorithm>
+
+#include "internal.h"
+
+namespace bake {
+
+namespace {
+
+__device__ __forceinline__ float3 f3(float x, float y, float z) { return make_float3(x, y, z); }
+__device__ __forceinline__ float3 add3(float3 a, float3 b) { return f3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ float3 sub3(float3 a, float3 b) { return f3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ float3 mul3(float3 a, float s) { return f3(a.x * s, a.y * s, a.z * s); }
+__device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ float3 cross3(float3 a, float3 b) {
+    return f3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ float3 ld3(const float* p, int64_t i) {
+    return f3(p[3 * i], p[3 * i + 1], p[3 * i + 2]);
+}
+__device__ __forceinline__ void st3(float* p, int64_t i, float3 v) {
+    p[3 * i] = v.x;
+    p[3 * i + 1] = v.y;
+    p[3 * i + 2] = v.z;
+}
+// (x - (x.u) u) / len: adjoint of u = y / |y| with |y| = len
+__device__ __forceinline__ float3 unit_adj(float3 xb, float3 u, float len) {
+    return mul3(sub3(xb, mul3(u, dot3(xb, u))), 1.0f / len);
+}
+
+struct RayGrad {  // 48 B per ray
+    float3 pb, mb, tfb, hb;
+};
+
+// Per-ray adjoint.  Also emits the three (hi vertex, item) sort pairs of the
+// ray; rays without a hit emit the out-of-range key nhv.
+__global__ void bwd_ray_kernel(const Ray* __restrict__ rays, const Hit* __restrict__ hits,
+                               const uint32_t* __restrict__ nrays_p, const float* __restrict__ lo_V,
+                               const int32_t* __restrict__ lo_F, const float4* __restrict__ lo_n,
+                               const float4* __restrict__ face_t, const float* __restrict__ hi_V,
+                               const int32_t* __restrict__ hi_F, int64_t nhv,
+                               const float* __restrict__ hi_N, const float* __restrict__ grad_map,
+                               RayGrad* __restrict__ rg, uint32_t* __restrict__ keys,
+                               uint32_t* __restrict__ vals) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t nrays = *nrays_p;
+    if (r >= nrays) return;
+    const Ray ray = rays[r];
+    const Hit hit = hits[r];
+    RayGrad g;
+    g.pb = g.mb = g.tfb = g.hb = f3(0.f, 0.f, 0.f);
+    uint32_t kv[3] = {(uint32_t)nhv, (uint32_t)nhv, (uint32_t)nhv};
+    if (hit.id >= 0) {
+        const int32_t f = ray.face;
+        const float b1 = ray.b1, b2 = ray.b2, b0 = 1.0f - b1 - b2;
+        const int32_t i0 = lo_F[3 * f], i1 = lo_F[3 * f + 1], i2 = lo_F[3 * f + 2];
+        const float4 n0 = lo_n[i0], n1 = lo_n[i1], n2 = lo_n[i2];
+        const float3 m = f3(b0 * n0.x + b1 * n1.x + b2 * n2.x, b0 * n0.y + b1 * n1.y + b2 * n2.y,
+                            b0 * n0.z + b1 * n1.z + b2 * n2.z);
+        const float lm = sqrtf(dot3(m, m));
+        const float3 d = mul3(m, 1.0f / lm);
+        const float4 T4 = face_t[f];
+        const float3 Tf = f3(T4.x, T4.y, T4.z);
+        const float H = T4.w;
+        const float3 Tt = sub3(Tf, mul3(d, dot3(d, Tf)));
+        const float lt = sqrtf(dot3(Tt, Tt));
+        const float3 Tp = mul3(Tt, 1.0f / lt);
+        const float3 Bp = mul3(cross3(d, Tp), H);
+        const int32_t j0 = hi_F[3 * (int64_t)hit.id], j1 = hi_F[3 * (int64_t)hit.id + 1],
+                      j2 = hi_F[3 * (int64_t)hit.id + 2];
+        const float3 A = ld3(hi_V, j0), e1 = sub3(ld3(hi_V, j1), A), e2 = sub3(ld3(hi_V, j2), A);
+        const float3 N0 = ld3(hi_N, j0), N1 = ld3(hi_N, j1), N2 = ld3(hi_N, j2);
+        const float be1 = hit.beta1, be2 = hit.beta2, be0 = 1.0f - be1 - be2;
+        const float3 h = add3(add3(mul3(N0, be0), mul3(N1, be1)), mul3(N2, be2));
+        const float lh = sqrtf(dot3(h, h));
+        const float3 n = mul3(h, 1.0f / lh);
+        const float3 o = ld3(grad_map, ray.texel);
+        // out = (n.T', n.B', n.d)
+        const float3 nb = add3(add3(mul3(Tp, o.x), mul3(Bp, o.y)), mul3(d, o.z));
+        const float3 Tpb = add3(mul3(n, o.x), mul3(cross3(n, d), o.y * H));
+        float3 db = add3(mul3(n, o.z), mul3(cross3(Tp, n), o.y * H));
+        // T' = T~/|T~|, T~ = T_f - (d.T_f) d
+        const float3 Ttb = unit_adj(Tpb, Tp, lt);
+        const float3 Tfb = sub3(Ttb, mul3(d, dot3(d, Ttb)));
+        db = sub3(db, add3(mul3(Ttb, dot3(d, Tf)), mul3(Tf, dot3(d, Ttb))));
+        // n = h/|h|; h = sum beta_k N_k
+        const float3 hb = unit_adj(nb, n, lh);
+        const float bb1 = dot3(hb, sub3(N1, N0)), bb2 = dot3(hb, sub3(N2, N0));
+        // M (t, beta1, beta2) = p - A with M = [-d | e1 | e2]:  w = M^-T (0, bb1, bb2),
+        // by Cramer on M^T (columns = the rows of M)
+        const float3 c0 = f3(-d.x, e1.x, e2.x), c1 = f3(-d.y, e1.y, e2.y), c2 = f3(-d.z, e1.z, e2.z);
+        const float3 rhs = f3(0.f, bb1, bb2);
+        const float3 c12 = cross3(c1, c2);
+        const float D = dot3(c0, c12);
+        const float rD = 1.0f / D;
+        const float3 w = f3(dot3(rhs, c12) * rD, dot3(c0, cross3(rhs, c2)) * rD,
+                            dot3(c0, cross3(c1, rhs)) * rD);
+        db = add3(db, mul3(w, hit.t));
+        g.pb = w;
+        g.mb = unit_adj(db, d, lm);
+        g.tfb = Tfb;
+        g.hb = hb;
+        kv[0] = (uint32_t)j0;
+        kv[1] = (uint32_t)j1;
+        kv[2] = (uint32_t)j2;
+    }
+    rg[r] = g;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        keys[3 * r + k] = kv[k];
+        vals[3 * r + k] = (uint32_t)(3 * r + k);
+    }
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// One wave per low-poly face: sums over its rays of b_k p_bar, b_k m_bar and
+// T_f_bar (lane-strided in ray order, then a fixed shuffle tree), and turns
+// T_f_bar into corner contributions through T_f = c1 (V1 - V0) + c2 (V2 - V0).
+// Output per face: Vbar[3 corners][3], nbar[3 corners][3].
+__global__ __launch_bounds__(256) void bwd_face_kernel(const Ray* __restrict__ rays,
+                                                       const RayGrad* __restrict__ rg,
+                                                       const uint32_t* __restrict__ face_off,
+                                                       const int4* __restrict__ face_uv, int64_t nf,
+                                                       float* __restrict__ face_acc) {
+    const int64_t f = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (f >= nf) return;
+    const uint32_t b = face_off[f], e = face_off[f + 1];
+    float acc[21];
+#pragma unroll
+    for (int q = 0; q < 21; ++q) acc[q] = 0.f;
+    for (uint32_t r = b + lane; r < e; r += 64) {
+        const Ray ray = rays[r];
+        const RayGrad g = rg[r];
+        const float bk[3] = {1.0f - ray.b1 - ray.b2, ray.b1, ray.b2};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            acc[3 * k] += bk[k] * g.pb.x;
+            acc[3 * k + 1] += bk[k] * g.pb.y;
+            acc[3 * k + 2] += bk[k] * g.pb.z;
+            acc[9 + 3 * k] += bk[k] * g.mb.x;
+            acc[9 + 3 * k + 1] += bk[k] * g.mb.y;
+            acc[9 + 3 * k + 2] += bk[k] * g.mb.z;
+        }
+        acc[18] += g.tfb.x;
+        acc[19] += g.tfb.y;
+        acc[20] += g.tfb.z;
+    }
+#pragma unroll
+    for (int q = 0; q < 21; ++q) acc[q] = wave_sum(acc[q]);
+    if (lane == 0) {
+        const int4 p = face_uv[2 * f], q = face_uv[2 * f + 1];
+        const int64_t du1 = (int64_t)p.z - p.x, dv1 = (int64_t)p.w - p.y;
+        const int64_t du2 = (int64_t)q.x - p.x, dv2 = (int64_t)q.y - p.y;
+        const int64_t det = du1 * dv2 - du2 * dv1;
+        const float sg = det > 0 ? 1.0f : (det < 0 ? -1.0f : 0.0f);
+        const float c1 = sg * (float)dv2, c2 = -sg * (float)dv1;
+        const float3 tfb = f3(acc[18], acc[19], acc[20]);
+        const float3 e1b = mul3(tfb, c1), e2b = mul3(tfb, c2);
+        float* o = face_acc + 18 * f;
+        const float3 v0 = sub3(f3(acc[0], acc[1], acc[2]), add3(e1b, e2b));
+        const float3 v1 = add3(f3(acc[3], acc[4], acc[5]), e1b);
+        const float3 v2 = add3(f3(acc[6], acc[7], acc[8]), e2b);
+        st3(o, 0, v0);
+        st3(o, 1, v1);
+        st3(o, 2, v2);
+#pragma unroll
+        for (int q2 = 0; q2 < 9; ++q2) o[9 + q2] = acc[9 + q2];
+    }
+}
+
+__device__ __forceinline__ int corner_of(const int32_t* __restrict__ F, int32_t f, int64_t v) {
+    return F[3 * f] == v ? 0 : (F[3 * f + 1] == v ? 1 : 2);
+}
+
+// Per low-poly vertex: gather the faces' corner sums (faces ascending), then
+// the adjoint of n_v = s_v/|s_v| with s_v recomputed in the forward's order.
+__global__ void bwd_vertex1_kernel(const float* __restrict__ V, int64_t nv, const int32_t* __restrict__ F,
+                                   const uint32_t* __restrict__ off, const int32_t* __restrict__ adj,
+                                   const float* __restrict__ face_acc, float* __restrict__ vbar,
+                                   float* __restrict__ sbar) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv) return;
+    float3 vb = f3(0.f, 0.f, 0.f), nb = f3(0.f, 0.f, 0.f), s = f3(0.f, 0.f, 0.f);
+    for (uint32_t i = off[v]; i < off[v + 1]; ++i) {
+        const int32_t f = adj[i];
+        const int k = corner_of(F, f, v);
+        const float* o = face_acc + 18 * (int64_t)f;
+        vb = add3(vb, f3(o[3 * k], o[3 * k + 1], o[3 * k + 2]));
+        nb = add3(nb, f3(o[9 + 3 * k], o[9 + 3 * k + 1], o[9 + 3 * k + 2]));
+        const float3 A = ld3(V, F[3 * f]), B = ld3(V, F[3 * f + 1]), C = ld3(V, F[3 * f + 2]);
+        const float3 c = cross3(sub3(B, A), sub3(C, A));
+        s.x += c.x;
+        s.y += c.y;
+        s.z += c.z;
+    }
+    const float ls = sqrtf(dot3(s, s));
+    float3 sb = f3(0.f, 0.f, 0.f);
+    if (ls > 0.f && isfinite(ls)) sb = unit_adj(nb, mul3(s, 1.0f / ls), ls);
+    st3(vbar, v, vb);
+    st3(sbar, v, sb);
+}
+
+// Per low-poly face: c_bar = sum of its vertices' s_bar; adjoint of the cross
+// product c = e1 x e2 into corner contributions.
+__global__ void bwd_face2_kernel(const float* __restrict__ V, const int32_t* __restrict__ F, int64_t nf,
+                                 int64_t nv, const float* __restrict__ sbar, float* __restrict__ face_acc2) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    float* o = face_acc2 + 9 * f;
+    const int32_t a = F[3 * f], b = F[3 * f + 1], c = F[3 * f + 2];
+    if (a < 0 || b < 0 || c < 0 || a >= nv || b >= nv || c >= nv) {
+        // faces with bad indices never entered the adjacency: nothing to add
+        for (int q = 0; q < 9; ++q) o[q] = 0.f;
+        return;
+    }
+    const float3 cb = add3(add3(ld3(sbar, a), ld3(sbar, b)), ld3(sbar, c));
+    const float3 A = ld3(V, a), e1 = sub3(ld3(V, b), A), e2 = sub3(ld3(V, c), A);
+    const float3 e1b = cross3(e2, cb), e2b = cross3(cb, e1);
+    st3(o, 0, mul3(add3(e1b, e2b), -1.0f));
+    st3(o, 1, e1b);
+    st3(o, 2, e2b);
+}
+
+__global__ void bwd_vertex2_kernel(int64_t nv, const int32_t* __restrict__ F,
+                                   const uint32_t* __restrict__ off, const int32_t* __restrict__ adj,
+                                   const float* __restrict__ face_acc2, const float* __restrict__ vbar,
+                                   float* __restrict__ grad_lo_V) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv) return;
+    float3 g = ld3(vbar, v);
+    for (uint32_t i = off[v]; i < off[v + 1]; ++i) {
+        const int32_t f = adj[i];
+        const int k = corner_of(F, f, v);
+        g = add3(g, ld3(face_acc2 + 9 * (int64_t)f, k));
+    }
+    st3(grad_lo_V, v, g);
+}
+
+// Sorted (vertex, item) pairs: the first item of each vertex's run sums the
+// run in order (items are ascending within a run: the sort is stable).
+__global__ void bwd_hiN_kernel(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                               const uint32_t* __restrict__ nrays_p, int64_t nhv,
+                               const Hit* __restrict__ hits, const RayGrad* __restrict__ rg,
+                               float* __restrict__ grad_hi_N) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = 3 * (int64_t)(*nrays_p);
+    if (i >= n) return;
+    const uint32_t key = keys[i];
+    if (key >= (uint32_t)nhv) return;
+    if (i > 0 && keys[i - 1] == key) return;
+    float3 g = f3(0.f, 0.f, 0.f);
+    for (int64_t j = i; j < n && keys[j] == key; ++j) {
+        const uint32_t item = vals[j];
+        const uint32_t r = item / 3, k = item - 3 * r;
+        const Hit h = hits[r];
+        const float beta = k == 0 ? 1.0f - h.beta1 - h.beta2 : (k == 1 ? h.beta1 : h.beta2);
+        g = add3(g, mul3(rg[r].hb, beta));
+    }
+    st3(grad_hi_N, key, g);
+}
+
+// Squared-error loss helper: grad = 2 (map - target), per-block partial sums
+// of (map - target)^2, then a single block adds the partials in order.
+__global__ __launch_bounds__(256) void sq_loss_kernel(const float* __restrict__ map,
+                                                      const float* __restrict__ target, int64_t n,
+                                                      float* __restrict__ grad, float* __restrict__ partial) {
+    __shared__ float red[4];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    float e = 0.f;
+    if (i < n) {
+        const float d = map[i] - target[i];
+        if (grad) grad[i] = 2.0f * d;
+        e = d * d;
+    }
+    e = wave_sum(e);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void sum_partials_kernel(const float* __restrict__ partial, int64_t m,
+                                                           float* __restrict__ out) {
+    __shared__ float red[4];
+    float acc = 0.f;
+    for (int64_t i = threadIdx.x; i < m; i += 256) acc += partial[i];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+hipError_t launch_backward(const float* hi_V, const int32_t* hi_F, int64_t nhv, const float* hi_N,
+                           const float* lo_V, const int32_t* lo_F, int64_t nlv, int64_t nlf,
+                           const float* grad_map, float* grad_lo_V, float* grad_hi_N, const Layout& L,
+                           char* ws, hipStream_t s) {
+    hipError_t e;
+    const uint32_t* counters = (const uint32_t*)(ws + L.counters);
+    const Ray* rays = (const Ray*)(ws + L.rays);
+    const Hit* hits = (const Hit*)(ws + L.hits);
+    RayGrad* rg = (RayGrad*)(ws + L.bwd_ray);
+    uint32_t* k0 = (uint32_t*)(ws + L.bwd_k0);
+    uint32_t* v0 = (uint32_t*)(ws + L.bwd_v0);
+    uint32_t* k1 = (uint32_t*)(ws + L.bwd_k1);
+    uint32_t* v1 = (uint32_t*)(ws + L.bwd_v1);
+    const int64_t max_items = 3 * L.max_rays;
+    if (L.max_rays > 0) {
+        hipLaunchKernelGGL(bwd_ray_kernel, dim3(blocks_for(L.max_rays, 256)), dim3(256), 0, s, rays, hits,
+                           counters + kCntRays, lo_V, lo_F, (const float4*)(ws + L.lo_n),
+                           (const float4*)(ws + L.face_t), hi_V, hi_F, nhv, hi_N, grad_map, rg, k0, v0);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (grad_lo_V && nlv > 0) {
+        float* face1 = (float*)(ws + L.bwd_face1);
+        float* face2 = (float*)(ws + L.bwd_face2);
+        float* sbar = (float*)(ws + L.bwd_sbar);
+        float* vbar = (float*)(ws + L.bwd_vbar);
+        const uint32_t* off = (const uint32_t*)(ws + L.lo_off);
+        const int32_t* adj = (const int32_t*)(ws + L.lo_adj);
+        if (nlf > 0) {
+            hipLaunchKernelGGL(bwd_face_kernel, dim3(blocks_for(nlf, 4)), dim3(256), 0, s, rays,
+                               (const RayGrad*)rg, (const uint32_t*)(ws + L.face_off),
+                               (const int4*)(ws + L.face_uv), nlf, face1);
+        }
+        hipLaunchKernelGGL(bwd_vertex1_kernel, dim3(blocks_for(nlv, 256)), dim3(256), 0, s, lo_V, nlv, lo_F,
+                           off, adj, (const float*)face1, vbar, sbar);
+        if (nlf > 0) {
+            hipLaunchKernelGGL(bwd_face2_kernel, dim3(blocks_for(nlf, 256)), dim3(256), 0, s, lo_V, lo_F, nlf,
+                               nlv, (const float*)sbar, face2);
+        }
+        hipLaunchKernelGGL(bwd_vertex2_kernel, dim3(blocks_for(nlv, 256)), dim3(256), 0, s, nlv, lo_F, off,
+                           adj, (const float*)face2, (const float*)vbar, grad_lo_V);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (grad_hi_N && nhv > 0) {
+        if ((e = fill_u32((uint32_t*)grad_hi_N, 0u, 3 * nhv, s)) != hipSuccess) return e;
+        int bits = 1;
+        while (bits < 32 && ((uint64_t)1 << bits) <= (uint64_t)nhv) ++bits;  // keys in [0, nhv]
+        bool in1 = false;
+        if ((e = radix_sort_pairs(k0, v0, k1, v1, max_items, bits, (uint32_t*)(ws + L.bwd_hist),
+                                  (uint32_t*)(ws + L.scan_tmp), &in1, s, counters + kCntRays, 3u)) !=
+            hipSuccess)
+            return e;
+        hipLaunchKernelGGL(bwd_hiN_kernel, dim3(blocks_for(max_items, 256)), dim3(256), 0, s,
+                           (const uint32_t*)(in1 ? k1 : k0), (const uint32_t*)(in1 ? v1 : v0),
+                           counters + kCntRays, nhv, hits, (const RayGrad*)rg, grad_hi_N);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_sq_loss(const float* map, const float* target, int64_t n3, float* grad, float* loss,
+                          float* partial, hipStream_t s) {
+    if (n3 <= 0) return fill_u32((uint32_t*)loss, 0u, 1, s);
+    const unsigned nb = blocks_for(n3, 256);
+    hipLaunchKernelGGL(sq_loss_kernel, dim3(nb), dim3(256), 0, s, map, target, n3, grad, partial);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, (const float*)partial, (int64_t)nb, loss);
+    return hipGetLastError();
+}
+
+}  // namespace bake

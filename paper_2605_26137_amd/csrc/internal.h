@@ -77,7 +77,8 @@ struct Layout {
     size_t keys0, keys1, vals0, vals1, hist;  // radix sort
     size_t nodes, leaves, node_parent, leaf_parent, refit_cnt, node_range, frontier, treelets;
     size_t spill;                             // traversal stack spill
-    size_t bwd0, bwd1, bwd2, bwd3, bwd4, bwd5;  // backward scratch
+    // backward scratch (BAKE_FLAG_SAVE only)
+    size_t bwd_ray, bwd_k0, bwd_v0, bwd_k1, bwd_v1, bwd_hist, bwd_face1, bwd_face2, bwd_sbar, bwd_vbar;
     size_t total;
     // sizes used by launchers
     int64_t n_texels, max_rays, sort_blocks, scan_tmp_n, spill_lanes;
@@ -120,6 +121,15 @@ int64_t scan_tmp_elems(int64_t n);
 hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp,
                               uint32_t* total, hipStream_t s);
 
+// Stable LSD radix sort of (key, value) pairs on the low `bits` bits, 8 per
+// pass, ping-ponging between (k0, v0) and (k1, v1); *result_in_1 tells where
+// the sorted pairs ended.  hist needs radix_hist_elems(n) u32.  With n_dev the
+// sorted length is min(n, n_mul * *n_dev) (a count that lives on the device).
+int64_t radix_hist_elems(int64_t n);
+hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n, int bits,
+                            uint32_t* hist, uint32_t* scan_tmp, bool* result_in_1, hipStream_t s,
+                            const uint32_t* n_dev = nullptr, uint32_t n_mul = 1);
+
 hipError_t launch_lo_prep(const float* lo_V, int64_t nlv, const int32_t* lo_F, int64_t nlf,
                           const float* lo_UV, int32_t res, const Layout& L, char* ws,
                           hipStream_t s);
@@ -137,9 +147,11 @@ hipError_t launch_dilate(int32_t res, int passes, float* out_map, const Layout& 
                          hipStream_t s);
 hipError_t launch_rgb8(int32_t res, const float* out_map, uint8_t* rgb, hipStream_t s);
 
-hipError_t launch_backward(const float* hi_V, const int32_t* hi_F, int64_t nhv, int64_t nhf,
-                           const float* hi_N, const float* lo_V, const int32_t* lo_F, int64_t nlv,
-                           int64_t nlf, int32_t res, const float* grad_map, float* grad_lo_V,
-                           float* grad_hi_N, const Layout& L, char* ws, hipStream_t s);
+hipError_t launch_backward(const float* hi_V, const int32_t* hi_F, int64_t nhv, const float* hi_N,
+                           const float* lo_V, const int32_t* lo_F, int64_t nlv, int64_t nlf,
+                           const float* grad_map, float* grad_lo_V, float* grad_hi_N, const Layout& L,
+                           char* ws, hipStream_t s);
+hipError_t launch_sq_loss(const float* map, const float* target, int64_t n3, float* grad, float* loss,
+                          float* partial, hipStream_t s);
 
 }  // namespace bake

@@ -154,10 +154,20 @@ __global__ void morton_kernel(const float* __restrict__ V, int64_t nv, const int
 // 3. stable LSD radix sort, 8-bit digits
 // ---------------------------------------------------------------------------
 
+// n_dev (optional): the element count is min(n, n_mul * *n_dev); the grid is
+// sized for n and blocks past the device count find nothing to do.
+__device__ __forceinline__ int64_t eff_count(int64_t n, const uint32_t* n_dev, uint32_t n_mul) {
+    if (!n_dev) return n;
+    int64_t m = (int64_t)n_mul * (int64_t)(*n_dev);
+    return m < n ? m : n;
+}
+
 __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __restrict__ keys,
-                                                            int64_t n, int shift, int64_t nb,
+                                                            int64_t n_host, const uint32_t* n_dev,
+                                                            uint32_t n_mul, int shift, int64_t nb,
                                                             uint32_t* __restrict__ hist) {
     __shared__ uint32_t h[256];
+    const int64_t n = eff_count(n_host, n_dev, n_mul);
     h[threadIdx.x] = 0;
     __syncthreads();
     int64_t base = (int64_t)blockIdx.x * kSortTile;
@@ -175,10 +185,12 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __re
 __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t* __restrict__ kin,
                                                                const uint32_t* __restrict__ vin,
                                                                uint32_t* __restrict__ kout,
-                                                               uint32_t* __restrict__ vout, int64_t n,
+                                                               uint32_t* __restrict__ vout, int64_t n_host,
+                                                               const uint32_t* n_dev, uint32_t n_mul,
                                                                int shift, int64_t nb,
                                                                const uint32_t* __restrict__ offs) {
     __shared__ uint32_t run[256];
+    const int64_t n = eff_count(n_host, n_dev, n_mul);
     __shared__ uint32_t wcnt[kBlock / 64][256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     (void)lane;
@@ -466,6 +478,30 @@ inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b
 
 }  // namespace
 
+int64_t radix_hist_elems(int64_t n) { return 256 * ((n + kSortTile - 1) / kSortTile); }
+
+hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n, int bits,
+                            uint32_t* hist, uint32_t* scan_tmp, bool* result_in_1, hipStream_t s,
+                            const uint32_t* n_dev, uint32_t n_mul) {
+    *result_in_1 = false;
+    if (n <= 0) return hipSuccess;
+    hipError_t e;
+    int64_t nb = (n + kSortTile - 1) / kSortTile;
+    uint32_t* kin = k0; uint32_t* vin = v0; uint32_t* kout = k1; uint32_t* vout = v1;
+    for (int shift = 0; shift < bits; shift += 8) {
+        hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nb), dim3(kBlock), 0, s,
+                           (const uint32_t*)kin, n, n_dev, n_mul, shift, nb, hist);
+        if ((e = exclusive_scan_u32(hist, hist, 256 * nb, scan_tmp, nullptr, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nb), dim3(kBlock), 0, s,
+                           (const uint32_t*)kin, (const uint32_t*)vin, kout, vout, n, n_dev, n_mul, shift,
+                           nb, (const uint32_t*)hist);
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+        *result_in_1 = !*result_in_1;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_bvh_build(const float* hi_V, int64_t nhv, const int32_t* hi_F, int64_t nhf,
                             const Layout& L, char* ws, hipStream_t s) {
     if (nhf <= 0) return hipSuccess;
@@ -494,21 +530,11 @@ hipError_t launch_bvh_build(const float* hi_V, int64_t nhv, const int32_t* hi_F,
                        hi_F, nhf, (const float*)bounds, k0, v0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
 
-    int64_t nb = (nhf + kSortTile - 1) / kSortTile;
-    uint32_t* kin = k0; uint32_t* vin = v0; uint32_t* kout = k1; uint32_t* vout = v1;
-    for (int shift = 0; shift < 32; shift += 8) {
-        hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nb), dim3(kBlock), 0, s,
-                           (const uint32_t*)kin, nhf, shift, nb, hist);
-        if ((e = exclusive_scan_u32(hist, hist, 256 * nb, (uint32_t*)(ws + L.scan_tmp), nullptr, s)) !=
-            hipSuccess)
-            return e;
-        hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nb), dim3(kBlock), 0, s,
-                           (const uint32_t*)kin, (const uint32_t*)vin, kout, vout, nhf, shift, nb,
-                           (const uint32_t*)hist);
-        std::swap(kin, kout);
-        std::swap(vin, vout);
-    }
-    // four passes: the sorted arrays are back in keys0 / vals0
+    bool in1 = false;
+    if ((e = radix_sort_pairs(k0, v0, k1, v1, nhf, 30, hist, (uint32_t*)(ws + L.scan_tmp), &in1, s)) !=
+        hipSuccess)
+        return e;
+    // 30-bit keys take four 8-bit passes: the sorted arrays are back in keys0 / vals0
     if (nhf > 1) {
         hipLaunchKernelGGL(karras_kernel, dim3(blocks_for(nhf - 1, kBlock)), dim3(kBlock), 0, s,
                            (const uint32_t*)k0, nhf, nodes, np, lp, range);
