@@ -6,10 +6,11 @@ by seeded 4-octave gradient noise, baked onto the level-5 icosphere (20,480
 triangles) with a per-face grid atlas of 2048^2 texels, max_dist 0.12.  Inputs
 are synthetic and resident in HBM before timing.
 
-A step is one whole bake through the C ABI: low-poly prep, UV raster, LBVH
-build over the high-poly, traversal + tangent-space encode, dilation, and the
-backward pass of a squared-error loss when the library provides it.  value =
-covered-texel rays per second of the full step.
+A step is one pass of the whole path through the C ABI: the forward bake
+(low-poly prep, UV raster, LBVH build over the high-poly, traversal + tangent-
+space encode, dilation) with its state saved, the squared-error loss against a
+target map baked from a second noise seed, and the backward pass to dL/dlo_V
+and dL/dhi_N.  value = covered-texel rays per second of the whole step.
 
 Besides the JSON line's required fields it reports:
   roofline      the dominant kernel (traversal) against the VALU issue peak,
@@ -17,7 +18,10 @@ Besides the JSON line's required fields it reports:
                 over the timed steps, and the algorithmic op count from an
                 instrumented bake (box and triangle tests);
   cpu_baseline  the FP64 brute-force oracle on a bounded sample of the same
-                rays, on this host's cores.
+                rays, on this host's cores;
+  batch         (--batch-assets N) N uneven assets (50k-2M triangles, 512^2-
+                2048^2 atlases) baked forward + backward as one graph-recorded
+                batch, against the same bakes as N sequential plain calls.
 """
 import argparse
 import hashlib
@@ -40,10 +44,10 @@ sys.path.insert(0, ROOT)
 OPS_BOX, OPS_TRI, OPS_RAY = 20, 54, 100
 # MI355X VALU issue rate: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (non-packed FP32)
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-HBM_PEAK_GBS = 8000.0
 
 WORKLOAD = "noise4 icosphere L8 (1,310,720 tris) -> icosphere L5 (20,480 tris), 2048^2 atlas, max_dist 0.12"
 METRIC = "baked rays/s (1.3M-tri→20k-tri, 2048² atlas); fwd+bwd ms; % HBM/VALU peak"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_traverse_noise4_L8_L5_2048.json")
 
 
 def source_hash(*names):
@@ -57,10 +61,9 @@ def source_hash(*names):
 def measured_traffic(kernel_hash):
     """HBM bytes per traversal launch from the committed rocprofv3 counter runs,
     if they were taken on the current kernel source; else None."""
-    p = os.path.join(ROOT, "profiles", "traffic_traverse_noise4_L8_L5_2048.json")
-    if not os.path.exists(p):
+    if not os.path.exists(TRAFFIC_FILE):
         return None
-    with open(p) as f:
+    with open(TRAFFIC_FILE) as f:
         d = json.load(f)
     if d.get("source_hash") != kernel_hash:
         return None
@@ -69,7 +72,8 @@ def measured_traffic(kernel_hash):
 
 def cpu_baseline(asset, target_s):
     """The oracle as it stands (FP64 brute force over every triangle) on a
-    seeded sample of the workload's covered texels."""
+    seeded sample of the workload's covered texels (forward query: the
+    oracle's per-ray adjoint is negligible next to it)."""
     import numpy as np
     import oracle
     cores = oracle.set_threads(0)
@@ -91,22 +95,107 @@ def cpu_baseline(asset, target_s):
                       f"{asset.hi_F.shape[0]} triangles, {dt:.1f} s"}
 
 
+def make_batch(n_assets, log):
+    """The uneven batch's inputs, generated in a process pool (before this
+    process touches the GPU)."""
+    from synth import make_batch_assets
+    t0 = time.perf_counter()
+    workers = max(1, min(16, os.cpu_count() or 1))
+    assets = make_batch_assets(n_assets, workers=workers)
+    log(f"[bench] batch: {n_assets} assets generated in {time.perf_counter() - t0:.1f} s")
+    return assets
+
+
+def bench_batch(B, assets, steps, warmup, trav, log):
+    """Uneven assets: forward + backward of the whole batch, recorded into one
+    graph, against the same work as sequential per-asset plain calls."""
+    import numpy as np
+    import torch
+    n_assets = len(assets)
+    dev = torch.device("cuda:0")
+    ins = [(*B.to_device(a, dev), a.res, a.max_dist) for a in assets]
+    rng = np.random.default_rng(99)
+    grads = [torch.from_numpy(rng.normal(size=(a.res, a.res, 3)).astype(np.float32)).to(dev) for a in assets]
+    batch = B.BakeBatch(ins, save=True, **trav)
+    for g, src in zip(batch.grad_maps, grads):
+        g.copy_(src)
+    tune = B.autotune(batch, reps=1)
+    log(f"[bench] batch autotune: block {tune['block']} stack {tune['stack']} persist {tune['persist']}")
+    batch.forward()
+    batch.backward()
+    torch.cuda.synchronize()
+    rays = int(sum(batch.ray_counts()))
+
+    # sequential plain calls (each with its own BVH build), one shared workspace
+    seq_opts = dict(trav_block=tune["block"], trav_stack=tune["stack"], trav_persist=tune["persist"])
+    ws_bytes = max(B.workspace_size(x[0].shape[0], x[1].shape[0], x[3].shape[0], x[4].shape[0], x[6],
+                                    B.make_options(save=True)) for x in ins)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    outs = [(torch.empty_like(batch.maps[i]), torch.empty_like(batch.hits[i]),
+             torch.empty_like(batch.grad_lo_V[i]), torch.empty_like(batch.grad_hi_N[i]))
+            for i in range(n_assets)]
+
+    def seq_step():
+        for i, x in enumerate(ins):
+            om, oh, glo, ghi = outs[i]
+            r = B.bake_normals(*x[:6], x[6], x[7], save=True, workspace=ws, out_map=om, out_hit=oh, **seq_opts)
+            B.bake_normals_backward(r, x[:6], grads[i], out_lo=glo, out_hi=ghi)
+
+    def timed(fn, k):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3 / k
+
+    seq_ms = timed(seq_step, steps)
+    # the sequential results equal the batch's, bitwise
+    same = all(torch.equal(outs[i][0].view(torch.int32), batch.maps[i].view(torch.int32))
+               and torch.equal(outs[i][1], batch.hits[i])
+               and torch.equal(outs[i][2].view(torch.int32), batch.grad_lo_V[i].view(torch.int32))
+               and torch.equal(outs[i][3].view(torch.int32), batch.grad_hi_N[i].view(torch.int32))
+               for i in range(n_assets))
+
+    def eager():
+        batch.forward()
+        batch.backward()
+
+    eager_ms = timed(eager, steps)
+    graph = batch.capture()
+    graph_ms = timed(graph.replay, steps)
+    log(f"[bench] batch: sequential {seq_ms:.2f} ms, batched eager {eager_ms:.2f} ms, graph {graph_ms:.2f} ms")
+    return {"assets": n_assets, "hi_tris": int(sum(a.hi_F.shape[0] for a in assets)),
+            "texels": int(sum(a.res * a.res for a in assets)), "rays": rays,
+            "step": "forward (save) + backward from a fixed dL/dmap per asset",
+            "sequential_ms": seq_ms, "batched_eager_ms": eager_ms, "batched_graph_ms": graph_ms,
+            "speedup_graph_vs_sequential": seq_ms / graph_ms,
+            "rays_per_s_graph": rays / (graph_ms / 1e3), "rays_per_s_sequential": rays / (seq_ms / 1e3),
+            "bitwise_equal_to_sequential": bool(same),
+            "tuned": {k: tune[k] for k in ("block", "stack", "persist")}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--trav-block", type=int, default=0)
     ap.add_argument("--trav-stack", type=int, default=0)
     ap.add_argument("--trav-persist", type=int, default=-1)
+    ap.add_argument("--batch-assets", type=int, default=0, metavar="N",
+                    help="also measure an N-asset batch (64 = the uneven batch workload)")
+    ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build bakes on a single device "
-              "(see DESIGN.md for how the bake would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the bake runs on a single device here "
+              "(DESIGN.md describes how it would shard); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -114,6 +203,10 @@ def main():
     import paper_2605_26137_amd.bake as B
     from synth import make_config
 
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    batch_assets = make_batch(args.batch_assets, log) if args.batch_assets > 0 else None
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     if args.calibrate_copy:
@@ -127,34 +220,49 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": n, "copies": 3}), flush=True)
         return
-    print(f"[bench] {B.version()} on {torch.cuda.get_device_name(0)}", file=sys.stderr, flush=True)
+    log(f"[bench] {B.version()} on {torch.cuda.get_device_name(0)}")
     asset = make_config(2)
     t = B.to_device(asset, dev)
     res, md = asset.res, asset.max_dist
-    kw = dict(trav_block=args.trav_block, trav_stack=args.trav_stack, trav_persist=args.trav_persist)
-    first = B.bake_normals(*t, res, md, **kw)
+    trav = dict(trav_block=args.trav_block, trav_stack=args.trav_stack, trav_persist=args.trav_persist)
+    # loss target: the map baked (by this library, untimed) from a second noise seed
+    tgt_asset = make_config(2, seed=1)
+    target = B.bake_normals(*B.to_device(tgt_asset, dev), res, md).map.clone()
+    first = B.bake_normals(*t, res, md, save=True, **trav)
     ws, out_map, out_hit = first.workspace, first.map, first.hit
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    gmap = torch.empty_like(out_map)
+    scratch = torch.empty(4 * ((out_map.numel() + 255) // 256 + 1), dtype=torch.uint8, device=dev)
+    glo = torch.empty_like(t[3])
+    ghi = torch.empty_like(t[2])
     torch.cuda.synchronize()
     rays = first.ray_count()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
 
-    def step(timing):
-        B.bake_normals(*t, res, md, timing=timing, workspace=ws, out_map=out_map,
-                       out_hit=out_hit, **kw)
+    def step(timing, k=None):
+        r = B.bake_normals(*t, res, md, save=True, timing=timing, workspace=ws, out_map=out_map,
+                           out_hit=out_hit, **trav)
+        if k is not None:
+            ev[2 * k].record()
+        B.sq_loss(out_map, target, out_loss=loss, out_grad=gmap, scratch=scratch)
+        B.bake_normals_backward(r, t, gmap, out_lo=glo, out_hi=ghi)
+        if k is not None:
+            ev[2 * k + 1].record()
 
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
-    # timed region: whole steps back to back, stage events on the bake stream
+    # timed region: whole steps back to back; stage events on the bake stream
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(True)
+    for k in range(args.steps):
+        step(True, k)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     hist = B.stage_history(min(args.steps, 64))
     stage_ms = {name: float(np.mean(hist[:, k])) for k, name in enumerate(B.STAGES)}
-    print(f"[bench] {args.steps} steps, {ms_per_step:.3f} ms/step, stages {stage_ms}",
-          file=sys.stderr, flush=True)
+    bwd_ms = float(np.mean([ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(args.steps)]))
+    log(f"[bench] {args.steps} steps, {ms_per_step:.3f} ms/step, stages {stage_ms}, loss+backward {bwd_ms:.3f} ms")
 
     # algorithmic op count of the traversal: one instrumented bake, untimed
     cnt = B.bake_normals(*t, res, md, count=True, workspace=ws, out_map=out_map, out_hit=out_hit)
@@ -162,8 +270,8 @@ def main():
     ops = n_box * OPS_BOX + n_tri * OPS_TRI + rays * OPS_RAY
     trav_s = stage_ms["traverse"] / 1e3
     achieved = ops / trav_s / 1e12
-    khash = source_hash("traverse.hip", "lbvh.hip")
-    roof = {"kernel": "traverse_kernel (traversal + encode)", "bound": "alu",
+    khash = source_hash("traverse.hip", "lbvh.hip", "internal.h")
+    roof = {"kernel": "traverse_batch_kernel (traversal + encode)", "bound": "alu",
             "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
             "frac": achieved / VALU_PEAK_TOPS, "traffic": measured_traffic(khash),
             "ops_per_launch": ops, "box_tests_per_ray": n_box / rays, "tri_tests_per_ray": n_tri / rays,
@@ -184,14 +292,18 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "rays": rays, "texels": res * res,
                    "hi_tris": int(asset.hi_F.shape[0]), "lo_tris": int(asset.lo_F.shape[0]),
-                   "step": "forward bake incl. BVH build"},
+                   "step": "forward bake incl. BVH build + squared-error loss + backward"},
+        "fwd_bwd_ms": ms_per_step,
         "fwd_ms": stage_ms["forward"],
+        "loss_bwd_ms": bwd_ms,
+        "fwd_rays_per_s": rays / (stage_ms["forward"] / 1e3),
         "stages_ms": stage_ms,
-        "texels_per_s": res * res / (ms_per_step / 1e3),
         "roofline": roof,
     }
+    if batch_assets:
+        out["batch"] = bench_batch(B, batch_assets, args.batch_steps, 1, trav, log)
     if not args.no_cpu_baseline:
-        print("[bench] timing the CPU oracle on a sample ...", file=sys.stderr, flush=True)
+        log("[bench] timing the CPU oracle on a sample ...")
         out["cpu_baseline"] = cpu_baseline(asset, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

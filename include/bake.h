@@ -64,6 +64,8 @@ extern "C" {
 #define BAKE_STATUS_BAD_UV 4u    /* UV non-finite or outside [-1, 2]; face skipped */
 #define BAKE_STATUS_NONFINITE 8u /* non-finite vertex position; face/triangle skipped */
 #define BAKE_STATUS_INTERNAL 16u /* internal consistency guard tripped (should never happen) */
+#define BAKE_STATUS_STATE 32u    /* a backward found the workspace no longer holding the saved
+                                    forward's state (reused since): it wrote nothing */
 
 /* ---- flags ------------------------------------------------------------ */
 #define BAKE_FLAG_SAVE 1u   /* keep the per-ray state that bake_normals_backward needs */
@@ -77,8 +79,9 @@ typedef struct bake_options {
     uint8_t *out_rgb8;     /* optional device [res,res,3] u8 map: floor((x+1)*127.5+0.5)   */
     int32_t trav_block;    /* traversal workgroup size: 64, 128, 256 (0 = tuned default)  */
     int32_t trav_stack;    /* LDS stack entries per lane: 8, 16, 32 (0 = tuned default)    */
-    int32_t trav_persist;  /* 1 = persistent waves refilling finished lanes, 0 = one ray
-                              per lane, -1 = tuned default                                */
+    int32_t trav_persist;  /* 1 = persistent waves refilling finished lanes from a ray
+                              queue, 0 = persistent waves taking whole 64-ray batches,
+                              -1 = tuned default                                          */
     int32_t reserved[4];
 } bake_options;
 
@@ -126,8 +129,10 @@ int32_t bake_normals(const float *hi_V, int64_t n_hi_v, const int32_t *hi_F, int
  * misses, unreliable, uncovered and dilated texels are constants.  (The paper
  * has no backward pass; this differentiates its bake as defined above.)
  * Needs the workspace of the last forward call made with BAKE_FLAG_SAVE on the
- * same inputs on this thread, not modified since (else BAKE_E_STATE); the
- * workspace size is the one of that forward.  Sums are done in a fixed order
+ * same inputs (else BAKE_E_STATE); the workspace size is the one of that
+ * forward.  That forward leaves a nonce in the workspace; if the memory was
+ * overwritten since, the backward kernels find a different value, write
+ * nothing and set BAKE_STATUS_STATE.  Sums are done in a fixed order
  * (no floating-point atomics): the result is bitwise reproducible.  Either
  * gradient pointer may be NULL to skip it. */
 int32_t bake_normals_backward(const float *hi_V, int64_t n_hi_v, const int32_t *hi_F,
@@ -178,6 +183,73 @@ int32_t bake_stage_times(float *ms_out, int32_t n);
 /* The same for up to the 64 most recent timed bakes on this thread, oldest
  * first: ms_out is [max_bakes][6].  Returns the number of bakes written. */
 int32_t bake_stage_history(float *ms_out, int32_t max_bakes);
+
+/* ---- batches: many bakes in one launch sequence ------------------------
+ *
+ * A batch runs the same stages as bake_normals for every asset, each stage as
+ * one set of launches over all assets: per-asset BVHs built together (sort
+ * tiles never straddle two assets), one traversal over a device work queue of
+ * (asset, 64-ray batch) items, and the backward likewise.  Every asset goes
+ * through exactly the arithmetic of a single bake, so a batched asset's
+ * outputs are bitwise equal to those of bake_normals / bake_normals_backward
+ * on the same inputs.  The calls enqueue kernels only (the asset table is
+ * passed as kernel arguments, no host-to-device copy), so a sequence of them
+ * can be recorded into a HIP graph and replayed while the pointers stay
+ * valid.  The batch's size limits: n_assets in [1, 65536]; every per-asset
+ * limit of bake_normals; 3 * sum(res^2) < 2^32 and sum(n_hi_f) < 2^31. */
+typedef struct bake_asset {
+    const float *hi_V;     /* [n_hi_v,3] */
+    int64_t n_hi_v;
+    const int32_t *hi_F;   /* [n_hi_f,3] */
+    int64_t n_hi_f;
+    const float *hi_N;     /* [n_hi_v,3] */
+    const float *lo_V;     /* [n_lo_v,3] */
+    int64_t n_lo_v;
+    const int32_t *lo_F;   /* [n_lo_f,3] */
+    int64_t n_lo_f;
+    const float *lo_UV;    /* [n_lo_f,3,2] */
+    int32_t res;
+    float max_dist;
+    float *out_map;        /* [res,res,3] */
+    int32_t *out_hit;      /* [res,res] */
+    uint8_t *out_rgb8;     /* optional [res,res,3] */
+    const float *grad_map; /* backward input  [res,res,3] */
+    float *grad_lo_V;      /* backward output [n_lo_v,3] or NULL */
+    float *grad_hi_N;      /* backward output [n_hi_v,3] or NULL */
+} bake_asset;
+
+/* Workspace bytes for a batch (opt as for bake_normals; opt->out_rgb8 must be
+ * NULL: RGB8 outputs are per asset). */
+int32_t bake_batch_workspace_size(const bake_asset *assets, int32_t n_assets, const bake_options *opt,
+                                  size_t *bytes_out);
+
+/* Forward bake of every asset of the batch (bake_normals semantics per asset;
+ * outputs through each asset's out_map / out_hit / out_rgb8).  The device
+ * status word is the OR over the batch. */
+int32_t bake_normals_batched(const bake_asset *assets, int32_t n_assets, const bake_options *opt,
+                             void *workspace, size_t workspace_bytes, void *stream);
+
+/* Backward of every asset of the batch (bake_normals_backward semantics per
+ * asset, from grad_map into grad_lo_V / grad_hi_N).  Needs the workspace of the
+ * last bake_normals_batched with BAKE_FLAG_SAVE on a batch of the same sizes. */
+int32_t bake_normals_batched_backward(const bake_asset *assets, int32_t n_assets, void *workspace,
+                                      size_t workspace_bytes, void *stream);
+
+/* bake_read_counter for asset `asset` of the last batch that used `workspace`. */
+int32_t bake_read_asset_counter(const void *workspace, int32_t asset, int32_t which, void *stream,
+                                int64_t *value_out);
+
+/* Traversal autotuner: bakes the batch with every traversal configuration
+ * (trav_block x trav_stack x trav_persist = 3 x 3 x 2), `reps` times each,
+ * and returns in *best_out the options of `base` (NULL = defaults) with the
+ * configuration of the smallest median traversal time; ms_out (NULL or 18
+ * floats) receives every configuration's median, in the order block-major,
+ * then stack, then persist.  Synchronises the stream; do not record it in a
+ * graph.  The outputs of the batch are those of the last configuration run
+ * (all configurations give identical results). */
+int32_t bake_autotune(const bake_asset *assets, int32_t n_assets, const bake_options *base, int32_t reps,
+                      void *workspace, size_t workspace_bytes, void *stream, bake_options *best_out,
+                      float *ms_out);
 
 /* Thread-local message of the last error on this thread ("" if none). */
 const char *bake_last_error(void);

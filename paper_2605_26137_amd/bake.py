@@ -32,6 +32,8 @@ BAKE_STATUS_LO_INDEX = 1
 BAKE_STATUS_HI_INDEX = 2
 BAKE_STATUS_BAD_UV = 4
 BAKE_STATUS_NONFINITE = 8
+BAKE_STATUS_INTERNAL = 16
+BAKE_STATUS_STATE = 32
 
 BAKE_FLAG_SAVE = 1
 BAKE_FLAG_TIMING = 2
@@ -60,6 +62,21 @@ class BakeOptions(C.Structure):
     ]
 
 
+class BakeAsset(C.Structure):
+    """One asset of a batch (struct bake_asset)."""
+    _fields_ = [
+        ("hi_V", C.c_void_p), ("n_hi_v", C.c_int64),
+        ("hi_F", C.c_void_p), ("n_hi_f", C.c_int64),
+        ("hi_N", C.c_void_p),
+        ("lo_V", C.c_void_p), ("n_lo_v", C.c_int64),
+        ("lo_F", C.c_void_p), ("n_lo_f", C.c_int64),
+        ("lo_UV", C.c_void_p),
+        ("res", C.c_int32), ("max_dist", C.c_float),
+        ("out_map", C.c_void_p), ("out_hit", C.c_void_p), ("out_rgb8", C.c_void_p),
+        ("grad_map", C.c_void_p), ("grad_lo_V", C.c_void_p), ("grad_hi_N", C.c_void_p),
+    ]
+
+
 _lib = None
 
 _EXPORTS = {
@@ -81,6 +98,15 @@ _EXPORTS = {
     "bake_workspace_view": (C.c_int32, [C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_int32,
                                         C.c_void_p, C.c_int32, C.POINTER(C.c_size_t),
                                         C.POINTER(C.c_size_t)]),
+    "bake_batch_workspace_size": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_size_t)]),
+    "bake_normals_batched": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t,
+                                         C.c_void_p]),
+    "bake_normals_batched_backward": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t,
+                                                  C.c_void_p]),
+    "bake_read_asset_counter": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
+                                            C.POINTER(C.c_int64)]),
+    "bake_autotune": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t,
+                                  C.c_void_p, C.c_void_p, C.POINTER(C.c_float)]),
     "bake_stage_times": (C.c_int32, [C.POINTER(C.c_float), C.c_int32]),
     "bake_stage_history": (C.c_int32, [C.POINTER(C.c_float), C.c_int32]),
     "bake_last_error": (C.c_char_p, []),
@@ -238,18 +264,24 @@ def bake_normals(hi_V, hi_F, hi_N, lo_V, lo_F, lo_UV, res: int, max_dist: float,
 
 
 def bake_normals_backward(result: BakeResult, inputs, grad_map, need_lo=True, need_hi=True,
-                          stream=None):
+                          stream=None, out_lo=None, out_hi=None):
     """Gradients of a loss on the pre-dilation map w.r.t. lo_V and hi_N, for a
     forward `result` made with save=True on the same `inputs` (the six tensors
     given to bake_normals, same order).  Returns (grad_lo_V, grad_hi_N); an
-    entry is None when not requested."""
+    entry is None when not requested.  out_lo / out_hi: optional preallocated
+    outputs."""
     hi_V, hi_F, hi_N, lo_V, lo_F, lo_UV = inputs
     res = result.sizes[4]
     g = _dev_tensor(grad_map.contiguous(), torch.float32, "grad_map")
     if tuple(g.shape) != (res, res, 3):
         raise ValueError(f"grad_map must be [{res},{res},3]")
-    glo = torch.empty_like(lo_V) if need_lo else None
-    ghi = torch.empty_like(hi_N) if need_hi else None
+    glo = (out_lo if out_lo is not None else torch.empty_like(lo_V)) if need_lo else None
+    ghi = (out_hi if out_hi is not None else torch.empty_like(hi_N)) if need_hi else None
+    for t, ref, name in ((glo, lo_V, "out_lo"), (ghi, hi_N, "out_hi")):
+        if t is not None:
+            _dev_tensor(t, torch.float32, name)
+            if t.shape != ref.shape:
+                raise ValueError(f"{name} must have shape {tuple(ref.shape)}")
     _check(lib().bake_normals_backward(
         _ptr(hi_V), hi_V.shape[0], _ptr(hi_F), hi_F.shape[0], _ptr(hi_N), _ptr(lo_V), lo_V.shape[0],
         _ptr(lo_F), lo_F.shape[0], _ptr(lo_UV), int(res), float(result.max_dist), _ptr(g), _ptr(glo),
@@ -257,16 +289,19 @@ def bake_normals_backward(result: BakeResult, inputs, grad_map, need_lo=True, ne
     return glo, ghi
 
 
-def sq_loss(map_, target, want_grad=True, stream=None):
-    """(sum (map - target)^2 as a 1-element tensor, 2 (map - target) or None)."""
+def sq_loss(map_, target, want_grad=True, stream=None, out_loss=None, out_grad=None, scratch=None):
+    """(sum (map - target)^2 as a 1-element tensor, 2 (map - target) or None).
+    out_loss / out_grad / scratch: optional preallocated buffers."""
     m = _dev_tensor(map_.contiguous(), torch.float32, "map")
     t = _dev_tensor(target.contiguous(), torch.float32, "target")
     if m.shape != t.shape:
         raise ValueError("map and target shapes differ")
     n = m.numel()
-    loss = torch.empty(1, dtype=torch.float32, device=m.device)
-    grad = torch.empty_like(m) if want_grad else None
-    scratch = torch.empty(4 * ((n + 255) // 256 + 1), dtype=torch.uint8, device=m.device)
+    loss = out_loss if out_loss is not None else torch.empty(1, dtype=torch.float32, device=m.device)
+    grad = (out_grad if out_grad is not None else torch.empty_like(m)) if want_grad else None
+    need = 4 * ((n + 255) // 256 + 1)
+    if scratch is None or scratch.numel() < need:
+        scratch = torch.empty(need, dtype=torch.uint8, device=m.device)
     _check(lib().bake_sq_loss(_ptr(m), _ptr(t), n, _ptr(grad), _ptr(loss), _ptr(scratch),
                               scratch.numel(), _stream_handle(stream)))
     return loss, grad
@@ -295,6 +330,176 @@ class BakeNormals(torch.autograd.Function):
                                          need_lo=ctx.needs_input_grad[0],
                                          need_hi=ctx.needs_input_grad[1])
         return glo, ghi, None, None, None, None, None, None, None
+
+
+class BakeBatch:
+    """Many assets baked by one launch sequence (bake_normals_batched).
+
+    `assets` is a list of (hi_V, hi_F, hi_N, lo_V, lo_F, lo_UV, res, max_dist)
+    with GPU tensors as for bake_normals.  The batch owns its outputs (maps[i],
+    hits[i], rgb8[i]), its gradient buffers (grad_maps[i] in, grad_lo_V[i] /
+    grad_hi_N[i] out) and its workspace, at fixed addresses, so forward() and
+    backward() can be recorded into a CUDA/HIP graph (capture()) and replayed.
+    Every asset's results are bitwise those of a single bake_normals call."""
+
+    def __init__(self, assets, *, save=False, dilate_passes=2, rgb8=False, trav_block=0,
+                 trav_stack=0, trav_persist=-1, need_lo=True, need_hi=True):
+        if not assets:
+            raise ValueError("empty batch")
+        self.inputs = []
+        self.maps, self.hits, self.rgb8 = [], [], []
+        self.grad_maps, self.grad_lo_V, self.grad_hi_N = [], [], []
+        self.n = len(assets)
+        self.save = bool(save)
+        self._arr = (BakeAsset * self.n)()
+        for i, a in enumerate(assets):
+            hi_V, hi_F, hi_N, lo_V, lo_F, lo_UV, res, max_dist = a
+            hi_V = _dev_tensor(hi_V, torch.float32, "hi_V", (3,))
+            hi_F = _dev_tensor(hi_F, torch.int32, "hi_F", (3,))
+            hi_N = _dev_tensor(hi_N, torch.float32, "hi_N", (3,))
+            lo_V = _dev_tensor(lo_V, torch.float32, "lo_V", (3,))
+            lo_F = _dev_tensor(lo_F, torch.int32, "lo_F", (3,))
+            lo_UV = _dev_tensor(lo_UV, torch.float32, "lo_UV", (3, 2))
+            if hi_N.shape[0] != hi_V.shape[0] or lo_UV.shape[0] != lo_F.shape[0]:
+                raise ValueError(f"asset {i}: inconsistent row counts")
+            dev = hi_V.device
+            res = int(res)
+            self.inputs.append((hi_V, hi_F, hi_N, lo_V, lo_F, lo_UV, res, float(max_dist)))
+            m = torch.empty((res, res, 3), dtype=torch.float32, device=dev)
+            h = torch.empty((res, res), dtype=torch.int32, device=dev)
+            r8 = torch.empty((res, res, 3), dtype=torch.uint8, device=dev) if rgb8 else None
+            gm = torch.zeros((res, res, 3), dtype=torch.float32, device=dev) if save else None
+            glo = torch.empty_like(lo_V) if (save and need_lo) else None
+            ghi = torch.empty_like(hi_N) if (save and need_hi) else None
+            self.maps.append(m)
+            self.hits.append(h)
+            self.rgb8.append(r8)
+            self.grad_maps.append(gm)
+            self.grad_lo_V.append(glo)
+            self.grad_hi_N.append(ghi)
+            e = self._arr[i]
+            e.hi_V, e.n_hi_v = hi_V.data_ptr(), hi_V.shape[0]
+            e.hi_F, e.n_hi_f = hi_F.data_ptr(), hi_F.shape[0]
+            e.hi_N = hi_N.data_ptr()
+            e.lo_V, e.n_lo_v = lo_V.data_ptr(), lo_V.shape[0]
+            e.lo_F, e.n_lo_f = lo_F.data_ptr(), lo_F.shape[0]
+            e.lo_UV = lo_UV.data_ptr()
+            e.res, e.max_dist = res, float(max_dist)
+            e.out_map, e.out_hit = m.data_ptr(), h.data_ptr()
+            e.out_rgb8 = r8.data_ptr() if r8 is not None else None
+            e.grad_map = gm.data_ptr() if gm is not None else None
+            e.grad_lo_V = glo.data_ptr() if glo is not None else None
+            e.grad_hi_N = ghi.data_ptr() if ghi is not None else None
+        self.device = self.inputs[0][0].device
+        self.opts = make_options(dilate_passes, save, False, 0, trav_block, trav_stack, trav_persist)
+        b = C.c_size_t(0)
+        _check(lib().bake_batch_workspace_size(self._arr, self.n, C.byref(self.opts), C.byref(b)))
+        self.workspace = torch.empty(b.value, dtype=torch.uint8, device=self.device)
+
+    def set_traversal(self, block=0, stack=0, persist=-1):
+        self.opts.trav_block, self.opts.trav_stack, self.opts.trav_persist = int(block), int(stack), int(persist)
+
+    def forward(self, timing=False, count=False, stream=None):
+        o = BakeOptions.from_buffer_copy(self.opts)
+        o.flags |= (BAKE_FLAG_TIMING if timing else 0) | (BAKE_FLAG_COUNT if count else 0)
+        _check(lib().bake_normals_batched(self._arr, self.n, C.byref(o), _ptr(self.workspace),
+                                          self.workspace.numel(), _stream_handle(stream)))
+
+    def backward(self, stream=None):
+        """Gradients from grad_maps[i] into grad_lo_V[i] / grad_hi_N[i] (needs save=True)."""
+        if not self.save:
+            raise BakeError(BAKE_E_STATE, "batch was made without save=True")
+        _check(lib().bake_normals_batched_backward(self._arr, self.n, _ptr(self.workspace),
+                                                   self.workspace.numel(), _stream_handle(stream)))
+
+    def capture(self, backward=None):
+        """Record forward (+ backward when the batch saves) into a CUDA graph;
+        returns the torch.cuda.CUDAGraph (replay() runs the whole batch)."""
+        backward = self.save if backward is None else backward
+        s = torch.cuda.Stream(device=self.device)
+        s.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(s):
+            self.forward()
+            if backward:
+                self.backward()
+        torch.cuda.current_stream(self.device).wait_stream(s)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            self.forward()
+            if backward:
+                self.backward()
+        return g
+
+    def counter(self, asset: int, which: int, stream=None) -> int:
+        v = C.c_int64(0)
+        _check(lib().bake_read_asset_counter(_ptr(self.workspace), int(asset), int(which),
+                                             _stream_handle(stream), C.byref(v)))
+        return v.value
+
+    def ray_counts(self, stream=None):
+        return [self.counter(i, 0, stream) for i in range(self.n)]
+
+    def status(self, stream=None) -> int:
+        v = C.c_uint32(0)
+        _check(lib().bake_query_status(_ptr(self.workspace), _stream_handle(stream), C.byref(v)))
+        return v.value
+
+    def size_class(self) -> str:
+        """Key of the autotuner cache: asset count and the rounded log2 of the
+        batch's texel and high-poly triangle totals."""
+        import math
+        tex = sum(a[6] * a[6] for a in self.inputs)
+        tri = sum(a[1].shape[0] for a in self.inputs)
+        return f"n{self.n}-tex2^{round(math.log2(max(tex, 1)))}-tri2^{round(math.log2(max(tri, 1)))}"
+
+
+TRAV_CONFIGS = [(b, s, p) for b in (64, 128, 256) for s in (8, 16, 32) for p in (0, 1)]
+
+
+def autotune(batch: BakeBatch, reps: int = 3, cache_path: Optional[str] = None, stream=None) -> dict:
+    """Time every traversal configuration on `batch` (bake_autotune), set the
+    fastest on the batch and, with cache_path, store it in the JSON cache under
+    the batch's size class.  Returns {"block", "stack", "persist", "ms": {...}}."""
+    import json
+    best = BakeOptions()
+    ms = (C.c_float * len(TRAV_CONFIGS))()
+    _check(lib().bake_autotune(batch._arr, batch.n, C.byref(batch.opts), int(reps), _ptr(batch.workspace),
+                               batch.workspace.numel(), _stream_handle(stream), C.byref(best), ms))
+    out = {"block": best.trav_block, "stack": best.trav_stack, "persist": best.trav_persist,
+           "ms": {f"{b}/{s}/{p}": float(ms[i]) for i, (b, s, p) in enumerate(TRAV_CONFIGS)}}
+    batch.set_traversal(best.trav_block, best.trav_stack, best.trav_persist)
+    if cache_path:
+        cache = {}
+        if os.path.exists(cache_path):
+            with open(cache_path) as f:
+                cache = json.load(f)
+        cache[batch.size_class()] = out
+        tmp = cache_path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, cache_path)
+    return out
+
+
+def apply_tuning(batch: BakeBatch, cache_path: str) -> bool:
+    """Set the cached traversal configuration of the batch's size class, if any."""
+    import json
+    if not os.path.exists(cache_path):
+        return False
+    with open(cache_path) as f:
+        e = json.load(f).get(batch.size_class())
+    if not e:
+        return False
+    batch.set_traversal(e["block"], e["stack"], e["persist"])
+    return True
+
+
+def bake_batched(assets, **kw) -> BakeBatch:
+    """Bake a list of assets in one launch sequence; returns the BakeBatch
+    (maps / hits per asset)."""
+    b = BakeBatch(assets, **kw)
+    b.forward()
+    return b
 
 
 def stage_times() -> dict:

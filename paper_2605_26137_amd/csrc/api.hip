@@ -1,15 +1,19 @@
-// C ABI of the normal baker: host-side argument validation, workspace carving
-// and the stream-ordered launch sequence of the bake (Sec. 6.4):
+// C ABI of the normal baker: host-side argument validation, the batch plan
+// (asset table, per-grid block prefix tables, workspace carving) and the
+// stream-ordered launch sequence of the bake (Sec. 6.4):
 //   low-poly prep -> UV raster (G-buffer) -> uncovered fill -> LBVH build ->
-//   traversal + encode -> dilation -> optional RGB8.
-// No device memory is allocated here; all scratch lives in the caller's
-// workspace, and nothing synchronises except the explicit query calls.
+//   traversal + encode -> dilation -> optional RGB8,
+// and of its backward.  A single bake is a batch of one asset.  No device
+// memory is allocated here; all scratch lives in the caller's workspace, the
+// asset table reaches the device as kernel arguments, and nothing
+// synchronises except the explicit query, timing and tuning calls.
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
 #include <mutex>
+#include <vector>
 
 #include "../../include/bake.h"
 #include "internal.h"
@@ -38,8 +42,10 @@ int32_t fail(int32_t code, const char* fmt, ...) {
 
 constexpr int64_t kMaxLanes = 256 * 2560;  // upper bound on resident traversal lanes
 constexpr int64_t kMaxCount = (int64_t)1 << 30;
+constexpr int kMaxAssets = 65536;
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 struct Opts {
     int dilate;
@@ -79,109 +85,274 @@ int32_t parse_opts(const bake_options* o, Opts* out) {
     return BAKE_OK;
 }
 
-int32_t check_sizes(int64_t nhv, int64_t nhf, int64_t nlv, int64_t nlf, int32_t res) {
-    if (nhv < 0 || nhf < 0 || nlv < 0 || nlf < 0)
+struct Sizes {
+    int64_t nhv, nhf, nlv, nlf;
+    int32_t res;
+};
+
+int32_t check_sizes(const Sizes& z) {
+    if (z.nhv < 0 || z.nhf < 0 || z.nlv < 0 || z.nlf < 0)
         return fail(BAKE_E_INVALID_ARG, "negative count");
-    if (nhv >= kMaxCount || nhf >= kMaxCount || nlv >= kMaxCount || nlf >= kMaxCount)
+    if (z.nhv >= kMaxCount || z.nhf >= kMaxCount || z.nlv >= kMaxCount || z.nlf >= kMaxCount)
         return fail(BAKE_E_UNSUPPORTED, "counts must be < 2^30");
-    if (nhf > 0 && nhv == 0) return fail(BAKE_E_INVALID_ARG, "hi triangles without hi vertices");
-    if (nlf > 0 && nlv == 0) return fail(BAKE_E_INVALID_ARG, "lo triangles without lo vertices");
-    if (res < 1 || res > 16384 || (res & (res - 1)) != 0)
-        return fail(BAKE_E_UNSUPPORTED, "res %d must be a power of two in [1, 16384]", res);
+    if (z.nhf > 0 && z.nhv == 0) return fail(BAKE_E_INVALID_ARG, "hi triangles without hi vertices");
+    if (z.nlf > 0 && z.nlv == 0) return fail(BAKE_E_INVALID_ARG, "lo triangles without lo vertices");
+    if (z.res < 1 || z.res > 16384 || (z.res & (z.res - 1)) != 0)
+        return fail(BAKE_E_UNSUPPORTED, "res %d must be a power of two in [1, 16384]", z.res);
     return BAKE_OK;
 }
 
-Layout make_layout(int64_t nhv, int64_t nhf, int64_t nlv, int64_t nlf, int32_t res, uint32_t flags) {
-    (void)nhv;
+// Blocks of grid g for one asset.
+int64_t grid_blocks(int g, const Sizes& z) {
+    const int64_t tex = (int64_t)z.res * z.res;
+    switch (g) {
+        case kGLoF: return cdiv(z.nlf, 256);
+        case kGLoFWave: return cdiv(z.nlf, 4);
+        case kGLoV: return cdiv(z.nlv, 256);
+        case kGHiV: return cdiv(z.nhv, 256);
+        case kGHiF: return cdiv(z.nhf, 256);
+        case kGNode: return cdiv(std::max<int64_t>(z.nhf - 1, 0), 256);
+        case kGAllNode: return cdiv(std::max<int64_t>(2 * z.nhf - 1, 0), 256);
+        case kGSort: return cdiv(z.nhf, kSortTile);
+        case kGTex: return cdiv(tex, 256);
+        case kGTex3: return cdiv(3 * tex, 256);
+        case kGBwdSort: return cdiv(3 * tex, kSortTile);
+    }
+    return 0;
+}
+
+// The batch plan: asset table (pointers filled by the caller), grid prefix
+// tables and the workspace layout.
+struct Plan {
     Layout L;
+    std::vector<AssetDev> A;
+    std::vector<AssetGrad> G;
+    std::vector<int32_t> gpf;  // [kGridCount][n + 1]
+    uint64_t sig = 0;          // signature of the batch's sizes
+};
+
+int32_t make_plan(const Sizes* z, int n, uint32_t flags, Plan* P) {
+    if (n < 1 || n > kMaxAssets) return fail(BAKE_E_INVALID_ARG, "n_assets %d outside [1, %d]", n, kMaxAssets);
+    Layout& L = P->L;
     memset(&L, 0, sizeof L);
+    L.n = n;
+    L.save = (flags & BAKE_FLAG_SAVE) != 0;
+    P->A.assign(n, AssetDev{});
+    P->gpf.assign((size_t)kGridCount * (n + 1), 0);
+    uint64_t sig = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) { sig = (sig ^ v) * 1099511628211ull; };
+    mix((uint64_t)n);
+    int64_t gsum[kGridCount] = {};
+    int64_t max_hv = 0;
+    for (int a = 0; a < n; ++a) {
+        int32_t rc = check_sizes(z[a]);
+        if (rc) return rc;
+        AssetDev& d = P->A[a];
+        d.nhv = (int32_t)z[a].nhv;
+        d.nhf = (int32_t)z[a].nhf;
+        d.nlv = (int32_t)z[a].nlv;
+        d.nlf = (int32_t)z[a].nlf;
+        d.res = z[a].res;
+        d.log2res = 0;
+        while ((1 << d.log2res) < d.res) ++d.log2res;
+        d.index = a;
+        d.lv = L.t_lv;
+        d.lf = L.t_lf;
+        d.hf = L.t_hf;
+        d.node = L.t_node;
+        d.tex = L.t_tex;
+        d.stile = L.t_stile;
+        d.btile = L.t_btile;
+        d.tl = L.t_tl;
+        const int64_t tex = (int64_t)z[a].res * z[a].res;
+        L.t_lv += z[a].nlv;
+        L.t_lf += z[a].nlf;
+        L.t_hv += z[a].nhv;
+        L.t_hf += z[a].nhf;
+        L.t_node += std::max<int64_t>(z[a].nhf - 1, 0);
+        L.t_tex += tex;
+        L.t_stile += cdiv(z[a].nhf, kSortTile);
+        L.t_btile += cdiv(3 * tex, kSortTile);
+        L.t_tl += treelet_cap(z[a].nhf);
+        max_hv = std::max(max_hv, z[a].nhv);
+        for (int g = 0; g < kGridCount; ++g) {
+            P->gpf[(size_t)g * (n + 1) + a] = (int32_t)gsum[g];
+            gsum[g] += grid_blocks(g, z[a]);
+        }
+        mix((uint64_t)z[a].nhv);
+        mix((uint64_t)z[a].nhf);
+        mix((uint64_t)z[a].nlv);
+        mix((uint64_t)z[a].nlf);
+        mix((uint64_t)z[a].res);
+    }
+    for (int g = 0; g < kGridCount; ++g) {
+        if (gsum[g] >= ((int64_t)1 << 31)) return fail(BAKE_E_UNSUPPORTED, "batch too large (grid %d)", g);
+        P->gpf[(size_t)g * (n + 1) + n] = (int32_t)gsum[g];
+    }
+    if (L.t_hf >= ((int64_t)1 << 31) || 3 * L.t_tex >= ((int64_t)1 << 32) || L.t_lv >= ((int64_t)1 << 31) ||
+        L.t_lf >= ((int64_t)1 << 31))
+        return fail(BAKE_E_UNSUPPORTED, "batch too large: needs sum(n_hi_f) < 2^31 and 3 sum(res^2) < 2^32");
+    L.max_hv_bits = 1;
+    while (L.max_hv_bits < 32 && ((int64_t)1 << L.max_hv_bits) <= max_hv) ++L.max_hv_bits;  // keys in [0, nhv]
+    P->sig = sig ^ (L.save ? 0x5A5Aull : 0ull);
+
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
         off += align256(bytes);
         return o;
     };
-    L.n_texels = (int64_t)res * res;
-    L.max_rays = L.n_texels;
-    L.sort_blocks = (nhf + 4095) / 4096;
-    int64_t scan_n = std::max<int64_t>(std::max<int64_t>(nlv, nlf), 256 * L.sort_blocks);
-    if (flags & BAKE_FLAG_SAVE) scan_n = std::max<int64_t>(scan_n, radix_hist_elems(3 * L.max_rays));
+    int64_t scan_n = std::max<int64_t>(std::max<int64_t>(L.t_lv, L.t_lf), 256 * L.t_stile);
+    if (L.save) scan_n = std::max<int64_t>(scan_n, 256 * L.t_btile);
     L.scan_tmp_n = scan_tmp_elems(scan_n) + 1;
-    int64_t lanes = std::min<int64_t>(std::max<int64_t>(L.max_rays, 256), kMaxLanes);
+    int64_t lanes = std::min<int64_t>(std::max<int64_t>(L.t_tex, 256), kMaxLanes);
     L.spill_lanes = (lanes + 255) / 256 * 256;
 
-    L.status = take(4);
-    L.counters = take(4 * kCntSlots);
-    L.lo_n = take(16 * (size_t)nlv);
-    L.lo_deg = take(4 * (size_t)nlv);
-    L.lo_off = take(4 * (size_t)(nlv + 1));
-    L.lo_cur = take(4 * (size_t)nlv);
-    L.lo_adj = take(12 * (size_t)nlf);
-    L.face_t = take(16 * (size_t)nlf);
-    L.face_uv = take(32 * (size_t)nlf);
-    L.face_cnt = take(4 * (size_t)nlf);
-    L.face_off = take(4 * (size_t)(nlf + 1));
+    L.status = take(4);  // the status block is 256 bytes: counters start at 256
+    L.counters = take(4 * (size_t)kCntSlots * n);
+    L.gcnt = take(4 * (size_t)kGcSlots);
+    L.table = take(sizeof(AssetDev) * (size_t)n + 4 * (size_t)kGridCount * (n + 1));
+    L.gpf = L.table + sizeof(AssetDev) * (size_t)n;
+    L.grads = take(sizeof(AssetGrad) * (size_t)n);
+    L.ray_pf = take(4 * (size_t)(n + 1));
+    L.rb_pf = take(4 * (size_t)(n + 1));
+    L.tl_pf = take(4 * (size_t)(n + 1));
+    L.lo_n = take(16 * (size_t)L.t_lv);
+    L.lo_deg = take(4 * (size_t)L.t_lv);
+    L.lo_off = take(4 * (size_t)(L.t_lv + 1));
+    L.lo_cur = take(4 * (size_t)L.t_lv);
+    L.lo_adj = take(12 * (size_t)L.t_lf);
+    L.face_t = take(16 * (size_t)L.t_lf);
+    L.face_uv = take(32 * (size_t)L.t_lf);
+    L.face_cnt = take(4 * (size_t)L.t_lf);
+    L.face_off = take(4 * (size_t)(L.t_lf + 1));
     L.scan_tmp = take(4 * (size_t)L.scan_tmp_n);
-    L.facemap = take(4 * (size_t)L.n_texels);
-    L.level = take((size_t)L.n_texels);
-    L.rays = take(16 * (size_t)L.max_rays);
-    L.hits = (flags & BAKE_FLAG_SAVE) ? take(16 * (size_t)L.max_rays) : off;
-    L.bounds_part = take(4 * 6 * 512);
-    L.bounds = take(4 * 6);
-    L.keys0 = take(4 * (size_t)nhf);
-    L.vals0 = take(4 * (size_t)nhf);
-    L.keys1 = take(4 * (size_t)nhf);
-    L.vals1 = take(4 * (size_t)nhf);
-    L.hist = take(4 * 256 * (size_t)L.sort_blocks);
-    L.nodes = take(64 * (size_t)std::max<int64_t>(nhf - 1, 1));
-    L.leaves = take(48 * (size_t)std::max<int64_t>(nhf, 1));
-    L.node_parent = take(4 * (size_t)std::max<int64_t>(nhf - 1, 1));
-    L.leaf_parent = take(4 * (size_t)std::max<int64_t>(nhf, 1));
-    L.refit_cnt = take(4 * (size_t)std::max<int64_t>(nhf - 1, 1));
-    L.node_range = take(8 * (size_t)std::max<int64_t>(nhf - 1, 1));
-    L.frontier = take(4 * (size_t)treelet_cap(nhf));
-    L.treelets = take(16 * (size_t)treelet_cap(nhf));
+    L.facemap = take(4 * (size_t)L.t_tex);
+    L.level = take((size_t)L.t_tex);
+    L.rays = take(16 * (size_t)L.t_tex);
+    L.hits = L.save ? take(16 * (size_t)L.t_tex) : off;
+    L.bounds_part = take(24 * (size_t)L.t_stile);
+    L.bounds = take(24 * (size_t)n);
+    L.keys0 = take(4 * (size_t)L.t_hf);
+    L.vals0 = take(4 * (size_t)L.t_hf);
+    L.keys1 = take(4 * (size_t)L.t_hf);
+    L.vals1 = take(4 * (size_t)L.t_hf);
+    L.hist = take(4 * 256 * (size_t)L.t_stile);
+    L.nodes = take(64 * (size_t)L.t_node);
+    L.leaves = take(48 * (size_t)L.t_hf);
+    L.node_parent = take(4 * (size_t)L.t_node);
+    L.leaf_parent = take(4 * (size_t)L.t_hf);
+    L.refit_cnt = take(4 * (size_t)L.t_node);
+    L.node_range = take(8 * (size_t)L.t_node);
+    L.frontier = take(4 * (size_t)L.t_tl);
+    L.treelets = take(16 * (size_t)L.t_tl);
     L.spill = take(4 * (size_t)kMaxDepth * (size_t)L.spill_lanes);
-    if (flags & BAKE_FLAG_SAVE) {
-        const size_t items = 3 * (size_t)L.max_rays;
-        L.bwd_ray = take(48 * (size_t)L.max_rays);
+    if (L.save) {
+        const size_t items = 3 * (size_t)L.t_tex;
+        L.bwd_ray = take(48 * (size_t)L.t_tex);
         L.bwd_k0 = take(4 * items);
         L.bwd_v0 = take(4 * items);
         L.bwd_k1 = take(4 * items);
         L.bwd_v1 = take(4 * items);
-        L.bwd_hist = take(4 * (size_t)radix_hist_elems((int64_t)items));
-        L.bwd_face1 = take(72 * (size_t)nlf);
-        L.bwd_face2 = take(36 * (size_t)nlf);
-        L.bwd_sbar = take(12 * (size_t)nlv);
-        L.bwd_vbar = take(12 * (size_t)nlv);
+        L.bwd_hist = take(4 * 256 * (size_t)L.t_btile);
+        L.bwd_face1 = take(72 * (size_t)L.t_lf);
+        L.bwd_face2 = take(36 * (size_t)L.t_lf);
+        L.bwd_sbar = take(12 * (size_t)L.t_lv);
+        L.bwd_vbar = take(12 * (size_t)L.t_lv);
     }
     L.total = off;
-    return L;
+    return BAKE_OK;
+}
+
+Sizes sizes_of(const bake_asset& a) { return Sizes{a.n_hi_v, a.n_hi_f, a.n_lo_v, a.n_lo_f, a.res}; }
+
+int32_t plan_batch(const bake_asset* as, int32_t n, uint32_t flags, Plan* P) {
+    if (!as) return fail(BAKE_E_INVALID_ARG, "assets is NULL");
+    if (n < 1 || n > kMaxAssets) return fail(BAKE_E_INVALID_ARG, "n_assets %d outside [1, %d]", n, kMaxAssets);
+    std::vector<Sizes> z(n);
+    for (int a = 0; a < n; ++a) z[a] = sizes_of(as[a]);
+    return make_plan(z.data(), n, flags, P);
+}
+
+int32_t validate_asset(const bake_asset& a, int idx) {
+    if (a.n_hi_v > 0 && (!a.hi_V || !a.hi_N))
+        return fail(BAKE_E_INVALID_ARG, "asset %d: hi_V / hi_N is NULL", idx);
+    if (a.n_hi_f > 0 && !a.hi_F) return fail(BAKE_E_INVALID_ARG, "asset %d: hi_F is NULL", idx);
+    if (a.n_lo_v > 0 && !a.lo_V) return fail(BAKE_E_INVALID_ARG, "asset %d: lo_V is NULL", idx);
+    if (a.n_lo_f > 0 && (!a.lo_F || !a.lo_UV))
+        return fail(BAKE_E_INVALID_ARG, "asset %d: lo_F / lo_UV is NULL", idx);
+    if (!(a.max_dist > 0.f) || !(a.max_dist < INFINITY))
+        return fail(BAKE_E_INVALID_ARG, "asset %d: max_dist must be finite and > 0", idx);
+    return BAKE_OK;
+}
+
+void fill_pointers(const bake_asset* as, Plan* P) {
+    for (int a = 0; a < P->L.n; ++a) {
+        AssetDev& d = P->A[a];
+        d.hi_V = as[a].hi_V;
+        d.hi_F = as[a].hi_F;
+        d.hi_N = as[a].hi_N;
+        d.lo_V = as[a].lo_V;
+        d.lo_F = as[a].lo_F;
+        d.lo_UV = as[a].lo_UV;
+        d.out_map = as[a].out_map;
+        d.out_hit = as[a].out_hit;
+        d.out_rgb8 = as[a].out_rgb8;
+        d.max_dist = as[a].max_dist;
+    }
+    P->G.assign(P->L.n, AssetGrad{});
+    for (int a = 0; a < P->L.n; ++a) P->G[a] = AssetGrad{as[a].grad_map, as[a].grad_lo_V, as[a].grad_hi_N};
+}
+
+BatchHost host_view(const Plan& P, char* ws) {
+    BatchHost H;
+    H.L = P.L;
+    H.A = P.A.data();
+    H.gpf = P.gpf.data();
+    H.ws = ws;
+    const Layout& L = P.L;
+    H.dev.A = (const AssetDev*)(ws + L.table);
+    H.dev.G = (const AssetGrad*)(ws + L.grads);
+    H.dev.gpf = (const int32_t*)(ws + L.gpf);
+    H.dev.ray_pf = (const uint32_t*)(ws + L.ray_pf);
+    H.dev.rb_pf = (const uint32_t*)(ws + L.rb_pf);
+    H.dev.tl_pf = (const uint32_t*)(ws + L.tl_pf);
+    H.dev.cnt = (uint32_t*)(ws + L.counters);
+    H.dev.gcnt = (uint32_t*)(ws + L.gcnt);
+    H.dev.status = (uint32_t*)(ws + L.status);
+    H.dev.n = L.n;
+    H.dev.seal = 0;
+    return H;
 }
 
 // ---- forwards that saved their state (for the backward pass) ---------------
-// Host-side record of the last saved forwards, keyed by workspace, so a
-// backward call can check it matches a saved forward of the same sizes.  It
-// is process-wide (autograd may run the backward on another thread).
+// Process-wide record of the last saved forwards, keyed by workspace, so a
+// backward call can check it matches a saved forward of the same batch sizes
+// (autograd may run the backward on another thread).
 struct Saved {
     const void* ws;
-    int64_t nhv, nhf, nlv, nlf;
-    int32_t res;
+    uint64_t sig;
+    uint32_t nonce;
 };
 constexpr int kSavedSlots = 64;
 std::mutex g_saved_mu;
 Saved g_saved[kSavedSlots];
 int g_saved_next = 0;
+uint32_t g_nonce = 0;
 
-void remember_saved(const void* ws, int64_t nhv, int64_t nhf, int64_t nlv, int64_t nlf, int32_t res) {
+// Registers a saved forward and returns the nonce it leaves in the workspace.
+uint32_t remember_saved(const void* ws, uint64_t sig) {
     std::lock_guard<std::mutex> lk(g_saved_mu);
+    if (++g_nonce == 0) g_nonce = 1;  // 0 marks a forward in flight
     for (int i = 0; i < kSavedSlots; ++i)
         if (g_saved[i].ws == ws) {
-            g_saved[i] = Saved{ws, nhv, nhf, nlv, nlf, res};
-            return;
+            g_saved[i].sig = sig;
+            g_saved[i].nonce = g_nonce;
+            return g_nonce;
         }
-    g_saved[g_saved_next] = Saved{ws, nhv, nhf, nlv, nlf, res};
+    g_saved[g_saved_next] = Saved{ws, sig, g_nonce};
     g_saved_next = (g_saved_next + 1) % kSavedSlots;
+    return g_nonce;
 }
 
 void forget_saved(const void* ws) {
@@ -190,13 +361,13 @@ void forget_saved(const void* ws) {
         if (g_saved[i].ws == ws) g_saved[i].ws = nullptr;
 }
 
-bool was_saved(const void* ws, int64_t nhv, int64_t nhf, int64_t nlv, int64_t nlf, int32_t res) {
+bool was_saved(const void* ws, uint64_t sig, uint32_t* nonce) {
     std::lock_guard<std::mutex> lk(g_saved_mu);
-    for (int i = 0; i < kSavedSlots; ++i) {
-        const Saved& v = g_saved[i];
-        if (v.ws == ws && ws != nullptr)
-            return v.nhv == nhv && v.nhf == nhf && v.nlv == nlv && v.nlf == nlf && v.res == res;
-    }
+    for (int i = 0; i < kSavedSlots; ++i)
+        if (g_saved[i].ws == ws && ws != nullptr) {
+            *nonce = g_saved[i].nonce;
+            return g_saved[i].sig == sig;
+        }
     return false;
 }
 
@@ -247,25 +418,103 @@ int32_t slot_times(int r, float* ms) {
     return BAKE_OK;
 }
 
-int32_t validate_common(const float* hi_V, int64_t nhv, const int32_t* hi_F, int64_t nhf,
-                        const float* hi_N, const float* lo_V, int64_t nlv, const int32_t* lo_F,
-                        int64_t nlf, const float* lo_UV, int32_t res, float max_dist) {
-    int32_t rc = check_sizes(nhv, nhf, nlv, nlf, res);
-    if (rc) return rc;
-    if (nhv > 0 && (!hi_V || !hi_N)) return fail(BAKE_E_INVALID_ARG, "hi_V / hi_N is NULL");
-    if (nhf > 0 && !hi_F) return fail(BAKE_E_INVALID_ARG, "hi_F is NULL");
-    if (nlv > 0 && !lo_V) return fail(BAKE_E_INVALID_ARG, "lo_V is NULL");
-    if (nlf > 0 && (!lo_F || !lo_UV)) return fail(BAKE_E_INVALID_ARG, "lo_F / lo_UV is NULL");
-    if (!(max_dist > 0.f) || !(max_dist < INFINITY))
-        return fail(BAKE_E_INVALID_ARG, "max_dist must be finite and > 0");
-    return BAKE_OK;
-}
-
 int32_t check_workspace(const void* ws, size_t bytes, const Layout& L) {
     if (!ws) return fail(BAKE_E_WORKSPACE, "workspace is NULL");
     if (((uintptr_t)ws & 255) != 0) return fail(BAKE_E_WORKSPACE, "workspace not 256-byte aligned");
     if (bytes < L.total)
         return fail(BAKE_E_WORKSPACE, "workspace has %zu bytes, needs %zu", bytes, L.total);
+    return BAKE_OK;
+}
+
+// The forward launch sequence of a planned batch.
+int32_t run_forward(Plan& P, const Opts& o, void* workspace, hipStream_t s) {
+    char* ws = (char*)workspace;
+    BatchHost H = host_view(P, ws);
+    const Layout& L = P.L;
+    const bool tim = (o.flags & BAKE_FLAG_TIMING) != 0;
+    HIP_OR_FAIL(tim_record(tim, 0, s));
+    // asset table + grid tables (one blob), then status, counters and batch
+    // counters (contiguous from offset 0) to zero
+    std::vector<char> blob(L.grads - L.table, 0);
+    memcpy(blob.data(), P.A.data(), sizeof(AssetDev) * (size_t)L.n);
+    memcpy(blob.data() + (L.gpf - L.table), P.gpf.data(), 4 * P.gpf.size());
+    HIP_OR_FAIL(write_table(ws + L.table, blob.data(), (L.gpf - L.table) + 4 * P.gpf.size(), s));
+    HIP_OR_FAIL(fill_u32((uint32_t*)ws, 0, (int64_t)(L.table / 4), s));
+    HIP_OR_FAIL(launch_lo_prep(H, s));
+    HIP_OR_FAIL(tim_record(tim, 1, s));
+    HIP_OR_FAIL(launch_raster(H, s));
+    HIP_OR_FAIL(launch_fill_uncovered(H, s));
+    HIP_OR_FAIL(tim_record(tim, 2, s));
+    HIP_OR_FAIL(launch_bvh_build(H, s));
+    HIP_OR_FAIL(tim_record(tim, 3, s));
+    TravConfig tc = o.trav;
+    tc.count = (o.flags & BAKE_FLAG_COUNT) != 0;
+    HIP_OR_FAIL(launch_traverse(H, tc, s));
+    HIP_OR_FAIL(tim_record(tim, 4, s));
+    HIP_OR_FAIL(launch_dilate(H, o.dilate, s));
+    bool any_rgb8 = false;
+    for (int a = 0; a < L.n; ++a) any_rgb8 = any_rgb8 || P.A[a].out_rgb8 != nullptr;
+    if (any_rgb8) HIP_OR_FAIL(launch_rgb8(H, s));
+    if (o.flags & BAKE_FLAG_SAVE) {
+        // seal the saved state: the backward checks this nonce on the device
+        const uint32_t nonce = remember_saved(workspace, P.sig);
+        HIP_OR_FAIL(fill_u32(H.dev.gcnt + kGcSeal, nonce, 1, s));
+    } else {
+        forget_saved(workspace);
+    }
+    HIP_OR_FAIL(tim_record(tim, 5, s));
+    tim_commit(tim);
+    return BAKE_OK;
+}
+
+int32_t run_backward(Plan& P, void* workspace, uint32_t nonce, hipStream_t s) {
+    char* ws = (char*)workspace;
+    BatchHost H = host_view(P, ws);
+    H.dev.seal = nonce;
+    bool any_lo = false, any_hi = false;
+    for (int a = 0; a < P.L.n; ++a) {
+        any_lo = any_lo || P.G[a].grad_lo_V != nullptr;
+        any_hi = any_hi || P.G[a].grad_hi_N != nullptr;
+    }
+    if (!any_lo && !any_hi) return BAKE_OK;
+    HIP_OR_FAIL(write_table(ws + P.L.grads, P.G.data(), sizeof(AssetGrad) * (size_t)P.L.n, s));
+    HIP_OR_FAIL(launch_backward(H, any_lo, any_hi, s));
+    return BAKE_OK;
+}
+
+bake_asset single_asset(const float* hi_V, int64_t n_hi_v, const int32_t* hi_F, int64_t n_hi_f,
+                        const float* hi_N, const float* lo_V, int64_t n_lo_v, const int32_t* lo_F,
+                        int64_t n_lo_f, const float* lo_UV, int32_t res, float max_dist) {
+    bake_asset a;
+    memset(&a, 0, sizeof a);
+    a.hi_V = hi_V;
+    a.n_hi_v = n_hi_v;
+    a.hi_F = hi_F;
+    a.n_hi_f = n_hi_f;
+    a.hi_N = hi_N;
+    a.lo_V = lo_V;
+    a.n_lo_v = n_lo_v;
+    a.lo_F = lo_F;
+    a.n_lo_f = n_lo_f;
+    a.lo_UV = lo_UV;
+    a.res = res;
+    a.max_dist = max_dist;
+    return a;
+}
+
+int32_t read_counter_at(const void* workspace, int32_t asset, int32_t which, void* stream, int64_t* value_out) {
+    if (!workspace || !value_out) return fail(BAKE_E_INVALID_ARG, "NULL argument");
+    if (which < 0 || which > 2) return fail(BAKE_E_INVALID_ARG, "unknown counter %d", which);
+    if (asset < 0 || asset >= kMaxAssets) return fail(BAKE_E_INVALID_ARG, "asset %d out of range", asset);
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t v[kCntSlots];
+    // per-asset counters start right after the 256-byte status block
+    HIP_OR_FAIL(hipMemcpyAsync(v, (const char*)workspace + 256 + 4 * (size_t)kCntSlots * asset, sizeof v,
+                               hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    if (which == 0) *value_out = v[kCntRays];
+    else if (which == 1) *value_out = (int64_t)v[kCntBoxLo] | ((int64_t)v[kCntBoxLo + 1] << 32);
+    else *value_out = (int64_t)v[kCntTriLo] | ((int64_t)v[kCntTriLo + 1] << 32);
     return BAKE_OK;
 }
 
@@ -282,7 +531,7 @@ void bake_default_options(bake_options* opt) {
 
 const char* bake_last_error(void) { return g_err; }
 
-const char* bake_version(void) { return "paper_2605_26137_amd bake 0.1 (gfx950)"; }
+const char* bake_version(void) { return "paper_2605_26137_amd bake 0.2 (gfx950)"; }
 
 int32_t bake_workspace_size(int64_t n_hi_v, int64_t n_hi_f, int64_t n_lo_v, int64_t n_lo_f,
                             int32_t res, const bake_options* opt, size_t* bytes_out) {
@@ -291,8 +540,10 @@ int32_t bake_workspace_size(int64_t n_hi_v, int64_t n_hi_f, int64_t n_lo_v, int6
     Opts o;
     int32_t rc = parse_opts(opt, &o);
     if (rc) return rc;
-    if ((rc = check_sizes(n_hi_v, n_hi_f, n_lo_v, n_lo_f, res))) return rc;
-    *bytes_out = make_layout(n_hi_v, n_hi_f, n_lo_v, n_lo_f, res, o.flags).total;
+    Sizes z{n_hi_v, n_hi_f, n_lo_v, n_lo_f, res};
+    Plan P;
+    if ((rc = make_plan(&z, 1, o.flags, &P))) return rc;
+    *bytes_out = P.L.total;
     return BAKE_OK;
 }
 
@@ -304,14 +555,17 @@ int32_t bake_workspace_view(int64_t n_hi_v, int64_t n_hi_f, int64_t n_lo_v, int6
     Opts o;
     int32_t rc = parse_opts(opt, &o);
     if (rc) return rc;
-    if ((rc = check_sizes(n_hi_v, n_hi_f, n_lo_v, n_lo_f, res))) return rc;
-    Layout L = make_layout(n_hi_v, n_hi_f, n_lo_v, n_lo_f, res, o.flags);
+    Sizes z{n_hi_v, n_hi_f, n_lo_v, n_lo_f, res};
+    Plan P;
+    if ((rc = make_plan(&z, 1, o.flags, &P))) return rc;
+    const Layout& L = P.L;
+    const size_t tex = (size_t)res * res;
     switch (which) {
-        case BAKE_VIEW_RAYS: *offset_out = L.rays; *bytes_out = 16 * (size_t)L.max_rays; break;
+        case BAKE_VIEW_RAYS: *offset_out = L.rays; *bytes_out = 16 * tex; break;
         case BAKE_VIEW_HITS:
             if (!(o.flags & BAKE_FLAG_SAVE)) return fail(BAKE_E_INVALID_ARG, "hits need BAKE_FLAG_SAVE");
-            *offset_out = L.hits; *bytes_out = 16 * (size_t)L.max_rays; break;
-        case BAKE_VIEW_FACEMAP: *offset_out = L.facemap; *bytes_out = 4 * (size_t)L.n_texels; break;
+            *offset_out = L.hits; *bytes_out = 16 * tex; break;
+        case BAKE_VIEW_FACEMAP: *offset_out = L.facemap; *bytes_out = 4 * tex; break;
         case BAKE_VIEW_LO_N: *offset_out = L.lo_n; *bytes_out = 16 * (size_t)n_lo_v; break;
         case BAKE_VIEW_SORTED: *offset_out = L.keys0; *bytes_out = 8 * (size_t)n_hi_f; break;
         case BAKE_VIEW_NODES:
@@ -332,40 +586,18 @@ int32_t bake_normals(const float* hi_V, int64_t n_hi_v, const int32_t* hi_F, int
     Opts o;
     int32_t rc = parse_opts(opt, &o);
     if (rc) return rc;
-    if ((rc = validate_common(hi_V, n_hi_v, hi_F, n_hi_f, hi_N, lo_V, n_lo_v, lo_F, n_lo_f, lo_UV,
-                              res, max_dist)))
-        return rc;
+    bake_asset a = single_asset(hi_V, n_hi_v, hi_F, n_hi_f, hi_N, lo_V, n_lo_v, lo_F, n_lo_f, lo_UV, res,
+                                max_dist);
+    a.out_map = out_map;
+    a.out_hit = out_hit;
+    a.out_rgb8 = o.rgb8;
+    Plan P;
+    if ((rc = plan_batch(&a, 1, o.flags, &P))) return rc;
+    if ((rc = validate_asset(a, 0))) return rc;
     if (!out_map || !out_hit) return fail(BAKE_E_INVALID_ARG, "out_map / out_hit is NULL");
-    Layout L = make_layout(n_hi_v, n_hi_f, n_lo_v, n_lo_f, res, o.flags);
-    if ((rc = check_workspace(workspace, workspace_bytes, L))) return rc;
-    // the save order of the ray list must be pinned for the backward pass, and
-    // the output buffers must not overlap the workspace
-    char* ws = (char*)workspace;
-    hipStream_t s = (hipStream_t)stream;
-    const bool tim = (o.flags & BAKE_FLAG_TIMING) != 0;
-
-    HIP_OR_FAIL(tim_record(tim, 0, s));
-    HIP_OR_FAIL(fill_u32((uint32_t*)(ws + L.status), 0, 1, s));
-    HIP_OR_FAIL(fill_u32((uint32_t*)(ws + L.counters), 0, kCntSlots, s));
-    HIP_OR_FAIL(launch_lo_prep(lo_V, n_lo_v, lo_F, n_lo_f, lo_UV, res, L, ws, s));
-    HIP_OR_FAIL(tim_record(tim, 1, s));
-    HIP_OR_FAIL(launch_raster(n_lo_f, res, L, ws, s));
-    HIP_OR_FAIL(launch_fill_uncovered(res, out_map, out_hit, L, ws, s));
-    HIP_OR_FAIL(tim_record(tim, 2, s));
-    HIP_OR_FAIL(launch_bvh_build(hi_V, n_hi_v, hi_F, n_hi_f, L, ws, s));
-    HIP_OR_FAIL(tim_record(tim, 3, s));
-    TravConfig tc = o.trav;
-    tc.count = (o.flags & BAKE_FLAG_COUNT) != 0;
-    HIP_OR_FAIL(launch_traverse(lo_V, lo_F, n_lo_f, hi_F, n_hi_v, n_hi_f, hi_N, max_dist, out_map,
-                                out_hit, (o.flags & BAKE_FLAG_SAVE) != 0, tc, L, ws, s));
-    HIP_OR_FAIL(tim_record(tim, 4, s));
-    HIP_OR_FAIL(launch_dilate(res, o.dilate, out_map, L, ws, s));
-    if (o.rgb8) HIP_OR_FAIL(launch_rgb8(res, out_map, o.rgb8, s));
-    HIP_OR_FAIL(tim_record(tim, 5, s));
-    tim_commit(tim);
-    if (o.flags & BAKE_FLAG_SAVE) remember_saved(workspace, n_hi_v, n_hi_f, n_lo_v, n_lo_f, res);
-    else forget_saved(workspace);
-    return BAKE_OK;
+    if ((rc = check_workspace(workspace, workspace_bytes, P.L))) return rc;
+    fill_pointers(&a, &P);
+    return run_forward(P, o, workspace, (hipStream_t)stream);
 }
 
 int32_t bake_normals_backward(const float* hi_V, int64_t n_hi_v, const int32_t* hi_F,
@@ -375,18 +607,106 @@ int32_t bake_normals_backward(const float* hi_V, int64_t n_hi_v, const int32_t* 
                               float* grad_hi_N, void* workspace, size_t workspace_bytes,
                               void* stream) {
     g_err[0] = 0;
-    int32_t rc = validate_common(hi_V, n_hi_v, hi_F, n_hi_f, hi_N, lo_V, n_lo_v, lo_F, n_lo_f, lo_UV,
-                                 res, max_dist);
+    bake_asset a = single_asset(hi_V, n_hi_v, hi_F, n_hi_f, hi_N, lo_V, n_lo_v, lo_F, n_lo_f, lo_UV, res,
+                                max_dist);
+    a.grad_map = grad_map;
+    a.grad_lo_V = grad_lo_V;
+    a.grad_hi_N = grad_hi_N;
+    return bake_normals_batched_backward(&a, 1, workspace, workspace_bytes, stream);
+}
+
+int32_t bake_batch_workspace_size(const bake_asset* assets, int32_t n_assets, const bake_options* opt,
+                                  size_t* bytes_out) {
+    g_err[0] = 0;
+    if (!bytes_out) return fail(BAKE_E_INVALID_ARG, "bytes_out is NULL");
+    Opts o;
+    int32_t rc = parse_opts(opt, &o);
     if (rc) return rc;
-    if (!grad_map) return fail(BAKE_E_INVALID_ARG, "grad_map is NULL");
-    Layout L = make_layout(n_hi_v, n_hi_f, n_lo_v, n_lo_f, res, BAKE_FLAG_SAVE);
-    if ((rc = check_workspace(workspace, workspace_bytes, L))) return rc;
-    if (!was_saved(workspace, n_hi_v, n_hi_f, n_lo_v, n_lo_f, res))
-        return fail(BAKE_E_STATE,
-                    "no forward bake with BAKE_FLAG_SAVE and these sizes used this workspace");
-    if (!grad_lo_V && !grad_hi_N) return BAKE_OK;
-    HIP_OR_FAIL(launch_backward(hi_V, hi_F, n_hi_v, hi_N, lo_V, lo_F, n_lo_v, n_lo_f, grad_map, grad_lo_V,
-                                grad_hi_N, L, (char*)workspace, (hipStream_t)stream));
+    Plan P;
+    if ((rc = plan_batch(assets, n_assets, o.flags, &P))) return rc;
+    *bytes_out = P.L.total;
+    return BAKE_OK;
+}
+
+int32_t bake_normals_batched(const bake_asset* assets, int32_t n_assets, const bake_options* opt,
+                             void* workspace, size_t workspace_bytes, void* stream) {
+    g_err[0] = 0;
+    Opts o;
+    int32_t rc = parse_opts(opt, &o);
+    if (rc) return rc;
+    if (o.rgb8) return fail(BAKE_E_INVALID_ARG, "batches take RGB8 outputs per asset (opt->out_rgb8 must be NULL)");
+    Plan P;
+    if ((rc = plan_batch(assets, n_assets, o.flags, &P))) return rc;
+    for (int a = 0; a < n_assets; ++a) {
+        if ((rc = validate_asset(assets[a], a))) return rc;
+        if (!assets[a].out_map || !assets[a].out_hit)
+            return fail(BAKE_E_INVALID_ARG, "asset %d: out_map / out_hit is NULL", a);
+    }
+    if ((rc = check_workspace(workspace, workspace_bytes, P.L))) return rc;
+    fill_pointers(assets, &P);
+    return run_forward(P, o, workspace, (hipStream_t)stream);
+}
+
+int32_t bake_normals_batched_backward(const bake_asset* assets, int32_t n_assets, void* workspace,
+                                      size_t workspace_bytes, void* stream) {
+    g_err[0] = 0;
+    Plan P;
+    int32_t rc = plan_batch(assets, n_assets, BAKE_FLAG_SAVE, &P);
+    if (rc) return rc;
+    for (int a = 0; a < n_assets; ++a) {
+        if ((rc = validate_asset(assets[a], a))) return rc;
+        if (!assets[a].grad_map && (assets[a].grad_lo_V || assets[a].grad_hi_N))
+            return fail(BAKE_E_INVALID_ARG, "asset %d: grad_map is NULL", a);
+    }
+    if ((rc = check_workspace(workspace, workspace_bytes, P.L))) return rc;
+    uint32_t nonce = 0;
+    if (!was_saved(workspace, P.sig, &nonce))
+        return fail(BAKE_E_STATE, "no forward bake with BAKE_FLAG_SAVE and these sizes used this workspace");
+    fill_pointers(assets, &P);
+    return run_backward(P, workspace, nonce, (hipStream_t)stream);
+}
+
+int32_t bake_autotune(const bake_asset* assets, int32_t n_assets, const bake_options* base, int32_t reps,
+                      void* workspace, size_t workspace_bytes, void* stream, bake_options* best_out,
+                      float* ms_out) {
+    g_err[0] = 0;
+    if (!best_out) return fail(BAKE_E_INVALID_ARG, "best_out is NULL");
+    if (reps < 1 || reps > 64) return fail(BAKE_E_INVALID_ARG, "reps %d outside [1, 64]", reps);
+    bake_options opt;
+    if (base) opt = *base;
+    else bake_default_options(&opt);
+    static const int blocks[3] = {64, 128, 256}, stacks[3] = {8, 16, 32};
+    float best = INFINITY;
+    bake_options best_opt = opt;
+    int idx = 0;
+    for (int bi = 0; bi < 3; ++bi)
+        for (int si = 0; si < 3; ++si)
+            for (int pe = 0; pe < 2; ++pe, ++idx) {
+                bake_options o = opt;
+                o.trav_block = blocks[bi];
+                o.trav_stack = stacks[si];
+                o.trav_persist = pe;
+                o.flags = (opt.flags & ~(uint32_t)BAKE_FLAG_COUNT) | BAKE_FLAG_TIMING;
+                std::vector<float> t(reps);
+                for (int r = 0; r < reps; ++r) {
+                    int32_t rc = bake_normals_batched(assets, n_assets, &o, workspace, workspace_bytes, stream);
+                    if (rc) return rc;
+                    float ms[kStages];
+                    if ((rc = slot_times((g_tim.next + kRing - 1) % kRing, ms))) return rc;
+                    t[r] = ms[3];
+                }
+                std::sort(t.begin(), t.end());
+                const float med = t[reps / 2];
+                if (ms_out) ms_out[idx] = med;
+                if (med < best) {
+                    best = med;
+                    best_opt = opt;
+                    best_opt.trav_block = blocks[bi];
+                    best_opt.trav_stack = stacks[si];
+                    best_opt.trav_persist = pe;
+                }
+            }
+    *best_out = best_opt;
     return BAKE_OK;
 }
 
@@ -415,17 +735,13 @@ int32_t bake_query_status(const void* workspace, void* stream, uint32_t* status_
 
 int32_t bake_read_counter(const void* workspace, int32_t which, void* stream, int64_t* value_out) {
     g_err[0] = 0;
-    if (!workspace || !value_out) return fail(BAKE_E_INVALID_ARG, "NULL argument");
-    if (which < 0 || which > 2) return fail(BAKE_E_INVALID_ARG, "unknown counter %d", which);
-    hipStream_t s = (hipStream_t)stream;
-    uint32_t v[kCntSlots];
-    // counters sit right after the 256-byte status block
-    HIP_OR_FAIL(hipMemcpyAsync(v, (const char*)workspace + 256, sizeof v, hipMemcpyDeviceToHost, s));
-    HIP_OR_FAIL(hipStreamSynchronize(s));
-    if (which == 0) *value_out = v[kCntRays];
-    else if (which == 1) *value_out = (int64_t)v[kCntBoxLo] | ((int64_t)v[kCntBoxLo + 1] << 32);
-    else *value_out = (int64_t)v[kCntTriLo] | ((int64_t)v[kCntTriLo + 1] << 32);
-    return BAKE_OK;
+    return read_counter_at(workspace, 0, which, stream, value_out);
+}
+
+int32_t bake_read_asset_counter(const void* workspace, int32_t asset, int32_t which, void* stream,
+                                int64_t* value_out) {
+    g_err[0] = 0;
+    return read_counter_at(workspace, asset, which, stream, value_out);
 }
 
 int32_t bake_stage_times(float* ms_out, int32_t n) {

@@ -17,7 +17,9 @@
 //   * high-poly: each hit ray contributes beta_k h_bar to the three vertices
 //     of its triangle; the (vertex, ray*3 + corner) pairs are radix-sorted
 //     stably and each vertex sums its run in ray order.
-// No floating-point atomics: the result is bitwise reproducible.
+// No floating-point atomics: the result is bitwise reproducible.  In a batch
+// the per-ray kernels take (asset, 64-ray batch) items like the traversal,
+// and the reductions stay inside each asset's ranges.
 #include <algorithm>
 
 #include "internal.h"
@@ -51,83 +53,117 @@ struct RayGrad {  // 48 B per ray
     float3 pb, mb, tfb, hb;
 };
 
+// The (asset, 64-ray batch) item q: the asset and the wave's global ray
+// (invalid when past the asset's rays).
+struct RayItem {
+    int a;
+    int64_t r;     // global ray index
+    bool valid;
+    int64_t begin, end;  // the asset's global ray range
+};
+
+__device__ __forceinline__ RayItem ray_item(const Batch& B, uint32_t q, int lane) {
+    RayItem it;
+    it.a = upper_asset(B.rb_pf, B.n, q);
+    const uint32_t nr = B.cnt[(int64_t)it.a * kCntSlots + kCntRays];
+    const uint32_t k = (q - B.rb_pf[it.a]) * 64u + (uint32_t)lane;
+    it.begin = B.ray_pf[it.a];
+    it.end = it.begin + nr;
+    it.r = it.begin + k;
+    it.valid = k < nr;
+    return it;
+}
+
 // Per-ray adjoint.  Also emits the three (hi vertex, item) sort pairs of the
 // ray; rays without a hit emit the out-of-range key nhv.
-__global__ void bwd_ray_kernel(const Ray* __restrict__ rays, const Hit* __restrict__ hits,
-                               const uint32_t* __restrict__ nrays_p, const float* __restrict__ lo_V,
-                               const int32_t* __restrict__ lo_F, const float4* __restrict__ lo_n,
-                               const float4* __restrict__ face_t, const float* __restrict__ hi_V,
-                               const int32_t* __restrict__ hi_F, int64_t nhv,
-                               const float* __restrict__ hi_N, const float* __restrict__ grad_map,
-                               RayGrad* __restrict__ rg, uint32_t* __restrict__ keys,
-                               uint32_t* __restrict__ vals) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t nrays = *nrays_p;
-    if (r >= nrays) return;
-    const Ray ray = rays[r];
-    const Hit hit = hits[r];
-    RayGrad g;
-    g.pb = g.mb = g.tfb = g.hb = f3(0.f, 0.f, 0.f);
-    uint32_t kv[3] = {(uint32_t)nhv, (uint32_t)nhv, (uint32_t)nhv};
-    if (hit.id >= 0) {
-        const int32_t f = ray.face;
-        const float b1 = ray.b1, b2 = ray.b2, b0 = 1.0f - b1 - b2;
-        const int32_t i0 = lo_F[3 * f], i1 = lo_F[3 * f + 1], i2 = lo_F[3 * f + 2];
-        const float4 n0 = lo_n[i0], n1 = lo_n[i1], n2 = lo_n[i2];
-        const float3 m = f3(b0 * n0.x + b1 * n1.x + b2 * n2.x, b0 * n0.y + b1 * n1.y + b2 * n2.y,
-                            b0 * n0.z + b1 * n1.z + b2 * n2.z);
-        const float lm = sqrtf(dot3(m, m));
-        const float3 d = mul3(m, 1.0f / lm);
-        const float4 T4 = face_t[f];
-        const float3 Tf = f3(T4.x, T4.y, T4.z);
-        const float H = T4.w;
-        const float3 Tt = sub3(Tf, mul3(d, dot3(d, Tf)));
-        const float lt = sqrtf(dot3(Tt, Tt));
-        const float3 Tp = mul3(Tt, 1.0f / lt);
-        const float3 Bp = mul3(cross3(d, Tp), H);
-        const int32_t j0 = hi_F[3 * (int64_t)hit.id], j1 = hi_F[3 * (int64_t)hit.id + 1],
-                      j2 = hi_F[3 * (int64_t)hit.id + 2];
-        const float3 A = ld3(hi_V, j0), e1 = sub3(ld3(hi_V, j1), A), e2 = sub3(ld3(hi_V, j2), A);
-        const float3 N0 = ld3(hi_N, j0), N1 = ld3(hi_N, j1), N2 = ld3(hi_N, j2);
-        const float be1 = hit.beta1, be2 = hit.beta2, be0 = 1.0f - be1 - be2;
-        const float3 h = add3(add3(mul3(N0, be0), mul3(N1, be1)), mul3(N2, be2));
-        const float lh = sqrtf(dot3(h, h));
-        const float3 n = mul3(h, 1.0f / lh);
-        const float3 o = ld3(grad_map, ray.texel);
-        // out = (n.T', n.B', n.d)
-        const float3 nb = add3(add3(mul3(Tp, o.x), mul3(Bp, o.y)), mul3(d, o.z));
-        const float3 Tpb = add3(mul3(n, o.x), mul3(cross3(n, d), o.y * H));
-        float3 db = add3(mul3(n, o.z), mul3(cross3(Tp, n), o.y * H));
-        // T' = T~/|T~|, T~ = T_f - (d.T_f) d
-        const float3 Ttb = unit_adj(Tpb, Tp, lt);
-        const float3 Tfb = sub3(Ttb, mul3(d, dot3(d, Ttb)));
-        db = sub3(db, add3(mul3(Ttb, dot3(d, Tf)), mul3(Tf, dot3(d, Ttb))));
-        // n = h/|h|; h = sum beta_k N_k
-        const float3 hb = unit_adj(nb, n, lh);
-        const float bb1 = dot3(hb, sub3(N1, N0)), bb2 = dot3(hb, sub3(N2, N0));
-        // M (t, beta1, beta2) = p - A with M = [-d | e1 | e2]:  w = M^-T (0, bb1, bb2),
-        // by Cramer on M^T (columns = the rows of M)
-        const float3 c0 = f3(-d.x, e1.x, e2.x), c1 = f3(-d.y, e1.y, e2.y), c2 = f3(-d.z, e1.z, e2.z);
-        const float3 rhs = f3(0.f, bb1, bb2);
-        const float3 c12 = cross3(c1, c2);
-        const float D = dot3(c0, c12);
-        const float rD = 1.0f / D;
-        const float3 w = f3(dot3(rhs, c12) * rD, dot3(c0, cross3(rhs, c2)) * rD,
-                            dot3(c0, cross3(c1, rhs)) * rD);
-        db = add3(db, mul3(w, hit.t));
-        g.pb = w;
-        g.mb = unit_adj(db, d, lm);
-        g.tfb = Tfb;
-        g.hb = hb;
-        kv[0] = (uint32_t)j0;
-        kv[1] = (uint32_t)j1;
-        kv[2] = (uint32_t)j2;
-    }
-    rg[r] = g;
+__global__ __launch_bounds__(256) void bwd_ray_kernel(Batch B, const Ray* __restrict__ rays,
+                                                      const Hit* __restrict__ hits,
+                                                      const float4* __restrict__ lo_n_all,
+                                                      const float4* __restrict__ face_t_all,
+                                                      RayGrad* __restrict__ rg, uint32_t* __restrict__ keys,
+                                                      uint32_t* __restrict__ vals) {
+    if (!sealed(B)) return;
+    const int lane = threadIdx.x & 63;
+    const uint32_t nb = B.rb_pf[B.n];
+    const uint32_t waves = gridDim.x * 4u;
+    for (uint32_t q = __builtin_amdgcn_readfirstlane(blockIdx.x * 4u + (threadIdx.x >> 6)); q < nb;
+         q += waves) {
+        const RayItem it = ray_item(B, q, lane);
+        if (!it.valid) continue;
+        const AssetDev& As = B.A[it.a];
+        const int64_t r = it.r;
+        const int64_t nhv = As.nhv;
+        const Ray ray = rays[r];
+        const Hit hit = hits[r];
+        RayGrad g;
+        g.pb = g.mb = g.tfb = g.hb = f3(0.f, 0.f, 0.f);
+        uint32_t kv[3] = {(uint32_t)nhv, (uint32_t)nhv, (uint32_t)nhv};
+        const float* grad_map = B.G[it.a].grad_map;  // NULL: the asset wants no gradient
+        if (hit.id >= 0 && grad_map) {
+            const float4* lo_n = lo_n_all + As.lv;
+            const int32_t* lo_F = As.lo_F;
+            const int32_t* hi_F = As.hi_F;
+            const float* hi_V = As.hi_V;
+            const float* hi_N = As.hi_N;
+            const int32_t f = ray.face;
+            const float b1 = ray.b1, b2 = ray.b2, b0 = 1.0f - b1 - b2;
+            const int32_t i0 = lo_F[3 * f], i1 = lo_F[3 * f + 1], i2 = lo_F[3 * f + 2];
+            const float4 n0 = lo_n[i0], n1 = lo_n[i1], n2 = lo_n[i2];
+            const float3 m = f3(b0 * n0.x + b1 * n1.x + b2 * n2.x, b0 * n0.y + b1 * n1.y + b2 * n2.y,
+                                b0 * n0.z + b1 * n1.z + b2 * n2.z);
+            const float lm = sqrtf(dot3(m, m));
+            const float3 d = mul3(m, 1.0f / lm);
+            const float4 T4 = face_t_all[As.lf + f];
+            const float3 Tf = f3(T4.x, T4.y, T4.z);
+            const float H = T4.w;
+            const float3 Tt = sub3(Tf, mul3(d, dot3(d, Tf)));
+            const float lt = sqrtf(dot3(Tt, Tt));
+            const float3 Tp = mul3(Tt, 1.0f / lt);
+            const float3 Bp = mul3(cross3(d, Tp), H);
+            const int32_t j0 = hi_F[3 * (int64_t)hit.id], j1 = hi_F[3 * (int64_t)hit.id + 1],
+                          j2 = hi_F[3 * (int64_t)hit.id + 2];
+            const float3 A = ld3(hi_V, j0), e1 = sub3(ld3(hi_V, j1), A), e2 = sub3(ld3(hi_V, j2), A);
+            const float3 N0 = ld3(hi_N, j0), N1 = ld3(hi_N, j1), N2 = ld3(hi_N, j2);
+            const float be1 = hit.beta1, be2 = hit.beta2, be0 = 1.0f - be1 - be2;
+            const float3 h = add3(add3(mul3(N0, be0), mul3(N1, be1)), mul3(N2, be2));
+            const float lh = sqrtf(dot3(h, h));
+            const float3 n = mul3(h, 1.0f / lh);
+            const float3 o = ld3(grad_map, ray.texel);
+            // out = (n.T', n.B', n.d)
+            const float3 nb3 = add3(add3(mul3(Tp, o.x), mul3(Bp, o.y)), mul3(d, o.z));
+            const float3 Tpb = add3(mul3(n, o.x), mul3(cross3(n, d), o.y * H));
+            float3 db = add3(mul3(n, o.z), mul3(cross3(Tp, n), o.y * H));
+            // T' = T~/|T~|, T~ = T_f - (d.T_f) d
+            const float3 Ttb = unit_adj(Tpb, Tp, lt);
+            const float3 Tfb = sub3(Ttb, mul3(d, dot3(d, Ttb)));
+            db = sub3(db, add3(mul3(Ttb, dot3(d, Tf)), mul3(Tf, dot3(d, Ttb))));
+            // n = h/|h|; h = sum beta_k N_k
+            const float3 hb = unit_adj(nb3, n, lh);
+            const float bb1 = dot3(hb, sub3(N1, N0)), bb2 = dot3(hb, sub3(N2, N0));
+            // M (t, beta1, beta2) = p - A with M = [-d | e1 | e2]:  w = M^-T (0, bb1, bb2),
+            // by Cramer on M^T (columns = the rows of M)
+            const float3 c0 = f3(-d.x, e1.x, e2.x), c1 = f3(-d.y, e1.y, e2.y), c2 = f3(-d.z, e1.z, e2.z);
+            const float3 rhs = f3(0.f, bb1, bb2);
+            const float3 c12 = cross3(c1, c2);
+            const float D = dot3(c0, c12);
+            const float rD = 1.0f / D;
+            const float3 w = f3(dot3(rhs, c12) * rD, dot3(c0, cross3(rhs, c2)) * rD,
+                                dot3(c0, cross3(c1, rhs)) * rD);
+            db = add3(db, mul3(w, hit.t));
+            g.pb = w;
+            g.mb = unit_adj(db, d, lm);
+            g.tfb = Tfb;
+            g.hb = hb;
+            kv[0] = (uint32_t)j0;
+            kv[1] = (uint32_t)j1;
+            kv[2] = (uint32_t)j2;
+        }
+        rg[r] = g;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        keys[3 * r + k] = kv[k];
-        vals[3 * r + k] = (uint32_t)(3 * r + k);
+        for (int k = 0; k < 3; ++k) {
+            keys[3 * r + k] = kv[k];
+            vals[3 * r + k] = (uint32_t)(3 * r + k);
+        }
     }
 }
 
@@ -141,15 +177,19 @@ __device__ __forceinline__ float wave_sum(float v) {
 // T_f_bar (lane-strided in ray order, then a fixed shuffle tree), and turns
 // T_f_bar into corner contributions through T_f = c1 (V1 - V0) + c2 (V2 - V0).
 // Output per face: Vbar[3 corners][3], nbar[3 corners][3].
-__global__ __launch_bounds__(256) void bwd_face_kernel(const Ray* __restrict__ rays,
+__global__ __launch_bounds__(256) void bwd_face_kernel(Batch B, const Ray* __restrict__ rays,
                                                        const RayGrad* __restrict__ rg,
                                                        const uint32_t* __restrict__ face_off,
-                                                       const int4* __restrict__ face_uv, int64_t nf,
+                                                       const int4* __restrict__ face_uv,
                                                        float* __restrict__ face_acc) {
-    const int64_t f = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (!sealed(B)) return;
+    int64_t lb;
+    const AssetDev& As = B.A[block_asset(B, kGLoFWave, blockIdx.x, &lb)];
+    const int64_t f = lb * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (f >= nf) return;
-    const uint32_t b = face_off[f], e = face_off[f + 1];
+    if (f >= As.nlf) return;
+    const int64_t fg = As.lf + f;
+    const uint32_t b = face_off[fg], e = face_off[fg + 1];
     float acc[21];
 #pragma unroll
     for (int q = 0; q < 21; ++q) acc[q] = 0.f;
@@ -173,7 +213,7 @@ __global__ __launch_bounds__(256) void bwd_face_kernel(const Ray* __restrict__ r
 #pragma unroll
     for (int q = 0; q < 21; ++q) acc[q] = wave_sum(acc[q]);
     if (lane == 0) {
-        const int4 p = face_uv[2 * f], q = face_uv[2 * f + 1];
+        const int4 p = face_uv[2 * fg], q = face_uv[2 * fg + 1];
         const int64_t du1 = (int64_t)p.z - p.x, dv1 = (int64_t)p.w - p.y;
         const int64_t du2 = (int64_t)q.x - p.x, dv2 = (int64_t)q.y - p.y;
         const int64_t det = du1 * dv2 - du2 * dv1;
@@ -181,7 +221,7 @@ __global__ __launch_bounds__(256) void bwd_face_kernel(const Ray* __restrict__ r
         const float c1 = sg * (float)dv2, c2 = -sg * (float)dv1;
         const float3 tfb = f3(acc[18], acc[19], acc[20]);
         const float3 e1b = mul3(tfb, c1), e2b = mul3(tfb, c2);
-        float* o = face_acc + 18 * f;
+        float* o = face_acc + 18 * fg;
         const float3 v0 = sub3(f3(acc[0], acc[1], acc[2]), add3(e1b, e2b));
         const float3 v1 = add3(f3(acc[3], acc[4], acc[5]), e1b);
         const float3 v2 = add3(f3(acc[6], acc[7], acc[8]), e2b);
@@ -199,21 +239,28 @@ __device__ __forceinline__ int corner_of(const int32_t* __restrict__ F, int32_t 
 
 // Per low-poly vertex: gather the faces' corner sums (faces ascending), then
 // the adjoint of n_v = s_v/|s_v| with s_v recomputed in the forward's order.
-__global__ void bwd_vertex1_kernel(const float* __restrict__ V, int64_t nv, const int32_t* __restrict__ F,
-                                   const uint32_t* __restrict__ off, const int32_t* __restrict__ adj,
-                                   const float* __restrict__ face_acc, float* __restrict__ vbar,
-                                   float* __restrict__ sbar) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= nv) return;
+__global__ __launch_bounds__(256) void bwd_vertex1_kernel(Batch B, const uint32_t* __restrict__ off,
+                                                          const int32_t* __restrict__ adj,
+                                                          const float* __restrict__ face_acc_all,
+                                                          float* __restrict__ vbar, float* __restrict__ sbar) {
+    if (!sealed(B)) return;
+    int64_t lb;
+    const AssetDev& As = B.A[block_asset(B, kGLoV, blockIdx.x, &lb)];
+    const int64_t v = lb * 256 + threadIdx.x;
+    if (v >= As.nlv) return;
+    const float* V = As.lo_V;
+    const int32_t* F = As.lo_F;
+    const float* face_acc = face_acc_all + 18 * As.lf;
+    const int64_t g = As.lv + v;
     float3 vb = f3(0.f, 0.f, 0.f), nb = f3(0.f, 0.f, 0.f), s = f3(0.f, 0.f, 0.f);
-    for (uint32_t i = off[v]; i < off[v + 1]; ++i) {
+    for (uint32_t i = off[g]; i < off[g + 1]; ++i) {
         const int32_t f = adj[i];
         const int k = corner_of(F, f, v);
         const float* o = face_acc + 18 * (int64_t)f;
         vb = add3(vb, f3(o[3 * k], o[3 * k + 1], o[3 * k + 2]));
         nb = add3(nb, f3(o[9 + 3 * k], o[9 + 3 * k + 1], o[9 + 3 * k + 2]));
-        const float3 A = ld3(V, F[3 * f]), B = ld3(V, F[3 * f + 1]), C = ld3(V, F[3 * f + 2]);
-        const float3 c = cross3(sub3(B, A), sub3(C, A));
+        const float3 A = ld3(V, F[3 * f]), Bv = ld3(V, F[3 * f + 1]), C = ld3(V, F[3 * f + 2]);
+        const float3 c = cross3(sub3(Bv, A), sub3(C, A));
         s.x += c.x;
         s.y += c.y;
         s.z += c.z;
@@ -221,17 +268,24 @@ __global__ void bwd_vertex1_kernel(const float* __restrict__ V, int64_t nv, cons
     const float ls = sqrtf(dot3(s, s));
     float3 sb = f3(0.f, 0.f, 0.f);
     if (ls > 0.f && isfinite(ls)) sb = unit_adj(nb, mul3(s, 1.0f / ls), ls);
-    st3(vbar, v, vb);
-    st3(sbar, v, sb);
+    st3(vbar, g, vb);
+    st3(sbar, g, sb);
 }
 
 // Per low-poly face: c_bar = sum of its vertices' s_bar; adjoint of the cross
 // product c = e1 x e2 into corner contributions.
-__global__ void bwd_face2_kernel(const float* __restrict__ V, const int32_t* __restrict__ F, int64_t nf,
-                                 int64_t nv, const float* __restrict__ sbar, float* __restrict__ face_acc2) {
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nf) return;
-    float* o = face_acc2 + 9 * f;
+__global__ __launch_bounds__(256) void bwd_face2_kernel(Batch B, const float* __restrict__ sbar_all,
+                                                        float* __restrict__ face_acc2) {
+    if (!sealed(B)) return;
+    int64_t lb;
+    const AssetDev& As = B.A[block_asset(B, kGLoF, blockIdx.x, &lb)];
+    const int64_t f = lb * 256 + threadIdx.x;
+    if (f >= As.nlf) return;
+    const float* V = As.lo_V;
+    const int32_t* F = As.lo_F;
+    const int64_t nv = As.nlv;
+    const float* sbar = sbar_all + 3 * As.lv;
+    float* o = face_acc2 + 9 * (As.lf + f);
     const int32_t a = F[3 * f], b = F[3 * f + 1], c = F[3 * f + 2];
     if (a < 0 || b < 0 || c < 0 || a >= nv || b >= nv || c >= nv) {
         // faces with bad indices never entered the adjacency: nothing to add
@@ -246,42 +300,74 @@ __global__ void bwd_face2_kernel(const float* __restrict__ V, const int32_t* __r
     st3(o, 2, e2b);
 }
 
-__global__ void bwd_vertex2_kernel(int64_t nv, const int32_t* __restrict__ F,
-                                   const uint32_t* __restrict__ off, const int32_t* __restrict__ adj,
-                                   const float* __restrict__ face_acc2, const float* __restrict__ vbar,
-                                   float* __restrict__ grad_lo_V) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= nv) return;
-    float3 g = ld3(vbar, v);
-    for (uint32_t i = off[v]; i < off[v + 1]; ++i) {
+__global__ __launch_bounds__(256) void bwd_vertex2_kernel(Batch B, const uint32_t* __restrict__ off,
+                                                          const int32_t* __restrict__ adj,
+                                                          const float* __restrict__ face_acc2_all,
+                                                          const float* __restrict__ vbar) {
+    if (!sealed(B)) return;
+    int64_t lb;
+    const int ai = block_asset(B, kGLoV, blockIdx.x, &lb);
+    const AssetDev& As = B.A[ai];
+    float* grad_lo_V = B.G[ai].grad_lo_V;
+    const int64_t v = lb * 256 + threadIdx.x;
+    if (v >= As.nlv || !grad_lo_V) return;
+    const int32_t* F = As.lo_F;
+    const float* face_acc2 = face_acc2_all + 9 * As.lf;
+    const int64_t g = As.lv + v;
+    float3 acc = ld3(vbar, g);
+    for (uint32_t i = off[g]; i < off[g + 1]; ++i) {
         const int32_t f = adj[i];
         const int k = corner_of(F, f, v);
-        g = add3(g, ld3(face_acc2 + 9 * (int64_t)f, k));
+        acc = add3(acc, ld3(face_acc2 + 9 * (int64_t)f, k));
     }
-    st3(grad_lo_V, v, g);
+    st3(grad_lo_V, v, acc);
 }
 
-// Sorted (vertex, item) pairs: the first item of each vertex's run sums the
-// run in order (items are ascending within a run: the sort is stable).
-__global__ void bwd_hiN_kernel(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
-                               const uint32_t* __restrict__ nrays_p, int64_t nhv,
-                               const Hit* __restrict__ hits, const RayGrad* __restrict__ rg,
-                               float* __restrict__ grad_hi_N) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t n = 3 * (int64_t)(*nrays_p);
-    if (i >= n) return;
-    const uint32_t key = keys[i];
-    if (key >= (uint32_t)nhv) return;
-    if (i > 0 && keys[i - 1] == key) return;
-    float3 g = f3(0.f, 0.f, 0.f);
-    for (int64_t j = i; j < n && keys[j] == key; ++j) {
-        const uint32_t item = vals[j];
-        const uint32_t r = item / 3, k = item - 3 * r;
-        const Hit h = hits[r];
-        const float beta = k == 0 ? 1.0f - h.beta1 - h.beta2 : (k == 1 ? h.beta1 : h.beta2);
-        g = add3(g, mul3(rg[r].hb, beta));
+__global__ __launch_bounds__(256) void zero_grad_hi_kernel(Batch B) {
+    if (!sealed(B)) return;
+    int64_t lb;
+    const int ai = block_asset(B, kGHiV, blockIdx.x, &lb);
+    float* out = B.G[ai].grad_hi_N;
+    const int64_t v = lb * 256 + threadIdx.x;
+    if (!out || v >= B.A[ai].nhv) return;
+    st3(out, v, f3(0.f, 0.f, 0.f));
+}
+
+// Sorted (vertex, item) pairs of an asset: the first item of each vertex's
+// run sums the run in order (items are ascending within a run: the sort is
+// stable).  Waves take (asset, 64-ray batch) items: 192 pairs each.
+__global__ __launch_bounds__(256) void bwd_hiN_kernel(Batch B, const uint32_t* __restrict__ keys,
+                                                      const uint32_t* __restrict__ vals,
+                                                      const Hit* __restrict__ hits,
+                                                      const RayGrad* __restrict__ rg) {
+    if (!sealed(B)) return;
+    const int lane = threadIdx.x & 63;
+    const uint32_t nb = B.rb_pf[B.n];
+    const uint32_t waves = gridDim.x * 4u;
+    for (uint32_t q = __builtin_amdgcn_readfirstlane(blockIdx.x * 4u + (threadIdx.x >> 6)); q < nb;
+         q += waves) {
+        const RayItem it = ray_item(B, q, 0);
+        float* grad_hi_N = B.G[it.a].grad_hi_N;
+        if (!grad_hi_N) continue;
+        const uint32_t nhv = (uint32_t)B.A[it.a].nhv;
+        const int64_t lo = 3 * it.begin, hi = 3 * it.end;
+        for (int k3 = 0; k3 < 3; ++k3) {
+            const int64_t i = 3 * it.r + 64 * k3 + lane;
+            if (i >= hi) continue;
+            const uint32_t key = keys[i];
+            if (key >= nhv) continue;
+            if (i > lo && keys[i - 1] == key) continue;
+            float3 g = f3(0.f, 0.f, 0.f);
+            for (int64_t j = i; j < hi && keys[j] == key; ++j) {
+                const uint32_t item = vals[j];
+                const uint32_t r = item / 3, k = item - 3 * r;
+                const Hit h = hits[r];
+                const float beta = k == 0 ? 1.0f - h.beta1 - h.beta2 : (k == 1 ? h.beta1 : h.beta2);
+                g = add3(g, mul3(rg[r].hb, beta));
+            }
+            st3(grad_hi_N, key, g);
+        }
     }
-    st3(grad_hi_N, key, g);
 }
 
 // Squared-error loss helper: grad = 2 (map - target), per-block partial sums
@@ -318,61 +404,57 @@ inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b
 
 }  // namespace
 
-hipError_t launch_backward(const float* hi_V, const int32_t* hi_F, int64_t nhv, const float* hi_N,
-                           const float* lo_V, const int32_t* lo_F, int64_t nlv, int64_t nlf,
-                           const float* grad_map, float* grad_lo_V, float* grad_hi_N, const Layout& L,
-                           char* ws, hipStream_t s) {
+hipError_t launch_backward(const BatchHost& H, bool any_lo, bool any_hi, hipStream_t s) {
+    const Layout& L = H.L;
+    char* ws = H.ws;
     hipError_t e;
-    const uint32_t* counters = (const uint32_t*)(ws + L.counters);
     const Ray* rays = (const Ray*)(ws + L.rays);
     const Hit* hits = (const Hit*)(ws + L.hits);
     RayGrad* rg = (RayGrad*)(ws + L.bwd_ray);
-    uint32_t* k0 = (uint32_t*)(ws + L.bwd_k0);
-    uint32_t* v0 = (uint32_t*)(ws + L.bwd_v0);
-    uint32_t* k1 = (uint32_t*)(ws + L.bwd_k1);
-    uint32_t* v1 = (uint32_t*)(ws + L.bwd_v1);
-    const int64_t max_items = 3 * L.max_rays;
-    if (L.max_rays > 0) {
-        hipLaunchKernelGGL(bwd_ray_kernel, dim3(blocks_for(L.max_rays, 256)), dim3(256), 0, s, rays, hits,
-                           counters + kCntRays, lo_V, lo_F, (const float4*)(ws + L.lo_n),
-                           (const float4*)(ws + L.face_t), hi_V, hi_F, nhv, hi_N, grad_map, rg, k0, v0);
+    // persistent waves over the (asset, 64-ray batch) items: enough for the
+    // largest possible ray count, capped
+    int64_t cap_batches = 0;
+    for (int a = 0; a < L.n; ++a) cap_batches += ((int64_t)H.A[a].res * H.A[a].res + 63) / 64;
+    const unsigned ray_grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((cap_batches + 3) / 4, 4096));
+    if (L.t_tex > 0) {
+        hipLaunchKernelGGL(bwd_ray_kernel, dim3(ray_grid), dim3(256), 0, s, H.dev, rays, hits,
+                           (const float4*)(ws + L.lo_n), (const float4*)(ws + L.face_t), rg,
+                           (uint32_t*)(ws + L.bwd_k0), (uint32_t*)(ws + L.bwd_v0));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if (grad_lo_V && nlv > 0) {
+    if (any_lo && L.t_lv > 0) {
         float* face1 = (float*)(ws + L.bwd_face1);
         float* face2 = (float*)(ws + L.bwd_face2);
         float* sbar = (float*)(ws + L.bwd_sbar);
         float* vbar = (float*)(ws + L.bwd_vbar);
         const uint32_t* off = (const uint32_t*)(ws + L.lo_off);
         const int32_t* adj = (const int32_t*)(ws + L.lo_adj);
-        if (nlf > 0) {
-            hipLaunchKernelGGL(bwd_face_kernel, dim3(blocks_for(nlf, 4)), dim3(256), 0, s, rays,
-                               (const RayGrad*)rg, (const uint32_t*)(ws + L.face_off),
-                               (const int4*)(ws + L.face_uv), nlf, face1);
+        if (H.blocks(kGLoFWave) > 0) {
+            hipLaunchKernelGGL(bwd_face_kernel, dim3((unsigned)H.blocks(kGLoFWave)), dim3(256), 0, s, H.dev,
+                               rays, (const RayGrad*)rg, (const uint32_t*)(ws + L.face_off),
+                               (const int4*)(ws + L.face_uv), face1);
         }
-        hipLaunchKernelGGL(bwd_vertex1_kernel, dim3(blocks_for(nlv, 256)), dim3(256), 0, s, lo_V, nlv, lo_F,
-                           off, adj, (const float*)face1, vbar, sbar);
-        if (nlf > 0) {
-            hipLaunchKernelGGL(bwd_face2_kernel, dim3(blocks_for(nlf, 256)), dim3(256), 0, s, lo_V, lo_F, nlf,
-                               nlv, (const float*)sbar, face2);
+        hipLaunchKernelGGL(bwd_vertex1_kernel, dim3((unsigned)H.blocks(kGLoV)), dim3(256), 0, s, H.dev, off,
+                           adj, (const float*)face1, vbar, sbar);
+        if (H.blocks(kGLoF) > 0) {
+            hipLaunchKernelGGL(bwd_face2_kernel, dim3((unsigned)H.blocks(kGLoF)), dim3(256), 0, s, H.dev,
+                               (const float*)sbar, face2);
         }
-        hipLaunchKernelGGL(bwd_vertex2_kernel, dim3(blocks_for(nlv, 256)), dim3(256), 0, s, nlv, lo_F, off,
-                           adj, (const float*)face2, (const float*)vbar, grad_lo_V);
+        hipLaunchKernelGGL(bwd_vertex2_kernel, dim3((unsigned)H.blocks(kGLoV)), dim3(256), 0, s, H.dev, off,
+                           adj, (const float*)face2, (const float*)vbar);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if (grad_hi_N && nhv > 0) {
-        if ((e = fill_u32((uint32_t*)grad_hi_N, 0u, 3 * nhv, s)) != hipSuccess) return e;
-        int bits = 1;
-        while (bits < 32 && ((uint64_t)1 << bits) <= (uint64_t)nhv) ++bits;  // keys in [0, nhv]
-        bool in1 = false;
-        if ((e = radix_sort_pairs(k0, v0, k1, v1, max_items, bits, (uint32_t*)(ws + L.bwd_hist),
-                                  (uint32_t*)(ws + L.scan_tmp), &in1, s, counters + kCntRays, 3u)) !=
-            hipSuccess)
-            return e;
-        hipLaunchKernelGGL(bwd_hiN_kernel, dim3(blocks_for(max_items, 256)), dim3(256), 0, s,
-                           (const uint32_t*)(in1 ? k1 : k0), (const uint32_t*)(in1 ? v1 : v0),
-                           counters + kCntRays, nhv, hits, (const RayGrad*)rg, grad_hi_N);
+    if (any_hi && L.t_hv > 0) {
+        hipLaunchKernelGGL(zero_grad_hi_kernel, dim3((unsigned)H.blocks(kGHiV)), dim3(256), 0, s, H.dev);
         if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (L.t_tex > 0) {
+            bool in1 = false;
+            if ((e = launch_sort(H, kSortBwd, L.max_hv_bits, &in1, s)) != hipSuccess) return e;
+            hipLaunchKernelGGL(bwd_hiN_kernel, dim3(ray_grid), dim3(256), 0, s, H.dev,
+                               (const uint32_t*)(ws + (in1 ? L.bwd_k1 : L.bwd_k0)),
+                               (const uint32_t*)(ws + (in1 ? L.bwd_v1 : L.bwd_v0)), hits, (const RayGrad*)rg);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }

@@ -58,54 +58,173 @@ constexpr int kMaxDepth = 64;
 
 // Device status word bits (mirror of BAKE_STATUS_* in bake.h).
 constexpr uint32_t kStLoIndex = 1u, kStHiIndex = 2u, kStBadUV = 4u, kStNonFinite = 8u,
-                   kStInternal = 16u;
+                   kStInternal = 16u, kStState = 32u;
 
 // Per-ray status values (mirror of bake.h).
 constexpr int32_t kMiss = -1, kUnreliable = -2, kUncovered = -3;
 
 // ---------------------------------------------------------------------------
-// Workspace layout (byte offsets into the caller's workspace)
+// Batches.  Every launch works on a batch of assets (a single bake is a batch
+// of one).  Per-element arrays of all assets are concatenated; each asset
+// knows where its elements start.  A launch's blocks are split among the
+// assets by a per-grid prefix table, so a block belongs to exactly one asset
+// and finds it by a binary search over that table: a batched asset goes
+// through exactly the arithmetic of a single bake.
 // ---------------------------------------------------------------------------
-struct Layout {
-    size_t status, counters;                 // u32 status word; counters (see kCnt*)
-    size_t lo_n, lo_deg, lo_off, lo_cur, lo_adj;  // lo vertex normals + vertex->face CSR
-    size_t face_t, face_uv, face_cnt, face_off;   // per lo face
-    size_t scan_tmp;                          // block sums for the scans
-    size_t facemap, level;                    // per texel
-    size_t rays, hits;                        // per ray
-    size_t bounds_part, bounds;               // centroid bounds reduction
-    size_t keys0, keys1, vals0, vals1, hist;  // radix sort
-    size_t nodes, leaves, node_parent, leaf_parent, refit_cnt, node_range, frontier, treelets;
-    size_t spill;                             // traversal stack spill
-    // backward scratch (BAKE_FLAG_SAVE only)
-    size_t bwd_ray, bwd_k0, bwd_v0, bwd_k1, bwd_v1, bwd_hist, bwd_face1, bwd_face2, bwd_sbar, bwd_vbar;
-    size_t total;
-    // sizes used by launchers
-    int64_t n_texels, max_rays, sort_blocks, scan_tmp_n, spill_lanes;
+
+struct AssetDev {
+    const float* hi_V;
+    const int32_t* hi_F;
+    const float* hi_N;
+    const float* lo_V;
+    const int32_t* lo_F;
+    const float* lo_UV;
+    float* out_map;
+    int32_t* out_hit;
+    uint8_t* out_rgb8;  // may be null
+    int32_t nhv, nhf, nlv, nlf;
+    int32_t res, log2res;
+    float max_dist;
+    int32_t index;  // position in the batch
+    // first element of this asset in the concatenated arrays
+    int64_t lv;     // lo vertices
+    int64_t lf;     // lo faces
+    int64_t hf;     // hi triangles (sort keys, leaves)
+    int64_t node;   // internal BVH nodes (nhf - 1 per asset)
+    int64_t tex;    // texels
+    int64_t stile;  // sort tiles of the BVH keys
+    int64_t btile;  // sort tiles of the backward pairs (capacity 3 res^2)
+    int64_t tl;     // treelet and frontier slots
 };
 
-// counters[] slots
-constexpr int kCntRays = 0;      // number of covered texels (rays)
-constexpr int kCntQueue = 1;     // persistent traversal work queue head
+// Inputs and outputs of the backward pass, one per asset.
+struct AssetGrad {
+    const float* grad_map;  // [res, res, 3]
+    float* grad_lo_V;       // [nlv, 3] or null
+    float* grad_hi_N;       // [nhv, 3] or null
+};
+
+// Grids: per-asset block counts of the launches, as prefix tables.
+enum GridId : int {
+    kGLoF = 0,  // lo faces, 256 per block
+    kGLoFWave,  // lo faces, one wave each (4 per block)
+    kGLoV,      // lo vertices, 256 per block
+    kGHiV,      // hi vertices, 256 per block
+    kGHiF,      // hi triangles, 256 per block
+    kGNode,     // internal nodes, 256 per block
+    kGAllNode,  // internal nodes + leaves, 256 per block
+    kGSort,     // BVH sort tiles (kSortTile keys per block)
+    kGTex,      // texels, 256 per block
+    kGTex3,     // texel channels, 256 per block
+    kGBwdSort,  // backward sort tiles (capacity 3 res^2, kSortTile per block)
+    kGridCount
+};
+
+constexpr int kSortTile = 4096;  // keys per radix-sort block and pass
+
+// Treelet and frontier capacity per asset.  Treelet roots are the small
+// children of the nodes with more than 2048 leaves ("big" nodes).  Big nodes
+// whose children are both small cover disjoint ranges of > 2048 leaves, so
+// there are fewer than n / 2048 of them, and every big node lies on the root
+// path (at most 62 nodes) of one of them: fewer than 62 n / 2048 + 62 big
+// nodes, one more treelet than big nodes.
+__host__ __device__ inline int64_t treelet_cap(int64_t n) { return n / 32 + 2 * kMaxDepth + 16; }
+
+// Per-asset counter slots.
+constexpr int kCntRays = 0;      // covered texels (rays)
 constexpr int kCntBoxLo = 2;     // u64 box tests (FLAG_COUNT), slots 2-3
 constexpr int kCntTriLo = 4;     // u64 triangle tests (FLAG_COUNT), slots 4-5
 constexpr int kCntFrontier = 6;  // refit frontier length
-constexpr int kCntTreelets = 7;  // number of refit treelets
-
-// Capacity of the treelet list and of the refit frontier.  Treelet roots are
-// the small children of the nodes with more than 2048 leaves ("big" nodes).
-// Big nodes whose children are both small cover disjoint ranges of > 2048
-// leaves, so there are fewer than n / 2048 of them, and every big node lies
-// on the root path (at most 62 nodes) of one of them: fewer than 62 n / 2048
-// + 62 big nodes, one more treelet than big nodes.
-inline int64_t treelet_cap(int64_t n) { return n / 32 + 2 * kMaxDepth + 16; }
+constexpr int kCntTreelets = 7;  // refit treelets
 constexpr int kCntSlots = 16;
+// Batch counter slots.
+constexpr int kGcQueue = 0;  // traversal work queue head
+constexpr int kGcSeal = 1;   // nonce of the last completed forward (0 while one runs)
+constexpr int kGcSlots = 16;
+
+// What every kernel receives: the asset table and the batch-wide tables.
+struct Batch {
+    const AssetDev* A;      // [n]
+    const AssetGrad* G;     // [n] (backward only)
+    const int32_t* gpf;     // [kGridCount][n + 1] block prefix of each grid
+    const uint32_t* ray_pf; // [n + 1] first ray of each asset (written after the raster)
+    const uint32_t* rb_pf;  // [n + 1] 64-ray batches before each asset
+    const uint32_t* tl_pf;  // [n + 1] treelets before each asset
+    uint32_t* cnt;          // [n][kCntSlots]
+    uint32_t* gcnt;         // [kGcSlots]
+    uint32_t* status;       // status word, OR over the batch
+    int n;
+    uint32_t seal;          // backward: the nonce the saved forward left in gcnt[kGcSeal]
+};
+
+// Backward kernels run only on the state of the forward they were planned
+// for: anything else (a workspace reused since) makes them do nothing.
+__device__ __forceinline__ bool sealed(const Batch& B) {
+    if (B.gcnt[kGcSeal] == B.seal) return true;
+    if (threadIdx.x == 0 && blockIdx.x == 0) atomicOr(B.status, kStState);
+    return false;
+}
+
+// Last index a in [0, n) with p[a] <= x (p ascending, p[0] <= x).
+template <typename T>
+__device__ __forceinline__ int upper_asset(const T* p, int n, int64_t x) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((int64_t)p[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Asset and asset-local block index of block `blk` of grid g.
+__device__ __forceinline__ int block_asset(const Batch& B, int g, int64_t blk, int64_t* local) {
+    const int32_t* p = B.gpf + (int64_t)g * (B.n + 1);
+    const int a = upper_asset(p, B.n, blk);
+    *local = blk - p[a];
+    return a;
+}
+
+__device__ __forceinline__ void set_status(const Batch& B, uint32_t bits) { atomicOr(B.status, bits); }
+
+// Host description of a batch: asset table, grid prefix tables and the
+// workspace layout.
+struct Layout {
+    size_t status, counters, gcnt, table, grads, gpf, ray_pf, rb_pf, tl_pf;
+    size_t lo_n, lo_deg, lo_off, lo_cur, lo_adj;  // lo vertex normals + vertex->face CSR
+    size_t face_t, face_uv, face_cnt, face_off;   // per lo face
+    size_t scan_tmp;                              // block sums of the scans
+    size_t facemap, level;                        // per texel
+    size_t rays, hits;                            // per ray
+    size_t bounds_part, bounds;                   // centroid bounds: per sort tile, per asset
+    size_t keys0, keys1, vals0, vals1, hist;      // radix sort of the BVH keys
+    size_t nodes, leaves, node_parent, leaf_parent, refit_cnt, node_range, frontier, treelets;
+    size_t spill;                                 // traversal stack spill
+    // backward scratch (BAKE_FLAG_SAVE only)
+    size_t bwd_ray, bwd_k0, bwd_v0, bwd_k1, bwd_v1, bwd_hist, bwd_face1, bwd_face2, bwd_sbar, bwd_vbar;
+    size_t total;
+    // batch totals
+    int n;
+    int64_t t_lv, t_lf, t_hv, t_hf, t_node, t_tex, t_stile, t_btile, t_tl;
+    int64_t spill_lanes, scan_tmp_n;
+    int max_hv_bits;  // bit length of the largest nhv (backward sort keys lie in [0, nhv])
+    bool save;
+};
+
+struct BatchHost {
+    Layout L;
+    const AssetDev* A = nullptr;  // [n] host copy of the table
+    const int32_t* gpf = nullptr; // [kGridCount][n + 1] host copy
+    char* ws = nullptr;           // device workspace
+    Batch dev;                    // kernel view (device pointers)
+    int64_t blocks(int g) const { return gpf[(int64_t)g * (L.n + 1) + L.n]; }
+};
 
 // Traversal configuration
 struct TravConfig {
     int block;    // 64 / 128 / 256
     int stack;    // LDS entries per lane: 8 / 16 / 32
-    int persist;  // 1: refill finished lanes from a work queue; 0: static striding
+    int persist;  // 1: refill finished lanes from a ray queue; 0: whole-wave 64-ray batches
     bool count = false;  // instrumented variant: count box and triangle tests
 };
 
@@ -121,36 +240,31 @@ int64_t scan_tmp_elems(int64_t n);
 hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp,
                               uint32_t* total, hipStream_t s);
 
-// Stable LSD radix sort of (key, value) pairs on the low `bits` bits, 8 per
-// pass, ping-ponging between (k0, v0) and (k1, v1); *result_in_1 tells where
-// the sorted pairs ended.  hist needs radix_hist_elems(n) u32.  With n_dev the
-// sorted length is min(n, n_mul * *n_dev) (a count that lives on the device).
-int64_t radix_hist_elems(int64_t n);
-hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n, int bits,
-                            uint32_t* hist, uint32_t* scan_tmp, bool* result_in_1, hipStream_t s,
-                            const uint32_t* n_dev = nullptr, uint32_t n_mul = 1);
+// Copies `bytes` host bytes to device memory through by-value kernel
+// arguments (no host-to-device copy, so it can be recorded in a graph).
+hipError_t write_table(void* dst, const void* src, size_t bytes, hipStream_t s);
 
-hipError_t launch_lo_prep(const float* lo_V, int64_t nlv, const int32_t* lo_F, int64_t nlf,
-                          const float* lo_UV, int32_t res, const Layout& L, char* ws,
-                          hipStream_t s);
-hipError_t launch_raster(int64_t nlf, int32_t res, const Layout& L, char* ws, hipStream_t s);
-hipError_t launch_bvh_build(const float* hi_V, int64_t nhv, const int32_t* hi_F, int64_t nhf,
-                            const Layout& L, char* ws, hipStream_t s);
-hipError_t launch_traverse(const float* lo_V, const int32_t* lo_F, int64_t nlf,
-                           const int32_t* hi_F, int64_t nhv, int64_t nhf, const float* hi_N,
-                           float max_dist,
-                           float* out_map, int32_t* out_hit, bool save, const TravConfig& cfg,
-                           const Layout& L, char* ws, hipStream_t s);
-hipError_t launch_fill_uncovered(int32_t res, float* out_map, int32_t* out_hit, const Layout& L,
-                                 char* ws, hipStream_t s);
-hipError_t launch_dilate(int32_t res, int passes, float* out_map, const Layout& L, char* ws,
-                         hipStream_t s);
-hipError_t launch_rgb8(int32_t res, const float* out_map, uint8_t* rgb, hipStream_t s);
+// Per-asset ray starts and 64-ray batch prefix (after the raster); treelet
+// prefix (after the treelet search).
+hipError_t launch_ray_spaces(const BatchHost& H, hipStream_t s);
+hipError_t launch_treelet_space(const BatchHost& H, hipStream_t s);
 
-hipError_t launch_backward(const float* hi_V, const int32_t* hi_F, int64_t nhv, const float* hi_N,
-                           const float* lo_V, const int32_t* lo_F, int64_t nlv, int64_t nlf,
-                           const float* grad_map, float* grad_lo_V, float* grad_hi_N, const Layout& L,
-                           char* ws, hipStream_t s);
+// Stable LSD radix sort of every asset's (key, value) pairs on the low `bits`
+// bits, 8 per pass, ping-ponging between the two buffers of the sort:
+// kSortBvh: the Morton keys (keys0/vals0 <-> keys1/vals1); kSortBwd: the
+// backward pairs (bwd_k0/bwd_v0 <-> bwd_k1/bwd_v1), three per ray.
+// *result_in_1 tells which buffer holds the result (the same for all assets).
+enum SortWhich : int { kSortBvh = 0, kSortBwd = 1 };
+hipError_t launch_sort(const BatchHost& H, int which, int bits, bool* result_in_1, hipStream_t s);
+
+hipError_t launch_lo_prep(const BatchHost& H, hipStream_t s);
+hipError_t launch_raster(const BatchHost& H, hipStream_t s);
+hipError_t launch_fill_uncovered(const BatchHost& H, hipStream_t s);
+hipError_t launch_bvh_build(const BatchHost& H, hipStream_t s);
+hipError_t launch_traverse(const BatchHost& H, const TravConfig& cfg, hipStream_t s);
+hipError_t launch_dilate(const BatchHost& H, int passes, hipStream_t s);
+hipError_t launch_rgb8(const BatchHost& H, hipStream_t s);
+hipError_t launch_backward(const BatchHost& H, bool any_lo, bool any_hi, hipStream_t s);
 hipError_t launch_sq_loss(const float* map, const float* target, int64_t n3, float* grad, float* loss,
                           float* partial, hipStream_t s);
 

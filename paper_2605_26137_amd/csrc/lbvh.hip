@@ -11,6 +11,9 @@
 //      bottom-up refit: per internal node an arrival counter; the second
 //      arriving child unions both boxes and continues upward.  min/max is
 //      exact, so the boxes do not depend on arrival order.
+// In a batch every asset gets its own tree over its own bounds; sort tiles
+// never straddle two assets, and one batch-wide scan of the digit counts
+// (asset-major) gives every key its place in the concatenated key arrays.
 #include <algorithm>
 #include <utility>
 
@@ -21,9 +24,7 @@ namespace bake {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kSortRounds = 16;
-constexpr int kSortTile = kBlock * kSortRounds;  // 4096 keys per block and pass
-constexpr int kBoundsBlocks = 512;
+constexpr int kSortRounds = kSortTile / kBlock;  // 16 keys per thread and pass
 constexpr float kLeafEps = 1.0f / 16384.0f;  // edge tolerance of the hit rule (traverse.hip)
 
 __device__ __forceinline__ int3 tri_idx(const int32_t* __restrict__ F, int64_t g, int64_t nv,
@@ -45,8 +46,10 @@ __device__ __forceinline__ float3 centroid(const float* __restrict__ V, int3 t) 
     return make_float3((a.x + b.x + c.x) * k, (a.y + b.y + c.y) * k, (a.z + b.z + c.z) * k);
 }
 
+__device__ __forceinline__ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
 // ---------------------------------------------------------------------------
-// 1. centroid bounds
+// 1. centroid bounds: a partial per sort tile, then one workgroup per asset
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ float wave_min(float v) {
@@ -79,16 +82,17 @@ __device__ void block_minmax6(float v[6], float* out) {
     }
 }
 
-__global__ __launch_bounds__(kBlock) void bounds_part_kernel(const float* __restrict__ V, int64_t nv,
-                                                             const int32_t* __restrict__ F, int64_t nf,
-                                                             float* __restrict__ part,
-                                                             uint32_t* __restrict__ status) {
+__global__ __launch_bounds__(kBlock) void bounds_part_kernel(Batch Bt, float* __restrict__ part) {
+    int64_t lt;
+    const AssetDev& As = Bt.A[block_asset(Bt, kGSort, blockIdx.x, &lt)];
+    const float* __restrict__ V = As.hi_V;
+    const int32_t* __restrict__ F = As.hi_F;
     float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
     bool anybad = false, nonfin = false;
-    for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < nf;
-         g += (int64_t)gridDim.x * kBlock) {
+    const int64_t end = min((int64_t)As.nhf, (lt + 1) * kSortTile);
+    for (int64_t g = lt * kSortTile + threadIdx.x; g < end; g += kBlock) {
         bool bad;
-        int3 t = tri_idx(F, g, nv, &bad);
+        int3 t = tri_idx(F, g, As.nhv, &bad);
         anybad |= bad;
         float3 c = centroid(V, t);
         if (!(isfinite(c.x) && isfinite(c.y) && isfinite(c.z))) {
@@ -98,23 +102,26 @@ __global__ __launch_bounds__(kBlock) void bounds_part_kernel(const float* __rest
         v[0] = fminf(v[0], c.x); v[1] = fminf(v[1], c.y); v[2] = fminf(v[2], c.z);
         v[3] = fmaxf(v[3], c.x); v[4] = fmaxf(v[4], c.y); v[5] = fmaxf(v[5], c.z);
     }
-    if (anybad) atomicOr(status, kStHiIndex);
-    if (nonfin) atomicOr(status, kStNonFinite);
-    block_minmax6(v, part + 6 * blockIdx.x);
+    if (anybad) set_status(Bt, kStHiIndex);
+    if (nonfin) set_status(Bt, kStNonFinite);
+    block_minmax6(v, part + 6 * (As.stile + lt));
 }
 
-__global__ __launch_bounds__(kBlock) void bounds_final_kernel(const float* __restrict__ part, int nparts,
+__global__ __launch_bounds__(kBlock) void bounds_final_kernel(Batch Bt, const float* __restrict__ part,
                                                               float* __restrict__ bounds) {
+    const AssetDev& As = Bt.A[blockIdx.x];
+    const int64_t nparts = ceil_div(As.nhf, kSortTile);
+    const float* p = part + 6 * As.stile;
     float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
-    for (int i = threadIdx.x; i < nparts; i += kBlock) {
-        for (int k = 0; k < 3; ++k) v[k] = fminf(v[k], part[6 * i + k]);
-        for (int k = 3; k < 6; ++k) v[k] = fmaxf(v[k], part[6 * i + k]);
+    for (int64_t i = threadIdx.x; i < nparts; i += kBlock) {
+        for (int k = 0; k < 3; ++k) v[k] = fminf(v[k], p[6 * i + k]);
+        for (int k = 3; k < 6; ++k) v[k] = fmaxf(v[k], p[6 * i + k]);
     }
-    block_minmax6(v, bounds);
+    block_minmax6(v, bounds + 6 * (int64_t)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
-// 2. Morton codes
+// 2. Morton codes (value = asset-local triangle index)
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ uint32_t spread10(uint32_t x) {
@@ -133,76 +140,99 @@ __device__ __forceinline__ uint32_t quant10(float c, float lo, float inv) {
     return (uint32_t)q;
 }
 
-__global__ void morton_kernel(const float* __restrict__ V, int64_t nv, const int32_t* __restrict__ F,
-                              int64_t nf, const float* __restrict__ bounds,
-                              uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= nf) return;
+__global__ __launch_bounds__(kBlock) void morton_kernel(Batch Bt, const float* __restrict__ bounds_all,
+                                                        uint32_t* __restrict__ keys,
+                                                        uint32_t* __restrict__ vals) {
+    int64_t lb;
+    const int a = block_asset(Bt, kGHiF, blockIdx.x, &lb);
+    const AssetDev& As = Bt.A[a];
+    const int64_t g = lb * kBlock + threadIdx.x;
+    if (g >= As.nhf) return;
+    const float* bounds = bounds_all + 6 * (int64_t)a;
     bool bad;
-    int3 t = tri_idx(F, g, nv, &bad);
-    float3 c = centroid(V, t);
+    int3 t = tri_idx(As.hi_F, g, As.nhv, &bad);
+    float3 c = centroid(As.hi_V, t);
     float ex = bounds[3] - bounds[0], ey = bounds[4] - bounds[1], ez = bounds[5] - bounds[2];
     float ix = ex > 0.f ? 1.0f / ex : 0.f, iy = ey > 0.f ? 1.0f / ey : 0.f,
           iz = ez > 0.f ? 1.0f / ez : 0.f;
     uint32_t x = quant10(c.x, bounds[0], ix), y = quant10(c.y, bounds[1], iy),
              z = quant10(c.z, bounds[2], iz);
-    keys[g] = (spread10(x) << 2) | (spread10(y) << 1) | spread10(z);
-    vals[g] = (uint32_t)g;
+    keys[As.hf + g] = (spread10(x) << 2) | (spread10(y) << 1) | spread10(z);
+    vals[As.hf + g] = (uint32_t)g;
 }
 
 // ---------------------------------------------------------------------------
-// 3. stable LSD radix sort, 8-bit digits
+// 3. stable LSD radix sort, 8-bit digits, per asset
 // ---------------------------------------------------------------------------
 
-// n_dev (optional): the element count is min(n, n_mul * *n_dev); the grid is
-// sized for n and blocks past the device count find nothing to do.
-__device__ __forceinline__ int64_t eff_count(int64_t n, const uint32_t* n_dev, uint32_t n_mul) {
-    if (!n_dev) return n;
-    int64_t m = (int64_t)n_mul * (int64_t)(*n_dev);
-    return m < n ? m : n;
+// The tile of a sort block: its asset's keys [start, start + count) in the
+// concatenated arrays, its digit-count column (hist[hbase + digit * tiles +
+// lt]) and its local tile lt.  BWD: the backward pairs, whose count lives on
+// the device (three per ray), with tiles sized for the capacity 3 res^2.
+struct SortTile {
+    int64_t start, count, hbase, tiles, lt;
+};
+
+template <bool BWD>
+__device__ __forceinline__ SortTile sort_tile(const Batch& Bt, int64_t blk) {
+    SortTile T;
+    const int a = block_asset(Bt, BWD ? kGBwdSort : kGSort, blk, &T.lt);
+    const AssetDev& As = Bt.A[a];
+    if (BWD) {
+        T.start = 3 * (int64_t)Bt.ray_pf[a];
+        T.count = 3 * (int64_t)Bt.cnt[(int64_t)a * kCntSlots + kCntRays];
+        T.hbase = 256 * As.btile;
+        T.tiles = ceil_div(3 * (int64_t)As.res * As.res, kSortTile);
+    } else {
+        T.start = As.hf;
+        T.count = As.nhf;
+        T.hbase = 256 * As.stile;
+        T.tiles = ceil_div(As.nhf, kSortTile);
+    }
+    return T;
 }
 
-__global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __restrict__ keys,
-                                                            int64_t n_host, const uint32_t* n_dev,
-                                                            uint32_t n_mul, int shift, int64_t nb,
-                                                            uint32_t* __restrict__ hist) {
+template <bool BWD>
+__global__ __launch_bounds__(kBlock) void radix_hist_kernel(Batch Bt, const uint32_t* __restrict__ keys,
+                                                            int shift, uint32_t* __restrict__ hist) {
     __shared__ uint32_t h[256];
-    const int64_t n = eff_count(n_host, n_dev, n_mul);
+    if (BWD && !sealed(Bt)) return;
+    const SortTile T = sort_tile<BWD>(Bt, blockIdx.x);
     h[threadIdx.x] = 0;
     __syncthreads();
-    int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const int64_t base = T.lt * kSortTile;
 #pragma unroll 4
     for (int r = 0; r < kSortRounds; ++r) {
         int64_t i = base + (int64_t)r * kBlock + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+        if (i < T.count) atomicAdd(&h[(keys[T.start + i] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+    hist[T.hbase + (int64_t)threadIdx.x * T.tiles + T.lt] = h[threadIdx.x];
 }
 
 // Element r*256 + tid of the block's tile is ranked among equal digits by
-// (earlier rounds, earlier waves, earlier lanes): a stable order.
-__global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t* __restrict__ kin,
+// (earlier rounds, earlier waves, earlier lanes): a stable order.  The scanned
+// digit counts are positions in the concatenated arrays.
+template <bool BWD>
+__global__ __launch_bounds__(kBlock) void radix_scatter_kernel(Batch Bt, const uint32_t* __restrict__ kin,
                                                                const uint32_t* __restrict__ vin,
                                                                uint32_t* __restrict__ kout,
-                                                               uint32_t* __restrict__ vout, int64_t n_host,
-                                                               const uint32_t* n_dev, uint32_t n_mul,
-                                                               int shift, int64_t nb,
+                                                               uint32_t* __restrict__ vout, int shift,
                                                                const uint32_t* __restrict__ offs) {
     __shared__ uint32_t run[256];
-    const int64_t n = eff_count(n_host, n_dev, n_mul);
     __shared__ uint32_t wcnt[kBlock / 64][256];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    (void)lane;
-    run[tid] = offs[(int64_t)tid * nb + blockIdx.x];
+    if (BWD && !sealed(Bt)) return;
+    const SortTile T = sort_tile<BWD>(Bt, blockIdx.x);
+    const int tid = threadIdx.x, wave = tid >> 6;
+    run[tid] = offs[T.hbase + (int64_t)tid * T.tiles + T.lt];
 #pragma unroll
     for (int w = 0; w < kBlock / 64; ++w) wcnt[w][tid] = 0;
     __syncthreads();
-    int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const int64_t base = T.lt * kSortTile;
     for (int r = 0; r < kSortRounds; ++r) {
         int64_t i = base + (int64_t)r * kBlock + tid;
-        bool valid = i < n;
-        uint32_t key = valid ? kin[i] : 0u, val = valid ? vin[i] : 0u;
+        bool valid = i < T.count;
+        uint32_t key = valid ? kin[T.start + i] : 0u, val = valid ? vin[T.start + i] : 0u;
         uint32_t dig = (key >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -246,11 +276,20 @@ __device__ __forceinline__ int cprefix(const uint32_t* __restrict__ k, int64_t n
     return __clz(a ^ b);
 }
 
-__global__ void karras_kernel(const uint32_t* __restrict__ keys, int64_t n, BvhNode* __restrict__ nodes,
-                              int32_t* __restrict__ node_parent, int32_t* __restrict__ leaf_parent,
-                              int2* __restrict__ node_range) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void karras_kernel(Batch Bt, const uint32_t* __restrict__ keys_all,
+                                                        BvhNode* __restrict__ nodes_all,
+                                                        int32_t* __restrict__ np_all,
+                                                        int32_t* __restrict__ lp_all,
+                                                        int2* __restrict__ range_all) {
+    int64_t lb;
+    const AssetDev& As = Bt.A[block_asset(Bt, kGNode, blockIdx.x, &lb)];
+    const int64_t n = As.nhf;
+    const int64_t i = lb * kBlock + threadIdx.x;
     if (i >= n - 1) return;
+    const uint32_t* __restrict__ keys = keys_all + As.hf;
+    BvhNode* __restrict__ nodes = nodes_all + As.node;
+    int32_t* __restrict__ node_parent = np_all + As.node;
+    int32_t* __restrict__ leaf_parent = lp_all + As.hf;
     int d = (cprefix(keys, n, i, i + 1) - cprefix(keys, n, i, i - 1)) >= 0 ? 1 : -1;
     int dmin = cprefix(keys, n, i, i - d);
     int64_t lmax = 2;
@@ -270,7 +309,7 @@ __global__ void karras_kernel(const uint32_t* __restrict__ keys, int64_t n, BvhN
     int32_t left = lo == gamma ? ~(int32_t)gamma : (int32_t)gamma;
     int32_t right = hi == gamma + 1 ? ~(int32_t)(gamma + 1) : (int32_t)(gamma + 1);
     nodes[i].ref = make_int4(left, right, 0, 0);
-    node_range[i] = make_int2((int32_t)lo, (int32_t)hi);
+    range_all[As.node + i] = make_int2((int32_t)lo, (int32_t)hi);
     if (left < 0) leaf_parent[gamma] = (int32_t)(i << 1);
     else node_parent[gamma] = (int32_t)(i << 1);
     if (right < 0) leaf_parent[gamma + 1] = (int32_t)((i << 1) | 1);
@@ -308,20 +347,21 @@ __device__ __forceinline__ void put_slot(BvhNode* node, int side, const float b[
     for (int k = 0; k < 6; ++k) f[k] = b[k];
 }
 
-__global__ void leaf_pack_kernel(const float* __restrict__ V, int64_t nv, const int32_t* __restrict__ F,
-                                 int64_t n, const uint32_t* __restrict__ sorted_idx,
-                                 Leaf* __restrict__ leaves) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    uint32_t g = sorted_idx[k];
+__global__ __launch_bounds__(kBlock) void leaf_pack_kernel(Batch Bt, const uint32_t* __restrict__ sorted_idx,
+                                                           Leaf* __restrict__ leaves) {
+    int64_t lb;
+    const AssetDev& As = Bt.A[block_asset(Bt, kGHiF, blockIdx.x, &lb)];
+    const int64_t k = lb * kBlock + threadIdx.x;
+    if (k >= As.nhf) return;
+    uint32_t g = sorted_idx[As.hf + k];
     bool bad;
-    int3 t = tri_idx(F, g, nv, &bad);
-    float3 a = ldv(V, t.x), b = ldv(V, t.y), c = ldv(V, t.z);
+    int3 t = tri_idx(As.hi_F, g, As.nhv, &bad);
+    float3 a = ldv(As.hi_V, t.x), b = ldv(As.hi_V, t.y), c = ldv(As.hi_V, t.z);
     Leaf lf;
     lf.a = make_float4(a.x, a.y, a.z, b.x);
     lf.b = make_float4(b.y, b.z, c.x, c.y);
     lf.c = make_float4(c.z, __int_as_float((int32_t)g), 0.f, 0.f);
-    leaves[k] = lf;
+    leaves[As.hf + k] = lf;
 }
 
 // Box of a leaf triangle, widened for the hit rule's edge tolerance: weights
@@ -343,46 +383,60 @@ __device__ __forceinline__ void leaf_box(const Leaf& L, float box[6]) {
 }
 
 // Treelet roots: nodes (internal i < n-1, or leaf ~k) of at most kTreelet
-// leaves whose parent has more (or that are the root).
-__global__ void treelet_find_kernel(int64_t n, const int2* __restrict__ node_range,
-                                    const int32_t* __restrict__ node_parent,
-                                    const int32_t* __restrict__ leaf_parent, int4* __restrict__ list,
-                                    uint32_t* __restrict__ count, uint32_t cap, uint32_t* __restrict__ status) {
-    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// leaves whose parent has more (or that are the root).  Entries are
+// asset-local (ref, lo, hi, parent link).
+__global__ __launch_bounds__(kBlock) void treelet_find_kernel(Batch Bt, const int2* __restrict__ range_all,
+                                                              const int32_t* __restrict__ np_all,
+                                                              const int32_t* __restrict__ lp_all,
+                                                              int4* __restrict__ list_all) {
+    int64_t lb;
+    const int a = block_asset(Bt, kGAllNode, blockIdx.x, &lb);
+    const AssetDev& As = Bt.A[a];
+    const int64_t n = As.nhf;
+    const int64_t x = lb * kBlock + threadIdx.x;
     if (x >= 2 * n - 1) return;
+    const int2* __restrict__ node_range = range_all + As.node;
     int32_t ref, lo, hi, pp;
     if (x < n - 1) {
         int2 r = node_range[x];
         ref = (int32_t)x; lo = r.x; hi = r.y;
-        pp = node_parent[x];
+        pp = np_all[As.node + x];
     } else {
         int32_t k = (int32_t)(x - (n - 1));
         ref = ~k; lo = hi = k;
-        pp = n > 1 ? leaf_parent[k] : -1;
+        pp = n > 1 ? lp_all[As.hf + k] : -1;
     }
     if (hi - lo + 1 > kTreelet) return;
     if (pp >= 0) {
         int2 pr = node_range[pp >> 1];
         if (pr.y - pr.x + 1 <= kTreelet) return;
     }
-    uint32_t e = atomicAdd(count, 1u);
-    if (e < cap) list[e] = make_int4(ref, lo, hi, pp);
-    else atomicOr(status, kStInternal);
+    uint32_t e = atomicAdd(&Bt.cnt[(int64_t)a * kCntSlots + kCntTreelets], 1u);
+    if (e < (uint32_t)treelet_cap(n)) list_all[As.tl + e] = make_int4(ref, lo, hi, pp);
+    else set_status(Bt, kStInternal);
 }
 
+// Workgroups take the batch's treelets in turn (the treelet prefix over the
+// assets is known on the device only).
 __global__ __launch_bounds__(kRefitBlock) void treelet_refit_kernel(
-    int64_t n, const Leaf* __restrict__ leaves, BvhNode* nodes,
-    const int32_t* __restrict__ node_parent, const int32_t* __restrict__ leaf_parent,
-    const int4* __restrict__ list, const uint32_t* __restrict__ count, uint32_t cap,
-    int32_t* __restrict__ frontier, uint32_t* __restrict__ nfront, uint32_t front_cap,
-    uint32_t* __restrict__ status) {
+    Batch Bt, const Leaf* __restrict__ leaves_all, BvhNode* nodes_all, const int32_t* __restrict__ np_all,
+    const int32_t* __restrict__ lp_all, const int4* __restrict__ list_all, int32_t* __restrict__ frontier_all) {
     __shared__ int32_t s_np[kTreelet];      // parent link of internal node lo + i
     __shared__ int32_t s_lp[kTreelet];      // parent link of leaf lo + i
     __shared__ uint32_t s_cnt[kTreelet];    // arrivals at internal node lo + i
     __shared__ float s_box[kTreelet][2][6]; // child boxes of internal node lo + i, by side
-    const uint32_t m = min(*count, cap);
-    for (uint32_t tl = blockIdx.x; tl < m; tl += gridDim.x) {
-        const int4 T = list[tl];
+    const uint32_t total = Bt.tl_pf[Bt.n];
+    for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
+        const int a = upper_asset(Bt.tl_pf, Bt.n, g);
+        const AssetDev& As = Bt.A[a];
+        const int64_t n = As.nhf;
+        const Leaf* __restrict__ leaves = leaves_all + As.hf;
+        BvhNode* nodes = nodes_all + As.node;
+        const int32_t* __restrict__ node_parent = np_all + As.node;
+        const int32_t* __restrict__ leaf_parent = lp_all + As.hf;
+        uint32_t* nfront = &Bt.cnt[(int64_t)a * kCntSlots + kCntFrontier];
+        const uint32_t front_cap = (uint32_t)treelet_cap(n);
+        const int4 T = list_all[As.tl + (g - Bt.tl_pf[a])];
         const int32_t ref = T.x, lo = T.y, hi = T.z, rootpp = T.w;
         const int32_t sz = hi - lo + 1;
         for (int i = threadIdx.x; i < sz; i += kRefitBlock) {
@@ -402,18 +456,18 @@ __global__ __launch_bounds__(kRefitBlock) void treelet_refit_kernel(
                     if (rootpp >= 0) {
                         put_slot(&nodes[rootpp >> 1], rootpp & 1, box);
                         uint32_t e = atomicAdd(nfront, 1u);
-                        if (e < front_cap) frontier[e] = rootpp;
-                        else atomicOr(status, kStInternal);
+                        if (e < front_cap) frontier_all[As.tl + e] = rootpp;
+                        else set_status(Bt, kStInternal);
                     }
                     break;
                 }
                 if (level > 2 * kMaxDepth || pp < 0) {  // only a malformed hierarchy gets here
-                    atomicOr(status, kStInternal);
+                    set_status(Bt, kStInternal);
                     break;
                 }
                 const int32_t p = pp >> 1, side = pp & 1, li = p - lo;
                 if (li < 0 || li >= sz) {  // only a malformed hierarchy gets here
-                    atomicOr(status, kStInternal);
+                    set_status(Bt, kStInternal);
                     break;
                 }
                 // each child leaves its box in its own LDS slot of p and
@@ -441,21 +495,26 @@ __global__ __launch_bounds__(kRefitBlock) void treelet_refit_kernel(
     }
 }
 
-// Top pass: one workgroup climbs from the frontier through the nodes above
-// the treelets.  Each frontier entry says: child `side` of node p is complete and its
-// box is in p's slot.
-__global__ __launch_bounds__(kTopBlock) void refit_top_kernel(BvhNode* nodes,
-                                                             const int32_t* __restrict__ node_parent,
-                                                             const int32_t* __restrict__ frontier,
-                                                             const uint32_t* __restrict__ nfront,
-                                                             uint32_t front_cap, uint32_t* cnt,
-                                                             uint32_t* __restrict__ status) {
-    const uint32_t m = min(*nfront, front_cap);
+// Top pass: one workgroup per asset climbs from its frontier through the nodes
+// above the treelets.  Each frontier entry says: child `side` of node p is
+// complete and its box is in p's slot.
+__global__ __launch_bounds__(kTopBlock) void refit_top_kernel(Batch Bt, BvhNode* nodes_all,
+                                                             const int32_t* __restrict__ np_all,
+                                                             const int32_t* __restrict__ frontier_all,
+                                                             uint32_t* cnt_all) {
+    const int a = blockIdx.x;
+    const AssetDev& As = Bt.A[a];
+    if (As.nhf <= 1) return;
+    BvhNode* nodes = nodes_all + As.node;
+    const int32_t* __restrict__ node_parent = np_all + As.node;
+    const int32_t* __restrict__ frontier = frontier_all + As.tl;
+    uint32_t* cnt = cnt_all + As.node;
+    const uint32_t m = min(Bt.cnt[(int64_t)a * kCntSlots + kCntFrontier], (uint32_t)treelet_cap(As.nhf));
     for (uint32_t e = threadIdx.x; e < m; e += kTopBlock) {
         int32_t pp = frontier[e];
         for (int level = 0; pp >= 0; ++level) {
             if (level > 2 * kMaxDepth) {
-                atomicOr(status, kStInternal);
+                set_status(Bt, kStInternal);
                 break;
             }
             int32_t p = pp >> 1;
@@ -478,23 +537,37 @@ inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b
 
 }  // namespace
 
-int64_t radix_hist_elems(int64_t n) { return 256 * ((n + kSortTile - 1) / kSortTile); }
-
-hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n, int bits,
-                            uint32_t* hist, uint32_t* scan_tmp, bool* result_in_1, hipStream_t s,
-                            const uint32_t* n_dev, uint32_t n_mul) {
+hipError_t launch_sort(const BatchHost& H, int which, int bits, bool* result_in_1, hipStream_t s) {
+    const Layout& L = H.L;
+    const bool bwd = which == kSortBwd;
+    const int64_t blocks = H.blocks(bwd ? kGBwdSort : kGSort);
     *result_in_1 = false;
-    if (n <= 0) return hipSuccess;
+    if (blocks == 0) return hipSuccess;
+    uint32_t* kin = (uint32_t*)(H.ws + (bwd ? L.bwd_k0 : L.keys0));
+    uint32_t* vin = (uint32_t*)(H.ws + (bwd ? L.bwd_v0 : L.vals0));
+    uint32_t* kout = (uint32_t*)(H.ws + (bwd ? L.bwd_k1 : L.keys1));
+    uint32_t* vout = (uint32_t*)(H.ws + (bwd ? L.bwd_v1 : L.vals1));
+    uint32_t* hist = (uint32_t*)(H.ws + (bwd ? L.bwd_hist : L.hist));
+    uint32_t* tmp = (uint32_t*)(H.ws + L.scan_tmp);
     hipError_t e;
-    int64_t nb = (n + kSortTile - 1) / kSortTile;
-    uint32_t* kin = k0; uint32_t* vin = v0; uint32_t* kout = k1; uint32_t* vout = v1;
     for (int shift = 0; shift < bits; shift += 8) {
-        hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nb), dim3(kBlock), 0, s,
-                           (const uint32_t*)kin, n, n_dev, n_mul, shift, nb, hist);
-        if ((e = exclusive_scan_u32(hist, hist, 256 * nb, scan_tmp, nullptr, s)) != hipSuccess) return e;
-        hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nb), dim3(kBlock), 0, s,
-                           (const uint32_t*)kin, (const uint32_t*)vin, kout, vout, n, n_dev, n_mul, shift,
-                           nb, (const uint32_t*)hist);
+        if (bwd) {
+            hipLaunchKernelGGL(radix_hist_kernel<true>, dim3((unsigned)blocks), dim3(kBlock), 0, s, H.dev,
+                               (const uint32_t*)kin, shift, hist);
+        } else {
+            hipLaunchKernelGGL(radix_hist_kernel<false>, dim3((unsigned)blocks), dim3(kBlock), 0, s, H.dev,
+                               (const uint32_t*)kin, shift, hist);
+        }
+        if ((e = exclusive_scan_u32(hist, hist, 256 * blocks, tmp, nullptr, s)) != hipSuccess) return e;
+        if (bwd) {
+            hipLaunchKernelGGL(radix_scatter_kernel<true>, dim3((unsigned)blocks), dim3(kBlock), 0, s, H.dev,
+                               (const uint32_t*)kin, (const uint32_t*)vin, kout, vout, shift,
+                               (const uint32_t*)hist);
+        } else {
+            hipLaunchKernelGGL(radix_scatter_kernel<false>, dim3((unsigned)blocks), dim3(kBlock), 0, s, H.dev,
+                               (const uint32_t*)kin, (const uint32_t*)vin, kout, vout, shift,
+                               (const uint32_t*)hist);
+        }
         std::swap(kin, kout);
         std::swap(vin, vout);
         *result_in_1 = !*result_in_1;
@@ -502,65 +575,56 @@ hipError_t radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* 
     return hipGetLastError();
 }
 
-hipError_t launch_bvh_build(const float* hi_V, int64_t nhv, const int32_t* hi_F, int64_t nhf,
-                            const Layout& L, char* ws, hipStream_t s) {
-    if (nhf <= 0) return hipSuccess;
+hipError_t launch_bvh_build(const BatchHost& H, hipStream_t s) {
+    const Layout& L = H.L;
+    if (L.t_hf <= 0) return hipSuccess;
+    char* ws = H.ws;
     hipError_t e;
     float* part = (float*)(ws + L.bounds_part);
     float* bounds = (float*)(ws + L.bounds);
     uint32_t* k0 = (uint32_t*)(ws + L.keys0);
-    uint32_t* k1 = (uint32_t*)(ws + L.keys1);
     uint32_t* v0 = (uint32_t*)(ws + L.vals0);
-    uint32_t* v1 = (uint32_t*)(ws + L.vals1);
-    uint32_t* hist = (uint32_t*)(ws + L.hist);
     BvhNode* nodes = (BvhNode*)(ws + L.nodes);
     Leaf* leaves = (Leaf*)(ws + L.leaves);
     int32_t* np = (int32_t*)(ws + L.node_parent);
     int32_t* lp = (int32_t*)(ws + L.leaf_parent);
     uint32_t* cnt = (uint32_t*)(ws + L.refit_cnt);
     int2* range = (int2*)(ws + L.node_range);
-    uint32_t* status = (uint32_t*)(ws + L.status);
+    int32_t* frontier = (int32_t*)(ws + L.frontier);
+    int4* tlist = (int4*)(ws + L.treelets);
 
-    int parts = (int)std::min<int64_t>(kBoundsBlocks, (nhf + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(bounds_part_kernel, dim3(parts), dim3(kBlock), 0, s, hi_V, nhv, hi_F, nhf,
-                       part, status);
-    hipLaunchKernelGGL(bounds_final_kernel, dim3(1), dim3(kBlock), 0, s, (const float*)part, parts,
-                       bounds);
-    hipLaunchKernelGGL(morton_kernel, dim3(blocks_for(nhf, kBlock)), dim3(kBlock), 0, s, hi_V, nhv,
-                       hi_F, nhf, (const float*)bounds, k0, v0);
+    hipLaunchKernelGGL(bounds_part_kernel, dim3((unsigned)H.blocks(kGSort)), dim3(kBlock), 0, s, H.dev, part);
+    hipLaunchKernelGGL(bounds_final_kernel, dim3((unsigned)L.n), dim3(kBlock), 0, s, H.dev,
+                       (const float*)part, bounds);
+    hipLaunchKernelGGL(morton_kernel, dim3((unsigned)H.blocks(kGHiF)), dim3(kBlock), 0, s, H.dev,
+                       (const float*)bounds, k0, v0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
 
     bool in1 = false;
-    if ((e = radix_sort_pairs(k0, v0, k1, v1, nhf, 30, hist, (uint32_t*)(ws + L.scan_tmp), &in1, s)) !=
-        hipSuccess)
-        return e;
+    if ((e = launch_sort(H, kSortBvh, 30, &in1, s)) != hipSuccess) return e;
     // 30-bit keys take four 8-bit passes: the sorted arrays are back in keys0 / vals0
-    if (nhf > 1) {
-        hipLaunchKernelGGL(karras_kernel, dim3(blocks_for(nhf - 1, kBlock)), dim3(kBlock), 0, s,
-                           (const uint32_t*)k0, nhf, nodes, np, lp, range);
-        if ((e = fill_u32(cnt, 0, nhf - 1, s)) != hipSuccess) return e;
+    if (H.blocks(kGNode) > 0) {
+        hipLaunchKernelGGL(karras_kernel, dim3((unsigned)H.blocks(kGNode)), dim3(kBlock), 0, s, H.dev,
+                           (const uint32_t*)k0, nodes, np, lp, range);
+        if ((e = fill_u32(cnt, 0, L.t_node, s)) != hipSuccess) return e;
     }
-    uint32_t* counters = (uint32_t*)(ws + L.counters);
-    uint32_t* nfront = counters + kCntFrontier;
-    uint32_t* ntl = counters + kCntTreelets;
-    int32_t* frontier = (int32_t*)(ws + L.frontier);
-    int4* tlist = (int4*)(ws + L.treelets);
-    const uint32_t tcap = (uint32_t)treelet_cap(nhf);
-    const uint32_t front_cap = tcap;
-    if ((e = fill_u32(nfront, 0, 2, s)) != hipSuccess) return e;  // frontier + treelet counts
-    hipLaunchKernelGGL(leaf_pack_kernel, dim3(blocks_for(nhf, kBlock)), dim3(kBlock), 0, s, hi_V, nhv,
-                       hi_F, nhf, (const uint32_t*)v0, leaves);
-    hipLaunchKernelGGL(treelet_find_kernel, dim3(blocks_for(2 * nhf - 1, kBlock)), dim3(kBlock), 0, s,
-                       nhf, (const int2*)range, (const int32_t*)np, (const int32_t*)lp, tlist, ntl, tcap,
-                       status);
-    if (nhf > 1) {
-        int grid = (int)std::min<int64_t>(2048, (nhf + kTreelet / 2 - 1) / (kTreelet / 2) + 1);
-        hipLaunchKernelGGL(treelet_refit_kernel, dim3(grid), dim3(kRefitBlock), 0, s, nhf,
+    hipLaunchKernelGGL(leaf_pack_kernel, dim3((unsigned)H.blocks(kGHiF)), dim3(kBlock), 0, s, H.dev,
+                       (const uint32_t*)v0, leaves);
+    hipLaunchKernelGGL(treelet_find_kernel, dim3((unsigned)H.blocks(kGAllNode)), dim3(kBlock), 0, s, H.dev,
+                       (const int2*)range, (const int32_t*)np, (const int32_t*)lp, tlist);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (L.t_node > 0) {
+        if ((e = launch_treelet_space(H, s)) != hipSuccess) return e;
+        // enough workgroups for the treelets of every asset (at least one per
+        // kTreelet / 2 leaves), capped
+        int64_t grid = 0;
+        for (int a = 0; a < L.n; ++a) grid += H.A[a].nhf / (kTreelet / 2) + 1;
+        grid = std::min<int64_t>(grid, 2048);
+        hipLaunchKernelGGL(treelet_refit_kernel, dim3((unsigned)grid), dim3(kRefitBlock), 0, s, H.dev,
                            (const Leaf*)leaves, nodes, (const int32_t*)np, (const int32_t*)lp,
-                           (const int4*)tlist, (const uint32_t*)ntl, tcap, frontier, nfront, front_cap,
-                           status);
-        hipLaunchKernelGGL(refit_top_kernel, dim3(1), dim3(kTopBlock), 0, s, nodes, (const int32_t*)np,
-                           (const int32_t*)frontier, (const uint32_t*)nfront, front_cap, cnt, status);
+                           (const int4*)tlist, frontier);
+        hipLaunchKernelGGL(refit_top_kernel, dim3((unsigned)L.n), dim3(kTopBlock), 0, s, H.dev, nodes,
+                           (const int32_t*)np, (const int32_t*)frontier, cnt);
     }
     return hipGetLastError();
 }

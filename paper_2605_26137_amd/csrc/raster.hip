@@ -37,12 +37,17 @@ __device__ __forceinline__ bool finite3(float3 a) {
 // Per face: snapped UV corners, tangent T_f = sgn(det) (e1 dv2 - e2 dv1) and
 // handedness h_f = sign(((e1 x e2) x T_f) . B_f) with B_f = sgn(det)(e2 du1 -
 // e1 du2); reliability flags; vertex degrees for the vertex -> face CSR.
-__global__ void lo_face_kernel(const float* __restrict__ V, int64_t nv, const int32_t* __restrict__ F,
-                               int64_t nf, const float* __restrict__ UV, int32_t res,
-                               float4* __restrict__ face_t, int4* __restrict__ face_uv,
-                               uint32_t* __restrict__ deg, uint32_t* __restrict__ status) {
-    int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nf) return;
+__global__ __launch_bounds__(256) void lo_face_kernel(Batch Bt, float4* __restrict__ face_t,
+                                                      int4* __restrict__ face_uv,
+                                                      uint32_t* __restrict__ deg) {
+    int64_t lb;
+    const AssetDev& As = Bt.A[block_asset(Bt, kGLoF, blockIdx.x, &lb)];
+    const int64_t f = lb * 256 + threadIdx.x;
+    if (f >= As.nlf) return;
+    const float* __restrict__ V = As.lo_V;
+    const int32_t* __restrict__ F = As.lo_F;
+    const float* __restrict__ UV = As.lo_UV;
+    const int64_t nv = As.nlv;
     int32_t a = F[3 * f], b = F[3 * f + 1], c = F[3 * f + 2];
     bool idx_ok = a >= 0 && b >= 0 && c >= 0 && a < nv && b < nv && c < nv;
     uint32_t st = 0;
@@ -55,7 +60,7 @@ __global__ void lo_face_kernel(const float* __restrict__ V, int64_t nv, const in
         uv_ok = uv_ok && isfinite(u[k]) && u[k] >= -1.0f && u[k] <= 2.0f;
     }
     if (!uv_ok) st |= kStBadUV;
-    const float sc = (float)res * 256.0f;
+    const float sc = (float)As.res * 256.0f;
     int32_t X[3], Y[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -75,47 +80,59 @@ __global__ void lo_face_kernel(const float* __restrict__ V, int64_t nv, const in
         float fdu1 = (float)du1, fdv1 = (float)dv1, fdu2 = (float)du2, fdv2 = (float)dv2;
         float3 T = make_float3(sg * (e1.x * fdv2 - e2.x * fdv1), sg * (e1.y * fdv2 - e2.y * fdv1),
                                sg * (e1.z * fdv2 - e2.z * fdv1));
-        float3 Bt = make_float3(sg * (e2.x * fdu1 - e1.x * fdu2), sg * (e2.y * fdu1 - e1.y * fdu2),
-                                sg * (e2.z * fdu1 - e1.z * fdu2));
+        float3 Bt3 = make_float3(sg * (e2.x * fdu1 - e1.x * fdu2), sg * (e2.y * fdu1 - e1.y * fdu2),
+                                 sg * (e2.z * fdu1 - e1.z * fdu2));
         float3 n = cross3(e1, e2);
-        float hs = dot3(cross3(n, T), Bt);
+        float hs = dot3(cross3(n, T), Bt3);
         T4 = make_float4(T.x, T.y, T.z, hs < 0.f ? -1.f : 1.f);
         bool area = n.x != 0.f || n.y != 0.f || n.z != 0.f;
         rel = fin && uv_ok && det != 0 && area;
-        atomicAdd(&deg[a], 1u);
-        atomicAdd(&deg[b], 1u);
-        atomicAdd(&deg[c], 1u);
+        atomicAdd(&deg[As.lv + a], 1u);
+        atomicAdd(&deg[As.lv + b], 1u);
+        atomicAdd(&deg[As.lv + c], 1u);
     }
     uint32_t flags = (rel ? kFaceReliable : 0u) | ((idx_ok && uv_ok && det != 0) ? kFaceRaster : 0u);
-    face_t[f] = T4;
-    face_uv[2 * f] = make_int4(X[0], Y[0], X[1], Y[1]);
-    face_uv[2 * f + 1] = make_int4(X[2], Y[2], (int32_t)flags, 0);
-    if (st) atomicOr(status, st);
+    const int64_t fg = As.lf + f;
+    face_t[fg] = T4;
+    face_uv[2 * fg] = make_int4(X[0], Y[0], X[1], Y[1]);
+    face_uv[2 * fg + 1] = make_int4(X[2], Y[2], (int32_t)flags, 0);
+    if (st) set_status(Bt, st);
 }
 
-__global__ void lo_adj_kernel(const int32_t* __restrict__ F, int64_t nv, int64_t nf,
-                              const uint32_t* __restrict__ off, uint32_t* __restrict__ cur,
-                              int32_t* __restrict__ adj) {
-    int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nf) return;
+// Adjacency entries hold asset-local face indices at the positions given by
+// the (batch-wide) exclusive scan of the degrees.
+__global__ __launch_bounds__(256) void lo_adj_kernel(Batch Bt, const uint32_t* __restrict__ off,
+                                                     uint32_t* __restrict__ cur, int32_t* __restrict__ adj) {
+    int64_t lb;
+    const AssetDev& As = Bt.A[block_asset(Bt, kGLoF, blockIdx.x, &lb)];
+    const int64_t f = lb * 256 + threadIdx.x;
+    if (f >= As.nlf) return;
+    const int32_t* __restrict__ F = As.lo_F;
+    const int64_t nv = As.nlv;
     int32_t v[3] = {F[3 * f], F[3 * f + 1], F[3 * f + 2]};
     if (v[0] < 0 || v[1] < 0 || v[2] < 0 || v[0] >= nv || v[1] >= nv || v[2] >= nv) return;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        uint32_t slot = atomicAdd(&cur[v[k]], 1u);
-        adj[off[v[k]] + slot] = (int32_t)f;
+        const int64_t g = As.lv + v[k];
+        uint32_t slot = atomicAdd(&cur[g], 1u);
+        adj[off[g] + slot] = (int32_t)f;
     }
 }
 
 // Per vertex: sort its incident faces ascending (fixed summation order, so the
 // result does not depend on the order the adjacency was filled in), then
 // n_v = normalise(sum (V1 - V0) x (V2 - V0)).
-__global__ void lo_normal_kernel(const float* __restrict__ V, int64_t nv, const int32_t* __restrict__ F,
-                                 const uint32_t* __restrict__ off, int32_t* __restrict__ adj,
-                                 float4* __restrict__ lo_n) {
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= nv) return;
-    uint32_t b = off[v], e = off[v + 1];
+__global__ __launch_bounds__(256) void lo_normal_kernel(Batch Bt, const uint32_t* __restrict__ off,
+                                                        int32_t* __restrict__ adj,
+                                                        float4* __restrict__ lo_n) {
+    int64_t lb;
+    const AssetDev& As = Bt.A[block_asset(Bt, kGLoV, blockIdx.x, &lb)];
+    const int64_t v = lb * 256 + threadIdx.x;
+    if (v >= As.nlv) return;
+    const float* __restrict__ V = As.lo_V;
+    const int32_t* __restrict__ F = As.lo_F;
+    const int64_t g = As.lv + v;
+    uint32_t b = off[g], e = off[g + 1];
     for (uint32_t i = b + 1; i < e; ++i) {
         int32_t x = adj[i];
         uint32_t j = i;
@@ -140,7 +157,7 @@ __global__ void lo_normal_kernel(const float* __restrict__ V, int64_t nv, const 
         float r = 1.0f / sqrtf(l2);
         out = make_float4(s.x * r, s.y * r, s.z * r, 1.f);
     }
-    lo_n[v] = out;
+    lo_n[g] = out;
 }
 
 // ---------------------------------------------------------------------------
@@ -156,10 +173,10 @@ struct FaceBox {
 
 __device__ __forceinline__ int32_t floor_div256(int32_t x) { return x >> 8; }  // arithmetic shift
 
-__device__ __forceinline__ FaceBox load_face_box(const int4* __restrict__ face_uv, int64_t f,
+__device__ __forceinline__ FaceBox load_face_box(const int4* __restrict__ face_uv, int64_t fg,
                                                  int32_t res) {
     FaceBox fb;
-    int4 p = face_uv[2 * f], q = face_uv[2 * f + 1];
+    int4 p = face_uv[2 * fg], q = face_uv[2 * fg + 1];
     fb.X[0] = p.x; fb.Y[0] = p.y; fb.X[1] = p.z; fb.Y[1] = p.w; fb.X[2] = q.x; fb.Y[2] = q.y;
     fb.ok = (q.z & kFaceRaster) != 0;
     int32_t xmin = min(min(fb.X[0], fb.X[1]), fb.X[2]), xmax = max(max(fb.X[0], fb.X[1]), fb.X[2]);
@@ -192,30 +209,42 @@ __device__ __forceinline__ bool cover(const FaceBox& fb, int32_t i, int32_t j, i
 constexpr int kRasterBlock = 256;
 constexpr int kWavesPerBlock = kRasterBlock / 64;
 
-__global__ __launch_bounds__(kRasterBlock) void raster_claim_kernel(const int4* __restrict__ face_uv,
-                                                                    int64_t nf, int32_t res,
+// The face of a raster wave, or -1 past the asset's faces.
+__device__ __forceinline__ int64_t raster_face(const Batch& Bt, const AssetDev** As) {
+    int64_t lb;
+    *As = &Bt.A[block_asset(Bt, kGLoFWave, blockIdx.x, &lb)];
+    const int64_t f = lb * kWavesPerBlock + (threadIdx.x >> 6);
+    return f < (*As)->nlf ? f : -1;
+}
+
+__global__ __launch_bounds__(kRasterBlock) void raster_claim_kernel(Batch Bt, const int4* __restrict__ face_uv,
                                                                     uint32_t* __restrict__ facemap) {
-    int64_t f = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    int lane = threadIdx.x & 63;
-    if (f >= nf) return;
-    FaceBox fb = load_face_box(face_uv, f, res);
+    const AssetDev* As;
+    const int64_t f = raster_face(Bt, &As);
+    const int lane = threadIdx.x & 63;
+    if (f < 0) return;
+    const int32_t res = As->res;
+    FaceBox fb = load_face_box(face_uv, As->lf + f, res);
     if (!fb.ok) return;
+    uint32_t* fm = facemap + As->tex;
     int64_t total = (int64_t)fb.w * fb.h;
     for (int64_t k = lane; k < total; k += 64) {
         int32_t i = fb.i0 + (int32_t)(k / fb.w), j = fb.j0 + (int32_t)(k % fb.w);
         int64_t E[3], S;
-        if (cover(fb, i, j, E, &S)) atomicMin(&facemap[(int64_t)i * res + j], (uint32_t)f);
+        if (cover(fb, i, j, E, &S)) atomicMin(&fm[(int64_t)i * res + j], (uint32_t)f);
     }
 }
 
-__global__ __launch_bounds__(kRasterBlock) void raster_count_kernel(const int4* __restrict__ face_uv,
-                                                                    int64_t nf, int32_t res,
+__global__ __launch_bounds__(kRasterBlock) void raster_count_kernel(Batch Bt, const int4* __restrict__ face_uv,
                                                                     const uint32_t* __restrict__ facemap,
                                                                     uint32_t* __restrict__ cnt) {
-    int64_t f = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    int lane = threadIdx.x & 63;
-    if (f >= nf) return;
-    FaceBox fb = load_face_box(face_uv, f, res);
+    const AssetDev* As;
+    const int64_t f = raster_face(Bt, &As);
+    const int lane = threadIdx.x & 63;
+    if (f < 0) return;
+    const int32_t res = As->res;
+    FaceBox fb = load_face_box(face_uv, As->lf + f, res);
+    const uint32_t* fm = facemap + As->tex;
     uint32_t c = 0;
     if (fb.ok) {
         int64_t total = (int64_t)fb.w * fb.h;
@@ -225,26 +254,28 @@ __global__ __launch_bounds__(kRasterBlock) void raster_count_kernel(const int4* 
             if (k < total) {
                 int32_t i = fb.i0 + (int32_t)(k / fb.w), j = fb.j0 + (int32_t)(k % fb.w);
                 int64_t E[3], S;
-                win = cover(fb, i, j, E, &S) && facemap[(int64_t)i * res + j] == (uint32_t)f;
+                win = cover(fb, i, j, E, &S) && fm[(int64_t)i * res + j] == (uint32_t)f;
             }
             c += (uint32_t)__popcll(__ballot(win));
         }
     }
-    if (lane == 0) cnt[f] = c;
+    if (lane == 0) cnt[As->lf + f] = c;
 }
 
-__global__ __launch_bounds__(kRasterBlock) void raster_emit_kernel(const int4* __restrict__ face_uv,
-                                                                   int64_t nf, int32_t res,
+__global__ __launch_bounds__(kRasterBlock) void raster_emit_kernel(Batch Bt, const int4* __restrict__ face_uv,
                                                                    const uint32_t* __restrict__ facemap,
                                                                    const uint32_t* __restrict__ off,
                                                                    Ray* __restrict__ rays) {
-    int64_t f = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    int lane = threadIdx.x & 63;
-    if (f >= nf) return;
-    FaceBox fb = load_face_box(face_uv, f, res);
+    const AssetDev* As;
+    const int64_t f = raster_face(Bt, &As);
+    const int lane = threadIdx.x & 63;
+    if (f < 0) return;
+    const int32_t res = As->res;
+    FaceBox fb = load_face_box(face_uv, As->lf + f, res);
     if (!fb.ok) return;
+    const uint32_t* fm = facemap + As->tex;
     int64_t total = (int64_t)fb.w * fb.h;
-    uint32_t run = off[f];
+    uint32_t run = off[As->lf + f];
     for (int64_t k0 = 0; k0 < total; k0 += 64) {
         int64_t k = k0 + lane;
         bool win = false;
@@ -253,7 +284,7 @@ __global__ __launch_bounds__(kRasterBlock) void raster_emit_kernel(const int4* _
         if (k < total) {
             i = fb.i0 + (int32_t)(k / fb.w);
             j = fb.j0 + (int32_t)(k % fb.w);
-            win = cover(fb, i, j, E, &S) && facemap[(int64_t)i * res + j] == (uint32_t)f;
+            win = cover(fb, i, j, E, &S) && fm[(int64_t)i * res + j] == (uint32_t)f;
         }
         uint64_t m = __ballot(win);
         if (win) {
@@ -274,31 +305,35 @@ __global__ __launch_bounds__(kRasterBlock) void raster_emit_kernel(const int4* _
 // Uncovered texels, dilation, RGB8
 // ---------------------------------------------------------------------------
 
-__global__ void fill_uncovered_kernel(const uint32_t* __restrict__ facemap, int64_t ntex,
-                                      float* __restrict__ map, int32_t* __restrict__ hit,
-                                      uint8_t* __restrict__ level) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ntex) return;
-    bool cov = facemap[t] != 0x7FFFFFFFu;
-    level[t] = cov ? 0 : 255;
+__global__ __launch_bounds__(256) void fill_uncovered_kernel(Batch Bt, const uint32_t* __restrict__ facemap,
+                                                             uint8_t* __restrict__ level) {
+    int64_t lb;
+    const AssetDev& As = Bt.A[block_asset(Bt, kGTex, blockIdx.x, &lb)];
+    const int64_t t = lb * 256 + threadIdx.x;
+    if (t >= (int64_t)As.res * As.res) return;
+    bool cov = facemap[As.tex + t] != 0x7FFFFFFFu;
+    level[As.tex + t] = cov ? 0 : 255;
     if (!cov) {
-        map[3 * t] = 0.f;
-        map[3 * t + 1] = 0.f;
-        map[3 * t + 2] = 1.f;
-        hit[t] = kUncovered;
+        As.out_map[3 * t] = 0.f;
+        As.out_map[3 * t + 1] = 0.f;
+        As.out_map[3 * t + 2] = 1.f;
+        As.out_hit[t] = kUncovered;
     }
 }
 
 // Pass k: a still-empty texel takes the normalised sum of its 8 neighbours
 // that had a value before this pass (level < k).  Texels written in this pass
 // are never read in it, so the map is updated in place.
-__global__ void dilate_kernel(int32_t res, int pass, float* __restrict__ map,
-                              uint8_t* __restrict__ level) {
-    int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    int32_t i = blockIdx.y;
-    if (j >= res) return;
-    int64_t t = (int64_t)i * res + j;
+__global__ __launch_bounds__(256) void dilate_kernel(Batch Bt, int pass, uint8_t* __restrict__ level_all) {
+    int64_t lb;
+    const AssetDev& As = Bt.A[block_asset(Bt, kGTex, blockIdx.x, &lb)];
+    const int32_t res = As.res;
+    const int64_t t = lb * 256 + threadIdx.x;
+    if (t >= (int64_t)res * res) return;
+    uint8_t* __restrict__ level = level_all + As.tex;
+    float* __restrict__ map = As.out_map;
     if (level[t] != 255) return;
+    const int32_t i = (int32_t)(t >> As.log2res), j = (int32_t)(t & (res - 1));
     float sx = 0.f, sy = 0.f, sz = 0.f;
     int cnt = 0;
 #pragma unroll
@@ -327,95 +362,98 @@ __global__ void dilate_kernel(int32_t res, int pass, float* __restrict__ map,
     level[t] = (uint8_t)pass;
 }
 
-__global__ void rgb8_kernel(const float* __restrict__ map, int64_t n, uint8_t* __restrict__ out) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    float c = floorf((map[k] + 1.0f) * 127.5f + 0.5f);
+__global__ __launch_bounds__(256) void rgb8_kernel(Batch Bt) {
+    int64_t lb;
+    const AssetDev& As = Bt.A[block_asset(Bt, kGTex3, blockIdx.x, &lb)];
+    const int64_t k = lb * 256 + threadIdx.x;
+    if (!As.out_rgb8 || k >= 3 * (int64_t)As.res * As.res) return;
+    float c = floorf((As.out_map[k] + 1.0f) * 127.5f + 0.5f);
     c = fminf(fmaxf(c, 0.0f), 255.0f);
-    out[k] = (uint8_t)c;
+    As.out_rgb8[k] = (uint8_t)c;
 }
 
 inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
-hipError_t launch_lo_prep(const float* lo_V, int64_t nlv, const int32_t* lo_F, int64_t nlf,
-                          const float* lo_UV, int32_t res, const Layout& L, char* ws,
-                          hipStream_t s) {
+hipError_t launch_lo_prep(const BatchHost& H, hipStream_t s) {
+    const Layout& L = H.L;
+    char* ws = H.ws;
     uint32_t* deg = (uint32_t*)(ws + L.lo_deg);
     uint32_t* off = (uint32_t*)(ws + L.lo_off);
     uint32_t* cur = (uint32_t*)(ws + L.lo_cur);
     hipError_t e;
-    if ((e = fill_u32(deg, 0, nlv, s)) != hipSuccess) return e;
-    if ((e = fill_u32(cur, 0, nlv, s)) != hipSuccess) return e;
-    if (nlf > 0) {
-        hipLaunchKernelGGL(lo_face_kernel, dim3(blocks_for(nlf, 256)), dim3(256), 0, s, lo_V, nlv,
-                           lo_F, nlf, lo_UV, res, (float4*)(ws + L.face_t), (int4*)(ws + L.face_uv),
-                           deg, (uint32_t*)(ws + L.status));
+    if ((e = fill_u32(deg, 0, L.t_lv, s)) != hipSuccess) return e;
+    if ((e = fill_u32(cur, 0, L.t_lv, s)) != hipSuccess) return e;
+    if (H.blocks(kGLoF) > 0) {
+        hipLaunchKernelGGL(lo_face_kernel, dim3((unsigned)H.blocks(kGLoF)), dim3(256), 0, s, H.dev,
+                           (float4*)(ws + L.face_t), (int4*)(ws + L.face_uv), deg);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if ((e = exclusive_scan_u32(deg, off, nlv, (uint32_t*)(ws + L.scan_tmp), off + nlv, s)) !=
+    // batch-wide scan: vertex g's faces sit at [off[g], off[g + 1])
+    if ((e = exclusive_scan_u32(deg, off, L.t_lv, (uint32_t*)(ws + L.scan_tmp), off + L.t_lv, s)) !=
         hipSuccess)
         return e;
-    if (nlf > 0) {
-        hipLaunchKernelGGL(lo_adj_kernel, dim3(blocks_for(nlf, 256)), dim3(256), 0, s, lo_F, nlv,
-                           nlf, (const uint32_t*)off, cur, (int32_t*)(ws + L.lo_adj));
+    if (H.blocks(kGLoF) > 0) {
+        hipLaunchKernelGGL(lo_adj_kernel, dim3((unsigned)H.blocks(kGLoF)), dim3(256), 0, s, H.dev,
+                           (const uint32_t*)off, cur, (int32_t*)(ws + L.lo_adj));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if (nlv > 0) {
-        hipLaunchKernelGGL(lo_normal_kernel, dim3(blocks_for(nlv, 256)), dim3(256), 0, s, lo_V,
-                           nlv, lo_F, (const uint32_t*)off, (int32_t*)(ws + L.lo_adj),
-                           (float4*)(ws + L.lo_n));
+    if (H.blocks(kGLoV) > 0) {
+        hipLaunchKernelGGL(lo_normal_kernel, dim3((unsigned)H.blocks(kGLoV)), dim3(256), 0, s, H.dev,
+                           (const uint32_t*)off, (int32_t*)(ws + L.lo_adj), (float4*)(ws + L.lo_n));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-hipError_t launch_raster(int64_t nlf, int32_t res, const Layout& L, char* ws, hipStream_t s) {
+hipError_t launch_raster(const BatchHost& H, hipStream_t s) {
+    const Layout& L = H.L;
+    char* ws = H.ws;
     uint32_t* facemap = (uint32_t*)(ws + L.facemap);
     uint32_t* cnt = (uint32_t*)(ws + L.face_cnt);
     uint32_t* off = (uint32_t*)(ws + L.face_off);
-    uint32_t* counters = (uint32_t*)(ws + L.counters);
     const int4* fuv = (const int4*)(ws + L.face_uv);
     hipError_t e;
-    if ((e = fill_u32(facemap, 0x7FFFFFFFu, L.n_texels, s)) != hipSuccess) return e;
-    if (nlf == 0) return fill_u32(counters + kCntRays, 0, 1, s);
-    unsigned g = blocks_for(nlf, kWavesPerBlock);
-    hipLaunchKernelGGL(raster_claim_kernel, dim3(g), dim3(kRasterBlock), 0, s, fuv, nlf, res, facemap);
-    hipLaunchKernelGGL(raster_count_kernel, dim3(g), dim3(kRasterBlock), 0, s, fuv, nlf, res,
-                       (const uint32_t*)facemap, cnt);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = exclusive_scan_u32(cnt, off, nlf, (uint32_t*)(ws + L.scan_tmp), counters + kCntRays,
-                                s)) != hipSuccess)
+    if ((e = fill_u32(facemap, 0x7FFFFFFFu, L.t_tex, s)) != hipSuccess) return e;
+    const unsigned g = (unsigned)H.blocks(kGLoFWave);
+    if (g > 0) {
+        hipLaunchKernelGGL(raster_claim_kernel, dim3(g), dim3(kRasterBlock), 0, s, H.dev, fuv, facemap);
+        hipLaunchKernelGGL(raster_count_kernel, dim3(g), dim3(kRasterBlock), 0, s, H.dev, fuv,
+                           (const uint32_t*)facemap, cnt);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    // batch-wide scan: the face-ordered ray lists of the assets, concatenated
+    if ((e = exclusive_scan_u32(cnt, off, L.t_lf, (uint32_t*)(ws + L.scan_tmp), off + L.t_lf, s)) !=
+        hipSuccess)
         return e;
-    hipLaunchKernelGGL(raster_emit_kernel, dim3(g), dim3(kRasterBlock), 0, s, fuv, nlf, res,
-                       (const uint32_t*)facemap, (const uint32_t*)off, (Ray*)(ws + L.rays));
-    return hipGetLastError();
-}
-
-hipError_t launch_fill_uncovered(int32_t res, float* out_map, int32_t* out_hit, const Layout& L,
-                                 char* ws, hipStream_t s) {
-    int64_t n = L.n_texels;
-    hipLaunchKernelGGL(fill_uncovered_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s,
-                       (const uint32_t*)(ws + L.facemap), n, out_map, out_hit,
-                       (uint8_t*)(ws + L.level));
-    return hipGetLastError();
-}
-
-hipError_t launch_dilate(int32_t res, int passes, float* out_map, const Layout& L, char* ws,
-                         hipStream_t s) {
-    int bx = res < 256 ? res : 256;
-    dim3 grid((unsigned)((res + bx - 1) / bx), (unsigned)res);
-    for (int k = 1; k <= passes; ++k) {
-        hipLaunchKernelGGL(dilate_kernel, grid, dim3(bx), 0, s, res, k, out_map,
-                           (uint8_t*)(ws + L.level));
+    if ((e = launch_ray_spaces(H, s)) != hipSuccess) return e;
+    if (g > 0) {
+        hipLaunchKernelGGL(raster_emit_kernel, dim3(g), dim3(kRasterBlock), 0, s, H.dev, fuv,
+                           (const uint32_t*)facemap, (const uint32_t*)off, (Ray*)(ws + L.rays));
     }
     return hipGetLastError();
 }
 
-hipError_t launch_rgb8(int32_t res, const float* out_map, uint8_t* rgb, hipStream_t s) {
-    int64_t n = (int64_t)res * res * 3;
-    hipLaunchKernelGGL(rgb8_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, out_map, n, rgb);
+hipError_t launch_fill_uncovered(const BatchHost& H, hipStream_t s) {
+    if (H.blocks(kGTex) == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_uncovered_kernel, dim3((unsigned)H.blocks(kGTex)), dim3(256), 0, s, H.dev,
+                       (const uint32_t*)(H.ws + H.L.facemap), (uint8_t*)(H.ws + H.L.level));
+    return hipGetLastError();
+}
+
+hipError_t launch_dilate(const BatchHost& H, int passes, hipStream_t s) {
+    if (H.blocks(kGTex) == 0) return hipSuccess;
+    for (int k = 1; k <= passes; ++k) {
+        hipLaunchKernelGGL(dilate_kernel, dim3((unsigned)H.blocks(kGTex)), dim3(256), 0, s, H.dev, k,
+                           (uint8_t*)(H.ws + H.L.level));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_rgb8(const BatchHost& H, hipStream_t s) {
+    if (H.blocks(kGTex3) == 0) return hipSuccess;
+    hipLaunchKernelGGL(rgb8_kernel, dim3((unsigned)H.blocks(kGTex3)), dim3(256), 0, s, H.dev);
     return hipGetLastError();
 }
 

@@ -6,12 +6,14 @@
 // project it into the texel's tangent frame.
 //
 // Traversal (two launch shapes, same per-ray arithmetic and results):
-//   * wave batches (default): persistent waves take 64 consecutive rays of the
-//     face-ordered ray list from a device work queue, trace them together in a
-//     tight loop and encode when the whole batch is done: neighbouring texels
-//     of one face walk nearly the same nodes;
-//   * lane refill: lanes whose ray finished are refilled from the queue while
-//     the rest continue (wave-level compaction after Aila & Laine 2009);
+//   * wave batches (default): persistent waves take (asset, 64-ray batch)
+//     items of the batch's face-ordered ray lists from one device work queue,
+//     trace the 64 rays together in a tight loop and encode when the whole
+//     batch is done: neighbouring texels of one face walk nearly the same
+//     nodes, and the asset is uniform across the wave;
+//   * lane refill: lanes whose ray finished are refilled from a ray queue over
+//     the concatenated lists while the rest continue (wave-level compaction
+//     after Aila & Laine 2009); lanes may then work on different assets;
 //   * conservative slab test: near/far planes picked by the sign of the
 //     direction, t widened outward by a relative 1e-6 (after Ize 2013); a zero
 //     direction component yields NaN for a ray lying in a slab plane, which
@@ -169,31 +171,38 @@ __device__ __forceinline__ void tri_test(const RayT& r, const Leaf& L, float max
 }
 
 struct TravArgs {
-    const Ray* rays;
-    const uint32_t* nrays;  // device count
-    uint32_t* queue;        // device work queue head
-    const float* lo_V;
-    const int32_t* lo_F;
-    const float4* lo_n;
-    const float4* face_t;
-    const int4* face_uv;
+    Batch B;
+    const Ray* rays;       // concatenated face-ordered ray lists
+    const float4* lo_n;    // concatenated lo vertex normals
+    const float4* face_t;  // concatenated per-face tangents
+    const int4* face_uv;   // concatenated snapped UVs + flags
+    const BvhNode* nodes;  // concatenated trees
+    const Leaf* leaves;
+    Hit* hits;             // optional, by global ray index
+    int32_t* spill;        // [kMaxDepth][spill_lanes]
+    int64_t spill_lanes;
+};
+
+// What the inner loop needs of an asset.
+struct TreeView {
     const BvhNode* nodes;
     const Leaf* leaves;
-    int32_t root;  // root ref, or kEmpty when there is no triangle
-    const int32_t* hi_F;
-    int64_t nhv;
-    const float* hi_N;
-    float max_dist;
-    float* out_map;
-    int32_t* out_hit;
-    Hit* hits;           // optional
-    int32_t* spill;      // [kMaxDepth][spill_lanes]
-    int64_t spill_lanes;
-    uint32_t* status;    // device status word
-    int32_t step_cap;    // per-ray safety bound on loop steps
-    unsigned long long* n_box;  // box tests (instrumented variant)
-    unsigned long long* n_tri;  // triangle tests (instrumented variant)
+    float max_dist, w, inv_w;
+    int32_t root;      // root ref, or kEmpty when there is no triangle
+    int32_t step_cap;  // per-ray safety bound on loop steps
 };
+
+__device__ __forceinline__ TreeView tree_view(const TravArgs& t, const AssetDev& As) {
+    TreeView v;
+    v.nodes = t.nodes + As.node;
+    v.leaves = t.leaves + As.hf;
+    v.max_dist = As.max_dist;
+    v.w = As.max_dist / kQuantScale;  // exact: power-of-two scaling
+    v.inv_w = kQuantScale / As.max_dist;
+    v.root = As.nhf <= 0 ? kEmpty : (As.nhf == 1 ? ~0 : 0);
+    v.step_cap = (int32_t)min((int64_t)4 * As.nhf + 1024, (int64_t)INT32_MAX);
+    return v;
+}
 
 // Ray setup from the G-buffer record: world position p, interpolated smooth
 // normal d, tangent T' orthogonalised against d, UV handedness.  rel = false
@@ -205,20 +214,22 @@ struct RaySetup {
     bool rel;
 };
 
-__device__ __forceinline__ RaySetup setup_ray(const TravArgs& a, const Ray& ray) {
+__device__ __forceinline__ RaySetup setup_ray(const TravArgs& a, const AssetDev& As, const Ray& ray) {
     RaySetup r;
     r.texel = ray.texel;
     const int32_t face = ray.face;
+    const float4* lo_n = a.lo_n + As.lv;
     float b1 = ray.b1, b2 = ray.b2, b0 = 1.0f - b1 - b2;
-    int32_t i0 = a.lo_F[3 * face], i1 = a.lo_F[3 * face + 1], i2 = a.lo_F[3 * face + 2];
-    float3 V0 = ld3(a.lo_V, i0), V1 = ld3(a.lo_V, i1), V2 = ld3(a.lo_V, i2);
-    float4 n0 = a.lo_n[i0], n1 = a.lo_n[i1], n2 = a.lo_n[i2];
+    int32_t i0 = As.lo_F[3 * face], i1 = As.lo_F[3 * face + 1], i2 = As.lo_F[3 * face + 2];
+    float3 V0 = ld3(As.lo_V, i0), V1 = ld3(As.lo_V, i1), V2 = ld3(As.lo_V, i2);
+    float4 n0 = lo_n[i0], n1 = lo_n[i1], n2 = lo_n[i2];
     r.p = f3(b0 * V0.x + b1 * V1.x + b2 * V2.x, b0 * V0.y + b1 * V1.y + b2 * V2.y,
              b0 * V0.z + b1 * V1.z + b2 * V2.z);
     float3 m = f3(b0 * n0.x + b1 * n1.x + b2 * n2.x, b0 * n0.y + b1 * n1.y + b2 * n2.y,
                   b0 * n0.z + b1 * n1.z + b2 * n2.z);
-    float4 T4 = a.face_t[face];
-    uint32_t fl = (uint32_t)a.face_uv[2 * face + 1].z;
+    const int64_t fg = As.lf + face;
+    float4 T4 = a.face_t[fg];
+    uint32_t fl = (uint32_t)a.face_uv[2 * fg + 1].z;
     bool rel = (fl & kFaceReliable) && n0.w != 0.f && n1.w != 0.f && n2.w != 0.f;
     float l2 = dot3(m, m);
     rel = rel && l2 > 0.f;
@@ -238,23 +249,24 @@ __device__ __forceinline__ RaySetup setup_ray(const TravArgs& a, const Ray& ray)
 
 // Interpolate the hit's high-poly normal, project it into (T', B', d) and
 // write the texel; unreliable and missed rays get (0,0,1).
-__device__ __forceinline__ void finish_ray(const TravArgs& a, uint32_t ridx, const RaySetup& rs,
-                                           const Best& best) {
+__device__ __forceinline__ void finish_ray(const TravArgs& a, const AssetDev& As, int64_t ridx,
+                                           const RaySetup& rs, const Best& best) {
     float3 out = f3(0.f, 0.f, 1.f);
     int32_t st = rs.rel ? kMiss : kUnreliable;
     float beta1 = 0.f, beta2 = 0.f, tt = 0.f;
     if (rs.rel && best.id != INT32_MAX) {
         int32_t g = best.id;
-        int32_t j0 = a.hi_F[3 * (int64_t)g], j1 = a.hi_F[3 * (int64_t)g + 1],
-                j2 = a.hi_F[3 * (int64_t)g + 2];
-        bool ok = j0 >= 0 && j1 >= 0 && j2 >= 0 && j0 < a.nhv && j1 < a.nhv && j2 < a.nhv;
+        const int32_t* hi_F = As.hi_F;
+        const int64_t nhv = As.nhv;
+        int32_t j0 = hi_F[3 * (int64_t)g], j1 = hi_F[3 * (int64_t)g + 1], j2 = hi_F[3 * (int64_t)g + 2];
+        bool ok = j0 >= 0 && j1 >= 0 && j2 >= 0 && j0 < nhv && j1 < nhv && j2 < nhv;
         beta1 = best.b1;
         beta2 = best.b2;
         tt = best.t;
         float beta0 = 1.0f - beta1 - beta2;
         st = kUnreliable;
         if (ok) {
-            float3 N0 = ld3(a.hi_N, j0), N1 = ld3(a.hi_N, j1), N2 = ld3(a.hi_N, j2);
+            float3 N0 = ld3(As.hi_N, j0), N1 = ld3(As.hi_N, j1), N2 = ld3(As.hi_N, j2);
             float3 h = f3(beta0 * N0.x + beta1 * N1.x + beta2 * N2.x,
                           beta0 * N0.y + beta1 * N1.y + beta2 * N2.y,
                           beta0 * N0.z + beta1 * N1.z + beta2 * N2.z);
@@ -270,10 +282,10 @@ __device__ __forceinline__ void finish_ray(const TravArgs& a, uint32_t ridx, con
         }
     }
     const int64_t t = rs.texel;
-    a.out_map[3 * t] = out.x;
-    a.out_map[3 * t + 1] = out.y;
-    a.out_map[3 * t + 2] = out.z;
-    a.out_hit[t] = st;
+    As.out_map[3 * t] = out.x;
+    As.out_map[3 * t + 1] = out.y;
+    As.out_map[3 * t + 2] = out.z;
+    As.out_hit[t] = st;
     if (a.hits) {
         Hit h;
         h.t = tt;
@@ -319,12 +331,11 @@ struct LaneStack {
 // the nearer hit, push the other) or a leaf (triangle test), then pop when the
 // lane has nowhere to go.  Returns the next node (kEmpty: the ray is done).
 template <int BLOCK, int STACK, bool COUNT>
-__device__ __forceinline__ int32_t trav_step(const TravArgs& a, int32_t node, const RayT& R,
-                                             Best& best, LaneStack<BLOCK, STACK>& st, int tid,
-                                             float inv_w, float w, unsigned long long& c_box,
-                                             unsigned long long& c_tri) {
+__device__ __forceinline__ int32_t trav_step(const TreeView& tv, uint32_t* status, int32_t node,
+                                             const RayT& R, Best& best, LaneStack<BLOCK, STACK>& st,
+                                             int tid, unsigned long long& c_box, unsigned long long& c_tri) {
     if (node >= 0) {
-        const BvhNode* nd = a.nodes + node;
+        const BvhNode* nd = tv.nodes + node;
         float4 na = nd->a, nb = nd->b, nc = nd->c;
         int4 ref = nd->ref;
         float mL, mR;
@@ -335,7 +346,7 @@ __device__ __forceinline__ int32_t trav_step(const TravArgs& a, int32_t node, co
         if (hL && hR) {
             bool rfirst = mR < mL;
             next = rfirst ? ref.y : ref.x;
-            st.push(rfirst ? ref.x : ref.y, tid, a.status);
+            st.push(rfirst ? ref.x : ref.y, tid, status);
         } else if (hL) {
             next = ref.x;
         } else if (hR) {
@@ -343,8 +354,8 @@ __device__ __forceinline__ int32_t trav_step(const TravArgs& a, int32_t node, co
         }
         node = next;
     } else {
-        const Leaf L = a.leaves[~node];
-        tri_test(R, L, a.max_dist, inv_w, w, &best);
+        const Leaf L = tv.leaves[~node];
+        tri_test(R, L, tv.max_dist, tv.inv_w, tv.w, &best);
         if (COUNT) c_tri += 1;
         node = kEmpty;
     }
@@ -359,70 +370,84 @@ __device__ __forceinline__ void reset_best(Best& b, float max_dist) {
     b.bound = max_dist * (1.0f + kPad);
 }
 
-// Wave batches: each wave takes 64 consecutive rays, traces them together and
-// encodes once all 64 are done.
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Wave batches: each wave takes one (asset, 64-ray batch) item at a time,
+// traces its rays together and encodes once all 64 are done.
 template <int BLOCK, int STACK, bool COUNT>
 __global__ __launch_bounds__(BLOCK) void traverse_batch_kernel(TravArgs a) {
     __shared__ int32_t stk[STACK][BLOCK];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const uint32_t nrays = *a.nrays;
-    const float w = a.max_dist / kQuantScale;  // exact: power-of-two scaling
-    const float inv_w = kQuantScale / a.max_dist;
+    const Batch& B = a.B;
+    const uint32_t nbatches = B.rb_pf[B.n];
     LaneStack<BLOCK, STACK> st;
     st.lds = stk;
     st.spill = a.spill;
     st.stride = a.spill_lanes;
     st.col = (int64_t)blockIdx.x * BLOCK + tid;
-    unsigned long long c_box = 0, c_tri = 0;
     for (;;) {
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(a.queue, 64u);
-        base = __shfl(base, 0, 64);
-        if (base >= nrays) break;
-        const uint32_t k = base + lane;
-        RaySetup rs;
-        rs.rel = false;
+        uint32_t q = 0;
+        if (lane == 0) q = atomicAdd(&B.gcnt[kGcQueue], 1u);
+        q = __builtin_amdgcn_readfirstlane(__shfl(q, 0, 64));
+        if (q >= nbatches) break;
+        const int ai = upper_asset(B.rb_pf, B.n, q);
+        const AssetDev& As = B.A[ai];
+        const TreeView tv = tree_view(a, As);
+        const uint32_t nr = B.cnt[(int64_t)ai * kCntSlots + kCntRays];
+        const uint32_t k = (q - B.rb_pf[ai]) * 64u + (uint32_t)lane;  // asset-local ray
+        const int64_t r = (int64_t)B.ray_pf[ai] + k;                    // global ray
         int32_t node = kEmpty;
         Best best;
-        reset_best(best, a.max_dist);
+        reset_best(best, tv.max_dist);
         RayT R;
-        if (k < nrays) {
-            rs = setup_ray(a, a.rays[k]);
+        if (k < nr) {
+            // the setup is recomputed for the encode below, so it is not
+            // kept live through the traversal loop
+            const RaySetup rs = setup_ray(a, As, a.rays[r]);
             if (rs.rel) {
                 R = make_rayt(rs.p, rs.d);
-                node = a.root;
+                node = tv.root;
             }
         }
         st.sp = st.lo = 0;
         int32_t steps = 0;
+        unsigned long long c_box = 0, c_tri = 0;
         while (__ballot(node != kEmpty)) {
             if (node != kEmpty) {
-                node = trav_step<BLOCK, STACK, COUNT>(a, node, R, best, st, tid, inv_w, w, c_box, c_tri);
-                if (++steps > a.step_cap) {
-                    atomicOr(a.status, kStInternal);
+                node = trav_step<BLOCK, STACK, COUNT>(tv, B.status, node, R, best, st, tid, c_box, c_tri);
+                if (++steps > tv.step_cap) {
+                    set_status(B, kStInternal);
                     node = kEmpty;
                 }
             }
         }
-        if (k < nrays) finish_ray(a, k, rs, best);
-    }
-    if (COUNT) {
-        atomicAdd(a.n_box, c_box);
-        atomicAdd(a.n_tri, c_tri);
+        if (k < nr) finish_ray(a, As, r, setup_ray(a, As, a.rays[r]), best);
+        if (COUNT) {
+            c_box = wave_sum_u64(c_box);
+            c_tri = wave_sum_u64(c_tri);
+            if (lane == 0) {
+                atomicAdd((unsigned long long*)&B.cnt[(int64_t)ai * kCntSlots + kCntBoxLo], c_box);
+                atomicAdd((unsigned long long*)&B.cnt[(int64_t)ai * kCntSlots + kCntTriLo], c_tri);
+            }
+        }
     }
 }
 
-// Lane refill: idle lanes take new rays from the queue when at least 16 of
-// the wave are idle; the rest keep traversing.
+// Lane refill: idle lanes take new rays from the ray queue when at least 16
+// of the wave are idle; the rest keep traversing.  Each lane finds the asset
+// of its ray.
 template <int BLOCK, int STACK, bool COUNT>
 __global__ __launch_bounds__(BLOCK) void traverse_refill_kernel(TravArgs a) {
     __shared__ int32_t stk[STACK][BLOCK];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const uint32_t nrays = *a.nrays;
-    const float w = a.max_dist / kQuantScale;
-    const float inv_w = kQuantScale / a.max_dist;
+    const Batch& B = a.B;
+    const uint32_t nrays = B.ray_pf[B.n];
     LaneStack<BLOCK, STACK> st;
     st.lds = stk;
     st.spill = a.spill;
@@ -431,11 +456,13 @@ __global__ __launch_bounds__(BLOCK) void traverse_refill_kernel(TravArgs a) {
     st.sp = st.lo = 0;
     bool active = false, exhausted = false;
     uint32_t ridx = 0;
+    int ai = 0;
     RaySetup rs;
     rs.rel = false;
     RayT R;
     Best best;
-    reset_best(best, a.max_dist);
+    TreeView tv = tree_view(a, B.A[0]);
+    reset_best(best, tv.max_dist);
     int32_t node = kEmpty;
     int32_t steps = 0;
     unsigned long long c_box = 0, c_tri = 0;
@@ -445,21 +472,29 @@ __global__ __launch_bounds__(BLOCK) void traverse_refill_kernel(TravArgs a) {
             int cnt = (int)__popcll(idle);
             int leader = __ffsll((long long)idle) - 1;
             uint32_t base = 0;
-            if (lane == leader) base = atomicAdd(a.queue, (uint32_t)cnt);
+            if (lane == leader) base = atomicAdd(&B.gcnt[kGcQueue], (uint32_t)cnt);
             base = __shfl(base, leader, 64);
             if (base >= nrays) exhausted = true;
             if (!active) {
                 uint32_t k = base + (uint32_t)__popcll(idle & __lanemask_lt());
                 if (k < nrays) {
+                    if (COUNT && (c_box | c_tri)) {
+                        atomicAdd((unsigned long long*)&B.cnt[(int64_t)ai * kCntSlots + kCntBoxLo], c_box);
+                        atomicAdd((unsigned long long*)&B.cnt[(int64_t)ai * kCntSlots + kCntTriLo], c_tri);
+                        c_box = c_tri = 0;
+                    }
                     ridx = k;
-                    rs = setup_ray(a, a.rays[k]);
-                    reset_best(best, a.max_dist);
-                    node = rs.rel ? a.root : kEmpty;
+                    ai = upper_asset(B.ray_pf, B.n, k);
+                    const AssetDev& As = B.A[ai];
+                    tv = tree_view(a, As);
+                    rs = setup_ray(a, As, a.rays[k]);
+                    reset_best(best, tv.max_dist);
+                    node = rs.rel ? tv.root : kEmpty;
                     st.sp = st.lo = 0;
                     steps = 0;
                     if (rs.rel) R = make_rayt(rs.p, rs.d);
                     active = node != kEmpty;
-                    if (!active) finish_ray(a, k, rs, best);
+                    if (!active) finish_ray(a, As, k, rs, best);
                 }
             }
         }
@@ -468,18 +503,18 @@ __global__ __launch_bounds__(BLOCK) void traverse_refill_kernel(TravArgs a) {
             continue;
         }
         if (!active) continue;
-        node = trav_step<BLOCK, STACK, COUNT>(a, node, R, best, st, tid, inv_w, w, c_box, c_tri);
-        if (++steps > a.step_cap) {
-            atomicOr(a.status, kStInternal);
+        node = trav_step<BLOCK, STACK, COUNT>(tv, B.status, node, R, best, st, tid, c_box, c_tri);
+        if (++steps > tv.step_cap) {
+            set_status(B, kStInternal);
             node = kEmpty;
         }
         if (node != kEmpty) continue;
         active = false;
-        finish_ray(a, ridx, rs, best);
+        finish_ray(a, B.A[ai], ridx, rs, best);
     }
-    if (COUNT) {
-        atomicAdd(a.n_box, c_box);
-        atomicAdd(a.n_tri, c_tri);
+    if (COUNT && (c_box | c_tri)) {
+        atomicAdd((unsigned long long*)&B.cnt[(int64_t)ai * kCntSlots + kCntBoxLo], c_box);
+        atomicAdd((unsigned long long*)&B.cnt[(int64_t)ai * kCntSlots + kCntTriLo], c_tri);
     }
 }
 
@@ -508,39 +543,23 @@ hipError_t launch_one(const TravArgs& args, hipStream_t s, int64_t max_lanes) {
 
 }  // namespace
 
-hipError_t launch_traverse(const float* lo_V, const int32_t* lo_F, int64_t nlf, const int32_t* hi_F,
-                           int64_t nhv, int64_t nhf, const float* hi_N, float max_dist, float* out_map,
-                           int32_t* out_hit, bool save, const TravConfig& cfg, const Layout& L,
-                           char* ws, hipStream_t s) {
-    (void)nlf;
-    uint32_t* counters = (uint32_t*)(ws + L.counters);
-    hipError_t e = fill_u32(counters + kCntQueue, 0, 1, s);
+hipError_t launch_traverse(const BatchHost& H, const TravConfig& cfg, hipStream_t s) {
+    const Layout& L = H.L;
+    char* ws = H.ws;
+    hipError_t e = fill_u32(H.dev.gcnt + kGcQueue, 0, 1, s);
     if (e != hipSuccess) return e;
+    if (L.t_tex == 0) return hipSuccess;
     TravArgs a;
+    a.B = H.dev;
     a.rays = (const Ray*)(ws + L.rays);
-    a.nrays = counters + kCntRays;
-    a.queue = counters + kCntQueue;
-    a.lo_V = lo_V;
-    a.lo_F = lo_F;
     a.lo_n = (const float4*)(ws + L.lo_n);
     a.face_t = (const float4*)(ws + L.face_t);
     a.face_uv = (const int4*)(ws + L.face_uv);
     a.nodes = (const BvhNode*)(ws + L.nodes);
     a.leaves = (const Leaf*)(ws + L.leaves);
-    a.root = nhf <= 0 ? kEmpty : (nhf == 1 ? ~0 : 0);
-    a.hi_F = hi_F;
-    a.nhv = nhv;
-    a.hi_N = hi_N;
-    a.max_dist = max_dist;
-    a.out_map = out_map;
-    a.out_hit = out_hit;
-    a.hits = save ? (Hit*)(ws + L.hits) : nullptr;
+    a.hits = L.save ? (Hit*)(ws + L.hits) : nullptr;
     a.spill = (int32_t*)(ws + L.spill);
     a.spill_lanes = L.spill_lanes;
-    a.status = (uint32_t*)(ws + L.status);
-    a.step_cap = (int32_t)std::min<int64_t>(4 * nhf + 1024, INT32_MAX);
-    a.n_box = (unsigned long long*)(counters + kCntBoxLo);
-    a.n_tri = (unsigned long long*)(counters + kCntTriLo);
     int64_t lanes = L.spill_lanes;
     if (cfg.count) {
         return cfg.persist ? launch_one<256, 16, true, true>(a, s, lanes)

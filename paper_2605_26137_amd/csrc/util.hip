@@ -1,5 +1,10 @@
-// Fills and a device-wide exclusive scan (reduce-then-scan, three launches,
-// fixed summation order so results are deterministic).
+// Fills, a device-wide exclusive scan (reduce-then-scan, three launches,
+// fixed summation order so results are deterministic), the asset-table
+// writer and the per-asset prefix tables that depend on device counts.
+#include <string.h>
+
+#include <algorithm>
+
 #include "internal.h"
 
 namespace bake {
@@ -149,6 +154,91 @@ __global__ __launch_bounds__(kSmallBlock) void scan_small_kernel(const uint32_t*
     if (threadIdx.x == 0 && total) *total = carry;
 }
 
+// Table writer: one chunk of host bytes travels as a by-value kernel
+// argument and is stored with vector writes.
+constexpr int kChunkWords = 504;
+struct TableChunk {
+    uint32_t words;
+    uint32_t pad;
+    uint32_t w[kChunkWords];
+};
+__global__ __launch_bounds__(256) void table_chunk_kernel(uint32_t* dst, TableChunk c) {
+    for (uint32_t i = threadIdx.x; i < c.words; i += 256) dst[i] = c.w[i];
+}
+
+// Exclusive prefix over the assets of a per-asset value, by one workgroup of
+// 1024 threads in chunks of 1024 assets; out[n] receives the total.
+constexpr int kPrefixBlock = 1024;
+__device__ void asset_prefix(uint32_t v, int a, int n, uint32_t* out, uint32_t* carry_lds,
+                             uint32_t* lw) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) lw[wave] = x;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+    for (int w = 0; w < kPrefixBlock / 64; ++w) {
+        uint32_t t = lw[w];
+        if (w < wave) base += t;
+        tot += t;
+    }
+    const uint32_t carry = *carry_lds;
+    if (a < n) out[a] = carry + base + x - v;
+    __syncthreads();
+    if (threadIdx.x == 0) *carry_lds = carry + tot;
+    __syncthreads();
+}
+
+// After the raster: the ray list is the concatenation of the assets' face-
+// ordered lists, and the exclusive scan of the per-face counts (total at
+// index t_lf) gives every face's first ray.
+__global__ __launch_bounds__(kPrefixBlock) void ray_spaces_kernel(Batch B, const uint32_t* face_off,
+                                                                 int64_t t_lf, uint32_t* ray_pf,
+                                                                 uint32_t* rb_pf) {
+    __shared__ uint32_t lw[kPrefixBlock / 64];
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int c = 0; c < B.n; c += kPrefixBlock) {
+        const int a = c + threadIdx.x;
+        uint32_t nb = 0;
+        if (a < B.n) {
+            const AssetDev& A = B.A[a];
+            const uint32_t start = face_off[A.lf], end = face_off[A.lf + A.nlf];
+            ray_pf[a] = start;
+            B.cnt[(int64_t)a * kCntSlots + kCntRays] = end - start;
+            nb = (end - start + 63u) / 64u;
+        }
+        asset_prefix(nb, a, B.n, rb_pf, &carry, lw);
+    }
+    if (threadIdx.x == 0) {
+        ray_pf[B.n] = face_off[t_lf];
+        rb_pf[B.n] = carry;
+    }
+}
+
+__global__ __launch_bounds__(kPrefixBlock) void treelet_space_kernel(Batch B, uint32_t* tl_pf) {
+    __shared__ uint32_t lw[kPrefixBlock / 64];
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int c = 0; c < B.n; c += kPrefixBlock) {
+        const int a = c + threadIdx.x;
+        uint32_t m = 0;
+        if (a < B.n) {
+            const uint32_t cap = (uint32_t)treelet_cap(B.A[a].nhf);
+            m = min(B.cnt[(int64_t)a * kCntSlots + kCntTreelets], cap);
+            if (B.A[a].nhf <= 1) m = 0;  // nothing to refit
+        }
+        asset_prefix(m, a, B.n, tl_pf, &carry, lw);
+    }
+    if (threadIdx.x == 0) tl_pf[B.n] = carry;
+}
+
 int grid_for(int64_t n, int block) {
     int64_t g = (n + block - 1) / block;
     if (g < 1) g = 1;
@@ -187,6 +277,35 @@ hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint
     hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kScanBlock), 0, s, tmp, nb, total);
     hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, out, n,
                        (const uint32_t*)tmp);
+    return hipGetLastError();
+}
+
+hipError_t write_table(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    const uint32_t* w = (const uint32_t*)src;
+    const size_t words = (bytes + 3) / 4;  // callers pass 4-byte multiples
+    for (size_t o = 0; o < words; o += kChunkWords) {
+        TableChunk c;
+        c.words = (uint32_t)std::min<size_t>(kChunkWords, words - o);
+        c.pad = 0;
+        memcpy(c.w, w + o, 4 * (size_t)c.words);
+        hipLaunchKernelGGL(table_chunk_kernel, dim3(1), dim3(256), 0, s, (uint32_t*)dst + o, c);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_ray_spaces(const BatchHost& H, hipStream_t s) {
+    const Layout& L = H.L;
+    hipLaunchKernelGGL(ray_spaces_kernel, dim3(1), dim3(kPrefixBlock), 0, s, H.dev,
+                       (const uint32_t*)(H.ws + L.face_off), L.t_lf, (uint32_t*)(H.ws + L.ray_pf),
+                       (uint32_t*)(H.ws + L.rb_pf));
+    return hipGetLastError();
+}
+
+hipError_t launch_treelet_space(const BatchHost& H, hipStream_t s) {
+    hipLaunchKernelGGL(treelet_space_kernel, dim3(1), dim3(kPrefixBlock), 0, s, H.dev,
+                       (uint32_t*)(H.ws + H.L.tl_pf));
     return hipGetLastError();
 }
 

@@ -20,5 +20,7 @@ from .meshes import (  # noqa: F401
     Asset,
     make_config,
     make_batch_assets,
+    batch_asset_specs,
+    make_batch_asset,
     CONFIGS,
 )

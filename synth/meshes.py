@@ -374,30 +374,48 @@ def _level_for(n_faces: int) -> int:
     return L
 
 
-def make_batch_assets(n_assets: int = 64, seed: int = 0, hi_range=(50_000, 2_000_000),
+def batch_asset_specs(n_assets: int = 64, seed: int = 0, hi_range=(50_000, 2_000_000),
                       lo_range=(1_300, 40_000), res_choices=(512, 1024, 2048),
                       max_dist: float = 0.1) -> list:
-    """Uneven multi-asset batch: asset i uses noise seed i (4 octaves, A 0.03).
-
-    Face counts are log-uniform in the given ranges; each mesh is the icosphere
-    of the nearest level at or above the count, randomly decimated down to it.
-    """
+    """Sizes of the uneven multi-asset batch: (index, hi faces, lo faces, res,
+    max_dist) per asset, face counts log-uniform in the given ranges."""
     rng = np.random.default_rng([int(seed), 0x62617463])
     out = []
     for i in range(n_assets):
         nh = int(round(math.exp(rng.uniform(math.log(hi_range[0]), math.log(hi_range[1])))))
         nl = int(round(math.exp(rng.uniform(math.log(lo_range[0]), math.log(lo_range[1])))))
         res = int(rng.choice(res_choices))
-        Lh, Ll = _level_for(nh), _level_for(nl)
-        V, F = icosphere(Lh)
-        U = unit_directions(V)
-        hV = displace(U, noise_radius(U, i, 4, 0.03))
-        hV, hF = decimate(hV, F, nh, seed=1000 + i)
-        hF = hF.astype(np.int32)
-        lV, lF = icosphere(Ll)
-        lV, lF = decimate(lV.astype(np.float32), lF, nl, seed=2000 + i)
-        lF = lF.astype(np.int32)
-        out.append(Asset(f"batch{i}", hV, hF, vertex_normals(hV, hF), lV, lF,
-                         face_grid_atlas(lF.shape[0], res), res=res, max_dist=max_dist,
-                         meta=dict(hi_level=Lh, lo_level=Ll)))
+        out.append((i, nh, nl, res, float(max_dist)))
     return out
+
+
+def make_batch_asset(spec) -> Asset:
+    """One asset of the batch: noise seed i (4 octaves, A 0.03) on the icosphere
+    of the nearest level at or above the face count, randomly decimated down
+    to it."""
+    i, nh, nl, res, max_dist = spec
+    Lh, Ll = _level_for(nh), _level_for(nl)
+    V, F = icosphere(Lh)
+    U = unit_directions(V)
+    hV = displace(U, noise_radius(U, i, 4, 0.03))
+    hV, hF = decimate(hV, F, nh, seed=1000 + i)
+    hF = hF.astype(np.int32)
+    lV, lF = icosphere(Ll)
+    lV, lF = decimate(lV.astype(np.float32), lF, nl, seed=2000 + i)
+    lF = lF.astype(np.int32)
+    return Asset(f"batch{i}", hV, hF, vertex_normals(hV, hF), lV, lF,
+                 face_grid_atlas(lF.shape[0], res), res=res, max_dist=max_dist,
+                 meta=dict(hi_level=Lh, lo_level=Ll))
+
+
+def make_batch_assets(n_assets: int = 64, seed: int = 0, hi_range=(50_000, 2_000_000),
+                      lo_range=(1_300, 40_000), res_choices=(512, 1024, 2048),
+                      max_dist: float = 0.1, workers: int = 1) -> list:
+    """Uneven multi-asset batch (batch_asset_specs + make_batch_asset); with
+    workers > 1 the assets are generated in a process pool."""
+    specs = batch_asset_specs(n_assets, seed, hi_range, lo_range, res_choices, max_dist)
+    if workers <= 1:
+        return [make_batch_asset(sp) for sp in specs]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(make_batch_asset, specs, chunksize=1)

@@ -123,3 +123,88 @@ def test_product_does_not_reach_the_oracle():
                 txt = open(os.path.join(dp, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
                 assert "liboracle" not in txt, f
+
+
+# ---- batches ---------------------------------------------------------------
+
+def _asset(B, **over):
+    """bake_asset with fake (never dereferenced) device pointers."""
+    fake = 0x1000
+    a = B.BakeAsset()
+    a.hi_V, a.n_hi_v, a.hi_F, a.n_hi_f, a.hi_N = fake, 3, fake, 1, fake
+    a.lo_V, a.n_lo_v, a.lo_F, a.n_lo_f, a.lo_UV = fake, 3, fake, 1, fake
+    a.res, a.max_dist = 16, 0.1
+    a.out_map, a.out_hit = fake, fake
+    for k, v in over.items():
+        setattr(a, k, v)
+    return a
+
+
+def _arr(B, assets):
+    arr = (B.BakeAsset * len(assets))()
+    for i, a in enumerate(assets):
+        arr[i] = a
+    return arr
+
+
+def test_batch_of_one_has_the_single_layout(B):
+    for sizes, save in [((2562, 5120, 42, 80, 128), False), ((655362, 1310720, 10242, 20480, 2048), True)]:
+        a = _asset(B, n_hi_v=sizes[0], n_hi_f=sizes[1], n_lo_v=sizes[2], n_lo_f=sizes[3], res=sizes[4])
+        o = B.make_options(save=save)
+        b = C.c_size_t(0)
+        assert B.lib().bake_batch_workspace_size(_arr(B, [a]), 1, C.byref(o), C.byref(b)) == 0
+        assert b.value == B.workspace_size(*sizes, o)
+
+
+def test_batch_workspace_grows_with_assets(B):
+    one = C.c_size_t(0)
+    two = C.c_size_t(0)
+    a = _asset(B, n_hi_v=2562, n_hi_f=5120, n_lo_v=42, n_lo_f=80, res=128)
+    assert B.lib().bake_batch_workspace_size(_arr(B, [a]), 1, None, C.byref(one)) == 0
+    assert B.lib().bake_batch_workspace_size(_arr(B, [a, a]), 2, None, C.byref(two)) == 0
+    assert one.value < two.value < 2 * one.value + (1 << 20)
+
+
+@pytest.mark.parametrize("n", [0, -1, 65537])
+def test_batch_bad_count(B, n):
+    b = C.c_size_t(0)
+    arr = _arr(B, [_asset(B)])
+    assert B.lib().bake_batch_workspace_size(arr, n, None, C.byref(b)) == B.BAKE_E_INVALID_ARG
+    assert B.lib().bake_batch_workspace_size(None, 1, None, C.byref(b)) == B.BAKE_E_INVALID_ARG
+
+
+@pytest.mark.parametrize("over,code", [
+    (dict(res=12), -2), (dict(n_hi_f=-1), -1), (dict(max_dist=0.0), -1), (dict(out_map=None), -1),
+    (dict(out_hit=None), -1), (dict(hi_V=None), -1), (dict(lo_UV=None), -1),
+])
+def test_batch_validation_codes(B, over, code):
+    arr = _arr(B, [_asset(B), _asset(B, **over)])
+    rc = B.lib().bake_normals_batched(arr, 2, None, C.c_void_p(0x100000), 1 << 40, None)
+    assert rc == code, B.lib().bake_last_error()
+    assert "asset 1" in B.lib().bake_last_error().decode() or code == -2 or "n_hi_f" in str(over)
+
+
+def test_batch_rejects_shared_rgb8_and_small_workspace(B):
+    arr = _arr(B, [_asset(B), _asset(B)])
+    o = B.make_options(rgb8_ptr=0x2000)
+    assert B.lib().bake_normals_batched(arr, 2, C.byref(o), C.c_void_p(0x100000), 1 << 40, None) == -1
+    assert B.lib().bake_normals_batched(arr, 2, None, C.c_void_p(0x100000), 4096, None) == B.BAKE_E_WORKSPACE
+    assert B.lib().bake_normals_batched(arr, 2, None, C.c_void_p(0x100010), 1 << 40, None) == B.BAKE_E_WORKSPACE
+
+
+def test_batch_backward_without_saved_forward(B):
+    arr = _arr(B, [_asset(B, grad_map=0x3000, grad_lo_V=0x4000)])
+    rc = B.lib().bake_normals_batched_backward(arr, 1, C.c_void_p(0x7000000), 1 << 40, None)
+    assert rc == B.BAKE_E_STATE
+    arr = _arr(B, [_asset(B, grad_lo_V=0x4000)])  # gradient wanted without grad_map
+    rc = B.lib().bake_normals_batched_backward(arr, 1, C.c_void_p(0x7000000), 1 << 40, None)
+    assert rc == B.BAKE_E_INVALID_ARG
+
+
+def test_autotune_argument_checks(B):
+    arr = _arr(B, [_asset(B)])
+    best = B.BakeOptions()
+    assert B.lib().bake_autotune(arr, 1, None, 0, C.c_void_p(0x100000), 1 << 40, None, C.byref(best),
+                                 None) == B.BAKE_E_INVALID_ARG
+    assert B.lib().bake_autotune(arr, 1, None, 3, C.c_void_p(0x100000), 1 << 40, None, None,
+                                 None) == B.BAKE_E_INVALID_ARG

@@ -58,7 +58,11 @@ def _compare_grads(name, g_gpu, g_orc, excl):
     keep = ~excl
     rel_l2 = np.linalg.norm(g_gpu[keep] - g_orc[keep]) / max(np.linalg.norm(g_orc[keep]), 1e-30)
     err = np.abs(g_gpu[keep] - g_orc[keep])
-    tol = 1e-3 * np.abs(g_orc[keep]) + 1e-6 * np.abs(g_orc).max()
+    # an entry sums the contributions of many rays; the FP32 error of such a
+    # sum is relative to the sum of the contributions' magnitudes, which can
+    # be far larger than the result when they cancel: hence an absolute floor
+    # of 1e-5 of the largest entry next to the 1e-3 relative bound
+    tol = 1e-3 * np.abs(g_orc[keep]) + 1e-5 * np.abs(g_orc).max()
     worst = float((err / np.maximum(tol, 1e-300)).max()) if err.size else 0.0
     say(f"[gpu] grad {name}: rel L2 {rel_l2:.2e} (all entries {rel_all:.2e}), excluded "
         f"{int(excl.sum())}, worst err/tol {worst:.3f}")
@@ -118,10 +122,9 @@ def test_backward_ignores_non_hit_texels(B):
 def test_backward_without_saved_forward_is_an_error(B):
     a = make_config(1)
     t = B.to_device(a)
-    r = B.bake_normals(*t, a.res, a.max_dist)  # no save
-    r.opts = B.make_options(save=True)
-    nbytes = B.workspace_size(*r.sizes, r.opts)
-    r.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    r = B.bake_normals(*t, a.res, a.max_dist, save=True, dilate_passes=0)
+    # a later forward without save on the same workspace drops the saved state
+    B.bake_normals(*t, a.res, a.max_dist, dilate_passes=0, workspace=r.workspace)
     with pytest.raises(B.BakeError) as e:
         B.bake_normals_backward(r, t, torch.zeros((a.res, a.res, 3), device="cuda"))
     assert e.value.code == B.BAKE_E_STATE
