@@ -120,14 +120,14 @@ def bench_batch(B, assets, steps, warmup, trav, log):
     for g, src in zip(batch.grad_maps, grads):
         g.copy_(src)
     tune = B.autotune(batch, reps=1)
-    log(f"[bench] batch autotune: block {tune['block']} stack {tune['stack']} persist {tune['persist']}")
+    log(f"[bench] batch autotune: block {tune['block']} stack {tune['stack']} mode {tune['mode']}")
     batch.forward()
     batch.backward()
     torch.cuda.synchronize()
     rays = int(sum(batch.ray_counts()))
 
     # sequential plain calls (each with its own BVH build), one shared workspace
-    seq_opts = dict(trav_block=tune["block"], trav_stack=tune["stack"], trav_persist=tune["persist"])
+    seq_opts = dict(trav_block=tune["block"], trav_stack=tune["stack"], trav_mode=tune["mode"])
     ws_bytes = max(B.workspace_size(x[0].shape[0], x[1].shape[0], x[3].shape[0], x[4].shape[0], x[6],
                                     B.make_options(save=True)) for x in ins)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
@@ -174,7 +174,7 @@ def bench_batch(B, assets, steps, warmup, trav, log):
             "speedup_graph_vs_sequential": seq_ms / graph_ms,
             "rays_per_s_graph": rays / (graph_ms / 1e3), "rays_per_s_sequential": rays / (seq_ms / 1e3),
             "bitwise_equal_to_sequential": bool(same),
-            "tuned": {k: tune[k] for k in ("block", "stack", "persist")}}
+            "tuned": {k: tune[k] for k in ("block", "stack", "mode")}}
 
 
 def main():
@@ -186,7 +186,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--trav-block", type=int, default=0)
     ap.add_argument("--trav-stack", type=int, default=0)
-    ap.add_argument("--trav-persist", type=int, default=-1)
+    ap.add_argument("--trav-mode", type=int, default=-1)
     ap.add_argument("--batch-assets", type=int, default=0, metavar="N",
                     help="also measure an N-asset batch (64 = the uneven batch workload)")
     ap.add_argument("--batch-steps", type=int, default=5)
@@ -224,7 +224,7 @@ def main():
     asset = make_config(2)
     t = B.to_device(asset, dev)
     res, md = asset.res, asset.max_dist
-    trav = dict(trav_block=args.trav_block, trav_stack=args.trav_stack, trav_persist=args.trav_persist)
+    trav = dict(trav_block=args.trav_block, trav_stack=args.trav_stack, trav_mode=args.trav_mode)
     # loss target: the map baked (by this library, untimed) from a second noise seed
     tgt_asset = make_config(2, seed=1)
     target = B.bake_normals(*B.to_device(tgt_asset, dev), res, md).map.clone()

@@ -79,9 +79,10 @@ typedef struct bake_options {
     uint8_t *out_rgb8;     /* optional device [res,res,3] u8 map: floor((x+1)*127.5+0.5)   */
     int32_t trav_block;    /* traversal workgroup size: 64, 128, 256 (0 = tuned default)  */
     int32_t trav_stack;    /* LDS stack entries per lane: 8, 16, 32 (0 = tuned default)    */
-    int32_t trav_persist;  /* 1 = persistent waves refilling finished lanes from a ray
-                              queue, 0 = persistent waves taking whole 64-ray batches,
-                              -1 = tuned default                                          */
+    int32_t trav_mode;     /* persistent waves; 0 = whole 64-ray batches, one loop over
+                              nodes and leaves; 1 = finished lanes refilled from a ray
+                              queue; 2 = whole 64-ray batches, internal nodes and
+                              leaves in separate phases; -1 = default (2)                 */
     int32_t reserved[4];
 } bake_options;
 
@@ -240,11 +241,11 @@ int32_t bake_read_asset_counter(const void *workspace, int32_t asset, int32_t wh
                                 int64_t *value_out);
 
 /* Traversal autotuner: bakes the batch with every traversal configuration
- * (trav_block x trav_stack x trav_persist = 3 x 3 x 2), `reps` times each,
+ * (trav_block x trav_stack x trav_mode = 3 x 3 x 3), `reps` times each,
  * and returns in *best_out the options of `base` (NULL = defaults) with the
- * configuration of the smallest median traversal time; ms_out (NULL or 18
+ * configuration of the smallest median traversal time; ms_out (NULL or 27
  * floats) receives every configuration's median, in the order block-major,
- * then stack, then persist.  Synchronises the stream; do not record it in a
+ * then stack, then mode.  Synchronises the stream; do not record it in a
  * graph.  The outputs of the batch are those of the last configuration run
  * (all configurations give identical results). */
 int32_t bake_autotune(const bake_asset *assets, int32_t n_assets, const bake_options *base, int32_t reps,

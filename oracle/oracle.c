@@ -433,22 +433,32 @@ static int32_t bvh_query(const bvh *B, const float *V, const int32_t *F, v3 p, v
     return best;
 }
 
+static void bvh_make(bvh *B, const float *V, const int32_t *F, int64_t nf) {
+    B->nodes = (bnode *)malloc(sizeof(bnode) * (size_t)(2 * (nf > 0 ? nf : 1)));
+    B->perm = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nf > 0 ? nf : 1));
+    B->nnodes = 0;
+    double *cent = (double *)malloc(sizeof(double) * (size_t)(3 * (nf > 0 ? nf : 1)));
+    for (int64_t g = 0; g < nf; ++g) {
+        B->perm[g] = g;
+        for (int k = 0; k < 3; ++k)
+            cent[3 * g + k] = ((double)V[3 * F[3 * g] + k] + V[3 * F[3 * g + 1] + k] + V[3 * F[3 * g + 2] + k]) / 3.0;
+    }
+    if (nf > 0) build_rec(B, V, F, cent, 0, nf);
+    free(cent);
+}
+
+static void bvh_release(bvh *B) {
+    free(B->perm);
+    free(B->nodes);
+}
+
 int orc_query_bvh(const float *V, int64_t nv, const int32_t *F, int64_t nf, int64_t n, const double *P,
                   const double *D, const uint8_t *active, double max_dist,
                   int32_t *id_out, double *t_out, double *beta_out) {
     (void)nv;
     bvh B;
-    B.nodes = (bnode *)malloc(sizeof(bnode) * (size_t)(2 * (nf > 0 ? nf : 1)));
-    B.perm = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nf > 0 ? nf : 1));
-    B.nnodes = 0;
-    double *cent = (double *)malloc(sizeof(double) * (size_t)(3 * (nf > 0 ? nf : 1)));
-    for (int64_t g = 0; g < nf; ++g) {
-        B.perm[g] = g;
-        for (int k = 0; k < 3; ++k)
-            cent[3 * g + k] = ((double)V[3 * F[3 * g] + k] + V[3 * F[3 * g + 1] + k] + V[3 * F[3 * g + 2] + k]) / 3.0;
-    }
+    bvh_make(&B, V, F, nf);
     int err = 0;
-    if (nf > 0) build_rec(&B, V, F, cent, 0, nf);
 #pragma omp parallel for schedule(dynamic, 64) reduction(| : err)
     for (int64_t r = 0; r < n; ++r) {
         double t = 0, beta[3] = {0, 0, 0};
@@ -461,10 +471,170 @@ int orc_query_bvh(const float *V, int64_t nv, const int32_t *F, int64_t nf, int6
         if (t_out) t_out[r] = id >= 0 ? t : 0;
         if (beta_out) { beta_out[3 * r] = beta[0]; beta_out[3 * r + 1] = beta[1]; beta_out[3 * r + 2] = beta[2]; }
     }
-    free(cent);
-    free(B.perm);
-    free(B.nodes);
+    bvh_release(&B);
     return err ? ORC_EINVAL : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Closest-point query (the paper's own form of the correspondence step)     */
+/* ------------------------------------------------------------------------ */
+/*
+ * Sec. 6.4 locates, for each texel's world position p, the closest point of
+ * the high-poly surface and rejects it when it is farther than a distance
+ * bound (the paper: 1% of the bounding-box diagonal; here max_dist).  Per
+ * triangle the nearest point q minimises |p - q| over the triangle: the
+ * orthogonal projection of p onto the plane when its barycentric weights are
+ * all >= 0; otherwise the minimum lies on the border (a convex function over a
+ * convex set whose free minimum is outside), i.e. the nearest of the three
+ * edges' nearest points.  Over the mesh the winner minimises
+ * (floor(dist / w), index) with w = max_dist 2^-20, as for the ray query, so a
+ * closest point on a shared edge or vertex resolves to the lower index.
+ */
+
+/* Parameter in [0, 1] of the point of segment [a, b] nearest to p. */
+static double seg_param(v3 p, v3 a, v3 b) {
+    v3 ab = sub(b, a);
+    double l2 = dot(ab, ab);
+    if (!(l2 > 0)) return 0.0;
+    double s = dot(sub(p, a), ab) / l2;
+    return s < 0 ? 0.0 : (s > 1 ? 1.0 : s);
+}
+
+/* Distance from p to triangle g and the barycentric weights of its nearest point. */
+static double tri_closest(v3 p, const float *V, const int32_t *F, int64_t g, double w[3]) {
+    v3 P3[3];
+    for (int k = 0; k < 3; ++k) P3[k] = ld3f(V, F[3 * g + k]);
+    v3 n = cross(sub(P3[1], P3[0]), sub(P3[2], P3[0]));
+    double nn = dot(n, n);
+    if (nn > 0) {
+        v3 q = sub(p, scl(n, dot(n, sub(p, P3[0])) / nn));
+        double wa = dot(n, cross(sub(P3[1], q), sub(P3[2], q))) / nn;
+        double wb = dot(n, cross(sub(P3[2], q), sub(P3[0], q))) / nn;
+        double wc = dot(n, cross(sub(P3[0], q), sub(P3[1], q))) / nn;
+        if (wa >= 0 && wb >= 0 && wc >= 0) {
+            w[0] = wa; w[1] = wb; w[2] = wc;
+            return norm(sub(p, q));
+        }
+    }
+    double best = INFINITY;
+    for (int e = 0; e < 3; ++e) {
+        int i = e, j = (e + 1) % 3;
+        double s = seg_param(p, P3[i], P3[j]);
+        double dd = norm(sub(p, add(P3[i], scl(sub(P3[j], P3[i]), s))));
+        if (dd < best) {
+            best = dd;
+            w[0] = w[1] = w[2] = 0;
+            w[i] = 1 - s;
+            w[j] = s;
+        }
+    }
+    return best;
+}
+
+/* Brute force over every triangle in ascending index order. */
+int orc_closest_brute(const float *V, const int32_t *F, int64_t nf, int64_t n, const double *P,
+                      const uint8_t *active, double max_dist, int32_t *id_out, double *dist_out,
+                      double *w_out) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < n; ++r) {
+        int32_t best = -1;
+        double bd = 0, bw[3] = {0, 0, 0};
+        if (!active || active[r]) {
+            v3 p = ld3d(P, r);
+            for (int64_t g = 0; g < nf; ++g) {
+                double w[3];
+                double dd = tri_closest(p, V, F, g, w);
+                if (!(dd <= max_dist)) continue;
+                if (best < 0 || better(dd, g, bd, best, max_dist)) {
+                    best = (int32_t)g; bd = dd; bw[0] = w[0]; bw[1] = w[1]; bw[2] = w[2];
+                }
+            }
+        }
+        id_out[r] = best;
+        if (dist_out) dist_out[r] = best >= 0 ? bd : 0;
+        if (w_out) { w_out[3 * r] = bw[0]; w_out[3 * r + 1] = bw[1]; w_out[3 * r + 2] = bw[2]; }
+    }
+    return ORC_OK;
+}
+
+/* Distance from p to the box (0 inside). */
+static double box_dist(const bnode *nd, v3 p) {
+    double pp[3] = {p.x, p.y, p.z}, s = 0;
+    for (int k = 0; k < 3; ++k) {
+        double e = 0;
+        if (pp[k] < nd->lo[k]) e = nd->lo[k] - pp[k];
+        else if (pp[k] > nd->hi[k]) e = pp[k] - nd->hi[k];
+        s += e * e;
+    }
+    return sqrt(s);
+}
+
+/* The same query on the FP64 BVH: nodes farther than the current best key's
+ * bin are skipped (boxes are padded outward, and the bound has a relative
+ * margin), so the result equals the brute force. */
+static int32_t bvh_closest(const bvh *B, const float *V, const int32_t *F, v3 p, double max_dist,
+                           double *d_out, double w_out[3]) {
+    int64_t stack[256];
+    int sp = 0;
+    int32_t best = -1;
+    double bd = 0, bw[3] = {0, 0, 0};
+    double bound = max_dist;
+    stack[sp++] = 0;
+    while (sp > 0) {
+        const bnode *nd = &B->nodes[stack[--sp]];
+        if (box_dist(nd, p) > bound * (1 + 1e-12)) continue;
+        if (nd->left < 0) {
+            for (int64_t i = nd->first; i < nd->first + nd->count; ++i) {
+                int64_t g = B->perm[i];
+                double w[3];
+                double dd = tri_closest(p, V, F, g, w);
+                if (!(dd <= max_dist)) continue;
+                if (best < 0 || better(dd, g, bd, best, max_dist)) {
+                    best = (int32_t)g; bd = dd; bw[0] = w[0]; bw[1] = w[1]; bw[2] = w[2];
+                    bound = (double)(tkey(bd, max_dist) + 1) * ldexp(max_dist, -T_QUANT_BITS);
+                }
+            }
+            continue;
+        }
+        if (sp + 2 > 256) return -100;
+        stack[sp++] = nd->left;
+        stack[sp++] = nd->right;
+    }
+    *d_out = bd;
+    w_out[0] = bw[0]; w_out[1] = bw[1]; w_out[2] = bw[2];
+    return best;
+}
+
+int orc_closest_bvh(const float *V, const int32_t *F, int64_t nf, int64_t n, const double *P,
+                    const uint8_t *active, double max_dist, int32_t *id_out, double *dist_out,
+                    double *w_out) {
+    bvh B;
+    bvh_make(&B, V, F, nf);
+    int err = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(| : err)
+    for (int64_t r = 0; r < n; ++r) {
+        double dd = 0, w[3] = {0, 0, 0};
+        int32_t id = -1;
+        if ((!active || active[r]) && nf > 0) {
+            id = bvh_closest(&B, V, F, ld3d(P, r), max_dist, &dd, w);
+            if (id == -100) { err = 1; id = -1; }
+        }
+        id_out[r] = id;
+        if (dist_out) dist_out[r] = id >= 0 ? dd : 0;
+        if (w_out) { w_out[3 * r] = w[0]; w_out[3 * r + 1] = w[1]; w_out[3 * r + 2] = w[2]; }
+    }
+    bvh_release(&B);
+    return err ? ORC_EINVAL : ORC_OK;
+}
+
+/* Comparator support: distance from P[r] to a given triangle g[r]. */
+int orc_closest_check(const float *V, const int32_t *F, int64_t n, const double *P, const int32_t *g,
+                      double *dist_out) {
+    for (int64_t r = 0; r < n; ++r) {
+        double w[3];
+        dist_out[r] = tri_closest(ld3d(P, r), V, F, g[r], w);
+    }
+    return ORC_OK;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -57,7 +57,7 @@ class BakeOptions(C.Structure):
         ("out_rgb8", C.c_void_p),
         ("trav_block", C.c_int32),
         ("trav_stack", C.c_int32),
-        ("trav_persist", C.c_int32),
+        ("trav_mode", C.c_int32),
         ("reserved", C.c_int32 * 4),
     ]
 
@@ -137,7 +137,7 @@ def _check(rc: int):
 
 
 def make_options(dilate_passes=2, save=False, timing=False, rgb8_ptr=0, trav_block=0,
-                 trav_stack=0, trav_persist=-1, count=False) -> BakeOptions:
+                 trav_stack=0, trav_mode=-1, count=False) -> BakeOptions:
     o = BakeOptions()
     lib().bake_default_options(C.byref(o))
     o.dilate_passes = int(dilate_passes)
@@ -146,7 +146,7 @@ def make_options(dilate_passes=2, save=False, timing=False, rgb8_ptr=0, trav_blo
     o.out_rgb8 = rgb8_ptr or None
     o.trav_block = int(trav_block)
     o.trav_stack = int(trav_stack)
-    o.trav_persist = int(trav_persist)
+    o.trav_mode = int(trav_mode)
     return o
 
 
@@ -225,7 +225,7 @@ class BakeResult:
 def bake_normals(hi_V, hi_F, hi_N, lo_V, lo_F, lo_UV, res: int, max_dist: float, *,
                  dilate_passes: int = 2, rgb8: bool = False, save: bool = False,
                  timing: bool = False, trav_block: int = 0, trav_stack: int = 0,
-                 trav_persist: int = -1, count: bool = False,
+                 trav_mode: int = -1, count: bool = False,
                  workspace: Optional[torch.Tensor] = None,
                  out_map: Optional[torch.Tensor] = None, out_hit: Optional[torch.Tensor] = None,
                  stream=None) -> BakeResult:
@@ -246,7 +246,7 @@ def bake_normals(hi_V, hi_F, hi_N, lo_V, lo_F, lo_UV, res: int, max_dist: float,
     sizes = (hi_V.shape[0], hi_F.shape[0], lo_V.shape[0], lo_F.shape[0], int(res))
     rgb = torch.empty((res, res, 3), dtype=torch.uint8, device=dev) if rgb8 else None
     opts = make_options(dilate_passes, save, timing, rgb.data_ptr() if rgb is not None else 0,
-                        trav_block, trav_stack, trav_persist, count)
+                        trav_block, trav_stack, trav_mode, count)
     nbytes = workspace_size(*sizes, opts)
     if workspace is None or workspace.numel() < nbytes:
         workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
@@ -343,7 +343,7 @@ class BakeBatch:
     Every asset's results are bitwise those of a single bake_normals call."""
 
     def __init__(self, assets, *, save=False, dilate_passes=2, rgb8=False, trav_block=0,
-                 trav_stack=0, trav_persist=-1, need_lo=True, need_hi=True):
+                 trav_stack=0, trav_mode=-1, need_lo=True, need_hi=True):
         if not assets:
             raise ValueError("empty batch")
         self.inputs = []
@@ -391,13 +391,13 @@ class BakeBatch:
             e.grad_lo_V = glo.data_ptr() if glo is not None else None
             e.grad_hi_N = ghi.data_ptr() if ghi is not None else None
         self.device = self.inputs[0][0].device
-        self.opts = make_options(dilate_passes, save, False, 0, trav_block, trav_stack, trav_persist)
+        self.opts = make_options(dilate_passes, save, False, 0, trav_block, trav_stack, trav_mode)
         b = C.c_size_t(0)
         _check(lib().bake_batch_workspace_size(self._arr, self.n, C.byref(self.opts), C.byref(b)))
         self.workspace = torch.empty(b.value, dtype=torch.uint8, device=self.device)
 
-    def set_traversal(self, block=0, stack=0, persist=-1):
-        self.opts.trav_block, self.opts.trav_stack, self.opts.trav_persist = int(block), int(stack), int(persist)
+    def set_traversal(self, block=0, stack=0, mode=-1):
+        self.opts.trav_block, self.opts.trav_stack, self.opts.trav_mode = int(block), int(stack), int(mode)
 
     def forward(self, timing=False, count=False, stream=None):
         o = BakeOptions.from_buffer_copy(self.opts)
@@ -453,21 +453,21 @@ class BakeBatch:
         return f"n{self.n}-tex2^{round(math.log2(max(tex, 1)))}-tri2^{round(math.log2(max(tri, 1)))}"
 
 
-TRAV_CONFIGS = [(b, s, p) for b in (64, 128, 256) for s in (8, 16, 32) for p in (0, 1)]
+TRAV_CONFIGS = [(b, s, m) for b in (64, 128, 256) for s in (8, 16, 32) for m in (0, 1, 2)]
 
 
 def autotune(batch: BakeBatch, reps: int = 3, cache_path: Optional[str] = None, stream=None) -> dict:
     """Time every traversal configuration on `batch` (bake_autotune), set the
     fastest on the batch and, with cache_path, store it in the JSON cache under
-    the batch's size class.  Returns {"block", "stack", "persist", "ms": {...}}."""
+    the batch's size class.  Returns {"block", "stack", "mode", "ms": {...}}."""
     import json
     best = BakeOptions()
     ms = (C.c_float * len(TRAV_CONFIGS))()
     _check(lib().bake_autotune(batch._arr, batch.n, C.byref(batch.opts), int(reps), _ptr(batch.workspace),
                                batch.workspace.numel(), _stream_handle(stream), C.byref(best), ms))
-    out = {"block": best.trav_block, "stack": best.trav_stack, "persist": best.trav_persist,
-           "ms": {f"{b}/{s}/{p}": float(ms[i]) for i, (b, s, p) in enumerate(TRAV_CONFIGS)}}
-    batch.set_traversal(best.trav_block, best.trav_stack, best.trav_persist)
+    out = {"block": best.trav_block, "stack": best.trav_stack, "mode": best.trav_mode,
+           "ms": {f"{b}/{s}/{m}": float(ms[i]) for i, (b, s, m) in enumerate(TRAV_CONFIGS)}}
+    batch.set_traversal(best.trav_block, best.trav_stack, best.trav_mode)
     if cache_path:
         cache = {}
         if os.path.exists(cache_path):
@@ -490,7 +490,7 @@ def apply_tuning(batch: BakeBatch, cache_path: str) -> bool:
         e = json.load(f).get(batch.size_class())
     if not e:
         return False
-    batch.set_traversal(e["block"], e["stack"], e["persist"])
+    batch.set_traversal(e["block"], e["stack"], e["mode"])
     return True
 
 

@@ -60,7 +60,7 @@ int32_t parse_opts(const bake_options* o, Opts* out) {
     out->rgb8 = nullptr;
     out->trav.block = 256;
     out->trav.stack = 16;
-    out->trav.persist = 0;
+    out->trav.mode = 2;
     if (!o) return BAKE_OK;
     if (o->dilate_passes < 0 || o->dilate_passes > 64)
         return fail(BAKE_E_INVALID_ARG, "dilate_passes %d outside [0, 64]", o->dilate_passes);
@@ -79,9 +79,9 @@ int32_t parse_opts(const bake_options* o, Opts* out) {
             return fail(BAKE_E_INVALID_ARG, "trav_stack %d not in {8,16,32}", o->trav_stack);
         out->trav.stack = o->trav_stack;
     }
-    if (o->trav_persist < -1 || o->trav_persist > 1)
-        return fail(BAKE_E_INVALID_ARG, "trav_persist %d not in {-1,0,1}", o->trav_persist);
-    if (o->trav_persist >= 0) out->trav.persist = o->trav_persist;
+    if (o->trav_mode < -1 || o->trav_mode > 2)
+        return fail(BAKE_E_INVALID_ARG, "trav_mode %d not in {-1,0,1,2}", o->trav_mode);
+    if (o->trav_mode >= 0) out->trav.mode = o->trav_mode;
     return BAKE_OK;
 }
 
@@ -117,6 +117,7 @@ int64_t grid_blocks(int g, const Sizes& z) {
         case kGTex: return cdiv(tex, 256);
         case kGTex3: return cdiv(3 * tex, 256);
         case kGBwdSort: return cdiv(3 * tex, kSortTile);
+        case kGTile: return cdiv(z.res, kFinishTile) * cdiv(z.res, kFinishTile);
     }
     return 0;
 }
@@ -443,7 +444,6 @@ int32_t run_forward(Plan& P, const Opts& o, void* workspace, hipStream_t s) {
     HIP_OR_FAIL(launch_lo_prep(H, s));
     HIP_OR_FAIL(tim_record(tim, 1, s));
     HIP_OR_FAIL(launch_raster(H, s));
-    HIP_OR_FAIL(launch_fill_uncovered(H, s));
     HIP_OR_FAIL(tim_record(tim, 2, s));
     HIP_OR_FAIL(launch_bvh_build(H, s));
     HIP_OR_FAIL(tim_record(tim, 3, s));
@@ -526,7 +526,7 @@ void bake_default_options(bake_options* opt) {
     if (!opt) return;
     memset(opt, 0, sizeof *opt);
     opt->dilate_passes = 2;
-    opt->trav_persist = -1;
+    opt->trav_mode = -1;
 }
 
 const char* bake_last_error(void) { return g_err; }
@@ -681,11 +681,11 @@ int32_t bake_autotune(const bake_asset* assets, int32_t n_assets, const bake_opt
     int idx = 0;
     for (int bi = 0; bi < 3; ++bi)
         for (int si = 0; si < 3; ++si)
-            for (int pe = 0; pe < 2; ++pe, ++idx) {
+            for (int pe = 0; pe < 3; ++pe, ++idx) {
                 bake_options o = opt;
                 o.trav_block = blocks[bi];
                 o.trav_stack = stacks[si];
-                o.trav_persist = pe;
+                o.trav_mode = pe;
                 o.flags = (opt.flags & ~(uint32_t)BAKE_FLAG_COUNT) | BAKE_FLAG_TIMING;
                 std::vector<float> t(reps);
                 for (int r = 0; r < reps; ++r) {
@@ -703,7 +703,7 @@ int32_t bake_autotune(const bake_asset* assets, int32_t n_assets, const bake_opt
                     best_opt = opt;
                     best_opt.trav_block = blocks[bi];
                     best_opt.trav_stack = stacks[si];
-                    best_opt.trav_persist = pe;
+                    best_opt.trav_mode = pe;
                 }
             }
     *best_out = best_opt;

@@ -117,10 +117,13 @@ enum GridId : int {
     kGTex,      // texels, 256 per block
     kGTex3,     // texel channels, 256 per block
     kGBwdSort,  // backward sort tiles (capacity 3 res^2, kSortTile per block)
+    kGTile,     // kFinishTile^2 texel tiles of the fused uncovered fill + dilation
     kGridCount
 };
 
 constexpr int kSortTile = 4096;  // keys per radix-sort block and pass
+constexpr int kFinishTile = 32;  // texel tile side of the fused fill + dilation
+constexpr int kMaxFusedPasses = 4;  // more dilation passes run one launch per pass
 
 // Treelet and frontier capacity per asset.  Treelet roots are the small
 // children of the nodes with more than 2048 leaves ("big" nodes).  Big nodes
@@ -224,7 +227,8 @@ struct BatchHost {
 struct TravConfig {
     int block;    // 64 / 128 / 256
     int stack;    // LDS entries per lane: 8 / 16 / 32
-    int persist;  // 1: refill finished lanes from a ray queue; 0: whole-wave 64-ray batches
+    int mode;     // 0: 64-ray batches, one loop; 1: lane refill from a ray queue;
+                  // 2: 64-ray batches, internal-node and leaf phases
     bool count = false;  // instrumented variant: count box and triangle tests
 };
 

@@ -211,7 +211,9 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(Batch Bt, const uint
 }
 
 // Element r*256 + tid of the block's tile is ranked among equal digits by
-// (earlier rounds, earlier waves, earlier lanes): a stable order.  The scanned
+// (earlier rounds, earlier waves, earlier lanes): a stable order.  The tile is
+// first placed in LDS in that order (digit runs contiguous), then written out
+// with consecutive lanes on consecutive positions of each run.  The scanned
 // digit counts are positions in the concatenated arrays.
 template <bool BWD>
 __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(Batch Bt, const uint32_t* __restrict__ kin,
@@ -219,36 +221,69 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(Batch Bt, const u
                                                                uint32_t* __restrict__ kout,
                                                                uint32_t* __restrict__ vout, int shift,
                                                                const uint32_t* __restrict__ offs) {
-    __shared__ uint32_t run[256];
+    __shared__ uint32_t s_key[kSortTile];
+    __shared__ uint32_t s_val[kSortTile];
+    __shared__ uint32_t s_loc[256];   // tile-local first position of each digit
+    __shared__ uint32_t s_glob[256];  // global position of the tile's first key of each digit
+    __shared__ uint32_t s_run[256];   // digit counts, then running positions
+    __shared__ uint32_t s_wsum[kBlock / 64];
     __shared__ uint32_t wcnt[kBlock / 64][256];
     if (BWD && !sealed(Bt)) return;
     const SortTile T = sort_tile<BWD>(Bt, blockIdx.x);
-    const int tid = threadIdx.x, wave = tid >> 6;
-    run[tid] = offs[T.hbase + (int64_t)tid * T.tiles + T.lt];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t base = T.lt * kSortTile;
+    const int64_t nvalid = min((int64_t)kSortTile, T.count - base);
+    if (nvalid <= 0) return;  // an empty capacity tile (uniform)
+    s_glob[tid] = offs[T.hbase + (int64_t)tid * T.tiles + T.lt];
+    s_run[tid] = 0;
 #pragma unroll
     for (int w = 0; w < kBlock / 64; ++w) wcnt[w][tid] = 0;
     __syncthreads();
-    const int64_t base = T.lt * kSortTile;
+    uint32_t key[kSortRounds], val[kSortRounds];
+#pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
-        int64_t i = base + (int64_t)r * kBlock + tid;
-        bool valid = i < T.count;
-        uint32_t key = valid ? kin[T.start + i] : 0u, val = valid ? vin[T.start + i] : 0u;
-        uint32_t dig = (key >> shift) & 255u;
+        const int64_t i = (int64_t)r * kBlock + tid;
+        const bool valid = i < nvalid;
+        key[r] = valid ? kin[T.start + base + i] : 0u;
+        val[r] = valid ? vin[T.start + base + i] : 0u;
+        if (valid) atomicAdd(&s_run[(key[r] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    {   // exclusive scan of the tile's digit counts (one digit per thread)
+        const uint32_t c = s_run[tid];
+        uint32_t x = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) s_wsum[wave] = x;
+        __syncthreads();
+        uint32_t before = 0;
+        for (int w = 0; w < wave; ++w) before += s_wsum[w];
+        s_loc[tid] = before + x - c;
+        s_run[tid] = before + x - c;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+        const bool valid = (int64_t)r * kBlock + tid < nvalid;
+        const uint32_t dig = (key[r] >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            bool bit = (dig >> b) & 1u;
-            uint64_t m = __ballot(bit);
+            const bool bit = (dig >> b) & 1u;
+            const uint64_t m = __ballot(bit);
             peers &= bit ? m : ~m;
         }
-        uint32_t rank = (uint32_t)__popcll(peers & __lanemask_lt());
+        const uint32_t rank = (uint32_t)__popcll(peers & __lanemask_lt());
         if (valid && rank == 0) wcnt[wave][dig] = (uint32_t)__popcll(peers);
         __syncthreads();
         if (valid) {
-            uint32_t pos = run[dig] + rank;
+            uint32_t pos = s_run[dig] + rank;
             for (int w = 0; w < wave; ++w) pos += wcnt[w][dig];
-            kout[pos] = key;
-            vout[pos] = val;
+            s_key[pos] = key[r];
+            s_val[pos] = val[r];
         }
         __syncthreads();
         uint32_t add = 0;
@@ -257,8 +292,18 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(Batch Bt, const u
             add += wcnt[w][tid];
             wcnt[w][tid] = 0;
         }
-        run[tid] += add;
+        s_run[tid] += add;
         __syncthreads();
+    }
+#pragma unroll 4
+    for (int r = 0; r < kSortRounds; ++r) {
+        const int e = r * kBlock + tid;
+        if (e >= nvalid) break;
+        const uint32_t k = s_key[e];
+        const uint32_t d = (k >> shift) & 255u;
+        const uint32_t pos = s_glob[d] + ((uint32_t)e - s_loc[d]);
+        kout[pos] = k;
+        vout[pos] = s_val[e];
     }
 }
 
@@ -338,7 +383,7 @@ __global__ __launch_bounds__(kBlock) void karras_kernel(Batch Bt, const uint32_t
 //     frontier (global counters that only this workgroup touches).
 
 constexpr int kTreelet = 2048;
-constexpr int kRefitBlock = 256;
+constexpr int kRefitBlock = 1024;  // 16 waves: the LDS footprint allows one workgroup per CU
 constexpr int kTopBlock = 1024;
 
 __device__ __forceinline__ void put_slot(BvhNode* node, int side, const float b[6]) {

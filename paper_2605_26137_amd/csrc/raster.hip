@@ -362,6 +362,98 @@ __global__ __launch_bounds__(256) void dilate_kernel(Batch Bt, int pass, uint8_t
     level[t] = (uint8_t)pass;
 }
 
+// Uncovered fill and k <= kMaxFusedPasses dilation passes in one launch: a
+// workgroup loads its kFinishTile^2 tile plus a k-texel halo into LDS
+// (covered texels with their traced value, uncovered ones as (0,0,1)), runs
+// the passes there with the pass rule of dilate_kernel, and writes the tile's
+// uncovered texels.  A value at distance d from the region's edge is exact
+// through pass d, so the tile (d >= k) is exact after k passes: the result is
+// bitwise that of the fill + per-pass launches.
+constexpr int kFinishBlock = 256;
+constexpr int kRegionMax = kFinishTile + 2 * kMaxFusedPasses;
+constexpr uint8_t kOutside = 254;  // outside the image: never read, never filled
+
+__global__ __launch_bounds__(kFinishBlock) void finish_kernel(Batch Bt, int passes,
+                                                              const uint32_t* __restrict__ facemap_all) {
+    __shared__ float s_map[kRegionMax * kRegionMax][3];
+    __shared__ uint8_t s_lvl[kRegionMax * kRegionMax];
+    int64_t lt;
+    const AssetDev& As = Bt.A[block_asset(Bt, kGTile, blockIdx.x, &lt)];
+    const int32_t res = As.res;
+    const int32_t tiles_x = (res + kFinishTile - 1) / kFinishTile;
+    const int32_t ti = (int32_t)(lt / tiles_x) * kFinishTile, tj = (int32_t)(lt % tiles_x) * kFinishTile;
+    const int32_t R = kFinishTile + 2 * passes;
+    const int32_t oi = ti - passes, oj = tj - passes;  // region origin
+    const uint32_t* __restrict__ facemap = facemap_all + As.tex;
+    const float* __restrict__ map = As.out_map;
+    for (int x = threadIdx.x; x < R * R; x += kFinishBlock) {
+        const int32_t i = oi + x / R, j = oj + x % R;
+        uint8_t lvl = kOutside;
+        float v0 = 0.f, v1 = 0.f, v2 = 1.f;
+        if (i >= 0 && j >= 0 && i < res && j < res) {
+            const int64_t t = (int64_t)i * res + j;
+            if (facemap[t] != 0x7FFFFFFFu) {
+                lvl = 0;
+                v0 = map[3 * t];
+                v1 = map[3 * t + 1];
+                v2 = map[3 * t + 2];
+            } else {
+                lvl = 255;
+            }
+        }
+        s_lvl[x] = lvl;
+        s_map[x][0] = v0;
+        s_map[x][1] = v1;
+        s_map[x][2] = v2;
+    }
+    __syncthreads();
+    for (int pass = 1; pass <= passes; ++pass) {
+        // texels filled in this pass get level `pass` and are never read in it
+        for (int x = threadIdx.x; x < R * R; x += kFinishBlock) {
+            if (s_lvl[x] != 255) continue;
+            const int32_t ri = x / R, rj = x % R;
+            float sx = 0.f, sy = 0.f, sz = 0.f;
+            int cnt = 0;
+#pragma unroll
+            for (int di = -1; di <= 1; ++di) {
+#pragma unroll
+                for (int dj = -1; dj <= 1; ++dj) {
+                    if (di == 0 && dj == 0) continue;
+                    const int32_t ii = ri + di, jj = rj + dj;
+                    if (ii < 0 || jj < 0 || ii >= R || jj >= R) continue;
+                    const int u = ii * R + jj;
+                    if (s_lvl[u] < pass) {
+                        sx += s_map[u][0];
+                        sy += s_map[u][1];
+                        sz += s_map[u][2];
+                        ++cnt;
+                    }
+                }
+            }
+            if (cnt == 0) continue;
+            float l2 = sx * sx + sy * sy + sz * sz;
+            if (!(l2 > 0.f)) continue;
+            float r = 1.0f / sqrtf(l2);
+            s_map[x][0] = sx * r;
+            s_map[x][1] = sy * r;
+            s_map[x][2] = sz * r;
+            s_lvl[x] = (uint8_t)pass;
+        }
+        __syncthreads();
+    }
+    for (int x = threadIdx.x; x < kFinishTile * kFinishTile; x += kFinishBlock) {
+        const int32_t i = ti + x / kFinishTile, j = tj + x % kFinishTile;
+        if (i >= res || j >= res) continue;
+        const int u = (i - oi) * R + (j - oj);
+        if (s_lvl[u] == 0) continue;  // covered: the traversal's value stays
+        const int64_t t = (int64_t)i * res + j;
+        As.out_map[3 * t] = s_map[u][0];
+        As.out_map[3 * t + 1] = s_map[u][1];
+        As.out_map[3 * t + 2] = s_map[u][2];
+        As.out_hit[t] = kUncovered;
+    }
+}
+
 __global__ __launch_bounds__(256) void rgb8_kernel(Batch Bt) {
     int64_t lb;
     const AssetDev& As = Bt.A[block_asset(Bt, kGTex3, blockIdx.x, &lb)];
@@ -442,8 +534,16 @@ hipError_t launch_fill_uncovered(const BatchHost& H, hipStream_t s) {
     return hipGetLastError();
 }
 
+// After the traversal: uncovered fill and dilation, fused for few passes.
 hipError_t launch_dilate(const BatchHost& H, int passes, hipStream_t s) {
-    if (H.blocks(kGTex) == 0) return hipSuccess;
+    if (passes <= kMaxFusedPasses) {
+        if (H.blocks(kGTile) == 0) return hipSuccess;
+        hipLaunchKernelGGL(finish_kernel, dim3((unsigned)H.blocks(kGTile)), dim3(kFinishBlock), 0, s, H.dev,
+                           passes, (const uint32_t*)(H.ws + H.L.facemap));
+        return hipGetLastError();
+    }
+    hipError_t e = launch_fill_uncovered(H, s);
+    if (e != hipSuccess || H.blocks(kGTex) == 0) return e;
     for (int k = 1; k <= passes; ++k) {
         hipLaunchKernelGGL(dilate_kernel, dim3((unsigned)H.blocks(kGTex)), dim3(256), 0, s, H.dev, k,
                            (uint8_t*)(H.ws + H.L.level));

@@ -327,40 +327,51 @@ struct LaneStack {
     }
 };
 
-// One traversal step of a lane: an internal node (test both child boxes, go to
-// the nearer hit, push the other) or a leaf (triangle test), then pop when the
-// lane has nowhere to go.  Returns the next node (kEmpty: the ray is done).
+// One traversal step of a lane at an internal node: test both child boxes, go
+// to the nearer hit and push the other, or pop when neither is hit.  Returns
+// the next node (internal, leaf, or kEmpty: the ray is done).
+template <int BLOCK, int STACK, bool COUNT>
+__device__ __forceinline__ int32_t inner_step(const TreeView& tv, uint32_t* status, int32_t node,
+                                              const RayT& R, const Best& best, LaneStack<BLOCK, STACK>& st,
+                                              int tid, unsigned long long& c_box) {
+    const BvhNode* nd = tv.nodes + node;
+    float4 na = nd->a, nb = nd->b, nc = nd->c;
+    int4 ref = nd->ref;
+    float mL, mR;
+    bool hL = box_test(R, f3(na.x, na.y, na.z), f3(na.w, nb.x, nb.y), best.bound, &mL);
+    bool hR = box_test(R, f3(nb.z, nb.w, nc.x), f3(nc.y, nc.z, nc.w), best.bound, &mR);
+    if (COUNT) c_box += 2;
+    int32_t next = kEmpty;
+    if (hL && hR) {
+        bool rfirst = mR < mL;
+        next = rfirst ? ref.y : ref.x;
+        st.push(rfirst ? ref.x : ref.y, tid, status);
+    } else if (hL) {
+        next = ref.x;
+    } else if (hR) {
+        next = ref.y;
+    }
+    if (next == kEmpty) next = st.pop(tid);
+    return next;
+}
+
+// A lane at a leaf: triangle test, then pop.
+template <int BLOCK, int STACK, bool COUNT>
+__device__ __forceinline__ int32_t leaf_step(const TreeView& tv, int32_t node, const RayT& R, Best& best,
+                                             LaneStack<BLOCK, STACK>& st, int tid, unsigned long long& c_tri) {
+    const Leaf L = tv.leaves[~node];
+    tri_test(R, L, tv.max_dist, tv.inv_w, tv.w, &best);
+    if (COUNT) c_tri += 1;
+    return st.pop(tid);
+}
+
+// One step of either kind.
 template <int BLOCK, int STACK, bool COUNT>
 __device__ __forceinline__ int32_t trav_step(const TreeView& tv, uint32_t* status, int32_t node,
                                              const RayT& R, Best& best, LaneStack<BLOCK, STACK>& st,
                                              int tid, unsigned long long& c_box, unsigned long long& c_tri) {
-    if (node >= 0) {
-        const BvhNode* nd = tv.nodes + node;
-        float4 na = nd->a, nb = nd->b, nc = nd->c;
-        int4 ref = nd->ref;
-        float mL, mR;
-        bool hL = box_test(R, f3(na.x, na.y, na.z), f3(na.w, nb.x, nb.y), best.bound, &mL);
-        bool hR = box_test(R, f3(nb.z, nb.w, nc.x), f3(nc.y, nc.z, nc.w), best.bound, &mR);
-        if (COUNT) c_box += 2;
-        int32_t next = kEmpty;
-        if (hL && hR) {
-            bool rfirst = mR < mL;
-            next = rfirst ? ref.y : ref.x;
-            st.push(rfirst ? ref.x : ref.y, tid, status);
-        } else if (hL) {
-            next = ref.x;
-        } else if (hR) {
-            next = ref.y;
-        }
-        node = next;
-    } else {
-        const Leaf L = tv.leaves[~node];
-        tri_test(R, L, tv.max_dist, tv.inv_w, tv.w, &best);
-        if (COUNT) c_tri += 1;
-        node = kEmpty;
-    }
-    if (node == kEmpty) node = st.pop(tid);
-    return node;
+    if (node >= 0) return inner_step<BLOCK, STACK, COUNT>(tv, status, node, R, best, st, tid, c_box);
+    return leaf_step<BLOCK, STACK, COUNT>(tv, node, R, best, st, tid, c_tri);
 }
 
 __device__ __forceinline__ void reset_best(Best& b, float max_dist) {
@@ -377,8 +388,12 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 }
 
 // Wave batches: each wave takes one (asset, 64-ray batch) item at a time,
-// traces its rays together and encodes once all 64 are done.
-template <int BLOCK, int STACK, bool COUNT>
+// traces its rays together and encodes once all 64 are done.  PHASED: the
+// lanes first advance through internal nodes until each has reached a leaf
+// or finished, then all lanes at a leaf test their triangle together (after
+// Aila & Laine's while-while loop), so the wave does not pay for the
+// triangle test on every step in which any one lane is at a leaf.
+template <int BLOCK, int STACK, bool COUNT, bool PHASED>
 __global__ __launch_bounds__(BLOCK) void traverse_batch_kernel(TravArgs a) {
     __shared__ int32_t stk[STACK][BLOCK];
     const int tid = threadIdx.x;
@@ -417,12 +432,33 @@ __global__ __launch_bounds__(BLOCK) void traverse_batch_kernel(TravArgs a) {
         st.sp = st.lo = 0;
         int32_t steps = 0;
         unsigned long long c_box = 0, c_tri = 0;
-        while (__ballot(node != kEmpty)) {
-            if (node != kEmpty) {
-                node = trav_step<BLOCK, STACK, COUNT>(tv, B.status, node, R, best, st, tid, c_box, c_tri);
-                if (++steps > tv.step_cap) {
-                    set_status(B, kStInternal);
-                    node = kEmpty;
+        if (PHASED) {
+            while (__ballot(node != kEmpty)) {
+                while (__ballot(node >= 0)) {
+                    if (node >= 0) {
+                        node = inner_step<BLOCK, STACK, COUNT>(tv, B.status, node, R, best, st, tid, c_box);
+                        if (++steps > tv.step_cap) {
+                            set_status(B, kStInternal);
+                            node = kEmpty;
+                        }
+                    }
+                }
+                if (node != kEmpty) {
+                    node = leaf_step<BLOCK, STACK, COUNT>(tv, node, R, best, st, tid, c_tri);
+                    if (++steps > tv.step_cap) {
+                        set_status(B, kStInternal);
+                        node = kEmpty;
+                    }
+                }
+            }
+        } else {
+            while (__ballot(node != kEmpty)) {
+                if (node != kEmpty) {
+                    node = trav_step<BLOCK, STACK, COUNT>(tv, B.status, node, R, best, st, tid, c_box, c_tri);
+                    if (++steps > tv.step_cap) {
+                        set_status(B, kStInternal);
+                        node = kEmpty;
+                    }
                 }
             }
         }
@@ -518,10 +554,11 @@ __global__ __launch_bounds__(BLOCK) void traverse_refill_kernel(TravArgs a) {
     }
 }
 
-template <int BLOCK, int STACK, bool COUNT, bool REFILL>
+template <int BLOCK, int STACK, bool COUNT, int MODE>
 hipError_t launch_one(const TravArgs& args, hipStream_t s, int64_t max_lanes) {
     static int cached_blocks = -1;
-    auto kern = REFILL ? traverse_refill_kernel<BLOCK, STACK, COUNT> : traverse_batch_kernel<BLOCK, STACK, COUNT>;
+    auto kern = MODE == 1 ? traverse_refill_kernel<BLOCK, STACK, COUNT>
+                          : traverse_batch_kernel<BLOCK, STACK, COUNT, MODE == 2>;
     if (cached_blocks < 0) {
         int dev = 0, cus = 0, per = 0;
         hipError_t e = hipGetDevice(&dev);
@@ -539,6 +576,16 @@ hipError_t launch_one(const TravArgs& args, hipStream_t s, int64_t max_lanes) {
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(BLOCK), 0, s, args);
     return hipGetLastError();
+}
+
+template <int BLOCK, int STACK, bool COUNT>
+hipError_t launch_mode(const TravArgs& args, int mode, hipStream_t s, int64_t max_lanes) {
+    switch (mode) {
+        case 0: return launch_one<BLOCK, STACK, COUNT, 0>(args, s, max_lanes);
+        case 1: return launch_one<BLOCK, STACK, COUNT, 1>(args, s, max_lanes);
+        case 2: return launch_one<BLOCK, STACK, COUNT, 2>(args, s, max_lanes);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -561,14 +608,9 @@ hipError_t launch_traverse(const BatchHost& H, const TravConfig& cfg, hipStream_
     a.spill = (int32_t*)(ws + L.spill);
     a.spill_lanes = L.spill_lanes;
     int64_t lanes = L.spill_lanes;
-    if (cfg.count) {
-        return cfg.persist ? launch_one<256, 16, true, true>(a, s, lanes)
-                           : launch_one<256, 16, true, false>(a, s, lanes);
-    }
-#define BAKE_TRAV_CASE(B, S)                                                         \
-    if (cfg.block == B && cfg.stack == S)                                            \
-        return cfg.persist ? launch_one<B, S, false, true>(a, s, lanes)              \
-                           : launch_one<B, S, false, false>(a, s, lanes);
+    if (cfg.count) return launch_mode<256, 16, true>(a, cfg.mode, s, lanes);
+#define BAKE_TRAV_CASE(B, S) \
+    if (cfg.block == B && cfg.stack == S) return launch_mode<B, S, false>(a, cfg.mode, s, lanes);
     BAKE_TRAV_CASE(64, 8) BAKE_TRAV_CASE(64, 16) BAKE_TRAV_CASE(64, 32)
     BAKE_TRAV_CASE(128, 8) BAKE_TRAV_CASE(128, 16) BAKE_TRAV_CASE(128, 32)
     BAKE_TRAV_CASE(256, 8) BAKE_TRAV_CASE(256, 16) BAKE_TRAV_CASE(256, 32)

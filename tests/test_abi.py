@@ -39,7 +39,7 @@ def test_every_declared_symbol_is_exported(B):
 def test_version_and_defaults(B):
     assert "gfx950" in B.version()
     o = B.make_options()
-    assert o.dilate_passes == 2 and o.flags == 0 and o.trav_persist == -1
+    assert o.dilate_passes == 2 and o.flags == 0 and o.trav_mode == -1
 
 
 def test_workspace_size_grows_with_inputs(B):
@@ -92,7 +92,7 @@ def test_host_validation_codes(B, over, code):
 
 
 @pytest.mark.parametrize("field,val", [("dilate_passes", -1), ("dilate_passes", 65), ("flags", 64),
-                                       ("trav_block", 96), ("trav_stack", 12), ("trav_persist", 2)])
+                                       ("trav_block", 96), ("trav_stack", 12), ("trav_mode", 3)])
 def test_bad_options(B, field, val):
     o = B.make_options()
     setattr(o, field, val)

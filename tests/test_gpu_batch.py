@@ -100,9 +100,11 @@ def test_batch_forward_equals_single_bakes(B):
     torch.cuda.synchronize()
     assert batch.status() == 0
     _check_batch_equals_single(B, batch, assets, singles)
-    # texels were really traced: most covered texels of the generated assets hit
-    h = batch.hits[0].cpu().numpy()
-    assert (h >= 0).sum() > 0.9 * (h != B.BAKE_UNCOVERED).sum()
+    # texels were really traced (generated assets are randomly decimated, so
+    # their high-poly has holes and a good part of the rays miss)
+    for i in (0, 1, 3):
+        h = batch.hits[i].cpu().numpy()
+        assert (h >= 0).sum() > 0.3 * (h != B.BAKE_UNCOVERED).sum(), i
 
 
 def test_batch_backward_equals_single(B):
@@ -174,16 +176,16 @@ def test_autotune_every_config_same_result(B, tmp_path):
     ref = [(_bits(m), h.cpu().numpy()) for m, h in zip(batch.maps, batch.hits)]
     cache = str(tmp_path / "tune.json")
     out = B.autotune(batch, reps=1, cache_path=cache)
-    say("[gpu] autotune", out["block"], out["stack"], out["persist"])
-    assert (out["block"], out["stack"], out["persist"]) in B.TRAV_CONFIGS
-    assert len(out["ms"]) == 18 and all(v > 0 for v in out["ms"].values())
-    # the last configuration tried is block 256 / stack 32 / refill
+    say("[gpu] autotune", out["block"], out["stack"], out["mode"])
+    assert (out["block"], out["stack"], out["mode"]) in B.TRAV_CONFIGS
+    assert len(out["ms"]) == 27 and all(v > 0 for v in out["ms"].values())
+    # every configuration gives the same results (the last one tried stays)
     for i, (m, h) in enumerate(zip(batch.maps, batch.hits)):
         assert np.array_equal(_bits(m), ref[i][0]) and np.array_equal(h.cpu().numpy(), ref[i][1])
     b2 = B.BakeBatch([_inputs(B, a) for a in assets])
     assert B.apply_tuning(b2, cache)
-    assert (b2.opts.trav_block, b2.opts.trav_stack, b2.opts.trav_persist) == \
-        (out["block"], out["stack"], out["persist"])
+    assert (b2.opts.trav_block, b2.opts.trav_stack, b2.opts.trav_mode) == \
+        (out["block"], out["stack"], out["mode"])
 
 
 def test_batch_errors(B):
@@ -233,7 +235,7 @@ def test_batched_asset_sample_against_oracle(B, oracle_lib):
         face, _ = oracle_lib.raster(a.lo_UV, a.res)
         cov = np.nonzero(face >= 0)[0]
         rng = np.random.default_rng(100 + i)
-        sample = np.sort(rng.choice(cov, size=min(400, cov.size), replace=False))
+        sample = np.sort(rng.choice(cov, size=min(2000, cov.size), replace=False))
         ob = oracle_lib.bake(a, method="brute", texels=sample, dilate_passes=0)
         rep = compare(oracle_lib, a, ob, batch.maps[i].cpu().numpy(), batch.hits[i].cpu().numpy(),
                       check_dilation=False)

@@ -194,8 +194,8 @@ def test_traversal_configs_bitwise_identical(B):
     rm, rh = np_out(ref)
     for blk in (64, 128, 256):
         for stk in (8, 16, 32):
-            for per in (0, 1):
-                r = run(B, a, trav_block=blk, trav_stack=stk, trav_persist=per)
+            for per in (0, 1, 2):
+                r = run(B, a, trav_block=blk, trav_stack=stk, trav_mode=per)
                 m, h = np_out(r)
                 assert np.array_equal(h, rh), (blk, stk, per)
                 assert np.array_equal(m.view(np.uint32), rm.view(np.uint32)), (blk, stk, per)
