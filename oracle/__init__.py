@@ -137,6 +137,29 @@ def query(hi_V, hi_F, P, D, max_dist, active=None, method="brute"):
     return ids, t, beta
 
 
+def closest(hi_V, hi_F, P, max_dist, active=None, method="brute"):
+    """Closest point of the high-poly within max_dist: (id [-1 miss], distance,
+    barycentric weights [3] of the closest point)."""
+    hi_V = _c(hi_V, np.float32); hi_F = _c(hi_F, np.int32)
+    P = _c(P, np.float64)
+    n = P.shape[0]
+    ids = np.zeros(n, np.int32); dist = np.zeros(n); w = np.zeros((n, 3))
+    act = None if active is None else _c(active, np.uint8)
+    fn = {"brute": "orc_closest_brute", "bvh": "orc_closest_bvh"}[method]
+    _call(fn, _p(hi_V), _p(hi_F), C.c_int64(hi_F.shape[0]), C.c_int64(n), _p(P), _p(act),
+          C.c_double(max_dist), _p(ids), _p(dist), _p(w))
+    return ids, dist, w
+
+
+def closest_check(hi_V, hi_F, P, g):
+    """Distance from each P[r] to triangle g[r]."""
+    hi_V = _c(hi_V, np.float32); hi_F = _c(hi_F, np.int32)
+    P = _c(P, np.float64); g = _c(g, np.int32)
+    dist = np.zeros(g.shape[0])
+    _call("orc_closest_check", _p(hi_V), _p(hi_F), C.c_int64(g.shape[0]), _p(P), _p(g), _p(dist))
+    return dist
+
+
 def frame_ok(lo_face, D, Tf):
     lo_face = _c(lo_face, np.int32); D = _c(D, np.float64); Tf = _c(Tf, np.float64)
     ok = np.zeros(lo_face.shape[0], np.uint8)
@@ -199,10 +222,14 @@ class Bake:
     level: np.ndarray       # [res*res] dilation level (0 covered, k filled in pass k, 255 empty)
 
 
-def bake(asset, method="brute", texels=None, dilate_passes=2) -> Bake:
-    """Oracle bake of a whole asset (or of a subset of covered texels)."""
+def bake(asset, method="brute", texels=None, dilate_passes=2, kind="ray", max_dist=None) -> Bake:
+    """Oracle bake of a whole asset (or of a subset of covered texels).
+    kind="ray": two-sided line query along the interpolated normal;
+    kind="closest": closest point of the high-poly (the paper's form), for
+    which Bake.t holds the distance.  max_dist defaults to the asset's."""
     hi_V, hi_F, hi_N, lo_V, lo_F, lo_UV = asset.arrays()
-    res, md = int(asset.res), float(asset.max_dist)
+    res = int(asset.res)
+    md = float(asset.max_dist if max_dist is None else max_dist)
     vn, vn_ok = lo_normals(lo_V, lo_F)
     Tf, _, hf, rel = face_frames(lo_V, lo_F, lo_UV, res, vn_ok)
     face, bary = raster(lo_UV, res)
@@ -215,7 +242,12 @@ def bake(asset, method="brute", texels=None, dilate_passes=2) -> Bake:
     P, D, mok = rays(lo_V, lo_F, vn, lf, bary[tex])
     fok = frame_ok(lf, D, Tf)
     active = rel[lf] & mok & fok
-    ids, t, beta = query(hi_V, hi_F, P, D, md, active=active, method=method)
+    if kind == "ray":
+        ids, t, beta = query(hi_V, hi_F, P, D, md, active=active, method=method)
+    elif kind == "closest":
+        ids, t, beta = closest(hi_V, hi_F, P, md, active=active, method=method)
+    else:
+        raise ValueError(kind)
     st = np.where(active, ids, ST_UNREL).astype(np.int32)
     out, st = encode(hi_F, hi_N, lf, D, Tf, hf, beta, st)
     ntex = res * res

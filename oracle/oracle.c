@@ -14,8 +14,8 @@
  * neutral normal (0,0,1); project the hit normal into the texel's tangent frame;
  * dilate at chart borders.  The correspondence query is a two-sided ray cast
  * along the interpolated low-poly normal, nearest |t| within +-max_dist, ties to
- * the lower triangle index (the paper's closest-point query is a different
- * variant of the same step).
+ * the lower triangle index; the paper's own form, the closest point of the
+ * high-poly surface within a distance bound, is the second query below.
  *
  * Everything is plain: brute force over every texel and every triangle,
  * FP64 arithmetic, no blocking or reordering beyond what the definitions say.
