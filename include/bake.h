@@ -67,6 +67,16 @@ extern "C" {
 #define BAKE_STATUS_STATE 32u    /* a backward found the workspace no longer holding the saved
                                     forward's state (reused since): it wrote nothing */
 
+/* ---- correspondence query (bake_options.query) ------------------------ */
+#define BAKE_QUERY_RAY 0     /* two-sided ray along the interpolated low-poly normal: the
+                                hit with the smallest |t| in [-max_dist, +max_dist]       */
+#define BAKE_QUERY_CLOSEST 1 /* the paper's own form (Sec. 6.4): the closest point of the
+                                high-poly surface within max_dist (the paper's bound is 1%
+                                of the bounding-box diagonal); ties within one distance
+                                quantum max_dist*2^-20 go to the lower triangle index.
+                                Forward only: BAKE_FLAG_SAVE is rejected (BAKE_E_UNSUPPORTED);
+                                trav_mode 1 runs as 2.                                     */
+
 /* ---- flags ------------------------------------------------------------ */
 #define BAKE_FLAG_SAVE 1u   /* keep the per-ray state that bake_normals_backward needs */
 #define BAKE_FLAG_TIMING 2u /* record per-stage HIP events (bake_stage_times) */
@@ -83,7 +93,8 @@ typedef struct bake_options {
                               nodes and leaves; 1 = finished lanes refilled from a ray
                               queue; 2 = whole 64-ray batches, internal nodes and
                               leaves in separate phases; -1 = default (2)                 */
-    int32_t reserved[4];
+    int32_t query;         /* BAKE_QUERY_RAY (default) or BAKE_QUERY_CLOSEST                 */
+    int32_t reserved[3];
 } bake_options;
 
 /* Default options: dilate_passes = 2, no flags, no RGB8, tuned traversal. */

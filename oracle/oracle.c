@@ -597,8 +597,11 @@ static int32_t bvh_closest(const bvh *B, const float *V, const int32_t *F, v3 p,
             continue;
         }
         if (sp + 2 > 256) return -100;
-        stack[sp++] = nd->left;
-        stack[sp++] = nd->right;
+        /* the nearer child is popped first, so the bound tightens early */
+        int64_t near = nd->left, far = nd->right;
+        if (box_dist(&B->nodes[far], p) < box_dist(&B->nodes[near], p)) { near = nd->right; far = nd->left; }
+        stack[sp++] = far;
+        stack[sp++] = near;
     }
     *d_out = bd;
     w_out[0] = bw[0]; w_out[1] = bw[1]; w_out[2] = bw[2];

@@ -35,6 +35,10 @@ BAKE_STATUS_NONFINITE = 8
 BAKE_STATUS_INTERNAL = 16
 BAKE_STATUS_STATE = 32
 
+BAKE_QUERY_RAY = 0
+BAKE_QUERY_CLOSEST = 1
+QUERIES = {"ray": BAKE_QUERY_RAY, "closest": BAKE_QUERY_CLOSEST}
+
 BAKE_FLAG_SAVE = 1
 BAKE_FLAG_TIMING = 2
 BAKE_FLAG_COUNT = 4
@@ -58,7 +62,8 @@ class BakeOptions(C.Structure):
         ("trav_block", C.c_int32),
         ("trav_stack", C.c_int32),
         ("trav_mode", C.c_int32),
-        ("reserved", C.c_int32 * 4),
+        ("query", C.c_int32),
+        ("reserved", C.c_int32 * 3),
     ]
 
 
@@ -137,7 +142,7 @@ def _check(rc: int):
 
 
 def make_options(dilate_passes=2, save=False, timing=False, rgb8_ptr=0, trav_block=0,
-                 trav_stack=0, trav_mode=-1, count=False) -> BakeOptions:
+                 trav_stack=0, trav_mode=-1, count=False, query="ray") -> BakeOptions:
     o = BakeOptions()
     lib().bake_default_options(C.byref(o))
     o.dilate_passes = int(dilate_passes)
@@ -147,6 +152,7 @@ def make_options(dilate_passes=2, save=False, timing=False, rgb8_ptr=0, trav_blo
     o.trav_block = int(trav_block)
     o.trav_stack = int(trav_stack)
     o.trav_mode = int(trav_mode)
+    o.query = QUERIES[query]
     return o
 
 
@@ -225,13 +231,15 @@ class BakeResult:
 def bake_normals(hi_V, hi_F, hi_N, lo_V, lo_F, lo_UV, res: int, max_dist: float, *,
                  dilate_passes: int = 2, rgb8: bool = False, save: bool = False,
                  timing: bool = False, trav_block: int = 0, trav_stack: int = 0,
-                 trav_mode: int = -1, count: bool = False,
+                 trav_mode: int = -1, count: bool = False, query: str = "ray",
                  workspace: Optional[torch.Tensor] = None,
                  out_map: Optional[torch.Tensor] = None, out_hit: Optional[torch.Tensor] = None,
                  stream=None) -> BakeResult:
     """Bake a tangent-space normal map of the high-poly onto the low-poly's UV
     atlas.  Inputs are GPU tensors: hi_V [Vh,3] f32, hi_F [Fh,3] i32, hi_N [Vh,3]
-    f32, lo_V [Vl,3] f32, lo_F [Fl,3] i32, lo_UV [Fl,3,2] f32."""
+    f32, lo_V [Vl,3] f32, lo_F [Fl,3] i32, lo_UV [Fl,3,2] f32.  query: "ray"
+    (two-sided ray along the interpolated normal) or "closest" (closest point
+    of the high-poly within max_dist, forward only)."""
     hi_V = _dev_tensor(hi_V, torch.float32, "hi_V", (3,))
     hi_F = _dev_tensor(hi_F, torch.int32, "hi_F", (3,))
     hi_N = _dev_tensor(hi_N, torch.float32, "hi_N", (3,))
@@ -246,7 +254,7 @@ def bake_normals(hi_V, hi_F, hi_N, lo_V, lo_F, lo_UV, res: int, max_dist: float,
     sizes = (hi_V.shape[0], hi_F.shape[0], lo_V.shape[0], lo_F.shape[0], int(res))
     rgb = torch.empty((res, res, 3), dtype=torch.uint8, device=dev) if rgb8 else None
     opts = make_options(dilate_passes, save, timing, rgb.data_ptr() if rgb is not None else 0,
-                        trav_block, trav_stack, trav_mode, count)
+                        trav_block, trav_stack, trav_mode, count, query)
     nbytes = workspace_size(*sizes, opts)
     if workspace is None or workspace.numel() < nbytes:
         workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
@@ -343,7 +351,7 @@ class BakeBatch:
     Every asset's results are bitwise those of a single bake_normals call."""
 
     def __init__(self, assets, *, save=False, dilate_passes=2, rgb8=False, trav_block=0,
-                 trav_stack=0, trav_mode=-1, need_lo=True, need_hi=True):
+                 trav_stack=0, trav_mode=-1, need_lo=True, need_hi=True, query="ray"):
         if not assets:
             raise ValueError("empty batch")
         self.inputs = []
@@ -391,7 +399,8 @@ class BakeBatch:
             e.grad_lo_V = glo.data_ptr() if glo is not None else None
             e.grad_hi_N = ghi.data_ptr() if ghi is not None else None
         self.device = self.inputs[0][0].device
-        self.opts = make_options(dilate_passes, save, False, 0, trav_block, trav_stack, trav_mode)
+        self.opts = make_options(dilate_passes, save, False, 0, trav_block, trav_stack, trav_mode,
+                                 query=query)
         b = C.c_size_t(0)
         _check(lib().bake_batch_workspace_size(self._arr, self.n, C.byref(self.opts), C.byref(b)))
         self.workspace = torch.empty(b.value, dtype=torch.uint8, device=self.device)

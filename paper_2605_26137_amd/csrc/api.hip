@@ -82,6 +82,11 @@ int32_t parse_opts(const bake_options* o, Opts* out) {
     if (o->trav_mode < -1 || o->trav_mode > 2)
         return fail(BAKE_E_INVALID_ARG, "trav_mode %d not in {-1,0,1,2}", o->trav_mode);
     if (o->trav_mode >= 0) out->trav.mode = o->trav_mode;
+    if (o->query != BAKE_QUERY_RAY && o->query != BAKE_QUERY_CLOSEST)
+        return fail(BAKE_E_INVALID_ARG, "query %d unknown", o->query);
+    out->trav.closest = o->query == BAKE_QUERY_CLOSEST;
+    if (out->trav.closest && (o->flags & BAKE_FLAG_SAVE))
+        return fail(BAKE_E_UNSUPPORTED, "the closest-point query has no backward (BAKE_FLAG_SAVE)");
     return BAKE_OK;
 }
 

@@ -371,17 +371,23 @@ __global__ __launch_bounds__(256) void bwd_hiN_kernel(Batch B, const uint32_t* _
 }
 
 // Squared-error loss helper: grad = 2 (map - target), per-block partial sums
-// of (map - target)^2, then a single block adds the partials in order.
+// of (map - target)^2 over kLossTile values (each thread its values in a fixed
+// order), then a single block adds the partials in order.
+constexpr int kLossItems = 16;
+constexpr int kLossTile = 256 * kLossItems;
 __global__ __launch_bounds__(256) void sq_loss_kernel(const float* __restrict__ map,
                                                       const float* __restrict__ target, int64_t n,
                                                       float* __restrict__ grad, float* __restrict__ partial) {
     __shared__ float red[4];
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     float e = 0.f;
-    if (i < n) {
-        const float d = map[i] - target[i];
-        if (grad) grad[i] = 2.0f * d;
-        e = d * d;
+#pragma unroll 4
+    for (int k = 0; k < kLossItems; ++k) {
+        const int64_t i = (int64_t)blockIdx.x * kLossTile + (int64_t)k * 256 + threadIdx.x;
+        if (i < n) {
+            const float d = map[i] - target[i];
+            if (grad) grad[i] = 2.0f * d;
+            e += d * d;
+        }
     }
     e = wave_sum(e);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
@@ -389,15 +395,19 @@ __global__ __launch_bounds__(256) void sq_loss_kernel(const float* __restrict__ 
     if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-__global__ __launch_bounds__(256) void sum_partials_kernel(const float* __restrict__ partial, int64_t m,
-                                                           float* __restrict__ out) {
-    __shared__ float red[4];
+__global__ __launch_bounds__(1024) void sum_partials_kernel(const float* __restrict__ partial, int64_t m,
+                                                            float* __restrict__ out) {
+    __shared__ float red[16];
     float acc = 0.f;
-    for (int64_t i = threadIdx.x; i < m; i += 256) acc += partial[i];
+    for (int64_t i = threadIdx.x; i < m; i += 1024) acc += partial[i];
     acc = wave_sum(acc);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) *out = (red[0] + red[1]) + (red[2] + red[3]);
+    if (threadIdx.x == 0) {
+        float s = 0.f;
+        for (int w = 0; w < 16; ++w) s += red[w];
+        *out = s;
+    }
 }
 
 inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -462,9 +472,9 @@ hipError_t launch_backward(const BatchHost& H, bool any_lo, bool any_hi, hipStre
 hipError_t launch_sq_loss(const float* map, const float* target, int64_t n3, float* grad, float* loss,
                           float* partial, hipStream_t s) {
     if (n3 <= 0) return fill_u32((uint32_t*)loss, 0u, 1, s);
-    const unsigned nb = blocks_for(n3, 256);
+    const unsigned nb = blocks_for(n3, kLossTile);
     hipLaunchKernelGGL(sq_loss_kernel, dim3(nb), dim3(256), 0, s, map, target, n3, grad, partial);
-    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, (const float*)partial, (int64_t)nb, loss);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(1024), 0, s, (const float*)partial, (int64_t)nb, loss);
     return hipGetLastError();
 }
 

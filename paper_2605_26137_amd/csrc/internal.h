@@ -229,7 +229,8 @@ struct TravConfig {
     int stack;    // LDS entries per lane: 8 / 16 / 32
     int mode;     // 0: 64-ray batches, one loop; 1: lane refill from a ray queue;
                   // 2: 64-ray batches, internal-node and leaf phases
-    bool count = false;  // instrumented variant: count box and triangle tests
+    bool count = false;    // instrumented variant: count box and triangle tests
+    bool closest = false;  // closest-point query instead of the ray query
 };
 
 // ---------------------------------------------------------------------------

@@ -32,6 +32,10 @@
 //     two faces; two-sided;
 //   * short per-lane stack in LDS, spilling its oldest entries to a per-lane
 //     global area when full (the Karras tree depth is bounded by 62).
+// The closest-point query (the paper's own form) shares the traversal: boxes
+// are pruned by their distance from the texel position, triangles report the
+// distance of their nearest point, and the same (distance bin, index) rule
+// picks the winner.
 #include <algorithm>
 
 #include "internal.h"
@@ -166,6 +170,102 @@ __device__ __forceinline__ void tri_test(const RayT& r, const Leaf& L, float max
         b->t = t;
         b->b1 = V * rdet;
         b->b2 = W * rdet;
+        b->bound = (float)(key + 1u) * w * (1.0f + kPad);
+    }
+}
+
+// Point-to-box distance test: true when the box may hold a point within
+// `bound` of p; *d2 = the squared distance (0 inside).  The FP32 rounding of
+// d2 is a few 2^-24 relative, well inside the bound's 1e-6 pad.
+__device__ __forceinline__ bool box_dist_test(float3 p, float3 lo, float3 hi, float bound, float* d2) {
+    const float dx = fmaxf(fmaxf(lo.x - p.x, p.x - hi.x), 0.f);
+    const float dy = fmaxf(fmaxf(lo.y - p.y, p.y - hi.y), 0.f);
+    const float dz = fmaxf(fmaxf(lo.z - p.z, p.z - hi.z), 0.f);
+    *d2 = dx * dx + dy * dy + dz * dz;
+    return *d2 <= bound * bound;
+}
+
+__device__ __forceinline__ bool coord_less(float3 a, float3 b) {
+    return a.x < b.x || (a.x == b.x && (a.y < b.y || (a.y == b.y && a.z < b.z)));
+}
+
+// Nearest point of a leaf triangle to p: the orthogonal projection when its
+// barycentric weights are all >= 0, else the nearest of the edges' nearest
+// points.  On a better (distance bin, index) updates the best, with t = the
+// distance and (b1, b2) = the weights of corners 1 and 2.
+__device__ __forceinline__ void tri_closest_test(float3 p, const Leaf& L, float max_dist, float inv_w,
+                                                 float w, Best* b) {
+    const float3 v[3] = {f3(L.a.x, L.a.y, L.a.z), f3(L.a.w, L.b.x, L.b.y), f3(L.b.z, L.b.w, L.c.x)};
+    const int32_t id = __float_as_int(L.c.y);
+    const float3 e1 = f3(v[1].x - v[0].x, v[1].y - v[0].y, v[1].z - v[0].z);
+    const float3 e2 = f3(v[2].x - v[0].x, v[2].y - v[0].y, v[2].z - v[0].z);
+    const float3 n = cross3(e1, e2);
+    const float nn = dot3(n, n);
+    float dist = INFINITY, w1 = 0.f, w2 = 0.f;
+    bool inside = false;
+    if (nn > 0.f) {
+        const float3 ap = f3(p.x - v[0].x, p.y - v[0].y, p.z - v[0].z);
+        const float sd = dot3(n, ap);
+        const float k = sd / nn;
+        const float3 q = f3(p.x - k * n.x, p.y - k * n.y, p.z - k * n.z);
+        const float inv = 1.0f / nn;
+        const float3 q0 = f3(v[0].x - q.x, v[0].y - q.y, v[0].z - q.z);
+        const float3 q1 = f3(v[1].x - q.x, v[1].y - q.y, v[1].z - q.z);
+        const float3 q2 = f3(v[2].x - q.x, v[2].y - q.y, v[2].z - q.z);
+        const float wa = dot3(n, cross3(q1, q2)) * inv;
+        const float wb = dot3(n, cross3(q2, q0)) * inv;
+        const float wc = dot3(n, cross3(q0, q1)) * inv;
+        if (wa >= 0.f && wb >= 0.f && wc >= 0.f) {
+            inside = true;
+            dist = fabsf(sd) / sqrtf(nn);
+            w1 = wb;
+            w2 = wc;
+        }
+    }
+    if (!inside) {
+        // an edge's distance is computed from its endpoints in a fixed
+        // (coordinate) order, and an endpoint's as |p - v|, so triangles that
+        // share the edge or vertex get bitwise the same value and a closest
+        // point there resolves to the lower index
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            int i = e, j = e == 2 ? 0 : e + 1;
+            if (coord_less(v[j], v[i])) {
+                const int t = i; i = j; j = t;
+            }
+            const float3 u = v[i];
+            const float3 ab = f3(v[j].x - u.x, v[j].y - u.y, v[j].z - u.z);
+            const float3 up = f3(p.x - u.x, p.y - u.y, p.z - u.z);
+            const float l2 = dot3(ab, ab);
+            float s = l2 > 0.f ? dot3(up, ab) / l2 : 0.f;
+            float de;
+            if (s <= 0.f) {
+                s = 0.f;
+                de = sqrtf(dot3(up, up));
+            } else if (s >= 1.f) {
+                s = 1.f;
+                const float3 vp = f3(p.x - v[j].x, p.y - v[j].y, p.z - v[j].z);
+                de = sqrtf(dot3(vp, vp));
+            } else {
+                const float3 r = f3(up.x - s * ab.x, up.y - s * ab.y, up.z - s * ab.z);
+                de = sqrtf(dot3(r, r));
+            }
+            if (de < dist) {
+                dist = de;
+                // weights of corners 1 and 2 for the point u + s (v_j - u)
+                w1 = (i == 1 ? 1.f - s : 0.f) + (j == 1 ? s : 0.f);
+                w2 = (i == 2 ? 1.f - s : 0.f) + (j == 2 ? s : 0.f);
+            }
+        }
+    }
+    if (!(dist <= max_dist)) return;
+    const uint32_t key = (uint32_t)(dist * inv_w);
+    if (key < b->key || (key == b->key && id < b->id)) {
+        b->key = key;
+        b->id = id;
+        b->t = dist;
+        b->b1 = w1;
+        b->b2 = w2;
         b->bound = (float)(key + 1u) * w * (1.0f + kPad);
     }
 }
@@ -365,6 +465,41 @@ __device__ __forceinline__ int32_t leaf_step(const TreeView& tv, int32_t node, c
     return st.pop(tid);
 }
 
+// The same two steps for the closest-point query (p = the texel position).
+template <int BLOCK, int STACK, bool COUNT>
+__device__ __forceinline__ int32_t inner_step_pt(const TreeView& tv, uint32_t* status, int32_t node,
+                                                 float3 p, const Best& best, LaneStack<BLOCK, STACK>& st,
+                                                 int tid, unsigned long long& c_box) {
+    const BvhNode* nd = tv.nodes + node;
+    float4 na = nd->a, nb = nd->b, nc = nd->c;
+    int4 ref = nd->ref;
+    float dL, dR;
+    bool hL = box_dist_test(p, f3(na.x, na.y, na.z), f3(na.w, nb.x, nb.y), best.bound, &dL);
+    bool hR = box_dist_test(p, f3(nb.z, nb.w, nc.x), f3(nc.y, nc.z, nc.w), best.bound, &dR);
+    if (COUNT) c_box += 2;
+    int32_t next = kEmpty;
+    if (hL && hR) {
+        bool rfirst = dR < dL;
+        next = rfirst ? ref.y : ref.x;
+        st.push(rfirst ? ref.x : ref.y, tid, status);
+    } else if (hL) {
+        next = ref.x;
+    } else if (hR) {
+        next = ref.y;
+    }
+    if (next == kEmpty) next = st.pop(tid);
+    return next;
+}
+
+template <int BLOCK, int STACK, bool COUNT>
+__device__ __forceinline__ int32_t leaf_step_pt(const TreeView& tv, int32_t node, float3 p, Best& best,
+                                                LaneStack<BLOCK, STACK>& st, int tid, unsigned long long& c_tri) {
+    const Leaf L = tv.leaves[~node];
+    tri_closest_test(p, L, tv.max_dist, tv.inv_w, tv.w, &best);
+    if (COUNT) c_tri += 1;
+    return st.pop(tid);
+}
+
 // One step of either kind.
 template <int BLOCK, int STACK, bool COUNT>
 __device__ __forceinline__ int32_t trav_step(const TreeView& tv, uint32_t* status, int32_t node,
@@ -393,7 +528,7 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 // or finished, then all lanes at a leaf test their triangle together (after
 // Aila & Laine's while-while loop), so the wave does not pay for the
 // triangle test on every step in which any one lane is at a leaf.
-template <int BLOCK, int STACK, bool COUNT, bool PHASED>
+template <int BLOCK, int STACK, bool COUNT, bool PHASED, bool CLOSEST>
 __global__ __launch_bounds__(BLOCK) void traverse_batch_kernel(TravArgs a) {
     __shared__ int32_t stk[STACK][BLOCK];
     const int tid = threadIdx.x;
@@ -432,7 +567,28 @@ __global__ __launch_bounds__(BLOCK) void traverse_batch_kernel(TravArgs a) {
         st.sp = st.lo = 0;
         int32_t steps = 0;
         unsigned long long c_box = 0, c_tri = 0;
-        if (PHASED) {
+        if (CLOSEST) {
+            // point query: the phased loop on box distances and nearest points
+            const float3 p = R.p;
+            while (__ballot(node != kEmpty)) {
+                while (__ballot(node >= 0)) {
+                    if (node >= 0) {
+                        node = inner_step_pt<BLOCK, STACK, COUNT>(tv, B.status, node, p, best, st, tid, c_box);
+                        if (++steps > tv.step_cap) {
+                            set_status(B, kStInternal);
+                            node = kEmpty;
+                        }
+                    }
+                }
+                if (node != kEmpty) {
+                    node = leaf_step_pt<BLOCK, STACK, COUNT>(tv, node, p, best, st, tid, c_tri);
+                    if (++steps > tv.step_cap) {
+                        set_status(B, kStInternal);
+                        node = kEmpty;
+                    }
+                }
+            }
+        } else if (PHASED) {
             while (__ballot(node != kEmpty)) {
                 while (__ballot(node >= 0)) {
                     if (node >= 0) {
@@ -554,11 +710,12 @@ __global__ __launch_bounds__(BLOCK) void traverse_refill_kernel(TravArgs a) {
     }
 }
 
+// MODE: 0 / 1 / 2 as TravConfig::mode for the ray query; 3 the closest-point query.
 template <int BLOCK, int STACK, bool COUNT, int MODE>
 hipError_t launch_one(const TravArgs& args, hipStream_t s, int64_t max_lanes) {
     static int cached_blocks = -1;
     auto kern = MODE == 1 ? traverse_refill_kernel<BLOCK, STACK, COUNT>
-                          : traverse_batch_kernel<BLOCK, STACK, COUNT, MODE == 2>;
+                          : traverse_batch_kernel<BLOCK, STACK, COUNT, MODE == 2, MODE == 3>;
     if (cached_blocks < 0) {
         int dev = 0, cus = 0, per = 0;
         hipError_t e = hipGetDevice(&dev);
@@ -579,7 +736,8 @@ hipError_t launch_one(const TravArgs& args, hipStream_t s, int64_t max_lanes) {
 }
 
 template <int BLOCK, int STACK, bool COUNT>
-hipError_t launch_mode(const TravArgs& args, int mode, hipStream_t s, int64_t max_lanes) {
+hipError_t launch_mode(const TravArgs& args, int mode, bool closest, hipStream_t s, int64_t max_lanes) {
+    if (closest) return launch_one<BLOCK, STACK, COUNT, 3>(args, s, max_lanes);
     switch (mode) {
         case 0: return launch_one<BLOCK, STACK, COUNT, 0>(args, s, max_lanes);
         case 1: return launch_one<BLOCK, STACK, COUNT, 1>(args, s, max_lanes);
@@ -608,9 +766,9 @@ hipError_t launch_traverse(const BatchHost& H, const TravConfig& cfg, hipStream_
     a.spill = (int32_t*)(ws + L.spill);
     a.spill_lanes = L.spill_lanes;
     int64_t lanes = L.spill_lanes;
-    if (cfg.count) return launch_mode<256, 16, true>(a, cfg.mode, s, lanes);
+    if (cfg.count) return launch_mode<256, 16, true>(a, cfg.mode, cfg.closest, s, lanes);
 #define BAKE_TRAV_CASE(B, S) \
-    if (cfg.block == B && cfg.stack == S) return launch_mode<B, S, false>(a, cfg.mode, s, lanes);
+    if (cfg.block == B && cfg.stack == S) return launch_mode<B, S, false>(a, cfg.mode, cfg.closest, s, lanes);
     BAKE_TRAV_CASE(64, 8) BAKE_TRAV_CASE(64, 16) BAKE_TRAV_CASE(64, 32)
     BAKE_TRAV_CASE(128, 8) BAKE_TRAV_CASE(128, 16) BAKE_TRAV_CASE(128, 32)
     BAKE_TRAV_CASE(256, 8) BAKE_TRAV_CASE(256, 16) BAKE_TRAV_CASE(256, 32)

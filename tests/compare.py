@@ -153,3 +153,94 @@ def compare(oracle, asset, ob, gpu_map: np.ndarray, gpu_hit: np.ndarray, check_d
             if rep.max_dilated_angle > ANGLE_TOL_DEG:
                 rep.failures.append(f"dilated max angle {rep.max_dilated_angle:.4f} deg")
     return rep
+
+
+# ---------------------------------------------------------------------------
+# closest-point query
+# ---------------------------------------------------------------------------
+#
+# The closest point of the high-poly is an argmin over triangles decided in
+# FP32 on the GPU and in FP64 in the oracle.  Exact ties (a nearest point on a
+# shared edge or vertex) resolve to the lower index on both sides; near ties
+# (two triangles whose distances differ by less than the FP32 noise of a
+# distance, about 1e-7 for O(1) coordinates) may resolve either way, and both
+# answers are correct.  So for this query the comparator checks that every id
+# disagreement is such a tie (the GPU's triangle, measured in FP64, is within
+# two quanta plus NOISE_ABS of the oracle's minimum, or both sit at the range
+# end), and compares the baked normals (0.05 degrees) where the ids agree.  A
+# near tie is not always between neighbouring triangles: a texel close to the
+# medial axis of the surface is equally far from two distinct surface points,
+# whose normals differ.
+
+NOISE_ABS = 1e-6  # FP32 distance noise allowance, absolute (coordinates are O(1))
+
+
+def compare_closest(oracle, asset, ob, gpu_map, gpu_hit, check_dilation=True) -> Report:
+    rep = Report()
+    res, md = ob.res, ob.max_dist
+    gm = np.asarray(gpu_map, np.float64).reshape(-1, 3)
+    gh = np.asarray(gpu_hit).reshape(-1).astype(np.int64)
+    cov = ob.face >= 0
+    rep.n_covered = int(cov.sum())
+    if not np.array_equal(gh == -3, ~cov):
+        rep.failures.append("coverage differs")
+        return rep
+    tex = ob.texels
+    oh = ob.hit.astype(np.int64)
+    ost = ob.status[tex].astype(np.int64)
+    g = gh[tex]
+    if not np.array_equal(g == -2, ost == -2):
+        rep.failures.append(f"unreliable status differs at {int(((g == -2) != (ost == -2)).sum())} texels")
+    rel = ost != -2
+    rep.n_compared = int(rel.sum())
+    if rep.n_compared == 0:
+        return rep
+    same = rel & (g == ost)
+    dis = rel & ~same
+    rep.n_disagree = int(dis.sum())
+    rep.agree = float(same.sum()) / rep.n_compared
+    w = md * 2.0 ** -20
+    if rep.n_disagree:
+        idx = np.nonzero(dis)[0]
+        tau = np.where(oh[idx] >= 0, ob.t[idx], np.inf)
+        gg = g[idx]
+        ok = np.zeros(idx.size, bool)
+        has_g = gg >= 0
+        # GPU miss: the oracle's point sits at the range end
+        ok[~has_g] = (gg[~has_g] == -1) & (tau[~has_g] >= md - NOISE_ABS)
+        if has_g.any():
+            j = idx[has_g]
+            dg = oracle.closest_check(asset.hi_V, asset.hi_F, ob.P[j], gg[has_g])
+            fin = np.isfinite(tau[has_g])
+            within = dg <= md + NOISE_ABS
+            t_ok = np.where(fin, np.abs(dg - tau[has_g]) <= 2 * w + NOISE_ABS, dg >= md - NOISE_ABS)
+            ok[has_g] = within & t_ok
+        rep.n_ties = int(ok.sum())
+        if not ok.all():
+            bad = idx[~ok][:5]
+            rep.failures.append(f"{int((~ok).sum())} non-tie disagreements, e.g. texels {tex[bad].tolist()} "
+                                f"gpu {g[bad].tolist()} oracle {ost[bad].tolist()}")
+    ang = angle_deg(gm[tex][same], ob.map_raw[tex][same])
+    if ang.size:
+        rep.max_angle = float(ang.max())
+        rep.p999_angle = float(np.quantile(ang, 0.999))
+        rep.mean_angle = float(ang.mean())
+        if rep.max_angle > ANGLE_TOL_DEG:
+            rep.failures.append(f"max angle {rep.max_angle:.4f} deg > {ANGLE_TOL_DEG}")
+    if check_dilation and tex.size == rep.n_covered:
+        unc = np.nonzero(~cov)[0]
+        near = np.zeros(res * res, bool)
+        bad_t = tex[dis]
+        ii, jj = bad_t // res, bad_t % res
+        for di in range(-3, 4):
+            for dj in range(-3, 4):
+                a, b = ii + di, jj + dj
+                m = (a >= 0) & (b >= 0) & (a < res) & (b < res)
+                near[a[m] * res + b[m]] = True
+        unc = unc[~near[unc]]
+        if unc.size:
+            angd = angle_deg(gm[unc], ob.map[unc])
+            rep.max_dilated_angle = float(angd.max())
+            if rep.max_dilated_angle > ANGLE_TOL_DEG:
+                rep.failures.append(f"dilated max angle {rep.max_dilated_angle:.4f} deg")
+    return rep
