@@ -42,10 +42,20 @@ sys.path.insert(0, ROOT)
 #   per ray (setup+encode): position, normal, frame, shear setup, hit
 #                           normal and projection                        = 100
 OPS_BOX, OPS_TRI, OPS_RAY = 20, 54, 100
+# closest-point query: point-to-box distance (3 x (2 sub + 2 max) + 3 mul/fma +
+# compare = 16); nearest point on a triangle through the projection branch
+# (edges 6, normal 9, |n|^2 3, signed distance 6, projection 4, corner
+# offsets 9, three cross products 27, three weights 9, compare 2 = 75)
+OPS_BOX_PT, OPS_TRI_PT = 16, 75
 # MI355X VALU issue rate: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (non-packed FP32)
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
-WORKLOAD = "noise4 icosphere L8 (1,310,720 tris) -> icosphere L5 (20,480 tris), 2048^2 atlas, max_dist 0.12"
+WORKLOADS = {
+    1: "ripple icosphere L4 (5,120 tris) -> icosphere L1 (80 tris), 128^2 atlas, max_dist 0.1",
+    2: "noise4 icosphere L8 (1,310,720 tris) -> icosphere L5 (20,480 tris), 2048^2 atlas, max_dist 0.12",
+    3: "noise6+bumps icosphere L9 (5,242,880 tris) -> icosphere L6 (81,920 tris), 4096^2 atlas, max_dist 0.15",
+}
+WORKLOAD = WORKLOADS[2]
 METRIC = "baked rays/s (1.3M-tri→20k-tri, 2048² atlas); fwd+bwd ms; % HBM/VALU peak"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_traverse_noise4_L8_L5_2048.json")
 
@@ -70,7 +80,7 @@ def measured_traffic(kernel_hash):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(asset, target_s):
+def cpu_baseline(asset, target_s, max_dist, kind):
     """The oracle as it stands (FP64 brute force over every triangle) on a
     seeded sample of the workload's covered texels (forward query: the
     oracle's per-ray adjoint is negligible next to it)."""
@@ -84,14 +94,14 @@ def cpu_baseline(asset, target_s):
     def run(n):
         sample = np.sort(rng.choice(cov, size=n, replace=False))
         t0 = time.perf_counter()
-        oracle.bake(asset, method="brute", texels=sample)
+        oracle.bake(asset, method="brute", texels=sample, kind=kind, max_dist=max_dist)
         return time.perf_counter() - t0
 
     t_small = run(64)
     n = int(max(64, min(cov.size, 64 * target_s / max(t_small, 1e-3))))
     dt = run(n)
     return {"value": n / dt, "unit": "rays/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} seeded covered texels of {cov.size}, FP64 brute force over all "
+            "sample": f"{n} seeded covered texels of {cov.size}, FP64 brute-force {kind} query over all "
                       f"{asset.hi_F.shape[0]} triangles, {dt:.1f} s"}
 
 
@@ -187,6 +197,11 @@ def main():
     ap.add_argument("--trav-block", type=int, default=0)
     ap.add_argument("--trav-stack", type=int, default=0)
     ap.add_argument("--trav-mode", type=int, default=-1)
+    ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3),
+                    help="workload: 2 = the headline 1.3M -> 20k triangle bake (default); 1 = the small "
+                         "ripple bake; 3 = the large 5.2M-triangle bake")
+    ap.add_argument("--query", choices=("ray", "closest"), default="ray",
+                    help="correspondence query (closest: the paper's closest-point form, forward only)")
     ap.add_argument("--batch-assets", type=int, default=0, metavar="N",
                     help="also measure an N-asset batch (64 = the uneven batch workload)")
     ap.add_argument("--batch-steps", type=int, default=5)
@@ -221,14 +236,19 @@ def main():
         print(json.dumps({"copy_bytes": n, "copies": 3}), flush=True)
         return
     log(f"[bench] {B.version()} on {torch.cuda.get_device_name(0)}")
-    asset = make_config(2)
+    asset = make_config(args.config)
     t = B.to_device(asset, dev)
     res, md = asset.res, asset.max_dist
-    trav = dict(trav_block=args.trav_block, trav_stack=args.trav_stack, trav_mode=args.trav_mode)
+    closest = args.query == "closest"
+    if closest:  # the paper's distance filter: 1% of the high-poly bounding-box diagonal
+        V = np.asarray(asset.hi_V, np.float64)
+        md = 0.01 * float(np.linalg.norm(V.max(0) - V.min(0)))
+    trav = dict(trav_block=args.trav_block, trav_stack=args.trav_stack, trav_mode=args.trav_mode,
+                query=args.query)
     # loss target: the map baked (by this library, untimed) from a second noise seed
-    tgt_asset = make_config(2, seed=1)
+    tgt_asset = make_config(args.config, seed=1)
     target = B.bake_normals(*B.to_device(tgt_asset, dev), res, md).map.clone()
-    first = B.bake_normals(*t, res, md, save=True, **trav)
+    first = B.bake_normals(*t, res, md, save=not closest, **trav)
     ws, out_map, out_hit = first.workspace, first.map, first.hit
     loss = torch.empty(1, dtype=torch.float32, device=dev)
     gmap = torch.empty_like(out_map)
@@ -240,12 +260,13 @@ def main():
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
 
     def step(timing, k=None):
-        r = B.bake_normals(*t, res, md, save=True, timing=timing, workspace=ws, out_map=out_map,
+        r = B.bake_normals(*t, res, md, save=not closest, timing=timing, workspace=ws, out_map=out_map,
                            out_hit=out_hit, **trav)
         if k is not None:
             ev[2 * k].record()
-        B.sq_loss(out_map, target, out_loss=loss, out_grad=gmap, scratch=scratch)
-        B.bake_normals_backward(r, t, gmap, out_lo=glo, out_hi=ghi)
+        if not closest:  # the closest-point query is forward only
+            B.sq_loss(out_map, target, out_loss=loss, out_grad=gmap, scratch=scratch)
+            B.bake_normals_backward(r, t, gmap, out_lo=glo, out_hi=ghi)
         if k is not None:
             ev[2 * k + 1].record()
 
@@ -265,13 +286,18 @@ def main():
     log(f"[bench] {args.steps} steps, {ms_per_step:.3f} ms/step, stages {stage_ms}, loss+backward {bwd_ms:.3f} ms")
 
     # algorithmic op count of the traversal: one instrumented bake, untimed
-    cnt = B.bake_normals(*t, res, md, count=True, workspace=ws, out_map=out_map, out_hit=out_hit)
+    cnt = B.bake_normals(*t, res, md, count=True, workspace=ws, out_map=out_map, out_hit=out_hit,
+                         query=args.query)
     n_box, n_tri = cnt.test_counts()
-    ops = n_box * OPS_BOX + n_tri * OPS_TRI + rays * OPS_RAY
+    if closest:
+        ops = n_box * OPS_BOX_PT + n_tri * OPS_TRI_PT + rays * OPS_RAY
+    else:
+        ops = n_box * OPS_BOX + n_tri * OPS_TRI + rays * OPS_RAY
     trav_s = stage_ms["traverse"] / 1e3
     achieved = ops / trav_s / 1e12
     khash = source_hash("traverse.hip", "lbvh.hip", "internal.h")
-    roof = {"kernel": "traverse_batch_kernel (traversal + encode)", "bound": "alu",
+    roof = {"kernel": "traverse_batch_kernel (" + ("closest-point query" if closest else "traversal") + " + encode)",
+            "bound": "alu",
             "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
             "frac": achieved / VALU_PEAK_TOPS, "traffic": measured_traffic(khash),
             "ops_per_launch": ops, "box_tests_per_ray": n_box / rays, "tri_tests_per_ray": n_tri / rays,
@@ -290,9 +316,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "rays": rays, "texels": res * res,
+        "config": {"workload": WORKLOADS[args.config] + (f", closest-point query (max_dist {md:.4f})" if closest else ""),
+                   "rays": rays, "texels": res * res,
                    "hi_tris": int(asset.hi_F.shape[0]), "lo_tris": int(asset.lo_F.shape[0]),
-                   "step": "forward bake incl. BVH build + squared-error loss + backward"},
+                   "step": ("forward bake incl. BVH build (closest-point query: no backward)" if closest else
+                            "forward bake incl. BVH build + squared-error loss + backward")},
         "fwd_bwd_ms": ms_per_step,
         "fwd_ms": stage_ms["forward"],
         "loss_bwd_ms": bwd_ms,
@@ -304,7 +332,7 @@ def main():
         out["batch"] = bench_batch(B, batch_assets, args.batch_steps, 1, trav, log)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a sample ...")
-        out["cpu_baseline"] = cpu_baseline(asset, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(asset, args.cpu_seconds, md, args.query)
     print(json.dumps(out), flush=True)
 
 

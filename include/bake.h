@@ -177,10 +177,11 @@ int32_t bake_read_counter(const void *workspace, int32_t which, void *stream, in
 #define BAKE_VIEW_HITS 1     /* [n_rays] {f32 t, f32 beta1, f32 beta2, i32 id} (FLAG_SAVE)   */
 #define BAKE_VIEW_FACEMAP 2  /* [res*res] i32 covering face or INT32_MAX                      */
 #define BAKE_VIEW_LO_N 3     /* [n_lo_v] {f32 x, y, z, valid}                                 */
-#define BAKE_VIEW_SORTED 4   /* [n_hi_f] {u32 morton key} then [n_hi_f] {u32 tri index}       */
+#define BAKE_VIEW_SORTED 4   /* [n_hi_f] u32 Morton keys, sorted                              */
 #define BAKE_VIEW_NODES 5    /* [n_hi_f-1] 64 B BVH nodes: child boxes + child refs            */
 #define BAKE_VIEW_LEAVES 6   /* [n_hi_f] 48 B leaf triangles: 3 vertices + original index      */
 #define BAKE_VIEW_FACE_T 7   /* [n_lo_f] {f32 Tx, Ty, Tz, h}                                   */
+#define BAKE_VIEW_SORTED_IDX 8 /* [n_hi_f] u32 triangle indices in the sorted key order      */
 int32_t bake_workspace_view(int64_t n_hi_v, int64_t n_hi_f, int64_t n_lo_v, int64_t n_lo_f,
                             int32_t res, const bake_options *opt, int32_t which,
                             size_t *offset_out, size_t *bytes_out);

@@ -43,7 +43,8 @@ BAKE_FLAG_SAVE = 1
 BAKE_FLAG_TIMING = 2
 BAKE_FLAG_COUNT = 4
 
-VIEW_RAYS, VIEW_HITS, VIEW_FACEMAP, VIEW_LO_N, VIEW_SORTED, VIEW_NODES, VIEW_LEAVES, VIEW_FACE_T = range(8)
+(VIEW_RAYS, VIEW_HITS, VIEW_FACEMAP, VIEW_LO_N, VIEW_SORTED, VIEW_NODES, VIEW_LEAVES, VIEW_FACE_T,
+ VIEW_SORTED_IDX) = range(9)
 
 STAGES = ("lo_prep", "raster", "bvh_build", "traverse", "dilate", "forward")
 

@@ -572,7 +572,8 @@ int32_t bake_workspace_view(int64_t n_hi_v, int64_t n_hi_f, int64_t n_lo_v, int6
             *offset_out = L.hits; *bytes_out = 16 * tex; break;
         case BAKE_VIEW_FACEMAP: *offset_out = L.facemap; *bytes_out = 4 * tex; break;
         case BAKE_VIEW_LO_N: *offset_out = L.lo_n; *bytes_out = 16 * (size_t)n_lo_v; break;
-        case BAKE_VIEW_SORTED: *offset_out = L.keys0; *bytes_out = 8 * (size_t)n_hi_f; break;
+        case BAKE_VIEW_SORTED: *offset_out = L.keys0; *bytes_out = 4 * (size_t)n_hi_f; break;
+        case BAKE_VIEW_SORTED_IDX: *offset_out = L.vals0; *bytes_out = 4 * (size_t)n_hi_f; break;
         case BAKE_VIEW_NODES:
             *offset_out = L.nodes; *bytes_out = 64 * (size_t)std::max<int64_t>(n_hi_f - 1, 0); break;
         case BAKE_VIEW_LEAVES: *offset_out = L.leaves; *bytes_out = 48 * (size_t)n_hi_f; break;

@@ -24,7 +24,9 @@ namespace bake {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kSortRounds = kSortTile / kBlock;  // 16 keys per thread and pass
+constexpr int kSortBlock = 1024;                     // sort workgroups: 16 waves
+constexpr int kSortRounds = kSortTile / kSortBlock;  // 4 keys per thread and pass
+constexpr int kSortWaves = kSortBlock / 64;
 constexpr float kLeafEps = 1.0f / 16384.0f;  // edge tolerance of the hit rule (traverse.hip)
 
 __device__ __forceinline__ int3 tri_idx(const int32_t* __restrict__ F, int64_t g, int64_t nv,
@@ -193,72 +195,79 @@ __device__ __forceinline__ SortTile sort_tile(const Batch& Bt, int64_t blk) {
 }
 
 template <bool BWD>
-__global__ __launch_bounds__(kBlock) void radix_hist_kernel(Batch Bt, const uint32_t* __restrict__ keys,
-                                                            int shift, uint32_t* __restrict__ hist) {
+__global__ __launch_bounds__(kSortBlock) void radix_hist_kernel(Batch Bt, const uint32_t* __restrict__ keys,
+                                                                int shift, uint32_t* __restrict__ hist) {
     __shared__ uint32_t h[256];
     if (BWD && !sealed(Bt)) return;
     const SortTile T = sort_tile<BWD>(Bt, blockIdx.x);
-    h[threadIdx.x] = 0;
+    if (threadIdx.x < 256) h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = T.lt * kSortTile;
-#pragma unroll 4
+#pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
-        int64_t i = base + (int64_t)r * kBlock + threadIdx.x;
+        int64_t i = base + (int64_t)r * kSortBlock + threadIdx.x;
         if (i < T.count) atomicAdd(&h[(keys[T.start + i] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    hist[T.hbase + (int64_t)threadIdx.x * T.tiles + T.lt] = h[threadIdx.x];
+    if (threadIdx.x < 256) hist[T.hbase + (int64_t)threadIdx.x * T.tiles + T.lt] = h[threadIdx.x];
 }
 
-// Element r*256 + tid of the block's tile is ranked among equal digits by
+// Element r*1024 + tid of the block's tile is ranked among equal digits by
 // (earlier rounds, earlier waves, earlier lanes): a stable order.  The tile is
 // first placed in LDS in that order (digit runs contiguous), then written out
 // with consecutive lanes on consecutive positions of each run.  The scanned
-// digit counts are positions in the concatenated arrays.
+// digit counts are positions in the concatenated arrays.  Per round: ballot
+// ranks within each wave, then one thread per digit turns the per-wave counts
+// into positions (double-buffered, so a round needs two barriers).
 template <bool BWD>
-__global__ __launch_bounds__(kBlock) void radix_scatter_kernel(Batch Bt, const uint32_t* __restrict__ kin,
-                                                               const uint32_t* __restrict__ vin,
-                                                               uint32_t* __restrict__ kout,
-                                                               uint32_t* __restrict__ vout, int shift,
-                                                               const uint32_t* __restrict__ offs) {
+__global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(Batch Bt, const uint32_t* __restrict__ kin,
+                                                                   const uint32_t* __restrict__ vin,
+                                                                   uint32_t* __restrict__ kout,
+                                                                   uint32_t* __restrict__ vout, int shift,
+                                                                   const uint32_t* __restrict__ offs) {
     __shared__ uint32_t s_key[kSortTile];
     __shared__ uint32_t s_val[kSortTile];
     __shared__ uint32_t s_loc[256];   // tile-local first position of each digit
     __shared__ uint32_t s_glob[256];  // global position of the tile's first key of each digit
     __shared__ uint32_t s_run[256];   // digit counts, then running positions
-    __shared__ uint32_t s_wsum[kBlock / 64];
-    __shared__ uint32_t wcnt[kBlock / 64][256];
+    __shared__ uint32_t s_wsum[4];
+    __shared__ uint32_t wcnt[2][kSortWaves][256];  // per-wave digit counts, then positions
     if (BWD && !sealed(Bt)) return;
     const SortTile T = sort_tile<BWD>(Bt, blockIdx.x);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t base = T.lt * kSortTile;
     const int64_t nvalid = min((int64_t)kSortTile, T.count - base);
     if (nvalid <= 0) return;  // an empty capacity tile (uniform)
-    s_glob[tid] = offs[T.hbase + (int64_t)tid * T.tiles + T.lt];
-    s_run[tid] = 0;
-#pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) wcnt[w][tid] = 0;
+    if (tid < 256) {
+        s_glob[tid] = offs[T.hbase + (int64_t)tid * T.tiles + T.lt];
+        s_run[tid] = 0;
+    }
+    for (int x = tid; x < 2 * kSortWaves * 256; x += kSortBlock) (&wcnt[0][0][0])[x] = 0;
     __syncthreads();
     uint32_t key[kSortRounds], val[kSortRounds];
 #pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
-        const int64_t i = (int64_t)r * kBlock + tid;
+        const int64_t i = (int64_t)r * kSortBlock + tid;
         const bool valid = i < nvalid;
         key[r] = valid ? kin[T.start + base + i] : 0u;
         val[r] = valid ? vin[T.start + base + i] : 0u;
         if (valid) atomicAdd(&s_run[(key[r] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    {   // exclusive scan of the tile's digit counts (one digit per thread)
-        const uint32_t c = s_run[tid];
-        uint32_t x = c;
+    // exclusive scan of the tile's digit counts (waves 0-3, one digit per thread)
+    uint32_t c = 0, x = 0;
+    if (tid < 256) {
+        c = s_run[tid];
+        x = c;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
             const uint32_t y = __shfl_up(x, o, 64);
             if (lane >= o) x += y;
         }
         if (lane == 63) s_wsum[wave] = x;
-        __syncthreads();
+    }
+    __syncthreads();
+    if (tid < 256) {
         uint32_t before = 0;
         for (int w = 0; w < wave; ++w) before += s_wsum[w];
         s_loc[tid] = before + x - c;
@@ -267,7 +276,8 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(Batch Bt, const u
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
-        const bool valid = (int64_t)r * kBlock + tid < nvalid;
+        uint32_t(*wc)[256] = wcnt[r & 1];
+        const bool valid = (int64_t)r * kSortBlock + tid < nvalid;
         const uint32_t dig = (key[r] >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -277,27 +287,31 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(Batch Bt, const u
             peers &= bit ? m : ~m;
         }
         const uint32_t rank = (uint32_t)__popcll(peers & __lanemask_lt());
-        if (valid && rank == 0) wcnt[wave][dig] = (uint32_t)__popcll(peers);
+        if (valid && rank == 0) wc[wave][dig] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (tid < 256) {
+            // counts -> first positions, waves in order; clear the other buffer
+            uint32_t p = s_run[tid];
+#pragma unroll
+            for (int w = 0; w < kSortWaves; ++w) {
+                const uint32_t t = wc[w][tid];
+                wc[w][tid] = p;
+                p += t;
+                wcnt[(r + 1) & 1][w][tid] = 0;
+            }
+            s_run[tid] = p;
+        }
         __syncthreads();
         if (valid) {
-            uint32_t pos = s_run[dig] + rank;
-            for (int w = 0; w < wave; ++w) pos += wcnt[w][dig];
+            const uint32_t pos = wc[wave][dig] + rank;
             s_key[pos] = key[r];
             s_val[pos] = val[r];
         }
-        __syncthreads();
-        uint32_t add = 0;
-#pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w) {
-            add += wcnt[w][tid];
-            wcnt[w][tid] = 0;
-        }
-        s_run[tid] += add;
-        __syncthreads();
     }
-#pragma unroll 4
+    __syncthreads();
+#pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
-        const int e = r * kBlock + tid;
+        const int e = r * kSortBlock + tid;
         if (e >= nvalid) break;
         const uint32_t k = s_key[e];
         const uint32_t d = (k >> shift) & 255u;
@@ -597,19 +611,19 @@ hipError_t launch_sort(const BatchHost& H, int which, int bits, bool* result_in_
     hipError_t e;
     for (int shift = 0; shift < bits; shift += 8) {
         if (bwd) {
-            hipLaunchKernelGGL(radix_hist_kernel<true>, dim3((unsigned)blocks), dim3(kBlock), 0, s, H.dev,
+            hipLaunchKernelGGL(radix_hist_kernel<true>, dim3((unsigned)blocks), dim3(kSortBlock), 0, s, H.dev,
                                (const uint32_t*)kin, shift, hist);
         } else {
-            hipLaunchKernelGGL(radix_hist_kernel<false>, dim3((unsigned)blocks), dim3(kBlock), 0, s, H.dev,
+            hipLaunchKernelGGL(radix_hist_kernel<false>, dim3((unsigned)blocks), dim3(kSortBlock), 0, s, H.dev,
                                (const uint32_t*)kin, shift, hist);
         }
         if ((e = exclusive_scan_u32(hist, hist, 256 * blocks, tmp, nullptr, s)) != hipSuccess) return e;
         if (bwd) {
-            hipLaunchKernelGGL(radix_scatter_kernel<true>, dim3((unsigned)blocks), dim3(kBlock), 0, s, H.dev,
+            hipLaunchKernelGGL(radix_scatter_kernel<true>, dim3((unsigned)blocks), dim3(kSortBlock), 0, s, H.dev,
                                (const uint32_t*)kin, (const uint32_t*)vin, kout, vout, shift,
                                (const uint32_t*)hist);
         } else {
-            hipLaunchKernelGGL(radix_scatter_kernel<false>, dim3((unsigned)blocks), dim3(kBlock), 0, s, H.dev,
+            hipLaunchKernelGGL(radix_scatter_kernel<false>, dim3((unsigned)blocks), dim3(kSortBlock), 0, s, H.dev,
                                (const uint32_t*)kin, (const uint32_t*)vin, kout, vout, shift,
                                (const uint32_t*)hist);
         }

@@ -16,8 +16,9 @@
 //     after Aila & Laine 2009); lanes may then work on different assets;
 //   * conservative slab test: near/far planes picked by the sign of the
 //     direction, t widened outward by a relative 1e-6 (after Ize 2013); a zero
-//     direction component yields NaN for a ray lying in a slab plane, which
-//     the NaN-ignoring min3/max3 treat as an unbounded slab;
+//     direction component gives +-inf slab ends (kept infinite by the
+//     widening), or NaN for a ray lying in a slab plane, which the
+//     NaN-ignoring min3/max3 treat as an unbounded slab;
 //   * hit rule: a triangle is hit when the crossing's barycentric weights are
 //     all >= -kEdgeEps (relative edge tolerance) and |t| <= max_dist; the
 //     winner minimises (floor(|t| / w), index) with the quantum w = max_dist
@@ -125,11 +126,13 @@ __device__ __forceinline__ bool box_test(const RayT& r, float3 lo, float3 hi, fl
     float t0z = (nz - r.p.z) * r.invd.z, t1z = (fz - r.p.z) * r.invd.z;
     float t0 = fmaxf(fmaxf(t0x, t0y), t0z);
     float t1 = fminf(fminf(t1x, t1y), t1z);
-    // widen outward by a relative kPad (one fma each).  An infinite end turns
-    // into NaN here, which the NaN-ignoring clamps below replace by the bound:
-    // the box is kept, never wrongly culled.
-    t0 = fmaf(-kPad, fabsf(t0), t0);
-    t1 = fmaf(kPad, fabsf(t1), t1);
+    // widen outward by a relative kPad.  An infinite end (a direction
+    // component of zero, or a slab distance that overflows) stays infinite:
+    // the fma gives inf - inf = NaN there, which the NaN-ignoring min / max
+    // drop, so a ray running outside a slab parallel to it rejects the box
+    // instead of keeping every box it meets.
+    t0 = fminf(t0, fmaf(-kPad, fabsf(t0), t0));
+    t1 = fmaxf(t1, fmaf(kPad, fabsf(t1), t1));
     t0 = fmaxf(t0, -bound);
     t1 = fminf(t1, bound);
     *mint = fmaxf(fmaxf(t0, -t1), 0.f);  // nearest |t| of [t0, t1]

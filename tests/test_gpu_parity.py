@@ -253,9 +253,8 @@ def test_sort_is_stable_sort_and_tree_invariants(B, hi_level):
     ws = torch.full((nbytes,), 255, dtype=torch.uint8, device="cuda")
     r = run(B, a, workspace=ws)
     nf = a.hi_F.shape[0]
-    s = r.view(B.VIEW_SORTED).view(torch.int32).cpu().numpy()
-    keys = s[:nf].view(np.uint32)
-    vals = s[nf:2 * nf]
+    keys = r.view(B.VIEW_SORTED).view(torch.int32).cpu().numpy().view(np.uint32)
+    vals = r.view(B.VIEW_SORTED_IDX).view(torch.int32).cpu().numpy()
     assert np.all(np.diff(keys.astype(np.int64)) >= 0)
     eq = keys[1:] == keys[:-1]
     assert np.all(vals[1:][eq] > vals[:-1][eq])          # stable: index order on equal keys
@@ -298,6 +297,25 @@ def test_sort_is_stable_sort_and_tree_invariants(B, hi_level):
         assert np.array_equal(nodes[~lf_, 6 * side + 3:6 * side + 6], chi)
     root_lo = np.minimum(nodes[0, 0:3], nodes[0, 6:9])
     assert np.all(root_lo <= a.hi_V[a.hi_F].reshape(-1, 3).min(0))
+
+
+def test_axis_parallel_rays_prune(B):
+    """Rays with zero direction components (a flat low-poly: d = (0, 0, 1)
+    exactly) must still prune: a slab the ray runs parallel to and outside of
+    rejects the box.  Results never depend on this (pruning is conservative);
+    the number of box tests does."""
+    n = 64
+    hV, hF = grid(n, z=lambda x, y: 0.01 + 0.02 * np.sin(7 * x) * np.cos(5 * y), x0=-0.05, y0=-0.05, size=1.1)
+    hN = np.tile(np.array([0, 0, 1], np.float32), (hV.shape[0], 1))
+    a = plane_asset(hV, hF, hN, res=128, lo_n=8, max_dist=0.25)
+    t = B.to_device(a)
+    r = B.bake_normals(*t, a.res, a.max_dist, count=True)
+    nb, nt = r.test_counts()
+    rays = r.ray_count()
+    say(f"[gpu] axis-parallel rays: {nb / rays:.1f} box and {nt / rays:.2f} triangle tests per ray "
+        f"({hF.shape[0]} triangles)")
+    assert rays == 128 * 128
+    assert nb / rays < 200 and nt / rays < 20  # ~8000 triangles: brute force would be thousands
 
 
 # ---------------------------------------------------------------------------
