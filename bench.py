@@ -286,9 +286,9 @@ def main():
     log(f"[bench] {args.steps} steps, {ms_per_step:.3f} ms/step, stages {stage_ms}, loss+backward {bwd_ms:.3f} ms")
 
     # algorithmic op count of the traversal: one instrumented bake, untimed
-    cnt = B.bake_normals(*t, res, md, count=True, workspace=ws, out_map=out_map, out_hit=out_hit,
-                         query=args.query)
+    cnt = B.bake_normals(*t, res, md, count=True, workspace=ws, out_map=out_map, out_hit=out_hit, **trav)
     n_box, n_tri = cnt.test_counts()
+    trips = cnt.wave_trips()
     if closest:
         ops = n_box * OPS_BOX_PT + n_tri * OPS_TRI_PT + rays * OPS_RAY
     else:
@@ -301,6 +301,10 @@ def main():
             "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
             "frac": achieved / VALU_PEAK_TOPS, "traffic": measured_traffic(khash),
             "ops_per_launch": ops, "box_tests_per_ray": n_box / rays, "tri_tests_per_ray": n_tri / rays,
+            # lanes of a wave that advance a ray in an average trip of its
+            # traversal loop (one trip: an internal node, two box tests, or a leaf)
+            "lane_utilisation": (n_box / 2 + n_tri) / (64 * trips) if trips else None,
+            "wave_trips_per_ray_batch": trips / ((rays + 63) // 64),
             "launch_ms": stage_ms["traverse"], "source_hash": khash}
 
     out = {

@@ -75,7 +75,7 @@ extern "C" {
                                 of the bounding-box diagonal); ties within one distance
                                 quantum max_dist*2^-20 go to the lower triangle index.
                                 Forward only: BAKE_FLAG_SAVE is rejected (BAKE_E_UNSUPPORTED);
-                                trav_mode 1 runs as 2.                                     */
+                                trav_mode 1 runs as 3.                                     */
 
 /* ---- flags ------------------------------------------------------------ */
 #define BAKE_FLAG_SAVE 1u   /* keep the per-ray state that bake_normals_backward needs */
@@ -89,10 +89,13 @@ typedef struct bake_options {
     uint8_t *out_rgb8;     /* optional device [res,res,3] u8 map: floor((x+1)*127.5+0.5)   */
     int32_t trav_block;    /* traversal workgroup size: 64, 128, 256 (0 = tuned default)  */
     int32_t trav_stack;    /* LDS stack entries per lane: 8, 16, 32 (0 = tuned default)    */
-    int32_t trav_mode;     /* persistent waves; 0 = whole 64-ray batches, one loop over
-                              nodes and leaves; 1 = finished lanes refilled from a ray
-                              queue; 2 = whole 64-ray batches, internal nodes and
-                              leaves in separate phases; -1 = default (2)                 */
+    int32_t trav_mode;     /* persistent waves; 0 = whole 64-ray batches, each loop trip
+                              a step of either kind per lane; 1 = finished lanes
+                              refilled from a ray queue; 2 = whole 64-ray batches,
+                              internal nodes and leaves in separate phases; 3 = whole
+                              64-ray batches, each trip all-internal or all-leaf, a
+                              leaf trip once half the busy lanes wait at a leaf;
+                              -1 = default (3).  Results do not depend on it.           */
     int32_t query;         /* BAKE_QUERY_RAY (default) or BAKE_QUERY_CLOSEST                 */
     int32_t reserved[3];
 } bake_options;
@@ -168,7 +171,10 @@ int32_t bake_query_status(const void *workspace, void *stream, uint32_t *status_
 
 /* Synchronises `stream` and returns a device counter of the last bake that used
  * `workspace`: which = 0 -> number of covered texels (rays traced); 1 -> box
- * tests and 2 -> triangle tests of the traversal (bakes with BAKE_FLAG_COUNT). */
+ * tests and 2 -> triangle tests of the traversal; 3 -> traversal loop trips
+ * of whole 64-lane waves (1-3: bakes with BAKE_FLAG_COUNT).  A ray takes one
+ * trip per internal node (two box tests) or leaf (one triangle test), so
+ * (box / 2 + tri) / (64 * trips) is the fraction of lanes doing useful work. */
 int32_t bake_read_counter(const void *workspace, int32_t which, void *stream, int64_t *value_out);
 
 /* Location of an internal array inside the workspace, for inspection by tests
@@ -253,9 +259,9 @@ int32_t bake_read_asset_counter(const void *workspace, int32_t asset, int32_t wh
                                 int64_t *value_out);
 
 /* Traversal autotuner: bakes the batch with every traversal configuration
- * (trav_block x trav_stack x trav_mode = 3 x 3 x 3), `reps` times each,
+ * (trav_block x trav_stack x trav_mode = 3 x 3 x 4), `reps` times each,
  * and returns in *best_out the options of `base` (NULL = defaults) with the
- * configuration of the smallest median traversal time; ms_out (NULL or 27
+ * configuration of the smallest median traversal time; ms_out (NULL or 36
  * floats) receives every configuration's median, in the order block-major,
  * then stack, then mode.  Synchronises the stream; do not record it in a
  * graph.  The outputs of the batch are those of the last configuration run

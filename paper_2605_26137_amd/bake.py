@@ -223,6 +223,11 @@ class BakeResult:
         """(box tests, triangle tests) of a bake made with count=True."""
         return self.counter(1, stream), self.counter(2, stream)
 
+    def wave_trips(self, stream=None) -> int:
+        """Traversal loop trips of whole 64-lane waves (a bake made with
+        count=True): (box / 2 + tri) / (64 trips) is the useful-lane fraction."""
+        return self.counter(3, stream)
+
     def status(self, stream=None) -> int:
         v = C.c_uint32(0)
         _check(lib().bake_query_status(_ptr(self.workspace), _stream_handle(stream), C.byref(v)))
@@ -463,7 +468,7 @@ class BakeBatch:
         return f"n{self.n}-tex2^{round(math.log2(max(tex, 1)))}-tri2^{round(math.log2(max(tri, 1)))}"
 
 
-TRAV_CONFIGS = [(b, s, m) for b in (64, 128, 256) for s in (8, 16, 32) for m in (0, 1, 2)]
+TRAV_CONFIGS = [(b, s, m) for b in (64, 128, 256) for s in (8, 16, 32) for m in (0, 1, 2, 3)]
 
 
 def autotune(batch: BakeBatch, reps: int = 3, cache_path: Optional[str] = None, stream=None) -> dict:

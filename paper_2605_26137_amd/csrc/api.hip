@@ -60,7 +60,7 @@ int32_t parse_opts(const bake_options* o, Opts* out) {
     out->rgb8 = nullptr;
     out->trav.block = 256;
     out->trav.stack = 16;
-    out->trav.mode = 2;
+    out->trav.mode = 3;
     if (!o) return BAKE_OK;
     if (o->dilate_passes < 0 || o->dilate_passes > 64)
         return fail(BAKE_E_INVALID_ARG, "dilate_passes %d outside [0, 64]", o->dilate_passes);
@@ -79,8 +79,8 @@ int32_t parse_opts(const bake_options* o, Opts* out) {
             return fail(BAKE_E_INVALID_ARG, "trav_stack %d not in {8,16,32}", o->trav_stack);
         out->trav.stack = o->trav_stack;
     }
-    if (o->trav_mode < -1 || o->trav_mode > 2)
-        return fail(BAKE_E_INVALID_ARG, "trav_mode %d not in {-1,0,1,2}", o->trav_mode);
+    if (o->trav_mode < -1 || o->trav_mode > 3)
+        return fail(BAKE_E_INVALID_ARG, "trav_mode %d not in {-1,0,1,2,3}", o->trav_mode);
     if (o->trav_mode >= 0) out->trav.mode = o->trav_mode;
     if (o->query != BAKE_QUERY_RAY && o->query != BAKE_QUERY_CLOSEST)
         return fail(BAKE_E_INVALID_ARG, "query %d unknown", o->query);
@@ -509,7 +509,7 @@ bake_asset single_asset(const float* hi_V, int64_t n_hi_v, const int32_t* hi_F, 
 
 int32_t read_counter_at(const void* workspace, int32_t asset, int32_t which, void* stream, int64_t* value_out) {
     if (!workspace || !value_out) return fail(BAKE_E_INVALID_ARG, "NULL argument");
-    if (which < 0 || which > 2) return fail(BAKE_E_INVALID_ARG, "unknown counter %d", which);
+    if (which < 0 || which > 3) return fail(BAKE_E_INVALID_ARG, "unknown counter %d", which);
     if (asset < 0 || asset >= kMaxAssets) return fail(BAKE_E_INVALID_ARG, "asset %d out of range", asset);
     hipStream_t s = (hipStream_t)stream;
     uint32_t v[kCntSlots];
@@ -519,7 +519,8 @@ int32_t read_counter_at(const void* workspace, int32_t asset, int32_t which, voi
     HIP_OR_FAIL(hipStreamSynchronize(s));
     if (which == 0) *value_out = v[kCntRays];
     else if (which == 1) *value_out = (int64_t)v[kCntBoxLo] | ((int64_t)v[kCntBoxLo + 1] << 32);
-    else *value_out = (int64_t)v[kCntTriLo] | ((int64_t)v[kCntTriLo + 1] << 32);
+    else if (which == 2) *value_out = (int64_t)v[kCntTriLo] | ((int64_t)v[kCntTriLo + 1] << 32);
+    else *value_out = (int64_t)v[kCntIterLo] | ((int64_t)v[kCntIterLo + 1] << 32);
     return BAKE_OK;
 }
 
@@ -687,7 +688,7 @@ int32_t bake_autotune(const bake_asset* assets, int32_t n_assets, const bake_opt
     int idx = 0;
     for (int bi = 0; bi < 3; ++bi)
         for (int si = 0; si < 3; ++si)
-            for (int pe = 0; pe < 3; ++pe, ++idx) {
+            for (int pe = 0; pe < 4; ++pe, ++idx) {
                 bake_options o = opt;
                 o.trav_block = blocks[bi];
                 o.trav_stack = stacks[si];

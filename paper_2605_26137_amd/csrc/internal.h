@@ -139,6 +139,7 @@ constexpr int kCntBoxLo = 2;     // u64 box tests (FLAG_COUNT), slots 2-3
 constexpr int kCntTriLo = 4;     // u64 triangle tests (FLAG_COUNT), slots 4-5
 constexpr int kCntFrontier = 6;  // refit frontier length
 constexpr int kCntTreelets = 7;  // refit treelets
+constexpr int kCntIterLo = 8;    // u64 traversal loop trips of whole waves (FLAG_COUNT), slots 8-9
 constexpr int kCntSlots = 16;
 // Batch counter slots.
 constexpr int kGcQueue = 0;  // traversal work queue head
@@ -227,8 +228,9 @@ struct BatchHost {
 struct TravConfig {
     int block;    // 64 / 128 / 256
     int stack;    // LDS entries per lane: 8 / 16 / 32
-    int mode;     // 0: 64-ray batches, one loop; 1: lane refill from a ray queue;
-                  // 2: 64-ray batches, internal-node and leaf phases
+    int mode;     // 0: 64-ray batches, mixed trips; 1: lane refill from a ray queue;
+                  // 2: 64-ray batches, internal-node and leaf phases;
+                  // 3: 64-ray batches, balanced all-node / all-leaf trips
     bool count = false;    // instrumented variant: count box and triangle tests
     bool closest = false;  // closest-point query instead of the ray query
 };

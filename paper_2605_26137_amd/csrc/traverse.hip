@@ -10,7 +10,10 @@
 //     items of the batch's face-ordered ray lists from one device work queue,
 //     trace the 64 rays together in a tight loop and encode when the whole
 //     batch is done: neighbouring texels of one face walk nearly the same
-//     nodes, and the asset is uniform across the wave;
+//     nodes, and the asset is uniform across the wave.  The loop's trips are
+//     all-internal-node or all-leaf, a leaf trip being taken once at least
+//     half of the busy lanes wait at a leaf (the balanced loop), or phased,
+//     or mixed (see traverse_batch_kernel);
 //   * lane refill: lanes whose ray finished are refilled from a ray queue over
 //     the concatenated lists while the rest continue (wave-level compaction
 //     after Aila & Laine 2009); lanes may then work on different assets;
@@ -525,13 +528,37 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
     return v;
 }
 
+// One internal-node or leaf step of either query (p = R.p for the closest point).
+template <int BLOCK, int STACK, bool COUNT, bool CLOSEST>
+__device__ __forceinline__ int32_t node_step(const TreeView& tv, uint32_t* status, int32_t node,
+                                             const RayT& R, Best& best, LaneStack<BLOCK, STACK>& st, int tid,
+                                             unsigned long long& c_box) {
+    if constexpr (CLOSEST) return inner_step_pt<BLOCK, STACK, COUNT>(tv, status, node, R.p, best, st, tid, c_box);
+    else return inner_step<BLOCK, STACK, COUNT>(tv, status, node, R, best, st, tid, c_box);
+}
+template <int BLOCK, int STACK, bool COUNT, bool CLOSEST>
+__device__ __forceinline__ int32_t tri_step(const TreeView& tv, int32_t node, const RayT& R, Best& best,
+                                            LaneStack<BLOCK, STACK>& st, int tid, unsigned long long& c_tri) {
+    if constexpr (CLOSEST) return leaf_step_pt<BLOCK, STACK, COUNT>(tv, node, R.p, best, st, tid, c_tri);
+    else return leaf_step<BLOCK, STACK, COUNT>(tv, node, R, best, st, tid, c_tri);
+}
+
+// Loop shapes of the wave batches (TravConfig::mode):
+constexpr int kLoopSingle = 0;    // every trip: each lane one step of its own kind
+constexpr int kLoopPhased = 2;    // internal-node trips until every lane is at a leaf, then one leaf trip
+constexpr int kLoopBalanced = 3;  // each trip is all-leaf or all-internal: a leaf trip once at least
+                                  // half of the busy lanes wait at a leaf
+
 // Wave batches: each wave takes one (asset, 64-ray batch) item at a time,
-// traces its rays together and encodes once all 64 are done.  PHASED: the
-// lanes first advance through internal nodes until each has reached a leaf
-// or finished, then all lanes at a leaf test their triangle together (after
-// Aila & Laine's while-while loop), so the wave does not pay for the
-// triangle test on every step in which any one lane is at a leaf.
-template <int BLOCK, int STACK, bool COUNT, bool PHASED, bool CLOSEST>
+// traces its rays together and encodes once all 64 are done.  Each lane's
+// sequence of steps is the same under every loop shape (it depends only on
+// its ray and the tree); the shapes differ in how the wave interleaves its
+// lanes' internal-node and leaf steps.  A trip that mixes both kinds costs
+// the wave both code paths; the phased shape (after Aila & Laine's
+// while-while loop) never mixes them but makes lanes that reached a leaf
+// early wait through the rest of the internal-node phase; the balanced shape
+// never mixes them and lets no more than half of the busy lanes wait.
+template <int BLOCK, int STACK, bool COUNT, int LOOP, bool CLOSEST>
 __global__ __launch_bounds__(BLOCK) void traverse_batch_kernel(TravArgs a) {
     __shared__ int32_t stk[STACK][BLOCK];
     const int tid = threadIdx.x;
@@ -563,61 +590,61 @@ __global__ __launch_bounds__(BLOCK) void traverse_batch_kernel(TravArgs a) {
             // kept live through the traversal loop
             const RaySetup rs = setup_ray(a, As, a.rays[r]);
             if (rs.rel) {
-                R = make_rayt(rs.p, rs.d);
+                if constexpr (CLOSEST) R.p = rs.p;
+                else R = make_rayt(rs.p, rs.d);
                 node = tv.root;
             }
         }
         st.sp = st.lo = 0;
         int32_t steps = 0;
-        unsigned long long c_box = 0, c_tri = 0;
-        if (CLOSEST) {
-            // point query: the phased loop on box distances and nearest points
-            const float3 p = R.p;
+        unsigned long long c_box = 0, c_tri = 0, c_iter = 0;  // c_iter: trips of the whole wave
+        // a lane past the step bound (only a malformed tree gets there) stops
+        auto capped = [&]() {
+            if (++steps > tv.step_cap) {
+                set_status(B, kStInternal);
+                node = kEmpty;
+            }
+        };
+        if constexpr (LOOP == kLoopPhased) {
             while (__ballot(node != kEmpty)) {
                 while (__ballot(node >= 0)) {
+                    if (COUNT) ++c_iter;
                     if (node >= 0) {
-                        node = inner_step_pt<BLOCK, STACK, COUNT>(tv, B.status, node, p, best, st, tid, c_box);
-                        if (++steps > tv.step_cap) {
-                            set_status(B, kStInternal);
-                            node = kEmpty;
-                        }
+                        node = node_step<BLOCK, STACK, COUNT, CLOSEST>(tv, B.status, node, R, best, st, tid, c_box);
+                        capped();
                     }
                 }
+                if (COUNT && __ballot(node != kEmpty)) ++c_iter;
                 if (node != kEmpty) {
-                    node = leaf_step_pt<BLOCK, STACK, COUNT>(tv, node, p, best, st, tid, c_tri);
-                    if (++steps > tv.step_cap) {
-                        set_status(B, kStInternal);
-                        node = kEmpty;
-                    }
+                    node = tri_step<BLOCK, STACK, COUNT, CLOSEST>(tv, node, R, best, st, tid, c_tri);
+                    capped();
                 }
             }
-        } else if (PHASED) {
-            while (__ballot(node != kEmpty)) {
-                while (__ballot(node >= 0)) {
-                    if (node >= 0) {
-                        node = inner_step<BLOCK, STACK, COUNT>(tv, B.status, node, R, best, st, tid, c_box);
-                        if (++steps > tv.step_cap) {
-                            set_status(B, kStInternal);
-                            node = kEmpty;
-                        }
+        } else if constexpr (LOOP == kLoopBalanced) {
+            for (;;) {
+                const uint64_t at_node = __ballot(node >= 0);
+                const uint64_t at_leaf = __ballot(node < 0 && node != kEmpty);
+                if ((at_node | at_leaf) == 0) break;
+                if (COUNT) ++c_iter;
+                if (__popcll(at_leaf) >= __popcll(at_node)) {
+                    if (node < 0 && node != kEmpty) {
+                        node = tri_step<BLOCK, STACK, COUNT, CLOSEST>(tv, node, R, best, st, tid, c_tri);
+                        capped();
                     }
-                }
-                if (node != kEmpty) {
-                    node = leaf_step<BLOCK, STACK, COUNT>(tv, node, R, best, st, tid, c_tri);
-                    if (++steps > tv.step_cap) {
-                        set_status(B, kStInternal);
-                        node = kEmpty;
-                    }
+                } else if (node >= 0) {
+                    node = node_step<BLOCK, STACK, COUNT, CLOSEST>(tv, B.status, node, R, best, st, tid, c_box);
+                    capped();
                 }
             }
         } else {
             while (__ballot(node != kEmpty)) {
-                if (node != kEmpty) {
-                    node = trav_step<BLOCK, STACK, COUNT>(tv, B.status, node, R, best, st, tid, c_box, c_tri);
-                    if (++steps > tv.step_cap) {
-                        set_status(B, kStInternal);
-                        node = kEmpty;
-                    }
+                if (COUNT) ++c_iter;
+                if (node >= 0) {
+                    node = node_step<BLOCK, STACK, COUNT, CLOSEST>(tv, B.status, node, R, best, st, tid, c_box);
+                    capped();
+                } else if (node != kEmpty) {
+                    node = tri_step<BLOCK, STACK, COUNT, CLOSEST>(tv, node, R, best, st, tid, c_tri);
+                    capped();
                 }
             }
         }
@@ -628,6 +655,7 @@ __global__ __launch_bounds__(BLOCK) void traverse_batch_kernel(TravArgs a) {
             if (lane == 0) {
                 atomicAdd((unsigned long long*)&B.cnt[(int64_t)ai * kCntSlots + kCntBoxLo], c_box);
                 atomicAdd((unsigned long long*)&B.cnt[(int64_t)ai * kCntSlots + kCntTriLo], c_tri);
+                atomicAdd((unsigned long long*)&B.cnt[(int64_t)ai * kCntSlots + kCntIterLo], c_iter);
             }
         }
     }
@@ -660,7 +688,9 @@ __global__ __launch_bounds__(BLOCK) void traverse_refill_kernel(TravArgs a) {
     reset_best(best, tv.max_dist);
     int32_t node = kEmpty;
     int32_t steps = 0;
-    unsigned long long c_box = 0, c_tri = 0;
+    // c_iter: trips of the whole wave, kept by the lowest active lane (so a
+    // trip is attributed to that lane's asset)
+    unsigned long long c_box = 0, c_tri = 0, c_iter = 0;
     for (;;) {
         uint64_t idle = __ballot(!active);
         if (!exhausted && (int)__popcll(idle) >= 16) {
@@ -673,10 +703,11 @@ __global__ __launch_bounds__(BLOCK) void traverse_refill_kernel(TravArgs a) {
             if (!active) {
                 uint32_t k = base + (uint32_t)__popcll(idle & __lanemask_lt());
                 if (k < nrays) {
-                    if (COUNT && (c_box | c_tri)) {
+                    if (COUNT && (c_box | c_tri | c_iter)) {
                         atomicAdd((unsigned long long*)&B.cnt[(int64_t)ai * kCntSlots + kCntBoxLo], c_box);
                         atomicAdd((unsigned long long*)&B.cnt[(int64_t)ai * kCntSlots + kCntTriLo], c_tri);
-                        c_box = c_tri = 0;
+                        atomicAdd((unsigned long long*)&B.cnt[(int64_t)ai * kCntSlots + kCntIterLo], c_iter);
+                        c_box = c_tri = c_iter = 0;
                     }
                     ridx = k;
                     ai = upper_asset(B.ray_pf, B.n, k);
@@ -698,6 +729,7 @@ __global__ __launch_bounds__(BLOCK) void traverse_refill_kernel(TravArgs a) {
             continue;
         }
         if (!active) continue;
+        if (COUNT && (__ballot(true) & __lanemask_lt()) == 0) ++c_iter;
         node = trav_step<BLOCK, STACK, COUNT>(tv, B.status, node, R, best, st, tid, c_box, c_tri);
         if (++steps > tv.step_cap) {
             set_status(B, kStInternal);
@@ -707,18 +739,21 @@ __global__ __launch_bounds__(BLOCK) void traverse_refill_kernel(TravArgs a) {
         active = false;
         finish_ray(a, B.A[ai], ridx, rs, best);
     }
-    if (COUNT && (c_box | c_tri)) {
+    if (COUNT && (c_box | c_tri | c_iter)) {
         atomicAdd((unsigned long long*)&B.cnt[(int64_t)ai * kCntSlots + kCntBoxLo], c_box);
         atomicAdd((unsigned long long*)&B.cnt[(int64_t)ai * kCntSlots + kCntTriLo], c_tri);
+        atomicAdd((unsigned long long*)&B.cnt[(int64_t)ai * kCntSlots + kCntIterLo], c_iter);
     }
 }
 
-// MODE: 0 / 1 / 2 as TravConfig::mode for the ray query; 3 the closest-point query.
-template <int BLOCK, int STACK, bool COUNT, int MODE>
+// MODE: TravConfig::mode (the closest-point query has no lane-refill kernel:
+// mode 1 runs the balanced loop there).
+template <int BLOCK, int STACK, bool COUNT, int MODE, bool CLOSEST>
 hipError_t launch_one(const TravArgs& args, hipStream_t s, int64_t max_lanes) {
     static int cached_blocks = -1;
-    auto kern = MODE == 1 ? traverse_refill_kernel<BLOCK, STACK, COUNT>
-                          : traverse_batch_kernel<BLOCK, STACK, COUNT, MODE == 2, MODE == 3>;
+    auto kern = (MODE == 1 && !CLOSEST) ? traverse_refill_kernel<BLOCK, STACK, COUNT>
+                                        : traverse_batch_kernel<BLOCK, STACK, COUNT, MODE == 1 ? kLoopBalanced : MODE,
+                                                                CLOSEST>;
     if (cached_blocks < 0) {
         int dev = 0, cus = 0, per = 0;
         hipError_t e = hipGetDevice(&dev);
@@ -738,15 +773,21 @@ hipError_t launch_one(const TravArgs& args, hipStream_t s, int64_t max_lanes) {
     return hipGetLastError();
 }
 
-template <int BLOCK, int STACK, bool COUNT>
-hipError_t launch_mode(const TravArgs& args, int mode, bool closest, hipStream_t s, int64_t max_lanes) {
-    if (closest) return launch_one<BLOCK, STACK, COUNT, 3>(args, s, max_lanes);
+template <int BLOCK, int STACK, bool COUNT, bool CLOSEST>
+hipError_t launch_mode_q(const TravArgs& args, int mode, hipStream_t s, int64_t max_lanes) {
     switch (mode) {
-        case 0: return launch_one<BLOCK, STACK, COUNT, 0>(args, s, max_lanes);
-        case 1: return launch_one<BLOCK, STACK, COUNT, 1>(args, s, max_lanes);
-        case 2: return launch_one<BLOCK, STACK, COUNT, 2>(args, s, max_lanes);
+        case 0: return launch_one<BLOCK, STACK, COUNT, 0, CLOSEST>(args, s, max_lanes);
+        case 1: return launch_one<BLOCK, STACK, COUNT, 1, CLOSEST>(args, s, max_lanes);
+        case 2: return launch_one<BLOCK, STACK, COUNT, 2, CLOSEST>(args, s, max_lanes);
+        case 3: return launch_one<BLOCK, STACK, COUNT, 3, CLOSEST>(args, s, max_lanes);
     }
     return hipErrorInvalidValue;
+}
+
+template <int BLOCK, int STACK, bool COUNT>
+hipError_t launch_mode(const TravArgs& args, int mode, bool closest, hipStream_t s, int64_t max_lanes) {
+    if (closest) return launch_mode_q<BLOCK, STACK, COUNT, true>(args, mode, s, max_lanes);
+    return launch_mode_q<BLOCK, STACK, COUNT, false>(args, mode, s, max_lanes);
 }
 
 }  // namespace

@@ -92,7 +92,7 @@ def test_host_validation_codes(B, over, code):
 
 
 @pytest.mark.parametrize("field,val", [("dilate_passes", -1), ("dilate_passes", 65), ("flags", 64),
-                                       ("trav_block", 96), ("trav_stack", 12), ("trav_mode", 3)])
+                                       ("trav_block", 96), ("trav_stack", 12), ("trav_mode", 4), ("trav_mode", -2)])
 def test_bad_options(B, field, val):
     o = B.make_options()
     setattr(o, field, val)

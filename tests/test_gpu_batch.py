@@ -178,7 +178,7 @@ def test_autotune_every_config_same_result(B, tmp_path):
     out = B.autotune(batch, reps=1, cache_path=cache)
     say("[gpu] autotune", out["block"], out["stack"], out["mode"])
     assert (out["block"], out["stack"], out["mode"]) in B.TRAV_CONFIGS
-    assert len(out["ms"]) == 27 and all(v > 0 for v in out["ms"].values())
+    assert len(out["ms"]) == 36 and all(v > 0 for v in out["ms"].values())
     # every configuration gives the same results (the last one tried stays)
     for i, (m, h) in enumerate(zip(batch.maps, batch.hits)):
         assert np.array_equal(_bits(m), ref[i][0]) and np.array_equal(h.cpu().numpy(), ref[i][1])

@@ -117,7 +117,7 @@ def test_traversal_configs_identical(B):
     _, m0, h0 = run(B, a, 0.1)
     for blk in (64, 128, 256):
         for stk in (8, 16, 32):
-            for mode in (0, 1, 2):
+            for mode in (0, 1, 2, 3):
                 _, m, h = run(B, a, 0.1, trav_block=blk, trav_stack=stk, trav_mode=mode)
                 assert np.array_equal(h, h0) and np.array_equal(m.view(np.uint32), m0.view(np.uint32))
 

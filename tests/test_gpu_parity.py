@@ -194,7 +194,7 @@ def test_traversal_configs_bitwise_identical(B):
     rm, rh = np_out(ref)
     for blk in (64, 128, 256):
         for stk in (8, 16, 32):
-            for per in (0, 1, 2):
+            for per in (0, 1, 2, 3):
                 r = run(B, a, trav_block=blk, trav_stack=stk, trav_mode=per)
                 m, h = np_out(r)
                 assert np.array_equal(h, rh), (blk, stk, per)
@@ -316,6 +316,17 @@ def test_axis_parallel_rays_prune(B):
         f"({hF.shape[0]} triangles)")
     assert rays == 128 * 128
     assert nb / rays < 200 and nt / rays < 20  # ~8000 triangles: brute force would be thousands
+    # every ray step is a lane of some whole-wave trip: a lane takes at most
+    # one step per trip, and a wave makes a trip only while a lane steps
+    trips = r.wave_trips()
+    steps = nb // 2 + nt
+    assert nb % 2 == 0
+    assert steps <= 64 * trips
+    assert trips <= steps
+    for mode in (0, 1, 2):
+        rm = B.bake_normals(*t, a.res, a.max_dist, count=True, trav_mode=mode)
+        assert rm.test_counts() == (nb, nt)
+        assert rm.wave_trips() <= steps <= 64 * rm.wave_trips()
 
 
 # ---------------------------------------------------------------------------
@@ -413,6 +424,7 @@ def _full_size(B, oracle_lib, cfg, n_brute):
     rep = compare(oracle_lib, a, ob, gm, gh)
     say(f"[gpu] cfg{cfg} full (oracle BVH):", rep)
     assert rep.ok(), str(rep)
+    assert rep.n_covered == ob.texels.size  # the oracle's rasteriser decides coverage
     # brute force on a seeded sample of covered texels
     rng = np.random.default_rng(cfg)
     sample = np.sort(rng.choice(ob.texels, size=n_brute, replace=False))
@@ -434,4 +446,4 @@ def test_config2_full_size(B, oracle_lib):
 @pytest.mark.slow
 def test_config3_full_size(B, oracle_lib):
     rep = _full_size(B, oracle_lib, 3, n_brute=64)
-    assert rep.n_covered == 4329034
+    assert rep.n_covered == 4328992
