@@ -205,6 +205,7 @@ def main():
     ap.add_argument("--batch-assets", type=int, default=0, metavar="N",
                     help="also measure an N-asset batch (64 = the uneven batch workload)")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--graph", action="store_true", help="also time the step replayed from a HIP graph")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -280,6 +281,28 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
+    graph_ms = None
+    if args.graph:
+        # the same step recorded once into a HIP graph and replayed: no host
+        # launch work per kernel
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step(False)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            step(False)
+        for _ in range(args.warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        for _ in range(args.steps):
+            g.replay()
+        torch.cuda.synchronize()
+        graph_ms = (time.perf_counter() - tg) * 1e3 / args.steps
+        log(f"[bench] graph-replayed step: {graph_ms:.3f} ms")
     hist = B.stage_history(min(args.steps, 64))
     stage_ms = {name: float(np.mean(hist[:, k])) for k, name in enumerate(B.STAGES)}
     bwd_ms = float(np.mean([ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(args.steps)]))
@@ -326,6 +349,7 @@ def main():
                    "step": ("forward bake incl. BVH build (closest-point query: no backward)" if closest else
                             "forward bake incl. BVH build + squared-error loss + backward")},
         "fwd_bwd_ms": ms_per_step,
+        "graph_ms_per_step": graph_ms,
         "fwd_ms": stage_ms["forward"],
         "loss_bwd_ms": bwd_ms,
         "fwd_rays_per_s": rays / (stage_ms["forward"] / 1e3),

@@ -184,7 +184,10 @@ int32_t bake_read_counter(const void *workspace, int32_t which, void *stream, in
 #define BAKE_VIEW_FACEMAP 2  /* [res*res] i32 covering face or INT32_MAX                      */
 #define BAKE_VIEW_LO_N 3     /* [n_lo_v] {f32 x, y, z, valid}                                 */
 #define BAKE_VIEW_SORTED 4   /* [n_hi_f] u32 Morton keys, sorted                              */
-#define BAKE_VIEW_NODES 5    /* [n_hi_f-1] 64 B BVH nodes: child boxes + child refs            */
+#define BAKE_VIEW_NODES 5    /* [n_hi_f-1] 32 B BVH nodes: frame origin (3 f32), per-axis
+                                step exponents (u8 x 3), 8-bit child planes (L.lo, L.hi,
+                                R.lo, R.hi, xyz each), left child index | leaf flags (bit
+                                30 left, 31 right); plane = fmaf(byte, 2^(e-127), origin) */
 #define BAKE_VIEW_LEAVES 6   /* [n_hi_f] 48 B leaf triangles: 3 vertices + original index      */
 #define BAKE_VIEW_FACE_T 7   /* [n_lo_f] {f32 Tx, Ty, Tz, h}                                   */
 #define BAKE_VIEW_SORTED_IDX 8 /* [n_hi_f] u32 triangle indices in the sorted key order      */

@@ -208,8 +208,7 @@ int32_t make_plan(const Sizes* z, int n, uint32_t flags, Plan* P) {
         off += align256(bytes);
         return o;
     };
-    int64_t scan_n = std::max<int64_t>(std::max<int64_t>(L.t_lv, L.t_lf), 256 * L.t_stile);
-    if (L.save) scan_n = std::max<int64_t>(scan_n, 256 * L.t_btile);
+    const int64_t scan_n = std::max<int64_t>(L.t_lv, L.t_lf);  // the low-poly CSR and raster scans
     L.scan_tmp_n = scan_tmp_elems(scan_n) + 1;
     int64_t lanes = std::min<int64_t>(std::max<int64_t>(L.t_tex, 256), kMaxLanes);
     L.spill_lanes = (lanes + 255) / 256 * 256;
@@ -244,7 +243,9 @@ int32_t make_plan(const Sizes* z, int n, uint32_t flags, Plan* P) {
     L.keys1 = take(4 * (size_t)L.t_hf);
     L.vals1 = take(4 * (size_t)L.t_hf);
     L.hist = take(4 * 256 * (size_t)L.t_stile);
+    L.sup = take(4 * 256 * (size_t)kSortPasses * (size_t)sort_super_rows(L.t_stile, n));
     L.nodes = take(64 * (size_t)L.t_node);
+    L.nodes_c = take(32 * (size_t)L.t_node);
     L.leaves = take(48 * (size_t)L.t_hf);
     L.node_parent = take(4 * (size_t)L.t_node);
     L.leaf_parent = take(4 * (size_t)L.t_hf);
@@ -261,6 +262,7 @@ int32_t make_plan(const Sizes* z, int n, uint32_t flags, Plan* P) {
         L.bwd_k1 = take(4 * items);
         L.bwd_v1 = take(4 * items);
         L.bwd_hist = take(4 * 256 * (size_t)L.t_btile);
+        L.bwd_sup = take(4 * 256 * (size_t)kSortPasses * (size_t)sort_super_rows(L.t_btile, n));
         L.bwd_face1 = take(72 * (size_t)L.t_lf);
         L.bwd_face2 = take(36 * (size_t)L.t_lf);
         L.bwd_sbar = take(12 * (size_t)L.t_lv);
@@ -576,7 +578,7 @@ int32_t bake_workspace_view(int64_t n_hi_v, int64_t n_hi_f, int64_t n_lo_v, int6
         case BAKE_VIEW_SORTED: *offset_out = L.keys0; *bytes_out = 4 * (size_t)n_hi_f; break;
         case BAKE_VIEW_SORTED_IDX: *offset_out = L.vals0; *bytes_out = 4 * (size_t)n_hi_f; break;
         case BAKE_VIEW_NODES:
-            *offset_out = L.nodes; *bytes_out = 64 * (size_t)std::max<int64_t>(n_hi_f - 1, 0); break;
+            *offset_out = L.nodes_c; *bytes_out = 32 * (size_t)std::max<int64_t>(n_hi_f - 1, 0); break;
         case BAKE_VIEW_LEAVES: *offset_out = L.leaves; *bytes_out = 48 * (size_t)n_hi_f; break;
         case BAKE_VIEW_FACE_T: *offset_out = L.face_t; *bytes_out = 16 * (size_t)n_lo_f; break;
         default: return fail(BAKE_E_INVALID_ARG, "unknown view %d", which);

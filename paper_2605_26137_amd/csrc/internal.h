@@ -30,17 +30,37 @@ struct Hit {
 };
 static_assert(sizeof(Hit) == 16, "Hit is 16 B");
 
-// Binary BVH node holding the boxes of both children (64 B, one cache line
-// fetch per visit):
+// Full-precision box slots of a binary node, by child side (build scratch:
+// the refit hands the boxes of the top levels over through these):
 //   a = (L.lo.x, L.lo.y, L.lo.z, L.hi.x)
 //   b = (L.hi.y, L.hi.z, R.lo.x, R.lo.y)
 //   c = (R.lo.z, R.hi.x, R.hi.y, R.hi.z)
-//   ref = (left, right, -, -): >= 0 internal node, < 0 leaf ~ref
 struct alignas(16) BvhNode {
     float4 a, b, c;
-    int4 ref;
+    int4 unused;
 };
 static_assert(sizeof(BvhNode) == 64, "BvhNode is 64 B");
+
+// Binary BVH node as the traversal reads it (32 B, two 16-B loads per
+// visit): the boxes of both children quantised to 8 bits per plane in a
+// frame of the node's own.
+//   a = (o.x, o.y, o.z, meta): meta byte k = biased exponent e_k of the axis-k
+//       step 2^(e_k - 127)
+//   q = (q0, q1, q2, child): the 12 bytes of q0..q2 in order are the planes
+//       L.lo.xyz, L.hi.xyz, R.lo.xyz, R.hi.xyz; child = index g of the left
+//       child (the right one is g + 1) with bit 30 / 31 set when the left /
+//       right child is a leaf
+// A plane with byte v decodes as fmaf(v, 2^(e_k - 127), o_k) in FP32; the
+// build picks the bytes so that every decoded child box contains the child's
+// box (a lower plane rounds down, an upper one up).  A node whose box is not
+// finite on an axis decodes to NaN planes there, which the box tests treat as
+// an unbounded slab.
+struct alignas(16) BvhNodeC {
+    float4 a;
+    uint4 q;
+};
+static_assert(sizeof(BvhNodeC) == 32, "BvhNodeC is 32 B");
+constexpr uint32_t kChildLeafL = 1u << 30, kChildLeafR = 1u << 31, kChildIndex = kChildLeafL - 1u;
 
 // Leaf triangle: vertices copied from hi_V (bit-exact) plus original index.
 //   a = (v0.x, v0.y, v0.z, v1.x), b = (v1.y, v1.z, v2.x, v2.y),
@@ -122,6 +142,11 @@ enum GridId : int {
 };
 
 constexpr int kSortTile = 4096;  // keys per radix-sort block and pass
+constexpr int kSortPasses = 4;   // 8-bit digits of keys up to 32 bits
+constexpr int kSuper = 32;       // sort tiles per super-tile (digit counts summed per super-tile)
+// Super-tile rows of a sort over `tiles` tiles of `n` assets (asset a's rows
+// start at its first tile / kSuper + a).
+__host__ __device__ inline int64_t sort_super_rows(int64_t tiles, int64_t n) { return tiles / kSuper + n + 1; }
 constexpr int kFinishTile = 32;  // texel tile side of the fused fill + dilation
 constexpr int kMaxFusedPasses = 4;  // more dilation passes run one launch per pass
 
@@ -201,11 +226,11 @@ struct Layout {
     size_t facemap, level;                        // per texel
     size_t rays, hits;                            // per ray
     size_t bounds_part, bounds;                   // centroid bounds: per sort tile, per asset
-    size_t keys0, keys1, vals0, vals1, hist;      // radix sort of the BVH keys
-    size_t nodes, leaves, node_parent, leaf_parent, refit_cnt, node_range, frontier, treelets;
+    size_t keys0, keys1, vals0, vals1, hist, sup; // radix sort of the BVH keys
+    size_t nodes, nodes_c, leaves, node_parent, leaf_parent, refit_cnt, node_range, frontier, treelets;
     size_t spill;                                 // traversal stack spill
     // backward scratch (BAKE_FLAG_SAVE only)
-    size_t bwd_ray, bwd_k0, bwd_v0, bwd_k1, bwd_v1, bwd_hist, bwd_face1, bwd_face2, bwd_sbar, bwd_vbar;
+    size_t bwd_ray, bwd_k0, bwd_v0, bwd_k1, bwd_v1, bwd_hist, bwd_sup, bwd_face1, bwd_face2, bwd_sbar, bwd_vbar;
     size_t total;
     // batch totals
     int n;

@@ -167,12 +167,24 @@ __global__ __launch_bounds__(kBlock) void morton_kernel(Batch Bt, const float* _
 // 3. stable LSD radix sort, 8-bit digits, per asset
 // ---------------------------------------------------------------------------
 
+// Digit offsets without a separate scan.  A pass is two launches: the
+// histogram kernel writes each tile's 256 digit counts as a row
+// (hist[hbase + 256 lt + digit]) and adds them into its super-tile's row
+// (kSuper consecutive tiles of one asset, sup[sbase + 256 (lt / kSuper) +
+// digit], integer atomics: the sums do not depend on their order); the
+// scatter kernel then finds where its tile's keys of digit d start from
+//   start + (the asset's keys with a smaller digit: all super-tile rows)
+//         + (earlier tiles' keys of digit d: earlier super-tiles' rows and the
+//            rows of the earlier tiles in its own super-tile),
+// which is the exclusive scan of the counts in (digit, tile) order.
 // The tile of a sort block: its asset's keys [start, start + count) in the
-// concatenated arrays, its digit-count column (hist[hbase + digit * tiles +
-// lt]) and its local tile lt.  BWD: the backward pairs, whose count lives on
-// the device (three per ray), with tiles sized for the capacity 3 res^2.
+// concatenated arrays, its count row (hbase + 256 lt), its super-tile rows
+// (from sbase; an asset's super-tiles start at tile_base / kSuper + asset,
+// which keeps assets apart) and its local tile lt.  BWD: the backward pairs,
+// whose count lives on the device (three per ray), with tiles sized for the
+// capacity 3 res^2.
 struct SortTile {
-    int64_t start, count, hbase, tiles, lt;
+    int64_t start, count, hbase, sbase, lt;
 };
 
 template <bool BWD>
@@ -180,26 +192,27 @@ __device__ __forceinline__ SortTile sort_tile(const Batch& Bt, int64_t blk) {
     SortTile T;
     const int a = block_asset(Bt, BWD ? kGBwdSort : kGSort, blk, &T.lt);
     const AssetDev& As = Bt.A[a];
+    const int64_t tile_base = BWD ? As.btile : As.stile;
     if (BWD) {
         T.start = 3 * (int64_t)Bt.ray_pf[a];
         T.count = 3 * (int64_t)Bt.cnt[(int64_t)a * kCntSlots + kCntRays];
-        T.hbase = 256 * As.btile;
-        T.tiles = ceil_div(3 * (int64_t)As.res * As.res, kSortTile);
     } else {
         T.start = As.hf;
         T.count = As.nhf;
-        T.hbase = 256 * As.stile;
-        T.tiles = ceil_div(As.nhf, kSortTile);
     }
+    T.hbase = 256 * tile_base;
+    T.sbase = 256 * (tile_base / kSuper + a);
     return T;
 }
 
 template <bool BWD>
 __global__ __launch_bounds__(kSortBlock) void radix_hist_kernel(Batch Bt, const uint32_t* __restrict__ keys,
-                                                                int shift, uint32_t* __restrict__ hist) {
+                                                                int shift, uint32_t* __restrict__ hist,
+                                                                uint32_t* __restrict__ sup) {
     __shared__ uint32_t h[256];
     if (BWD && !sealed(Bt)) return;
     const SortTile T = sort_tile<BWD>(Bt, blockIdx.x);
+    if (T.lt * kSortTile >= T.count) return;  // an empty capacity tile (uniform)
     if (threadIdx.x < 256) h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = T.lt * kSortTile;
@@ -209,22 +222,28 @@ __global__ __launch_bounds__(kSortBlock) void radix_hist_kernel(Batch Bt, const 
         if (i < T.count) atomicAdd(&h[(keys[T.start + i] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    if (threadIdx.x < 256) hist[T.hbase + (int64_t)threadIdx.x * T.tiles + T.lt] = h[threadIdx.x];
+    if (threadIdx.x < 256) {
+        const uint32_t c = h[threadIdx.x];
+        hist[T.hbase + 256 * T.lt + threadIdx.x] = c;
+        if (c) atomicAdd(&sup[T.sbase + 256 * (T.lt / kSuper) + threadIdx.x], c);
+    }
 }
 
 // Element r*1024 + tid of the block's tile is ranked among equal digits by
 // (earlier rounds, earlier waves, earlier lanes): a stable order.  The tile is
 // first placed in LDS in that order (digit runs contiguous), then written out
-// with consecutive lanes on consecutive positions of each run.  The scanned
-// digit counts are positions in the concatenated arrays.  Per round: ballot
-// ranks within each wave, then one thread per digit turns the per-wave counts
-// into positions (double-buffered, so a round needs two barriers).
+// with consecutive lanes on consecutive positions of each run.  The tile's
+// first position of each digit comes from the count rows (see kSuper).  Per
+// round: ballot ranks within each wave, then one thread per digit turns the
+// per-wave counts into positions (double-buffered, so a round needs two
+// barriers).
 template <bool BWD>
 __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(Batch Bt, const uint32_t* __restrict__ kin,
                                                                    const uint32_t* __restrict__ vin,
                                                                    uint32_t* __restrict__ kout,
                                                                    uint32_t* __restrict__ vout, int shift,
-                                                                   const uint32_t* __restrict__ offs) {
+                                                                   const uint32_t* __restrict__ hist,
+                                                                   const uint32_t* __restrict__ sup) {
     __shared__ uint32_t s_key[kSortTile];
     __shared__ uint32_t s_val[kSortTile];
     __shared__ uint32_t s_loc[256];   // tile-local first position of each digit
@@ -238,8 +257,43 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(Batch Bt, con
     const int64_t base = T.lt * kSortTile;
     const int64_t nvalid = min((int64_t)kSortTile, T.count - base);
     if (nvalid <= 0) return;  // an empty capacity tile (uniform)
+    {
+        // per digit, in four parts: the asset's count (all super-tile rows)
+        // and the count before this tile (earlier super-tiles, then the
+        // earlier tiles of its own super-tile); wcnt[0] is free until the
+        // rounds below
+        const int d = tid & 255, part = tid >> 8;
+        const int64_t S = T.lt / kSuper, nS = ceil_div(ceil_div(T.count, kSortTile), kSuper);
+        uint32_t tot = 0, before = 0;
+        for (int64_t x = part; x < nS; x += 4) {
+            const uint32_t v = sup[T.sbase + 256 * x + d];
+            tot += v;
+            if (x < S) before += v;
+        }
+        for (int64_t t = S * kSuper + part; t < T.lt; t += 4) before += hist[T.hbase + 256 * t + d];
+        wcnt[0][part][d] = tot;
+        wcnt[0][4 + part][d] = before;
+    }
+    __syncthreads();
+    uint32_t tot = 0, before = 0;
     if (tid < 256) {
-        s_glob[tid] = offs[T.hbase + (int64_t)tid * T.tiles + T.lt];
+        tot = (wcnt[0][0][tid] + wcnt[0][1][tid]) + (wcnt[0][2][tid] + wcnt[0][3][tid]);
+        before = (wcnt[0][4][tid] + wcnt[0][5][tid]) + (wcnt[0][6][tid] + wcnt[0][7][tid]);
+        // exclusive scan of the asset's digit counts (waves 0-3)
+        uint32_t x = tot;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) s_wsum[wave] = x;
+        tot = x - tot;  // exclusive within the wave
+    }
+    __syncthreads();
+    if (tid < 256) {
+        uint32_t w = 0;
+        for (int k = 0; k < wave; ++k) w += s_wsum[k];
+        s_glob[tid] = (uint32_t)T.start + w + tot + before;
         s_run[tid] = 0;
     }
     for (int x = tid; x < 2 * kSortWaves * 256; x += kSortBlock) (&wcnt[0][0][0])[x] = 0;
@@ -316,8 +370,12 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(Batch Bt, con
         const uint32_t k = s_key[e];
         const uint32_t d = (k >> shift) & 255u;
         const uint32_t pos = s_glob[d] + ((uint32_t)e - s_loc[d]);
-        kout[pos] = k;
-        vout[pos] = s_val[e];
+        if ((int64_t)pos < T.start + T.count) {  // always, unless the counts were corrupted
+            kout[pos] = k;
+            vout[pos] = s_val[e];
+        } else {
+            set_status(Bt, kStInternal);
+        }
     }
 }
 
@@ -336,7 +394,7 @@ __device__ __forceinline__ int cprefix(const uint32_t* __restrict__ k, int64_t n
 }
 
 __global__ __launch_bounds__(kBlock) void karras_kernel(Batch Bt, const uint32_t* __restrict__ keys_all,
-                                                        BvhNode* __restrict__ nodes_all,
+                                                        BvhNodeC* __restrict__ nodes_all,
                                                         int32_t* __restrict__ np_all,
                                                         int32_t* __restrict__ lp_all,
                                                         int2* __restrict__ range_all) {
@@ -346,7 +404,7 @@ __global__ __launch_bounds__(kBlock) void karras_kernel(Batch Bt, const uint32_t
     const int64_t i = lb * kBlock + threadIdx.x;
     if (i >= n - 1) return;
     const uint32_t* __restrict__ keys = keys_all + As.hf;
-    BvhNode* __restrict__ nodes = nodes_all + As.node;
+    BvhNodeC* __restrict__ nodes = nodes_all + As.node;
     int32_t* __restrict__ node_parent = np_all + As.node;
     int32_t* __restrict__ leaf_parent = lp_all + As.hf;
     int d = (cprefix(keys, n, i, i + 1) - cprefix(keys, n, i, i - 1)) >= 0 ? 1 : -1;
@@ -367,7 +425,7 @@ __global__ __launch_bounds__(kBlock) void karras_kernel(Batch Bt, const uint32_t
     int64_t lo = i < j ? i : j, hi = i < j ? j : i;
     int32_t left = lo == gamma ? ~(int32_t)gamma : (int32_t)gamma;
     int32_t right = hi == gamma + 1 ? ~(int32_t)(gamma + 1) : (int32_t)(gamma + 1);
-    nodes[i].ref = make_int4(left, right, 0, 0);
+    nodes[i].q.w = (uint32_t)gamma | (left < 0 ? kChildLeafL : 0u) | (right < 0 ? kChildLeafR : 0u);
     range_all[As.node + i] = make_int2((int32_t)lo, (int32_t)hi);
     if (left < 0) leaf_parent[gamma] = (int32_t)(i << 1);
     else node_parent[gamma] = (int32_t)(i << 1);
@@ -399,11 +457,75 @@ __global__ __launch_bounds__(kBlock) void karras_kernel(Batch Bt, const uint32_t
 constexpr int kTreelet = 2048;
 constexpr int kRefitBlock = 1024;  // 16 waves: the LDS footprint allows one workgroup per CU
 constexpr int kTopBlock = 1024;
+constexpr int kTopList = 8192;
 
 __device__ __forceinline__ void put_slot(BvhNode* node, int side, const float b[6]) {
     float* f = reinterpret_cast<float*>(node) + 6 * side;
 #pragma unroll
     for (int k = 0; k < 6; ++k) f[k] = b[k];
+}
+
+__device__ __forceinline__ float pow2f(uint32_t e) { return __uint_as_float(e << 23); }  // 2^(e - 127)
+
+// One axis of a compressed node: the frame [o, o + 255 s] with s a power of
+// two, and the bytes of the four child planes.  A decoded plane fmaf(v, s, o)
+// rounds lo + v s once, and lo + v s is exact whenever it is representable,
+// so it lies on the outer side of a plane c exactly when lo + v s does: the
+// bytes come from (c - lo) / s (exact scaling of a once-rounded difference,
+// off by at most one) and one check each.
+__device__ __forceinline__ uint32_t quantise_axis(float lL, float hL, float lR, float hR, float* o_out,
+                                                  uint32_t q_out[4]) {
+    const float lo = fminf(lL, lR), hi = fmaxf(hL, hR);
+    if (!(isfinite(lo) && isfinite(hi) && lo <= hi)) {
+        // NaN planes: an unbounded slab in the box tests
+        *o_out = __uint_as_float(0x7FC00000u);
+        q_out[0] = q_out[1] = q_out[2] = q_out[3] = 0;
+        return 127u;
+    }
+    // ext / 2^(E - 7) lies in [128, 256) for ext in [2^E, 2^(E+1)); one
+    // doubling when 255 steps still fall short of hi
+    const float ext = hi - lo;
+    const uint32_t eb = (__float_as_uint(ext) >> 23) & 0xFFu;
+    uint32_t e = eb > 8u ? eb - 7u : 1u;
+    if (e < 254u && fmaf(255.f, pow2f(e), lo) < hi) ++e;
+    const float s = pow2f(e), inv = pow2f(254u - e);  // inv = 1 / s
+    const float pl[4] = {lL, hL, lR, hR};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float c = pl[j];
+        const float x = fminf(fmaxf((c - lo) * inv, 0.f), 255.f);
+        uint32_t v;
+        if ((j & 1) == 0) {  // lower plane: the largest v with lo + v s <= c
+            v = (uint32_t)floorf(x);
+            if (v > 0u && fmaf((float)v, s, lo) > c) --v;
+        } else {             // upper plane: the smallest v with lo + v s >= c
+            v = (uint32_t)ceilf(x);
+            if (v < 255u && fmaf((float)v, s, lo) < c) ++v;
+        }
+        q_out[j] = v;
+    }
+    *o_out = lo;
+    return e;
+}
+
+// Writes the frame and child planes of node p (its child word is the
+// hierarchy kernel's).
+__device__ __forceinline__ void write_compressed(BvhNodeC* node, const float L[6], const float R[6]) {
+    float o[3];
+    uint32_t q[3][4], e[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) e[k] = quantise_axis(L[k], L[k + 3], R[k], R[k + 3], &o[k], q[k]);
+    // byte order: L.lo.xyz, L.hi.xyz, R.lo.xyz, R.hi.xyz
+    const uint32_t b[12] = {q[0][0], q[1][0], q[2][0], q[0][1], q[1][1], q[2][1],
+                            q[0][2], q[1][2], q[2][2], q[0][3], q[1][3], q[2][3]};
+    uint32_t w[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) w[i] = b[4 * i] | (b[4 * i + 1] << 8) | (b[4 * i + 2] << 16) | (b[4 * i + 3] << 24);
+    node->a = make_float4(o[0], o[1], o[2], __uint_as_float(e[0] | (e[1] << 8) | (e[2] << 16)));
+    uint32_t* qw = reinterpret_cast<uint32_t*>(&node->q);
+    qw[0] = w[0];
+    qw[1] = w[1];
+    qw[2] = w[2];
 }
 
 __global__ __launch_bounds__(kBlock) void leaf_pack_kernel(Batch Bt, const uint32_t* __restrict__ sorted_idx,
@@ -478,7 +600,8 @@ __global__ __launch_bounds__(kBlock) void treelet_find_kernel(Batch Bt, const in
 // Workgroups take the batch's treelets in turn (the treelet prefix over the
 // assets is known on the device only).
 __global__ __launch_bounds__(kRefitBlock) void treelet_refit_kernel(
-    Batch Bt, const Leaf* __restrict__ leaves_all, BvhNode* nodes_all, const int32_t* __restrict__ np_all,
+    Batch Bt, const Leaf* __restrict__ leaves_all, BvhNode* nodes_all, BvhNodeC* __restrict__ nodes_c_all,
+    const int32_t* __restrict__ np_all,
     const int32_t* __restrict__ lp_all, const int4* __restrict__ list_all, int32_t* __restrict__ frontier_all) {
     __shared__ int32_t s_np[kTreelet];      // parent link of internal node lo + i
     __shared__ int32_t s_lp[kTreelet];      // parent link of leaf lo + i
@@ -491,6 +614,7 @@ __global__ __launch_bounds__(kRefitBlock) void treelet_refit_kernel(
         const int64_t n = As.nhf;
         const Leaf* __restrict__ leaves = leaves_all + As.hf;
         BvhNode* nodes = nodes_all + As.node;
+        BvhNodeC* __restrict__ nodes_c = nodes_c_all + As.node;
         const int32_t* __restrict__ node_parent = np_all + As.node;
         const int32_t* __restrict__ leaf_parent = lp_all + As.hf;
         uint32_t* nfront = &Bt.cnt[(int64_t)a * kCntSlots + kCntFrontier];
@@ -540,8 +664,7 @@ __global__ __launch_bounds__(kRefitBlock) void treelet_refit_kernel(
                 float sib[6];
 #pragma unroll
                 for (int q = 0; q < 6; ++q) sib[q] = s_box[li][1 - side][q];
-                put_slot(&nodes[p], side, box);
-                put_slot(&nodes[p], 1 - side, sib);
+
 #pragma unroll
                 for (int q = 0; q < 3; ++q) box[q] = fminf(box[q], sib[q]);
 #pragma unroll
@@ -551,6 +674,11 @@ __global__ __launch_bounds__(kRefitBlock) void treelet_refit_kernel(
             }
         }
         __syncthreads();
+        // the treelet's internal nodes (both children arrived) from their LDS
+        // slots, in parallel
+        for (int i = threadIdx.x; i < sz; i += kRefitBlock)
+            if (s_cnt[i] == 2u) write_compressed(&nodes_c[lo + i], s_box[i][0], s_box[i][1]);
+        __syncthreads();
     }
 }
 
@@ -558,13 +686,21 @@ __global__ __launch_bounds__(kRefitBlock) void treelet_refit_kernel(
 // above the treelets.  Each frontier entry says: child `side` of node p is
 // complete and its box is in p's slot.
 __global__ __launch_bounds__(kTopBlock) void refit_top_kernel(Batch Bt, BvhNode* nodes_all,
+                                                             BvhNodeC* __restrict__ nodes_c_all,
                                                              const int32_t* __restrict__ np_all,
                                                              const int32_t* __restrict__ frontier_all,
                                                              uint32_t* cnt_all) {
+    // nodes completed by the climb, compressed in parallel after it (beyond
+    // the list's capacity a node is compressed where it completes)
+    __shared__ int32_t s_done[kTopList];
+    __shared__ uint32_t s_ndone;
     const int a = blockIdx.x;
     const AssetDev& As = Bt.A[a];
     if (As.nhf <= 1) return;
+    if (threadIdx.x == 0) s_ndone = 0;
+    __syncthreads();
     BvhNode* nodes = nodes_all + As.node;
+    BvhNodeC* __restrict__ nodes_c = nodes_c_all + As.node;
     const int32_t* __restrict__ node_parent = np_all + As.node;
     const int32_t* __restrict__ frontier = frontier_all + As.tl;
     uint32_t* cnt = cnt_all + As.node;
@@ -580,15 +716,36 @@ __global__ __launch_bounds__(kTopBlock) void refit_top_kernel(Batch Bt, BvhNode*
             uint32_t old = __hip_atomic_fetch_add(&cnt[p], 1u, __ATOMIC_ACQ_REL,
                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
             if (old == 0) break;
-            float box[6];
+            float box[6], bl[6], br[6];
             const float* f = reinterpret_cast<const float*>(&nodes[p]);
 #pragma unroll
-            for (int q = 0; q < 3; ++q) box[q] = fminf(f[q], f[6 + q]);
+            for (int q = 0; q < 6; ++q) {
+                bl[q] = f[q];
+                br[q] = f[6 + q];
+            }
+            const uint32_t slot = atomicAdd(&s_ndone, 1u);
+            if (slot < (uint32_t)kTopList) s_done[slot] = p;
+            else write_compressed(&nodes_c[p], bl, br);
 #pragma unroll
-            for (int q = 3; q < 6; ++q) box[q] = fmaxf(f[q], f[6 + q]);
+            for (int q = 0; q < 3; ++q) box[q] = fminf(bl[q], br[q]);
+#pragma unroll
+            for (int q = 3; q < 6; ++q) box[q] = fmaxf(bl[q], br[q]);
             pp = node_parent[p];
             if (pp >= 0) put_slot(&nodes[pp >> 1], pp & 1, box);
         }
+    }
+    __syncthreads();
+    const uint32_t nd = min(s_ndone, (uint32_t)kTopList);
+    for (uint32_t i = threadIdx.x; i < nd; i += kTopBlock) {
+        const int32_t p = s_done[i];
+        const float* f = reinterpret_cast<const float*>(&nodes[p]);
+        float bl[6], br[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            bl[q] = f[q];
+            br[q] = f[6 + q];
+        }
+        write_compressed(&nodes_c[p], bl, br);
     }
 }
 
@@ -607,25 +764,27 @@ hipError_t launch_sort(const BatchHost& H, int which, int bits, bool* result_in_
     uint32_t* kout = (uint32_t*)(H.ws + (bwd ? L.bwd_k1 : L.keys1));
     uint32_t* vout = (uint32_t*)(H.ws + (bwd ? L.bwd_v1 : L.vals1));
     uint32_t* hist = (uint32_t*)(H.ws + (bwd ? L.bwd_hist : L.hist));
-    uint32_t* tmp = (uint32_t*)(H.ws + L.scan_tmp);
-    hipError_t e;
-    for (int shift = 0; shift < bits; shift += 8) {
+    uint32_t* sup = (uint32_t*)(H.ws + (bwd ? L.bwd_sup : L.sup));
+    const int64_t sup_pass = sort_super_rows(bwd ? L.t_btile : L.t_stile, L.n) * 256;
+    const int passes = (bits + 7) / 8;
+    if (passes > kSortPasses) return hipErrorInvalidValue;
+    hipError_t e = fill_u32(sup, 0, sup_pass * passes, s);
+    if (e != hipSuccess) return e;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        uint32_t* sp = sup + sup_pass * p;
         if (bwd) {
             hipLaunchKernelGGL(radix_hist_kernel<true>, dim3((unsigned)blocks), dim3(kSortBlock), 0, s, H.dev,
-                               (const uint32_t*)kin, shift, hist);
-        } else {
-            hipLaunchKernelGGL(radix_hist_kernel<false>, dim3((unsigned)blocks), dim3(kSortBlock), 0, s, H.dev,
-                               (const uint32_t*)kin, shift, hist);
-        }
-        if ((e = exclusive_scan_u32(hist, hist, 256 * blocks, tmp, nullptr, s)) != hipSuccess) return e;
-        if (bwd) {
+                               (const uint32_t*)kin, shift, hist, sp);
             hipLaunchKernelGGL(radix_scatter_kernel<true>, dim3((unsigned)blocks), dim3(kSortBlock), 0, s, H.dev,
                                (const uint32_t*)kin, (const uint32_t*)vin, kout, vout, shift,
-                               (const uint32_t*)hist);
+                               (const uint32_t*)hist, (const uint32_t*)sp);
         } else {
+            hipLaunchKernelGGL(radix_hist_kernel<false>, dim3((unsigned)blocks), dim3(kSortBlock), 0, s, H.dev,
+                               (const uint32_t*)kin, shift, hist, sp);
             hipLaunchKernelGGL(radix_scatter_kernel<false>, dim3((unsigned)blocks), dim3(kSortBlock), 0, s, H.dev,
                                (const uint32_t*)kin, (const uint32_t*)vin, kout, vout, shift,
-                               (const uint32_t*)hist);
+                               (const uint32_t*)hist, (const uint32_t*)sp);
         }
         std::swap(kin, kout);
         std::swap(vin, vout);
@@ -644,6 +803,7 @@ hipError_t launch_bvh_build(const BatchHost& H, hipStream_t s) {
     uint32_t* k0 = (uint32_t*)(ws + L.keys0);
     uint32_t* v0 = (uint32_t*)(ws + L.vals0);
     BvhNode* nodes = (BvhNode*)(ws + L.nodes);
+    BvhNodeC* nodes_c = (BvhNodeC*)(ws + L.nodes_c);
     Leaf* leaves = (Leaf*)(ws + L.leaves);
     int32_t* np = (int32_t*)(ws + L.node_parent);
     int32_t* lp = (int32_t*)(ws + L.leaf_parent);
@@ -664,7 +824,7 @@ hipError_t launch_bvh_build(const BatchHost& H, hipStream_t s) {
     // 30-bit keys take four 8-bit passes: the sorted arrays are back in keys0 / vals0
     if (H.blocks(kGNode) > 0) {
         hipLaunchKernelGGL(karras_kernel, dim3((unsigned)H.blocks(kGNode)), dim3(kBlock), 0, s, H.dev,
-                           (const uint32_t*)k0, nodes, np, lp, range);
+                           (const uint32_t*)k0, nodes_c, np, lp, range);
         if ((e = fill_u32(cnt, 0, L.t_node, s)) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(leaf_pack_kernel, dim3((unsigned)H.blocks(kGHiF)), dim3(kBlock), 0, s, H.dev,
@@ -680,9 +840,9 @@ hipError_t launch_bvh_build(const BatchHost& H, hipStream_t s) {
         for (int a = 0; a < L.n; ++a) grid += H.A[a].nhf / (kTreelet / 2) + 1;
         grid = std::min<int64_t>(grid, 2048);
         hipLaunchKernelGGL(treelet_refit_kernel, dim3((unsigned)grid), dim3(kRefitBlock), 0, s, H.dev,
-                           (const Leaf*)leaves, nodes, (const int32_t*)np, (const int32_t*)lp,
+                           (const Leaf*)leaves, nodes, nodes_c, (const int32_t*)np, (const int32_t*)lp,
                            (const int4*)tlist, frontier);
-        hipLaunchKernelGGL(refit_top_kernel, dim3((unsigned)L.n), dim3(kTopBlock), 0, s, H.dev, nodes,
+        hipLaunchKernelGGL(refit_top_kernel, dim3((unsigned)L.n), dim3(kTopBlock), 0, s, H.dev, nodes, nodes_c,
                            (const int32_t*)np, (const int32_t*)frontier, cnt);
     }
     return hipGetLastError();

@@ -282,7 +282,7 @@ struct TravArgs {
     const float4* lo_n;    // concatenated lo vertex normals
     const float4* face_t;  // concatenated per-face tangents
     const int4* face_uv;   // concatenated snapped UVs + flags
-    const BvhNode* nodes;  // concatenated trees
+    const BvhNodeC* nodes;  // concatenated trees
     const Leaf* leaves;
     Hit* hits;             // optional, by global ray index
     int32_t* spill;        // [kMaxDepth][spill_lanes]
@@ -291,7 +291,7 @@ struct TravArgs {
 
 // What the inner loop needs of an asset.
 struct TreeView {
-    const BvhNode* nodes;
+    const BvhNodeC* nodes;
     const Leaf* leaves;
     float max_dist, w, inv_w;
     int32_t root;      // root ref, or kEmpty when there is no triangle
@@ -433,6 +433,31 @@ struct LaneStack {
     }
 };
 
+// The child boxes and references of a compressed node (two 16-B loads).
+struct NodeBoxes {
+    float3 llo, lhi, rlo, rhi;
+    int32_t left, right;
+};
+
+__device__ __forceinline__ float byte_f(uint32_t w, int k) { return (float)((w >> (8 * k)) & 0xFFu); }
+
+__device__ __forceinline__ NodeBoxes load_node(const BvhNodeC* nd) {
+    const float4 a = nd->a;
+    const uint4 q = nd->q;
+    const uint32_t meta = __float_as_uint(a.w);
+    const float sx = __uint_as_float((meta & 0xFFu) << 23), sy = __uint_as_float(((meta >> 8) & 0xFFu) << 23),
+                sz = __uint_as_float(((meta >> 16) & 0xFFu) << 23);
+    NodeBoxes n;
+    n.llo = f3(fmaf(byte_f(q.x, 0), sx, a.x), fmaf(byte_f(q.x, 1), sy, a.y), fmaf(byte_f(q.x, 2), sz, a.z));
+    n.lhi = f3(fmaf(byte_f(q.x, 3), sx, a.x), fmaf(byte_f(q.y, 0), sy, a.y), fmaf(byte_f(q.y, 1), sz, a.z));
+    n.rlo = f3(fmaf(byte_f(q.y, 2), sx, a.x), fmaf(byte_f(q.y, 3), sy, a.y), fmaf(byte_f(q.z, 0), sz, a.z));
+    n.rhi = f3(fmaf(byte_f(q.z, 1), sx, a.x), fmaf(byte_f(q.z, 2), sy, a.y), fmaf(byte_f(q.z, 3), sz, a.z));
+    const int32_t g = (int32_t)(q.w & kChildIndex);
+    n.left = (q.w & kChildLeafL) ? ~g : g;
+    n.right = (q.w & kChildLeafR) ? ~(g + 1) : g + 1;
+    return n;
+}
+
 // One traversal step of a lane at an internal node: test both child boxes, go
 // to the nearer hit and push the other, or pop when neither is hit.  Returns
 // the next node (internal, leaf, or kEmpty: the ray is done).
@@ -440,12 +465,11 @@ template <int BLOCK, int STACK, bool COUNT>
 __device__ __forceinline__ int32_t inner_step(const TreeView& tv, uint32_t* status, int32_t node,
                                               const RayT& R, const Best& best, LaneStack<BLOCK, STACK>& st,
                                               int tid, unsigned long long& c_box) {
-    const BvhNode* nd = tv.nodes + node;
-    float4 na = nd->a, nb = nd->b, nc = nd->c;
-    int4 ref = nd->ref;
+    const NodeBoxes nb = load_node(tv.nodes + node);
+    const int4 ref = make_int4(nb.left, nb.right, 0, 0);
     float mL, mR;
-    bool hL = box_test(R, f3(na.x, na.y, na.z), f3(na.w, nb.x, nb.y), best.bound, &mL);
-    bool hR = box_test(R, f3(nb.z, nb.w, nc.x), f3(nc.y, nc.z, nc.w), best.bound, &mR);
+    bool hL = box_test(R, nb.llo, nb.lhi, best.bound, &mL);
+    bool hR = box_test(R, nb.rlo, nb.rhi, best.bound, &mR);
     if (COUNT) c_box += 2;
     int32_t next = kEmpty;
     if (hL && hR) {
@@ -476,12 +500,11 @@ template <int BLOCK, int STACK, bool COUNT>
 __device__ __forceinline__ int32_t inner_step_pt(const TreeView& tv, uint32_t* status, int32_t node,
                                                  float3 p, const Best& best, LaneStack<BLOCK, STACK>& st,
                                                  int tid, unsigned long long& c_box) {
-    const BvhNode* nd = tv.nodes + node;
-    float4 na = nd->a, nb = nd->b, nc = nd->c;
-    int4 ref = nd->ref;
+    const NodeBoxes nb = load_node(tv.nodes + node);
+    const int4 ref = make_int4(nb.left, nb.right, 0, 0);
     float dL, dR;
-    bool hL = box_dist_test(p, f3(na.x, na.y, na.z), f3(na.w, nb.x, nb.y), best.bound, &dL);
-    bool hR = box_dist_test(p, f3(nb.z, nb.w, nc.x), f3(nc.y, nc.z, nc.w), best.bound, &dR);
+    bool hL = box_dist_test(p, nb.llo, nb.lhi, best.bound, &dL);
+    bool hR = box_dist_test(p, nb.rlo, nb.rhi, best.bound, &dR);
     if (COUNT) c_box += 2;
     int32_t next = kEmpty;
     if (hL && hR) {
@@ -804,7 +827,7 @@ hipError_t launch_traverse(const BatchHost& H, const TravConfig& cfg, hipStream_
     a.lo_n = (const float4*)(ws + L.lo_n);
     a.face_t = (const float4*)(ws + L.face_t);
     a.face_uv = (const int4*)(ws + L.face_uv);
-    a.nodes = (const BvhNode*)(ws + L.nodes);
+    a.nodes = (const BvhNodeC*)(ws + L.nodes_c);
     a.leaves = (const Leaf*)(ws + L.leaves);
     a.hits = L.save ? (Hit*)(ws + L.hits) : nullptr;
     a.spill = (int32_t*)(ws + L.spill);

@@ -244,6 +244,25 @@ def test_lo_normals_and_frames(B, oracle_lib):
     assert angle_deg(ft[:, :3], T).max() < 1e-4
 
 
+def decode_nodes(raw):
+    """Compressed BVH nodes [n, 8] int32 -> decoded child boxes lo, hi [n, 2, 3]
+    (float32 arithmetic: the byte times the power-of-two step is exact, the
+    add rounds once, as the kernels' fmaf), child refs [n, 2] and the per-axis
+    steps [n, 3]."""
+    o = raw[:, 0:3].copy().view(np.float32)
+    meta = raw[:, 3].copy().view(np.uint32)
+    step = np.stack([((meta >> (8 * k)) & 0xFF) << 23 for k in range(3)], 1).astype(np.uint32).view(np.float32)
+    qb = raw[:, 4:7].copy().view(np.uint8).reshape(-1, 12).astype(np.float32)
+    planes = (qb.reshape(-1, 4, 3) * step[:, None, :] + o[:, None, :]).astype(np.float32)
+    lo = np.stack([planes[:, 0], planes[:, 2]], 1)
+    hi = np.stack([planes[:, 1], planes[:, 3]], 1)
+    child = raw[:, 7].copy().view(np.uint32).astype(np.int64)
+    g = (child & ((1 << 30) - 1)).astype(np.int32)
+    left = np.where((child >> 30) & 1, ~g, g)
+    right = np.where((child >> 31) & 1, ~(g + 1), g + 1)
+    return lo, hi, np.stack([left, right], 1).astype(np.int32), step.astype(np.float64)
+
+
 @pytest.mark.parametrize("hi_level", [6, 8])
 def test_sort_is_stable_sort_and_tree_invariants(B, hi_level):
     a = _noise_asset(hi_level, 2, 64, seed=2)
@@ -259,44 +278,60 @@ def test_sort_is_stable_sort_and_tree_invariants(B, hi_level):
     eq = keys[1:] == keys[:-1]
     assert np.all(vals[1:][eq] > vals[:-1][eq])          # stable: index order on equal keys
     assert np.array_equal(np.sort(vals), np.arange(nf))   # a permutation
-    nodes = r.view(B.VIEW_NODES).view(torch.float32).cpu().numpy().reshape(-1, 16)
-    refs = nodes[:, 12:14].copy().view(np.int32)
+    raw = r.view(B.VIEW_NODES).view(torch.int32).cpu().numpy().reshape(-1, 8)
+    lo3, hi3, refs, step = decode_nodes(raw)
     leaves = r.view(B.VIEW_LEAVES).view(torch.float32).cpu().numpy().reshape(-1, 12)
     # every leaf and every non-root internal node is referenced exactly once
     lf = refs[refs < 0]
     assert np.array_equal(np.sort(~lf), np.arange(nf))
     inn = refs[refs >= 0]
     assert np.array_equal(np.sort(inn), np.arange(1, nf - 1))
-    # child boxes enclose their triangles / grandchildren boxes
     tri = leaves[:, :9].reshape(-1, 3, 3)
     tlo, thi = tri.min(1).astype(np.float64), tri.max(1).astype(np.float64)
     ids = leaves[:, 9].copy().view(np.int32)
     assert np.array_equal(np.sort(ids), np.arange(nf))
     assert np.array_equal(tri, a.hi_V[a.hi_F[ids]])
-    box = lambda k, side: (nodes[k, 6 * side:6 * side + 3], nodes[k, 6 * side + 3:6 * side + 6])
-    assert np.isfinite(nodes[:, :12]).all()
-    # leaf boxes are the triangle bounds widened for the edge tolerance of the
-    # hit rule (barycentric weights down to -2^-14): by 3 * 2^-14 of the extent
-    # at least, and not much more
+    assert np.isfinite(lo3).all() and np.isfinite(hi3).all()  # every node written (poisoned workspace)
+    # the boxes a leaf must have: the triangle bounds widened for the hit
+    # rule's edge tolerance (barycentric weights down to -2^-14) by 3 * 2^-14
+    # of the extent; subtree boxes are their unions, bottom-up over the levels
     eps = 1.0 / 16384.0
-    ext = (thi - tlo).astype(np.float64)
-    for side in (0, 1):
-        lo = nodes[:, 6 * side:6 * side + 3].astype(np.float64)
-        hi = nodes[:, 6 * side + 3:6 * side + 6].astype(np.float64)
-        c = refs[:, side]
-        lf_ = c < 0
-        li = ~c[lf_]
-        assert np.all(lo[lf_] <= tlo[li] - 3 * eps * ext[li])
-        assert np.all(hi[lf_] >= thi[li] + 3 * eps * ext[li])
-        slack = 6 * eps * ext[li] + 1e-6 * np.maximum(np.abs(tlo[li]), np.abs(thi[li]))
-        assert np.all(lo[lf_] >= tlo[li] - slack) and np.all(hi[lf_] <= thi[li] + slack)
-        ci = c[~lf_]
-        clo = np.minimum(nodes[ci, 0:3], nodes[ci, 6:9])
-        chi = np.maximum(nodes[ci, 3:6], nodes[ci, 9:12])
-        assert np.array_equal(nodes[~lf_, 6 * side:6 * side + 3], clo)
-        assert np.array_equal(nodes[~lf_, 6 * side + 3:6 * side + 6], chi)
-    root_lo = np.minimum(nodes[0, 0:3], nodes[0, 6:9])
-    assert np.all(root_lo <= a.hi_V[a.hi_F].reshape(-1, 3).min(0))
+    ext = thi - tlo
+    need_lo, need_hi = tlo - 3 * eps * ext, thi + 3 * eps * ext
+    levels = [np.array([0])]
+    while True:
+        c = refs[levels[-1]].reshape(-1)
+        c = c[c >= 0]
+        if c.size == 0:
+            break
+        levels.append(c)
+    assert sum(x.size for x in levels) == nf - 1
+    sub_lo = np.zeros((nf - 1, 3))
+    sub_hi = np.zeros((nf - 1, 3))
+
+    def child_box(c):
+        blo = np.where((c < 0)[:, None], need_lo[np.where(c < 0, ~c, 0)], sub_lo[np.maximum(c, 0)])
+        bhi = np.where((c < 0)[:, None], need_hi[np.where(c < 0, ~c, 0)], sub_hi[np.maximum(c, 0)])
+        return blo, bhi
+
+    for lv in reversed(levels):
+        for side in (0, 1):
+            blo, bhi = child_box(refs[lv, side])
+            # the decoded child box contains every triangle below it, widened
+            assert np.all(lo3[lv, side] <= blo) and np.all(hi3[lv, side] >= bhi)
+            # and is tight to a quantisation step (plus the kernel's own
+            # widening of a few 2^-14 of the extent and ulps)
+            slack = step[lv] + 4 * eps * (bhi - blo) + 1e-6 * np.maximum(np.abs(blo), np.abs(bhi)) + 1e-30
+            assert np.all(lo3[lv, side] >= blo - slack) and np.all(hi3[lv, side] <= bhi + slack)
+        l0, h0 = child_box(refs[lv, 0])
+        l1, h1 = child_box(refs[lv, 1])
+        sub_lo[lv] = np.minimum(l0, l1)
+        sub_hi[lv] = np.maximum(h0, h1)
+        # the step is about the smallest power of two with 255 steps spanning
+        # the node's box (one doubling more where the rounded end falls short)
+        span = np.maximum(h0, h1) - np.minimum(l0, l1)
+        assert np.all(step[lv] <= np.maximum(4.04 * span / 255, 2.0 ** -125))
+    assert np.all(sub_lo[0] <= a.hi_V[a.hi_F].reshape(-1, 3).min(0))
 
 
 def test_axis_parallel_rays_prune(B):
