@@ -333,9 +333,24 @@ __global__ __launch_bounds__(256) void zero_grad_hi_kernel(Batch B) {
     st3(out, v, f3(0.f, 0.f, 0.f));
 }
 
-// Sorted (vertex, item) pairs of an asset: the first item of each vertex's
-// run sums the run in order (items are ascending within a run: the sort is
-// stable).  Waves take (asset, 64-ray batch) items: 192 pairs each.
+// The term of sorted pair j: the hit's barycentric weight of corner k times
+// the ray's adjoint of the interpolated high-poly normal (item = 3 ray + k).
+__device__ __forceinline__ float3 hiN_term(const uint32_t* __restrict__ vals, const Hit* __restrict__ hits,
+                                           const RayGrad* __restrict__ rg, int64_t j) {
+    const uint32_t item = vals[j];
+    const uint32_t r = item / 3, k = item - 3 * r;
+    const Hit h = hits[r];
+    const float beta = k == 0 ? 1.0f - h.beta1 - h.beta2 : (k == 1 ? h.beta1 : h.beta2);
+    return mul3(rg[r].hb, beta);
+}
+
+// Sorted (vertex, item) pairs of an asset, 64 at a time per wave: each lane
+// forms its pair's term, a segmented scan over the wave adds the terms of
+// each vertex's run (items ascending within a run: the sort is stable) in a
+// fixed tree order, and the lane at the run's end writes the sum.  A run
+// that goes on past the wave's 64 pairs is finished by that lane, adding the
+// rest in pair order; the waves holding the rest skip it.  Waves take
+// (asset, 64-ray batch) items: 192 pairs each.
 __global__ __launch_bounds__(256) void bwd_hiN_kernel(Batch B, const uint32_t* __restrict__ keys,
                                                       const uint32_t* __restrict__ vals,
                                                       const Hit* __restrict__ hits,
@@ -352,18 +367,36 @@ __global__ __launch_bounds__(256) void bwd_hiN_kernel(Batch B, const uint32_t* _
         const uint32_t nhv = (uint32_t)B.A[it.a].nhv;
         const int64_t lo = 3 * it.begin, hi = 3 * it.end;
         for (int k3 = 0; k3 < 3; ++k3) {
-            const int64_t i = 3 * it.r + 64 * k3 + lane;
-            if (i >= hi) continue;
-            const uint32_t key = keys[i];
-            if (key >= nhv) continue;
-            if (i > lo && keys[i - 1] == key) continue;
+            const int64_t i0 = 3 * it.r + 64 * k3;  // the wave's first pair
+            if (i0 >= hi) break;
+            const int64_t i = i0 + lane;
+            const bool in = i < hi;
+            const uint32_t key = in ? keys[i] : 0xFFFFFFFFu;  // past the end: a run of its own
             float3 g = f3(0.f, 0.f, 0.f);
-            for (int64_t j = i; j < hi && keys[j] == key; ++j) {
-                const uint32_t item = vals[j];
-                const uint32_t r = item / 3, k = item - 3 * r;
-                const Hit h = hits[r];
-                const float beta = k == 0 ? 1.0f - h.beta1 - h.beta2 : (k == 1 ? h.beta1 : h.beta2);
-                g = add3(g, mul3(rg[r].hb, beta));
+            if (in && key < nhv) g = hiN_term(vals, hits, rg, i);
+            const uint32_t prev = __shfl_up(key, 1, 64);
+            const uint32_t next = __shfl_down(key, 1, 64);
+            bool head = lane == 0 || prev != key;
+            // lanes of lane 0's run; it started before this wave when the pair
+            // before i0 has the same key
+            const uint64_t heads = __ballot(lane > 0 && prev != key);
+            const int first_change = heads ? __ffsll((long long)heads) - 1 : 64;
+            const bool cont_in = i0 > lo && keys[i0 - 1] == __shfl(key, 0, 64);
+            // segmented inclusive scan: (v1, f1) then (v2, f2) -> (f2 ? v2 : v1 + v2, f1 | f2)
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const float ux = __shfl_up(g.x, o, 64), uy = __shfl_up(g.y, o, 64), uz = __shfl_up(g.z, o, 64);
+                const bool uh = __shfl_up((int)head, o, 64) != 0;
+                if (lane >= o) {
+                    if (!head) g = f3(ux + g.x, uy + g.y, uz + g.z);
+                    head = head || uh;
+                }
+            }
+            const bool run_end = lane == 63 || next != key;
+            if (!in || key >= nhv || !run_end) continue;
+            if (lane < first_change && cont_in) continue;  // an earlier wave's run
+            if (lane == 63) {
+                for (int64_t j = i0 + 64; j < hi && keys[j] == key; ++j) g = add3(g, hiN_term(vals, hits, rg, j));
             }
             st3(grad_hi_N, key, g);
         }

@@ -370,19 +370,19 @@ __global__ __launch_bounds__(256) void dilate_kernel(Batch Bt, int pass, uint8_t
 // through pass d, so the tile (d >= k) is exact after k passes: the result is
 // bitwise that of the fill + per-pass launches.
 constexpr int kFinishBlock = 256;
-constexpr int kRegionMax = kFinishTile + 2 * kMaxFusedPasses;
 constexpr uint8_t kOutside = 254;  // outside the image: never read, never filled
 
-__global__ __launch_bounds__(kFinishBlock) void finish_kernel(Batch Bt, int passes,
-                                                              const uint32_t* __restrict__ facemap_all) {
-    __shared__ float s_map[kRegionMax * kRegionMax][3];
-    __shared__ uint8_t s_lvl[kRegionMax * kRegionMax];
+template <int PASSES>
+__global__ __launch_bounds__(kFinishBlock) void finish_kernel(Batch Bt, const uint32_t* __restrict__ facemap_all) {
+    constexpr int passes = PASSES;
+    constexpr int32_t R = kFinishTile + 2 * PASSES;  // region side: divisions by it are by a constant
+    __shared__ float s_map[R * R][3];
+    __shared__ uint8_t s_lvl[R * R];
     int64_t lt;
     const AssetDev& As = Bt.A[block_asset(Bt, kGTile, blockIdx.x, &lt)];
     const int32_t res = As.res;
     const int32_t tiles_x = (res + kFinishTile - 1) / kFinishTile;
     const int32_t ti = (int32_t)(lt / tiles_x) * kFinishTile, tj = (int32_t)(lt % tiles_x) * kFinishTile;
-    const int32_t R = kFinishTile + 2 * passes;
     const int32_t oi = ti - passes, oj = tj - passes;  // region origin
     const uint32_t* __restrict__ facemap = facemap_all + As.tex;
     const float* __restrict__ map = As.out_map;
@@ -538,8 +538,16 @@ hipError_t launch_fill_uncovered(const BatchHost& H, hipStream_t s) {
 hipError_t launch_dilate(const BatchHost& H, int passes, hipStream_t s) {
     if (passes <= kMaxFusedPasses) {
         if (H.blocks(kGTile) == 0) return hipSuccess;
-        hipLaunchKernelGGL(finish_kernel, dim3((unsigned)H.blocks(kGTile)), dim3(kFinishBlock), 0, s, H.dev,
-                           passes, (const uint32_t*)(H.ws + H.L.facemap));
+        const dim3 grid((unsigned)H.blocks(kGTile)), block(kFinishBlock);
+        const uint32_t* fm = (const uint32_t*)(H.ws + H.L.facemap);
+        switch (passes) {
+            case 0: hipLaunchKernelGGL(finish_kernel<0>, grid, block, 0, s, H.dev, fm); break;
+            case 1: hipLaunchKernelGGL(finish_kernel<1>, grid, block, 0, s, H.dev, fm); break;
+            case 2: hipLaunchKernelGGL(finish_kernel<2>, grid, block, 0, s, H.dev, fm); break;
+            case 3: hipLaunchKernelGGL(finish_kernel<3>, grid, block, 0, s, H.dev, fm); break;
+            default: hipLaunchKernelGGL(finish_kernel<4>, grid, block, 0, s, H.dev, fm); break;
+        }
+        static_assert(kMaxFusedPasses == 4, "one finish_kernel instance per fused pass count");
         return hipGetLastError();
     }
     hipError_t e = launch_fill_uncovered(H, s);
