@@ -21,6 +21,12 @@ paper's bake (Sec. 6.4 "Normal Map Baking"):
    (0,0,1) for misses / unreliable / uncovered texels;
 6. chart dilation.
 
+The hidden-face removal of Sec. 6.2 is here too: camera rays from viewpoints
+around the mesh, the first hit of each on the mesh (same triangle test, one
+sided), the per-face visibility mask, and the flood fill over shared edges
+gated by the face normals (``camera_rays``, ``first_hit``, ``visibility``,
+``flood_fill``; ``oracle.c`` states the readings).
+
 Parity unpinned: none of the paper's own quality numbers (its 50-asset
 benchmark) can be reproduced here; every other function has a pin in
 ``tests/test_oracle.py``.
@@ -314,3 +320,49 @@ def bake_adjoint(asset, ob, grad_map):
     _, _, hf, _ = face_frames(asset.lo_V, asset.lo_F, asset.lo_UV, asset.res, ok)
     gm = np.asarray(grad_map, np.float64).reshape(-1, 3)[tex]
     return adjoint(asset, face, ob.bary[tex], ob.hit[hit], hf[face], gm)
+
+
+# ---------------------------------------------------------------------------
+# Hidden-face removal (Sec. 6.2)
+# ---------------------------------------------------------------------------
+
+def camera_rays(eyes, target, tan_half, res):
+    """Origins and unit directions [n_views*res*res, 3] of every pixel's ray,
+    ray index (v res + i) res + j (readings in oracle.c)."""
+    eyes = _c(eyes, np.float32).reshape(-1, 3)
+    tg = _c(target, np.float64).reshape(3)
+    n = eyes.shape[0] * res * res
+    P = np.zeros((n, 3)); D = np.zeros((n, 3))
+    _call("orc_camera_rays", _p(eyes), C.c_int32(eyes.shape[0]), _p(tg), C.c_double(tan_half),
+          C.c_int32(res), _p(P), _p(D))
+    return P, D
+
+
+def first_hit(V, F, P, D, t_far, method="brute"):
+    """First hit id (-1: none) and t of each half-line, t in (0, t_far]."""
+    V = _c(V, np.float32); F = _c(F, np.int32); P = _c(P, np.float64); D = _c(D, np.float64)
+    n = P.shape[0]
+    ids = np.zeros(n, np.int32); t = np.zeros(n)
+    fn = "orc_first_hit_brute" if method == "brute" else "orc_first_hit_bvh"
+    _call(fn, _p(V), _p(F), C.c_int64(F.shape[0]), C.c_int64(n), _p(P), _p(D), C.c_double(t_far),
+          _p(ids), _p(t))
+    return ids, t
+
+
+def visibility(V, F, eyes, target, tan_half, res, t_far, method="bvh"):
+    """Per-ray first hits [n_views, res, res] and the per-face visibility mask."""
+    P, D = camera_rays(eyes, target, tan_half, res)
+    ids, t = first_hit(V, F, P, D, t_far, method)
+    vis = np.zeros(np.asarray(F).shape[0], bool)
+    vis[ids[ids >= 0]] = True
+    return ids.reshape(-1, res, res), t.reshape(-1, res, res), vis
+
+
+def flood_fill(V, F, seed):
+    """Exterior mask: the seeds and every face connected to one through shared
+    edges whose two faces' normals agree in direction."""
+    V = _c(V, np.float32); F = _c(F, np.int32); sd = _c(np.asarray(seed, bool), np.uint8)
+    ext = np.zeros(F.shape[0], np.uint8)
+    _call("orc_flood_fill", _p(V), C.c_int64(V.shape[0]), _p(F), C.c_int64(F.shape[0]), _p(sd), _p(ext))
+    return ext.astype(bool)
+

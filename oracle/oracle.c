@@ -17,6 +17,10 @@
  * the lower triangle index; the paper's own form, the closest point of the
  * high-poly surface within a distance bound, is the second query below.
  *
+ * The hidden-face removal of Sec. 6.2 (visibility rays from viewpoints around
+ * the mesh and a normal-gated flood fill over shared edges) reuses the same
+ * triangle test and BVH.
+ *
  * Everything is plain: brute force over every texel and every triangle,
  * FP64 arithmetic, no blocking or reordering beyond what the definitions say.
  * A separate, equally plain FP64 BVH (median split) answers the same query and
@@ -637,6 +641,207 @@ int orc_closest_check(const float *V, const int32_t *F, int64_t n, const double 
         double w[3];
         dist_out[r] = tri_closest(ld3d(P, r), V, F, g[r], w);
     }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Hidden-face removal (Sec. 6.2): visibility rays from viewpoints around    */
+/* the mesh, then a flood fill over shared edges gated by the face normals   */
+/* ------------------------------------------------------------------------ */
+/*
+ * Readings (the paper names the viewpoint count, the resolution and the
+ * rule, not the camera):
+ *   view v: a pinhole at eye_v looking at `target`; forward f = (target -
+ *     eye) / |target - eye|; helper axis a = the world axis with the smallest
+ *     |f_k| (the lowest k on ties); right r = (f x a) / |f x a|; up u = r x f;
+ *   pixel (i, j) of a res x res image: x = ((j + 1/2) 2 / res - 1) tan_half,
+ *     y = (1 - (i + 1/2) 2 / res) tan_half; the ray leaves the eye along
+ *     normalise(f + x r + y u);
+ *   first hit: the hit rule of the bake (edge tolerance EDGE_EPS) on the
+ *     half-line, t in (0, t_far], winner minimising (floor(t / w), index) with
+ *     w = t_far 2^-20; a face is visible when it is some ray's first hit;
+ *   flood fill: faces f and g are adjacent when they share two distinct vertex
+ *     indices; g joins the exterior from an exterior neighbour f when
+ *     n_f . n_g > 0, n = (V1 - V0) x (V2 - V0) evaluated in FP64 from the
+ *     float vertices in this order (x, y, z; no fused operations); seeds are
+ *     the visible faces.  The condition is symmetric, so the exterior is the
+ *     set of faces connected to a seed through such edges, whatever the order
+ *     of the traversal.
+ */
+
+/* Rays of every pixel of every view, ray index (v res + i) res + j. */
+int orc_camera_rays(const float *eyes, int32_t nviews, const double *target, double tan_half, int32_t res,
+                    double *P_out, double *D_out) {
+    for (int32_t v = 0; v < nviews; ++v) {
+        v3 e = ld3f(eyes, v), c = mk(target[0], target[1], target[2]);
+        v3 f = sub(c, e);
+        double lf = norm(f);
+        if (!(lf > 0)) return ORC_EINVAL;
+        f = scl(f, 1.0 / lf);
+        double af[3] = {fabs(f.x), fabs(f.y), fabs(f.z)};
+        int k = 0;
+        if (af[1] < af[k]) k = 1;
+        if (af[2] < af[k]) k = 2;
+        v3 a = mk(k == 0, k == 1, k == 2);
+        v3 r = cross(f, a);
+        r = scl(r, 1.0 / norm(r));
+        v3 u = cross(r, f);
+        for (int32_t i = 0; i < res; ++i) {
+            for (int32_t j = 0; j < res; ++j) {
+                double x = ((j + 0.5) * 2.0 / res - 1.0) * tan_half;
+                double y = (1.0 - (i + 0.5) * 2.0 / res) * tan_half;
+                v3 d = add(add(f, scl(r, x)), scl(u, y));
+                d = scl(d, 1.0 / norm(d));
+                int64_t q = ((int64_t)v * res + i) * res + j;
+                st3d(P_out, q, e);
+                st3d(D_out, q, d);
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/* First hit of each half-line by brute force over every triangle. */
+int orc_first_hit_brute(const float *V, const int32_t *F, int64_t nf, int64_t n, const double *P,
+                        const double *D, double t_far, int32_t *id_out, double *t_out) {
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t r = 0; r < n; ++r) {
+        int32_t best = -1;
+        double bt = 0;
+        v3 p = ld3d(P, r), d = ld3d(D, r);
+        for (int64_t g = 0; g < nf; ++g) {
+            double t, beta[3];
+            if (!tri_hit(p, d, V, F, g, &t, beta)) continue;
+            if (!(t > 0) || t > t_far) continue;
+            if (best < 0 || better(t, g, bt, best, t_far)) { best = (int32_t)g; bt = t; }
+        }
+        id_out[r] = best;
+        if (t_out) t_out[r] = best >= 0 ? bt : 0;
+    }
+    return ORC_OK;
+}
+
+/* The same on the FP64 BVH: a node is skipped when its interval ends before
+ * t = 0 or starts past the upper end of the best key's bin. */
+static int32_t bvh_first_hit(const bvh *B, const float *V, const int32_t *F, v3 p, v3 d, double t_far,
+                             double *t_out) {
+    int64_t stack[256];
+    int sp = 0;
+    stack[sp++] = 0;
+    int32_t best = -1;
+    double bt = 0, bound = t_far * (1.0 + 1e-12);
+    const double w = t_far * ldexp(1.0, -T_QUANT_BITS);
+    while (sp > 0) {
+        const bnode *nd = &B->nodes[stack[--sp]];
+        double t0, t1;
+        if (!box_interval(nd, p, d, &t0, &t1)) continue;
+        if (t0 > bound || t1 < 0) continue;
+        if (nd->left < 0) {
+            for (int64_t i = nd->first; i < nd->first + nd->count; ++i) {
+                int64_t g = B->perm[i];
+                double t, beta[3];
+                if (!tri_hit(p, d, V, F, g, &t, beta)) continue;
+                if (!(t > 0) || t > t_far) continue;
+                if (best < 0 || better(t, g, bt, best, t_far)) {
+                    best = (int32_t)g; bt = t;
+                    bound = (double)(tkey(t, t_far) + 1) * w * (1.0 + 1e-12);
+                }
+            }
+        } else {
+            if (sp + 2 > 256) return -100;
+            stack[sp++] = nd->right;
+            stack[sp++] = nd->left;
+        }
+    }
+    *t_out = bt;
+    return best;
+}
+
+int orc_first_hit_bvh(const float *V, const int32_t *F, int64_t nf, int64_t n, const double *P, const double *D,
+                      double t_far, int32_t *id_out, double *t_out) {
+    bvh B;
+    bvh_make(&B, V, F, nf);
+    int err = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(| : err)
+    for (int64_t r = 0; r < n; ++r) {
+        double t = 0;
+        int32_t id = -1;
+        if (nf > 0) {
+            id = bvh_first_hit(&B, V, F, ld3d(P, r), ld3d(D, r), t_far, &t);
+            if (id == -100) { err = 1; id = -1; }
+        }
+        id_out[r] = id;
+        if (t_out) t_out[r] = id >= 0 ? t : 0;
+    }
+    bvh_release(&B);
+    return err ? ORC_EINVAL : ORC_OK;
+}
+
+/* Unnormalised face normal (V1 - V0) x (V2 - V0) from the float vertices. */
+static v3 face_normal(const float *V, const int32_t *F, int64_t f) {
+    v3 a = ld3f(V, F[3 * f]), b = ld3f(V, F[3 * f + 1]), c = ld3f(V, F[3 * f + 2]);
+    return cross(sub(b, a), sub(c, a));
+}
+
+/* Number of distinct vertex indices faces f and g have in common. */
+static int shared_vertices(const int32_t *F, int64_t f, int64_t g) {
+    int n = 0;
+    for (int i = 0; i < 3; ++i) {
+        int32_t x = F[3 * f + i];
+        int dup = 0;
+        for (int k = 0; k < i; ++k) dup |= F[3 * f + k] == x;
+        if (dup) continue;
+        if (F[3 * g] == x || F[3 * g + 1] == x || F[3 * g + 2] == x) ++n;
+    }
+    return n;
+}
+
+/* Breadth-first flood fill from the seed faces (ext_out = 1 for the seeds and
+ * every face reached).  Faces are found through per-vertex face lists. */
+int orc_flood_fill(const float *V, int64_t nv, const int32_t *F, int64_t nf, const uint8_t *seed,
+                   uint8_t *ext_out) {
+    int64_t *deg = (int64_t *)calloc((size_t)nv + 1, sizeof(int64_t));
+    int64_t *lst = (int64_t *)malloc(sizeof(int64_t) * (size_t)(3 * nf + 1));
+    int64_t *fill = (int64_t *)calloc((size_t)nv + 1, sizeof(int64_t));
+    int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nf + 1));
+    if (!deg || !lst || !fill || !queue) { free(deg); free(lst); free(fill); free(queue); return ORC_EINVAL; }
+    for (int64_t f = 0; f < nf; ++f)
+        for (int i = 0; i < 3; ++i) {
+            int32_t x = F[3 * f + i];
+            if (x < 0 || x >= nv) { free(deg); free(lst); free(fill); free(queue); return ORC_EINVAL; }
+            int dup = 0;
+            for (int k = 0; k < i; ++k) dup |= F[3 * f + k] == x;
+            if (!dup) deg[x + 1]++;
+        }
+    for (int64_t v = 0; v < nv; ++v) deg[v + 1] += deg[v];
+    for (int64_t f = 0; f < nf; ++f)
+        for (int i = 0; i < 3; ++i) {
+            int32_t x = F[3 * f + i];
+            int dup = 0;
+            for (int k = 0; k < i; ++k) dup |= F[3 * f + k] == x;
+            if (!dup) lst[deg[x] + fill[x]++] = f;
+        }
+    int64_t head = 0, tail = 0;
+    for (int64_t f = 0; f < nf; ++f) {
+        ext_out[f] = seed[f] ? 1 : 0;
+        if (seed[f]) queue[tail++] = f;
+    }
+    while (head < tail) {
+        int64_t f = queue[head++];
+        v3 nf_ = face_normal(V, F, f);
+        for (int i = 0; i < 3; ++i) {
+            int32_t x = F[3 * f + i];
+            for (int64_t k = deg[x]; k < deg[x + 1]; ++k) {
+                int64_t g = lst[k];
+                if (g == f || ext_out[g] || shared_vertices(F, f, g) < 2) continue;
+                if (dot(nf_, face_normal(V, F, g)) > 0) {
+                    ext_out[g] = 1;
+                    queue[tail++] = g;
+                }
+            }
+        }
+    }
+    free(deg); free(lst); free(fill); free(queue);
     return ORC_OK;
 }
 

@@ -282,6 +282,34 @@ def face_grid_atlas(n_faces: int, res: int, pad_texels: float = 2.0) -> np.ndarr
     return (uv / res).astype(np.float32)
 
 
+def sphere_viewpoints(n: int, center, radius: float) -> np.ndarray:
+    """n points spread over the sphere of the given centre and radius
+    (Fibonacci spiral: z_k = 1 - (2k + 1)/n, longitude k times the golden
+    angle), float32 [n, 3]: camera positions around a mesh."""
+    k = np.arange(n, dtype=np.float64)
+    z = 1.0 - (2.0 * k + 1.0) / n
+    rho = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    phi = k * math.pi * (3.0 - math.sqrt(5.0))
+    P = np.stack([rho * np.cos(phi), rho * np.sin(phi), z], 1) * radius + np.asarray(center, np.float64)
+    return P.astype(np.float32)
+
+
+def hidden_face_mesh(outer_level: int = 5, inner_level: int = 3, inner_scale: float = 0.55, seed: int = 7):
+    """A closed noise-displaced shell (icosphere outer_level) enclosing a
+    smaller sphere (icosphere inner_level) that no exterior viewpoint sees:
+    20,480 + 1,280 = 21,760 faces at the defaults, the size of the generated
+    meshes the hidden-face pass runs on.  Returns float32 V, int32 F and the
+    number of shell faces (the shell's faces come first)."""
+    Vo, Fo = icosphere(outer_level)
+    U = unit_directions(Vo)
+    Vo = displace(U, noise_radius(U, seed, 4, 0.03))
+    Vi, Fi = icosphere(inner_level)
+    Vi = (Vi * inner_scale).astype(np.float32)
+    V = np.concatenate([Vo.astype(np.float32), Vi])
+    F = np.concatenate([Fo, Fi + Vo.shape[0]]).astype(np.int32)
+    return V, F, Fo.shape[0]
+
+
 def decimate(V: np.ndarray, F: np.ndarray, n_target: int, seed: int):
     """Delete uniformly random faces (seeded) down to n_target, then drop
     unreferenced vertices keeping the order of the rest."""

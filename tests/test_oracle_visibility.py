@@ -1,0 +1,173 @@
+"""Pins of the oracle's hidden-face removal (Sec. 6.2): camera rays against
+their closed form, first hits on planes against the ray-plane intersection,
+occlusion, convex and nested meshes, brute force against the independent BVH,
+and the normal-gated flood fill on hand-built strips, books and spheres."""
+import math
+
+import numpy as np
+import pytest
+
+from planes import grid, grid_cell_triangle
+from synth import meshes as M
+
+TAN30 = math.tan(math.radians(30.0))
+
+
+def test_camera_rays_closed_form(oracle_lib):
+    eye = np.array([[0.3, -0.2, 2.5]], np.float32)
+    target = eye[0].astype(np.float64) * [1, 1, 0]  # straight down: forward = -z exactly
+    res = 8
+    P, D = oracle_lib.camera_rays(eye, target, TAN30, res)
+    assert np.allclose(P, eye.astype(np.float64), atol=0)
+    assert np.allclose(np.linalg.norm(D, axis=1), 1.0, atol=1e-15)
+    D = D.reshape(res, res, 3)
+    f = np.array([0.0, 0.0, -1.0])
+    # pixels mirrored through the image centre: their directions are
+    # symmetric about the forward axis
+    s = D + D[::-1, ::-1]
+    assert np.allclose(np.cross(s.reshape(-1, 3), f), 0.0, atol=1e-15)
+    # angle to the forward axis: tan = |(x, y)| with x, y = (2 (k + 1/2) / res - 1) tan_half
+    c = (2 * (np.arange(res) + 0.5) / res - 1) * TAN30
+    tan_expected = np.sqrt(c[None, :] ** 2 + c[:, None] ** 2)
+    cosang = D @ f
+    assert np.allclose(np.tan(np.arccos(np.clip(cosang, -1, 1))), tan_expected, atol=1e-12)
+    # the frame: helper axis x (|f_x| = |f_y| = 0 -> lowest index), right =
+    # f x (1,0,0) = (0,-1,0), up = right x f = (1,0,0); pixel (0, 0) is at
+    # x = -(1 - 1/res) tan_half along right and +(1 - 1/res) tan_half along up
+    a = (1 - 1 / res) * TAN30
+    d00 = np.array([a, a, -1.0]) / math.sqrt(1 + 2 * a * a)
+    assert np.allclose(D[0, 0], d00, atol=1e-15)
+
+
+def test_plane_first_hit_closed_form(oracle_lib):
+    """Plane z = 0 as an n x n grid over [0, 1]^2 seen from above: each ray
+    meets it at t = -e_z / d_z in the grid triangle containing e + t d."""
+    n = 16
+    V, F = grid(n)
+    eye = np.array([[0.43, 0.61, 1.7]], np.float32)
+    res = 48
+    P, D = oracle_lib.camera_rays(eye, eye[0].astype(np.float64) * [1, 1, 0], math.tan(math.radians(12)), res)
+    ids, t = oracle_lib.first_hit(V, F, P, D, 10.0)
+    te = -P[:, 2] / D[:, 2]
+    q = P + te[:, None] * D
+    inside = (q[:, 0] > 0) & (q[:, 0] < 1) & (q[:, 1] > 0) & (q[:, 1] < 1)
+    assert inside.all()
+    # margins from cell borders and the diagonal (a near-tie takes the lower index)
+    fx, fy = q[:, 0] * n % 1, q[:, 1] * n % 1
+    clear = np.minimum.reduce([fx, 1 - fx, fy, 1 - fy, np.abs(fx - fy)]) > 1e-6
+    assert clear.sum() > 0.95 * clear.size
+    assert np.array_equal(ids[clear], grid_cell_triangle(q[clear, 0], q[clear, 1], n))
+    assert np.abs(t - te).max() < 1e-12 + 10.0 * 2.0 ** -20
+
+
+def test_occluded_plane_is_not_visible(oracle_lib):
+    """Two parallel squares: the one farther from the camera is fully behind
+    the nearer one and gets no first hit; from the other side the roles swap."""
+    n = 6
+    V1, F1 = grid(n, z=lambda x, y: 0.0 * x)
+    V2, F2 = grid(n, z=lambda x, y: 0.0 * x - 0.5)
+    V = np.concatenate([V1, V2])
+    F = np.concatenate([F1, F2 + V1.shape[0]]).astype(np.int32)
+    tan_half = math.tan(math.radians(8))
+    for z, front in ((2.0, 0), (-2.5, 1)):
+        ids, _, vis = oracle_lib.visibility(V, F, np.array([[0.5, 0.5, z]], np.float32), [0.5, 0.5, -0.25],
+                                            tan_half, 32, 10.0, method="brute")
+        nf = F1.shape[0]
+        assert (ids >= 0).all()
+        assert vis[front * nf:(front + 1) * nf].any() and not vis[(1 - front) * nf:(2 - front) * nf].any()
+
+
+def test_convex_mesh_all_visible_and_nested_sphere_hidden(oracle_lib):
+    Vo, Fo = M.icosphere(2)
+    Vi, Fi = M.icosphere(1)
+    V = np.concatenate([Vo, 0.5 * Vi]).astype(np.float32)
+    F = np.concatenate([Fo, Fi + Vo.shape[0]]).astype(np.int32)
+    eyes = M.sphere_viewpoints(32, [0, 0, 0], 2.5)
+    _, _, vis = oracle_lib.visibility(V, F, eyes, [0, 0, 0], TAN30, 48, 5.0)
+    assert vis[:Fo.shape[0]].all()       # every face of the convex shell
+    assert not vis[Fo.shape[0]:].any()   # nothing of the sphere inside it
+
+
+def _soup(n, seed):
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(-1, 1, size=(n, 3))
+    V = (c[:, None, :] + 0.2 * rng.normal(size=(n, 3, 3))).reshape(-1, 3).astype(np.float32)
+    F = np.arange(3 * n, dtype=np.int32).reshape(n, 3)
+    F[1::2, 0] = F[0::2, 1][: F[1::2].shape[0]]  # some shared vertices
+    return V, F
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_first_hit_bvh_equals_brute(oracle_lib, seed):
+    V, F = _soup(2500, seed)
+    F[3] = [F[3, 0], F[3, 0], F[3, 1]]  # a degenerate triangle
+    eyes = M.sphere_viewpoints(6, [0, 0, 0], 3.0)
+    P, D = oracle_lib.camera_rays(eyes, [0, 0, 0], math.tan(math.radians(25)), 24)
+    i1, t1 = oracle_lib.first_hit(V, F, P, D, 6.0, "brute")
+    i2, t2 = oracle_lib.first_hit(V, F, P, D, 6.0, "bvh")
+    assert (i1 >= 0).sum() > 1000 and (i1 < 0).sum() > 50
+    assert np.array_equal(i1, i2) and np.array_equal(t1, t2)
+    # t_far cuts: nothing beyond it, and the nearest hit survives a cut just past it
+    ok = i1 >= 0
+    cut = np.median(t1[ok])
+    i3, t3 = oracle_lib.first_hit(V, F, P, D, cut, "bvh")
+    assert np.all(t3[i3 >= 0] <= cut)
+    near = ok & (t1 < 0.99 * cut)
+    assert np.array_equal(i3[near], i1[near])
+
+
+def _strip():
+    """Four triangles in the plane z = 0, each sharing an edge with the next;
+    face 2 is wound the other way (normal -z)."""
+    V = np.array([[0, 0, 0], [1, 0, 0], [0.5, 1, 0], [1.5, 1, 0], [2, 0, 0], [2.5, 1, 0]], np.float32)
+    F = np.array([[0, 1, 2], [1, 3, 2], [1, 4, 3], [4, 5, 3]], np.int32)
+    F[2] = F[2][::-1]
+    return V, F
+
+
+@pytest.mark.parametrize("seeds,expected", [
+    ([0], [0, 1]),              # 1 agrees with 0; 2 is flipped: the fill stops there
+    ([0, 3], [0, 1, 3]),        # 3 cannot reach 2 either
+    ([2], [2]),                 # a flipped seed promotes no neighbour
+    ([1], [0, 1]),
+])
+def test_flood_fill_strip(oracle_lib, seeds, expected):
+    V, F = _strip()
+    seed = np.zeros(F.shape[0], bool)
+    seed[seeds] = True
+    ext = oracle_lib.flood_fill(V, F, seed)
+    assert np.array_equal(np.nonzero(ext)[0], expected)
+
+
+def test_flood_fill_book_and_degenerate(oracle_lib):
+    """Pages around one edge (0,1) along x: normals +z (seed), +y (90 deg: dot
+    0, not promoted), -z (180 deg, not promoted) and a page tilted 45 deg
+    (promoted); a zero-area face on the edge never joins; a face sharing a
+    single vertex is no neighbour."""
+    V = np.array([[0, 0, 0], [1, 0, 0],
+                  [0.5, 1, 0],      # page 0 (normal +z)
+                  [0.5, 0, -1],     # page 1: (1,0,0) x (0.5,0,-1) = (0, 1, 0)
+                  [0.5, -1, 0],     # page 2: normal -z
+                  [0.5, 1, 1],      # page 3: normal (0,-1,1): dot +1
+                  [0.5, 0, 0],      # degenerate page (collinear)
+                  [-1, 0, 0.5], [-1, -1, 0.5]], np.float32)  # face 5: shares vertex 0 only
+    F = np.array([[0, 1, 2], [0, 1, 3], [0, 1, 4], [0, 1, 5], [0, 1, 6], [0, 7, 8]], np.int32)
+    n = np.cross(V[F[:, 1]] - V[F[:, 0]], V[F[:, 2]] - V[F[:, 0]])
+    assert n[0] @ n[1] == 0 and n[0] @ n[2] < 0 and n[0] @ n[3] > 0 and not n[4].any() and n[0] @ n[5] > 0
+    seed = np.array([1, 0, 0, 0, 0, 0], bool)
+    ext = oracle_lib.flood_fill(V, F, seed)
+    assert np.array_equal(np.nonzero(ext)[0], [0, 3])
+
+
+def test_flood_fill_closed_spheres(oracle_lib):
+    """One seed on a closed convex shell reaches every shell face (adjacent
+    outward normals agree) and none of a separate sphere inside it."""
+    V, F, n_outer = M.hidden_face_mesh(outer_level=3, inner_level=2)
+    seed = np.zeros(F.shape[0], bool)
+    seed[17] = True
+    ext = oracle_lib.flood_fill(V, F, seed)
+    assert ext[:n_outer].all() and not ext[n_outer:].any()
+    # every shell face is visible from the viewpoints already; the fill keeps it
+    _, _, vis = oracle_lib.visibility(V, F, M.sphere_viewpoints(24, [0, 0, 0], 2.5), [0, 0, 0], TAN30, 40, 5.0)
+    assert vis[:n_outer].mean() > 0.99 and not vis[n_outer:].any()
+    assert np.array_equal(oracle_lib.flood_fill(V, F, vis), np.arange(F.shape[0]) < n_outer)
