@@ -26,6 +26,7 @@ Besides the JSON line's required fields it reports:
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -103,6 +104,88 @@ def cpu_baseline(asset, target_s, max_dist, kind):
     return {"value": n / dt, "unit": "rays/s", "cores": cores, "kind": "oracle",
             "sample": f"{n} seeded covered texels of {cov.size}, FP64 brute-force {kind} query over all "
                       f"{asset.hi_F.shape[0]} triangles, {dt:.1f} s"}
+
+
+VIS_WORKLOAD = ("hidden-face pass: noise-displaced shell (icosphere L5, 20,480 tris) around a hidden "
+                "sphere (1,280 tris), 512 viewpoints on a sphere of radius 2.5, 1024^2 rays each, "
+                "BVH build + first-hit rays + normal-gated flood fill")
+# camera ray setup per ray (frame, pixel direction, ray-space shear): ~60 FP32 ops
+OPS_CAM = 60
+
+
+def bench_visibility(args, B, log):
+    """The hidden-face pass (Sec. 6.2) at the paper's settings: one step is
+    one whole call (BVH build over the mesh, 512 x 1024^2 camera rays, flood
+    fill)."""
+    import numpy as np
+    import torch
+    from synth import meshes as M
+    dev = torch.device("cuda:0")
+    V, F, n_out = M.hidden_face_mesh()
+    n_views, res, t_far = 512, 1024, 4.0
+    tan_half = math.tan(math.radians(30.0))
+    eyes = M.sphere_viewpoints(n_views, [0, 0, 0], 2.5)
+    Vd, Fd, Ed = (torch.from_numpy(x).to(dev) for x in (V, F, eyes))
+    ws = torch.empty(B.visibility_workspace_size(V.shape[0], F.shape[0]), dtype=torch.uint8, device=dev)
+    out = (torch.empty(F.shape[0], dtype=torch.uint8, device=dev), torch.empty(F.shape[0], dtype=torch.uint8,
+                                                                               device=dev))
+    rays = n_views * res * res
+
+    def step(timing):
+        return B.visibility(Vd, Fd, Ed, [0, 0, 0], tan_half, res, t_far, workspace=ws, out=out, timing=timing)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    hist = B.stage_history(min(args.steps, 64))
+    stage_ms = {name: float(np.mean(hist[:, k])) for k, name in enumerate(B.VIS_STAGES) if name != "unused"}
+    r = B.visibility(Vd, Fd, Ed, [0, 0, 0], tan_half, res, t_far, workspace=ws, out=out, count=True)
+    n_box, n_tri, trips = r.counter(1), r.counter(2), r.counter(3)
+    vis = r.visible.cpu().numpy()
+    ext = r.exterior.cpu().numpy()
+    assert r.status() == 0
+    log(f"[bench] visibility: {ms:.3f} ms/step, stages {stage_ms}; shell visible {vis[:n_out].mean():.4f}, "
+        f"exterior {ext[:n_out].mean():.4f}, inner visible {int(vis[n_out:].sum())}")
+    ops = n_box * OPS_BOX + n_tri * OPS_TRI + rays * OPS_CAM
+    achieved = ops / (stage_ms["rays"] / 1e3) / 1e12
+    out_json = {
+        "metric": "camera rays/s of the hidden-face pass (512 views x 1024^2, 21,760-tri mesh)",
+        "value": rays / (ms / 1e3), "unit": "rays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": VIS_WORKLOAD, "rays": rays, "tris": int(F.shape[0]), "views": n_views, "res": res},
+        "stages_ms": stage_ms,
+        "roofline": {"kernel": "visibility_kernel (camera rays, first hit)", "bound": "alu", "achieved": achieved,
+                     "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                     "box_tests_per_ray": n_box / rays, "tri_tests_per_ray": n_tri / rays,
+                     "lane_utilisation": (n_box / 2 + n_tri) / (64 * trips) if trips else None,
+                     "launch_ms": stage_ms["rays"]},
+        "paper_context_s_per_mesh": 0.179,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        cores = oracle.set_threads(0)
+        rng = np.random.default_rng(1234)
+
+        def run(n):
+            which = np.sort(rng.choice(rays, size=n, replace=False))
+            P, D = oracle.camera_rays(eyes, [0, 0, 0], tan_half, res, which=which)
+            t1 = time.perf_counter()
+            oracle.first_hit(V, F, P, D, t_far, "brute")
+            return time.perf_counter() - t1
+
+        t_small = run(256)
+        n = int(max(256, min(rays, 256 * args.cpu_seconds / max(t_small, 1e-3))))
+        dt = run(n)
+        out_json["cpu_baseline"] = {"value": n / dt, "unit": "rays/s", "cores": cores, "kind": "oracle",
+                                    "sample": f"{n} seeded camera rays of {rays}, FP64 brute-force first hit over "
+                                              f"all {F.shape[0]} triangles, {dt:.1f} s"}
+    return out_json
 
 
 def make_batch(n_assets, log):
@@ -200,8 +283,9 @@ def main():
     ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3),
                     help="workload: 2 = the headline 1.3M -> 20k triangle bake (default); 1 = the small "
                          "ripple bake; 3 = the large 5.2M-triangle bake")
-    ap.add_argument("--query", choices=("ray", "closest"), default="ray",
-                    help="correspondence query (closest: the paper's closest-point form, forward only)")
+    ap.add_argument("--query", choices=("ray", "closest", "visibility"), default="ray",
+                    help="correspondence query (closest: the paper's closest-point form, forward only); "
+                         "visibility: the hidden-face pass instead of the bake")
     ap.add_argument("--batch-assets", type=int, default=0, metavar="N",
                     help="also measure an N-asset batch (64 = the uneven batch workload)")
     ap.add_argument("--batch-steps", type=int, default=5)
@@ -237,6 +321,9 @@ def main():
         print(json.dumps({"copy_bytes": n, "copies": 3}), flush=True)
         return
     log(f"[bench] {B.version()} on {torch.cuda.get_device_name(0)}")
+    if args.query == "visibility":
+        print(json.dumps(bench_visibility(args, B, log)), flush=True)
+        return
     asset = make_config(args.config)
     t = B.to_device(asset, dev)
     res, md = asset.res, asset.max_dist

@@ -157,6 +157,46 @@ int32_t bake_normals_backward(const float *hi_V, int64_t n_hi_v, const int32_t *
                               float *grad_hi_N, void *workspace, size_t workspace_bytes,
                               void *stream);
 
+/* ---- hidden-face removal (Sec. 6.2) ------------------------------------ */
+/* Visibility rays from viewpoints around a mesh, then a flood fill that
+ * propagates "exterior" across shared edges (the paper's pass that finds the
+ * interior faces of a generated mesh: 512 viewpoints on a surrounding sphere,
+ * 1024-pixel images, a face is visible when some ray reaches it unoccluded;
+ * the fill starts from the visible faces and crosses an edge only when the
+ * two faces' normals agree in direction).
+ *
+ * Cameras: view v is a pinhole at eyes[v] looking at target (3 floats, HOST
+ * pointer); with forward f = normalise(target - eye), helper a = the world
+ * axis with the smallest |f_k| (lowest k on ties), right r = normalise(f x a),
+ * up u = r x f, pixel (i, j) of the res x res image looks along
+ * normalise(f + x r + y u), x = ((j + 1/2) 2/res - 1) tan_half_fov,
+ * y = (1 - (i + 1/2) 2/res) tan_half_fov.  A ray's first hit is the face
+ * minimising (floor(t / w), index), w = t_far 2^-20, over the faces it
+ * crosses at 0 < t <= t_far with every barycentric weight >= -2^-14 (the
+ * bake's hit rule on the half-line).
+ * Flood fill: faces f, g sharing two distinct vertex indices; g joins from
+ * an exterior f when n_f . n_g > 0, n = (V1 - V0) x (V2 - V0) in FP64 from
+ * the float vertices (no fused operations).
+ *
+ * V [n_v,3] f32, F [n_f,3] i32, eyes [n_views,3] f32: device.  Outputs
+ * (device, caller-owned): visible_out [n_f] u8 (1 = some ray's first hit),
+ * exterior_out [n_f] u8 or NULL (visible faces and every face the fill
+ * reaches), first_hit_out NULL or [n_views][res][res] i32 (first hit id, -1
+ * none).  flags: BAKE_FLAG_COUNT (box / triangle tests and wave trips of the
+ * camera rays, bake_read_counter 1-3), BAKE_FLAG_TIMING (bake_stage_times:
+ * setup, BVH build, rays, flood fill, -, total).  The workspace (>=
+ * bake_visibility_workspace_size bytes, 256-byte aligned) is overwritten; no
+ * device memory is allocated.  Indices outside [0, n_v) raise
+ * BAKE_STATUS_HI_INDEX (the face is never hit and never joins the fill).
+ * Errors: BAKE_E_INVALID_ARG (NULL pointers, n_views outside [1, 2^20], res
+ * outside [1, 16384], non-finite or non-positive tan_half_fov / t_far),
+ * BAKE_E_UNSUPPORTED (counts >= 2^30), BAKE_E_WORKSPACE. */
+int32_t bake_visibility_workspace_size(int64_t n_v, int64_t n_f, size_t *bytes_out);
+int32_t bake_visibility(const float *V, const int32_t *F, int64_t n_v, int64_t n_f, const float *eyes,
+                        int32_t n_views, const float *target, float tan_half_fov, int32_t res, float t_far,
+                        uint32_t flags, uint8_t *visible_out, uint8_t *exterior_out, int32_t *first_hit_out,
+                        void *workspace, size_t workspace_bytes, void *stream);
+
 /* Squared-error map loss, a helper for training-style use of the backward:
  * loss_out[0] = sum_i (map[i] - target[i])^2 and, if grad_out is not NULL,
  * grad_out[i] = 2 (map[i] - target[i]), over n floats (n = res*res*3 for a map).

@@ -326,15 +326,23 @@ def bake_adjoint(asset, ob, grad_map):
 # Hidden-face removal (Sec. 6.2)
 # ---------------------------------------------------------------------------
 
-def camera_rays(eyes, target, tan_half, res):
-    """Origins and unit directions [n_views*res*res, 3] of every pixel's ray,
-    ray index (v res + i) res + j (readings in oracle.c)."""
+def camera_rays(eyes, target, tan_half, res, which=None):
+    """Origins and unit directions [n, 3] of the pixels' rays, ray index (v res
+    + i) res + j: every ray of every view, or the rays listed in `which`
+    (readings in oracle.c)."""
     eyes = _c(eyes, np.float32).reshape(-1, 3)
     tg = _c(target, np.float64).reshape(3)
-    n = eyes.shape[0] * res * res
-    P = np.zeros((n, 3)); D = np.zeros((n, 3))
-    _call("orc_camera_rays", _p(eyes), C.c_int32(eyes.shape[0]), _p(tg), C.c_double(tan_half),
-          C.c_int32(res), _p(P), _p(D))
+    if which is None:
+        n = eyes.shape[0] * res * res
+        P = np.zeros((n, 3)); D = np.zeros((n, 3))
+        _call("orc_camera_rays", _p(eyes), C.c_int32(eyes.shape[0]), _p(tg), C.c_double(tan_half),
+              C.c_int32(res), _p(P), _p(D))
+        return P, D
+    which = _c(which, np.int64).reshape(-1)
+    assert which.size == 0 or (which.min() >= 0 and which.max() < eyes.shape[0] * res * res)
+    P = np.zeros((which.size, 3)); D = np.zeros((which.size, 3))
+    _call("orc_camera_rays_at", _p(eyes), _p(tg), C.c_double(tan_half), C.c_int32(res),
+          C.c_int64(which.size), _p(which), _p(P), _p(D))
     return P, D
 
 

@@ -669,34 +669,53 @@ int orc_closest_check(const float *V, const int32_t *F, int64_t n, const double 
  *     of the traversal.
  */
 
+/* Ray q = (v res + i) res + j: origin eye_v, unit direction of pixel (i, j). */
+static int camera_ray(const float *eyes, const double *target, double tan_half, int32_t res, int64_t q,
+                      v3 *p_out, v3 *d_out) {
+    int64_t v = q / ((int64_t)res * res), pix = q % ((int64_t)res * res);
+    int64_t i = pix / res, j = pix % res;
+    v3 e = ld3f(eyes, v), c = mk(target[0], target[1], target[2]);
+    v3 f = sub(c, e);
+    double lf = norm(f);
+    if (!(lf > 0)) return ORC_EINVAL;
+    f = scl(f, 1.0 / lf);
+    double af[3] = {fabs(f.x), fabs(f.y), fabs(f.z)};
+    int k = 0;
+    if (af[1] < af[k]) k = 1;
+    if (af[2] < af[k]) k = 2;
+    v3 a = mk(k == 0, k == 1, k == 2);
+    v3 r = cross(f, a);
+    r = scl(r, 1.0 / norm(r));
+    v3 u = cross(r, f);
+    double x = ((j + 0.5) * 2.0 / res - 1.0) * tan_half;
+    double y = (1.0 - (i + 0.5) * 2.0 / res) * tan_half;
+    v3 d = add(add(f, scl(r, x)), scl(u, y));
+    *p_out = e;
+    *d_out = scl(d, 1.0 / norm(d));
+    return ORC_OK;
+}
+
 /* Rays of every pixel of every view, ray index (v res + i) res + j. */
 int orc_camera_rays(const float *eyes, int32_t nviews, const double *target, double tan_half, int32_t res,
                     double *P_out, double *D_out) {
-    for (int32_t v = 0; v < nviews; ++v) {
-        v3 e = ld3f(eyes, v), c = mk(target[0], target[1], target[2]);
-        v3 f = sub(c, e);
-        double lf = norm(f);
-        if (!(lf > 0)) return ORC_EINVAL;
-        f = scl(f, 1.0 / lf);
-        double af[3] = {fabs(f.x), fabs(f.y), fabs(f.z)};
-        int k = 0;
-        if (af[1] < af[k]) k = 1;
-        if (af[2] < af[k]) k = 2;
-        v3 a = mk(k == 0, k == 1, k == 2);
-        v3 r = cross(f, a);
-        r = scl(r, 1.0 / norm(r));
-        v3 u = cross(r, f);
-        for (int32_t i = 0; i < res; ++i) {
-            for (int32_t j = 0; j < res; ++j) {
-                double x = ((j + 0.5) * 2.0 / res - 1.0) * tan_half;
-                double y = (1.0 - (i + 0.5) * 2.0 / res) * tan_half;
-                v3 d = add(add(f, scl(r, x)), scl(u, y));
-                d = scl(d, 1.0 / norm(d));
-                int64_t q = ((int64_t)v * res + i) * res + j;
-                st3d(P_out, q, e);
-                st3d(D_out, q, d);
-            }
-        }
+    const int64_t n = (int64_t)nviews * res * res;
+    for (int64_t q = 0; q < n; ++q) {
+        v3 p, d;
+        if (camera_ray(eyes, target, tan_half, res, q, &p, &d)) return ORC_EINVAL;
+        st3d(P_out, q, p);
+        st3d(D_out, q, d);
+    }
+    return ORC_OK;
+}
+
+/* The rays of a list of ray indices. */
+int orc_camera_rays_at(const float *eyes, const double *target, double tan_half, int32_t res, int64_t n,
+                       const int64_t *which, double *P_out, double *D_out) {
+    for (int64_t k = 0; k < n; ++k) {
+        v3 p, d;
+        if (camera_ray(eyes, target, tan_half, res, which[k], &p, &d)) return ORC_EINVAL;
+        st3d(P_out, k, p);
+        st3d(D_out, k, d);
     }
     return ORC_OK;
 }

@@ -113,6 +113,10 @@ _EXPORTS = {
                                             C.POINTER(C.c_int64)]),
     "bake_autotune": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t,
                                   C.c_void_p, C.c_void_p, C.POINTER(C.c_float)]),
+    "bake_visibility_workspace_size": (C.c_int32, [C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
+    "bake_visibility": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_int32,
+                                    C.POINTER(C.c_float), C.c_float, C.c_int32, C.c_float, C.c_uint32,
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "bake_stage_times": (C.c_int32, [C.POINTER(C.c_float), C.c_int32]),
     "bake_stage_history": (C.c_int32, [C.POINTER(C.c_float), C.c_int32]),
     "bake_last_error": (C.c_char_p, []),
@@ -542,3 +546,64 @@ def to_device(asset, device="cuda"):
     f = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(device)
     return (f(asset.hi_V, np.float32), f(asset.hi_F, np.int32), f(asset.hi_N, np.float32),
             f(asset.lo_V, np.float32), f(asset.lo_F, np.int32), f(asset.lo_UV, np.float32))
+
+
+# ---------------------------------------------------------------------------
+# Hidden-face removal (Sec. 6.2)
+# ---------------------------------------------------------------------------
+
+VIS_STAGES = ("setup", "bvh_build", "rays", "flood_fill", "unused", "total")
+
+
+def visibility_workspace_size(n_v: int, n_f: int) -> int:
+    out = C.c_size_t(0)
+    _check(lib().bake_visibility_workspace_size(int(n_v), int(n_f), C.byref(out)))
+    return out.value
+
+
+@dataclass
+class VisibilityResult:
+    visible: torch.Tensor               # [n_f] bool: some camera ray's first hit
+    exterior: torch.Tensor              # [n_f] bool: visible or reached by the flood fill
+    first_hit: Optional[torch.Tensor]   # [n_views, res, res] i32 (-1: no hit) when asked for
+    workspace: torch.Tensor
+
+    def counter(self, which: int, stream=None) -> int:
+        v = C.c_int64(0)
+        _check(lib().bake_read_counter(_ptr(self.workspace), int(which), _stream_handle(stream),
+                                       C.byref(v)))
+        return v.value
+
+    def status(self, stream=None) -> int:
+        v = C.c_uint32(0)
+        _check(lib().bake_query_status(_ptr(self.workspace), _stream_handle(stream), C.byref(v)))
+        return v.value
+
+
+def visibility(V, F, eyes, target, tan_half: float, res: int, t_far: float, *, first_hit: bool = False,
+               count: bool = False, timing: bool = False, workspace: Optional[torch.Tensor] = None,
+               out: Optional[tuple] = None, stream=None) -> VisibilityResult:
+    """The hidden-face pass on GPU tensors V [n_v,3] f32, F [n_f,3] i32 and
+    eyes [n_views,3] f32 (camera positions); target: 3 floats (the point every
+    camera looks at).  out: optional preallocated (visible u8 [n_f], exterior
+    u8 [n_f])."""
+    V = _dev_tensor(V, torch.float32, "V", (3,))
+    F = _dev_tensor(F, torch.int32, "F", (3,))
+    eyes = _dev_tensor(eyes, torch.float32, "eyes", (3,))
+    dev = V.device
+    nv, nf, nviews = V.shape[0], F.shape[0], eyes.shape[0]
+    if workspace is None:
+        workspace = torch.empty(visibility_workspace_size(nv, nf), dtype=torch.uint8, device=dev)
+    if out is None:
+        vis = torch.empty(nf, dtype=torch.uint8, device=dev)
+        ext = torch.empty(nf, dtype=torch.uint8, device=dev)
+    else:
+        vis, ext = out
+    fh = torch.empty((nviews, res, res), dtype=torch.int32, device=dev) if first_hit else None
+    tg = (C.c_float * 3)(*[float(x) for x in target])
+    flags = (BAKE_FLAG_COUNT if count else 0) | (BAKE_FLAG_TIMING if timing else 0)
+    _check(lib().bake_visibility(_ptr(V), _ptr(F), nv, nf, _ptr(eyes), nviews, tg, float(tan_half), int(res),
+                                 float(t_far), flags, _ptr(vis), _ptr(ext), _ptr(fh), _ptr(workspace),
+                                 workspace.numel(), _stream_handle(stream)))
+    return VisibilityResult(vis.view(torch.bool), ext.view(torch.bool), fh, workspace)
+

@@ -526,6 +526,43 @@ int32_t read_counter_at(const void* workspace, int32_t asset, int32_t which, voi
     return BAKE_OK;
 }
 
+// ---- hidden-face removal (Sec. 6.2) ----------------------------------------
+// The workspace of a visibility pass: the batch-of-one plan whose asset has
+// the mesh as its high-poly and no low-poly (its BVH build is the bake's),
+// then the flood fill's arrays and the camera rays' spill columns.
+struct VisLayout {
+    size_t deg, off, cur, adj, vis, ext, front0, front1, scan_tmp, spill, total;
+};
+
+int32_t plan_visibility(int64_t nv, int64_t nf, Plan* P, VisLayout* V) {
+    Sizes z;
+    z.nhv = nv;
+    z.nhf = nf;
+    z.nlv = 0;
+    z.nlf = 0;
+    z.res = 1;
+    int32_t rc = make_plan(&z, 1, 0, P);
+    if (rc) return rc;
+    size_t off = align256(P->L.total);
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    V->deg = take(4 * (size_t)(nv + 1));
+    V->off = take(4 * (size_t)(nv + 1));
+    V->cur = take(4 * (size_t)(nv + 1));
+    V->adj = take(4 * (size_t)(3 * nf + 1));
+    V->vis = take(4 * (size_t)(nf + 1));
+    V->ext = take(4 * (size_t)(nf + 1));
+    V->front0 = take(4 * (size_t)(nf + 1));
+    V->front1 = take(4 * (size_t)(nf + 1));
+    V->scan_tmp = take(4 * (size_t)(scan_tmp_elems(nv + 1) + 1));
+    V->spill = take(4 * (size_t)kMaxDepth * (size_t)kMaxLanes);
+    V->total = off;
+    return BAKE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -716,6 +753,96 @@ int32_t bake_autotune(const bake_asset* assets, int32_t n_assets, const bake_opt
                 }
             }
     *best_out = best_opt;
+    return BAKE_OK;
+}
+
+int32_t bake_visibility_workspace_size(int64_t n_v, int64_t n_f, size_t* bytes_out) {
+    g_err[0] = 0;
+    if (!bytes_out) return fail(BAKE_E_INVALID_ARG, "bytes_out is NULL");
+    Plan P;
+    VisLayout VL;
+    int32_t rc = plan_visibility(n_v, n_f, &P, &VL);
+    if (rc) return rc;
+    *bytes_out = VL.total;
+    return BAKE_OK;
+}
+
+int32_t bake_visibility(const float* V, const int32_t* F, int64_t n_v, int64_t n_f, const float* eyes,
+                        int32_t n_views, const float* target, float tan_half_fov, int32_t res, float t_far,
+                        uint32_t flags, uint8_t* visible_out, uint8_t* exterior_out, int32_t* first_hit_out,
+                        void* workspace, size_t workspace_bytes, void* stream) {
+    g_err[0] = 0;
+    if (n_v > 0 && !V) return fail(BAKE_E_INVALID_ARG, "V is NULL");
+    if (n_f > 0 && (!F || !visible_out)) return fail(BAKE_E_INVALID_ARG, "F / visible_out is NULL");
+    if (n_views < 1 || n_views > (1 << 20)) return fail(BAKE_E_INVALID_ARG, "n_views %d outside [1, 2^20]", n_views);
+    if (!eyes || !target) return fail(BAKE_E_INVALID_ARG, "eyes / target is NULL");
+    if (res < 1 || res > 16384) return fail(BAKE_E_INVALID_ARG, "res %d outside [1, 16384]", res);
+    if (!(tan_half_fov > 0.f) || !(tan_half_fov < INFINITY))
+        return fail(BAKE_E_INVALID_ARG, "tan_half_fov must be finite and > 0");
+    if (!(t_far > 0.f) || !(t_far < INFINITY)) return fail(BAKE_E_INVALID_ARG, "t_far must be finite and > 0");
+    for (int k = 0; k < 3; ++k)
+        if (!(fabsf(target[k]) < INFINITY)) return fail(BAKE_E_INVALID_ARG, "target must be finite");
+    if ((flags & ~(uint32_t)(BAKE_FLAG_COUNT | BAKE_FLAG_TIMING)) != 0)
+        return fail(BAKE_E_INVALID_ARG, "flags 0x%x: only BAKE_FLAG_COUNT and BAKE_FLAG_TIMING apply", flags);
+    Plan P;
+    VisLayout VL;
+    int32_t rc = plan_visibility(n_v, n_f, &P, &VL);
+    if (rc) return rc;
+    if (!workspace) return fail(BAKE_E_WORKSPACE, "workspace is NULL");
+    if (((uintptr_t)workspace & 255) != 0) return fail(BAKE_E_WORKSPACE, "workspace not 256-byte aligned");
+    if (workspace_bytes < VL.total)
+        return fail(BAKE_E_WORKSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, VL.total);
+    AssetDev& d = P.A[0];
+    d.hi_V = V;
+    d.hi_F = F;
+    d.max_dist = t_far;
+    P.G.assign(1, AssetGrad{});
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)workspace;
+    BatchHost H = host_view(P, ws);
+    const Layout& L = P.L;
+    const bool tim = (flags & BAKE_FLAG_TIMING) != 0;
+    HIP_OR_FAIL(tim_record(tim, 0, s));
+    std::vector<char> blob(L.grads - L.table, 0);
+    memcpy(blob.data(), P.A.data(), sizeof(AssetDev));
+    memcpy(blob.data() + (L.gpf - L.table), P.gpf.data(), 4 * P.gpf.size());
+    HIP_OR_FAIL(write_table(ws + L.table, blob.data(), (L.gpf - L.table) + 4 * P.gpf.size(), s));
+    HIP_OR_FAIL(fill_u32((uint32_t*)ws, 0, (int64_t)(L.table / 4), s));
+    forget_saved(workspace);
+    HIP_OR_FAIL(tim_record(tim, 1, s));
+    HIP_OR_FAIL(launch_bvh_build(H, s));
+    HIP_OR_FAIL(tim_record(tim, 2, s));
+    uint32_t* vis = (uint32_t*)(ws + VL.vis);
+    HIP_OR_FAIL(fill_u32(vis, 0, n_f, s));
+    VisRun vr;
+    vr.eyes = eyes;
+    for (int k = 0; k < 3; ++k) vr.target[k] = target[k];
+    vr.tan_half = tan_half_fov;
+    vr.n_views = n_views;
+    vr.res = res;
+    vr.visible = vis;
+    vr.first_hit = first_hit_out;
+    vr.spill = (int32_t*)(ws + VL.spill);
+    vr.spill_lanes = kMaxLanes;
+    vr.count = (flags & BAKE_FLAG_COUNT) != 0;
+    HIP_OR_FAIL(launch_visibility_rays(H, vr, s));
+    HIP_OR_FAIL(tim_record(tim, 3, s));
+    FillRun fr;
+    fr.deg = (uint32_t*)(ws + VL.deg);
+    fr.off = (uint32_t*)(ws + VL.off);
+    fr.cur = (uint32_t*)(ws + VL.cur);
+    fr.adj = (uint32_t*)(ws + VL.adj);
+    fr.ext = (uint32_t*)(ws + VL.ext);
+    fr.front0 = (uint32_t*)(ws + VL.front0);
+    fr.front1 = (uint32_t*)(ws + VL.front1);
+    fr.scan_tmp = (uint32_t*)(ws + VL.scan_tmp);
+    fr.visible = vis;
+    fr.visible_out = visible_out;
+    fr.exterior_out = exterior_out;
+    if (n_f > 0) HIP_OR_FAIL(launch_flood_fill(H, fr, s));
+    HIP_OR_FAIL(tim_record(tim, 4, s));
+    HIP_OR_FAIL(tim_record(tim, 5, s));
+    tim_commit(tim);
     return BAKE_OK;
 }
 

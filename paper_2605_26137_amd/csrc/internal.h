@@ -294,6 +294,28 @@ hipError_t launch_raster(const BatchHost& H, hipStream_t s);
 hipError_t launch_fill_uncovered(const BatchHost& H, hipStream_t s);
 hipError_t launch_bvh_build(const BatchHost& H, hipStream_t s);
 hipError_t launch_traverse(const BatchHost& H, const TravConfig& cfg, hipStream_t s);
+
+// Hidden-face removal (Sec. 6.2) on the BVH of asset 0 of a planned batch.
+struct VisRun {
+    const float* eyes;   // device [n_views][3]
+    float target[3];
+    float tan_half;
+    int32_t n_views, res;
+    uint32_t* visible;   // device [n_f] flags, set to 1 for every first-hit face
+    int32_t* first_hit;  // NULL or device [n_views res^2]
+    int32_t* spill;      // [kMaxDepth][spill_lanes]
+    int64_t spill_lanes;
+    bool count;          // instrumented: box / triangle tests and wave trips into asset 0's counters
+};
+hipError_t launch_visibility_rays(const BatchHost& H, const VisRun& v, hipStream_t s);
+// Vertex -> face lists and the normal-gated flood fill from `visible` into
+// `ext` (both [n_f] u32 flags), then both written out as bytes.
+struct FillRun {
+    uint32_t *deg, *off, *cur, *adj, *ext, *front0, *front1, *scan_tmp;
+    const uint32_t* visible;
+    uint8_t *visible_out, *exterior_out;
+};
+hipError_t launch_flood_fill(const BatchHost& H, const FillRun& f, hipStream_t s);
 hipError_t launch_dilate(const BatchHost& H, int passes, hipStream_t s);
 hipError_t launch_rgb8(const BatchHost& H, hipStream_t s);
 hipError_t launch_backward(const BatchHost& H, bool any_lo, bool any_hi, hipStream_t s);

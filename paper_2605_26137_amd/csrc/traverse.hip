@@ -117,8 +117,10 @@ __device__ __forceinline__ float3 shear(const RayT& r, float3 v) {
               fmaf(r.S.r2.z, a.z, fmaf(r.S.r2.y, a.y, r.S.r2.x * a.x)));
 }
 
-// Slab test of box [lo, hi]; on overlap with [-bound, bound] returns true and
-// the smallest |t| of the (widened) overlap in *mint.
+// Slab test of box [lo, hi]; on overlap with [-bound, bound] (ONE: with
+// [0, bound], the half-line) returns true and the smallest |t| of the
+// (widened) overlap in *mint.
+template <bool ONE = false>
 __device__ __forceinline__ bool box_test(const RayT& r, float3 lo, float3 hi, float bound,
                                          float* mint) {
     float nx = (r.sgn & 1u) ? hi.x : lo.x, fx = (r.sgn & 1u) ? lo.x : hi.x;
@@ -136,7 +138,7 @@ __device__ __forceinline__ bool box_test(const RayT& r, float3 lo, float3 hi, fl
     // instead of keeping every box it meets.
     t0 = fminf(t0, fmaf(-kPad, fabsf(t0), t0));
     t1 = fmaxf(t1, fmaf(kPad, fabsf(t1), t1));
-    t0 = fmaxf(t0, -bound);
+    t0 = fmaxf(t0, ONE ? 0.f : -bound);
     t1 = fminf(t1, bound);
     *mint = fmaxf(fmaxf(t0, -t1), 0.f);  // nearest |t| of [t0, t1]
     return t0 <= t1;
@@ -149,7 +151,9 @@ struct Best {
     float bound;    // prune nodes whose nearest |t| exceeds this
 };
 
-// Watertight two-sided test; on a better (key, id) hit updates the best.
+// Watertight test, two-sided (|t| <= max_dist) or ONE-sided (0 < t <=
+// max_dist); on a better (key, id) hit updates the best.
+template <bool ONE = false>
 __device__ __forceinline__ void tri_test(const RayT& r, const Leaf& L, float max_dist, float inv_w,
                                          float w, Best* b) {
     float3 v0 = f3(L.a.x, L.a.y, L.a.z), v1 = f3(L.a.w, L.b.x, L.b.y), v2 = f3(L.b.z, L.b.w, L.c.x);
@@ -168,7 +172,7 @@ __device__ __forceinline__ void tri_test(const RayT& r, const Leaf& L, float max
     float rdet = 1.0f / det;
     float t = T * rdet;
     float at = fabsf(t);
-    if (!(at <= max_dist)) return;
+    if (ONE ? !(t > 0.f && t <= max_dist) : !(at <= max_dist)) return;
     uint32_t key = (uint32_t)(at * inv_w);
     if (key < b->key || (key == b->key && id < b->id)) {
         b->key = key;
@@ -461,15 +465,15 @@ __device__ __forceinline__ NodeBoxes load_node(const BvhNodeC* nd) {
 // One traversal step of a lane at an internal node: test both child boxes, go
 // to the nearer hit and push the other, or pop when neither is hit.  Returns
 // the next node (internal, leaf, or kEmpty: the ray is done).
-template <int BLOCK, int STACK, bool COUNT>
+template <int BLOCK, int STACK, bool COUNT, bool ONE = false>
 __device__ __forceinline__ int32_t inner_step(const TreeView& tv, uint32_t* status, int32_t node,
                                               const RayT& R, const Best& best, LaneStack<BLOCK, STACK>& st,
                                               int tid, unsigned long long& c_box) {
     const NodeBoxes nb = load_node(tv.nodes + node);
     const int4 ref = make_int4(nb.left, nb.right, 0, 0);
     float mL, mR;
-    bool hL = box_test(R, nb.llo, nb.lhi, best.bound, &mL);
-    bool hR = box_test(R, nb.rlo, nb.rhi, best.bound, &mR);
+    bool hL = box_test<ONE>(R, nb.llo, nb.lhi, best.bound, &mL);
+    bool hR = box_test<ONE>(R, nb.rlo, nb.rhi, best.bound, &mR);
     if (COUNT) c_box += 2;
     int32_t next = kEmpty;
     if (hL && hR) {
@@ -486,11 +490,11 @@ __device__ __forceinline__ int32_t inner_step(const TreeView& tv, uint32_t* stat
 }
 
 // A lane at a leaf: triangle test, then pop.
-template <int BLOCK, int STACK, bool COUNT>
+template <int BLOCK, int STACK, bool COUNT, bool ONE = false>
 __device__ __forceinline__ int32_t leaf_step(const TreeView& tv, int32_t node, const RayT& R, Best& best,
                                              LaneStack<BLOCK, STACK>& st, int tid, unsigned long long& c_tri) {
     const Leaf L = tv.leaves[~node];
-    tri_test(R, L, tv.max_dist, tv.inv_w, tv.w, &best);
+    tri_test<ONE>(R, L, tv.max_dist, tv.inv_w, tv.w, &best);
     if (COUNT) c_tri += 1;
     return st.pop(tid);
 }
@@ -551,19 +555,23 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
     return v;
 }
 
-// One internal-node or leaf step of either query (p = R.p for the closest point).
-template <int BLOCK, int STACK, bool COUNT, bool CLOSEST>
+// Query kinds of the shared traversal: the two-sided ray of the bake, the
+// closest point (p = R.p), the first hit of a half-line (camera rays).
+constexpr int kQRay = 0, kQPoint = 1, kQFirst = 2;
+
+// One internal-node or leaf step of a query.
+template <int BLOCK, int STACK, bool COUNT, int Q>
 __device__ __forceinline__ int32_t node_step(const TreeView& tv, uint32_t* status, int32_t node,
                                              const RayT& R, Best& best, LaneStack<BLOCK, STACK>& st, int tid,
                                              unsigned long long& c_box) {
-    if constexpr (CLOSEST) return inner_step_pt<BLOCK, STACK, COUNT>(tv, status, node, R.p, best, st, tid, c_box);
-    else return inner_step<BLOCK, STACK, COUNT>(tv, status, node, R, best, st, tid, c_box);
+    if constexpr (Q == kQPoint) return inner_step_pt<BLOCK, STACK, COUNT>(tv, status, node, R.p, best, st, tid, c_box);
+    else return inner_step<BLOCK, STACK, COUNT, Q == kQFirst>(tv, status, node, R, best, st, tid, c_box);
 }
-template <int BLOCK, int STACK, bool COUNT, bool CLOSEST>
+template <int BLOCK, int STACK, bool COUNT, int Q>
 __device__ __forceinline__ int32_t tri_step(const TreeView& tv, int32_t node, const RayT& R, Best& best,
                                             LaneStack<BLOCK, STACK>& st, int tid, unsigned long long& c_tri) {
-    if constexpr (CLOSEST) return leaf_step_pt<BLOCK, STACK, COUNT>(tv, node, R.p, best, st, tid, c_tri);
-    else return leaf_step<BLOCK, STACK, COUNT>(tv, node, R, best, st, tid, c_tri);
+    if constexpr (Q == kQPoint) return leaf_step_pt<BLOCK, STACK, COUNT>(tv, node, R.p, best, st, tid, c_tri);
+    else return leaf_step<BLOCK, STACK, COUNT, Q == kQFirst>(tv, node, R, best, st, tid, c_tri);
 }
 
 // Loop shapes of the wave batches (TravConfig::mode):
@@ -633,13 +641,13 @@ __global__ __launch_bounds__(BLOCK) void traverse_batch_kernel(TravArgs a) {
                 while (__ballot(node >= 0)) {
                     if (COUNT) ++c_iter;
                     if (node >= 0) {
-                        node = node_step<BLOCK, STACK, COUNT, CLOSEST>(tv, B.status, node, R, best, st, tid, c_box);
+                        node = node_step<BLOCK, STACK, COUNT, CLOSEST ? kQPoint : kQRay>(tv, B.status, node, R, best, st, tid, c_box);
                         capped();
                     }
                 }
                 if (COUNT && __ballot(node != kEmpty)) ++c_iter;
                 if (node != kEmpty) {
-                    node = tri_step<BLOCK, STACK, COUNT, CLOSEST>(tv, node, R, best, st, tid, c_tri);
+                    node = tri_step<BLOCK, STACK, COUNT, CLOSEST ? kQPoint : kQRay>(tv, node, R, best, st, tid, c_tri);
                     capped();
                 }
             }
@@ -651,11 +659,11 @@ __global__ __launch_bounds__(BLOCK) void traverse_batch_kernel(TravArgs a) {
                 if (COUNT) ++c_iter;
                 if (__popcll(at_leaf) >= __popcll(at_node)) {
                     if (node < 0 && node != kEmpty) {
-                        node = tri_step<BLOCK, STACK, COUNT, CLOSEST>(tv, node, R, best, st, tid, c_tri);
+                        node = tri_step<BLOCK, STACK, COUNT, CLOSEST ? kQPoint : kQRay>(tv, node, R, best, st, tid, c_tri);
                         capped();
                     }
                 } else if (node >= 0) {
-                    node = node_step<BLOCK, STACK, COUNT, CLOSEST>(tv, B.status, node, R, best, st, tid, c_box);
+                    node = node_step<BLOCK, STACK, COUNT, CLOSEST ? kQPoint : kQRay>(tv, B.status, node, R, best, st, tid, c_box);
                     capped();
                 }
             }
@@ -663,10 +671,10 @@ __global__ __launch_bounds__(BLOCK) void traverse_batch_kernel(TravArgs a) {
             while (__ballot(node != kEmpty)) {
                 if (COUNT) ++c_iter;
                 if (node >= 0) {
-                    node = node_step<BLOCK, STACK, COUNT, CLOSEST>(tv, B.status, node, R, best, st, tid, c_box);
+                    node = node_step<BLOCK, STACK, COUNT, CLOSEST ? kQPoint : kQRay>(tv, B.status, node, R, best, st, tid, c_box);
                     capped();
                 } else if (node != kEmpty) {
-                    node = tri_step<BLOCK, STACK, COUNT, CLOSEST>(tv, node, R, best, st, tid, c_tri);
+                    node = tri_step<BLOCK, STACK, COUNT, CLOSEST ? kQPoint : kQRay>(tv, node, R, best, st, tid, c_tri);
                     capped();
                 }
             }
@@ -680,6 +688,105 @@ __global__ __launch_bounds__(BLOCK) void traverse_batch_kernel(TravArgs a) {
                 atomicAdd((unsigned long long*)&B.cnt[(int64_t)ai * kCntSlots + kCntTriLo], c_tri);
                 atomicAdd((unsigned long long*)&B.cnt[(int64_t)ai * kCntSlots + kCntIterLo], c_iter);
             }
+        }
+    }
+}
+
+// Camera rays of the hidden-face pass (Sec. 6.2): view v is a pinhole at
+// eye_v looking at the target; forward f, the world axis least aligned with
+// f as helper a, right r = normalise(f x a), up u = r x f; pixel (i, j) of
+// the res x res image looks along normalise(f + x r + y u) with x = ((j +
+// 1/2) 2 / res - 1) tan_half and y = (1 - (i + 1/2) 2 / res) tan_half.  Each
+// wave takes 64 consecutive pixels of one view (grid-stride over the
+// (view, 64-pixel batch) items), finds every ray's first hit on the half-line
+// (0, t_far] with the bake's hit rule and flags the hit face visible.
+struct VisArgs {
+    TravArgs t;
+    const float* eyes;
+    float3 target;
+    float tan_half;
+    int32_t n_views, res;
+    uint32_t* visible;
+    int32_t* first_hit;
+};
+
+template <int BLOCK, int STACK, bool COUNT>
+__global__ __launch_bounds__(BLOCK) void visibility_kernel(VisArgs a) {
+    __shared__ int32_t stk[STACK][BLOCK];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const Batch& B = a.t.B;
+    const TreeView tv = tree_view(a.t, B.A[0]);
+    LaneStack<BLOCK, STACK> st;
+    st.lds = stk;
+    st.spill = a.t.spill;
+    st.stride = a.t.spill_lanes;
+    st.col = (int64_t)blockIdx.x * BLOCK + tid;
+    const int64_t px = (int64_t)a.res * a.res;
+    const int64_t bpv = (px + 63) / 64;
+    const int64_t items = bpv * a.n_views;
+    const int64_t nwaves = ((int64_t)gridDim.x * BLOCK) >> 6;
+    unsigned long long c_box = 0, c_tri = 0, c_iter = 0;
+    for (int64_t it = ((int64_t)blockIdx.x * BLOCK + tid) >> 6; it < items; it += nwaves) {
+        const int32_t v = (int32_t)(it / bpv);
+        const int64_t p = (it - (int64_t)v * bpv) * 64 + lane;
+        const bool valid = p < px;
+        const float3 e = ld3(a.eyes, v);
+        float3 f = f3(a.target.x - e.x, a.target.y - e.y, a.target.z - e.z);
+        const float rf = 1.0f / sqrtf(dot3(f, f));
+        f = f3(f.x * rf, f.y * rf, f.z * rf);
+        const float ax = fabsf(f.x), ay = fabsf(f.y), az = fabsf(f.z);
+        int k = 0;
+        if (ay < ax) k = 1;
+        if (az < (k == 0 ? ax : ay)) k = 2;
+        float3 r = cross3(f, f3(k == 0 ? 1.f : 0.f, k == 1 ? 1.f : 0.f, k == 2 ? 1.f : 0.f));
+        const float rr = 1.0f / sqrtf(dot3(r, r));
+        r = f3(r.x * rr, r.y * rr, r.z * rr);
+        const float3 u = cross3(r, f);
+        const int32_t i = (int32_t)(p / a.res), j = (int32_t)(p - (int64_t)i * a.res);
+        const float x = (((float)j + 0.5f) * 2.0f / (float)a.res - 1.0f) * a.tan_half;
+        const float y = (1.0f - ((float)i + 0.5f) * 2.0f / (float)a.res) * a.tan_half;
+        float3 d = f3(f.x + x * r.x + y * u.x, f.y + x * r.y + y * u.y, f.z + x * r.z + y * u.z);
+        const float rd = 1.0f / sqrtf(dot3(d, d));
+        d = f3(d.x * rd, d.y * rd, d.z * rd);
+        const RayT R = make_rayt(e, d);
+        int32_t node = valid ? tv.root : kEmpty;
+        Best best;
+        reset_best(best, tv.max_dist);
+        st.sp = st.lo = 0;
+        int32_t steps = 0;
+        for (;;) {
+            const uint64_t at_node = __ballot(node >= 0);
+            const uint64_t at_leaf = __ballot(node < 0 && node != kEmpty);
+            if ((at_node | at_leaf) == 0) break;
+            if (COUNT) ++c_iter;
+            if (__popcll(at_leaf) >= __popcll(at_node)) {
+                if (node < 0 && node != kEmpty)
+                    node = tri_step<BLOCK, STACK, COUNT, kQFirst>(tv, node, R, best, st, tid, c_tri);
+                else continue;
+            } else if (node >= 0) {
+                node = node_step<BLOCK, STACK, COUNT, kQFirst>(tv, B.status, node, R, best, st, tid, c_box);
+            } else {
+                continue;
+            }
+            if (++steps > tv.step_cap) {
+                set_status(B, kStInternal);
+                node = kEmpty;
+            }
+        }
+        if (valid) {
+            const int32_t id = best.id == INT32_MAX ? -1 : best.id;
+            if (a.first_hit) a.first_hit[(int64_t)v * px + p] = id;
+            if (id >= 0) a.visible[id] = 1u;
+        }
+    }
+    if (COUNT) {
+        c_box = wave_sum_u64(c_box);
+        c_tri = wave_sum_u64(c_tri);
+        if (lane == 0) {
+            atomicAdd((unsigned long long*)&B.cnt[kCntBoxLo], c_box);
+            atomicAdd((unsigned long long*)&B.cnt[kCntTriLo], c_tri);
+            atomicAdd((unsigned long long*)&B.cnt[kCntIterLo], c_iter);
         }
     }
 }
@@ -814,6 +921,45 @@ hipError_t launch_mode(const TravArgs& args, int mode, bool closest, hipStream_t
 }
 
 }  // namespace
+
+hipError_t launch_visibility_rays(const BatchHost& H, const VisRun& v, hipStream_t s) {
+    const Layout& L = H.L;
+    char* ws = H.ws;
+    if (v.n_views <= 0 || v.res <= 0) return hipSuccess;
+    constexpr int kBlk = 256, kStk = 16;
+    VisArgs a;
+    a.t.B = H.dev;
+    a.t.rays = nullptr;
+    a.t.lo_n = nullptr;
+    a.t.face_t = nullptr;
+    a.t.face_uv = nullptr;
+    a.t.nodes = (const BvhNodeC*)(ws + L.nodes_c);
+    a.t.leaves = (const Leaf*)(ws + L.leaves);
+    a.t.hits = nullptr;
+    a.t.spill = v.spill;
+    a.t.spill_lanes = v.spill_lanes;
+    a.eyes = v.eyes;
+    a.target = make_float3(v.target[0], v.target[1], v.target[2]);
+    a.tan_half = v.tan_half;
+    a.n_views = v.n_views;
+    a.res = v.res;
+    a.visible = v.visible;
+    a.first_hit = v.first_hit;
+    auto kern = v.count ? visibility_kernel<kBlk, kStk, true> : visibility_kernel<kBlk, kStk, false>;
+    int dev = 0, cus = 0, per = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kBlk, 0)) != hipSuccess) return e;
+    const int64_t px = (int64_t)v.res * v.res;
+    const int64_t waves = ((px + 63) / 64) * v.n_views;
+    int64_t blocks = (int64_t)cus * std::max(per, 1);
+    blocks = std::min(blocks, (waves + kBlk / 64 - 1) / (kBlk / 64));  // no block without an item
+    blocks = std::min(blocks, v.spill_lanes / kBlk);                    // every lane has a spill column
+    blocks = std::max<int64_t>(blocks, 1);
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kBlk), 0, s, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_traverse(const BatchHost& H, const TravConfig& cfg, hipStream_t s) {
     const Layout& L = H.L;

@@ -208,3 +208,37 @@ def test_autotune_argument_checks(B):
                                  None) == B.BAKE_E_INVALID_ARG
     assert B.lib().bake_autotune(arr, 1, None, 3, C.c_void_p(0x100000), 1 << 40, None, None,
                                  None) == B.BAKE_E_INVALID_ARG
+
+
+def _vis_call(B, **over):
+    """bake_visibility with fake (never dereferenced) device pointers."""
+    fake = C.c_void_p(0x1000)
+    a = dict(V=fake, F=fake, nv=3, nf=1, eyes=fake, nviews=4, target=(C.c_float * 3)(0, 0, 0),
+             tan_half=0.5, res=16, t_far=5.0, flags=0, vis=fake, ext=fake, fh=None,
+             ws=C.c_void_p(0x100000), ws_bytes=1 << 40, stream=None)
+    a.update(over)
+    return B.lib().bake_visibility(a["V"], a["F"], a["nv"], a["nf"], a["eyes"], a["nviews"], a["target"],
+                                   a["tan_half"], a["res"], a["t_far"], a["flags"], a["vis"], a["ext"],
+                                   a["fh"], a["ws"], a["ws_bytes"], a["stream"])
+
+
+@pytest.mark.parametrize("over,code", [
+    (dict(V=None), -1), (dict(F=None), -1), (dict(vis=None), -1), (dict(eyes=None), -1),
+    (dict(target=None), -1), (dict(nviews=0), -1), (dict(res=0), -1), (dict(res=16385), -1),
+    (dict(tan_half=0.0), -1), (dict(tan_half=float("inf")), -1), (dict(t_far=float("nan")), -1),
+    (dict(t_far=-1.0), -1), (dict(flags=1), -1), (dict(nv=-1), -1), (dict(nf=1 << 30), -2),
+    (dict(ws=None), -3), (dict(ws=C.c_void_p(0x100010)), -3), (dict(ws_bytes=1000), -3),
+    (dict(target=(C.c_float * 3)(0, float("inf"), 0)), -1),
+])
+def test_visibility_host_validation_codes(B, over, code):
+    rc = _vis_call(B, **over)
+    assert rc == code, B.lib().bake_last_error()
+    assert B.lib().bake_last_error()
+
+
+def test_visibility_workspace_size(B):
+    a = B.visibility_workspace_size(1000, 2000)
+    b = B.visibility_workspace_size(2000, 4000)
+    assert 0 < a < b and a % 256 == 0
+    with pytest.raises(B.BakeError):
+        B.visibility_workspace_size(-1, 5)

@@ -171,3 +171,11 @@ def test_flood_fill_closed_spheres(oracle_lib):
     _, _, vis = oracle_lib.visibility(V, F, M.sphere_viewpoints(24, [0, 0, 0], 2.5), [0, 0, 0], TAN30, 40, 5.0)
     assert vis[:n_outer].mean() > 0.99 and not vis[n_outer:].any()
     assert np.array_equal(oracle_lib.flood_fill(V, F, vis), np.arange(F.shape[0]) < n_outer)
+
+
+def test_camera_rays_at_equals_full(oracle_lib):
+    eyes = M.sphere_viewpoints(5, [0.1, 0, 0], 2.0)
+    P, D = oracle_lib.camera_rays(eyes, [0.1, 0, 0], TAN30, 12)
+    which = np.array([0, 7, 143, 144, 500, 5 * 144 - 1])
+    P2, D2 = oracle_lib.camera_rays(eyes, [0.1, 0, 0], TAN30, 12, which=which)
+    assert np.array_equal(P2, P[which]) and np.array_equal(D2, D[which])
