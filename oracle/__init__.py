@@ -374,3 +374,39 @@ def flood_fill(V, F, seed):
     _call("orc_flood_fill", _p(V), C.c_int64(V.shape[0]), _p(F), C.c_int64(F.shape[0]), _p(sd), _p(ext))
     return ext.astype(bool)
 
+
+# ---------------------------------------------------------------------------
+# Backprojection precompute (Sec. 6.5)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class ViewMaps:
+    texels: np.ndarray     # covered texels (row-major index)
+    P: np.ndarray          # [n, 3] surface points
+    N: np.ndarray          # [n, 3] unit smooth normals
+    ok: np.ndarray         # [n] normal defined
+    ray_t: np.ndarray      # [K, res_img, res_img] first-hit t of the depth rays (0: none)
+    ray_id: np.ndarray     # [K, res_img, res_img] first-hit face (-1: none)
+    uv: np.ndarray         # [K, n, 2] image coordinates (-1, -1 outside)
+    inc: np.ndarray        # [K, n] incidence after the visibility test
+
+
+def view_maps(V, F, UV, res, eyes, target, tan_half, img_res, t_far, tol, method="bvh") -> ViewMaps:
+    """Per covered texel of the res^2 atlas and per view: image coordinates,
+    incidence max(0, n . d_k) and the depth-buffer visibility test (readings
+    in oracle.c)."""
+    face, bary = raster(UV, res)
+    vn, _ = lo_normals(V, F)
+    texels = np.nonzero(face >= 0)[0]
+    P, N, ok = rays(V, F, vn, face[texels], bary[texels])
+    eyes = _c(eyes, np.float32).reshape(-1, 3)
+    Pc, Dc = camera_rays(eyes, target, tan_half, img_res)
+    ids, t = first_hit(V, F, Pc, Dc, t_far, method)
+    K, n = eyes.shape[0], texels.size
+    uv = np.zeros((K, n, 2)); inc = np.zeros((K, n))
+    tg = _c(target, np.float64).reshape(3)
+    okc = _c(ok, np.uint8)
+    _call("orc_view_maps", _p(P), _p(N), _p(okc), C.c_int64(n), _p(eyes), C.c_int32(K), _p(tg),
+          C.c_double(tan_half), C.c_int32(img_res), _p(t), C.c_double(tol), _p(uv), _p(inc))
+    return ViewMaps(texels, P, N, ok, t.reshape(K, img_res, img_res), ids.reshape(K, img_res, img_res), uv, inc)
+

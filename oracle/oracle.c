@@ -669,11 +669,8 @@ int orc_closest_check(const float *V, const int32_t *F, int64_t n, const double 
  *     of the traversal.
  */
 
-/* Ray q = (v res + i) res + j: origin eye_v, unit direction of pixel (i, j). */
-static int camera_ray(const float *eyes, const double *target, double tan_half, int32_t res, int64_t q,
-                      v3 *p_out, v3 *d_out) {
-    int64_t v = q / ((int64_t)res * res), pix = q % ((int64_t)res * res);
-    int64_t i = pix / res, j = pix % res;
+/* Camera frame of view v: forward, right, up. */
+static int camera_frame(const float *eyes, const double *target, int64_t v, v3 *f_out, v3 *r_out, v3 *u_out) {
     v3 e = ld3f(eyes, v), c = mk(target[0], target[1], target[2]);
     v3 f = sub(c, e);
     double lf = norm(f);
@@ -686,7 +683,19 @@ static int camera_ray(const float *eyes, const double *target, double tan_half, 
     v3 a = mk(k == 0, k == 1, k == 2);
     v3 r = cross(f, a);
     r = scl(r, 1.0 / norm(r));
-    v3 u = cross(r, f);
+    *f_out = f;
+    *r_out = r;
+    *u_out = cross(r, f);
+    return ORC_OK;
+}
+
+/* Ray q = (v res + i) res + j: origin eye_v, unit direction of pixel (i, j). */
+static int camera_ray(const float *eyes, const double *target, double tan_half, int32_t res, int64_t q,
+                      v3 *p_out, v3 *d_out) {
+    int64_t v = q / ((int64_t)res * res), pix = q % ((int64_t)res * res);
+    int64_t i = pix / res, j = pix % res;
+    v3 e = ld3f(eyes, v), f, r, u;
+    if (camera_frame(eyes, target, v, &f, &r, &u)) return ORC_EINVAL;
     double x = ((j + 0.5) * 2.0 / res - 1.0) * tan_half;
     double y = (1.0 - (i + 0.5) * 2.0 / res) * tan_half;
     v3 d = add(add(f, scl(r, x)), scl(u, y));
@@ -861,6 +870,64 @@ int orc_flood_fill(const float *V, int64_t nv, const int32_t *F, int64_t nf, con
         }
     }
     free(deg); free(lst); free(fill); free(queue);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Backprojection precompute (Sec. 6.5, TextureGen post-processing): per     */
+/* atlas texel and view, the image position, the incidence and the depth-    */
+/* buffer visibility                                                          */
+/* ------------------------------------------------------------------------ */
+/*
+ * Readings: the texel's surface point p and unit smooth normal n are the
+ * bake's G-buffer (rasterised atlas, interpolated area-weighted vertex
+ * normals); the views are the pinholes of the hidden-face pass; the viewing
+ * direction is d_k = (e_k - p) / |e_k - p| and the raw incidence max(0, n.d_k);
+ * the depth buffer of view k holds, per pixel, the view-axis depth z = t (d.f)
+ * of the pixel ray's first hit (+inf where it hits nothing), i.e. a depth
+ * buffer sampled at pixel centres; with q = p - e_k and z = q.f, the texel's
+ * image coordinates are col = (q.r / (z tan_half) + 1) res / 2 - 1/2 and
+ * row = (1 - q.u / (z tan_half)) res / 2 - 1/2 (pixel centres at integers),
+ * inside when z > 0 and both lie in [-1/2, res - 1/2); it is occluded when z
+ * exceeds the depth of its nearest pixel (floor(row + 1/2), floor(col + 1/2))
+ * by more than tol.  The incidence is 0 outside the image, when occluded, or
+ * where n is undefined; image coordinates are (-1, -1) outside.
+ */
+int orc_view_maps(const double *P, const double *N, const uint8_t *ok, int64_t n, const float *eyes, int32_t nviews,
+                  const double *target, double tan_half, int32_t res, const double *ray_t, double tol,
+                  double *uv_out, double *inc_out) {
+    const int64_t px = (int64_t)res * res;
+    for (int32_t k = 0; k < nviews; ++k) {
+        v3 f, r, u, e = ld3f(eyes, k);
+        if (camera_frame(eyes, target, k, &f, &r, &u)) return ORC_EINVAL;
+        for (int64_t t = 0; t < n; ++t) {
+            double *uv = uv_out + 2 * ((int64_t)k * n + t);
+            double *inc = inc_out + (int64_t)k * n + t;
+            uv[0] = uv[1] = -1.0;
+            *inc = 0.0;
+            v3 p = ld3d(P, t), q = sub(p, e);
+            double z = dot(q, f);
+            if (!(z > 0)) continue;
+            double col = (dot(q, r) / (z * tan_half) + 1.0) * res / 2.0 - 0.5;
+            double row = (1.0 - dot(q, u) / (z * tan_half)) * res / 2.0 - 0.5;
+            if (!(col >= -0.5 && col < res - 0.5 && row >= -0.5 && row < res - 0.5)) continue;
+            uv[0] = col;
+            uv[1] = row;
+            if (!ok[t]) continue;
+            int64_t i = (int64_t)floor(row + 0.5), j = (int64_t)floor(col + 0.5);
+            int64_t pq = (int64_t)k * px + i * res + j;
+            double zb = INFINITY;
+            if (ray_t[pq] > 0) {
+                v3 pe, pd;
+                if (camera_ray(eyes, target, tan_half, res, pq, &pe, &pd)) return ORC_EINVAL;
+                zb = ray_t[pq] * dot(pd, f);
+            }
+            if (z > zb + tol) continue;
+            v3 dk = scl(sub(e, p), 1.0 / norm(sub(e, p)));
+            double c = dot(ld3d(N, t), dk);
+            *inc = c > 0 ? c : 0.0;
+        }
+    }
     return ORC_OK;
 }
 
