@@ -188,6 +188,76 @@ def bench_visibility(args, B, log):
     return out_json
 
 
+MAP_WORKLOAD = ("backprojection precompute: noise + bump displaced icosphere L5 (20,480 tris) with a 2048^2 "
+                "per-face grid atlas, the ten texturing views at radius 2.5, 1024^2 depth buffers; G-buffer "
+                "raster + BVH build + depth rays + per texel-view projection, incidence and visibility")
+
+
+def bench_view_maps(args, B, log):
+    """The backprojection precompute (Sec. 6.5) at the paper's scale: one step
+    is one whole call; value = covered texel-views per second."""
+    import numpy as np
+    import torch
+    from synth import meshes as M
+    dev = torch.device("cuda:0")
+    V, F, UV = M.textured_bumpy_mesh(level=5, res=2048)
+    res, img, t_far, tol = 2048, 1024, 5.0, 2e-3
+    tan_half = math.tan(math.radians(30.0))
+    eyes = M.texture_views(2.5)
+    Vd, Fd, UVd, Ed = (torch.from_numpy(x).to(dev) for x in (V, F, UV, eyes))
+    K = eyes.shape[0]
+    ws = torch.empty(B.view_maps_workspace_size(V.shape[0], F.shape[0], res, K, img), dtype=torch.uint8, device=dev)
+    out = (torch.empty((K, res, res, 2), dtype=torch.float32, device=dev),
+           torch.empty((K, res, res), dtype=torch.float32, device=dev))
+
+    def step(timing, count=False):
+        return B.view_maps(Vd, Fd, UVd, res, Ed, [0, 0, 0], tan_half, img, t_far, tol, workspace=ws, out=out,
+                           timing=timing, count=count)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    hist = B.stage_history(min(args.steps, 64))
+    stage_ms = {name: float(np.mean(hist[:, k])) for k, name in enumerate(B.MAP_STAGES) if name != "unused"}
+    r = step(False, count=True)
+    torch.cuda.synchronize()
+    inc = out[1].cpu().numpy()
+    n_box, n_tri, trips = r.counter(1), r.counter(2), r.counter(3)
+    rays_depth = K * img * img
+    covered = r.counter(0)
+    tv = covered * K
+    log(f"[bench] view maps: {ms:.3f} ms/step, stages {stage_ms}; {covered} covered texels, weight from some view "
+        f"{(inc.reshape(K, -1).max(0) > 0).sum() / max(covered, 1):.4f}")
+    ops = n_box * OPS_BOX + n_tri * OPS_TRI + rays_depth * OPS_CAM
+    achieved = ops / (stage_ms["depth_rays"] / 1e3) / 1e12
+    # the maps stage writes 12 B per texel-view (both outputs, every texel)
+    # after reading the ray list (16 B per covered texel) and the depth buffers
+    map_bytes = 12 * K * res * res + 16 * covered + 4 * rays_depth
+    out_json = {
+        "metric": "covered texel-views/s of the backprojection precompute (20,480-tri mesh, 2048^2 atlas, 10 views)",
+        "value": tv / (ms / 1e3), "unit": "texel-views/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": MAP_WORKLOAD, "covered_texels": covered, "views": K, "depth_res": img,
+                   "tris": int(F.shape[0])},
+        "stages_ms": stage_ms,
+        "roofline": {"kernel": "visibility_kernel (depth rays, first hit)", "bound": "alu", "achieved": achieved,
+                     "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                     "box_tests_per_ray": n_box / rays_depth, "tri_tests_per_ray": n_tri / rays_depth,
+                     "lane_utilisation": (n_box / 2 + n_tri) / (64 * trips) if trips else None,
+                     "launch_ms": stage_ms["depth_rays"]},
+        "maps_stage": {"bound": "hbm", "bytes": map_bytes, "ms": stage_ms["maps"],
+                       "achieved_GBps": map_bytes / (stage_ms["maps"] / 1e3) / 1e9, "peak_GBps": 8000.0},
+        "paper_context_s": 1.455,
+    }
+    return out_json
+
+
 def make_batch(n_assets, log):
     """The uneven batch's inputs, generated in a process pool (before this
     process touches the GPU)."""
@@ -283,9 +353,10 @@ def main():
     ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3),
                     help="workload: 2 = the headline 1.3M -> 20k triangle bake (default); 1 = the small "
                          "ripple bake; 3 = the large 5.2M-triangle bake")
-    ap.add_argument("--query", choices=("ray", "closest", "visibility"), default="ray",
+    ap.add_argument("--query", choices=("ray", "closest", "visibility", "viewmaps"), default="ray",
                     help="correspondence query (closest: the paper's closest-point form, forward only); "
-                         "visibility: the hidden-face pass instead of the bake")
+                         "visibility: the hidden-face pass instead of the bake; viewmaps: the "
+                         "backprojection precompute")
     ap.add_argument("--batch-assets", type=int, default=0, metavar="N",
                     help="also measure an N-asset batch (64 = the uneven batch workload)")
     ap.add_argument("--batch-steps", type=int, default=5)
@@ -323,6 +394,9 @@ def main():
     log(f"[bench] {B.version()} on {torch.cuda.get_device_name(0)}")
     if args.query == "visibility":
         print(json.dumps(bench_visibility(args, B, log)), flush=True)
+        return
+    if args.query == "viewmaps":
+        print(json.dumps(bench_view_maps(args, B, log)), flush=True)
         return
     asset = make_config(args.config)
     t = B.to_device(asset, dev)

@@ -167,7 +167,8 @@ int32_t bake_normals_backward(const float *hi_V, int64_t n_hi_v, const int32_t *
  *
  * Cameras: view v is a pinhole at eyes[v] looking at target (3 floats, HOST
  * pointer); with forward f = normalise(target - eye), helper a = the world
- * axis with the smallest |f_k| (lowest k on ties), right r = normalise(f x a),
+ * axis with the smallest |target_k - eye_k| (lowest k on ties, decided on the
+ * exact differences), right r = normalise(f x a),
  * up u = r x f, pixel (i, j) of the res x res image looks along
  * normalise(f + x r + y u), x = ((j + 1/2) 2/res - 1) tan_half_fov,
  * y = (1 - (i + 1/2) 2/res) tan_half_fov.  A ray's first hit is the face
@@ -196,6 +197,48 @@ int32_t bake_visibility(const float *V, const int32_t *F, int64_t n_v, int64_t n
                         int32_t n_views, const float *target, float tan_half_fov, int32_t res, float t_far,
                         uint32_t flags, uint8_t *visible_out, uint8_t *exterior_out, int32_t *first_hit_out,
                         void *workspace, size_t workspace_bytes, void *stream);
+
+/* ---- backprojection precompute (Sec. 6.5) -------------------------------- */
+/* The per-texel, per-view data that backprojecting K generated views onto a
+ * UV atlas needs: the paper recovers each atlas texel's surface point,
+ * projects it into every view, weights a view by the incidence between the
+ * surface normal and the viewing direction, and zeroes that weight where a
+ * depth-buffer test finds the point occluded beyond a fixed tolerance.
+ *
+ * The atlas is rasterised exactly as the bake's low-poly (texel centres,
+ * 1/256-texel snapped UVs, lowest face on overlaps); a covered texel's surface
+ * point p and unit smooth normal n (interpolated area-weighted vertex
+ * normals) are the bake's G-buffer.  Views are the pinholes of
+ * bake_visibility (eyes, target, tan_half_fov, img_res x img_res pixels).
+ * Depth buffer of view k: per pixel, the view-axis depth t (d . f) of the
+ * pixel ray's first hit on the mesh (+inf where it hits nothing, t in
+ * (0, t_far]).  Per texel and view, with q = p - e_k and z = q . f:
+ *   image coordinates col = (q.r / (z tan_half) + 1) img_res / 2 - 1/2,
+ *   row = (1 - q.u / (z tan_half)) img_res / 2 - 1/2 (pixel centres at
+ *   integers), or (-1, -1) when z <= 0 or either lies outside
+ *   [-1/2, img_res - 1/2);
+ *   incidence max(0, n . (e_k - p) / |e_k - p|), or 0 when outside, when the
+ *   normal is undefined, or when z > depth[nearest pixel] + depth_tol.
+ *
+ * V [n_v,3] f32, F [n_f,3] i32, UV [n_f,3,2] f32 (per corner), eyes
+ * [n_views,3] f32: device.  target: HOST pointer to 3 floats.  Outputs
+ * (device, caller-owned): uv_out [n_views][res*res][2] f32 (col, row),
+ * inc_out [n_views][res*res] f32 (uncovered texels: (-1, -1) and 0),
+ * depth_out NULL or [n_views][img_res][img_res] f32.  flags: BAKE_FLAG_COUNT
+ * (box / triangle tests and wave trips of the depth rays, bake_read_counter
+ * 1-3), BAKE_FLAG_TIMING (bake_stage_times: G-buffer, BVH build, depth rays,
+ * maps, -, total).
+ * Workspace >= bake_view_maps_workspace_size bytes, 256-byte aligned,
+ * overwritten; nothing is allocated.  Errors: BAKE_E_INVALID_ARG (NULL
+ * pointers, n_views outside [1, 4096], img_res outside [1, 16384], non-finite
+ * or non-positive tan_half_fov / t_far, negative depth_tol), BAKE_E_UNSUPPORTED
+ * (res not a power of two in [1, 16384], counts >= 2^30), BAKE_E_WORKSPACE. */
+int32_t bake_view_maps_workspace_size(int64_t n_v, int64_t n_f, int32_t res, int32_t n_views, int32_t img_res,
+                                      size_t *bytes_out);
+int32_t bake_view_maps(const float *V, const int32_t *F, const float *UV, int64_t n_v, int64_t n_f, int32_t res,
+                       const float *eyes, int32_t n_views, const float *target, float tan_half_fov,
+                       int32_t img_res, float t_far, float depth_tol, uint32_t flags, float *uv_out,
+                       float *inc_out, float *depth_out, void *workspace, size_t workspace_bytes, void *stream);
 
 /* Squared-error map loss, a helper for training-style use of the backward:
  * loss_out[0] = sum_i (map[i] - target[i])^2 and, if grad_out is not NULL,

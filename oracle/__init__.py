@@ -331,7 +331,7 @@ def camera_rays(eyes, target, tan_half, res, which=None):
     + i) res + j: every ray of every view, or the rays listed in `which`
     (readings in oracle.c)."""
     eyes = _c(eyes, np.float32).reshape(-1, 3)
-    tg = _c(target, np.float64).reshape(3)
+    tg = _c(np.asarray(target, np.float32), np.float64).reshape(3)  # the target is a float input
     if which is None:
         n = eyes.shape[0] * res * res
         P = np.zeros((n, 3)); D = np.zeros((n, 3))
@@ -404,7 +404,7 @@ def view_maps(V, F, UV, res, eyes, target, tan_half, img_res, t_far, tol, method
     ids, t = first_hit(V, F, Pc, Dc, t_far, method)
     K, n = eyes.shape[0], texels.size
     uv = np.zeros((K, n, 2)); inc = np.zeros((K, n))
-    tg = _c(target, np.float64).reshape(3)
+    tg = _c(np.asarray(target, np.float32), np.float64).reshape(3)
     okc = _c(ok, np.uint8)
     _call("orc_view_maps", _p(P), _p(N), _p(okc), C.c_int64(n), _p(eyes), C.c_int32(K), _p(tg),
           C.c_double(tan_half), C.c_int32(img_res), _p(t), C.c_double(tol), _p(uv), _p(inc))

@@ -651,9 +651,10 @@ int orc_closest_check(const float *V, const int32_t *F, int64_t n, const double 
 /*
  * Readings (the paper names the viewpoint count, the resolution and the
  * rule, not the camera):
- *   view v: a pinhole at eye_v looking at `target`; forward f = (target -
- *     eye) / |target - eye|; helper axis a = the world axis with the smallest
- *     |f_k| (the lowest k on ties); right r = (f x a) / |f x a|; up u = r x f;
+ *   view v: a pinhole at eye_v looking at `target` (both float); forward f =
+ *     (target - eye) / |target - eye|; helper axis a = the world axis with the
+ *     smallest |target_k - eye_k| (the lowest k on ties; the differences of
+ *     float inputs are exact); right r = (f x a) / |f x a|; up u = r x f;
  *   pixel (i, j) of a res x res image: x = ((j + 1/2) 2 / res - 1) tan_half,
  *     y = (1 - (i + 1/2) 2 / res) tan_half; the ray leaves the eye along
  *     normalise(f + x r + y u);
@@ -669,14 +670,16 @@ int orc_closest_check(const float *V, const int32_t *F, int64_t n, const double 
  *     of the traversal.
  */
 
-/* Camera frame of view v: forward, right, up. */
+/* Camera frame of view v: forward, right, up.  The helper axis is chosen on
+ * the differences target - eye themselves (exact for float inputs), so the
+ * choice does not depend on how the forward vector is rounded. */
 static int camera_frame(const float *eyes, const double *target, int64_t v, v3 *f_out, v3 *r_out, v3 *u_out) {
     v3 e = ld3f(eyes, v), c = mk(target[0], target[1], target[2]);
     v3 f = sub(c, e);
+    double af[3] = {fabs(f.x), fabs(f.y), fabs(f.z)};
     double lf = norm(f);
     if (!(lf > 0)) return ORC_EINVAL;
     f = scl(f, 1.0 / lf);
-    double af[3] = {fabs(f.x), fabs(f.y), fabs(f.z)};
     int k = 0;
     if (af[1] < af[k]) k = 1;
     if (af[2] < af[k]) k = 2;

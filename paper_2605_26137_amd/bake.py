@@ -117,6 +117,12 @@ _EXPORTS = {
     "bake_visibility": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_int32,
                                     C.POINTER(C.c_float), C.c_float, C.c_int32, C.c_float, C.c_uint32,
                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "bake_view_maps_workspace_size": (C.c_int32, [C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
+                                                  C.POINTER(C.c_size_t)]),
+    "bake_view_maps": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int32,
+                                   C.c_void_p, C.c_int32, C.POINTER(C.c_float), C.c_float, C.c_int32, C.c_float,
+                                   C.c_float, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_size_t, C.c_void_p]),
     "bake_stage_times": (C.c_int32, [C.POINTER(C.c_float), C.c_int32]),
     "bake_stage_history": (C.c_int32, [C.POINTER(C.c_float), C.c_int32]),
     "bake_last_error": (C.c_char_p, []),
@@ -606,4 +612,61 @@ def visibility(V, F, eyes, target, tan_half: float, res: int, t_far: float, *, f
                                  float(t_far), flags, _ptr(vis), _ptr(ext), _ptr(fh), _ptr(workspace),
                                  workspace.numel(), _stream_handle(stream)))
     return VisibilityResult(vis.view(torch.bool), ext.view(torch.bool), fh, workspace)
+
+
+# ---------------------------------------------------------------------------
+# Backprojection precompute (Sec. 6.5)
+# ---------------------------------------------------------------------------
+
+MAP_STAGES = ("gbuffer", "bvh_build", "depth_rays", "maps", "unused", "total")
+
+
+def view_maps_workspace_size(n_v: int, n_f: int, res: int, n_views: int, img_res: int) -> int:
+    out = C.c_size_t(0)
+    _check(lib().bake_view_maps_workspace_size(int(n_v), int(n_f), int(res), int(n_views), int(img_res),
+                                               C.byref(out)))
+    return out.value
+
+
+@dataclass
+class ViewMapsResult:
+    uv: torch.Tensor               # [n_views, res, res, 2] image coordinates (col, row); (-1, -1) outside
+    inc: torch.Tensor              # [n_views, res, res] incidence after the visibility test
+    depth: Optional[torch.Tensor]  # [n_views, img_res, img_res] view-axis depth buffers when asked for
+    workspace: torch.Tensor
+
+    def counter(self, which: int, stream=None) -> int:
+        v = C.c_int64(0)
+        _check(lib().bake_read_counter(_ptr(self.workspace), int(which), _stream_handle(stream),
+                                       C.byref(v)))
+        return v.value
+
+
+def view_maps(V, F, UV, res: int, eyes, target, tan_half: float, img_res: int, t_far: float, depth_tol: float, *,
+              depth: bool = False, timing: bool = False, count: bool = False,
+              workspace: Optional[torch.Tensor] = None,
+              out: Optional[tuple] = None, stream=None) -> ViewMapsResult:
+    """The backprojection precompute on GPU tensors V [n_v,3] f32, F [n_f,3]
+    i32, UV [n_f,3,2] f32 and eyes [n_views,3] f32 (target: 3 floats).
+    out: optional preallocated (uv [n_views,res,res,2] f32, inc [n_views,res,res] f32)."""
+    V = _dev_tensor(V, torch.float32, "V", (3,))
+    F = _dev_tensor(F, torch.int32, "F", (3,))
+    UV = _dev_tensor(UV, torch.float32, "UV", (3, 2))
+    eyes = _dev_tensor(eyes, torch.float32, "eyes", (3,))
+    dev = V.device
+    nv, nf, k = V.shape[0], F.shape[0], eyes.shape[0]
+    if workspace is None:
+        workspace = torch.empty(view_maps_workspace_size(nv, nf, res, k, img_res), dtype=torch.uint8, device=dev)
+    if out is None:
+        uv = torch.empty((k, res, res, 2), dtype=torch.float32, device=dev)
+        inc = torch.empty((k, res, res), dtype=torch.float32, device=dev)
+    else:
+        uv, inc = out
+    dep = torch.empty((k, img_res, img_res), dtype=torch.float32, device=dev) if depth else None
+    tg = (C.c_float * 3)(*[float(x) for x in target])
+    flags = (BAKE_FLAG_TIMING if timing else 0) | (BAKE_FLAG_COUNT if count else 0)
+    _check(lib().bake_view_maps(_ptr(V), _ptr(F), _ptr(UV), nv, nf, int(res), _ptr(eyes), k, tg, float(tan_half),
+                                int(img_res), float(t_far), float(depth_tol), flags, _ptr(uv), _ptr(inc), _ptr(dep),
+                                _ptr(workspace), workspace.numel(), _stream_handle(stream)))
+    return ViewMapsResult(uv, inc, dep, workspace)
 

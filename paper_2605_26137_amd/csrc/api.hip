@@ -563,6 +563,36 @@ int32_t plan_visibility(int64_t nv, int64_t nf, Plan* P, VisLayout* V) {
     return BAKE_OK;
 }
 
+// ---- backprojection precompute (Sec. 6.5) -----------------------------------
+// A batch of one asset whose low-poly and high-poly are both the textured
+// mesh (its atlas rasterised as in the bake, its BVH for the depth rays),
+// then the views' depth buffers and the depth rays' spill columns.
+struct MapLayout {
+    size_t depth, spill, total;
+};
+
+int32_t plan_view_maps(int64_t nv, int64_t nf, int32_t res, int32_t n_views, int32_t img_res, Plan* P,
+                       MapLayout* M) {
+    Sizes z;
+    z.nhv = z.nlv = nv;
+    z.nhf = z.nlf = nf;
+    z.res = res;
+    int32_t rc = make_plan(&z, 1, 0, P);
+    if (rc) return rc;
+    if (n_views < 1 || n_views > 4096) return fail(BAKE_E_INVALID_ARG, "n_views %d outside [1, 4096]", n_views);
+    if (img_res < 1 || img_res > 16384) return fail(BAKE_E_INVALID_ARG, "img_res %d outside [1, 16384]", img_res);
+    size_t off = align256(P->L.total);
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    M->depth = take(4 * (size_t)n_views * (size_t)img_res * (size_t)img_res);
+    M->spill = take(4 * (size_t)kMaxDepth * (size_t)kMaxLanes);
+    M->total = off;
+    return BAKE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -814,7 +844,7 @@ int32_t bake_visibility(const float* V, const int32_t* F, int64_t n_v, int64_t n
     HIP_OR_FAIL(tim_record(tim, 2, s));
     uint32_t* vis = (uint32_t*)(ws + VL.vis);
     HIP_OR_FAIL(fill_u32(vis, 0, n_f, s));
-    VisRun vr;
+    VisRun vr{};
     vr.eyes = eyes;
     for (int k = 0; k < 3; ++k) vr.target[k] = target[k];
     vr.tan_half = tan_half_fov;
@@ -822,6 +852,7 @@ int32_t bake_visibility(const float* V, const int32_t* F, int64_t n_v, int64_t n
     vr.res = res;
     vr.visible = vis;
     vr.first_hit = first_hit_out;
+    vr.depth = nullptr;
     vr.spill = (int32_t*)(ws + VL.spill);
     vr.spill_lanes = kMaxLanes;
     vr.count = (flags & BAKE_FLAG_COUNT) != 0;
@@ -840,6 +871,101 @@ int32_t bake_visibility(const float* V, const int32_t* F, int64_t n_v, int64_t n
     fr.visible_out = visible_out;
     fr.exterior_out = exterior_out;
     if (n_f > 0) HIP_OR_FAIL(launch_flood_fill(H, fr, s));
+    HIP_OR_FAIL(tim_record(tim, 4, s));
+    HIP_OR_FAIL(tim_record(tim, 5, s));
+    tim_commit(tim);
+    return BAKE_OK;
+}
+
+int32_t bake_view_maps_workspace_size(int64_t n_v, int64_t n_f, int32_t res, int32_t n_views, int32_t img_res,
+                                      size_t* bytes_out) {
+    g_err[0] = 0;
+    if (!bytes_out) return fail(BAKE_E_INVALID_ARG, "bytes_out is NULL");
+    Plan P;
+    MapLayout M;
+    int32_t rc = plan_view_maps(n_v, n_f, res, n_views, img_res, &P, &M);
+    if (rc) return rc;
+    *bytes_out = M.total;
+    return BAKE_OK;
+}
+
+int32_t bake_view_maps(const float* V, const int32_t* F, const float* UV, int64_t n_v, int64_t n_f, int32_t res,
+                       const float* eyes, int32_t n_views, const float* target, float tan_half_fov,
+                       int32_t img_res, float t_far, float depth_tol, uint32_t flags, float* uv_out,
+                       float* inc_out, float* depth_out, void* workspace, size_t workspace_bytes, void* stream) {
+    g_err[0] = 0;
+    if (n_v > 0 && !V) return fail(BAKE_E_INVALID_ARG, "V is NULL");
+    if (n_f > 0 && (!F || !UV)) return fail(BAKE_E_INVALID_ARG, "F / UV is NULL");
+    if (!eyes || !target || !uv_out || !inc_out) return fail(BAKE_E_INVALID_ARG, "eyes / target / outputs NULL");
+    if (!(tan_half_fov > 0.f) || !(tan_half_fov < INFINITY))
+        return fail(BAKE_E_INVALID_ARG, "tan_half_fov must be finite and > 0");
+    if (!(t_far > 0.f) || !(t_far < INFINITY)) return fail(BAKE_E_INVALID_ARG, "t_far must be finite and > 0");
+    if (!(depth_tol >= 0.f) || !(depth_tol < INFINITY))
+        return fail(BAKE_E_INVALID_ARG, "depth_tol must be finite and >= 0");
+    for (int k = 0; k < 3; ++k)
+        if (!(fabsf(target[k]) < INFINITY)) return fail(BAKE_E_INVALID_ARG, "target must be finite");
+    if ((flags & ~(uint32_t)(BAKE_FLAG_COUNT | BAKE_FLAG_TIMING)) != 0)
+        return fail(BAKE_E_INVALID_ARG, "flags 0x%x: only BAKE_FLAG_COUNT and BAKE_FLAG_TIMING apply", flags);
+    Plan P;
+    MapLayout M;
+    int32_t rc = plan_view_maps(n_v, n_f, res, n_views, img_res, &P, &M);
+    if (rc) return rc;
+    if (!workspace) return fail(BAKE_E_WORKSPACE, "workspace is NULL");
+    if (((uintptr_t)workspace & 255) != 0) return fail(BAKE_E_WORKSPACE, "workspace not 256-byte aligned");
+    if (workspace_bytes < M.total)
+        return fail(BAKE_E_WORKSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, M.total);
+    AssetDev& d = P.A[0];
+    d.hi_V = d.lo_V = V;
+    d.hi_F = d.lo_F = F;
+    d.lo_UV = UV;
+    d.max_dist = t_far;
+    P.G.assign(1, AssetGrad{});
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)workspace;
+    BatchHost H = host_view(P, ws);
+    const Layout& L = P.L;
+    const bool tim = (flags & BAKE_FLAG_TIMING) != 0;
+    HIP_OR_FAIL(tim_record(tim, 0, s));
+    std::vector<char> blob(L.grads - L.table, 0);
+    memcpy(blob.data(), P.A.data(), sizeof(AssetDev));
+    memcpy(blob.data() + (L.gpf - L.table), P.gpf.data(), 4 * P.gpf.size());
+    HIP_OR_FAIL(write_table(ws + L.table, blob.data(), (L.gpf - L.table) + 4 * P.gpf.size(), s));
+    HIP_OR_FAIL(fill_u32((uint32_t*)ws, 0, (int64_t)(L.table / 4), s));
+    forget_saved(workspace);
+    HIP_OR_FAIL(launch_lo_prep(H, s));
+    HIP_OR_FAIL(launch_raster(H, s));
+    HIP_OR_FAIL(tim_record(tim, 1, s));
+    HIP_OR_FAIL(launch_bvh_build(H, s));
+    HIP_OR_FAIL(tim_record(tim, 2, s));
+    float* depth = depth_out ? depth_out : (float*)(ws + M.depth);
+    VisRun vr{};
+    vr.eyes = eyes;
+    for (int k = 0; k < 3; ++k) vr.target[k] = target[k];
+    vr.tan_half = tan_half_fov;
+    vr.n_views = n_views;
+    vr.res = img_res;
+    vr.visible = nullptr;
+    vr.first_hit = nullptr;
+    vr.depth = depth;
+    vr.spill = (int32_t*)(ws + M.spill);
+    vr.spill_lanes = kMaxLanes;
+    vr.count = (flags & BAKE_FLAG_COUNT) != 0;
+    HIP_OR_FAIL(launch_visibility_rays(H, vr, s));
+    HIP_OR_FAIL(tim_record(tim, 3, s));
+    const int64_t tex = (int64_t)res * res;
+    HIP_OR_FAIL(fill_u32((uint32_t*)uv_out, 0xBF800000u, 2 * (int64_t)n_views * tex, s));  // -1.0f
+    HIP_OR_FAIL(fill_u32((uint32_t*)inc_out, 0u, (int64_t)n_views * tex, s));
+    MapRun mr{};
+    mr.eyes = eyes;
+    for (int k = 0; k < 3; ++k) mr.target[k] = target[k];
+    mr.tan_half = tan_half_fov;
+    mr.n_views = n_views;
+    mr.img_res = img_res;
+    mr.depth = depth;
+    mr.tol = depth_tol;
+    mr.uv_out = uv_out;
+    mr.inc_out = inc_out;
+    HIP_OR_FAIL(launch_view_maps(H, mr, s));
     HIP_OR_FAIL(tim_record(tim, 4, s));
     HIP_OR_FAIL(tim_record(tim, 5, s));
     tim_commit(tim);

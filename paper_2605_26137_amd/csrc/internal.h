@@ -303,11 +303,25 @@ struct VisRun {
     int32_t n_views, res;
     uint32_t* visible;   // device [n_f] flags, set to 1 for every first-hit face
     int32_t* first_hit;  // NULL or device [n_views res^2]
+    float* depth;        // NULL or device [n_views res^2]: view-axis depth of the first hit, +inf none
     int32_t* spill;      // [kMaxDepth][spill_lanes]
     int64_t spill_lanes;
     bool count;          // instrumented: box / triangle tests and wave trips into asset 0's counters
 };
 hipError_t launch_visibility_rays(const BatchHost& H, const VisRun& v, hipStream_t s);
+// Backprojection precompute (Sec. 6.5) for asset 0's covered texels (its ray
+// list and low-poly normals) against the depth buffers of the views.
+struct MapRun {
+    const float* eyes;  // device [n_views][3]
+    float target[3];
+    float tan_half;
+    int32_t n_views, img_res;
+    const float* depth;  // device [n_views][img_res^2]
+    float tol;
+    float* uv_out;       // device [n_views][res^2][2], pre-filled with -1
+    float* inc_out;      // device [n_views][res^2], pre-filled with 0
+};
+hipError_t launch_view_maps(const BatchHost& H, const MapRun& m, hipStream_t s);
 // Vertex -> face lists and the normal-gated flood fill from `visible` into
 // `ext` (both [n_f] u32 flags), then both written out as bytes.
 struct FillRun {

@@ -693,8 +693,9 @@ __global__ __launch_bounds__(BLOCK) void traverse_batch_kernel(TravArgs a) {
 }
 
 // Camera rays of the hidden-face pass (Sec. 6.2): view v is a pinhole at
-// eye_v looking at the target; forward f, the world axis least aligned with
-// f as helper a, right r = normalise(f x a), up u = r x f; pixel (i, j) of
+// eye_v looking at the target; forward f, helper a = the world axis with the
+// smallest |target_k - eye_k| (lowest k on ties), right r = normalise(f x a),
+// up u = r x f; pixel (i, j) of
 // the res x res image looks along normalise(f + x r + y u) with x = ((j +
 // 1/2) 2 / res - 1) tan_half and y = (1 - (i + 1/2) 2 / res) tan_half.  Each
 // wave takes 64 consecutive pixels of one view (grid-stride over the
@@ -706,9 +707,30 @@ struct VisArgs {
     float3 target;
     float tan_half;
     int32_t n_views, res;
-    uint32_t* visible;
-    int32_t* first_hit;
+    uint32_t* visible;   // NULL: no visibility flags
+    int32_t* first_hit;  // NULL or per pixel
+    float* depth;        // NULL or per pixel: view-axis depth of the first hit, +inf for none
 };
+
+// The pinhole frame of a view (forward, right, up; see visibility_kernel).
+// The helper axis is chosen on the exact FP64 differences target - eye, so
+// the choice is the same however the forward vector rounds.
+__device__ __forceinline__ void view_frame(float3 e, float3 target, float3* f_out, float3* r_out, float3* u_out) {
+    const double ax = fabs((double)target.x - (double)e.x), ay = fabs((double)target.y - (double)e.y),
+                 az = fabs((double)target.z - (double)e.z);
+    float3 f = f3(target.x - e.x, target.y - e.y, target.z - e.z);
+    const float rf = 1.0f / sqrtf(dot3(f, f));
+    f = f3(f.x * rf, f.y * rf, f.z * rf);
+    int k = 0;
+    if (ay < ax) k = 1;
+    if (az < (k == 0 ? ax : ay)) k = 2;
+    float3 r = cross3(f, f3(k == 0 ? 1.f : 0.f, k == 1 ? 1.f : 0.f, k == 2 ? 1.f : 0.f));
+    const float rr = 1.0f / sqrtf(dot3(r, r));
+    r = f3(r.x * rr, r.y * rr, r.z * rr);
+    *f_out = f;
+    *r_out = r;
+    *u_out = cross3(r, f);
+}
 
 template <int BLOCK, int STACK, bool COUNT>
 __global__ __launch_bounds__(BLOCK) void visibility_kernel(VisArgs a) {
@@ -732,17 +754,8 @@ __global__ __launch_bounds__(BLOCK) void visibility_kernel(VisArgs a) {
         const int64_t p = (it - (int64_t)v * bpv) * 64 + lane;
         const bool valid = p < px;
         const float3 e = ld3(a.eyes, v);
-        float3 f = f3(a.target.x - e.x, a.target.y - e.y, a.target.z - e.z);
-        const float rf = 1.0f / sqrtf(dot3(f, f));
-        f = f3(f.x * rf, f.y * rf, f.z * rf);
-        const float ax = fabsf(f.x), ay = fabsf(f.y), az = fabsf(f.z);
-        int k = 0;
-        if (ay < ax) k = 1;
-        if (az < (k == 0 ? ax : ay)) k = 2;
-        float3 r = cross3(f, f3(k == 0 ? 1.f : 0.f, k == 1 ? 1.f : 0.f, k == 2 ? 1.f : 0.f));
-        const float rr = 1.0f / sqrtf(dot3(r, r));
-        r = f3(r.x * rr, r.y * rr, r.z * rr);
-        const float3 u = cross3(r, f);
+        float3 f, r, u;
+        view_frame(e, a.target, &f, &r, &u);
         const int32_t i = (int32_t)(p / a.res), j = (int32_t)(p - (int64_t)i * a.res);
         const float x = (((float)j + 0.5f) * 2.0f / (float)a.res - 1.0f) * a.tan_half;
         const float y = (1.0f - ((float)i + 0.5f) * 2.0f / (float)a.res) * a.tan_half;
@@ -777,7 +790,8 @@ __global__ __launch_bounds__(BLOCK) void visibility_kernel(VisArgs a) {
         if (valid) {
             const int32_t id = best.id == INT32_MAX ? -1 : best.id;
             if (a.first_hit) a.first_hit[(int64_t)v * px + p] = id;
-            if (id >= 0) a.visible[id] = 1u;
+            if (a.depth) a.depth[(int64_t)v * px + p] = id >= 0 ? best.t * dot3(d, f) : INFINITY;
+            if (id >= 0 && a.visible) a.visible[id] = 1u;
         }
     }
     if (COUNT) {
@@ -788,6 +802,78 @@ __global__ __launch_bounds__(BLOCK) void visibility_kernel(VisArgs a) {
             atomicAdd((unsigned long long*)&B.cnt[kCntTriLo], c_tri);
             atomicAdd((unsigned long long*)&B.cnt[kCntIterLo], c_iter);
         }
+    }
+}
+
+// Backprojection precompute (Sec. 6.5): per covered texel of asset 0 (its
+// surface point p and smooth normal from the G-buffer) and per view: image
+// coordinates col = (q.r / (z tan_half) + 1) res / 2 - 1/2, row = (1 - q.u /
+// (z tan_half)) res / 2 - 1/2 with q = p - e, z = q.f (pixel centres at
+// integers; (-1, -1) outside the image or behind the eye), and the incidence
+// max(0, n . (e - p) / |e - p|), set to 0 when z exceeds the depth buffer at
+// the nearest pixel by more than tol (occluded) or the normal is undefined.
+struct MapArgs {
+    TravArgs t;
+    const float* eyes;
+    float3 target;
+    float tan_half;
+    int32_t n_views, img_res;
+    const float* depth;  // [n_views][img_res^2]
+    float tol;
+    float* uv_out;       // [n_views][res^2][2]
+    float* inc_out;      // [n_views][res^2]
+};
+
+__global__ __launch_bounds__(256) void view_map_kernel(MapArgs a) {
+    const Batch& B = a.t.B;
+    const AssetDev& As = B.A[0];
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= (int64_t)B.cnt[kCntRays]) return;
+    const Ray ray = a.t.rays[r];
+    const float b1 = ray.b1, b2 = ray.b2, b0 = 1.0f - b1 - b2;
+    const int32_t i0 = As.lo_F[3 * ray.face], i1 = As.lo_F[3 * ray.face + 1], i2 = As.lo_F[3 * ray.face + 2];
+    const float3 V0 = ld3(As.lo_V, i0), V1 = ld3(As.lo_V, i1), V2 = ld3(As.lo_V, i2);
+    const float4 n0 = a.t.lo_n[i0], n1 = a.t.lo_n[i1], n2 = a.t.lo_n[i2];
+    const float3 p = f3(b0 * V0.x + b1 * V1.x + b2 * V2.x, b0 * V0.y + b1 * V1.y + b2 * V2.y,
+                        b0 * V0.z + b1 * V1.z + b2 * V2.z);
+    float3 n = f3(b0 * n0.x + b1 * n1.x + b2 * n2.x, b0 * n0.y + b1 * n1.y + b2 * n2.y,
+                  b0 * n0.z + b1 * n1.z + b2 * n2.z);
+    const float l2 = dot3(n, n);
+    const bool ok = l2 > 0.f;
+    const float rl = ok ? 1.0f / sqrtf(l2) : 0.f;
+    n = f3(n.x * rl, n.y * rl, n.z * rl);
+    const int64_t texels = (int64_t)As.res * As.res, tex = ray.texel;
+    const int64_t px = (int64_t)a.img_res * a.img_res;
+    const float half = 0.5f * (float)a.img_res;
+    for (int32_t k = 0; k < a.n_views; ++k) {
+        const float3 e = ld3(a.eyes, k);
+        float3 f, rt, u;
+        view_frame(e, a.target, &f, &rt, &u);
+        const float3 q = f3(p.x - e.x, p.y - e.y, p.z - e.z);
+        const float z = dot3(q, f);
+        float col = -1.f, row = -1.f, inc = 0.f;
+        if (z > 0.f) {
+            const float c = (dot3(q, rt) / (z * a.tan_half) + 1.0f) * half - 0.5f;
+            const float w = (1.0f - dot3(q, u) / (z * a.tan_half)) * half - 0.5f;
+            const float hi = (float)a.img_res - 0.5f;
+            if (c >= -0.5f && c < hi && w >= -0.5f && w < hi) {
+                col = c;
+                row = w;
+                if (ok) {
+                    const int32_t pi = min(max((int32_t)floorf(w + 0.5f), 0), a.img_res - 1);
+                    const int32_t pj = min(max((int32_t)floorf(c + 0.5f), 0), a.img_res - 1);
+                    const float zb = a.depth[(int64_t)k * px + (int64_t)pi * a.img_res + pj];
+                    if (!(z > zb + a.tol)) {
+                        const float3 dk = f3(-q.x, -q.y, -q.z);
+                        const float cs = dot3(n, dk) / sqrtf(dot3(dk, dk));
+                        inc = fmaxf(cs, 0.f);
+                    }
+                }
+            }
+        }
+        a.uv_out[2 * ((int64_t)k * texels + tex)] = col;
+        a.uv_out[2 * ((int64_t)k * texels + tex) + 1] = row;
+        a.inc_out[(int64_t)k * texels + tex] = inc;
     }
 }
 
@@ -945,6 +1031,7 @@ hipError_t launch_visibility_rays(const BatchHost& H, const VisRun& v, hipStream
     a.res = v.res;
     a.visible = v.visible;
     a.first_hit = v.first_hit;
+    a.depth = v.depth;
     auto kern = v.count ? visibility_kernel<kBlk, kStk, true> : visibility_kernel<kBlk, kStk, false>;
     int dev = 0, cus = 0, per = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -958,6 +1045,36 @@ hipError_t launch_visibility_rays(const BatchHost& H, const VisRun& v, hipStream
     blocks = std::min(blocks, v.spill_lanes / kBlk);                    // every lane has a spill column
     blocks = std::max<int64_t>(blocks, 1);
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kBlk), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_view_maps(const BatchHost& H, const MapRun& m, hipStream_t s) {
+    const Layout& L = H.L;
+    char* ws = H.ws;
+    if (L.t_tex == 0 || m.n_views <= 0) return hipSuccess;
+    MapArgs a;
+    a.t.B = H.dev;
+    a.t.rays = (const Ray*)(ws + L.rays);
+    a.t.lo_n = (const float4*)(ws + L.lo_n);
+    a.t.face_t = nullptr;
+    a.t.face_uv = nullptr;
+    a.t.nodes = nullptr;
+    a.t.leaves = nullptr;
+    a.t.hits = nullptr;
+    a.t.spill = nullptr;
+    a.t.spill_lanes = 0;
+    a.eyes = m.eyes;
+    a.target = make_float3(m.target[0], m.target[1], m.target[2]);
+    a.tan_half = m.tan_half;
+    a.n_views = m.n_views;
+    a.img_res = m.img_res;
+    a.depth = m.depth;
+    a.tol = m.tol;
+    a.uv_out = m.uv_out;
+    a.inc_out = m.inc_out;
+    // one thread per texel of the atlas bounds the covered texels (rays)
+    const unsigned blocks = (unsigned)((L.t_tex + 255) / 256);
+    hipLaunchKernelGGL(view_map_kernel, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -310,6 +310,26 @@ def hidden_face_mesh(outer_level: int = 5, inner_level: int = 3, inner_scale: fl
     return V, F, Fo.shape[0]
 
 
+def texture_views(radius: float) -> np.ndarray:
+    """The ten generated views of the paper's texturing (front, rear, top,
+    bottom, +-45 deg frontal, left, right, +-45 deg rear) as camera positions
+    on a circle / the poles of the given radius, y up, front = +z; float32 [10, 3]."""
+    s = radius * math.sqrt(0.5)
+    P = [(0, 0, radius), (0, 0, -radius), (0, radius, 0), (0, -radius, 0), (s, 0, s), (-s, 0, s),
+         (radius, 0, 0), (-radius, 0, 0), (s, 0, -s), (-s, 0, -s)]
+    return np.array(P, np.float32)
+
+
+def textured_bumpy_mesh(level: int = 5, res: int = 2048, seed: int = 3):
+    """An icosphere displaced by 4-octave noise and 32 Gaussian bumps (which
+    occlude each other at grazing views), with the per-face grid atlas:
+    float32 V, int32 F, float32 per-corner UV [F, 3, 2]."""
+    V, F = icosphere(level)
+    U = unit_directions(V)
+    Vd = displace(U, noise_radius(U, seed, 4, 0.03) + bump_radius(U, seed + 1, 32, 0.08, 0.06))
+    return Vd.astype(np.float32), F.astype(np.int32), face_grid_atlas(F.shape[0], res)
+
+
 def decimate(V: np.ndarray, F: np.ndarray, n_target: int, seed: int):
     """Delete uniformly random faces (seeded) down to n_target, then drop
     unreferenced vertices keeping the order of the rest."""

@@ -242,3 +242,32 @@ def test_visibility_workspace_size(B):
     assert 0 < a < b and a % 256 == 0
     with pytest.raises(B.BakeError):
         B.visibility_workspace_size(-1, 5)
+
+
+def _map_call(B, **over):
+    """bake_view_maps with fake (never dereferenced) device pointers."""
+    fake = C.c_void_p(0x1000)
+    a = dict(V=fake, F=fake, UV=fake, nv=3, nf=1, res=16, eyes=fake, nviews=4, target=(C.c_float * 3)(0, 0, 0),
+             tan_half=0.5, img=64, t_far=5.0, tol=1e-3, flags=0, uv=fake, inc=fake, dep=None,
+             ws=C.c_void_p(0x100000), ws_bytes=1 << 40, stream=None)
+    a.update(over)
+    return B.lib().bake_view_maps(a["V"], a["F"], a["UV"], a["nv"], a["nf"], a["res"], a["eyes"], a["nviews"],
+                                  a["target"], a["tan_half"], a["img"], a["t_far"], a["tol"], a["flags"], a["uv"],
+                                  a["inc"], a["dep"], a["ws"], a["ws_bytes"], a["stream"])
+
+
+@pytest.mark.parametrize("over,code", [
+    (dict(V=None), -1), (dict(F=None), -1), (dict(UV=None), -1), (dict(eyes=None), -1), (dict(target=None), -1),
+    (dict(uv=None), -1), (dict(inc=None), -1), (dict(nviews=0), -1), (dict(img=0), -1), (dict(res=12), -2),
+    (dict(tan_half=-1.0), -1), (dict(t_far=float("inf")), -1), (dict(tol=-1e-3), -1), (dict(tol=float("nan")), -1),
+    (dict(flags=1), -1), (dict(ws=None), -3), (dict(ws_bytes=1000), -3),
+])
+def test_view_maps_host_validation_codes(B, over, code):
+    rc = _map_call(B, **over)
+    assert rc == code, B.lib().bake_last_error()
+
+
+def test_view_maps_workspace_size(B):
+    a = B.view_maps_workspace_size(1000, 2000, 256, 10, 256)
+    b = B.view_maps_workspace_size(1000, 2000, 256, 10, 512)
+    assert 0 < a < b and a % 256 == 0

@@ -1,0 +1,139 @@
+"""GPU backprojection precompute (Sec. 6.5) against the FP64 oracle through the
+C ABI: image coordinates within 2e-3 pixel, incidence within 1e-5 where both
+sides see the texel, and every visibility disagreement explained (the nearest
+pixel is ambiguous at rounding level, the depth comparison is within 1e-4 of
+the tolerance, or the two depth buffers differ at that pixel because its ray is
+a tie between surfaces)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from planes import textured_plane  # noqa: E402
+from synth import meshes as M  # noqa: E402
+
+TAN30 = math.tan(math.radians(30.0))
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2605_26137_amd.bake as bake
+    bake.lib()
+    return bake
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run(B, V, F, UV, res, eyes, target, tan_half, img_res, t_far, tol, **kw):
+    say(f"[gpu] view maps n_f={F.shape[0]} res={res} views={eyes.shape[0]} img={img_res}")
+    d = torch.device("cuda")
+    t = lambda x, dt: torch.from_numpy(np.ascontiguousarray(x, dt)).to(d)
+    r = B.view_maps(t(V, np.float32), t(F, np.int32), t(UV, np.float32), res, t(eyes, np.float32), target,
+                    tan_half, img_res, t_far, tol, depth=True, **kw)
+    torch.cuda.synchronize()
+    return r
+
+
+def compare(oracle_lib, V, F, UV, res, eyes, target, tan_half, img_res, t_far, tol, r):
+    om = oracle_lib.view_maps(V, F, UV, res, eyes, target, tan_half, img_res, t_far, tol)
+    K, n = om.inc.shape
+    tex = om.texels
+    g_uv = r.uv.cpu().numpy().reshape(K, -1, 2)
+    g_inc = r.inc.cpu().numpy().reshape(K, -1)
+    g_dep = r.depth.cpu().numpy()
+    # uncovered texels: (-1, -1), 0
+    unc = np.ones(res * res, bool)
+    unc[tex] = False
+    assert np.all(g_uv[:, unc] == -1) and np.all(g_inc[:, unc] == 0)
+    g_uv, g_inc = g_uv[:, tex], g_inc[:, tex]
+    # depth buffers: view-axis depth of each pixel's first hit
+    f = np.asarray(target, np.float64)[None, :] - eyes.astype(np.float64)
+    f /= np.linalg.norm(f, axis=1, keepdims=True)
+    _, Dc = oracle_lib.camera_rays(eyes, target, tan_half, img_res)
+    o_dep = np.where(om.ray_t > 0, om.ray_t * np.einsum("kpj,kj->kp", Dc.reshape(K, -1, 3), f).reshape(om.ray_t.shape),
+                     np.inf)
+    with np.errstate(invalid="ignore"):
+        dep_ok = (np.isinf(o_dep) & np.isinf(g_dep)) | (np.abs(o_dep - g_dep) <= 1e-5 * t_far)
+    say(f"[gpu] depth pixels agree {dep_ok.mean():.6f}")
+    assert dep_ok.mean() >= 0.999
+    # image coordinates
+    o_in, g_in = om.uv[..., 0] >= -0.5, g_uv[..., 0] >= -0.5
+    border = ((np.abs(om.uv[..., 0] + 0.5) < 1e-3) | (np.abs(om.uv[..., 0] - (img_res - 0.5)) < 1e-3) |
+              (np.abs(om.uv[..., 1] + 0.5) < 1e-3) | (np.abs(om.uv[..., 1] - (img_res - 0.5)) < 1e-3))
+    assert np.all((o_in == g_in) | border)
+    both = o_in & g_in
+    assert np.abs(om.uv[both] - g_uv[both]).max() <= 2e-3
+    # incidence
+    o_vis, g_vis = om.inc > 0, g_inc > 0
+    agree_vis = o_vis == g_vis
+    close = both & o_vis & g_vis
+    if close.any():
+        assert np.abs(om.inc[close] - g_inc[close]).max() <= 1e-5
+    bad = np.nonzero(~agree_vis)
+    say(f"[gpu] texel-views {K * n}: visibility agrees on {agree_vis.mean():.6f}, {bad[0].size} to explain")
+    assert agree_vis.mean() >= 0.999
+    for k, t in zip(*bad):
+        col, row = om.uv[k, t]
+        if col < -0.5:
+            assert border[k, t]
+            continue
+        amb = max(abs((row + 0.5) % 1 - 0.5), abs((col + 0.5) % 1 - 0.5)) > 0.5 - 1e-3  # either coordinate
+        i, j = int(math.floor(row + 0.5)), int(math.floor(col + 0.5))
+        e = eyes[k].astype(np.float64)
+        z = (om.P[t] - e) @ f[k]
+        zb = o_dep[k, i, j]
+        near_tol = np.isfinite(zb) and abs(z - zb - tol) <= 1e-4
+        tie_pixel = not dep_ok[k, i, j]
+        grazing = max(om.inc[k, t], g_inc[k, t]) < 1e-5
+        assert amb or near_tol or tie_pixel or grazing, (k, t, col, row, z, zb)
+    return om
+
+
+def test_plane_with_occluder(B, oracle_lib):
+    V, F, UV = textured_plane(n=8, occluder=True)
+    eyes = np.array([[0.45, 0.5, 1.6], [1.6, 0.4, 1.1], [-0.8, -0.9, 1.3]], np.float32)
+    tg = [0.5, 0.5, 0.0]
+    r = run(B, V, F, UV, 128, eyes, tg, TAN30, 256, 6.0, 1e-3)
+    om = compare(oracle_lib, V, F, UV, 128, eyes, tg, TAN30, 256, 6.0, 1e-3, r)
+    plane = np.abs(om.P[:, 2]) < 1e-6
+    # view 0 looks straight at the occluder: part of the plane gets no weight
+    assert (om.inc[0, plane] == 0).mean() > 0.05 and (om.inc[0, plane] > 0.5).mean() > 0.5
+
+
+def test_bumpy_sphere_ten_views(B, oracle_lib):
+    V, F, UV = M.textured_bumpy_mesh(level=3, res=256)
+    eyes = M.texture_views(2.5)
+    r = run(B, V, F, UV, 256, eyes, [0, 0, 0], TAN30, 256, 5.0, 2e-3)
+    om = compare(oracle_lib, V, F, UV, 256, eyes, [0, 0, 0], TAN30, 256, 5.0, 2e-3, r)
+    # nearly every covered texel gets weight from some view; some are hidden
+    # from a view they face
+    assert (om.inc.max(0) > 0).mean() > 0.95
+    occl = (om.inc == 0) & (np.einsum("tj,ktj->kt", om.N, eyes[:, None, :] - om.P[None]) > 0.05)
+    assert occl.sum() > 100
+
+
+def test_repeat_bitwise(B):
+    V, F, UV = M.textured_bumpy_mesh(level=3, res=128)
+    eyes = M.texture_views(2.5)
+    r1 = run(B, V, F, UV, 128, eyes, [0, 0, 0], TAN30, 128, 5.0, 2e-3)
+    r2 = run(B, V, F, UV, 128, eyes, [0, 0, 0], TAN30, 128, 5.0, 2e-3)
+    assert torch.equal(r1.uv, r2.uv) and torch.equal(r1.inc, r2.inc) and torch.equal(r1.depth, r2.depth)
+
+
+def test_paper_configuration(B, oracle_lib):
+    """20,480-face bumpy mesh, 2048^2 atlas, the paper's ten views (depth
+    buffers at 512^2 so the FP64 oracle recomputes every texel-view)."""
+    V, F, UV = M.textured_bumpy_mesh(level=5, res=2048)
+    eyes = M.texture_views(2.5)
+    r = run(B, V, F, UV, 2048, eyes, [0, 0, 0], TAN30, 512, 5.0, 2e-3)
+    compare(oracle_lib, V, F, UV, 2048, eyes, [0, 0, 0], TAN30, 512, 5.0, 2e-3, r)

@@ -6,26 +6,9 @@ import math
 
 import numpy as np
 
-from planes import grid
+from planes import textured_plane as plane_mesh
 
 TAN30 = math.tan(math.radians(30.0))
-
-
-def plane_mesh(n=8, occluder=False):
-    """Grid over [0,1]^2 at z = 0 with UV = (x / 2, y) (the atlas' left half);
-    optionally a square occluder at z = 0.5 over [0.3, 0.6] x [0.2, 0.7] with
-    its UVs in the right half."""
-    V, F = grid(n)
-    UV = np.stack([V[F][:, :, 0] / 2, V[F][:, :, 1]], 2)
-    if occluder:
-        Vo, Fo = grid(2, z=lambda x, y: 0.0 * x + 0.5, x0=0.0, y0=0.0, size=1.0)
-        Vo[:, 0] = 0.3 + 0.3 * Vo[:, 0]
-        Vo[:, 1] = 0.2 + 0.5 * Vo[:, 1]
-        uvo = np.stack([0.5 + 0.5 * (Vo[Fo][:, :, 0] - 0.3) / 0.3, (Vo[Fo][:, :, 1] - 0.2) / 0.5], 2)
-        V = np.concatenate([V, Vo])
-        F = np.concatenate([F, Fo + (n + 1) ** 2])
-        UV = np.concatenate([UV, uvo])
-    return V.astype(np.float32), F.astype(np.int32), np.ascontiguousarray(UV, np.float32)
 
 
 def test_plane_projection_and_incidence_closed_form(oracle_lib):

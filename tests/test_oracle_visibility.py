@@ -179,3 +179,19 @@ def test_camera_rays_at_equals_full(oracle_lib):
     which = np.array([0, 7, 143, 144, 500, 5 * 144 - 1])
     P2, D2 = oracle_lib.camera_rays(eyes, [0.1, 0, 0], TAN30, 12, which=which)
     assert np.array_equal(P2, P[which]) and np.array_equal(D2, D[which])
+
+
+def test_camera_helper_axis_tie_is_exact(oracle_lib):
+    """|target_x - eye_x| = |target_z - eye_z| exactly: the helper axis is x
+    (the lower index), decided on the float differences themselves."""
+    eye = np.array([[-0.75, -0.875, 1.25]], np.float32)
+    tg = np.array([0.5, 0.5, 0.0])
+    P, D = oracle_lib.camera_rays(eye, tg, TAN30, 4)
+    f = tg - eye[0].astype(np.float64)
+    f /= np.linalg.norm(f)
+    r = np.cross(f, [1.0, 0.0, 0.0])
+    r /= np.linalg.norm(r)
+    u = np.cross(r, f)
+    x = y = (1 - 1 / 4) * TAN30  # pixel (0, 3): x = +, y = +
+    d = f + x * r + y * u
+    assert np.allclose(D.reshape(4, 4, 3)[0, 3], d / np.linalg.norm(d), atol=1e-15)
