@@ -212,7 +212,7 @@ int32_t bake_visibility(const float *V, const int32_t *F, int64_t n_v, int64_t n
  * bake_visibility (eyes, target, tan_half_fov, img_res x img_res pixels).
  * Depth buffer of view k: per pixel, the view-axis depth t (d . f) of the
  * pixel ray's first hit on the mesh (+inf where it hits nothing, t in
- * (0, t_far]).  Per texel and view, with q = p - e_k and z = q . f:
+ * (0, t_far]); depth_out receives the hit distances t themselves.  Per texel and view, with q = p - e_k and z = q . f:
  *   image coordinates col = (q.r / (z tan_half) + 1) img_res / 2 - 1/2,
  *   row = (1 - q.u / (z tan_half)) img_res / 2 - 1/2 (pixel centres at
  *   integers), or (-1, -1) when z <= 0 or either lies outside
@@ -224,7 +224,8 @@ int32_t bake_visibility(const float *V, const int32_t *F, int64_t n_v, int64_t n
  * [n_views,3] f32: device.  target: HOST pointer to 3 floats.  Outputs
  * (device, caller-owned): uv_out [n_views][res*res][2] f32 (col, row),
  * inc_out [n_views][res*res] f32 (uncovered texels: (-1, -1) and 0),
- * depth_out NULL or [n_views][img_res][img_res] f32.  flags: BAKE_FLAG_COUNT
+ * depth_out NULL or [n_views][img_res][img_res] f32 (first-hit distance t of
+ * each pixel ray, +inf for none).  flags: BAKE_FLAG_COUNT
  * (box / triangle tests and wave trips of the depth rays, bake_read_counter
  * 1-3), BAKE_FLAG_TIMING (bake_stage_times: G-buffer, BVH build, depth rays,
  * maps, -, total).

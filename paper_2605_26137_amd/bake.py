@@ -632,7 +632,7 @@ def view_maps_workspace_size(n_v: int, n_f: int, res: int, n_views: int, img_res
 class ViewMapsResult:
     uv: torch.Tensor               # [n_views, res, res, 2] image coordinates (col, row); (-1, -1) outside
     inc: torch.Tensor              # [n_views, res, res] incidence after the visibility test
-    depth: Optional[torch.Tensor]  # [n_views, img_res, img_res] view-axis depth buffers when asked for
+    depth: Optional[torch.Tensor]  # [n_views, img_res, img_res] first-hit distances of the pixel rays when asked for
     workspace: torch.Tensor
 
     def counter(self, which: int, stream=None) -> int:

@@ -303,7 +303,7 @@ struct VisRun {
     int32_t n_views, res;
     uint32_t* visible;   // device [n_f] flags, set to 1 for every first-hit face
     int32_t* first_hit;  // NULL or device [n_views res^2]
-    float* depth;        // NULL or device [n_views res^2]: view-axis depth of the first hit, +inf none
+    float* depth;        // NULL or device [n_views res^2]: first-hit distance along the ray, +inf none
     int32_t* spill;      // [kMaxDepth][spill_lanes]
     int64_t spill_lanes;
     bool count;          // instrumented: box / triangle tests and wave trips into asset 0's counters
@@ -316,7 +316,7 @@ struct MapRun {
     float target[3];
     float tan_half;
     int32_t n_views, img_res;
-    const float* depth;  // device [n_views][img_res^2]
+    const float* depth;  // device [n_views][img_res^2]: first-hit distances along the pixel rays
     float tol;
     float* uv_out;       // device [n_views][res^2][2], pre-filled with -1
     float* inc_out;      // device [n_views][res^2], pre-filled with 0

@@ -709,7 +709,7 @@ struct VisArgs {
     int32_t n_views, res;
     uint32_t* visible;   // NULL: no visibility flags
     int32_t* first_hit;  // NULL or per pixel
-    float* depth;        // NULL or per pixel: view-axis depth of the first hit, +inf for none
+    float* depth;        // NULL or per pixel: distance t of the first hit along the ray, +inf for none
 };
 
 // The pinhole frame of a view (forward, right, up; see visibility_kernel).
@@ -730,6 +730,22 @@ __device__ __forceinline__ void view_frame(float3 e, float3 target, float3* f_ou
     *f_out = f;
     *r_out = r;
     *u_out = cross3(r, f);
+}
+
+// Eye, unit direction and view forward of pixel p of view v.
+__device__ __forceinline__ void pixel_ray(const VisArgs& a, int32_t v, int64_t p, float3* e_out, float3* d_out,
+                                          float3* f_out) {
+    const float3 e = ld3(a.eyes, v);
+    float3 f, r, u;
+    view_frame(e, a.target, &f, &r, &u);
+    const int32_t i = (int32_t)(p / a.res), j = (int32_t)(p - (int64_t)i * a.res);
+    const float x = (((float)j + 0.5f) * 2.0f / (float)a.res - 1.0f) * a.tan_half;
+    const float y = (1.0f - ((float)i + 0.5f) * 2.0f / (float)a.res) * a.tan_half;
+    float3 d = f3(f.x + x * r.x + y * u.x, f.y + x * r.y + y * u.y, f.z + x * r.z + y * u.z);
+    const float rd = 1.0f / sqrtf(dot3(d, d));
+    *e_out = e;
+    *d_out = f3(d.x * rd, d.y * rd, d.z * rd);
+    *f_out = f;
 }
 
 template <int BLOCK, int STACK, bool COUNT>
@@ -753,16 +769,12 @@ __global__ __launch_bounds__(BLOCK) void visibility_kernel(VisArgs a) {
         const int32_t v = (int32_t)(it / bpv);
         const int64_t p = (it - (int64_t)v * bpv) * 64 + lane;
         const bool valid = p < px;
-        const float3 e = ld3(a.eyes, v);
-        float3 f, r, u;
-        view_frame(e, a.target, &f, &r, &u);
-        const int32_t i = (int32_t)(p / a.res), j = (int32_t)(p - (int64_t)i * a.res);
-        const float x = (((float)j + 0.5f) * 2.0f / (float)a.res - 1.0f) * a.tan_half;
-        const float y = (1.0f - ((float)i + 0.5f) * 2.0f / (float)a.res) * a.tan_half;
-        float3 d = f3(f.x + x * r.x + y * u.x, f.y + x * r.y + y * u.y, f.z + x * r.z + y * u.z);
-        const float rd = 1.0f / sqrtf(dot3(d, d));
-        d = f3(d.x * rd, d.y * rd, d.z * rd);
-        const RayT R = make_rayt(e, d);
+        RayT R;
+        {
+            float3 e, d, f;
+            pixel_ray(a, v, p, &e, &d, &f);
+            R = make_rayt(e, d);
+        }
         int32_t node = valid ? tv.root : kEmpty;
         Best best;
         reset_best(best, tv.max_dist);
@@ -790,7 +802,7 @@ __global__ __launch_bounds__(BLOCK) void visibility_kernel(VisArgs a) {
         if (valid) {
             const int32_t id = best.id == INT32_MAX ? -1 : best.id;
             if (a.first_hit) a.first_hit[(int64_t)v * px + p] = id;
-            if (a.depth) a.depth[(int64_t)v * px + p] = id >= 0 ? best.t * dot3(d, f) : INFINITY;
+            if (a.depth) a.depth[(int64_t)v * px + p] = id >= 0 ? best.t : INFINITY;
             if (id >= 0 && a.visible) a.visible[id] = 1u;
         }
     }
@@ -818,7 +830,7 @@ struct MapArgs {
     float3 target;
     float tan_half;
     int32_t n_views, img_res;
-    const float* depth;  // [n_views][img_res^2]
+    const float* depth;  // [n_views][img_res^2] first-hit distances along the pixel rays
     float tol;
     float* uv_out;       // [n_views][res^2][2]
     float* inc_out;      // [n_views][res^2]
@@ -862,7 +874,11 @@ __global__ __launch_bounds__(256) void view_map_kernel(MapArgs a) {
                 if (ok) {
                     const int32_t pi = min(max((int32_t)floorf(w + 0.5f), 0), a.img_res - 1);
                     const int32_t pj = min(max((int32_t)floorf(c + 0.5f), 0), a.img_res - 1);
-                    const float zb = a.depth[(int64_t)k * px + (int64_t)pi * a.img_res + pj];
+                    // the pixel ray's hit distance to view-axis depth: d . f =
+                    // 1 / |f + x r + y u| = 1 / sqrt(1 + x^2 + y^2)
+                    const float x = (((float)pj + 0.5f) / half - 1.0f) * a.tan_half;
+                    const float y = (1.0f - ((float)pi + 0.5f) / half) * a.tan_half;
+                    const float zb = a.depth[(int64_t)k * px + (int64_t)pi * a.img_res + pj] / sqrtf(1.0f + x * x + y * y);
                     if (!(z > zb + a.tol)) {
                         const float3 dk = f3(-q.x, -q.y, -q.z);
                         const float cs = dot3(n, dk) / sqrtf(dot3(dk, dk));

@@ -56,14 +56,15 @@ def compare(oracle_lib, V, F, UV, res, eyes, target, tan_half, img_res, t_far, t
     unc[tex] = False
     assert np.all(g_uv[:, unc] == -1) and np.all(g_inc[:, unc] == 0)
     g_uv, g_inc = g_uv[:, tex], g_inc[:, tex]
-    # depth buffers: view-axis depth of each pixel's first hit
+    # depth buffers: each pixel ray's first-hit distance (the GPU's output) and
+    # its view-axis depth (the oracle's comparison value)
     f = np.asarray(target, np.float64)[None, :] - eyes.astype(np.float64)
     f /= np.linalg.norm(f, axis=1, keepdims=True)
     _, Dc = oracle_lib.camera_rays(eyes, target, tan_half, img_res)
-    o_dep = np.where(om.ray_t > 0, om.ray_t * np.einsum("kpj,kj->kp", Dc.reshape(K, -1, 3), f).reshape(om.ray_t.shape),
-                     np.inf)
+    o_t = np.where(om.ray_t > 0, om.ray_t, np.inf)
+    o_dep = o_t * np.einsum("kpj,kj->kp", Dc.reshape(K, -1, 3), f).reshape(om.ray_t.shape)
     with np.errstate(invalid="ignore"):
-        dep_ok = (np.isinf(o_dep) & np.isinf(g_dep)) | (np.abs(o_dep - g_dep) <= 1e-5 * t_far)
+        dep_ok = (np.isinf(o_t) & np.isinf(g_dep)) | (np.abs(o_t - g_dep) <= 1e-5 * t_far)
     say(f"[gpu] depth pixels agree {dep_ok.mean():.6f}")
     assert dep_ok.mean() >= 0.999
     # image coordinates
