@@ -10,7 +10,11 @@ A step is one pass of the whole path through the C ABI: the forward bake
 (low-poly prep, UV raster, LBVH build over the high-poly, traversal + tangent-
 space encode, dilation) with its state saved, the squared-error loss against a
 target map baked from a second noise seed, and the backward pass to dL/dlo_V
-and dL/dhi_N.  value = covered-texel rays per second of the whole step.
+and dL/dhi_N.  value = covered-texel rays per second of the whole step.  The
+step is first timed as plain API calls (which also gives the per-stage
+times), then recorded once into a HIP graph and replayed K times; the replays
+must reproduce the eager outputs bitwise, and their time is the reported one
+(--eager reports the plain calls instead).
 
 Besides the JSON line's required fields it reports:
   roofline      the dominant kernel (traversal) against the VALU issue peak,
@@ -81,6 +85,19 @@ def measured_traffic(kernel_hash):
     return d.get("bytes_per_launch")
 
 
+def sized_sample(run, pilot, limit, target_s):
+    """Grow a sample until one run of the oracle takes about target_s seconds
+    (a small pilot overstates the per-item time: fixed set-up cost, idle
+    threads); returns (n, seconds) of the last run."""
+    n, dt = pilot, run(pilot)
+    for _ in range(3):
+        if dt >= 0.6 * target_s or n >= limit:
+            break
+        n = int(min(limit, max(n + 1, n * target_s / max(dt, 1e-3))))
+        dt = run(n)
+    return n, dt
+
+
 def cpu_baseline(asset, target_s, max_dist, kind):
     """The oracle as it stands (FP64 brute force over every triangle) on a
     seeded sample of the workload's covered texels (forward query: the
@@ -98,9 +115,7 @@ def cpu_baseline(asset, target_s, max_dist, kind):
         oracle.bake(asset, method="brute", texels=sample, kind=kind, max_dist=max_dist)
         return time.perf_counter() - t0
 
-    t_small = run(64)
-    n = int(max(64, min(cov.size, 64 * target_s / max(t_small, 1e-3))))
-    dt = run(n)
+    n, dt = sized_sample(run, 64, cov.size, target_s)
     return {"value": n / dt, "unit": "rays/s", "cores": cores, "kind": "oracle",
             "sample": f"{n} seeded covered texels of {cov.size}, FP64 brute-force {kind} query over all "
                       f"{asset.hi_F.shape[0]} triangles, {dt:.1f} s"}
@@ -179,9 +194,7 @@ def bench_visibility(args, B, log):
             oracle.first_hit(V, F, P, D, t_far, "brute")
             return time.perf_counter() - t1
 
-        t_small = run(256)
-        n = int(max(256, min(rays, 256 * args.cpu_seconds / max(t_small, 1e-3))))
-        dt = run(n)
+        n, dt = sized_sample(run, 256, rays, args.cpu_seconds)
         out_json["cpu_baseline"] = {"value": n / dt, "unit": "rays/s", "cores": cores, "kind": "oracle",
                                     "sample": f"{n} seeded camera rays of {rays}, FP64 brute-force first hit over "
                                               f"all {F.shape[0]} triangles, {dt:.1f} s"}
@@ -255,6 +268,21 @@ def bench_view_maps(args, B, log):
                        "achieved_GBps": map_bytes / (stage_ms["maps"] / 1e3) / 1e9, "peak_GBps": 8000.0},
         "paper_context_s": 1.455,
     }
+    if not args.no_cpu_baseline:
+        # the oracle on the whole workload (its own FP64 BVH for the depth
+        # rays), repeated until about cpu_seconds have passed
+        import oracle
+        cores = oracle.set_threads(0)
+        reps, t1 = 0, time.perf_counter()
+        while reps == 0 or time.perf_counter() - t1 < args.cpu_seconds:
+            vm = oracle.view_maps(V, F, UV, res, eyes, [0, 0, 0], tan_half, img, t_far, tol)
+            reps += 1
+        dt = time.perf_counter() - t1
+        out_json["cpu_baseline"] = {"value": reps * vm.texels.size * K / dt, "unit": "texel-views/s",
+                                    "cores": cores, "kind": "oracle",
+                                    "sample": f"the whole workload x {reps} ({vm.texels.size} covered texels x {K} "
+                                              f"views, {K} depth buffers of {img}^2 by the oracle's FP64 BVH), "
+                                              f"{dt:.1f} s"}
     return out_json
 
 
@@ -360,7 +388,9 @@ def main():
     ap.add_argument("--batch-assets", type=int, default=0, metavar="N",
                     help="also measure an N-asset batch (64 = the uneven batch workload)")
     ap.add_argument("--batch-steps", type=int, default=5)
-    ap.add_argument("--graph", action="store_true", help="also time the step replayed from a HIP graph")
+    ap.add_argument("--eager", action="store_true",
+                    help="time plain per-step API calls only (default: also record the step into a HIP graph "
+                         "and report the replayed step)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -441,11 +471,12 @@ def main():
         step(True, k)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    graph_ms = None
-    if args.graph:
-        # the same step recorded once into a HIP graph and replayed: no host
-        # launch work per kernel
+    eager_ms = (t1 - t0) * 1e3 / args.steps
+    graph_ms, graph_equal = None, None
+    if not args.eager:
+        # the same step recorded once into a HIP graph and replayed (no host
+        # work per kernel); the replays must reproduce the eager outputs
+        ref = [x.clone() for x in ((out_map, glo, ghi) if not closest else (out_map,))]
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
@@ -463,11 +494,15 @@ def main():
             g.replay()
         torch.cuda.synchronize()
         graph_ms = (time.perf_counter() - tg) * 1e3 / args.steps
-        log(f"[bench] graph-replayed step: {graph_ms:.3f} ms")
+        got = (out_map, glo, ghi) if not closest else (out_map,)
+        graph_equal = all(torch.equal(a.view(torch.int32), b.view(torch.int32)) for a, b in zip(ref, got))
+        log(f"[bench] graph-replayed step: {graph_ms:.3f} ms (outputs equal to the eager step: {graph_equal})")
+        assert graph_equal, "graph replay changed the results"
+    ms_per_step = graph_ms if graph_ms is not None else eager_ms
     hist = B.stage_history(min(args.steps, 64))
     stage_ms = {name: float(np.mean(hist[:, k])) for k, name in enumerate(B.STAGES)}
     bwd_ms = float(np.mean([ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(args.steps)]))
-    log(f"[bench] {args.steps} steps, {ms_per_step:.3f} ms/step, stages {stage_ms}, loss+backward {bwd_ms:.3f} ms")
+    log(f"[bench] {args.steps} eager steps, {eager_ms:.3f} ms/step, stages {stage_ms}, loss+backward {bwd_ms:.3f} ms")
 
     # algorithmic op count of the traversal: one instrumented bake, untimed
     cnt = B.bake_normals(*t, res, md, count=True, workspace=ws, out_map=out_map, out_hit=out_hit, **trav)
@@ -508,9 +543,12 @@ def main():
                    "rays": rays, "texels": res * res,
                    "hi_tris": int(asset.hi_F.shape[0]), "lo_tris": int(asset.lo_F.shape[0]),
                    "step": ("forward bake incl. BVH build (closest-point query: no backward)" if closest else
-                            "forward bake incl. BVH build + squared-error loss + backward")},
+                            "forward bake incl. BVH build + squared-error loss + backward"),
+                   "launch": ("the whole step recorded once into a HIP graph and replayed" if graph_ms is not None
+                              else "plain API calls per step")},
         "fwd_bwd_ms": ms_per_step,
-        "graph_ms_per_step": graph_ms,
+        "eager_ms_per_step": eager_ms,
+        "graph_equal_to_eager": graph_equal,
         "fwd_ms": stage_ms["forward"],
         "loss_bwd_ms": bwd_ms,
         "fwd_rays_per_s": rays / (stage_ms["forward"] / 1e3),
