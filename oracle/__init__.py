@@ -27,6 +27,12 @@ sided), the per-face visibility mask, and the flood fill over shared edges
 gated by the face normals (``camera_rays``, ``first_hit``, ``visibility``,
 ``flood_fill``; ``oracle.c`` states the readings).
 
+Mesh simplification (Sec. 6.1) lives in ``qem.c``: per-vertex quadrics, the
+edge-constrained optimal placement, a serial greedy driver and the parallel
+round schedule (``qem_quadrics``, ``qem_edges``, ``qem_simplify``), and a
+sampled surface distance between two meshes (``mesh_distance``) for the
+quality comparisons the section makes.
+
 Parity unpinned: none of the paper's own quality numbers (its 50-asset
 benchmark) can be reproduced here; every other function has a pin in
 ``tests/test_oracle.py``.
@@ -42,7 +48,7 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "oracle.c")
+_SRC = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "qem.c")]
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -50,11 +56,11 @@ ST_MISS, ST_UNREL, ST_UNCOV = -1, -2, -3
 
 
 def build(force: bool = True) -> str:
-    """Compile oracle.c with gcc (FP64, no fast-math, no FP contraction)."""
+    """Compile oracle.c and qem.c with gcc (FP64, no fast-math, no FP contraction)."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
         cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-               "-shared", "-Wall", "-o", tmp, _SRC, "-lm"]
+               "-shared", "-Wall", "-o", tmp, *_SRC, "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -410,3 +416,90 @@ def view_maps(V, F, UV, res, eyes, target, tan_half, img_res, t_far, tol, method
           C.c_double(tan_half), C.c_int32(img_res), _p(t), C.c_double(tol), _p(uv), _p(inc))
     return ViewMaps(texels, P, N, ok, t.reshape(K, img_res, img_res), ids.reshape(K, img_res, img_res), uv, inc)
 
+
+
+# ------------------------------------------------------------ simplification
+
+def qem_quadrics(V, F):
+    """Per-vertex quadrics [nv, 10] (q00 q01 q02 q03 q11 q12 q13 q22 q23 q33)."""
+    V = _c(V, np.float32); F = _c(F, np.int32)
+    Q = np.zeros((V.shape[0], 10))
+    _call("orc_qem_quadrics", _p(V), C.c_int64(V.shape[0]), _p(F), C.c_int64(F.shape[0]), _p(Q))
+    return Q
+
+
+@dataclass
+class QemEdges:
+    edges: np.ndarray    # [ne, 2] int32, v0 < v1, in (v0, v1) order
+    valid: np.ndarray    # [ne] bool
+    faces: np.ndarray    # [ne] faces of the edge (= faces a collapse removes)
+    cost: np.ndarray     # [ne] float64
+    p: np.ndarray        # [ne, 3] float64 placement
+
+
+def qem_edges(V, F, Q=None, midpoint=False):
+    """Every edge of the mesh (FP64 positions; vertex quadrics Q, default from
+    the faces) with its collapse evaluated (placement, cost, validity)."""
+    V = _c(V, np.float64); F = _c(F, np.int32)
+    Qc = None if Q is None else _c(Q, np.float64)
+    cap = 3 * F.shape[0] + 16
+    E = np.zeros((cap, 2), np.int32); ok = np.zeros(cap, np.uint8); nf = np.zeros(cap, np.int32)
+    cost = np.zeros(cap); P = np.zeros((cap, 3)); n = np.zeros(1, np.int64)
+    _call("orc_qem_edges", _p(V), C.c_int64(V.shape[0]), _p(F), C.c_int64(F.shape[0]), _p(Qc),
+          C.c_int32(int(midpoint)), C.c_int64(cap), _p(E), _p(ok), _p(nf), _p(cost), _p(P), _p(n))
+    k = int(n[0])
+    return QemEdges(E[:k], ok[:k].astype(bool), nf[:k], cost[:k], P[:k])
+
+
+@dataclass
+class QemResult:
+    V: np.ndarray        # [nv', 3] float64
+    F: np.ndarray        # [nf', 3] int32
+    rounds: int          # rounds run (round schedule) or collapses (greedy)
+    stats: np.ndarray    # [rounds, 4]: edges, valid edges, collapses, faces after (round schedule)
+
+
+def qem_simplify(V, F, target, method="rounds", rho=0.25, max_rounds=1000, midpoint=False) -> QemResult:
+    """Simplify to `target` faces: the parallel round schedule or the serial
+    greedy order (``qem.c`` states both)."""
+    V = _c(V, np.float32); F = _c(F, np.int32)
+    nv, nf = V.shape[0], F.shape[0]
+    Vo = np.zeros((max(nv, 1), 3)); Fo = np.zeros((max(nf, 1), 3), np.int32); cnt = np.zeros(2, np.int64)
+    if method == "rounds":
+        st = np.zeros((max(max_rounds, 1), 4), np.int64); nr = np.zeros(1, np.int32)
+        _call("orc_qem_rounds", _p(V), C.c_int64(nv), _p(F), C.c_int64(nf), C.c_int64(target), C.c_double(rho),
+              C.c_int32(max_rounds), C.c_int32(int(midpoint)), _p(Vo), _p(Fo), _p(cnt), _p(st), _p(nr))
+        r = int(nr[0])
+        return QemResult(Vo[:cnt[0]], Fo[:cnt[1]], r, st[:r])
+    if method == "greedy":
+        done = np.zeros(1, np.int64)
+        _call("orc_qem_greedy", _p(V), C.c_int64(nv), _p(F), C.c_int64(nf), C.c_int64(target),
+              C.c_int32(int(midpoint)), _p(Vo), _p(Fo), _p(cnt), _p(done))
+        return QemResult(Vo[:cnt[0]], Fo[:cnt[1]], int(done[0]), np.zeros((0, 4), np.int64))
+    raise ValueError(method)
+
+
+def sample_surface(V, F, n, seed):
+    """n points uniformly by area on the mesh (seeded)."""
+    V = np.asarray(V, np.float64); F = np.asarray(F, np.int64)
+    a, b, c = V[F[:, 0]], V[F[:, 1]], V[F[:, 2]]
+    area = 0.5 * np.linalg.norm(np.cross(b - a, c - a), axis=1)
+    rng = np.random.default_rng(seed)
+    f = rng.choice(F.shape[0], size=n, p=area / area.sum())
+    r1, r2 = rng.random(n), rng.random(n)
+    s = np.sqrt(r1)
+    return (1 - s)[:, None] * a[f] + (s * (1 - r2))[:, None] * b[f] + (s * r2)[:, None] * c[f]
+
+
+def mesh_distance(VA, FA, VB, FB, n=4000, seed=0):
+    """Two-sided sampled surface distance: (Chamfer = mean of the two mean
+    point-to-surface distances, Hausdorff = the larger maximum)."""
+    out = []
+    both = np.concatenate([np.asarray(VA, np.float64), np.asarray(VB, np.float64)])
+    reach = 2.0 * float(np.linalg.norm(both.max(0) - both.min(0)))   # beyond any distance between them
+    for (V1, F1, V2, F2, sd) in ((VA, FA, VB, FB, seed), (VB, FB, VA, FA, seed + 1)):
+        P = sample_surface(V1, F1, n, sd)
+        ids, d, _ = closest(np.asarray(V2, np.float32), F2, P, reach, method="bvh")
+        assert (ids >= 0).all()
+        out.append(d)
+    return 0.5 * (out[0].mean() + out[1].mean()), max(out[0].max(), out[1].max())
