@@ -357,6 +357,71 @@ int32_t bake_autotune(const bake_asset *assets, int32_t n_assets, const bake_opt
                       void *workspace, size_t workspace_bytes, void *stream, bake_options *best_out,
                       float *ms_out);
 
+/* ---- mesh simplification (Sec. 6.1) ------------------------------------
+ *
+ * Quadric-error edge collapse with the edge-constrained optimal placement:
+ * every vertex carries the quadric of its faces' planes; collapsing edge
+ * (v0, v1) costs min E over the placement under Q = Q_v0 + Q_v1; an interior
+ * edge is placed at the solution of A x = -b projected onto the edge
+ * (t = <x - v0, v1 - v0> / |v1 - v0|^2 clamped to [0, 1]), at the midpoint
+ * when A is singular (det A <= 1e-8 (trace A)^3); boundary vertices stay put
+ * and a boundary edge keeps its endpoint of lower error; the same placement
+ * ranks and collapses.  A collapse is allowed when the edge has one or two
+ * faces, the endpoint rings share exactly that many vertices, the endpoints
+ * are not both of three neighbours, an interior edge does not join two
+ * boundary vertices, and no face around an endpoint turns its normal to a
+ * non-positive dot with the old one.  All of this is FP64.
+ *
+ * Collapses run in rounds over the whole mesh: edges numbered in (v0, v1)
+ * order take the key (float32(cost) bits, number); the eligible edges are the
+ * allowed ones with float32 cost at most the k-th smallest, k = ceil(rho *
+ * allowed); an eligible edge collapses when its key is the least among the
+ * eligible edges at its endpoints and at their neighbours, so the collapses of
+ * a round touch disjoint faces; if they would remove more faces than remain
+ * above target_faces, only the prefix in key order that fits is applied.  v0
+ * (the lower index) survives at the placement with Q_v0 + Q_v1; faces holding
+ * both endpoints disappear.  Rounds end when the face count reaches
+ * target_faces, when nothing collapses, or after max_rounds.
+ *
+ * V [n_v,3] f32 and F [n_f,3] i32: device, read only.  Outputs, device and
+ * caller-owned: V_out [n_v,3] f32 and F_out [n_f,3] i32 receive the result
+ * (the surviving vertices referenced by a face in ascending input index,
+ * positions rounded from FP64 to f32; the surviving faces in their input
+ * order, renumbered).  HOST outputs: counts_out[2] = (vertices, faces) of the
+ * result, *rounds_out = rounds run, stats_out NULL or [max_rounds][4] per
+ * round (edges, allowed edges, collapses, faces after the round).
+ * flags: BAKE_QEM_MIDPOINT places interior edges at their midpoint (the
+ * original placement the section compares against).  Workspace >=
+ * bake_qem_workspace_size bytes, 256-byte aligned, overwritten; nothing is
+ * allocated.  Unlike the bake, these calls are BLOCKING: the number of rounds
+ * depends on the data, so the stream is synchronised once per round to read
+ * its counts; they return once the outputs are written.
+ * Errors: BAKE_E_INVALID_ARG (NULL pointers, negative counts, target_faces < 4,
+ * rho outside (0, 1], max_rounds < 0), BAKE_E_UNSUPPORTED (n_v or n_f >= 2^28),
+ * BAKE_E_INDEX (a face with an index outside [0, n_v) or a repeated vertex),
+ * BAKE_E_WORKSPACE, BAKE_E_HIP. */
+#define BAKE_QEM_MIDPOINT 1u
+
+int32_t bake_qem_workspace_size(int64_t n_v, int64_t n_f, size_t *bytes_out);
+int32_t bake_qem_simplify(const float *V, const int32_t *F, int64_t n_v, int64_t n_f, int64_t target_faces,
+                          double rho, int32_t max_rounds, uint32_t flags, float *V_out, int32_t *F_out,
+                          int64_t *counts_out, int32_t *rounds_out, int64_t *stats_out, void *workspace,
+                          size_t workspace_bytes, void *stream);
+
+/* Every edge of the input mesh with its collapse evaluated, as the first
+ * round of bake_qem_simplify sees it.  Device outputs (caller-owned, `cap`
+ * rows): edges_out [cap][2] i32 (v0 < v1, in (v0, v1) order), valid_out [cap]
+ * u8 (the collapse is allowed), faces_out [cap] i32 (faces on the edge),
+ * cost_out [cap] f64 (max(E(p), 0); 0 where no placement was computed),
+ * p_out [cap][3] f64 (the placement; zeros where none), Q_out NULL or
+ * [n_v][10] f64 (vertex quadrics q00 q01 q02 q03 q11 q12 q13 q22 q23 q33).
+ * HOST output *n_edges_out = number of edges; when it exceeds cap nothing is
+ * written and the call fails with BAKE_E_INVALID_ARG.  BLOCKING.  Same
+ * workspace and errors as bake_qem_simplify. */
+int32_t bake_qem_edges(const float *V, const int32_t *F, int64_t n_v, int64_t n_f, uint32_t flags, int64_t cap,
+                       int32_t *edges_out, uint8_t *valid_out, int32_t *faces_out, double *cost_out, double *p_out,
+                       double *Q_out, int64_t *n_edges_out, void *workspace, size_t workspace_bytes, void *stream);
+
 /* Thread-local message of the last error on this thread ("" if none). */
 const char *bake_last_error(void);
 

@@ -123,6 +123,13 @@ _EXPORTS = {
                                    C.c_void_p, C.c_int32, C.POINTER(C.c_float), C.c_float, C.c_int32, C.c_float,
                                    C.c_float, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_size_t, C.c_void_p]),
+    "bake_qem_workspace_size": (C.c_int32, [C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
+    "bake_qem_simplify": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_double,
+                                      C.c_int32, C.c_uint32, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_int32), C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "bake_qem_edges": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_uint32, C.c_int64,
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.POINTER(C.c_int64), C.c_void_p, C.c_size_t, C.c_void_p]),
     "bake_stage_times": (C.c_int32, [C.POINTER(C.c_float), C.c_int32]),
     "bake_stage_history": (C.c_int32, [C.POINTER(C.c_float), C.c_int32]),
     "bake_last_error": (C.c_char_p, []),
@@ -670,3 +677,86 @@ def view_maps(V, F, UV, res: int, eyes, target, tan_half: float, img_res: int, t
                                 _ptr(workspace), workspace.numel(), _stream_handle(stream)))
     return ViewMapsResult(uv, inc, dep, workspace)
 
+
+
+# ---------------------------------------------------------------------------
+# Mesh simplification (Sec. 6.1)
+# ---------------------------------------------------------------------------
+
+BAKE_QEM_MIDPOINT = 1
+
+
+def qem_workspace_size(n_v: int, n_f: int) -> int:
+    out = C.c_size_t(0)
+    _check(lib().bake_qem_workspace_size(int(n_v), int(n_f), C.byref(out)))
+    return out.value
+
+
+@dataclass
+class QemEdges:
+    edges: torch.Tensor   # [ne, 2] i32, v0 < v1 in (v0, v1) order
+    valid: torch.Tensor   # [ne] bool: the collapse is allowed
+    faces: torch.Tensor   # [ne] i32: faces on the edge
+    cost: torch.Tensor    # [ne] f64
+    p: torch.Tensor       # [ne, 3] f64 placement
+    Q: torch.Tensor       # [n_v, 10] f64 vertex quadrics
+
+
+def qem_edges(V, F, *, midpoint: bool = False, workspace: Optional[torch.Tensor] = None, stream=None) -> QemEdges:
+    """Every edge of the mesh (GPU tensors V [n_v,3] f32, F [n_f,3] i32) with
+    its collapse evaluated, as the first simplification round sees it."""
+    V = _dev_tensor(V, torch.float32, "V", (3,))
+    F = _dev_tensor(F, torch.int32, "F", (3,))
+    dev = V.device
+    nv, nf = V.shape[0], F.shape[0]
+    if workspace is None:
+        workspace = torch.empty(qem_workspace_size(nv, nf), dtype=torch.uint8, device=dev)
+    cap = 3 * nf
+    E = torch.empty((cap, 2), dtype=torch.int32, device=dev)
+    ok = torch.empty(cap, dtype=torch.uint8, device=dev)
+    fc = torch.empty(cap, dtype=torch.int32, device=dev)
+    cost = torch.empty(cap, dtype=torch.float64, device=dev)
+    P = torch.empty((cap, 3), dtype=torch.float64, device=dev)
+    Q = torch.empty((nv, 10), dtype=torch.float64, device=dev)
+    n = C.c_int64(0)
+    _check(lib().bake_qem_edges(_ptr(V), _ptr(F), nv, nf, BAKE_QEM_MIDPOINT if midpoint else 0, cap, _ptr(E),
+                                _ptr(ok), _ptr(fc), _ptr(cost), _ptr(P), _ptr(Q), C.byref(n), _ptr(workspace),
+                                workspace.numel(), _stream_handle(stream)))
+    k = n.value
+    return QemEdges(E[:k], ok[:k].bool(), fc[:k], cost[:k], P[:k], Q)
+
+
+@dataclass
+class QemResult:
+    V: torch.Tensor        # [n_v', 3] f32
+    F: torch.Tensor        # [n_f', 3] i32
+    rounds: int
+    stats: "numpy.ndarray"  # [rounds, 4]: edges, allowed edges, collapses, faces after the round
+
+
+def qem_simplify(V, F, target: int, *, rho: float = 0.25, max_rounds: int = 1000, midpoint: bool = False,
+                 workspace: Optional[torch.Tensor] = None, out: Optional[tuple] = None, stream=None) -> QemResult:
+    """Simplify the mesh (GPU tensors V [n_v,3] f32, F [n_f,3] i32) to `target`
+    faces by rounds of quadric edge collapses (blocking).  out: optional
+    preallocated (V_out [n_v,3] f32, F_out [n_f,3] i32)."""
+    import numpy as np
+    V = _dev_tensor(V, torch.float32, "V", (3,))
+    F = _dev_tensor(F, torch.int32, "F", (3,))
+    dev = V.device
+    nv, nf = V.shape[0], F.shape[0]
+    if workspace is None:
+        workspace = torch.empty(qem_workspace_size(nv, nf), dtype=torch.uint8, device=dev)
+    if out is None:
+        Vo = torch.empty((nv, 3), dtype=torch.float32, device=dev)
+        Fo = torch.empty((nf, 3), dtype=torch.int32, device=dev)
+    else:
+        Vo, Fo = out
+    counts = (C.c_int64 * 2)()
+    rounds = C.c_int32(0)
+    stats = np.zeros((max(int(max_rounds), 1), 4), np.int64)
+    _check(lib().bake_qem_simplify(_ptr(V), _ptr(F), nv, nf, int(target), float(rho), int(max_rounds),
+                                   BAKE_QEM_MIDPOINT if midpoint else 0, _ptr(Vo), _ptr(Fo), counts,
+                                   C.byref(rounds), stats.ctypes.data, _ptr(workspace), workspace.numel(),
+                                   _stream_handle(stream)))
+    r = rounds.value
+    return QemResult(Vo[:counts[0]], Fo[:counts[1]], r, stats[:r])

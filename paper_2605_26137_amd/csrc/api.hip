@@ -1030,4 +1030,74 @@ int32_t bake_stage_history(float* ms_out, int32_t max_bakes) {
     return m;
 }
 
+// ---- mesh simplification (Sec. 6.1) ---------------------------------------
+
+int32_t bake_qem_workspace_size(int64_t n_v, int64_t n_f, size_t* bytes_out) {
+    g_err[0] = 0;
+    if (!bytes_out) return fail(BAKE_E_INVALID_ARG, "bytes_out is NULL");
+    if (n_v < 0 || n_f < 0) return fail(BAKE_E_INVALID_ARG, "negative count");
+    if (n_v >= ((int64_t)1 << 28) || n_f >= ((int64_t)1 << 28))
+        return fail(BAKE_E_UNSUPPORTED, "counts must be < 2^28");
+    QemLayout L;
+    *bytes_out = qem_layout(n_v, n_f, &L);
+    return BAKE_OK;
+}
+
+static int32_t qem_common(const float* V, const int32_t* F, int64_t n_v, int64_t n_f, uint32_t flags,
+                          void* workspace, size_t workspace_bytes, QemLayout* L) {
+    if (n_v < 0 || n_f < 0) return fail(BAKE_E_INVALID_ARG, "negative count");
+    if (n_v >= ((int64_t)1 << 28) || n_f >= ((int64_t)1 << 28))
+        return fail(BAKE_E_UNSUPPORTED, "counts must be < 2^28");
+    if (n_v > 0 && !V) return fail(BAKE_E_INVALID_ARG, "V is NULL");
+    if (n_f > 0 && !F) return fail(BAKE_E_INVALID_ARG, "F is NULL");
+    if ((flags & ~BAKE_QEM_MIDPOINT) != 0) return fail(BAKE_E_INVALID_ARG, "unknown flag bits 0x%x", flags);
+    const size_t need = qem_layout(n_v, n_f, L);
+    if (!workspace) return fail(BAKE_E_WORKSPACE, "workspace is NULL");
+    if (((uintptr_t)workspace & 255) != 0) return fail(BAKE_E_WORKSPACE, "workspace not 256-byte aligned");
+    if (workspace_bytes < need) return fail(BAKE_E_WORKSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    return BAKE_OK;
+}
+
+int32_t bake_qem_simplify(const float* V, const int32_t* F, int64_t n_v, int64_t n_f, int64_t target_faces,
+                          double rho, int32_t max_rounds, uint32_t flags, float* V_out, int32_t* F_out,
+                          int64_t* counts_out, int32_t* rounds_out, int64_t* stats_out, void* workspace,
+                          size_t workspace_bytes, void* stream) {
+    g_err[0] = 0;
+    if (target_faces < 4) return fail(BAKE_E_INVALID_ARG, "target_faces %lld < 4", (long long)target_faces);
+    if (!(rho > 0.0 && rho <= 1.0)) return fail(BAKE_E_INVALID_ARG, "rho must lie in (0, 1]");
+    if (max_rounds < 0) return fail(BAKE_E_INVALID_ARG, "max_rounds < 0");
+    if (!counts_out || !rounds_out) return fail(BAKE_E_INVALID_ARG, "counts_out / rounds_out is NULL");
+    if ((n_v > 0 && !V_out) || (n_f > 0 && !F_out)) return fail(BAKE_E_INVALID_ARG, "V_out / F_out is NULL");
+    QemLayout L;
+    int32_t rc = qem_common(V, F, n_v, n_f, flags, workspace, workspace_bytes, &L);
+    if (rc) return rc;
+    uint32_t status = 0;
+    HIP_OR_FAIL(qem_simplify_run(L, (char*)workspace, V, F, target_faces, rho, max_rounds,
+                                 (flags & BAKE_QEM_MIDPOINT) ? 1 : 0, V_out, F_out, counts_out, rounds_out, stats_out,
+                                 &status, (hipStream_t)stream));
+    if (status) return fail(BAKE_E_INDEX, "a face has an index outside [0, n_v) or a repeated vertex");
+    return BAKE_OK;
+}
+
+int32_t bake_qem_edges(const float* V, const int32_t* F, int64_t n_v, int64_t n_f, uint32_t flags, int64_t cap,
+                       int32_t* edges_out, uint8_t* valid_out, int32_t* faces_out, double* cost_out, double* p_out,
+                       double* Q_out, int64_t* n_edges_out, void* workspace, size_t workspace_bytes, void* stream) {
+    g_err[0] = 0;
+    if (!n_edges_out) return fail(BAKE_E_INVALID_ARG, "n_edges_out is NULL");
+    if (cap < 0) return fail(BAKE_E_INVALID_ARG, "cap < 0");
+    if (cap > 0 && (!edges_out || !valid_out || !faces_out || !cost_out || !p_out))
+        return fail(BAKE_E_INVALID_ARG, "an edge output is NULL");
+    QemLayout L;
+    int32_t rc = qem_common(V, F, n_v, n_f, flags, workspace, workspace_bytes, &L);
+    if (rc) return rc;
+    uint32_t status = 0;
+    HIP_OR_FAIL(qem_edges_run(L, (char*)workspace, V, F, (flags & BAKE_QEM_MIDPOINT) ? 1 : 0, Q_out, cap, edges_out,
+                              valid_out, faces_out, cost_out, p_out, &status, n_edges_out, (hipStream_t)stream));
+    if (status) return fail(BAKE_E_INDEX, "a face has an index outside [0, n_v) or a repeated vertex");
+    if (*n_edges_out > cap)
+        return fail(BAKE_E_INVALID_ARG, "the mesh has %lld edges, cap is %lld", (long long)*n_edges_out,
+                    (long long)cap);
+    return BAKE_OK;
+}
+
 }  // extern "C"

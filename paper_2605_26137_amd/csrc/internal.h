@@ -330,6 +330,23 @@ struct FillRun {
     uint8_t *visible_out, *exterior_out;
 };
 hipError_t launch_flood_fill(const BatchHost& H, const FillRun& f, hipStream_t s);
+// Quadric edge-collapse simplification (Sec. 6.1): workspace carving and the
+// two blocking drivers (they synchronise `s` to read the per-round counts).
+struct QemLayout {
+    int64_t nv, nf, edge_cap;
+    size_t cnt, hist, P, Q, F, F2, keep, koff, deg, off, cur, adj, ncnt, noff, hcnt, eoff, bnd, nbr, E, bits, faces,
+        pl, m, M, partner, win, scan_tmp;
+    size_t total;
+};
+size_t qem_layout(int64_t nv, int64_t nf, QemLayout* L);
+// Edges of the input mesh with their collapse evaluated; *status != 0 flags
+// bad faces, *n_edges > cap leaves the outputs untouched.
+hipError_t qem_edges_run(const QemLayout& L, char* ws, const float* V, const int32_t* F, int midpoint,
+                         double* Q_out, int64_t cap, int32_t* E_out, uint8_t* valid_out, int32_t* faces_out,
+                         double* cost_out, double* p_out, uint32_t* status, int64_t* n_edges, hipStream_t s);
+hipError_t qem_simplify_run(const QemLayout& L, char* ws, const float* V, const int32_t* F, int64_t target, double rho,
+                            int32_t max_rounds, int midpoint, float* V_out, int32_t* F_out, int64_t* counts,
+                            int32_t* rounds_out, int64_t* stats, uint32_t* status, hipStream_t s);
 hipError_t launch_dilate(const BatchHost& H, int passes, hipStream_t s);
 hipError_t launch_rgb8(const BatchHost& H, hipStream_t s);
 hipError_t launch_backward(const BatchHost& H, bool any_lo, bool any_hi, hipStream_t s);

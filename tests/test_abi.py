@@ -271,3 +271,51 @@ def test_view_maps_workspace_size(B):
     a = B.view_maps_workspace_size(1000, 2000, 256, 10, 256)
     b = B.view_maps_workspace_size(1000, 2000, 256, 10, 512)
     assert 0 < a < b and a % 256 == 0
+
+
+def _qem_call(B, **over):
+    """bake_qem_simplify with fake (never dereferenced) device pointers."""
+    fake = C.c_void_p(0x1000)
+    a = dict(V=fake, F=fake, nv=4, nf=4, target=4, rho=0.25, rounds=10, flags=0, Vo=fake, Fo=fake,
+             counts=(C.c_int64 * 2)(), nr=C.pointer(C.c_int32(0)), stats=None,
+             ws=C.c_void_p(0x100000), ws_bytes=1 << 40, stream=None)
+    a.update(over)
+    return B.lib().bake_qem_simplify(a["V"], a["F"], a["nv"], a["nf"], a["target"], a["rho"], a["rounds"],
+                                     a["flags"], a["Vo"], a["Fo"], a["counts"], a["nr"], a["stats"], a["ws"],
+                                     a["ws_bytes"], a["stream"])
+
+
+@pytest.mark.parametrize("over,code", [
+    (dict(V=None), -1), (dict(F=None), -1), (dict(Vo=None), -1), (dict(Fo=None), -1), (dict(counts=None), -1),
+    (dict(nr=None), -1), (dict(target=3), -1), (dict(rho=0.0), -1), (dict(rho=1.5), -1),
+    (dict(rho=float("nan")), -1), (dict(rounds=-1), -1), (dict(flags=2), -1), (dict(nv=-1), -1),
+    (dict(nf=1 << 28), -2), (dict(ws=None), -3), (dict(ws=C.c_void_p(0x100010)), -3), (dict(ws_bytes=1000), -3),
+])
+def test_qem_host_validation_codes(B, over, code):
+    rc = _qem_call(B, **over)
+    assert rc == code, B.lib().bake_last_error()
+    assert B.lib().bake_last_error()
+
+
+def test_qem_edges_host_validation_codes(B):
+    fake = C.c_void_p(0x1000)
+    n = C.c_int64(0)
+    L = B.lib()
+    names = ["V", "F", "nv", "nf", "flags", "cap", "E", "ok", "fc", "cost", "p", "Q", "n", "ws", "ws_bytes", "s"]
+    base = [fake, fake, 4, 4, 0, 12, fake, fake, fake, fake, fake, None, C.byref(n), C.c_void_p(0x100000), 1 << 40,
+            None]
+    for name, v, code in (("n", None, -1), ("cap", -1, -1), ("E", None, -1), ("nf", 1 << 28, -2),
+                          ("flags", 2, -1), ("ws", None, -3), ("ws_bytes", 100, -3)):
+        args = list(base)
+        args[names.index(name)] = v
+        assert L.bake_qem_edges(*args) == code, (name, v, L.bake_last_error())
+
+
+def test_qem_workspace_size(B):
+    a = B.qem_workspace_size(1000, 2000)
+    b = B.qem_workspace_size(2000, 4000)
+    assert 0 < a < b and a % 256 == 0
+    with pytest.raises(B.BakeError):
+        B.qem_workspace_size(-1, 5)
+    with pytest.raises(B.BakeError):
+        B.qem_workspace_size(10, 1 << 28)
