@@ -335,7 +335,7 @@ hipError_t launch_flood_fill(const BatchHost& H, const FillRun& f, hipStream_t s
 struct QemLayout {
     int64_t nv, nf, edge_cap;
     size_t cnt, hist, P, Q, F, F2, keep, koff, deg, off, cur, adj, ncnt, noff, hcnt, eoff, bnd, nbr, E, bits, faces,
-        pl, m, M, partner, win, scan_tmp;
+        pl, m, M, partner, wflag, part, scan_tmp;
     size_t total;
 };
 size_t qem_layout(int64_t nv, int64_t nf, QemLayout* L);

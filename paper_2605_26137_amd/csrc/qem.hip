@@ -164,78 +164,94 @@ __device__ __forceinline__ uint32_t shared_count(const int32_t* F, const uint32_
     return c;
 }
 
-// Per vertex: unique neighbour count, neighbours of higher index, boundary flag.
-__global__ void qem_vertex_kernel(const int32_t* __restrict__ F, int64_t nv, const uint32_t* __restrict__ off,
-                                  const uint32_t* __restrict__ adj, uint32_t* __restrict__ ncnt,
-                                  uint32_t* __restrict__ hcnt, uint32_t* __restrict__ bnd) {
+// The rings.  Around v, the other two corners of every face name v's
+// neighbours, each once per face it shares with v: sorted, the runs of that
+// list are the unique neighbours in ascending order, and a run of length one
+// is an edge with a single face (v is then a boundary vertex).  The list is
+// gathered and insertion-sorted in LDS; vertices with more than kRingFaces
+// faces take a slower path over global memory.
+//   count pass: unique neighbours, neighbours above v, boundary flag;
+//   write pass: the sorted ring into nbr[noff[v] ...] and the edges (v, x),
+//               x > v ascending, from eoff[v].
+constexpr int kRB = 128;        // threads per block of the ring kernels
+constexpr int kRingFaces = 24;  // faces per vertex sorted in LDS
+
+template <bool WRITE>
+__global__ void __launch_bounds__(kRB) qem_ring_kernel(const int32_t* __restrict__ F, int64_t nv,
+                                                       const uint32_t* __restrict__ off,
+                                                       const uint32_t* __restrict__ adj, uint32_t* __restrict__ ncnt,
+                                                       uint32_t* __restrict__ hcnt, uint32_t* __restrict__ bnd,
+                                                       const uint32_t* __restrict__ noff,
+                                                       const uint32_t* __restrict__ eoff, int32_t* __restrict__ nbr,
+                                                       int32_t* __restrict__ E) {
+    __shared__ int32_t ent[2 * kRingFaces][kRB];
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= nv) return;
     const uint32_t b = off[v], n = off[v + 1] - b;
+    const int t = threadIdx.x;
+    if (n <= (uint32_t)kRingFaces) {
+        uint32_t m = 0;
+        for (uint32_t i = 0; i < n; ++i) {
+            const int32_t* f = F + 3 * (int64_t)adj[b + i];
+            const int32_t c0 = f[0], c1 = f[1], c2 = f[2];
+            const int32_t x = c0 == (int32_t)v ? c1 : c0;
+            const int32_t y = c2 == (int32_t)v ? c1 : c2;
+            // insertion of x, then y, into the sorted prefix
+            uint32_t j = m;
+            while (j > 0 && ent[j - 1][t] > x) {
+                ent[j][t] = ent[j - 1][t];
+                --j;
+            }
+            ent[j][t] = x;
+            ++m;
+            j = m;
+            while (j > 0 && ent[j - 1][t] > y) {
+                ent[j][t] = ent[j - 1][t];
+                --j;
+            }
+            ent[j][t] = y;
+            ++m;
+        }
+        uint32_t uniq = 0, higher = 0, boundary = 0;
+        uint32_t e = WRITE ? eoff[v] : 0, r = WRITE ? noff[v] : 0;
+        for (uint32_t i = 0; i < m;) {
+            const int32_t x = ent[i][t];
+            uint32_t k = i + 1;
+            while (k < m && ent[k][t] == x) ++k;
+            if (k - i == 1) boundary = 1;
+            ++uniq;
+            if (WRITE) {
+                nbr[r++] = x;
+                if (x > (int32_t)v) {
+                    E[2 * (int64_t)e] = (int32_t)v;
+                    E[2 * (int64_t)e + 1] = x;
+                    ++e;
+                }
+            } else if (x > (int32_t)v) {
+                ++higher;
+            }
+            i = k;
+        }
+        if (!WRITE) {
+            ncnt[v] = uniq;
+            hcnt[v] = higher;
+            bnd[v] = boundary;
+        }
+        return;
+    }
+    // many faces: the same quantities straight from the face list
     uint32_t uniq = 0, higher = 0, boundary = 0;
     for (uint32_t i = 0; i < n; ++i) {
         const int32_t* f = F + 3 * (int64_t)adj[b + i];
         for (int k = 0; k < 3; ++k) {
             const int32_t x = f[k];
             if (x == (int32_t)v || seen_before(F, adj, b, i, x)) continue;
-            ++uniq;
-            if (x > (int32_t)v) ++higher;
-            if (shared_count(F, adj, b, n, x) == 1) boundary = 1;
-        }
-    }
-    ncnt[v] = uniq;
-    hcnt[v] = higher;
-    bnd[v] = boundary;
-}
-
-// Sorted unique neighbours of v into nbr[noff[v] ...]; the ones above v are the
-// edges (v, x), numbered from eoff[v] in ascending x.
-__global__ void __launch_bounds__(kQB) qem_nbr_kernel(const int32_t* __restrict__ F, int64_t nv,
-                                                      const uint32_t* __restrict__ off,
-                                                      const uint32_t* __restrict__ adj,
-                                                      const uint32_t* __restrict__ noff,
-                                                      const uint32_t* __restrict__ eoff,
-                                                      int32_t* __restrict__ nbr, int32_t* __restrict__ E) {
-    __shared__ int32_t buf[kSortCap][kQB];
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= nv) return;
-    const uint32_t b = off[v], n = off[v + 1] - b;
-    const uint32_t nb0 = noff[v], cnt = noff[v + 1] - nb0;
-    const int t = threadIdx.x;
-    if (cnt <= (uint32_t)kSortCap) {
-        uint32_t m = 0;
-        for (uint32_t i = 0; i < n; ++i) {
-            const int32_t* f = F + 3 * (int64_t)adj[b + i];
-            for (int k = 0; k < 3; ++k) {
-                const int32_t x = f[k];
-                if (x == (int32_t)v || seen_before(F, adj, b, i, x)) continue;
-                // insertion into the sorted prefix buf[0..m)
-                uint32_t j = m;
-                while (j > 0 && buf[j - 1][t] > x) {
-                    buf[j][t] = buf[j - 1][t];
-                    --j;
-                }
-                buf[j][t] = x;
-                ++m;
+            if (!WRITE) {
+                ++uniq;
+                if (x > (int32_t)v) ++higher;
+                if (shared_count(F, adj, b, n, x) == 1) boundary = 1;
+                continue;
             }
-        }
-        uint32_t e = eoff[v];
-        for (uint32_t j = 0; j < m; ++j) {
-            const int32_t x = buf[j][t];
-            nbr[nb0 + j] = x;
-            if (x > (int32_t)v) {
-                E[2 * (int64_t)e] = (int32_t)v;
-                E[2 * (int64_t)e + 1] = x;
-                ++e;
-            }
-        }
-        return;
-    }
-    // many neighbours: rank each one directly
-    for (uint32_t i = 0; i < n; ++i) {
-        const int32_t* f = F + 3 * (int64_t)adj[b + i];
-        for (int k = 0; k < 3; ++k) {
-            const int32_t x = f[k];
-            if (x == (int32_t)v || seen_before(F, adj, b, i, x)) continue;
             uint32_t below = 0, below_hi = 0;
             for (uint32_t i2 = 0; i2 < n; ++i2) {
                 const int32_t* g = F + 3 * (int64_t)adj[b + i2];
@@ -246,13 +262,18 @@ __global__ void __launch_bounds__(kQB) qem_nbr_kernel(const int32_t* __restrict_
                     if (y > (int32_t)v) ++below_hi;
                 }
             }
-            nbr[nb0 + below] = x;
+            nbr[noff[v] + below] = x;
             if (x > (int32_t)v) {
                 const int64_t e = (int64_t)eoff[v] + below_hi;
                 E[2 * e] = (int32_t)v;
                 E[2 * e + 1] = x;
             }
         }
+    }
+    if (!WRITE) {
+        ncnt[v] = uniq;
+        hcnt[v] = higher;
+        bnd[v] = boundary;
     }
 }
 
@@ -507,8 +528,8 @@ __global__ void __launch_bounds__(kQB) qem_hist_kernel(const uint32_t* __restric
 }
 
 // Counter slots of a round
-constexpr int kQcEdges = 0, kQcValid = 1, kQcWin = 2, kQcTotal = 3, kQcTau = 4, kQcLive = 5, kQcApplied = 6,
-              kQcRemoved = 7, kQcCutLo = 8, kQcCutHi = 9, kQcStatus = 10, kQcOut = 11, kQcSlots = 16;
+constexpr int kQcEdges = 0, kQcValid = 1, kQcTau = 4, kQcLive = 5, kQcApplied = 6, kQcRemoved = 7, kQcCutLo = 8,
+              kQcCutHi = 9, kQcStatus = 10, kQcOut = 11, kQcSlots = 16;
 
 // m(v): least key of the eligible edges at v.
 __global__ void __launch_bounds__(kQB) qem_vmin_kernel(const int32_t* __restrict__ E,
@@ -539,112 +560,187 @@ __global__ void __launch_bounds__(kQB) qem_vmin_kernel(const int32_t* __restrict
     atomicMin((unsigned long long*)&m[E[2 * e + 1]], key);
 }
 
-__global__ void qem_copy_u64_kernel(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = src[i];
-}
-
-// M(v): least m over v and its ring (every edge, collapsible or not).
+// M(v): least m over v and its ring (every edge, collapsible or not; M
+// starts at all ones and a vertex with an eligible edge has that edge).
 __global__ void qem_nmin_kernel(const int32_t* __restrict__ E, const uint32_t* __restrict__ cnt,
                                 const uint64_t* __restrict__ m, uint64_t* __restrict__ M) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (int64_t)cnt[kQcEdges]) return;
     const int32_t a = E[2 * e], b = E[2 * e + 1];
     const uint64_t ma = m[a], mb = m[b];
-    if (mb != ~0ull) atomicMin((unsigned long long*)&M[a], (unsigned long long)mb);
-    if (ma != ~0ull) atomicMin((unsigned long long*)&M[b], (unsigned long long)ma);
+    const uint64_t lo = ma < mb ? ma : mb;
+    if (lo == ~0ull) return;
+    if (lo < M[a]) atomicMin((unsigned long long*)&M[a], (unsigned long long)lo);
+    if (lo < M[b]) atomicMin((unsigned long long*)&M[b], (unsigned long long)lo);
 }
 
-__global__ void qem_win_kernel(const int32_t* __restrict__ E, const uint32_t* __restrict__ bits,
-                               const uint8_t* __restrict__ faces, const uint64_t* __restrict__ M,
-                               uint32_t* __restrict__ cnt, uint64_t* __restrict__ win) {
+// Winners: flag per edge, and per block the number of winners and the faces
+// they would remove (no atomics: a round has tens of thousands of winners).
+__global__ void __launch_bounds__(kQB) qem_win_kernel(const int32_t* __restrict__ E,
+                                                      const uint32_t* __restrict__ bits,
+                                                      const uint8_t* __restrict__ faces,
+                                                      const uint64_t* __restrict__ M,
+                                                      const uint32_t* __restrict__ cnt, uint8_t* __restrict__ wflag,
+                                                      uint32_t* __restrict__ part) {
+    __shared__ uint32_t s_n[kQB / 64], s_f[kQB / 64];
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)cnt[kQcEdges] || cnt[kQcValid] == 0) return;
-    const uint32_t x = bits[e];
-    if (x == kNoKey || x > cnt[kQcTau]) return;
-    const uint64_t key = ((uint64_t)x << 32) | (uint64_t)(uint32_t)e;
-    if (M[E[2 * e]] != key || M[E[2 * e + 1]] != key) return;
-    const uint32_t slot = atomicAdd(&cnt[kQcWin], 1u);
-    win[slot] = key;
-    atomicAdd(&cnt[kQcTotal], (uint32_t)faces[e]);
+    const int64_t ne = cnt[kQcEdges];
+    bool w = false;
+    uint32_t f = 0;
+    if (e < ne) {
+        const uint32_t x = bits[e];
+        if (cnt[kQcValid] != 0 && x != kNoKey && x <= cnt[kQcTau]) {
+            const uint64_t key = ((uint64_t)x << 32) | (uint64_t)(uint32_t)e;
+            w = M[E[2 * e]] == key && M[E[2 * e + 1]] == key;
+            if (w) f = faces[e];
+        }
+        wflag[e] = w ? 1 : 0;
+    }
+    uint32_t n = w ? 1u : 0u;
+    for (int o = 32; o >= 1; o >>= 1) {
+        n += __shfl_xor(n, o, 64);
+        f += __shfl_xor(f, o, 64);
+    }
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s_n[wave] = n;
+        s_f[wave] = f;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tn = 0, tf = 0;
+        for (int k = 0; k < kQB / 64; ++k) {
+            tn += s_n[k];
+            tf += s_f[k];
+        }
+        part[2 * blockIdx.x] = tn;
+        part[2 * blockIdx.x + 1] = tf;
+    }
 }
 
-// When the winners would remove more than live - target faces, the smallest
-// key that no longer fits (keys in ascending order, face counts summed):
-// radix descent over the 64-bit keys, 8 bits per level, one workgroup.
-__global__ void __launch_bounds__(1024) qem_cut_kernel(const uint64_t* __restrict__ win,
-                                                       const uint8_t* __restrict__ faces, uint32_t* __restrict__ cnt,
-                                                       int64_t target) {
-    __shared__ uint32_t h[256];
+// The collapses a round applies.  Sums the per-block winner counts; when the
+// winners would remove more than live - target faces, finds the smallest key
+// that no longer fits (keys ascending, face counts summed) by a radix descent
+// over the winners' 64-bit keys, 8 bits per level.  Writes the cut key and the
+// number of collapses kept and the faces they remove.  One workgroup.
+__global__ void __launch_bounds__(1024) qem_cut_kernel(const uint8_t* __restrict__ wflag,
+                                                       const uint32_t* __restrict__ bits,
+                                                       const uint8_t* __restrict__ faces,
+                                                       const uint32_t* __restrict__ part, int64_t nblk,
+                                                       uint32_t* __restrict__ cnt, int64_t target) {
+    __shared__ uint32_t h[256], hc[256];
+    __shared__ uint32_t s_red[2][1024 / 64];
     __shared__ unsigned long long s_prefix;
-    __shared__ uint32_t s_budget;
-    const uint32_t n = cnt[kQcWin];
+    __shared__ uint32_t s_budget, s_kf, s_kn;
+    uint32_t n = 0, f = 0;
+    for (int64_t i = threadIdx.x; i < nblk; i += blockDim.x) {
+        n += part[2 * i];
+        f += part[2 * i + 1];
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+        n += __shfl_xor(n, o, 64);
+        f += __shfl_xor(f, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        s_red[0][threadIdx.x >> 6] = n;
+        s_red[1][threadIdx.x >> 6] = f;
+    }
+    __syncthreads();
+    uint32_t tn = 0, tf = 0;
+    for (int k = 0; k < 1024 / 64; ++k) {
+        tn += s_red[0][k];
+        tf += s_red[1][k];
+    }
     const int64_t budget = (int64_t)cnt[kQcLive] - target;
-    if ((int64_t)cnt[kQcTotal] <= budget) {
+    if ((int64_t)tf <= budget) {
         if (threadIdx.x == 0) {
             cnt[kQcCutLo] = 0xFFFFFFFFu;
             cnt[kQcCutHi] = 0xFFFFFFFFu;
+            cnt[kQcApplied] = tn;
+            cnt[kQcRemoved] = tf;
         }
         return;
     }
+    const int64_t ne = cnt[kQcEdges];
     if (threadIdx.x == 0) {
         s_prefix = 0;
         s_budget = (uint32_t)(budget > 0 ? budget : 0);
+        s_kf = 0;
+        s_kn = 0;
     }
     for (int level = 0; level < 8; ++level) {
         const int shift = 56 - 8 * level;
-        if (threadIdx.x < 256) h[threadIdx.x] = 0;
+        if (threadIdx.x < 256) {
+            h[threadIdx.x] = 0;
+            hc[threadIdx.x] = 0;
+        }
         __syncthreads();
         const unsigned long long pre = s_prefix;
-        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-            const uint64_t k = win[i];
+        for (int64_t e = threadIdx.x; e < ne; e += blockDim.x) {
+            if (!wflag[e]) continue;
+            const uint64_t k = ((uint64_t)bits[e] << 32) | (uint64_t)(uint32_t)e;
             if (level > 0 && (k >> (shift + 8)) != pre) continue;
-            atomicAdd(&h[(k >> shift) & 255u], (uint32_t)faces[(uint32_t)k]);
+            atomicAdd(&h[(k >> shift) & 255u], (uint32_t)faces[e]);
+            atomicAdd(&hc[(k >> shift) & 255u], 1u);
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            uint32_t acc = 0, d = 0;
+            uint32_t acc = 0, accn = 0, d = 0;
             for (; d < 256; ++d) {
                 if (acc + h[d] > s_budget) break;
                 acc += h[d];
+                accn += hc[d];
             }
-            // the keys under the prefix weigh more than the budget, so some digit overflows
+            // the winners under the prefix weigh more than the budget, so a digit overflows
             s_prefix = (pre << 8) | (d < 256 ? d : 255u);
             s_budget -= acc;
+            s_kf += acc;
+            s_kn += accn;
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         cnt[kQcCutLo] = (uint32_t)s_prefix;
         cnt[kQcCutHi] = (uint32_t)(s_prefix >> 32);
+        cnt[kQcApplied] = s_kn;
+        cnt[kQcRemoved] = s_kf;
     }
 }
 
-__global__ void qem_apply_kernel(const uint64_t* __restrict__ win, const int32_t* __restrict__ E,
-                                 const uint8_t* __restrict__ faces, const double* __restrict__ pl,
-                                 uint32_t* __restrict__ cnt, double* __restrict__ P, double* __restrict__ Q,
+__global__ void qem_apply_kernel(const uint8_t* __restrict__ wflag, const uint32_t* __restrict__ bits,
+                                 const int32_t* __restrict__ E, const double* __restrict__ pl,
+                                 const uint32_t* __restrict__ cnt, double* __restrict__ P, double* __restrict__ Q,
                                  int32_t* __restrict__ partner) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)cnt[kQcWin]) return;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)cnt[kQcEdges] || !wflag[e]) return;
     const uint64_t cut = ((uint64_t)cnt[kQcCutHi] << 32) | cnt[kQcCutLo];
-    const uint64_t key = win[i];
+    const uint64_t key = ((uint64_t)bits[e] << 32) | (uint64_t)(uint32_t)e;
     if (key >= cut) return;
-    const int64_t e = (uint32_t)key;
     const int32_t v0 = E[2 * e], v1 = E[2 * e + 1];
     P[3 * (int64_t)v0] = pl[3 * e];
     P[3 * (int64_t)v0 + 1] = pl[3 * e + 1];
     P[3 * (int64_t)v0 + 2] = pl[3 * e + 2];
     for (int k = 0; k < 10; ++k) Q[10 * (int64_t)v0 + k] = Q[10 * (int64_t)v0 + k] + Q[10 * (int64_t)v1 + k];
     partner[v1] = v0;
-    atomicAdd(&cnt[kQcApplied], 1u);
-    atomicAdd(&cnt[kQcRemoved], (uint32_t)faces[e]);
 }
 
-__global__ void qem_unpartner_kernel(const uint64_t* __restrict__ win, const int32_t* __restrict__ E,
-                                     const uint32_t* __restrict__ cnt, int32_t* __restrict__ partner) {
+// Start of a round: counters (status kept), histograms, m, M, partners, and
+// when the face lists are rebuilt, their degree and cursor arrays.
+__global__ void qem_reset_kernel(int64_t nv, uint32_t live, int lists, uint32_t* __restrict__ cnt,
+                                 uint32_t* __restrict__ hist, uint64_t* __restrict__ m, uint64_t* __restrict__ M,
+                                 int32_t* __restrict__ partner, uint32_t* __restrict__ deg,
+                                 uint32_t* __restrict__ cur) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)cnt[kQcWin]) return;
-    partner[E[2 * (int64_t)(uint32_t)win[i] + 1]] = -1;
+    if (i < kQcStatus) cnt[i] = 0;
+    if (i == kQcLive) cnt[i] = live;
+    if (i < 4 * 256) hist[i] = 0;
+    if (i < nv) {
+        m[i] = ~0ull;
+        M[i] = ~0ull;
+        partner[i] = -1;
+        if (lists) cur[i] = 0;
+    }
+    if (lists && i <= nv) deg[i] = 0;
 }
 
 __global__ void qem_face_flag_kernel(const int32_t* __restrict__ F, int64_t live, const int32_t* __restrict__ partner,
@@ -755,7 +851,8 @@ size_t qem_layout(int64_t nv, int64_t nf, QemLayout* L) {
     L->m = take(8 * (size_t)nv);
     L->M = take(8 * (size_t)nv);
     L->partner = take(4 * (size_t)nv);
-    L->win = take(8 * (size_t)(nv / 2 + 1));
+    L->wflag = take((size_t)cap);
+    L->part = take(8 * (size_t)blocks_for(cap));
     L->scan_tmp = take(4 * (size_t)(scan_tmp_elems(scan_n) + 1));
     L->total = off;
     return off;
@@ -767,8 +864,9 @@ struct QemPtrs {
     uint32_t *cnt, *hist, *keep, *koff, *deg, *off, *cur, *adj, *ncnt, *noff, *hcnt, *eoff, *bnd, *bits, *scan_tmp;
     double *P, *Q, *pl;
     int32_t *F, *F2, *nbr, *E, *partner;
-    uint8_t* faces;
-    uint64_t *m, *M, *win;
+    uint8_t *faces, *wflag;
+    uint32_t* part;
+    uint64_t *m, *M;
 };
 
 QemPtrs ptrs(const QemLayout& L, char* ws) {
@@ -799,7 +897,8 @@ QemPtrs ptrs(const QemLayout& L, char* ws) {
     p.faces = (uint8_t*)(ws + L.faces);
     p.m = (uint64_t*)(ws + L.m);
     p.M = (uint64_t*)(ws + L.M);
-    p.win = (uint64_t*)(ws + L.win);
+    p.wflag = (uint8_t*)(ws + L.wflag);
+    p.part = (uint32_t*)(ws + L.part);
     return p;
 }
 
@@ -809,11 +908,9 @@ QemPtrs ptrs(const QemLayout& L, char* ws) {
         if (e_ != hipSuccess) return e_;     \
     } while (0)
 
-// vertex -> face lists of the `live` current faces
+// vertex -> face lists of the `live` current faces (deg and cur zeroed)
 hipError_t build_lists(const QemLayout& L, const QemPtrs& p, int64_t live, hipStream_t s) {
     const int64_t nv = L.nv;
-    QEM_TRY(fill_u32(p.deg, 0, nv + 1, s));
-    QEM_TRY(fill_u32(p.cur, 0, nv, s));
     hipLaunchKernelGGL(qem_deg_kernel, dim3(blocks_for(live)), dim3(kQB), 0, s, p.F, live, p.deg);
     QEM_TRY(hipGetLastError());
     QEM_TRY(exclusive_scan_u32(p.deg, p.off, nv, p.scan_tmp, p.off + nv, s));
@@ -824,13 +921,14 @@ hipError_t build_lists(const QemLayout& L, const QemPtrs& p, int64_t live, hipSt
 // rings and edges of the current mesh; edge count at cnt[kQcEdges]
 hipError_t build_edges(const QemLayout& L, const QemPtrs& p, hipStream_t s) {
     const int64_t nv = L.nv;
-    hipLaunchKernelGGL(qem_vertex_kernel, dim3(blocks_for(nv)), dim3(kQB), 0, s, p.F, nv, p.off, p.adj, p.ncnt,
-                       p.hcnt, p.bnd);
+    const int64_t g = nv <= 0 ? 1 : (nv + kRB - 1) / kRB;
+    hipLaunchKernelGGL(qem_ring_kernel<false>, dim3(g), dim3(kRB), 0, s, p.F, nv, p.off, p.adj, p.ncnt, p.hcnt,
+                       p.bnd, p.noff, p.eoff, p.nbr, p.E);
     QEM_TRY(hipGetLastError());
     QEM_TRY(exclusive_scan_u32(p.ncnt, p.noff, nv, p.scan_tmp, p.noff + nv, s));
     QEM_TRY(exclusive_scan_u32(p.hcnt, p.eoff, nv, p.scan_tmp, p.cnt + kQcEdges, s));
-    hipLaunchKernelGGL(qem_nbr_kernel, dim3(blocks_for(nv)), dim3(kQB), 0, s, p.F, nv, p.off, p.adj, p.noff, p.eoff,
-                       p.nbr, p.E);
+    hipLaunchKernelGGL(qem_ring_kernel<true>, dim3(g), dim3(kRB), 0, s, p.F, nv, p.off, p.adj, p.ncnt, p.hcnt,
+                       p.bnd, p.noff, p.eoff, p.nbr, p.E);
     return hipGetLastError();
 }
 
@@ -863,6 +961,8 @@ hipError_t set_up(const QemLayout& L, const QemPtrs& p, const float* V, const in
     hipLaunchKernelGGL(qem_init_kernel, dim3(blocks_for(n)), dim3(kQB), 0, s, V, L.nv, F, L.nf, p.P, p.partner,
                        p.F, p.cnt + kQcStatus);
     QEM_TRY(hipGetLastError());
+    QEM_TRY(fill_u32(p.deg, 0, L.nv + 1, s));
+    QEM_TRY(fill_u32(p.cur, 0, L.nv, s));
     QEM_TRY(build_lists(L, p, L.nf, s));
     hipLaunchKernelGGL(qem_quadric_kernel, dim3(blocks_for(L.nv)), dim3(kQB), 0, s, p.P, p.F, L.nv, p.off, p.adj,
                        p.Q);
@@ -905,35 +1005,31 @@ hipError_t qem_simplify_run(const QemLayout& L, char* ws, const float* V, const 
     int64_t live = L.nf;
     int32_t round = 0;
     while (live > target && round < max_rounds) {
+        hipLaunchKernelGGL(qem_reset_kernel, dim3(blocks_for(std::max<int64_t>(nv + 1, 4 * 256))), dim3(kQB), 0, s,
+                           nv, (uint32_t)live, round > 0 ? 1 : 0, p.cnt, p.hist, p.m, p.M, p.partner, p.deg, p.cur);
+        QEM_TRY(hipGetLastError());
         if (round > 0) QEM_TRY(build_lists(L, p, live, s));
-        // per-round counters: everything but the status word
-        QEM_TRY(fill_u32(p.cnt, 0, kQcStatus, s));
-        QEM_TRY(fill_u32(p.cnt + kQcLive, (uint32_t)live, 1, s));
         QEM_TRY(build_edges(L, p, s));
         const int64_t egrid = 3 * live;
         QEM_TRY(eval_edges(p, egrid, midpoint, nullptr, nullptr, s));
-        QEM_TRY(fill_u32(p.hist, 0, 4 * 256, s));
         const int64_t hgrid = std::min<int64_t>(blocks_for(egrid), 2048);
         for (int level = 0; level < 4; ++level) {
             hipLaunchKernelGGL(qem_hist_kernel, dim3(hgrid), dim3(kQB), 0, s, p.bits, p.cnt + kQcEdges,
                                hgrid * kQB, p.hist, level, rho);
             QEM_TRY(hipGetLastError());
         }
-        QEM_TRY(fill_u32((uint32_t*)p.m, 0xFFFFFFFFu, 2 * nv, s));
         hipLaunchKernelGGL(qem_vmin_kernel, dim3(blocks_for(egrid)), dim3(kQB), 0, s, p.E, p.bits, p.hist, p.cnt,
                            rho, p.m);
-        QEM_TRY(hipGetLastError());
-        hipLaunchKernelGGL(qem_copy_u64_kernel, dim3(blocks_for(nv)), dim3(kQB), 0, s, p.m, p.M, nv);
         QEM_TRY(hipGetLastError());
         hipLaunchKernelGGL(qem_nmin_kernel, dim3(blocks_for(egrid)), dim3(kQB), 0, s, p.E, p.cnt, p.m, p.M);
         QEM_TRY(hipGetLastError());
         hipLaunchKernelGGL(qem_win_kernel, dim3(blocks_for(egrid)), dim3(kQB), 0, s, p.E, p.bits, p.faces, p.M,
-                           p.cnt, p.win);
+                           p.cnt, p.wflag, p.part);
         QEM_TRY(hipGetLastError());
-        hipLaunchKernelGGL(qem_cut_kernel, dim3(1), dim3(1024), 0, s, p.win, p.faces, p.cnt, target);
+        hipLaunchKernelGGL(qem_cut_kernel, dim3(1), dim3(1024), 0, s, p.wflag, p.bits, p.faces, p.part,
+                           blocks_for(egrid), p.cnt, target);
         QEM_TRY(hipGetLastError());
-        const int64_t wgrid = std::min<int64_t>(nv / 2 + 1, live);
-        hipLaunchKernelGGL(qem_apply_kernel, dim3(blocks_for(wgrid)), dim3(kQB), 0, s, p.win, p.E, p.faces, p.pl,
+        hipLaunchKernelGGL(qem_apply_kernel, dim3(blocks_for(egrid)), dim3(kQB), 0, s, p.wflag, p.bits, p.E, p.pl,
                            p.cnt, p.P, p.Q, p.partner);
         QEM_TRY(hipGetLastError());
         hipLaunchKernelGGL(qem_face_flag_kernel, dim3(blocks_for(live)), dim3(kQB), 0, s, p.F, live, p.partner, p.F2,
@@ -942,9 +1038,6 @@ hipError_t qem_simplify_run(const QemLayout& L, char* ws, const float* V, const 
         QEM_TRY(exclusive_scan_u32(p.keep, p.koff, live, p.scan_tmp, p.cnt + kQcOut, s));
         hipLaunchKernelGGL(qem_face_scatter_kernel, dim3(blocks_for(live)), dim3(kQB), 0, s, p.F2, live, p.keep,
                            p.koff, p.F);
-        QEM_TRY(hipGetLastError());
-        hipLaunchKernelGGL(qem_unpartner_kernel, dim3(blocks_for(wgrid)), dim3(kQB), 0, s, p.win, p.E, p.cnt,
-                           p.partner);
         QEM_TRY(hipGetLastError());
         QEM_TRY(hipMemcpyAsync(h, p.cnt, sizeof h, hipMemcpyDeviceToHost, s));
         QEM_TRY(hipStreamSynchronize(s));
