@@ -98,6 +98,21 @@ def sized_sample(run, pilot, limit, target_s):
     return n, dt
 
 
+QEM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_qem_eval_noise4_L8_10k.json")
+
+
+def measured_qem_traffic():
+    """HBM bytes of the per-edge evaluation over one run, from the committed
+    rocprofv3 counter runs, if taken on the current source; else None."""
+    if not os.path.exists(QEM_TRAFFIC_FILE):
+        return None
+    with open(QEM_TRAFFIC_FILE) as f:
+        d = json.load(f)
+    if d.get("source_hash") != source_hash("qem.hip"):
+        return None
+    return d.get("bytes_per_run")
+
+
 def cpu_baseline(asset, target_s, max_dist, kind):
     """The oracle as it stands (FP64 brute force over every triangle) on a
     seeded sample of the workload's covered texels (forward query: the
@@ -304,13 +319,27 @@ def bench_simplify(args, B, log):
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    eval_ms = 0.0
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        r = step()
+        r = B.qem_simplify(Vd, Fd, target, workspace=ws, out=out, timing=True)
+        eval_ms += r.times_ms[0]
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    eval_ms /= args.steps
     removed = F.shape[0] - r.F.shape[0]
-    log(f"[bench] simplify: {ms:.3f} ms/step, {r.rounds} rounds, {r.F.shape[0]} faces")
+    # algorithmic bytes of the per-edge evaluation over the run: per round each
+    # live vertex's position, quadric, list offsets and boundary flag (116 B),
+    # each face and its three face-list entries (24 B), and per edge its ends,
+    # two ring entries and the written cost bits, face count and placement
+    # (45 B); live vertices from Euler's formula (closed genus-0 mesh)
+    st = r.stats.astype(np.int64)
+    faces_before = np.concatenate([[F.shape[0]], st[:-1, 3]])
+    verts = 2 + st[:, 0] - faces_before
+    algo = float(np.sum(116 * verts + 24 * faces_before + 45 * st[:, 0]))
+    achieved = algo / (eval_ms / 1e3) / 1e9
+    log(f"[bench] simplify: {ms:.3f} ms/step, {r.rounds} rounds, {r.F.shape[0]} faces; evaluation {eval_ms:.3f} ms, "
+        f"{achieved:.0f} GB/s algorithmic")
     out_json = {
         "metric": "faces removed per second by QEM simplification (1.31M-face mesh -> 10,000 faces)",
         "value": removed / (ms / 1e3), "unit": "faces/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -320,6 +349,11 @@ def bench_simplify(args, B, log):
                    ", rho 0.25 (cheapest quarter of the allowed edges eligible per round)",
                    "faces_in": int(F.shape[0]), "faces_out": int(r.F.shape[0]), "rounds": int(r.rounds),
                    "edges_evaluated": int(r.stats[:, 0].sum())},
+        "roofline": {"kernel": "qem_eval_kernel (per-edge collapse evaluation, summed over the rounds of a run)",
+                     "bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+                     "frac": achieved / 8000.0, "traffic": measured_qem_traffic(),
+                     "algorithmic_bytes_per_run": algo, "eval_ms_per_run": eval_ms,
+                     "edges_evaluated_per_run": int(st[:, 0].sum())},
         "paper_context_s": 0.45,
     }
     if not args.no_cpu_baseline:

@@ -389,7 +389,9 @@ int32_t bake_autotune(const bake_asset *assets, int32_t n_assets, const bake_opt
  * positions rounded from FP64 to f32; the surviving faces in their input
  * order, renumbered).  HOST outputs: counts_out[2] = (vertices, faces) of the
  * result, *rounds_out = rounds run, stats_out NULL or [max_rounds][4] per
- * round (edges, allowed edges, collapses, faces after the round).
+ * round (edges, allowed edges, collapses, faces after the round),
+ * times_ms_out NULL or [2]: the summed duration of the per-edge evaluation
+ * launches and of the whole call, from HIP events on the stream.
  * flags: BAKE_QEM_MIDPOINT places interior edges at their midpoint (the
  * original placement the section compares against).  Workspace >=
  * bake_qem_workspace_size bytes, 256-byte aligned, overwritten; nothing is
@@ -405,8 +407,8 @@ int32_t bake_autotune(const bake_asset *assets, int32_t n_assets, const bake_opt
 int32_t bake_qem_workspace_size(int64_t n_v, int64_t n_f, size_t *bytes_out);
 int32_t bake_qem_simplify(const float *V, const int32_t *F, int64_t n_v, int64_t n_f, int64_t target_faces,
                           double rho, int32_t max_rounds, uint32_t flags, float *V_out, int32_t *F_out,
-                          int64_t *counts_out, int32_t *rounds_out, int64_t *stats_out, void *workspace,
-                          size_t workspace_bytes, void *stream);
+                          int64_t *counts_out, int32_t *rounds_out, int64_t *stats_out, float *times_ms_out,
+                          void *workspace, size_t workspace_bytes, void *stream);
 
 /* Every edge of the input mesh with its collapse evaluated, as the first
  * round of bake_qem_simplify sees it.  Device outputs (caller-owned, `cap`

@@ -126,7 +126,8 @@ _EXPORTS = {
     "bake_qem_workspace_size": (C.c_int32, [C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
     "bake_qem_simplify": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_double,
                                       C.c_int32, C.c_uint32, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64),
-                                      C.POINTER(C.c_int32), C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+                                      C.POINTER(C.c_int32), C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                                      C.c_void_p]),
     "bake_qem_edges": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_uint32, C.c_int64,
                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.POINTER(C.c_int64), C.c_void_p, C.c_size_t, C.c_void_p]),
@@ -732,10 +733,12 @@ class QemResult:
     F: torch.Tensor        # [n_f', 3] i32
     rounds: int
     stats: "numpy.ndarray"  # [rounds, 4]: edges, allowed edges, collapses, faces after the round
+    times_ms: Optional[tuple] = None  # (per-edge evaluation launches summed, whole call) when timed
 
 
 def qem_simplify(V, F, target: int, *, rho: float = 0.25, max_rounds: int = 1000, midpoint: bool = False,
-                 workspace: Optional[torch.Tensor] = None, out: Optional[tuple] = None, stream=None) -> QemResult:
+                 timing: bool = False, workspace: Optional[torch.Tensor] = None, out: Optional[tuple] = None,
+                 stream=None) -> QemResult:
     """Simplify the mesh (GPU tensors V [n_v,3] f32, F [n_f,3] i32) to `target`
     faces by rounds of quadric edge collapses (blocking).  out: optional
     preallocated (V_out [n_v,3] f32, F_out [n_f,3] i32)."""
@@ -754,9 +757,10 @@ def qem_simplify(V, F, target: int, *, rho: float = 0.25, max_rounds: int = 1000
     counts = (C.c_int64 * 2)()
     rounds = C.c_int32(0)
     stats = np.zeros((max(int(max_rounds), 1), 4), np.int64)
+    tms = (C.c_float * 2)() if timing else None
     _check(lib().bake_qem_simplify(_ptr(V), _ptr(F), nv, nf, int(target), float(rho), int(max_rounds),
                                    BAKE_QEM_MIDPOINT if midpoint else 0, _ptr(Vo), _ptr(Fo), counts,
-                                   C.byref(rounds), stats.ctypes.data, _ptr(workspace), workspace.numel(),
+                                   C.byref(rounds), stats.ctypes.data, tms, _ptr(workspace), workspace.numel(),
                                    _stream_handle(stream)))
     r = rounds.value
-    return QemResult(Vo[:counts[0]], Fo[:counts[1]], r, stats[:r])
+    return QemResult(Vo[:counts[0]], Fo[:counts[1]], r, stats[:r], (tms[0], tms[1]) if timing else None)

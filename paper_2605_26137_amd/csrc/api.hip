@@ -1060,8 +1060,8 @@ static int32_t qem_common(const float* V, const int32_t* F, int64_t n_v, int64_t
 
 int32_t bake_qem_simplify(const float* V, const int32_t* F, int64_t n_v, int64_t n_f, int64_t target_faces,
                           double rho, int32_t max_rounds, uint32_t flags, float* V_out, int32_t* F_out,
-                          int64_t* counts_out, int32_t* rounds_out, int64_t* stats_out, void* workspace,
-                          size_t workspace_bytes, void* stream) {
+                          int64_t* counts_out, int32_t* rounds_out, int64_t* stats_out, float* times_ms_out,
+                          void* workspace, size_t workspace_bytes, void* stream) {
     g_err[0] = 0;
     if (target_faces < 4) return fail(BAKE_E_INVALID_ARG, "target_faces %lld < 4", (long long)target_faces);
     if (!(rho > 0.0 && rho <= 1.0)) return fail(BAKE_E_INVALID_ARG, "rho must lie in (0, 1]");
@@ -1074,7 +1074,7 @@ int32_t bake_qem_simplify(const float* V, const int32_t* F, int64_t n_v, int64_t
     uint32_t status = 0;
     HIP_OR_FAIL(qem_simplify_run(L, (char*)workspace, V, F, target_faces, rho, max_rounds,
                                  (flags & BAKE_QEM_MIDPOINT) ? 1 : 0, V_out, F_out, counts_out, rounds_out, stats_out,
-                                 &status, (hipStream_t)stream));
+                                 times_ms_out, &status, (hipStream_t)stream));
     if (status) return fail(BAKE_E_INDEX, "a face has an index outside [0, n_v) or a repeated vertex");
     return BAKE_OK;
 }

@@ -346,7 +346,7 @@ hipError_t qem_edges_run(const QemLayout& L, char* ws, const float* V, const int
                          double* cost_out, double* p_out, uint32_t* status, int64_t* n_edges, hipStream_t s);
 hipError_t qem_simplify_run(const QemLayout& L, char* ws, const float* V, const int32_t* F, int64_t target, double rho,
                             int32_t max_rounds, int midpoint, float* V_out, int32_t* F_out, int64_t* counts,
-                            int32_t* rounds_out, int64_t* stats, uint32_t* status, hipStream_t s);
+                            int32_t* rounds_out, int64_t* stats, float* times_ms, uint32_t* status, hipStream_t s);
 hipError_t launch_dilate(const BatchHost& H, int passes, hipStream_t s);
 hipError_t launch_rgb8(const BatchHost& H, hipStream_t s);
 hipError_t launch_backward(const BatchHost& H, bool any_lo, bool any_hi, hipStream_t s);

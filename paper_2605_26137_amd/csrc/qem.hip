@@ -53,6 +53,7 @@ constexpr int kSortCap = 32;                // neighbours sorted in LDS per vert
 
 inline int64_t blocks_for(int64_t n) { return n <= 0 ? 1 : (n + kQB - 1) / kQB; }
 
+
 __device__ __forceinline__ bool holds(const int32_t* f, int32_t x) { return f[0] == x || f[1] == x || f[2] == x; }
 
 __device__ __forceinline__ uint32_t f32_bits(double c) { return __float_as_uint((float)c); }
@@ -993,8 +994,16 @@ hipError_t qem_edges_run(const QemLayout& L, char* ws, const float* V, const int
 
 hipError_t qem_simplify_run(const QemLayout& L, char* ws, const float* V, const int32_t* F, int64_t target, double rho,
                             int32_t max_rounds, int midpoint, float* V_out, int32_t* F_out, int64_t* counts,
-                            int32_t* rounds_out, int64_t* stats, uint32_t* status, hipStream_t s) {
+                            int32_t* rounds_out, int64_t* stats, float* times_ms, uint32_t* status, hipStream_t s) {
     const QemPtrs p = ptrs(L, ws);
+    // optional timing: the whole call, and the per-edge evaluation launches summed
+    static thread_local hipEvent_t tev[4] = {nullptr, nullptr, nullptr, nullptr};
+    if (times_ms) {
+        for (int k = 0; k < 4; ++k)
+            if (!tev[k]) QEM_TRY(hipEventCreate(&tev[k]));
+        times_ms[0] = times_ms[1] = 0.f;
+        QEM_TRY(hipEventRecord(tev[2], s));
+    }
     QEM_TRY(set_up(L, p, V, F, s));
     uint32_t h[kQcSlots];
     QEM_TRY(hipMemcpyAsync(h, p.cnt, sizeof h, hipMemcpyDeviceToHost, s));
@@ -1011,7 +1020,9 @@ hipError_t qem_simplify_run(const QemLayout& L, char* ws, const float* V, const 
         if (round > 0) QEM_TRY(build_lists(L, p, live, s));
         QEM_TRY(build_edges(L, p, s));
         const int64_t egrid = 3 * live;
+        if (times_ms) QEM_TRY(hipEventRecord(tev[0], s));
         QEM_TRY(eval_edges(p, egrid, midpoint, nullptr, nullptr, s));
+        if (times_ms) QEM_TRY(hipEventRecord(tev[1], s));
         const int64_t hgrid = std::min<int64_t>(blocks_for(egrid), 2048);
         for (int level = 0; level < 4; ++level) {
             hipLaunchKernelGGL(qem_hist_kernel, dim3(hgrid), dim3(kQB), 0, s, p.bits, p.cnt + kQcEdges,
@@ -1042,6 +1053,11 @@ hipError_t qem_simplify_run(const QemLayout& L, char* ws, const float* V, const 
         QEM_TRY(hipMemcpyAsync(h, p.cnt, sizeof h, hipMemcpyDeviceToHost, s));
         QEM_TRY(hipStreamSynchronize(s));
         live = h[kQcOut];
+        if (times_ms) {
+            float ms = 0.f;
+            QEM_TRY(hipEventElapsedTime(&ms, tev[0], tev[1]));
+            times_ms[0] += ms;
+        }
         if (stats) {
             stats[4 * round] = h[kQcEdges];
             stats[4 * round + 1] = h[kQcValid];
@@ -1064,7 +1080,9 @@ hipError_t qem_simplify_run(const QemLayout& L, char* ws, const float* V, const 
     hipLaunchKernelGGL(qem_fout_kernel, dim3(blocks_for(live)), dim3(kQB), 0, s, p.F, live, vid, F_out);
     QEM_TRY(hipGetLastError());
     QEM_TRY(hipMemcpyAsync(h, p.cnt, sizeof h, hipMemcpyDeviceToHost, s));
+    if (times_ms) QEM_TRY(hipEventRecord(tev[3], s));
     QEM_TRY(hipStreamSynchronize(s));
+    if (times_ms) QEM_TRY(hipEventElapsedTime(&times_ms[1], tev[2], tev[3]));
     counts[0] = h[kQcOut];
     counts[1] = live;
     return hipSuccess;

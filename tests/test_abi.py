@@ -277,12 +277,12 @@ def _qem_call(B, **over):
     """bake_qem_simplify with fake (never dereferenced) device pointers."""
     fake = C.c_void_p(0x1000)
     a = dict(V=fake, F=fake, nv=4, nf=4, target=4, rho=0.25, rounds=10, flags=0, Vo=fake, Fo=fake,
-             counts=(C.c_int64 * 2)(), nr=C.pointer(C.c_int32(0)), stats=None,
+             counts=(C.c_int64 * 2)(), nr=C.pointer(C.c_int32(0)), stats=None, tms=None,
              ws=C.c_void_p(0x100000), ws_bytes=1 << 40, stream=None)
     a.update(over)
     return B.lib().bake_qem_simplify(a["V"], a["F"], a["nv"], a["nf"], a["target"], a["rho"], a["rounds"],
-                                     a["flags"], a["Vo"], a["Fo"], a["counts"], a["nr"], a["stats"], a["ws"],
-                                     a["ws_bytes"], a["stream"])
+                                     a["flags"], a["Vo"], a["Fo"], a["counts"], a["nr"], a["stats"], a["tms"],
+                                     a["ws"], a["ws_bytes"], a["stream"])
 
 
 @pytest.mark.parametrize("over,code", [
