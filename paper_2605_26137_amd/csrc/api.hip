@@ -386,6 +386,7 @@ constexpr int kStages = 6;
 constexpr int kRing = 64;
 struct Timing {
     hipEvent_t ev[kRing][kStages];
+    bool beside[kRing] = {};  // the slot's lo prep and raster ran beside the BVH build
     bool created = false;
     int next = 0;   // ring slot of the next timed bake
     int count = 0;  // timed bakes recorded (saturates at kRing)
@@ -412,11 +413,15 @@ void tim_commit(bool on) {
 }
 
 // Stage times of ring slot r: 0 lo prep, 1 raster, 2 BVH, 3 traversal, 4 dilation, 5 total.
+// When the lo prep and raster ran beside the build, stage 2 spans from the
+// start of the bake to the end of all three.
 int32_t slot_times(int r, float* ms) {
     HIP_OR_FAIL(hipEventSynchronize(g_tim.ev[r][kStages - 1]));
     for (int k = 0; k < kStages; ++k) {
         float v = 0.f;
-        if (k < kStages - 1) {
+        if (k == 2 && g_tim.beside[r]) {
+            HIP_OR_FAIL(hipEventElapsedTime(&v, g_tim.ev[r][0], g_tim.ev[r][3]));
+        } else if (k < kStages - 1) {
             HIP_OR_FAIL(hipEventElapsedTime(&v, g_tim.ev[r][k], g_tim.ev[r][k + 1]));
         } else {
             HIP_OR_FAIL(hipEventElapsedTime(&v, g_tim.ev[r][0], g_tim.ev[r][kStages - 1]));
@@ -434,6 +439,45 @@ int32_t check_workspace(const void* ws, size_t bytes, const Layout& L) {
     return BAKE_OK;
 }
 
+// ---- the second stream --------------------------------------------------
+// The low-poly prep and the UV raster do not depend on the BVH build (they
+// share no workspace region with it), so the forward runs them on a second
+// stream of the device, forked from and joined back to the caller's stream
+// with events; under graph capture the fork and join become graph edges.  The
+// stream and its events are created on the first forward of the device that
+// is not being captured (a captured forward before that runs everything on
+// the caller's stream).  Default priority.  The fork-join enqueue is
+// serialised so that concurrent callers never see each other's event records.
+constexpr int kMaxDevices = 64;
+struct Side {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+Side g_side[kMaxDevices];
+std::mutex g_side_mu;
+
+Side* side_stream(hipStream_t s) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    Side& d = g_side[dev];
+    if (d.s) return &d;
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess || st != hipStreamCaptureStatusNone) return nullptr;
+    hipStream_t t = nullptr;
+    hipEvent_t f = nullptr, j = nullptr;
+    if (hipStreamCreateWithFlags(&t, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&f, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&j, hipEventDisableTiming) != hipSuccess) {
+        if (f) (void)hipEventDestroy(f);
+        (void)hipStreamDestroy(t);
+        return nullptr;
+    }
+    d.fork = f;
+    d.join = j;
+    d.s = t;
+    return &d;
+}
+
 // The forward launch sequence of a planned batch.
 int32_t run_forward(Plan& P, const Opts& o, void* workspace, hipStream_t s) {
     char* ws = (char*)workspace;
@@ -448,11 +492,28 @@ int32_t run_forward(Plan& P, const Opts& o, void* workspace, hipStream_t s) {
     memcpy(blob.data() + (L.gpf - L.table), P.gpf.data(), 4 * P.gpf.size());
     HIP_OR_FAIL(write_table(ws + L.table, blob.data(), (L.gpf - L.table) + 4 * P.gpf.size(), s));
     HIP_OR_FAIL(fill_u32((uint32_t*)ws, 0, (int64_t)(L.table / 4), s));
-    HIP_OR_FAIL(launch_lo_prep(H, s));
-    HIP_OR_FAIL(tim_record(tim, 1, s));
-    HIP_OR_FAIL(launch_raster(H, s));
-    HIP_OR_FAIL(tim_record(tim, 2, s));
-    HIP_OR_FAIL(launch_bvh_build(H, s));
+    std::unique_lock<std::mutex> side_lock(g_side_mu);
+    Side* side = side_stream(s);
+    if (side) {
+        HIP_OR_FAIL(hipEventRecord(side->fork, s));
+        HIP_OR_FAIL(hipStreamWaitEvent(side->s, side->fork, 0));
+        HIP_OR_FAIL(launch_lo_prep(H, side->s));
+        HIP_OR_FAIL(tim_record(tim, 1, side->s));
+        HIP_OR_FAIL(launch_raster(H, side->s));
+        HIP_OR_FAIL(tim_record(tim, 2, side->s));
+        HIP_OR_FAIL(hipEventRecord(side->join, side->s));
+        HIP_OR_FAIL(launch_bvh_build(H, s));
+        HIP_OR_FAIL(hipStreamWaitEvent(s, side->join, 0));
+    } else {
+        side_lock.unlock();
+        HIP_OR_FAIL(launch_lo_prep(H, s));
+        HIP_OR_FAIL(tim_record(tim, 1, s));
+        HIP_OR_FAIL(launch_raster(H, s));
+        HIP_OR_FAIL(tim_record(tim, 2, s));
+        HIP_OR_FAIL(launch_bvh_build(H, s));
+    }
+    if (side_lock.owns_lock()) side_lock.unlock();
+    if (tim) g_tim.beside[g_tim.next] = side != nullptr;
     HIP_OR_FAIL(tim_record(tim, 3, s));
     TravConfig tc = o.trav;
     tc.count = (o.flags & BAKE_FLAG_COUNT) != 0;
