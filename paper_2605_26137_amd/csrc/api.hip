@@ -546,7 +546,13 @@ int32_t run_backward(Plan& P, void* workspace, uint32_t nonce, hipStream_t s) {
     }
     if (!any_lo && !any_hi) return BAKE_OK;
     HIP_OR_FAIL(write_table(ws + P.L.grads, P.G.data(), sizeof(AssetGrad) * (size_t)P.L.n, s));
-    HIP_OR_FAIL(launch_backward(H, any_lo, any_hi, s));
+    std::lock_guard<std::mutex> side_lock(g_side_mu);
+    Side* side = side_stream(s);
+    if (side) {
+        HIP_OR_FAIL(launch_backward(H, any_lo, any_hi, s, side->s, side->fork, side->join));
+    } else {
+        HIP_OR_FAIL(launch_backward(H, any_lo, any_hi, s));
+    }
     return BAKE_OK;
 }
 

@@ -447,7 +447,8 @@ inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b
 
 }  // namespace
 
-hipError_t launch_backward(const BatchHost& H, bool any_lo, bool any_hi, hipStream_t s) {
+hipError_t launch_backward(const BatchHost& H, bool any_lo, bool any_hi, hipStream_t s, hipStream_t side,
+                           hipEvent_t fork, hipEvent_t join) {
     const Layout& L = H.L;
     char* ws = H.ws;
     hipError_t e;
@@ -465,6 +466,15 @@ hipError_t launch_backward(const BatchHost& H, bool any_lo, bool any_hi, hipStre
                            (uint32_t*)(ws + L.bwd_k0), (uint32_t*)(ws + L.bwd_v0));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+    // the low-poly and high-poly gradients only share the per-ray adjoint:
+    // with a second stream, the low-poly chain runs beside the sort
+    const bool beside = side != nullptr && any_lo && L.t_lv > 0 && any_hi && L.t_hv > 0;
+    hipStream_t ls = s;
+    if (beside) {
+        if ((e = hipEventRecord(fork, s)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(side, fork, 0)) != hipSuccess) return e;
+        ls = side;
+    }
     if (any_lo && L.t_lv > 0) {
         float* face1 = (float*)(ws + L.bwd_face1);
         float* face2 = (float*)(ws + L.bwd_face2);
@@ -473,20 +483,21 @@ hipError_t launch_backward(const BatchHost& H, bool any_lo, bool any_hi, hipStre
         const uint32_t* off = (const uint32_t*)(ws + L.lo_off);
         const int32_t* adj = (const int32_t*)(ws + L.lo_adj);
         if (H.blocks(kGLoFWave) > 0) {
-            hipLaunchKernelGGL(bwd_face_kernel, dim3((unsigned)H.blocks(kGLoFWave)), dim3(256), 0, s, H.dev,
+            hipLaunchKernelGGL(bwd_face_kernel, dim3((unsigned)H.blocks(kGLoFWave)), dim3(256), 0, ls, H.dev,
                                rays, (const RayGrad*)rg, (const uint32_t*)(ws + L.face_off),
                                (const int4*)(ws + L.face_uv), face1);
         }
-        hipLaunchKernelGGL(bwd_vertex1_kernel, dim3((unsigned)H.blocks(kGLoV)), dim3(256), 0, s, H.dev, off,
+        hipLaunchKernelGGL(bwd_vertex1_kernel, dim3((unsigned)H.blocks(kGLoV)), dim3(256), 0, ls, H.dev, off,
                            adj, (const float*)face1, vbar, sbar);
         if (H.blocks(kGLoF) > 0) {
-            hipLaunchKernelGGL(bwd_face2_kernel, dim3((unsigned)H.blocks(kGLoF)), dim3(256), 0, s, H.dev,
+            hipLaunchKernelGGL(bwd_face2_kernel, dim3((unsigned)H.blocks(kGLoF)), dim3(256), 0, ls, H.dev,
                                (const float*)sbar, face2);
         }
-        hipLaunchKernelGGL(bwd_vertex2_kernel, dim3((unsigned)H.blocks(kGLoV)), dim3(256), 0, s, H.dev, off,
+        hipLaunchKernelGGL(bwd_vertex2_kernel, dim3((unsigned)H.blocks(kGLoV)), dim3(256), 0, ls, H.dev, off,
                            adj, (const float*)face2, (const float*)vbar);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+    if (beside && (e = hipEventRecord(join, side)) != hipSuccess) return e;
     if (any_hi && L.t_hv > 0) {
         hipLaunchKernelGGL(zero_grad_hi_kernel, dim3((unsigned)H.blocks(kGHiV)), dim3(256), 0, s, H.dev);
         if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -499,6 +510,7 @@ hipError_t launch_backward(const BatchHost& H, bool any_lo, bool any_hi, hipStre
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
     }
+    if (beside && (e = hipStreamWaitEvent(s, join, 0)) != hipSuccess) return e;
     return hipSuccess;
 }
 

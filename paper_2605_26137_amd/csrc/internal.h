@@ -349,7 +349,10 @@ hipError_t qem_simplify_run(const QemLayout& L, char* ws, const float* V, const 
                             int32_t* rounds_out, int64_t* stats, float* times_ms, uint32_t* status, hipStream_t s);
 hipError_t launch_dilate(const BatchHost& H, int passes, hipStream_t s);
 hipError_t launch_rgb8(const BatchHost& H, hipStream_t s);
-hipError_t launch_backward(const BatchHost& H, bool any_lo, bool any_hi, hipStream_t s);
+// With `side` (and its fork / join events), the low-poly gradient chain runs on
+// `side` beside the high-poly one and joins `s` before the call returns.
+hipError_t launch_backward(const BatchHost& H, bool any_lo, bool any_hi, hipStream_t s, hipStream_t side = nullptr,
+                           hipEvent_t fork = nullptr, hipEvent_t join = nullptr);
 hipError_t launch_sq_loss(const float* map, const float* target, int64_t n3, float* grad, float* loss,
                           float* partial, hipStream_t s);
 
