@@ -417,7 +417,8 @@ int32_t bake_qem_simplify(const float *V, const int32_t *F, int64_t n_v, int64_t
 /* Every edge of the input mesh with its collapse evaluated, as the first
  * round of bake_qem_simplify sees it.  Device outputs (caller-owned, `cap`
  * rows): edges_out [cap][2] i32 (v0 < v1, in (v0, v1) order), valid_out [cap]
- * u8 (the collapse is allowed), faces_out [cap] i32 (faces on the edge),
+ * u8 (the collapse is allowed), faces_out [cap] i32 (faces on the edge; 7
+ * stands for seven or more),
  * cost_out [cap] f64 (max(E(p), 0); 0 where no placement was computed),
  * p_out [cap][3] f64 (the placement; zeros where none), Q_out NULL or
  * [n_v][10] f64 (vertex quadrics q00 q01 q02 q03 q11 q12 q13 q22 q23 q33).

@@ -171,11 +171,17 @@ __device__ __forceinline__ uint32_t shared_count(const int32_t* F, const uint32_
 // is an edge with a single face (v is then a boundary vertex).  The list is
 // gathered and insertion-sorted in LDS; vertices with more than kRingFaces
 // faces take a slower path over global memory.
-//   count pass: unique neighbours, neighbours above v, boundary flag;
+// A ring entry is (x << 3) | min(faces shared with x, 7): the ring carries
+// each edge's face count for the per-edge evaluation (vertex indices are
+// below 2^28).
+//   count pass: unique neighbours, neighbours above v, boundary flag, and
+//               rings of up to kRingKeep vertices kept at keep[v][...];
 //   write pass: the sorted ring into nbr[noff[v] ...] and the edges (v, x),
-//               x > v ascending, from eoff[v].
+//               x > v ascending, from eoff[v] (from keep when it holds the
+//               ring, else gathered again).
 constexpr int kRB = 128;        // threads per block of the ring kernels
 constexpr int kRingFaces = 24;  // faces per vertex sorted in LDS
+constexpr int kRingKeep = 16;   // ring entries kept per vertex between the two passes
 
 template <bool WRITE>
 __global__ void __launch_bounds__(kRB) qem_ring_kernel(const int32_t* __restrict__ F, int64_t nv,
@@ -184,12 +190,27 @@ __global__ void __launch_bounds__(kRB) qem_ring_kernel(const int32_t* __restrict
                                                        uint32_t* __restrict__ hcnt, uint32_t* __restrict__ bnd,
                                                        const uint32_t* __restrict__ noff,
                                                        const uint32_t* __restrict__ eoff, int32_t* __restrict__ nbr,
-                                                       int32_t* __restrict__ E) {
+                                                       int32_t* __restrict__ E, int32_t* __restrict__ keep) {
     __shared__ int32_t ent[2 * kRingFaces][kRB];
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= nv) return;
     const uint32_t b = off[v], n = off[v + 1] - b;
     const int t = threadIdx.x;
+    if (WRITE && n <= (uint32_t)kRingFaces && ncnt[v] <= (uint32_t)kRingKeep) {
+        const uint32_t m = ncnt[v];
+        const int32_t* kv = keep + (int64_t)kRingKeep * v;
+        uint32_t e = eoff[v], r = noff[v];
+        for (uint32_t j = 0; j < m; ++j) {
+            const int32_t code = kv[j], x = code >> 3;
+            nbr[r++] = code;
+            if (x > (int32_t)v) {
+                E[2 * (int64_t)e] = (int32_t)v;
+                E[2 * (int64_t)e + 1] = x;
+                ++e;
+            }
+        }
+        return;
+    }
     if (n <= (uint32_t)kRingFaces) {
         uint32_t m = 0;
         for (uint32_t i = 0; i < n; ++i) {
@@ -220,9 +241,11 @@ __global__ void __launch_bounds__(kRB) qem_ring_kernel(const int32_t* __restrict
             uint32_t k = i + 1;
             while (k < m && ent[k][t] == x) ++k;
             if (k - i == 1) boundary = 1;
+            const int32_t code = (x << 3) | (int32_t)(k - i < 7 ? k - i : 7);
+            if (!WRITE && uniq < (uint32_t)kRingKeep) keep[(int64_t)kRingKeep * v + uniq] = code;
             ++uniq;
             if (WRITE) {
-                nbr[r++] = x;
+                nbr[r++] = code;
                 if (x > (int32_t)v) {
                     E[2 * (int64_t)e] = (int32_t)v;
                     E[2 * (int64_t)e + 1] = x;
@@ -263,7 +286,8 @@ __global__ void __launch_bounds__(kRB) qem_ring_kernel(const int32_t* __restrict
                     if (y > (int32_t)v) ++below_hi;
                 }
             }
-            nbr[noff[v] + below] = x;
+            const uint32_t sc = shared_count(F, adj, b, n, x);
+            nbr[noff[v] + below] = (x << 3) | (int32_t)(sc < 7 ? sc : 7);
             if (x > (int32_t)v) {
                 const int64_t e = (int64_t)eoff[v] + below_hi;
                 E[2 * e] = (int32_t)v;
@@ -335,16 +359,24 @@ __global__ void qem_eval_kernel(EvalArgs a) {
     const int32_t v0 = a.E[2 * e], v1 = a.E[2 * e + 1];
     const uint32_t b0 = a.off[v0], n0 = a.off[v0 + 1] - b0;
     const uint32_t b1 = a.off[v1], n1 = a.off[v1 + 1] - b1;
-    const uint32_t c = shared_count(a.F, a.adj, b0, n0, v1);
+    const uint32_t r0 = a.noff[v0], m0 = a.noff[v0 + 1] - r0;
+    const uint32_t r1 = a.noff[v1], m1 = a.noff[v1 + 1] - r1;
+    // faces on the edge: v1's entry in v0's ring (seven stands for more)
+    uint32_t c = 0;
+    for (uint32_t i = 0; i < m0; ++i) {
+        const int32_t code = a.nbr[r0 + i];
+        if ((code >> 3) == v1) {
+            c = (uint32_t)(code & 7);
+            break;
+        }
+    }
     bool ok = c >= 1 && c <= 2;
     double p[3] = {0.0, 0.0, 0.0}, cost = 0.0;
     if (ok) {
         // link condition over the sorted rings
-        const uint32_t r0 = a.noff[v0], m0 = a.noff[v0 + 1] - r0;
-        const uint32_t r1 = a.noff[v1], m1 = a.noff[v1 + 1] - r1;
         uint32_t i = 0, j = 0, common = 0;
         while (i < m0 && j < m1) {
-            const int32_t x = a.nbr[r0 + i], y = a.nbr[r1 + j];
+            const int32_t x = a.nbr[r0 + i] >> 3, y = a.nbr[r1 + j] >> 3;
             if (x == y) {
                 ++common;
                 ++i;
@@ -845,6 +877,7 @@ size_t qem_layout(int64_t nv, int64_t nf, QemLayout* L) {
     L->eoff = take(4 * (size_t)(nv + 1));
     L->bnd = take(4 * (size_t)nv);
     L->nbr = take(4 * (size_t)nbr_cap);
+    L->keep_ring = take(4 * (size_t)kRingKeep * (size_t)nv);
     L->E = take(8 * (size_t)cap);
     L->bits = take(4 * (size_t)cap);
     L->faces = take((size_t)cap);
@@ -864,7 +897,7 @@ namespace {
 struct QemPtrs {
     uint32_t *cnt, *hist, *keep, *koff, *deg, *off, *cur, *adj, *ncnt, *noff, *hcnt, *eoff, *bnd, *bits, *scan_tmp;
     double *P, *Q, *pl;
-    int32_t *F, *F2, *nbr, *E, *partner;
+    int32_t *F, *F2, *nbr, *keep_ring, *E, *partner;
     uint8_t *faces, *wflag;
     uint32_t* part;
     uint64_t *m, *M;
@@ -893,6 +926,7 @@ QemPtrs ptrs(const QemLayout& L, char* ws) {
     p.F = (int32_t*)(ws + L.F);
     p.F2 = (int32_t*)(ws + L.F2);
     p.nbr = (int32_t*)(ws + L.nbr);
+    p.keep_ring = (int32_t*)(ws + L.keep_ring);
     p.E = (int32_t*)(ws + L.E);
     p.partner = (int32_t*)(ws + L.partner);
     p.faces = (uint8_t*)(ws + L.faces);
@@ -924,12 +958,12 @@ hipError_t build_edges(const QemLayout& L, const QemPtrs& p, hipStream_t s) {
     const int64_t nv = L.nv;
     const int64_t g = nv <= 0 ? 1 : (nv + kRB - 1) / kRB;
     hipLaunchKernelGGL(qem_ring_kernel<false>, dim3(g), dim3(kRB), 0, s, p.F, nv, p.off, p.adj, p.ncnt, p.hcnt,
-                       p.bnd, p.noff, p.eoff, p.nbr, p.E);
+                       p.bnd, p.noff, p.eoff, p.nbr, p.E, p.keep_ring);
     QEM_TRY(hipGetLastError());
     QEM_TRY(exclusive_scan_u32(p.ncnt, p.noff, nv, p.scan_tmp, p.noff + nv, s));
     QEM_TRY(exclusive_scan_u32(p.hcnt, p.eoff, nv, p.scan_tmp, p.cnt + kQcEdges, s));
     hipLaunchKernelGGL(qem_ring_kernel<true>, dim3(g), dim3(kRB), 0, s, p.F, nv, p.off, p.adj, p.ncnt, p.hcnt,
-                       p.bnd, p.noff, p.eoff, p.nbr, p.E);
+                       p.bnd, p.noff, p.eoff, p.nbr, p.E, p.keep_ring);
     return hipGetLastError();
 }
 
@@ -1023,7 +1057,7 @@ hipError_t qem_simplify_run(const QemLayout& L, char* ws, const float* V, const 
         if (times_ms) QEM_TRY(hipEventRecord(tev[0], s));
         QEM_TRY(eval_edges(p, egrid, midpoint, nullptr, nullptr, s));
         if (times_ms) QEM_TRY(hipEventRecord(tev[1], s));
-        const int64_t hgrid = std::min<int64_t>(blocks_for(egrid), 2048);
+        const int64_t hgrid = std::min<int64_t>(blocks_for(egrid), 256);  // few blocks: each merges its bins with global atomics
         for (int level = 0; level < 4; ++level) {
             hipLaunchKernelGGL(qem_hist_kernel, dim3(hgrid), dim3(kQB), 0, s, p.bits, p.cnt + kQcEdges,
                                hgrid * kQB, p.hist, level, rho);
