@@ -334,7 +334,7 @@ hipError_t launch_flood_fill(const BatchHost& H, const FillRun& f, hipStream_t s
 // two blocking drivers (they synchronise `s` to read the per-round counts).
 struct QemLayout {
     int64_t nv, nf, edge_cap;
-    size_t cnt, hist, P, Q, F, F2, keep, koff, deg, off, cur, adj, ncnt, noff, hcnt, eoff, bnd, nbr, keep_ring, E, bits, faces,
+    size_t cnt, hist, P, Q, P2, Q2, F, F2, keep, koff, deg, off, cur, adj, ncnt, noff, hcnt, eoff, bnd, nbr, keep_ring, E, bits, faces,
         pl, m, M, partner, wflag, part, scan_tmp;
     size_t total;
 };

@@ -41,6 +41,9 @@
 // counts and FP64 placements, and the winner keys.
 #pragma clang fp contract(off)
 
+#include <algorithm>
+#include <utility>
+
 #include "internal.h"
 
 namespace bake {
@@ -92,16 +95,21 @@ __global__ void qem_init_kernel(const float* __restrict__ V, int64_t nv, const i
 
 // ---- vertex -> face lists -------------------------------------------------
 
+// A face with a repeated vertex (only the stand-in for a bad input face, which
+// fails the call after set-up) joins no vertex's list: every list then holds
+// distinct faces.
+__device__ __forceinline__ bool proper(const int32_t* f) { return f[0] != f[1] && f[1] != f[2] && f[0] != f[2]; }
+
 __global__ void qem_deg_kernel(const int32_t* __restrict__ F, int64_t live, uint32_t* __restrict__ deg) {
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= live) return;
+    if (f >= live || !proper(F + 3 * f)) return;
     for (int k = 0; k < 3; ++k) atomicAdd(&deg[F[3 * f + k]], 1u);
 }
 
 __global__ void qem_adj_kernel(const int32_t* __restrict__ F, int64_t live, const uint32_t* __restrict__ off,
                                uint32_t* __restrict__ cur, uint32_t* __restrict__ adj) {
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= live) return;
+    if (f >= live || !proper(F + 3 * f)) return;
     for (int k = 0; k < 3; ++k) {
         const int32_t v = F[3 * f + k];
         const uint32_t slot = atomicAdd(&cur[v], 1u);
@@ -126,6 +134,7 @@ __global__ void qem_quadric_kernel(const double* __restrict__ P, const int32_t* 
             const int64_t g = adj[b + i];
             if (g > last && g < f) f = g;
         }
+        if (f == INT64_MAX) break;  // (the list's faces are distinct: not reached)
         last = f;
         const int32_t* fv = F + 3 * f;
         const double* a = P + 3 * (int64_t)fv[0];
@@ -562,7 +571,7 @@ __global__ void __launch_bounds__(kQB) qem_hist_kernel(const uint32_t* __restric
 
 // Counter slots of a round
 constexpr int kQcEdges = 0, kQcValid = 1, kQcTau = 4, kQcLive = 5, kQcApplied = 6, kQcRemoved = 7, kQcCutLo = 8,
-              kQcCutHi = 9, kQcStatus = 10, kQcOut = 11, kQcSlots = 16;
+              kQcCutHi = 9, kQcStatus = 10, kQcOut = 11, kQcVerts = 12, kQcSlots = 16;
 
 // m(v): least key of the eligible edges at v.
 __global__ void __launch_bounds__(kQB) qem_vmin_kernel(const int32_t* __restrict__ E,
@@ -803,6 +812,28 @@ __global__ void qem_face_scatter_kernel(const int32_t* __restrict__ F2, int64_t 
     F[3 * o + 2] = F2[3 * f + 2];
 }
 
+// ---- renumbering -----------------------------------------------------------
+// Once most vertices are gone, the survivors are renumbered in their order
+// (new index = rank among the vertices a live face references): the edge
+// order, the keys and the lower-index rule are unchanged, and the per-vertex
+// passes of later rounds cover only the survivors.
+
+__global__ void qem_vmove_kernel(const double* __restrict__ P, const double* __restrict__ Q, int64_t nv,
+                                 const uint32_t* __restrict__ ref, const uint32_t* __restrict__ vid,
+                                 double* __restrict__ P2, double* __restrict__ Q2) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv || !ref[v]) return;
+    const int64_t o = vid[v];
+    for (int k = 0; k < 3; ++k) P2[3 * o + k] = P[3 * v + k];
+    for (int k = 0; k < 10; ++k) Q2[10 * o + k] = Q[10 * v + k];
+}
+
+__global__ void qem_frenum_kernel(int32_t* __restrict__ F, int64_t live, const uint32_t* __restrict__ vid) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= live) return;
+    for (int k = 0; k < 3; ++k) F[3 * f + k] = (int32_t)vid[F[3 * f + k]];
+}
+
 // ---- output ---------------------------------------------------------------
 
 __global__ void qem_ref_kernel(const int32_t* __restrict__ F, int64_t live, uint32_t* __restrict__ ref) {
@@ -863,6 +894,8 @@ size_t qem_layout(int64_t nv, int64_t nf, QemLayout* L) {
     L->hist = take(4 * 256 * 4);
     L->P = take(24 * (size_t)nv);
     L->Q = take(80 * (size_t)nv);
+    L->P2 = take(24 * (size_t)nv);
+    L->Q2 = take(80 * (size_t)nv);
     L->F = take(12 * (size_t)nf);
     L->F2 = take(12 * (size_t)nf);
     L->keep = take(4 * (size_t)nf);
@@ -896,7 +929,7 @@ namespace {
 
 struct QemPtrs {
     uint32_t *cnt, *hist, *keep, *koff, *deg, *off, *cur, *adj, *ncnt, *noff, *hcnt, *eoff, *bnd, *bits, *scan_tmp;
-    double *P, *Q, *pl;
+    double *P, *Q, *P2, *Q2, *pl;
     int32_t *F, *F2, *nbr, *keep_ring, *E, *partner;
     uint8_t *faces, *wflag;
     uint32_t* part;
@@ -922,6 +955,8 @@ QemPtrs ptrs(const QemLayout& L, char* ws) {
     p.scan_tmp = (uint32_t*)(ws + L.scan_tmp);
     p.P = (double*)(ws + L.P);
     p.Q = (double*)(ws + L.Q);
+    p.P2 = (double*)(ws + L.P2);
+    p.Q2 = (double*)(ws + L.Q2);
     p.pl = (double*)(ws + L.pl);
     p.F = (int32_t*)(ws + L.F);
     p.F2 = (int32_t*)(ws + L.F2);
@@ -944,8 +979,7 @@ QemPtrs ptrs(const QemLayout& L, char* ws) {
     } while (0)
 
 // vertex -> face lists of the `live` current faces (deg and cur zeroed)
-hipError_t build_lists(const QemLayout& L, const QemPtrs& p, int64_t live, hipStream_t s) {
-    const int64_t nv = L.nv;
+hipError_t build_lists(int64_t nv, const QemPtrs& p, int64_t live, hipStream_t s) {
     hipLaunchKernelGGL(qem_deg_kernel, dim3(blocks_for(live)), dim3(kQB), 0, s, p.F, live, p.deg);
     QEM_TRY(hipGetLastError());
     QEM_TRY(exclusive_scan_u32(p.deg, p.off, nv, p.scan_tmp, p.off + nv, s));
@@ -954,8 +988,7 @@ hipError_t build_lists(const QemLayout& L, const QemPtrs& p, int64_t live, hipSt
 }
 
 // rings and edges of the current mesh; edge count at cnt[kQcEdges]
-hipError_t build_edges(const QemLayout& L, const QemPtrs& p, hipStream_t s) {
-    const int64_t nv = L.nv;
+hipError_t build_edges(int64_t nv, const QemPtrs& p, hipStream_t s) {
     const int64_t g = nv <= 0 ? 1 : (nv + kRB - 1) / kRB;
     hipLaunchKernelGGL(qem_ring_kernel<false>, dim3(g), dim3(kRB), 0, s, p.F, nv, p.off, p.adj, p.ncnt, p.hcnt,
                        p.bnd, p.noff, p.eoff, p.nbr, p.E, p.keep_ring);
@@ -998,7 +1031,7 @@ hipError_t set_up(const QemLayout& L, const QemPtrs& p, const float* V, const in
     QEM_TRY(hipGetLastError());
     QEM_TRY(fill_u32(p.deg, 0, L.nv + 1, s));
     QEM_TRY(fill_u32(p.cur, 0, L.nv, s));
-    QEM_TRY(build_lists(L, p, L.nf, s));
+    QEM_TRY(build_lists(L.nv, p, L.nf, s));
     hipLaunchKernelGGL(qem_quadric_kernel, dim3(blocks_for(L.nv)), dim3(kQB), 0, s, p.P, p.F, L.nv, p.off, p.adj,
                        p.Q);
     return hipGetLastError();
@@ -1011,7 +1044,7 @@ hipError_t qem_edges_run(const QemLayout& L, char* ws, const float* V, const int
                          double* cost_out, double* p_out, uint32_t* status, int64_t* n_edges, hipStream_t s) {
     const QemPtrs p = ptrs(L, ws);
     QEM_TRY(set_up(L, p, V, F, s));
-    QEM_TRY(build_edges(L, p, s));
+    QEM_TRY(build_edges(L.nv, p, s));
     uint32_t h[kQcSlots];
     QEM_TRY(hipMemcpyAsync(h, p.cnt, sizeof h, hipMemcpyDeviceToHost, s));
     QEM_TRY(hipStreamSynchronize(s));
@@ -1029,7 +1062,7 @@ hipError_t qem_edges_run(const QemLayout& L, char* ws, const float* V, const int
 hipError_t qem_simplify_run(const QemLayout& L, char* ws, const float* V, const int32_t* F, int64_t target, double rho,
                             int32_t max_rounds, int midpoint, float* V_out, int32_t* F_out, int64_t* counts,
                             int32_t* rounds_out, int64_t* stats, float* times_ms, uint32_t* status, hipStream_t s) {
-    const QemPtrs p = ptrs(L, ws);
+    QemPtrs p = ptrs(L, ws);
     // optional timing: the whole call, and the per-edge evaluation launches summed
     static thread_local hipEvent_t tev[4] = {nullptr, nullptr, nullptr, nullptr};
     if (times_ms) {
@@ -1044,15 +1077,15 @@ hipError_t qem_simplify_run(const QemLayout& L, char* ws, const float* V, const 
     QEM_TRY(hipStreamSynchronize(s));
     *status = h[kQcStatus];
     if (h[kQcStatus]) return hipSuccess;
-    const int64_t nv = L.nv;
+    int64_t nv = L.nv;  // vertex slots in use (shrinks when the survivors are renumbered)
     int64_t live = L.nf;
     int32_t round = 0;
     while (live > target && round < max_rounds) {
         hipLaunchKernelGGL(qem_reset_kernel, dim3(blocks_for(std::max<int64_t>(nv + 1, 4 * 256))), dim3(kQB), 0, s,
                            nv, (uint32_t)live, round > 0 ? 1 : 0, p.cnt, p.hist, p.m, p.M, p.partner, p.deg, p.cur);
         QEM_TRY(hipGetLastError());
-        if (round > 0) QEM_TRY(build_lists(L, p, live, s));
-        QEM_TRY(build_edges(L, p, s));
+        if (round > 0) QEM_TRY(build_lists(nv, p, live, s));
+        QEM_TRY(build_edges(nv, p, s));
         const int64_t egrid = 3 * live;
         if (times_ms) QEM_TRY(hipEventRecord(tev[0], s));
         QEM_TRY(eval_edges(p, egrid, midpoint, nullptr, nullptr, s));
@@ -1100,6 +1133,27 @@ hipError_t qem_simplify_run(const QemLayout& L, char* ws, const float* V, const 
         }
         ++round;
         if (h[kQcApplied] == 0) break;
+        if (live > target && live < nv) {
+            // about twice as many slots as live vertices (a closed mesh has
+            // about two faces per vertex): renumber the survivors
+            uint32_t* ref = p.deg;  // per-round scratch until the next lists
+            uint32_t* vid = p.off;
+            QEM_TRY(fill_u32(ref, 0, nv + 1, s));
+            hipLaunchKernelGGL(qem_ref_kernel, dim3(blocks_for(live)), dim3(kQB), 0, s, p.F, live, ref);
+            QEM_TRY(hipGetLastError());
+            QEM_TRY(exclusive_scan_u32(ref, vid, nv, p.scan_tmp, p.cnt + kQcVerts, s));
+            hipLaunchKernelGGL(qem_vmove_kernel, dim3(blocks_for(nv)), dim3(kQB), 0, s, p.P, p.Q, nv, ref, vid, p.P2,
+                               p.Q2);
+            QEM_TRY(hipGetLastError());
+            hipLaunchKernelGGL(qem_frenum_kernel, dim3(blocks_for(live)), dim3(kQB), 0, s, p.F, live, vid);
+            QEM_TRY(hipGetLastError());
+            uint32_t nvn = 0;
+            QEM_TRY(hipMemcpyAsync(&nvn, p.cnt + kQcVerts, 4, hipMemcpyDeviceToHost, s));
+            QEM_TRY(hipStreamSynchronize(s));
+            nv = nvn;
+            std::swap(p.P, p.P2);
+            std::swap(p.Q, p.Q2);
+        }
     }
     *rounds_out = round;
     // output: referenced vertices in ascending index, faces in their order

@@ -136,12 +136,23 @@ def test_empty_mesh(B):
     assert gV.shape == (0, 3) and gF.shape == (0, 3) and gr == 0
 
 
-def test_bad_faces_are_reported(B):
+@pytest.mark.parametrize("fill", [None, 0x7F])
+def test_bad_faces_are_reported(B, fill):
+    # a bad face is replaced by a degenerate stand-in that joins no vertex's
+    # face list; the workspace filled with a byte pattern first makes sure no
+    # pass reads anything the call did not write
     V, F = S.noisy_sphere(1, seed=0)
     for bad in (np.array([[0, 1, V.shape[0]]]), np.array([[0, 1, -1]]), np.array([[2, 2, 3]])):
-        say(f"[gpu] qem bad face {bad.tolist()}")
+        say(f"[gpu] qem bad face {bad.tolist()} workspace fill {fill}")
+        Fb = np.concatenate([F, bad])
+        ws = None
+        if fill is not None:
+            ws = torch.full((B.qem_workspace_size(V.shape[0], Fb.shape[0]),), fill, dtype=torch.uint8, device="cuda")
         with pytest.raises(B.BakeError) as e:
-            B.qem_simplify(dev(V, np.float32), dev(np.concatenate([F, bad]), np.int32), 10)
+            B.qem_simplify(dev(V, np.float32), dev(Fb, np.int32), 10, workspace=ws)
+        assert e.value.code == B.BAKE_E_INDEX
+        with pytest.raises(B.BakeError) as e:
+            B.qem_edges(dev(V, np.float32), dev(Fb, np.int32), workspace=ws)
         assert e.value.code == B.BAKE_E_INDEX
 
 
