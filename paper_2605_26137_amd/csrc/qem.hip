@@ -314,18 +314,28 @@ __global__ void __launch_bounds__(kRB) qem_ring_kernel(const int32_t* __restrict
 // ---- per-edge collapse ----------------------------------------------------
 
 // Faces around `moved` that lack `other` keep a positive dot of old and new
-// normal when `moved` goes to p.
+// normal when `moved` (now at pm) goes to p; only the other two corners are
+// loaded.
 __device__ bool no_fold(const double* P, const int32_t* F, const uint32_t* adj, uint32_t b, uint32_t n,
-                        int32_t moved, int32_t other, const double* p) {
+                        int32_t moved, int32_t other, const double* pm, const double* p) {
     for (uint32_t i = 0; i < n; ++i) {
         const int32_t* f = F + 3 * (int64_t)adj[b + i];
-        if (holds(f, other)) continue;
+        const int32_t f0 = f[0], f1 = f[1], f2 = f[2];
+        if (f0 == other || f1 == other || f2 == other) continue;
+        const int32_t fk[3] = {f0, f1, f2};
         double a[3][3], q[3][3];
         for (int k = 0; k < 3; ++k) {
-            const double* src = P + 3 * (int64_t)f[k];
-            for (int c = 0; c < 3; ++c) {
-                a[k][c] = src[c];
-                q[k][c] = f[k] == moved ? p[c] : src[c];
+            if (fk[k] == moved) {
+                for (int c = 0; c < 3; ++c) {
+                    a[k][c] = pm[c];
+                    q[k][c] = p[c];
+                }
+            } else {
+                const double* src = P + 3 * (int64_t)fk[k];
+                for (int c = 0; c < 3; ++c) {
+                    a[k][c] = src[c];
+                    q[k][c] = src[c];
+                }
             }
         }
         double e1[3], e2[3], g1[3], g2[3];
@@ -452,7 +462,8 @@ __global__ void qem_eval_kernel(EvalArgs a) {
         const double E = qerr(q, p);
         if (E == E) {
             cost = E > 0.0 ? E : 0.0;
-            ok = no_fold(a.P, a.F, a.adj, b0, n0, v0, v1, p) && no_fold(a.P, a.F, a.adj, b1, n1, v1, v0, p);
+            const double m0[3] = {p0[0], p0[1], p0[2]}, m1[3] = {p1[0], p1[1], p1[2]};
+            ok = no_fold(a.P, a.F, a.adj, b0, n0, v0, v1, m0, p) && no_fold(a.P, a.F, a.adj, b1, n1, v1, v0, m1, p);
         } else {
             ok = false;
         }
