@@ -283,11 +283,12 @@ int32_t bake_workspace_view(int64_t n_hi_v, int64_t n_hi_f, int64_t n_lo_v, int6
  * BAKE_FLAG_TIMING, from HIP events recorded on the bake's stream
  * (synchronises on those events).  Stages: 0 lo prep, 1 raster (+ uncovered
  * fill), 2 BVH build, 3 traversal + encode, 4 dilation (+ RGB8), 5 whole
- * forward.  The lo prep and raster run beside the BVH build on a second
- * stream of the library (forked from and joined to the bake's stream by
- * events; created on the device's first forward that is not being graph
- * captured): stage 2 then spans from the start of the bake to the end of all
- * three.  Returns the number of stages written. */
+ * forward.  For batches of at least 65,536 high-poly faces the lo prep and
+ * raster run beside the BVH build on a second stream of the library (forked
+ * from and joined to the bake's stream by events; created on the device's
+ * first such forward that is not being graph captured): stage 2 then spans
+ * from the start of the bake to the end of all three.  Returns the number of
+ * stages written. */
 int32_t bake_stage_times(float *ms_out, int32_t n);
 
 /* The same for up to the 64 most recent timed bakes on this thread, oldest

@@ -449,6 +449,7 @@ int32_t check_workspace(const void* ws, size_t bytes, const Layout& L) {
 // the caller's stream).  Default priority.  The fork-join enqueue is
 // serialised so that concurrent callers never see each other's event records.
 constexpr int kMaxDevices = 64;
+constexpr int64_t kSideMinFaces = 1 << 16;  // high-poly faces of a batch below which one stream is used
 struct Side {
     hipStream_t s = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
@@ -492,8 +493,10 @@ int32_t run_forward(Plan& P, const Opts& o, void* workspace, hipStream_t s) {
     memcpy(blob.data() + (L.gpf - L.table), P.gpf.data(), 4 * P.gpf.size());
     HIP_OR_FAIL(write_table(ws + L.table, blob.data(), (L.gpf - L.table) + 4 * P.gpf.size(), s));
     HIP_OR_FAIL(fill_u32((uint32_t*)ws, 0, (int64_t)(L.table / 4), s));
+    // small bakes run on one stream: there the fork and join cost more than
+    // the overlap saves
     std::unique_lock<std::mutex> side_lock(g_side_mu);
-    Side* side = side_stream(s);
+    Side* side = L.t_hf >= kSideMinFaces ? side_stream(s) : nullptr;
     if (side) {
         HIP_OR_FAIL(hipEventRecord(side->fork, s));
         HIP_OR_FAIL(hipStreamWaitEvent(side->s, side->fork, 0));
@@ -547,7 +550,7 @@ int32_t run_backward(Plan& P, void* workspace, uint32_t nonce, hipStream_t s) {
     if (!any_lo && !any_hi) return BAKE_OK;
     HIP_OR_FAIL(write_table(ws + P.L.grads, P.G.data(), sizeof(AssetGrad) * (size_t)P.L.n, s));
     std::lock_guard<std::mutex> side_lock(g_side_mu);
-    Side* side = side_stream(s);
+    Side* side = P.L.t_hf >= kSideMinFaces ? side_stream(s) : nullptr;
     if (side) {
         HIP_OR_FAIL(launch_backward(H, any_lo, any_hi, s, side->s, side->fork, side->join));
     } else {
