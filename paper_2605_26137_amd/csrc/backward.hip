@@ -474,6 +474,10 @@ hipError_t launch_backward(const BatchHost& H, bool any_lo, bool any_hi, hipStre
         if ((e = hipEventRecord(fork, s)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(side, fork, 0)) != hipSuccess) return e;
         ls = side;
+        // the zeroing of dL/dhi_N goes to the second stream too; the segment
+        // sums wait for it (and for the low-poly chain) after the sort
+        hipLaunchKernelGGL(zero_grad_hi_kernel, dim3((unsigned)H.blocks(kGHiV)), dim3(256), 0, side, H.dev);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (any_lo && L.t_lv > 0) {
         float* face1 = (float*)(ws + L.bwd_face1);
@@ -499,11 +503,14 @@ hipError_t launch_backward(const BatchHost& H, bool any_lo, bool any_hi, hipStre
     }
     if (beside && (e = hipEventRecord(join, side)) != hipSuccess) return e;
     if (any_hi && L.t_hv > 0) {
-        hipLaunchKernelGGL(zero_grad_hi_kernel, dim3((unsigned)H.blocks(kGHiV)), dim3(256), 0, s, H.dev);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (!beside) {
+            hipLaunchKernelGGL(zero_grad_hi_kernel, dim3((unsigned)H.blocks(kGHiV)), dim3(256), 0, s, H.dev);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
         if (L.t_tex > 0) {
             bool in1 = false;
             if ((e = launch_sort(H, kSortBwd, L.max_hv_bits, &in1, s)) != hipSuccess) return e;
+            if (beside && (e = hipStreamWaitEvent(s, join, 0)) != hipSuccess) return e;
             hipLaunchKernelGGL(bwd_hiN_kernel, dim3(ray_grid), dim3(256), 0, s, H.dev,
                                (const uint32_t*)(ws + (in1 ? L.bwd_k1 : L.bwd_k0)),
                                (const uint32_t*)(ws + (in1 ? L.bwd_v1 : L.bwd_v0)), hits, (const RayGrad*)rg);

@@ -268,7 +268,7 @@ hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint
         if (total) return fill_u32(total, 0, 1, s);
         return hipSuccess;
     }
-    if (n <= (int64_t)4 * kSmallBlock * kSmallItems) {  // up to four tiles: one launch beats three
+    if (n <= (int64_t)kSmallBlock * kSmallItems) {  // one tile: a single launch beats three
         hipLaunchKernelGGL(scan_small_kernel, dim3(1), dim3(kSmallBlock), 0, s, in, out, n, total);
         return hipGetLastError();
     }
