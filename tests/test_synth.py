@@ -92,3 +92,50 @@ def test_config_shapes_small():
     assert a.lo_UV.shape == (80, 3, 2) and a.res == 128 and a.max_dist == 0.1
     assert a.hi_V.dtype == np.float32 and a.hi_F.dtype == np.int32
     assert np.allclose(np.linalg.norm(a.hi_N, axis=1), 1, atol=1e-6)
+
+
+# ---- the simplification's shapes ------------------------------------------
+
+def _edge_counts(F):
+    import numpy as np
+    F = np.asarray(F, np.int64)
+    e = np.sort(np.concatenate([F[:, [0, 1]], F[:, [1, 2]], F[:, [2, 0]]]), axis=1)
+    _, c = np.unique(e, axis=0, return_counts=True)
+    return c
+
+
+def test_closed_shapes_are_oriented_genus_zero_manifolds():
+    import numpy as np
+    from synth import shapes as S
+    for V, F in (S.cube_grid(1), S.cube_grid(4), S.tetrahedron(), S.bipyramid(), S.octahedron(),
+                 S.noisy_sphere(2, seed=1)):
+        V = np.asarray(V, np.float64)
+        c = _edge_counts(F)
+        assert (c == 2).all()
+        assert V.shape[0] - c.size + F.shape[0] == 2
+        a, b, d = (V[np.asarray(F)[:, k]] for k in range(3))
+        n = np.cross(b - a, d - a)
+        centre = V.mean(0)
+        assert ((n * ((a + b + d) / 3 - centre)).sum(1) > 0).all()    # outward (star-shaped shapes)
+
+
+def test_cube_grid_and_patch_counts():
+    import numpy as np
+    from synth import shapes as S
+    V, F = S.cube_grid(3)
+    assert V.shape == (6 * 9 + 2, 3) and F.shape == (12 * 9, 3)
+    assert set(np.unique(V)) <= {0.0, 1 / 3, 2 / 3, 1.0}
+    V, F = S.grid_patch(5, amp=0.2, seed=3)
+    assert V.shape == (36, 3) and F.shape == (50, 3)
+    c = _edge_counts(F)
+    assert (c == 1).sum() == 4 * 5 and ((c == 1) | (c == 2)).all()   # the square's border
+
+
+def test_simplify_inputs_are_seeded_and_sized():
+    import numpy as np
+    from synth import shapes as S
+    V, F, target, name = S.simplify_input(0)
+    V2, F2, _, _ = S.simplify_input(0)
+    assert F.shape == (20480, 3) and target == 1000 and V.dtype == np.float32 and F.dtype == np.int32
+    assert np.array_equal(V, V2) and np.array_equal(F, F2)
+    assert not np.array_equal(V, S.simplify_input(0, seed=1)[0])
