@@ -486,7 +486,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the bake runs on a single device here "
-              "(DESIGN.md describes how it would shard); run with --gpus 1", file=sys.stderr)
+              "(forward shards by rays or assets with no exchange; the backward reduces the "
+              "per-GPU gradients in a fixed rank order); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

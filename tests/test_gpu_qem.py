@@ -176,7 +176,7 @@ def test_full_size_first_round_matches_the_oracle(B, oracle_lib, big):
     V, F, target = big
     gV, gF, gr, gst = gpu_simplify(B, V, F, target, max_rounds=1)
     o = oracle_lib.qem_simplify(V, F, target, method="rounds", max_rounds=1)
-    say(f"[gpu] full size round 1: {gst.tolist()}")
+    say(f"[gpu] full size, first collapse round: {gst.tolist()}")
     np.testing.assert_array_equal(gst, o.stats)
     np.testing.assert_array_equal(gF, o.F)
     np.testing.assert_array_equal(gV, o.V.astype(np.float32))
