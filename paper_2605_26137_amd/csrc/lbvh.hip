@@ -92,17 +92,31 @@ __global__ __launch_bounds__(kBlock) void bounds_part_kernel(Batch Bt, float* __
     float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
     bool anybad = false, nonfin = false;
     const int64_t end = min((int64_t)As.nhf, (lt + 1) * kSortTile);
-    for (int64_t g = lt * kSortTile + threadIdx.x; g < end; g += kBlock) {
-        bool bad;
-        int3 t = tri_idx(F, g, As.nhv, &bad);
-        anybad |= bad;
-        float3 c = centroid(V, t);
-        if (!(isfinite(c.x) && isfinite(c.y) && isfinite(c.z))) {
-            nonfin = true;
-            continue;
+    // kU triangles per thread and trip, their index and vertex loads issued
+    // together (one gather latency per trip instead of per triangle)
+    constexpr int kU = 4;
+    for (int64_t g0 = lt * kSortTile + threadIdx.x; g0 < end; g0 += kU * kBlock) {
+        int3 t[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            bool bad = false;
+            const int64_t g = g0 + (int64_t)u * kBlock;
+            t[u] = g < end ? tri_idx(F, g, As.nhv, &bad) : make_int3(0, 0, 0);
+            anybad |= bad;
         }
-        v[0] = fminf(v[0], c.x); v[1] = fminf(v[1], c.y); v[2] = fminf(v[2], c.z);
-        v[3] = fmaxf(v[3], c.x); v[4] = fmaxf(v[4], c.y); v[5] = fmaxf(v[5], c.z);
+        float3 c[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) c[u] = centroid(V, t[u]);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            if (g0 + (int64_t)u * kBlock >= end) continue;
+            if (!(isfinite(c[u].x) && isfinite(c[u].y) && isfinite(c[u].z))) {
+                nonfin = true;
+                continue;
+            }
+            v[0] = fminf(v[0], c[u].x); v[1] = fminf(v[1], c[u].y); v[2] = fminf(v[2], c[u].z);
+            v[3] = fmaxf(v[3], c[u].x); v[4] = fmaxf(v[4], c[u].y); v[5] = fmaxf(v[5], c[u].z);
+        }
     }
     if (anybad) set_status(Bt, kStHiIndex);
     if (nonfin) set_status(Bt, kStNonFinite);
