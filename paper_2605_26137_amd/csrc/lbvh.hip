@@ -247,10 +247,13 @@ __global__ __launch_bounds__(kSortBlock) void radix_hist_kernel(Batch Bt, const 
 // (earlier rounds, earlier waves, earlier lanes): a stable order.  The tile is
 // first placed in LDS in that order (digit runs contiguous), then written out
 // with consecutive lanes on consecutive positions of each run.  The tile's
-// first position of each digit comes from the count rows (see kSuper).  Per
-// round: ballot ranks within each wave, then one thread per digit turns the
-// per-wave counts into positions (double-buffered, so a round needs two
-// barriers).
+// first position of each digit comes from the count rows (see kSuper).  The
+// keys are loaded first, so that their latency overlaps the reads of the
+// count rows.  Ranking: each wave finds, per round, the lanes of each digit
+// (ballots over the digit's bits) and records their count for its (round,
+// wave, digit); one scan per digit over the 64 (round, wave) counts, in that
+// order, then turns the counts into positions, so the whole tile is ranked
+// between two barriers.
 template <bool BWD>
 __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(Batch Bt, const uint32_t* __restrict__ kin,
                                                                    const uint32_t* __restrict__ vin,
@@ -258,24 +261,36 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(Batch Bt, con
                                                                    uint32_t* __restrict__ vout, int shift,
                                                                    const uint32_t* __restrict__ hist,
                                                                    const uint32_t* __restrict__ sup) {
-    __shared__ uint32_t s_key[kSortTile];
+    __shared__ uint32_t s_key[kSortTile];  // also the scratch of the count-row sums
     __shared__ uint32_t s_val[kSortTile];
     __shared__ uint32_t s_loc[256];   // tile-local first position of each digit
     __shared__ uint32_t s_glob[256];  // global position of the tile's first key of each digit
-    __shared__ uint32_t s_run[256];   // digit counts, then running positions
+    __shared__ uint32_t s_run[256];   // the tile's digit counts
     __shared__ uint32_t s_wsum[4];
-    __shared__ uint32_t wcnt[2][kSortWaves][256];  // per-wave digit counts, then positions
+    __shared__ uint32_t s_part[kSortRounds][256];  // per round: the digit's keys in the round
+    // per (round, wave, digit): the count, then the tile-local first position
+    __shared__ uint16_t wcnt[kSortRounds][kSortWaves][256];
+    static_assert(kSortTile <= 65535, "tile positions are kept in 16 bits");
+    static_assert(kSortBlock == 4 * 256 && kSortRounds * kSortWaves == 64, "one scan thread per (round, digit)");
     if (BWD && !sealed(Bt)) return;
     const SortTile T = sort_tile<BWD>(Bt, blockIdx.x);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t base = T.lt * kSortTile;
     const int64_t nvalid = min((int64_t)kSortTile, T.count - base);
     if (nvalid <= 0) return;  // an empty capacity tile (uniform)
+    uint32_t key[kSortRounds], val[kSortRounds];
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+        const int64_t i = (int64_t)r * kSortBlock + tid;
+        const bool valid = i < nvalid;
+        key[r] = valid ? kin[T.start + base + i] : 0u;
+        val[r] = valid ? vin[T.start + base + i] : 0u;
+    }
+    uint32_t(*scratch)[256] = reinterpret_cast<uint32_t(*)[256]>(s_key);
     {
         // per digit, in four parts: the asset's count (all super-tile rows)
         // and the count before this tile (earlier super-tiles, then the
-        // earlier tiles of its own super-tile); wcnt[0] is free until the
-        // rounds below
+        // earlier tiles of its own super-tile)
         const int d = tid & 255, part = tid >> 8;
         const int64_t S = T.lt / kSuper, nS = ceil_div(ceil_div(T.count, kSortTile), kSuper);
         uint32_t tot = 0, before = 0;
@@ -285,14 +300,14 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(Batch Bt, con
             if (x < S) before += v;
         }
         for (int64_t t = S * kSuper + part; t < T.lt; t += 4) before += hist[T.hbase + 256 * t + d];
-        wcnt[0][part][d] = tot;
-        wcnt[0][4 + part][d] = before;
+        scratch[part][d] = tot;
+        scratch[4 + part][d] = before;
     }
     __syncthreads();
     uint32_t tot = 0, before = 0;
     if (tid < 256) {
-        tot = (wcnt[0][0][tid] + wcnt[0][1][tid]) + (wcnt[0][2][tid] + wcnt[0][3][tid]);
-        before = (wcnt[0][4][tid] + wcnt[0][5][tid]) + (wcnt[0][6][tid] + wcnt[0][7][tid]);
+        tot = (scratch[0][tid] + scratch[1][tid]) + (scratch[2][tid] + scratch[3][tid]);
+        before = (scratch[4][tid] + scratch[5][tid]) + (scratch[6][tid] + scratch[7][tid]);
         // exclusive scan of the asset's digit counts (waves 0-3)
         uint32_t x = tot;
 #pragma unroll
@@ -310,19 +325,40 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(Batch Bt, con
         s_glob[tid] = (uint32_t)T.start + w + tot + before;
         s_run[tid] = 0;
     }
-    for (int x = tid; x < 2 * kSortWaves * 256; x += kSortBlock) (&wcnt[0][0][0])[x] = 0;
+    for (int x = tid; x < kSortRounds * kSortWaves * 256 / 2; x += kSortBlock)
+        reinterpret_cast<uint32_t*>(&wcnt[0][0][0])[x] = 0;
     __syncthreads();
-    uint32_t key[kSortRounds], val[kSortRounds];
+    // the tile's digit counts, and every wave's per-round digit counts
+    uint32_t rank[kSortRounds];
 #pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
-        const int64_t i = (int64_t)r * kSortBlock + tid;
-        const bool valid = i < nvalid;
-        key[r] = valid ? kin[T.start + base + i] : 0u;
-        val[r] = valid ? vin[T.start + base + i] : 0u;
-        if (valid) atomicAdd(&s_run[(key[r] >> shift) & 255u], 1u);
+        const bool valid = (int64_t)r * kSortBlock + tid < nvalid;
+        const uint32_t dig = (key[r] >> shift) & 255u;
+        if (valid) atomicAdd(&s_run[dig], 1u);
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (dig >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        rank[r] = (uint32_t)__popcll(peers & __lanemask_lt());
+        if (valid && rank[r] == 0) wcnt[r][wave][dig] = (uint16_t)__popcll(peers);
     }
     __syncthreads();
-    // exclusive scan of the tile's digit counts (waves 0-3, one digit per thread)
+    // thread (rr, d): exclusive scan of digit d's counts over the waves of
+    // round rr; waves 0-3 also scan the tile's digit counts
+    const int sd = tid & 255, rr = tid >> 8;
+    uint32_t ex[kSortWaves];
+    {
+        uint32_t acc = 0;
+#pragma unroll
+        for (int w = 0; w < kSortWaves; ++w) {
+            ex[w] = acc;
+            acc += wcnt[rr][w][sd];
+        }
+        s_part[rr][sd] = acc;
+    }
     uint32_t c = 0, x = 0;
     if (tid < 256) {
         c = s_run[tid];
@@ -336,42 +372,23 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(Batch Bt, con
     }
     __syncthreads();
     if (tid < 256) {
-        uint32_t before = 0;
-        for (int w = 0; w < wave; ++w) before += s_wsum[w];
-        s_loc[tid] = before + x - c;
-        s_run[tid] = before + x - c;
+        uint32_t b = 0;
+        for (int w = 0; w < wave; ++w) b += s_wsum[w];
+        s_loc[tid] = b + x - c;
+    }
+    __syncthreads();
+    {
+        uint32_t p = s_loc[sd];
+        for (int r = 0; r < rr; ++r) p += s_part[r][sd];
+#pragma unroll
+        for (int w = 0; w < kSortWaves; ++w) wcnt[rr][w][sd] = (uint16_t)(p + ex[w]);
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
-        uint32_t(*wc)[256] = wcnt[r & 1];
-        const bool valid = (int64_t)r * kSortBlock + tid < nvalid;
-        const uint32_t dig = (key[r] >> shift) & 255u;
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bool bit = (dig >> b) & 1u;
-            const uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
-        }
-        const uint32_t rank = (uint32_t)__popcll(peers & __lanemask_lt());
-        if (valid && rank == 0) wc[wave][dig] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (tid < 256) {
-            // counts -> first positions, waves in order; clear the other buffer
-            uint32_t p = s_run[tid];
-#pragma unroll
-            for (int w = 0; w < kSortWaves; ++w) {
-                const uint32_t t = wc[w][tid];
-                wc[w][tid] = p;
-                p += t;
-                wcnt[(r + 1) & 1][w][tid] = 0;
-            }
-            s_run[tid] = p;
-        }
-        __syncthreads();
-        if (valid) {
-            const uint32_t pos = wc[wave][dig] + rank;
+        if ((int64_t)r * kSortBlock + tid < nvalid) {
+            const uint32_t dig = (key[r] >> shift) & 255u;
+            const uint32_t pos = (uint32_t)wcnt[r][wave][dig] + rank[r];
             s_key[pos] = key[r];
             s_val[pos] = val[r];
         }
