@@ -609,10 +609,14 @@ def main():
     trav_s = stage_ms["traverse"] / 1e3
     achieved = ops / trav_s / 1e12
     khash = source_hash("traverse.hip", "lbvh.hip", "internal.h")
+    # the counters were taken on the headline workload with the default launch
+    # configuration: another workload or configuration reports none
+    headline = (args.config == 2 and not closest and args.trav_block == 0 and args.trav_stack == 0
+                and args.trav_mode == -1)
     roof = {"kernel": "traverse_batch_kernel (" + ("closest-point query" if closest else "traversal") + " + encode)",
             "bound": "alu",
             "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-            "frac": achieved / VALU_PEAK_TOPS, "traffic": measured_traffic(khash),
+            "frac": achieved / VALU_PEAK_TOPS, "traffic": measured_traffic(khash) if headline else None,
             "ops_per_launch": ops, "box_tests_per_ray": n_box / rays, "tri_tests_per_ray": n_tri / rays,
             # lanes of a wave that advance a ray in an average trip of its
             # traversal loop (one trip: an internal node, two box tests, or a leaf)

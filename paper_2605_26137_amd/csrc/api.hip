@@ -236,7 +236,7 @@ int32_t make_plan(const Sizes* z, int n, uint32_t flags, Plan* P) {
     L.level = take((size_t)L.t_tex);
     L.rays = take(16 * (size_t)L.t_tex);
     L.hits = L.save ? take(16 * (size_t)L.t_tex) : off;
-    L.bounds_part = take(24 * (size_t)L.t_stile);
+    L.bounds_part = take(24 * (size_t)kBoundsSplit * (size_t)L.t_stile);
     L.bounds = take(24 * (size_t)n);
     L.keys0 = take(4 * (size_t)L.t_hf);
     L.vals0 = take(4 * (size_t)L.t_hf);

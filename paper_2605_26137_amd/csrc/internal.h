@@ -142,6 +142,7 @@ enum GridId : int {
 };
 
 constexpr int kSortTile = 4096;  // keys per radix-sort block and pass
+constexpr int kBoundsSplit = 4;  // centroid-bounds workgroups per sort tile (a partial each)
 constexpr int kSortPasses = 4;   // 8-bit digits of keys up to 32 bits
 constexpr int kSuper = 32;       // sort tiles per super-tile (digit counts summed per super-tile)
 // Super-tile rows of a sort over `tiles` tiles of `n` assets (asset a's rows

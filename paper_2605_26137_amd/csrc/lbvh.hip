@@ -85,17 +85,21 @@ __device__ void block_minmax6(float v[6], float* out) {
 }
 
 __global__ __launch_bounds__(kBlock) void bounds_part_kernel(Batch Bt, float* __restrict__ part) {
+    // kBoundsSplit workgroups per sort tile, each over its 1/kBoundsSplit of it
     int64_t lt;
-    const AssetDev& As = Bt.A[block_asset(Bt, kGSort, blockIdx.x, &lt)];
+    const int sub = (int)(blockIdx.x % kBoundsSplit);
+    const AssetDev& As = Bt.A[block_asset(Bt, kGSort, blockIdx.x / kBoundsSplit, &lt)];
     const float* __restrict__ V = As.hi_V;
     const int32_t* __restrict__ F = As.hi_F;
     float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
     bool anybad = false, nonfin = false;
-    const int64_t end = min((int64_t)As.nhf, (lt + 1) * kSortTile);
+    constexpr int64_t kPart = kSortTile / kBoundsSplit;
+    const int64_t first = lt * kSortTile + sub * kPart;
+    const int64_t end = min((int64_t)As.nhf, first + kPart);
     // kU triangles per thread and trip, their index and vertex loads issued
     // together (one gather latency per trip instead of per triangle)
     constexpr int kU = 4;
-    for (int64_t g0 = lt * kSortTile + threadIdx.x; g0 < end; g0 += kU * kBlock) {
+    for (int64_t g0 = first + threadIdx.x; g0 < end; g0 += kU * kBlock) {
         int3 t[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
@@ -120,14 +124,14 @@ __global__ __launch_bounds__(kBlock) void bounds_part_kernel(Batch Bt, float* __
     }
     if (anybad) set_status(Bt, kStHiIndex);
     if (nonfin) set_status(Bt, kStNonFinite);
-    block_minmax6(v, part + 6 * (As.stile + lt));
+    block_minmax6(v, part + 6 * (kBoundsSplit * (As.stile + lt) + sub));
 }
 
 __global__ __launch_bounds__(kBlock) void bounds_final_kernel(Batch Bt, const float* __restrict__ part,
                                                               float* __restrict__ bounds) {
     const AssetDev& As = Bt.A[blockIdx.x];
-    const int64_t nparts = ceil_div(As.nhf, kSortTile);
-    const float* p = part + 6 * As.stile;
+    const int64_t nparts = kBoundsSplit * ceil_div(As.nhf, kSortTile);
+    const float* p = part + 6 * kBoundsSplit * As.stile;
     float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
     for (int64_t i = threadIdx.x; i < nparts; i += kBlock) {
         for (int k = 0; k < 3; ++k) v[k] = fminf(v[k], p[6 * i + k]);
@@ -843,7 +847,8 @@ hipError_t launch_bvh_build(const BatchHost& H, hipStream_t s) {
     int32_t* frontier = (int32_t*)(ws + L.frontier);
     int4* tlist = (int4*)(ws + L.treelets);
 
-    hipLaunchKernelGGL(bounds_part_kernel, dim3((unsigned)H.blocks(kGSort)), dim3(kBlock), 0, s, H.dev, part);
+    hipLaunchKernelGGL(bounds_part_kernel, dim3((unsigned)(H.blocks(kGSort) * kBoundsSplit)), dim3(kBlock), 0, s,
+                       H.dev, part);
     hipLaunchKernelGGL(bounds_final_kernel, dim3((unsigned)L.n), dim3(kBlock), 0, s, H.dev,
                        (const float*)part, bounds);
     hipLaunchKernelGGL(morton_kernel, dim3((unsigned)H.blocks(kGHiF)), dim3(kBlock), 0, s, H.dev,
