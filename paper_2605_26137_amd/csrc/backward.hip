@@ -366,14 +366,28 @@ __global__ __launch_bounds__(256) void bwd_hiN_kernel(Batch B, const uint32_t* _
         if (!grad_hi_N) continue;
         const uint32_t nhv = (uint32_t)B.A[it.a].nhv;
         const int64_t lo = 3 * it.begin, hi = 3 * it.end;
+        // the three 64-pair groups' loads first (keys, items, then each
+        // item's hit and ray gradient), so their latencies overlap; the
+        // scans below are unchanged
+        uint32_t keyv[3];
+        float3 gv[3];
+        bool contv[3];
+#pragma unroll
+        for (int k3 = 0; k3 < 3; ++k3) {
+            const int64_t i0 = 3 * it.r + 64 * k3;
+            const int64_t i = i0 + lane;
+            const bool in = i < hi;  // false for every lane past the batch's pairs
+            keyv[k3] = in ? keys[i] : 0xFFFFFFFFu;  // past the end: a run of its own
+            gv[k3] = in ? hiN_term(vals, hits, rg, i) : f3(0.f, 0.f, 0.f);
+            contv[k3] = i0 < hi && i0 > lo && keys[i0 - 1] == keys[i0];
+        }
         for (int k3 = 0; k3 < 3; ++k3) {
             const int64_t i0 = 3 * it.r + 64 * k3;  // the wave's first pair
             if (i0 >= hi) break;
             const int64_t i = i0 + lane;
             const bool in = i < hi;
-            const uint32_t key = in ? keys[i] : 0xFFFFFFFFu;  // past the end: a run of its own
-            float3 g = f3(0.f, 0.f, 0.f);
-            if (in && key < nhv) g = hiN_term(vals, hits, rg, i);
+            const uint32_t key = keyv[k3];
+            float3 g = in && key < nhv ? gv[k3] : f3(0.f, 0.f, 0.f);
             const uint32_t prev = __shfl_up(key, 1, 64);
             const uint32_t next = __shfl_down(key, 1, 64);
             bool head = lane == 0 || prev != key;
@@ -381,7 +395,7 @@ __global__ __launch_bounds__(256) void bwd_hiN_kernel(Batch B, const uint32_t* _
             // before i0 has the same key
             const uint64_t heads = __ballot(lane > 0 && prev != key);
             const int first_change = heads ? __ffsll((long long)heads) - 1 : 64;
-            const bool cont_in = i0 > lo && keys[i0 - 1] == __shfl(key, 0, 64);
+            const bool cont_in = contv[k3];
             // segmented inclusive scan: (v1, f1) then (v2, f2) -> (f2 ? v2 : v1 + v2, f1 | f2)
 #pragma unroll
             for (int o = 1; o < 64; o <<= 1) {
