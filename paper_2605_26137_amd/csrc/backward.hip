@@ -484,8 +484,17 @@ hipError_t launch_backward(const BatchHost& H, bool any_lo, bool any_hi, hipStre
     // with a second stream, the low-poly chain runs beside the sort
     const bool beside = side != nullptr && any_lo && L.t_lv > 0 && any_hi && L.t_hv > 0;
     hipStream_t ls = s;
+    bool sorted = false, in1 = false;
     if (beside) {
-        if ((e = hipEventRecord(fork, s)) != hipSuccess) return e;
+        // the sort is queued first and the fork recorded after its first
+        // histogram: that short latency-bound launch runs alone, the
+        // low-poly chain beside the scatters
+        if (L.t_tex > 0) {
+            if ((e = launch_sort(H, kSortBwd, L.max_hv_bits, &in1, s, fork)) != hipSuccess) return e;
+            sorted = true;
+        } else if ((e = hipEventRecord(fork, s)) != hipSuccess) {
+            return e;
+        }
         if ((e = hipStreamWaitEvent(side, fork, 0)) != hipSuccess) return e;
         ls = side;
         // the zeroing of dL/dhi_N goes to the second stream too; the segment
@@ -522,8 +531,7 @@ hipError_t launch_backward(const BatchHost& H, bool any_lo, bool any_hi, hipStre
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         if (L.t_tex > 0) {
-            bool in1 = false;
-            if ((e = launch_sort(H, kSortBwd, L.max_hv_bits, &in1, s)) != hipSuccess) return e;
+            if (!sorted && (e = launch_sort(H, kSortBwd, L.max_hv_bits, &in1, s)) != hipSuccess) return e;
             if (beside && (e = hipStreamWaitEvent(s, join, 0)) != hipSuccess) return e;
             hipLaunchKernelGGL(bwd_hiN_kernel, dim3(ray_grid), dim3(256), 0, s, H.dev,
                                (const uint32_t*)(ws + (in1 ? L.bwd_k1 : L.bwd_k0)),

@@ -288,7 +288,10 @@ hipError_t launch_treelet_space(const BatchHost& H, hipStream_t s);
 // backward pairs (bwd_k0/bwd_v0 <-> bwd_k1/bwd_v1), three per ray.
 // *result_in_1 tells which buffer holds the result (the same for all assets).
 enum SortWhich : int { kSortBvh = 0, kSortBwd = 1 };
-hipError_t launch_sort(const BatchHost& H, int which, int bits, bool* result_in_1, hipStream_t s);
+// after_first: if not null, recorded on s once the first pass's histogram is
+// queued (or at once when there is nothing to sort).
+hipError_t launch_sort(const BatchHost& H, int which, int bits, bool* result_in_1, hipStream_t s,
+                       hipEvent_t after_first = nullptr);
 
 hipError_t launch_lo_prep(const BatchHost& H, hipStream_t s);
 hipError_t launch_raster(const BatchHost& H, hipStream_t s);

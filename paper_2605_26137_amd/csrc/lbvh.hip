@@ -788,12 +788,14 @@ inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b
 
 }  // namespace
 
-hipError_t launch_sort(const BatchHost& H, int which, int bits, bool* result_in_1, hipStream_t s) {
+hipError_t launch_sort(const BatchHost& H, int which, int bits, bool* result_in_1, hipStream_t s,
+                       hipEvent_t after_first) {
     const Layout& L = H.L;
     const bool bwd = which == kSortBwd;
     const int64_t blocks = H.blocks(bwd ? kGBwdSort : kGSort);
     *result_in_1 = false;
-    if (blocks == 0) return hipSuccess;
+    const int passes = (bits + 7) / 8;
+    if (blocks == 0 || passes == 0) return after_first ? hipEventRecord(after_first, s) : hipSuccess;
     uint32_t* kin = (uint32_t*)(H.ws + (bwd ? L.bwd_k0 : L.keys0));
     uint32_t* vin = (uint32_t*)(H.ws + (bwd ? L.bwd_v0 : L.vals0));
     uint32_t* kout = (uint32_t*)(H.ws + (bwd ? L.bwd_k1 : L.keys1));
@@ -801,7 +803,6 @@ hipError_t launch_sort(const BatchHost& H, int which, int bits, bool* result_in_
     uint32_t* hist = (uint32_t*)(H.ws + (bwd ? L.bwd_hist : L.hist));
     uint32_t* sup = (uint32_t*)(H.ws + (bwd ? L.bwd_sup : L.sup));
     const int64_t sup_pass = sort_super_rows(bwd ? L.t_btile : L.t_stile, L.n) * 256;
-    const int passes = (bits + 7) / 8;
     if (passes > kSortPasses) return hipErrorInvalidValue;
     hipError_t e = fill_u32(sup, 0, sup_pass * passes, s);
     if (e != hipSuccess) return e;
@@ -811,12 +812,14 @@ hipError_t launch_sort(const BatchHost& H, int which, int bits, bool* result_in_
         if (bwd) {
             hipLaunchKernelGGL(radix_hist_kernel<true>, dim3((unsigned)blocks), dim3(kSortBlock), 0, s, H.dev,
                                (const uint32_t*)kin, shift, hist, sp);
+            if (p == 0 && after_first && (e = hipEventRecord(after_first, s)) != hipSuccess) return e;
             hipLaunchKernelGGL(radix_scatter_kernel<true>, dim3((unsigned)blocks), dim3(kSortBlock), 0, s, H.dev,
                                (const uint32_t*)kin, (const uint32_t*)vin, kout, vout, shift,
                                (const uint32_t*)hist, (const uint32_t*)sp);
         } else {
             hipLaunchKernelGGL(radix_hist_kernel<false>, dim3((unsigned)blocks), dim3(kSortBlock), 0, s, H.dev,
                                (const uint32_t*)kin, shift, hist, sp);
+            if (p == 0 && after_first && (e = hipEventRecord(after_first, s)) != hipSuccess) return e;
             hipLaunchKernelGGL(radix_scatter_kernel<false>, dim3((unsigned)blocks), dim3(kSortBlock), 0, s, H.dev,
                                (const uint32_t*)kin, (const uint32_t*)vin, kout, vout, shift,
                                (const uint32_t*)hist, (const uint32_t*)sp);
