@@ -177,3 +177,41 @@ def test_differentiation_workload_full_size(B, oracle_lib):
     lo_ex, hi_ex = _excluded(a, ob, r.hit.cpu().numpy())
     _compare_grads("lo_V", glo, olo, np.repeat(lo_ex[:, None], 3, 1))
     _compare_grads("hi_N", ghi, ohi, np.repeat(hi_ex[:, None], 3, 1))
+
+
+def _large_asset(uv_zero, seed=9):
+    # 81,920 high-poly faces: enough for the backward to run its low-poly
+    # chain on the second stream, forked after the sort's first histogram
+    lV, lF = M.icosphere(2)
+    hV, hF = M.icosphere(6)
+    U = M.unit_directions(hV)
+    hiV = M.displace(U, M.noise_radius(U, seed, 4, 0.03))
+    hiF = hF.astype(np.int32)
+    res = 256
+    uv = M.face_grid_atlas(lF.shape[0], res)
+    if uv_zero:
+        uv = np.zeros_like(uv)  # every chart collapsed to a point: no texel covered
+    return Asset("noise_L6_L2_256" + ("_nouv" if uv_zero else ""), hiV, hiF, M.vertex_normals(hiV, hiF),
+                 lV.astype(np.float32), lF.astype(np.int32), uv, res=res, max_dist=0.12)
+
+
+def test_backward_on_two_streams_is_repeatable(B):
+    a = _large_asset(False)
+    assert a.hi_F.shape[0] >= 65536
+    rng = np.random.default_rng(12)
+    gm = rng.normal(size=(a.res, a.res, 3))
+    say(f"[gpu] {a.name}: backward twice")
+    r, _, _, glo1, ghi1 = _run(B, a, gm)
+    assert r.ray_count() > 0 and np.abs(ghi1).sum() > 0 and np.abs(glo1).sum() > 0
+    _, _, _, glo2, ghi2 = _run(B, a, gm)
+    assert np.array_equal(glo1.view(np.uint32), glo2.view(np.uint32))
+    assert np.array_equal(ghi1.view(np.uint32), ghi2.view(np.uint32))
+
+
+def test_backward_with_no_covered_texel_on_two_streams(B):
+    a = _large_asset(True)
+    gm = np.ones((a.res, a.res, 3))
+    say(f"[gpu] {a.name}: backward with no rays")
+    r, _, _, glo, ghi = _run(B, a, gm)
+    assert r.ray_count() == 0
+    assert not glo.any() and not ghi.any()
