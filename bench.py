@@ -113,6 +113,19 @@ def measured_qem_traffic():
     return d.get("bytes_per_run")
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (as lscpu reports it), for the CPU baselines."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(asset, target_s, max_dist, kind):
     """The oracle as it stands (FP64 brute force over every triangle) on a
     seeded sample of the workload's covered texels (forward query: the
@@ -131,7 +144,7 @@ def cpu_baseline(asset, target_s, max_dist, kind):
         return time.perf_counter() - t0
 
     n, dt = sized_sample(run, 64, cov.size, target_s)
-    return {"value": n / dt, "unit": "rays/s", "cores": cores, "kind": "oracle",
+    return {"value": n / dt, "unit": "rays/s", "cores": cores, "cpu": cpu_model(), "kind": "oracle",
             "sample": f"{n} seeded covered texels of {cov.size}, FP64 brute-force {kind} query over all "
                       f"{asset.hi_F.shape[0]} triangles, {dt:.1f} s"}
 
@@ -210,7 +223,7 @@ def bench_visibility(args, B, log):
             return time.perf_counter() - t1
 
         n, dt = sized_sample(run, 256, rays, args.cpu_seconds)
-        out_json["cpu_baseline"] = {"value": n / dt, "unit": "rays/s", "cores": cores, "kind": "oracle",
+        out_json["cpu_baseline"] = {"value": n / dt, "unit": "rays/s", "cores": cores, "cpu": cpu_model(), "kind": "oracle",
                                     "sample": f"{n} seeded camera rays of {rays}, FP64 brute-force first hit over "
                                               f"all {F.shape[0]} triangles, {dt:.1f} s"}
     return out_json
@@ -222,7 +235,7 @@ MAP_WORKLOAD = ("backprojection precompute: noise + bump displaced icosphere L5 
 
 
 def bench_view_maps(args, B, log):
-    """The backprojection precompute (Sec. 6.5) at the paper's scale: one step
+    """The backprojection precompute (Sec. 7.4, TextureGen Postprocessing) at the paper's scale: one step
     is one whole call; value = covered texel-views per second."""
     import numpy as np
     import torch
@@ -294,7 +307,7 @@ def bench_view_maps(args, B, log):
             reps += 1
         dt = time.perf_counter() - t1
         out_json["cpu_baseline"] = {"value": reps * vm.texels.size * K / dt, "unit": "texel-views/s",
-                                    "cores": cores, "kind": "oracle",
+                                    "cores": cores, "cpu": cpu_model(), "kind": "oracle",
                                     "sample": f"the whole workload x {reps} ({vm.texels.size} covered texels x {K} "
                                               f"views, {K} depth buffers of {img}^2 by the oracle's FP64 BVH), "
                                               f"{dt:.1f} s"}
@@ -370,7 +383,7 @@ def bench_simplify(args, B, log):
             if dt >= 0.5 * args.cpu_seconds or o.rounds < n_rounds:
                 break
             n_rounds = max(n_rounds + 1, int(n_rounds * args.cpu_seconds / max(dt, 1e-3)))
-        out_json["cpu_baseline"] = {"value": done / dt, "unit": "faces/s", "cores": cores, "kind": "oracle",
+        out_json["cpu_baseline"] = {"value": done / dt, "unit": "faces/s", "cores": cores, "cpu": cpu_model(), "kind": "oracle",
                                     "sample": f"the oracle's first {o.rounds} rounds of the same workload "
                                               f"({F.shape[0]} -> {o.F.shape[0]} faces), {dt:.1f} s"}
     return out_json

@@ -82,6 +82,11 @@ extern "C" {
 #define BAKE_FLAG_TIMING 2u /* record per-stage HIP events (bake_stage_times) */
 #define BAKE_FLAG_COUNT 4u  /* instrumented traversal: count box and triangle tests
                                (bake_read_counter 1 and 2); slower, same results */
+#define BAKE_FLAG_ONE_STREAM 8u /* run every stage on the caller's stream: no second
+                                   stream for the low-poly work beside the BVH build
+                                   (forward) and the high-poly sort (backward); the
+                                   backward of a saved forward follows the forward's
+                                   choice.  Same results bit for bit.              */
 
 typedef struct bake_options {
     int32_t dilate_passes; /* chart dilation passes, 0..64 (default 2)                    */
@@ -198,7 +203,7 @@ int32_t bake_visibility(const float *V, const int32_t *F, int64_t n_v, int64_t n
                         uint32_t flags, uint8_t *visible_out, uint8_t *exterior_out, int32_t *first_hit_out,
                         void *workspace, size_t workspace_bytes, void *stream);
 
-/* ---- backprojection precompute (Sec. 6.5) -------------------------------- */
+/* ---- backprojection precompute (Sec. 7.4, TextureGen Postprocessing) ---- */
 /* The per-texel, per-view data that backprojecting K generated views onto a
  * UV atlas needs: the paper recovers each atlas texel's surface point,
  * projects it into every view, weights a view by the incidence between the

@@ -12,11 +12,14 @@ paper's bake (Sec. 6.4 "Normal Map Baking"):
 2. UV-space rasterisation of the low-poly (texel -> face, barycentrics);
 3. per texel a world position p and the interpolated smooth normal d;
 4. nearest line hit on the high-poly within +-max_dist (brute force over
-   every triangle, or the independent FP64 BVH pinned against it).  A triangle
-   is hit when the crossing's barycentric weights are all >= -EDGE_EPS; the
+   every triangle, or the independent FP64 BVH pinned against it), under one
+   of two hit rules.  "plain" is the plain definition: a triangle is hit when
+   the line meets it (all barycentric weights of the crossing >= 0) and the
+   winner minimises (|t|, index).  "robust" is the convention the GPU library
+   implements: a triangle is hit when the weights are all >= -EDGE_EPS and the
    winner minimises (floor(|t| / w), index) with w = max_dist * 2^-20, so a
    line through a shared edge or vertex, or two surfaces at the same distance,
-   resolve to the lower triangle index robustly;
+   resolve to the lower triangle index instead of to rounding noise;
 5. barycentric high-poly normal, projection into the tangent frame, neutral
    (0,0,1) for misses / unreliable / uncovered texels;
 6. chart dilation.
@@ -131,19 +134,53 @@ def rays(V, F, vn, face, bary):
     return P, D, ok.astype(bool)
 
 
-def query(hi_V, hi_F, P, D, max_dist, active=None, method="brute"):
-    """Nearest-|t| two-sided line hit: (id [-1 miss], t, beta[3])."""
+RULES = {"plain": 0, "robust": 1}
+
+
+def _rule(rule):
+    if rule not in RULES:
+        raise ValueError(f"rule must be one of {sorted(RULES)}, not {rule!r}")
+    return C.c_int(RULES[rule])
+
+
+N_EXCLUDE = 4  # triangle ids a query can skip per ray
+
+
+def _exclude(exclude, n):
+    """Per-ray triangle ids to skip: None, [n] or [n, k <= N_EXCLUDE] (-1: none)."""
+    if exclude is None:
+        return None
+    e = np.asarray(exclude, np.int64)
+    if e.ndim == 1:
+        e = e[:, None]
+    if e.ndim != 2 or e.shape[0] != n or e.shape[1] > N_EXCLUDE:
+        raise ValueError(f"exclude must be [n] or [n, <= {N_EXCLUDE}], got {e.shape}")
+    out = np.full((n, N_EXCLUDE), -1, np.int32)
+    out[:, :e.shape[1]] = e
+    return out
+
+
+def query(hi_V, hi_F, P, D, max_dist, active=None, method="brute", rule="robust", exclude=None):
+    """Nearest-|t| two-sided line hit: (id [-1 miss], t, beta[3]).
+
+    rule="plain": the plain definition (all weights >= 0, winner min (|t|,
+    index)); rule="robust": the edge tolerance and distance quantum of the GPU
+    library's convention (oracle.c states both).  exclude: triangle ids to skip
+    per ray ([n] or [n, k <= N_EXCLUDE], -1 none), for the comparator's
+    runner-up queries."""
     hi_V = _c(hi_V, np.float32); hi_F = _c(hi_F, np.int32)
     P = _c(P, np.float64); D = _c(D, np.float64)
     n = P.shape[0]
     ids = np.zeros(n, np.int32); t = np.zeros(n); beta = np.zeros((n, 3))
     act = None if active is None else _c(active, np.uint8)
+    ex = _exclude(exclude, n)
     if method == "brute":
         _call("orc_query_brute", _p(hi_V), _p(hi_F), C.c_int64(hi_F.shape[0]), C.c_int64(n), _p(P),
-              _p(D), _p(act), C.c_double(max_dist), _p(ids), _p(t), _p(beta))
+              _p(D), _p(act), C.c_double(max_dist), _rule(rule), _p(ex), _p(ids), _p(t), _p(beta))
     elif method == "bvh":
         _call("orc_query_bvh", _p(hi_V), C.c_int64(hi_V.shape[0]), _p(hi_F), C.c_int64(hi_F.shape[0]),
-              C.c_int64(n), _p(P), _p(D), _p(act), C.c_double(max_dist), _p(ids), _p(t), _p(beta))
+              C.c_int64(n), _p(P), _p(D), _p(act), C.c_double(max_dist), _rule(rule), _p(ex), _p(ids),
+              _p(t), _p(beta))
     else:
         raise ValueError(method)
     return ids, t, beta
@@ -170,6 +207,18 @@ def closest_check(hi_V, hi_F, P, g):
     dist = np.zeros(g.shape[0])
     _call("orc_closest_check", _p(hi_V), _p(hi_F), C.c_int64(g.shape[0]), _p(P), _p(g), _p(dist))
     return dist
+
+
+def closest_near(hi_V, hi_F, P, ids, dist, delta, eps_exact=1e-12):
+    """Per point: does a triangle other than ids[r] lie within delta of the
+    winning distance dist[r] without being an exact tie (|difference| >
+    eps_exact)?  Such points are near ties of the closest-point query."""
+    hi_V = _c(hi_V, np.float32); hi_F = _c(hi_F, np.int32)
+    P = _c(P, np.float64); ids = _c(ids, np.int32); dist = _c(dist, np.float64)
+    out = np.zeros(P.shape[0], np.uint8)
+    _call("orc_closest_near", _p(hi_V), _p(hi_F), C.c_int64(hi_F.shape[0]), C.c_int64(P.shape[0]), _p(P),
+          _p(ids), _p(dist), C.c_double(delta), C.c_double(eps_exact), _p(out))
+    return out.astype(bool)
 
 
 def frame_ok(lo_face, D, Tf):
@@ -234,9 +283,12 @@ class Bake:
     level: np.ndarray       # [res*res] dilation level (0 covered, k filled in pass k, 255 empty)
 
 
-def bake(asset, method="brute", texels=None, dilate_passes=2, kind="ray", max_dist=None) -> Bake:
+def bake(asset, method="brute", texels=None, dilate_passes=2, kind="ray", max_dist=None,
+         rule="robust") -> Bake:
     """Oracle bake of a whole asset (or of a subset of covered texels).
-    kind="ray": two-sided line query along the interpolated normal;
+    kind="ray": two-sided line query along the interpolated normal, under the
+    hit rule `rule` ("robust": the GPU library's convention; "plain": the plain
+    nearest hit);
     kind="closest": closest point of the high-poly (the paper's form), for
     which Bake.t holds the distance.  max_dist defaults to the asset's."""
     hi_V, hi_F, hi_N, lo_V, lo_F, lo_UV = asset.arrays()
@@ -255,7 +307,7 @@ def bake(asset, method="brute", texels=None, dilate_passes=2, kind="ray", max_di
     fok = frame_ok(lf, D, Tf)
     active = rel[lf] & mok & fok
     if kind == "ray":
-        ids, t, beta = query(hi_V, hi_F, P, D, md, active=active, method=method)
+        ids, t, beta = query(hi_V, hi_F, P, D, md, active=active, method=method, rule=rule)
     elif kind == "closest":
         ids, t, beta = closest(hi_V, hi_F, P, md, active=active, method=method)
     else:
@@ -301,16 +353,36 @@ def frozen_forward(asset, face, bary, g, hf):
     return out, tb
 
 
-def adjoint(asset, face, bary, g, hf, grad_out):
+def adjoint(asset, face, bary, g, hf, grad_out, magnitudes=False):
     """FP64 reverse mode of frozen_forward: given d(loss)/d(out) per ray,
-    returns (d loss / d lo_V [Vl,3], d loss / d hi_N [Vh,3])."""
+    returns (d loss / d lo_V [Vl,3], d loss / d hi_N [Vh,3]); with
+    magnitudes=True also, per entry, the summed magnitudes of the terms added
+    into it (the scale a floating-point evaluation of the sums is accurate to)."""
     loV, loF, UV, hiV, hiF, hiN, face, bary, g, hf = _frozen_args(asset, face, bary, g, hf)
     go = _c(grad_out, np.float64)
     glo = np.zeros((loV.shape[0], 3)); ghi = np.zeros((hiV.shape[0], 3))
+    alo = np.zeros((loV.shape[0], 3)) if magnitudes else None
+    ahi = np.zeros((hiV.shape[0], 3)) if magnitudes else None
     _call("orc_adjoint", _p(loV), C.c_int64(loV.shape[0]), _p(loF), C.c_int64(loF.shape[0]), _p(UV),
           C.c_int32(asset.res), _p(hiV), C.c_int64(hiV.shape[0]), _p(hiF), _p(hiN),
-          C.c_int64(face.shape[0]), _p(face), _p(bary), _p(g), _p(hf), _p(go), _p(glo), _p(ghi))
-    return glo, ghi
+          C.c_int64(face.shape[0]), _p(face), _p(bary), _p(g), _p(hf), _p(go), _p(glo), _p(ghi),
+          _p(alo), _p(ahi))
+    return (glo, ghi, alo, ahi) if magnitudes else (glo, ghi)
+
+
+def adjoint_at(asset, hit, grad_map, magnitudes=False):
+    """Adjoint of a whole bake's pre-dilation map at a given hit selection:
+    hit [res*res] (a bake's status per texel, >= 0 for hits: e.g. the GPU's
+    own), grad_map [res*res, 3].  The texel -> face assignment and barycentrics
+    are the rasteriser's (exact integers), h_f the face frames'."""
+    hit = np.asarray(hit).reshape(-1)
+    face, bary = raster(asset.lo_UV, asset.res)
+    tex = np.nonzero((face >= 0) & (hit >= 0))[0]
+    _, ok = lo_normals(asset.lo_V, asset.lo_F)
+    _, _, hf, _ = face_frames(asset.lo_V, asset.lo_F, asset.lo_UV, asset.res, ok)
+    gm = np.asarray(grad_map, np.float64).reshape(-1, 3)[tex]
+    f = face[tex]
+    return adjoint(asset, f, bary[tex], hit[tex], hf[f], gm, magnitudes)
 
 
 def bake_adjoint(asset, ob, grad_map):
@@ -352,14 +424,16 @@ def camera_rays(eyes, target, tan_half, res, which=None):
     return P, D
 
 
-def first_hit(V, F, P, D, t_far, method="brute"):
-    """First hit id (-1: none) and t of each half-line, t in (0, t_far]."""
+def first_hit(V, F, P, D, t_far, method="brute", rule="robust", exclude=None):
+    """First hit id (-1: none) and t of each half-line, t in (0, t_far], under
+    the hit rule `rule`; exclude as for ``query``."""
     V = _c(V, np.float32); F = _c(F, np.int32); P = _c(P, np.float64); D = _c(D, np.float64)
     n = P.shape[0]
     ids = np.zeros(n, np.int32); t = np.zeros(n)
+    ex = _exclude(exclude, n)
     fn = "orc_first_hit_brute" if method == "brute" else "orc_first_hit_bvh"
     _call(fn, _p(V), _p(F), C.c_int64(F.shape[0]), C.c_int64(n), _p(P), _p(D), C.c_double(t_far),
-          _p(ids), _p(t))
+          _rule(rule), _p(ex), _p(ids), _p(t))
     return ids, t
 
 
@@ -382,7 +456,7 @@ def flood_fill(V, F, seed):
 
 
 # ---------------------------------------------------------------------------
-# Backprojection precompute (Sec. 6.5)
+# Backprojection precompute (Sec. 7.4, TextureGen Postprocessing)
 # ---------------------------------------------------------------------------
 
 @dataclass

@@ -36,12 +36,20 @@
  *   tangent frame from the snapped UV deltas; per texel Gram-Schmidt against the
  *     interpolated normal; bitangent = h_f * (d x T');
  *   status: >= 0 hit id, -1 miss, -2 unreliable, -3 uncovered;
- *   hit rule: a triangle is hit when the line crosses its plane at barycentric
- *     weights all >= -EDGE_EPS (a relative edge tolerance, so a line grazing a
- *     shared edge or vertex hits every face there); among hits with |t| <=
- *     max_dist the winner minimises (floor(|t| / w), index) with the distance
- *     quantum w = max_dist * 2^-20, so hits whose distances agree to within
- *     the quantum resolve to the lower triangle index.
+ *   hit rules (the `rule` argument of the ray queries):
+ *     RULE_PLAIN, the plain definition of the nearest hit: a triangle is hit
+ *       when the three signed volumes of the line against its edges share a
+ *       sign (zeros allowed, not all zero); among hits with |t| <= max_dist the
+ *       winner minimises (|t|, index);
+ *     RULE_ROBUST, the convention the GPU library implements: a triangle is
+ *       hit when the line crosses its plane at barycentric weights all >=
+ *       -EDGE_EPS (a relative edge tolerance, so a line grazing a shared edge
+ *       or vertex hits every face there); the winner minimises
+ *       (floor(|t| / w), index) with the distance quantum w = max_dist * 2^-20,
+ *       so hits whose distances agree to within the quantum resolve to the
+ *       lower triangle index.  It differs from the plain rule only on lines
+ *       passing within the tolerance of an edge and on distances within a
+ *       quantum: the tests measure that difference on the workloads.
  */
 #include <math.h>
 #include <stdint.h>
@@ -52,9 +60,13 @@
 #define ORC_OK 0
 #define ORC_EINVAL -1
 
-/* relative edge tolerance (in barycentric units) and distance quantum */
+/* relative edge tolerance (in barycentric units) and distance quantum of the
+ * robust rule */
 #define EDGE_EPS (1.0 / 16384.0)
 #define T_QUANT_BITS 20
+
+#define RULE_PLAIN 0
+#define RULE_ROBUST 1
 
 #define ST_MISS -1
 #define ST_UNREL -2
@@ -249,21 +261,28 @@ static double svol(v3 p, v3 d, const float *V, int32_t ia, int32_t ib) {
 
 /* Line p + t d against triangle g.  With the three volumes s_k and their sum
  * S != 0, the plane crossing has barycentric weights beta = (s_bc, s_ca,
- * s_ab) / S; the triangle is hit iff every weight is >= -EDGE_EPS.
- * q = sum beta_k v_k, t = (q - p) . d.  Returns 1 on a hit. */
-static int tri_hit(v3 p, v3 d, const float *V, const int32_t *F, int64_t g, double *t, double beta[3]) {
+ * s_ab) / S.  RULE_PLAIN: hit iff the volumes share a sign (zeros allowed, not
+ * all zero), i.e. every weight >= 0; RULE_ROBUST: hit iff every weight is >=
+ * -EDGE_EPS.  q = sum beta_k v_k, t = (q - p) . d.  Returns 1 on a hit. */
+static int tri_hit(v3 p, v3 d, const float *V, const int32_t *F, int64_t g, int rule, double *t,
+                   double beta[3]) {
     int32_t a = F[3 * g], b = F[3 * g + 1], c = F[3 * g + 2];
     double s0 = svol(p, d, V, b, c), s1 = svol(p, d, V, c, a), s2 = svol(p, d, V, a, b);
     double S = s0 + s1 + s2;
-    if (S == 0) return 0;
+    if (rule == RULE_PLAIN) {
+        int same = (s0 >= 0 && s1 >= 0 && s2 >= 0) || (s0 <= 0 && s1 <= 0 && s2 <= 0);
+        if (!same || S == 0) return 0;
+    } else if (S == 0) {
+        return 0;
+    }
     beta[0] = s0 / S; beta[1] = s1 / S; beta[2] = s2 / S;
-    if (beta[0] < -EDGE_EPS || beta[1] < -EDGE_EPS || beta[2] < -EDGE_EPS) return 0;
+    if (rule != RULE_PLAIN && (beta[0] < -EDGE_EPS || beta[1] < -EDGE_EPS || beta[2] < -EDGE_EPS)) return 0;
     v3 q = add(add(scl(ld3f(V, a), beta[0]), scl(ld3f(V, b), beta[1])), scl(ld3f(V, c), beta[2]));
     *t = dot(sub(q, p), d);
     return 1;
 }
 
-/* Distance key: floor(|t| / w) with w = max_dist * 2^-T_QUANT_BITS. */
+/* Distance key of the robust rule: floor(|t| / w) with w = max_dist * 2^-T_QUANT_BITS. */
 static int64_t tkey(double t, double max_dist) {
     return (int64_t)floor(fabs(t) * ldexp(1.0, T_QUANT_BITS) / max_dist);
 }
@@ -274,10 +293,30 @@ static int better(double ta, int64_t ga, double tb, int64_t gb, double max_dist)
     return a < b || (a == b && ga < gb);
 }
 
+/* The order of the rule: (|t|, g) for RULE_PLAIN, (key, g) for RULE_ROBUST. */
+static int better_rule(int rule, double ta, int64_t ga, double tb, int64_t gb, double max_dist) {
+    if (rule == RULE_PLAIN) return fabs(ta) < fabs(tb) || (fabs(ta) == fabs(tb) && ga < gb);
+    return better(ta, ga, tb, gb, max_dist);
+}
+
+/* Is triangle g excluded for ray r?  exclude: [n][N_EXCLUDE] triangle ids
+ * (-1: none) that the query skips (the comparator's runner-up queries), or
+ * NULL. */
+#define N_EXCLUDE 4
+static int excluded(const int32_t *exclude, int64_t r, int64_t g) {
+    if (!exclude) return 0;
+    for (int k = 0; k < N_EXCLUDE; ++k)
+        if (exclude[N_EXCLUDE * r + k] == g) return 1;
+    return 0;
+}
+
+static int rule_ok(int rule) { return rule == RULE_PLAIN || rule == RULE_ROBUST; }
+
 /* Brute force over every triangle in ascending index order. */
 int orc_query_brute(const float *V, const int32_t *F, int64_t nf, int64_t n, const double *P,
-                    const double *D, const uint8_t *active, double max_dist,
-                    int32_t *id_out, double *t_out, double *beta_out) {
+                    const double *D, const uint8_t *active, double max_dist, int rule,
+                    const int32_t *exclude, int32_t *id_out, double *t_out, double *beta_out) {
+    if (!rule_ok(rule)) return ORC_EINVAL;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t r = 0; r < n; ++r) {
         int32_t best = -1;
@@ -286,9 +325,10 @@ int orc_query_brute(const float *V, const int32_t *F, int64_t nf, int64_t n, con
             v3 p = ld3d(P, r), d = ld3d(D, r);
             for (int64_t g = 0; g < nf; ++g) {
                 double t, beta[3];
-                if (!tri_hit(p, d, V, F, g, &t, beta)) continue;
+                if (excluded(exclude, r, g)) continue;
+                if (!tri_hit(p, d, V, F, g, rule, &t, beta)) continue;
                 if (fabs(t) > max_dist) continue;
-                if (best < 0 || better(t, g, bt, best, max_dist)) {
+                if (best < 0 || better_rule(rule, t, g, bt, best, max_dist)) {
                     best = (int32_t)g; bt = t; bb[0] = beta[0]; bb[1] = beta[1]; bb[2] = beta[2];
                 }
             }
@@ -402,7 +442,7 @@ static int box_interval(const bnode *nd, v3 p, v3 d, double *t0, double *t1) {
 }
 
 static int32_t bvh_query(const bvh *B, const float *V, const int32_t *F, v3 p, v3 d, double max_dist,
-                         double *t_out, double beta_out[3]) {
+                         int rule, const int32_t *exclude, int64_t r, double *t_out, double beta_out[3]) {
     int64_t stack[256];
     int sp = 0;
     stack[sp++] = 0;
@@ -413,18 +453,19 @@ static int32_t bvh_query(const bvh *B, const float *V, const int32_t *F, v3 p, v
         const bnode *nd = &B->nodes[stack[--sp]];
         double t0, t1;
         if (!box_interval(nd, p, d, &t0, &t1)) continue;
-        if (t0 > bound || t1 < -bound) continue; /* a node reaching the best key's bin is visited */
+        if (t0 > bound || t1 < -bound) continue; /* a node that may hold an equal or better hit is visited */
         if (nd->left < 0) {
             for (int64_t i = nd->first; i < nd->first + nd->count; ++i) {
                 int64_t g = B->perm[i];
                 double t, beta[3];
-                if (!tri_hit(p, d, V, F, g, &t, beta)) continue;
+                if (excluded(exclude, r, g)) continue;
+                if (!tri_hit(p, d, V, F, g, rule, &t, beta)) continue;
                 if (fabs(t) > max_dist) continue;
-                if (best < 0 || better(t, g, bt, best, max_dist)) {
+                if (best < 0 || better_rule(rule, t, g, bt, best, max_dist)) {
                     best = (int32_t)g; bt = t;
                     beta_out[0] = beta[0]; beta_out[1] = beta[1]; beta_out[2] = beta[2];
-                    /* upper end of the best key's bin, widened */
-                    bound = (double)(tkey(t, max_dist) + 1) * w * (1.0 + 1e-12);
+                    /* plain: |t| itself; robust: the upper end of the best key's bin; widened */
+                    bound = (rule == RULE_PLAIN ? fabs(t) : (double)(tkey(t, max_dist) + 1) * w) * (1.0 + 1e-12);
                 }
             }
         } else {
@@ -457,9 +498,10 @@ static void bvh_release(bvh *B) {
 }
 
 int orc_query_bvh(const float *V, int64_t nv, const int32_t *F, int64_t nf, int64_t n, const double *P,
-                  const double *D, const uint8_t *active, double max_dist,
-                  int32_t *id_out, double *t_out, double *beta_out) {
+                  const double *D, const uint8_t *active, double max_dist, int rule,
+                  const int32_t *exclude, int32_t *id_out, double *t_out, double *beta_out) {
     (void)nv;
+    if (!rule_ok(rule)) return ORC_EINVAL;
     bvh B;
     bvh_make(&B, V, F, nf);
     int err = 0;
@@ -468,7 +510,7 @@ int orc_query_bvh(const float *V, int64_t nv, const int32_t *F, int64_t nf, int6
         double t = 0, beta[3] = {0, 0, 0};
         int32_t id = -1;
         if ((!active || active[r]) && nf > 0) {
-            id = bvh_query(&B, V, F, ld3d(P, r), ld3d(D, r), max_dist, &t, beta);
+            id = bvh_query(&B, V, F, ld3d(P, r), ld3d(D, r), max_dist, rule, exclude, r, &t, beta);
             if (id == -100) { err = 1; id = -1; }
         }
         id_out[r] = id;
@@ -634,6 +676,49 @@ int orc_closest_bvh(const float *V, const int32_t *F, int64_t nf, int64_t n, con
     return err ? ORC_EINVAL : ORC_OK;
 }
 
+/* Near ties of the closest-point query: near_out[r] = 1 when some triangle
+ * other than the winner id[r] lies at a distance within delta of the winner's
+ * dist[r] but differs from it by more than eps_exact (triangles sharing the
+ * nearest vertex or edge are at the same distance: exact ties, which both
+ * sides resolve to the lower index).  An FP32 evaluation of the distances may
+ * order such a near tie either way.  On the FP64 BVH. */
+int orc_closest_near(const float *V, const int32_t *F, int64_t nf, int64_t n, const double *P,
+                     const int32_t *id, const double *dist, double delta, double eps_exact,
+                     uint8_t *near_out) {
+    bvh B;
+    bvh_make(&B, V, F, nf);
+    int err = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(| : err)
+    for (int64_t r = 0; r < n; ++r) {
+        near_out[r] = 0;
+        if (id[r] < 0 || nf == 0) continue;
+        v3 p = ld3d(P, r);
+        const double lim = dist[r] + delta;
+        int64_t stack[256];
+        int sp = 0;
+        stack[sp++] = 0;
+        while (sp > 0 && !near_out[r]) {
+            const bnode *nd = &B.nodes[stack[--sp]];
+            if (box_dist(nd, p) > lim * (1 + 1e-12)) continue;
+            if (nd->left < 0) {
+                for (int64_t i = nd->first; i < nd->first + nd->count; ++i) {
+                    int64_t g = B.perm[i];
+                    if (g == id[r]) continue;
+                    double w[3];
+                    double dd = tri_closest(p, V, F, g, w);
+                    if (fabs(dd - dist[r]) <= delta && fabs(dd - dist[r]) > eps_exact) { near_out[r] = 1; break; }
+                }
+                continue;
+            }
+            if (sp + 2 > 256) { err = 1; break; }
+            stack[sp++] = nd->right;
+            stack[sp++] = nd->left;
+        }
+    }
+    bvh_release(&B);
+    return err ? ORC_EINVAL : ORC_OK;
+}
+
 /* Comparator support: distance from P[r] to a given triangle g[r]. */
 int orc_closest_check(const float *V, const int32_t *F, int64_t n, const double *P, const int32_t *g,
                       double *dist_out) {
@@ -732,9 +817,12 @@ int orc_camera_rays_at(const float *eyes, const double *target, double tan_half,
     return ORC_OK;
 }
 
-/* First hit of each half-line by brute force over every triangle. */
+/* First hit of each half-line by brute force over every triangle, under
+ * `rule` (the order is then on t > 0 itself); `exclude` as for the line query. */
 int orc_first_hit_brute(const float *V, const int32_t *F, int64_t nf, int64_t n, const double *P,
-                        const double *D, double t_far, int32_t *id_out, double *t_out) {
+                        const double *D, double t_far, int rule, const int32_t *exclude,
+                        int32_t *id_out, double *t_out) {
+    if (!rule_ok(rule)) return ORC_EINVAL;
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t r = 0; r < n; ++r) {
         int32_t best = -1;
@@ -742,9 +830,10 @@ int orc_first_hit_brute(const float *V, const int32_t *F, int64_t nf, int64_t n,
         v3 p = ld3d(P, r), d = ld3d(D, r);
         for (int64_t g = 0; g < nf; ++g) {
             double t, beta[3];
-            if (!tri_hit(p, d, V, F, g, &t, beta)) continue;
+            if (excluded(exclude, r, g)) continue;
+            if (!tri_hit(p, d, V, F, g, rule, &t, beta)) continue;
             if (!(t > 0) || t > t_far) continue;
-            if (best < 0 || better(t, g, bt, best, t_far)) { best = (int32_t)g; bt = t; }
+            if (best < 0 || better_rule(rule, t, g, bt, best, t_far)) { best = (int32_t)g; bt = t; }
         }
         id_out[r] = best;
         if (t_out) t_out[r] = best >= 0 ? bt : 0;
@@ -753,9 +842,10 @@ int orc_first_hit_brute(const float *V, const int32_t *F, int64_t nf, int64_t n,
 }
 
 /* The same on the FP64 BVH: a node is skipped when its interval ends before
- * t = 0 or starts past the upper end of the best key's bin. */
+ * t = 0 or starts past the best hit (plain) or the upper end of the best
+ * key's bin (robust). */
 static int32_t bvh_first_hit(const bvh *B, const float *V, const int32_t *F, v3 p, v3 d, double t_far,
-                             double *t_out) {
+                             int rule, const int32_t *exclude, int64_t r, double *t_out) {
     int64_t stack[256];
     int sp = 0;
     stack[sp++] = 0;
@@ -771,11 +861,12 @@ static int32_t bvh_first_hit(const bvh *B, const float *V, const int32_t *F, v3 
             for (int64_t i = nd->first; i < nd->first + nd->count; ++i) {
                 int64_t g = B->perm[i];
                 double t, beta[3];
-                if (!tri_hit(p, d, V, F, g, &t, beta)) continue;
+                if (excluded(exclude, r, g)) continue;
+                if (!tri_hit(p, d, V, F, g, rule, &t, beta)) continue;
                 if (!(t > 0) || t > t_far) continue;
-                if (best < 0 || better(t, g, bt, best, t_far)) {
+                if (best < 0 || better_rule(rule, t, g, bt, best, t_far)) {
                     best = (int32_t)g; bt = t;
-                    bound = (double)(tkey(t, t_far) + 1) * w * (1.0 + 1e-12);
+                    bound = (rule == RULE_PLAIN ? t : (double)(tkey(t, t_far) + 1) * w) * (1.0 + 1e-12);
                 }
             }
         } else {
@@ -789,7 +880,8 @@ static int32_t bvh_first_hit(const bvh *B, const float *V, const int32_t *F, v3 
 }
 
 int orc_first_hit_bvh(const float *V, const int32_t *F, int64_t nf, int64_t n, const double *P, const double *D,
-                      double t_far, int32_t *id_out, double *t_out) {
+                      double t_far, int rule, const int32_t *exclude, int32_t *id_out, double *t_out) {
+    if (!rule_ok(rule)) return ORC_EINVAL;
     bvh B;
     bvh_make(&B, V, F, nf);
     int err = 0;
@@ -798,7 +890,7 @@ int orc_first_hit_bvh(const float *V, const int32_t *F, int64_t nf, int64_t n, c
         double t = 0;
         int32_t id = -1;
         if (nf > 0) {
-            id = bvh_first_hit(&B, V, F, ld3d(P, r), ld3d(D, r), t_far, &t);
+            id = bvh_first_hit(&B, V, F, ld3d(P, r), ld3d(D, r), t_far, rule, exclude, r, &t);
             if (id == -100) { err = 1; id = -1; }
         }
         id_out[r] = id;
@@ -877,7 +969,7 @@ int orc_flood_fill(const float *V, int64_t nv, const int32_t *F, int64_t nf, con
 }
 
 /* ------------------------------------------------------------------------ */
-/* Backprojection precompute (Sec. 6.5, TextureGen post-processing): per     */
+/* Backprojection precompute (Sec. 7.4, TextureGen Postprocessing): per     */
 /* atlas texel and view, the image position, the incidence and the depth-    */
 /* buffer visibility                                                          */
 /* ------------------------------------------------------------------------ */
@@ -1178,17 +1270,33 @@ int orc_frozen_forward(const float *loV, int64_t nlv, const int32_t *loF, int64_
     return ORC_OK;
 }
 
+static v3 vabs(v3 a) { return mk(fabs(a.x), fabs(a.y), fabs(a.z)); }
+/* Componentwise bound on |a x b| from |a| and |b|. */
+static v3 cross_abs(v3 a, v3 b) {
+    return mk(a.y * b.z + a.z * b.y, a.z * b.x + a.x * b.z, a.x * b.y + a.y * b.x);
+}
+static void acc_abs(double *p, int64_t i, v3 a) {
+    if (p) st3d(p, i, add(ld3d(p, i), vabs(a)));
+}
+
+/* gloV_abs / ghiN_abs (optional, NULL to skip): per gradient entry, the sum of
+ * the magnitudes of the terms that the adjoint adds into it (through the
+ * vertex-normal chain, a componentwise bound of the same), the scale to which
+ * a floating-point evaluation of the sums is accurate. */
 int orc_adjoint(const float *loV, int64_t nlv, const int32_t *loF, int64_t nlf, const float *UV,
                 int32_t res, const float *hiV, int64_t nhv, const int32_t *hiF, const float *hiN, int64_t n,
                 const int32_t *face, const double *bary, const int32_t *g, const int8_t *hf,
-                const double *gout, double *gloV, double *ghiN) {
+                const double *gout, double *gloV, double *ghiN, double *gloV_abs, double *ghiN_abs) {
     double *s = (double *)malloc(sizeof(double) * (size_t)(3 * (nlv > 0 ? nlv : 1)));
     double *nrm = (double *)malloc(sizeof(double) * (size_t)(3 * (nlv > 0 ? nlv : 1)));
     double *nbar = (double *)calloc((size_t)(3 * (nlv > 0 ? nlv : 1)), sizeof(double));
+    double *nbar_abs = (double *)calloc((size_t)(3 * (nlv > 0 ? nlv : 1)), sizeof(double));
     lo_vertex_sums(loV, nlv, loF, nlf, s);
     for (int64_t v = 0; v < nlv; ++v) st3d(nrm, v, scl(ld3d(s, v), 1.0 / norm(ld3d(s, v))));
     for (int64_t i = 0; i < 3 * nlv; ++i) gloV[i] = 0;
     for (int64_t i = 0; i < 3 * nhv; ++i) ghiN[i] = 0;
+    if (gloV_abs) for (int64_t i = 0; i < 3 * nlv; ++i) gloV_abs[i] = 0;
+    if (ghiN_abs) for (int64_t i = 0; i < 3 * nhv; ++i) ghiN_abs[i] = 0;
     for (int64_t r = 0; r < n; ++r) {
         rstate S;
         ray_forward(loV, loF, nrm, UV, res, hiV, hiF, hiN, face[r], bary + 3 * r, g[r], hf[r], &S);
@@ -1206,7 +1314,10 @@ int orc_adjoint(const float *loV, int64_t nlv, const int32_t *loF, int64_t nlf, 
         /* n = h/|h| */
         v3 hb = scl(sub(nb, scl(S.n, dot(nb, S.n))), 1.0 / S.lh);
         double beta[3] = {1.0 - S.b1 - S.b2, S.b1, S.b2};
-        for (int k = 0; k < 3; ++k) st3d(ghiN, S.hv[k], add(ld3d(ghiN, S.hv[k]), scl(hb, beta[k])));
+        for (int k = 0; k < 3; ++k) {
+            st3d(ghiN, S.hv[k], add(ld3d(ghiN, S.hv[k]), scl(hb, beta[k])));
+            acc_abs(ghiN_abs, S.hv[k], scl(hb, beta[k]));
+        }
         double b1b = dot(hb, sub(S.N[1], S.N[0])), b2b = dot(hb, sub(S.N[2], S.N[0]));
         /* [-d | e1 | e2] (t, b1, b2) = p - A: w = M^-T (0, b1b, b2b) */
         v3 md = scl(S.d, -1.0);
@@ -1228,18 +1339,28 @@ int orc_adjoint(const float *loV, int64_t nlv, const int32_t *loF, int64_t nlf, 
             int32_t v = S.lv[k];
             st3d(gloV, v, add(ld3d(gloV, v), scl(pb, bk[k])));
             st3d(nbar, v, add(ld3d(nbar, v), scl(mb, bk[k])));
+            acc_abs(gloV_abs, v, scl(pb, bk[k]));
+            acc_abs(nbar_abs, v, scl(mb, bk[k]));
         }
         /* T_f = c1 (V1 - V0) + c2 (V2 - V0) */
         v3 e1b = scl(Tfb, S.c1), e2b = scl(Tfb, S.c2);
         st3d(gloV, S.lv[1], add(ld3d(gloV, S.lv[1]), e1b));
         st3d(gloV, S.lv[2], add(ld3d(gloV, S.lv[2]), e2b));
         st3d(gloV, S.lv[0], sub(ld3d(gloV, S.lv[0]), add(e1b, e2b)));
+        acc_abs(gloV_abs, S.lv[1], e1b);
+        acc_abs(gloV_abs, S.lv[2], e2b);
+        acc_abs(gloV_abs, S.lv[0], add(vabs(e1b), vabs(e2b)));
     }
     /* n_v = s_v/|s_v|, s_v = sum of face cross products */
     double *sb = (double *)calloc((size_t)(3 * (nlv > 0 ? nlv : 1)), sizeof(double));
+    double *sb_abs = (double *)calloc((size_t)(3 * (nlv > 0 ? nlv : 1)), sizeof(double));
     for (int64_t v = 0; v < nlv; ++v) {
         v3 nv = ld3d(nrm, v), nbv = ld3d(nbar, v);
-        st3d(sb, v, scl(sub(nbv, scl(nv, dot(nbv, nv))), 1.0 / norm(ld3d(s, v))));
+        double ls = norm(ld3d(s, v));
+        st3d(sb, v, scl(sub(nbv, scl(nv, dot(nbv, nv))), 1.0 / ls));
+        /* |(I - n n^T) x| <= |x| + |n| (|n| . |x|) componentwise */
+        v3 xa = ld3d(nbar_abs, v), na = vabs(nv);
+        st3d(sb_abs, v, scl(add(xa, scl(na, dot(na, xa))), 1.0 / ls));
     }
     for (int64_t f = 0; f < nlf; ++f) {
         int32_t a = loF[3 * f], b = loF[3 * f + 1], c = loF[3 * f + 2];
@@ -1250,7 +1371,16 @@ int orc_adjoint(const float *loV, int64_t nlv, const int32_t *loF, int64_t nlf, 
         st3d(gloV, b, add(ld3d(gloV, b), e1b));
         st3d(gloV, c, add(ld3d(gloV, c), e2b));
         st3d(gloV, a, sub(ld3d(gloV, a), add(e1b, e2b)));
+        if (gloV_abs) {
+            v3 cba = add(add(ld3d(sb_abs, a), ld3d(sb_abs, b)), ld3d(sb_abs, c));
+            v3 e1ba = cross_abs(vabs(e2), cba), e2ba = cross_abs(cba, vabs(e1));
+            acc_abs(gloV_abs, b, e1ba);
+            acc_abs(gloV_abs, c, e2ba);
+            acc_abs(gloV_abs, a, add(e1ba, e2ba));
+        }
     }
+    free(sb_abs);
+    free(nbar_abs);
     free(sb);
     free(nbar);
     free(nrm);

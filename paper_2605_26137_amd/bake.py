@@ -42,6 +42,7 @@ QUERIES = {"ray": BAKE_QUERY_RAY, "closest": BAKE_QUERY_CLOSEST}
 BAKE_FLAG_SAVE = 1
 BAKE_FLAG_TIMING = 2
 BAKE_FLAG_COUNT = 4
+BAKE_FLAG_ONE_STREAM = 8
 
 (VIEW_RAYS, VIEW_HITS, VIEW_FACEMAP, VIEW_LO_N, VIEW_SORTED, VIEW_NODES, VIEW_LEAVES, VIEW_FACE_T,
  VIEW_SORTED_IDX) = range(9)
@@ -161,12 +162,12 @@ def _check(rc: int):
 
 
 def make_options(dilate_passes=2, save=False, timing=False, rgb8_ptr=0, trav_block=0,
-                 trav_stack=0, trav_mode=-1, count=False, query="ray") -> BakeOptions:
+                 trav_stack=0, trav_mode=-1, count=False, query="ray", one_stream=False) -> BakeOptions:
     o = BakeOptions()
     lib().bake_default_options(C.byref(o))
     o.dilate_passes = int(dilate_passes)
     o.flags = ((BAKE_FLAG_SAVE if save else 0) | (BAKE_FLAG_TIMING if timing else 0)
-               | (BAKE_FLAG_COUNT if count else 0))
+               | (BAKE_FLAG_COUNT if count else 0) | (BAKE_FLAG_ONE_STREAM if one_stream else 0))
     o.out_rgb8 = rgb8_ptr or None
     o.trav_block = int(trav_block)
     o.trav_stack = int(trav_stack)
@@ -256,14 +257,16 @@ def bake_normals(hi_V, hi_F, hi_N, lo_V, lo_F, lo_UV, res: int, max_dist: float,
                  dilate_passes: int = 2, rgb8: bool = False, save: bool = False,
                  timing: bool = False, trav_block: int = 0, trav_stack: int = 0,
                  trav_mode: int = -1, count: bool = False, query: str = "ray",
-                 workspace: Optional[torch.Tensor] = None,
+                 one_stream: bool = False, workspace: Optional[torch.Tensor] = None,
                  out_map: Optional[torch.Tensor] = None, out_hit: Optional[torch.Tensor] = None,
                  stream=None) -> BakeResult:
     """Bake a tangent-space normal map of the high-poly onto the low-poly's UV
     atlas.  Inputs are GPU tensors: hi_V [Vh,3] f32, hi_F [Fh,3] i32, hi_N [Vh,3]
     f32, lo_V [Vl,3] f32, lo_F [Fl,3] i32, lo_UV [Fl,3,2] f32.  query: "ray"
     (two-sided ray along the interpolated normal) or "closest" (closest point
-    of the high-poly within max_dist, forward only)."""
+    of the high-poly within max_dist, forward only).  one_stream: run every
+    stage on the caller's stream (no second stream beside the BVH build; the
+    backward of a saved bake follows), with the same results bit for bit."""
     hi_V = _dev_tensor(hi_V, torch.float32, "hi_V", (3,))
     hi_F = _dev_tensor(hi_F, torch.int32, "hi_F", (3,))
     hi_N = _dev_tensor(hi_N, torch.float32, "hi_N", (3,))
@@ -278,7 +281,7 @@ def bake_normals(hi_V, hi_F, hi_N, lo_V, lo_F, lo_UV, res: int, max_dist: float,
     sizes = (hi_V.shape[0], hi_F.shape[0], lo_V.shape[0], lo_F.shape[0], int(res))
     rgb = torch.empty((res, res, 3), dtype=torch.uint8, device=dev) if rgb8 else None
     opts = make_options(dilate_passes, save, timing, rgb.data_ptr() if rgb is not None else 0,
-                        trav_block, trav_stack, trav_mode, count, query)
+                        trav_block, trav_stack, trav_mode, count, query, one_stream)
     nbytes = workspace_size(*sizes, opts)
     if workspace is None or workspace.numel() < nbytes:
         workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
@@ -623,7 +626,7 @@ def visibility(V, F, eyes, target, tan_half: float, res: int, t_far: float, *, f
 
 
 # ---------------------------------------------------------------------------
-# Backprojection precompute (Sec. 6.5)
+# Backprojection precompute (Sec. 7.4, TextureGen Postprocessing)
 # ---------------------------------------------------------------------------
 
 MAP_STAGES = ("gbuffer", "bvh_build", "depth_rays", "maps", "unused", "total")

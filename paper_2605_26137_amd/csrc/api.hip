@@ -65,7 +65,7 @@ int32_t parse_opts(const bake_options* o, Opts* out) {
     if (o->dilate_passes < 0 || o->dilate_passes > 64)
         return fail(BAKE_E_INVALID_ARG, "dilate_passes %d outside [0, 64]", o->dilate_passes);
     out->dilate = o->dilate_passes;
-    if (o->flags & ~(uint32_t)(BAKE_FLAG_SAVE | BAKE_FLAG_TIMING | BAKE_FLAG_COUNT))
+    if (o->flags & ~(uint32_t)(BAKE_FLAG_SAVE | BAKE_FLAG_TIMING | BAKE_FLAG_COUNT | BAKE_FLAG_ONE_STREAM))
         return fail(BAKE_E_INVALID_ARG, "unknown flag bits 0x%x", o->flags);
     out->flags = o->flags;
     out->rgb8 = o->out_rgb8;
@@ -341,6 +341,7 @@ struct Saved {
     const void* ws;
     uint64_t sig;
     uint32_t nonce;
+    bool one_stream;  // the forward ran on the caller's stream only; its backward does too
 };
 constexpr int kSavedSlots = 64;
 std::mutex g_saved_mu;
@@ -349,16 +350,17 @@ int g_saved_next = 0;
 uint32_t g_nonce = 0;
 
 // Registers a saved forward and returns the nonce it leaves in the workspace.
-uint32_t remember_saved(const void* ws, uint64_t sig) {
+uint32_t remember_saved(const void* ws, uint64_t sig, bool one_stream) {
     std::lock_guard<std::mutex> lk(g_saved_mu);
     if (++g_nonce == 0) g_nonce = 1;  // 0 marks a forward in flight
     for (int i = 0; i < kSavedSlots; ++i)
         if (g_saved[i].ws == ws) {
             g_saved[i].sig = sig;
             g_saved[i].nonce = g_nonce;
+            g_saved[i].one_stream = one_stream;
             return g_nonce;
         }
-    g_saved[g_saved_next] = Saved{ws, sig, g_nonce};
+    g_saved[g_saved_next] = Saved{ws, sig, g_nonce, one_stream};
     g_saved_next = (g_saved_next + 1) % kSavedSlots;
     return g_nonce;
 }
@@ -369,11 +371,12 @@ void forget_saved(const void* ws) {
         if (g_saved[i].ws == ws) g_saved[i].ws = nullptr;
 }
 
-bool was_saved(const void* ws, uint64_t sig, uint32_t* nonce) {
+bool was_saved(const void* ws, uint64_t sig, uint32_t* nonce, bool* one_stream) {
     std::lock_guard<std::mutex> lk(g_saved_mu);
     for (int i = 0; i < kSavedSlots; ++i)
         if (g_saved[i].ws == ws && ws != nullptr) {
             *nonce = g_saved[i].nonce;
+            *one_stream = g_saved[i].one_stream;
             return g_saved[i].sig == sig;
         }
     return false;
@@ -495,8 +498,9 @@ int32_t run_forward(Plan& P, const Opts& o, void* workspace, hipStream_t s) {
     HIP_OR_FAIL(fill_u32((uint32_t*)ws, 0, (int64_t)(L.table / 4), s));
     // small bakes run on one stream: there the fork and join cost more than
     // the overlap saves
+    const bool one_stream = (o.flags & BAKE_FLAG_ONE_STREAM) != 0;
     std::unique_lock<std::mutex> side_lock(g_side_mu);
-    Side* side = L.t_hf >= kSideMinFaces ? side_stream(s) : nullptr;
+    Side* side = L.t_hf >= kSideMinFaces && !one_stream ? side_stream(s) : nullptr;
     if (side) {
         HIP_OR_FAIL(hipEventRecord(side->fork, s));
         HIP_OR_FAIL(hipStreamWaitEvent(side->s, side->fork, 0));
@@ -528,7 +532,7 @@ int32_t run_forward(Plan& P, const Opts& o, void* workspace, hipStream_t s) {
     if (any_rgb8) HIP_OR_FAIL(launch_rgb8(H, s));
     if (o.flags & BAKE_FLAG_SAVE) {
         // seal the saved state: the backward checks this nonce on the device
-        const uint32_t nonce = remember_saved(workspace, P.sig);
+        const uint32_t nonce = remember_saved(workspace, P.sig, one_stream);
         HIP_OR_FAIL(fill_u32(H.dev.gcnt + kGcSeal, nonce, 1, s));
     } else {
         forget_saved(workspace);
@@ -538,7 +542,7 @@ int32_t run_forward(Plan& P, const Opts& o, void* workspace, hipStream_t s) {
     return BAKE_OK;
 }
 
-int32_t run_backward(Plan& P, void* workspace, uint32_t nonce, hipStream_t s) {
+int32_t run_backward(Plan& P, void* workspace, uint32_t nonce, bool one_stream, hipStream_t s) {
     char* ws = (char*)workspace;
     BatchHost H = host_view(P, ws);
     H.dev.seal = nonce;
@@ -550,7 +554,7 @@ int32_t run_backward(Plan& P, void* workspace, uint32_t nonce, hipStream_t s) {
     if (!any_lo && !any_hi) return BAKE_OK;
     HIP_OR_FAIL(write_table(ws + P.L.grads, P.G.data(), sizeof(AssetGrad) * (size_t)P.L.n, s));
     std::lock_guard<std::mutex> side_lock(g_side_mu);
-    Side* side = P.L.t_hf >= kSideMinFaces ? side_stream(s) : nullptr;
+    Side* side = P.L.t_hf >= kSideMinFaces && !one_stream ? side_stream(s) : nullptr;
     if (side) {
         HIP_OR_FAIL(launch_backward(H, any_lo, any_hi, s, side->s, side->fork, side->join));
     } else {
@@ -633,7 +637,7 @@ int32_t plan_visibility(int64_t nv, int64_t nf, Plan* P, VisLayout* V) {
     return BAKE_OK;
 }
 
-// ---- backprojection precompute (Sec. 6.5) -----------------------------------
+// ---- backprojection precompute (Sec. 7.4, TextureGen Postprocessing) ----
 // A batch of one asset whose low-poly and high-poly are both the textured
 // mesh (its atlas rasterised as in the bake, its BVH for the depth rays),
 // then the views' depth buffers and the depth rays' spill columns.
@@ -806,10 +810,11 @@ int32_t bake_normals_batched_backward(const bake_asset* assets, int32_t n_assets
     }
     if ((rc = check_workspace(workspace, workspace_bytes, P.L))) return rc;
     uint32_t nonce = 0;
-    if (!was_saved(workspace, P.sig, &nonce))
+    bool one_stream = false;
+    if (!was_saved(workspace, P.sig, &nonce, &one_stream))
         return fail(BAKE_E_STATE, "no forward bake with BAKE_FLAG_SAVE and these sizes used this workspace");
     fill_pointers(assets, &P);
-    return run_backward(P, workspace, nonce, (hipStream_t)stream);
+    return run_backward(P, workspace, nonce, one_stream, (hipStream_t)stream);
 }
 
 int32_t bake_autotune(const bake_asset* assets, int32_t n_assets, const bake_options* base, int32_t reps,

@@ -313,8 +313,9 @@ struct VisRun {
     bool count;          // instrumented: box / triangle tests and wave trips into asset 0's counters
 };
 hipError_t launch_visibility_rays(const BatchHost& H, const VisRun& v, hipStream_t s);
-// Backprojection precompute (Sec. 6.5) for asset 0's covered texels (its ray
-// list and low-poly normals) against the depth buffers of the views.
+// Backprojection precompute (Sec. 7.4, TextureGen Postprocessing) for asset
+// 0's covered texels (its ray list and low-poly normals) against the depth
+// buffers of the views.
 struct MapRun {
     const float* eyes;  // device [n_views][3]
     float target[3];

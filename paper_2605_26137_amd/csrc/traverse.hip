@@ -817,7 +817,7 @@ __global__ __launch_bounds__(BLOCK) void visibility_kernel(VisArgs a) {
     }
 }
 
-// Backprojection precompute (Sec. 6.5): per covered texel of asset 0 (its
+// Backprojection precompute (Sec. 7.4, TextureGen Postprocessing): per covered texel of asset 0 (its
 // surface point p and smooth normal from the G-buffer) and per view: image
 // coordinates col = (q.r / (z tan_half) + 1) res / 2 - 1/2, row = (1 - q.u /
 // (z tan_half)) res / 2 - 1/2 with q = p - e, z = q.f (pixel centres at

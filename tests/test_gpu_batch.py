@@ -222,22 +222,92 @@ def test_backward_on_overwritten_workspace_writes_nothing(B):
     assert batch.status() == 0
 
 
+def _sample(oracle_lib, a, n, seed):
+    face, _ = oracle_lib.raster(a.lo_UV, a.res)
+    cov = np.nonzero(face >= 0)[0]
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(cov, size=min(n, cov.size), replace=False))
+
+
+# a sample of n texels cannot measure a 0.1 % disagreement rate; instead the
+# number of (verified) ties in it is bounded: at a true rate of 0.1 %, more
+# than 3 ties in 500 texels has probability < 2e-3
+MAX_TIES_PER_500 = 3
+
+
 def test_batched_asset_sample_against_oracle(B, oracle_lib):
-    """Texels of generated batch assets against the oracle's brute force
-    (independent of the single-bake path)."""
-    from compare import compare
+    """500 seeded texels of each of three generated batch assets against the
+    oracle's brute force (independent of the single-bake path)."""
+    from compare import compare, compare_plain
     assets = make_batch_assets(3, seed=3, hi_range=(20_000, 80_000), lo_range=(500, 3_000),
                                res_choices=(256,), max_dist=0.1)
     batch = B.BakeBatch([_inputs(B, a) for a in assets], dilate_passes=0)
     batch.forward()
     torch.cuda.synchronize()
     for i, a in enumerate(assets):
-        face, _ = oracle_lib.raster(a.lo_UV, a.res)
-        cov = np.nonzero(face >= 0)[0]
-        rng = np.random.default_rng(100 + i)
-        sample = np.sort(rng.choice(cov, size=min(2000, cov.size), replace=False))
+        sample = _sample(oracle_lib, a, 500, 100 + i)
+        gm, gh = batch.maps[i].cpu().numpy(), batch.hits[i].cpu().numpy()
         ob = oracle_lib.bake(a, method="brute", texels=sample, dilate_passes=0)
-        rep = compare(oracle_lib, a, ob, batch.maps[i].cpu().numpy(), batch.hits[i].cpu().numpy(),
-                      check_dilation=False)
+        rep = compare(oracle_lib, a, ob, gm, gh, check_dilation=False, agree_min=None)
         say(f"[gpu] batch asset {i} sample (brute force):", rep)
         assert rep.ok(), str(rep)
+        assert rep.n_disagree <= MAX_TIES_PER_500
+        obp = oracle_lib.bake(a, method="brute", texels=sample, dilate_passes=0, rule="plain")
+        rp = compare_plain(oracle_lib, a, obp, gm, gh)
+        say(f"[gpu] batch asset {i} sample:", rp)
+        assert rp.ok(), str(rp)
+
+
+@pytest.mark.slow
+def test_batch_workload_against_oracle(B, oracle_lib):
+    """The 64-asset batch the benchmark times (24.7M high-poly triangles in
+    all, 53k-1.87M per asset, atlases 512-2048, holes from the decimation),
+    forward + backward in one batched call: 500 seeded covered texels of
+    every asset against the oracle's brute force (robust rule, plain-rule
+    ties), and the backward of four assets (the smallest, the largest and two
+    seeded picks) against the FP64 adjoint at the GPU's hit selection."""
+    from compare import compare, compare_plain
+    say("[gpu] batch workload: generating 64 assets")
+    assets = make_batch_assets(64, seed=0, workers=8)
+    batch = B.BakeBatch([_inputs(B, a) for a in assets], save=True, dilate_passes=0)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(31)
+    for g in batch.grad_maps:
+        g.normal_(generator=gen)
+    say("[gpu] batch workload: forward + backward")
+    batch.forward()
+    batch.backward()
+    torch.cuda.synchronize()
+    assert batch.status() == 0
+    n_all = n_dis = 0
+    for i, a in enumerate(assets):
+        sample = _sample(oracle_lib, a, 500, 1000 + i)
+        gm, gh = batch.maps[i].cpu().numpy(), batch.hits[i].cpu().numpy()
+        ob = oracle_lib.bake(a, method="brute", texels=sample, dilate_passes=0)
+        rep = compare(oracle_lib, a, ob, gm, gh, check_dilation=False, agree_min=None)
+        obp = oracle_lib.bake(a, method="brute", texels=sample, dilate_passes=0, rule="plain")
+        rp = compare_plain(oracle_lib, a, obp, gm, gh)
+        say(f"[gpu] batch asset {i} ({a.hi_F.shape[0]} tris, {a.res}^2): {rep} | {rp}")
+        assert rep.ok(), (i, str(rep))
+        assert rp.ok(), (i, str(rp))
+        assert rep.n_disagree <= MAX_TIES_PER_500, i
+        n_all += rep.n_compared
+        n_dis += rep.n_disagree
+    say(f"[gpu] batch workload: {n_all} sampled texels, {n_dis} verified ties, "
+        f"agreement {1 - n_dis / n_all:.6f}")
+    assert 1 - n_dis / n_all >= 0.999
+    sizes = np.array([a.hi_F.shape[0] for a in assets])
+    rng = np.random.default_rng(5)
+    picks = [int(sizes.argmin()), int(sizes.argmax())]
+    picks += [int(x) for x in rng.choice([k for k in range(64) if k not in picks], 2, replace=False)]
+    for i in picks:
+        a = assets[i]
+        olo, ohi = oracle_lib.adjoint_at(a, batch.hits[i].cpu().numpy(),
+                                         batch.grad_maps[i].cpu().numpy().astype(np.float64).reshape(-1, 3))
+        for name, x, y in (("lo_V", batch.grad_lo_V[i], olo), ("hi_N", batch.grad_hi_N[i], ohi)):
+            x = x.cpu().numpy().astype(np.float64)
+            rel = np.linalg.norm(x - y) / max(np.linalg.norm(y), 1e-30)
+            worst = float((np.abs(x - y) / (1e-3 * np.abs(y) + 1e-6 * np.abs(y).max())).max())
+            say(f"[gpu] batch asset {i} ({a.hi_F.shape[0]} tris) grad {name}: rel L2 {rel:.2e}, "
+                f"worst err/tol {worst:.3f}")
+            assert rel <= 1e-4 and worst <= 1.0, (i, name, rel, worst)

@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-from compare import compare, angle_deg  # noqa: E402
+from compare import compare, compare_plain, angle_deg  # noqa: E402
 from planes import grid, plane_asset, plane_uv  # noqa: E402
 from synth import Asset, make_config  # noqa: E402
 from synth import meshes as M  # noqa: E402
@@ -46,12 +46,18 @@ def np_out(r):
 
 
 def check(oracle, asset, r, ob=None, method="brute", min_agree=None):
+    """Against the oracle's robust rule (the library's convention: the parity
+    bar) and its plain rule (every disagreement a tie)."""
     if ob is None:
         ob = oracle.bake(asset, method=method)
     gm, gh = np_out(r)
     rep = compare(oracle, asset, ob, gm, gh)
     say("[gpu]", asset.name, rep)
     assert rep.ok(), str(rep)
+    rp = compare_plain(oracle, asset, oracle.bake(asset, method=method, texels=None if ob.texels.size == rep.n_covered
+                                                  else ob.texels, rule="plain", dilate_passes=0), gm, gh)
+    say("[gpu]", asset.name, rp)
+    assert rp.ok(), str(rp)
     assert r.status() == 0
     return rep, ob
 
@@ -460,6 +466,9 @@ def _full_size(B, oracle_lib, cfg, n_brute):
     say(f"[gpu] cfg{cfg} full (oracle BVH):", rep)
     assert rep.ok(), str(rep)
     assert rep.n_covered == ob.texels.size  # the oracle's rasteriser decides coverage
+    rp = compare_plain(oracle_lib, a, oracle_lib.bake(a, method="bvh", rule="plain", dilate_passes=0), gm, gh)
+    say(f"[gpu] cfg{cfg} full (oracle BVH):", rp)
+    assert rp.ok(), str(rp)
     # brute force on a seeded sample of covered texels
     rng = np.random.default_rng(cfg)
     sample = np.sort(rng.choice(ob.texels, size=n_brute, replace=False))

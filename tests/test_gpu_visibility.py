@@ -1,9 +1,9 @@
 """GPU hidden-face removal (Sec. 6.2) against the FP64 oracle, through the C
-ABI: every camera ray's first hit (ids agree, or the two sides' faces tie on
-the same ray: both crossed within the edge tolerance at distances equal to
-the rounding of the FP32 ray), the visibility mask (every face seen by one
-side only is a tie's other face), and the flood fill (bit-exact: the oracle's
-fill from the GPU's visible faces)."""
+ABI: every camera ray's first hit (ids agree on 99.9 % of the rays, and every
+disagreement is explained by the FP32 noise at the hit rule's fences: see
+compare.check_first_hits), the visibility mask (every face seen by one side
+only is named by such a ray), and the flood fill (bit-exact: the oracle's fill
+from the GPU's visible faces)."""
 import math
 import sys
 
@@ -14,11 +14,11 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
+from compare import check_first_hits  # noqa: E402
 from planes import grid, grid_cell_triangle  # noqa: E402
 from synth import meshes as M  # noqa: E402
 
 TAN30 = math.tan(math.radians(30.0))
-EDGE_EPS = 1.0 / 16384.0
 
 
 @pytest.fixture(scope="module")
@@ -47,32 +47,13 @@ def run(B, V, F, eyes, target, tan_half, res, t_far, **kw):
 
 
 def check_rays(oracle_lib, V, F, P, D, g_ids, o_ids, o_t, t_far, min_agree=0.999):
-    """Per-ray parity; returns the faces that disagreeing rays name (either side)."""
-    g_ids = np.asarray(g_ids).reshape(-1)
-    o_ids = np.asarray(o_ids).reshape(-1)
-    dis = np.nonzero(g_ids != o_ids)[0]
-    agree = 1.0 - dis.size / max(g_ids.size, 1)
-    say(f"[gpu] rays {g_ids.size}: agree {agree:.6f} ({dis.size} ties to check)")
-    assert agree >= min_agree
-    w = t_far * 2.0 ** -20
-    for r in dis:
-        g, o = int(g_ids[r]), int(o_ids[r])
-        assert g >= 0 or o >= 0
-        for face in (g, o):
-            if face < 0:
-                continue
-            # the face is crossed by the oracle's ray within a few times the
-            # edge tolerance, in front of the eye
-            t, _, bmin = oracle_lib.plane_check(V, F, P[r:r + 1], D[r:r + 1], np.array([face], np.int32))
-            assert bmin[0] >= -4 * EDGE_EPS, (r, face, bmin[0])
-            assert 0 < t[0] <= t_far * (1 + 1e-6) + w
-            if g >= 0 and o >= 0:
-                assert abs(t[0] - o_t[r]) <= 1e-6 * t_far + 2 * w, (r, face, t[0], o_t[r])
-        if g < 0 or o < 0:
-            # a ray one side misses must graze the other side's face
-            t, _, bmin = oracle_lib.plane_check(V, F, P[r:r + 1], D[r:r + 1], np.array([max(g, o)], np.int32))
-            assert bmin[0] <= 4 * EDGE_EPS or t[0] >= t_far * (1 - 1e-6)
-    return set(int(x) for x in np.concatenate([g_ids[dis], o_ids[dis]]) if x >= 0)
+    """Per-ray parity (compare.check_first_hits states the rule); returns the
+    faces that disagreeing rays name (either side)."""
+    method = "brute" if F.shape[0] <= 200_000 else "bvh"
+    rep = check_first_hits(oracle_lib, V, F, P, D, g_ids, o_ids, o_t, t_far, min_agree, method)
+    say("[gpu]", rep)
+    assert rep.ok(), str(rep)
+    return rep.tie_faces
 
 
 def check_masks(oracle_lib, V, F, r, o_vis, tie_faces):

@@ -183,3 +183,26 @@ def test_bvh_equals_brute_force_bake_cfg1(oracle_lib):
     b2 = oracle_lib.bake(a, method="bvh", kind="closest")
     assert np.array_equal(b1.hit, b2.hit) and np.array_equal(b1.map, b2.map)
     assert (b1.hit >= 0).sum() > 4000
+
+
+def test_near_ties_marked(oracle_lib):
+    """Two parallel triangles at heights 0.1 and 0.1 + g above a point: a near
+    tie when 0 < g <= delta, none when g > delta or when the only other
+    triangle shares the nearest point exactly (a fan around a vertex)."""
+    delta = 1e-6
+    P = np.array([[0.2, 0.2, 0.0]])
+    for g, near in ((0.5e-6, True), (3e-6, False)):
+        z2 = 0.1 + g
+        V = np.float32([[-1, -1, 0.1], [3, -1, 0.1], [-1, 3, 0.1], [-1, -1, z2], [3, -1, z2], [-1, 3, z2]])
+        F = np.int32([[0, 1, 2], [3, 4, 5]])
+        ids, d, _ = oracle_lib.closest(V, F, P, 1.0)
+        assert ids[0] == 0
+        assert oracle_lib.closest_near(V, F, P, ids, d, delta).tolist() == [near], g
+    # a fan of four triangles around the vertex (0, 0, 0.1) right above the
+    # point: every triangle's nearest point is that vertex, an exact tie
+    V = np.float32([[0, 0, 0.1], [1, 0, 0.1], [0, 1, 0.1], [-1, 0, 0.1], [0, -1, 0.1]])
+    F = np.int32([[0, 1, 2], [0, 2, 3], [0, 3, 4], [0, 4, 1]])
+    P = np.array([[0.0, 0.0, -0.2]])
+    ids, d, _ = oracle_lib.closest(V, F, P, 1.0)
+    assert ids[0] == 0 and abs(d[0] - 0.3) < 1e-7
+    assert oracle_lib.closest_near(V, F, P, ids, d, delta).tolist() == [False]

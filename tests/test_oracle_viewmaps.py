@@ -1,4 +1,4 @@
-"""Pins of the oracle's backprojection precompute (Sec. 6.5): image
+"""Pins of the oracle's backprojection precompute (Sec. 7.4, TextureGen Postprocessing): image
 coordinates of a plane's texels against the pinhole projection in closed form,
 the round trip through the camera ray, the incidence of a plane, back faces,
 texels outside the image, and the depth-buffer visibility under an occluder."""
