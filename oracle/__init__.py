@@ -353,28 +353,36 @@ def frozen_forward(asset, face, bary, g, hf):
     return out, tb
 
 
-def adjoint(asset, face, bary, g, hf, grad_out, magnitudes=False):
+def adjoint(asset, face, bary, g, hf, grad_out, magnitudes=False, bnoise=None):
     """FP64 reverse mode of frozen_forward: given d(loss)/d(out) per ray,
     returns (d loss / d lo_V [Vl,3], d loss / d hi_N [Vh,3]); with
     magnitudes=True also, per entry, the summed magnitudes of the terms added
-    into it (the scale a floating-point evaluation of the sums is accurate to)."""
+    into it (the scale a floating-point evaluation of the sums is accurate to).
+    With bnoise [n] (a bound per ray on the perturbation of the hit weights
+    beta1, beta2) also, per entry of d loss / d hi_N, the first-order bound of
+    how far its terms move under such a perturbation (oracle.c, orc_adjoint)."""
     loV, loF, UV, hiV, hiF, hiN, face, bary, g, hf = _frozen_args(asset, face, bary, g, hf)
     go = _c(grad_out, np.float64)
     glo = np.zeros((loV.shape[0], 3)); ghi = np.zeros((hiV.shape[0], 3))
     alo = np.zeros((loV.shape[0], 3)) if magnitudes else None
     ahi = np.zeros((hiV.shape[0], 3)) if magnitudes else None
+    bn = None if bnoise is None else _c(np.broadcast_to(np.asarray(bnoise, np.float64), (face.shape[0],)), np.float64)
+    shi = np.zeros((hiV.shape[0], 3)) if bn is not None else None
     _call("orc_adjoint", _p(loV), C.c_int64(loV.shape[0]), _p(loF), C.c_int64(loF.shape[0]), _p(UV),
           C.c_int32(asset.res), _p(hiV), C.c_int64(hiV.shape[0]), _p(hiF), _p(hiN),
           C.c_int64(face.shape[0]), _p(face), _p(bary), _p(g), _p(hf), _p(go), _p(glo), _p(ghi),
-          _p(alo), _p(ahi))
-    return (glo, ghi, alo, ahi) if magnitudes else (glo, ghi)
+          _p(alo), _p(ahi), _p(bn), _p(shi))
+    out = (glo, ghi, alo, ahi) if magnitudes else (glo, ghi)
+    return out + (shi,) if bn is not None else out
 
 
-def adjoint_at(asset, hit, grad_map, magnitudes=False):
+def adjoint_at(asset, hit, grad_map, magnitudes=False, bnoise=None):
     """Adjoint of a whole bake's pre-dilation map at a given hit selection:
     hit [res*res] (a bake's status per texel, >= 0 for hits: e.g. the GPU's
     own), grad_map [res*res, 3].  The texel -> face assignment and barycentrics
-    are the rasteriser's (exact integers), h_f the face frames'."""
+    are the rasteriser's (exact integers), h_f the face frames'.  bnoise: None,
+    or a function of (texels, t [n]) giving the weight perturbation bound per
+    hit texel (t: the FP64 crossing distance at that selection), see adjoint."""
     hit = np.asarray(hit).reshape(-1)
     face, bary = raster(asset.lo_UV, asset.res)
     tex = np.nonzero((face >= 0) & (hit >= 0))[0]
@@ -382,7 +390,11 @@ def adjoint_at(asset, hit, grad_map, magnitudes=False):
     _, _, hf, _ = face_frames(asset.lo_V, asset.lo_F, asset.lo_UV, asset.res, ok)
     gm = np.asarray(grad_map, np.float64).reshape(-1, 3)[tex]
     f = face[tex]
-    return adjoint(asset, f, bary[tex], hit[tex], hf[f], gm, magnitudes)
+    bn = None
+    if bnoise is not None:
+        _, tb = frozen_forward(asset, f, bary[tex], hit[tex], hf[f])
+        bn = bnoise(tex, tb[:, 0])
+    return adjoint(asset, f, bary[tex], hit[tex], hf[f], gm, magnitudes, bn)
 
 
 def bake_adjoint(asset, ob, grad_map):

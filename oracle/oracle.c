@@ -1282,11 +1282,21 @@ static void acc_abs(double *p, int64_t i, v3 a) {
 /* gloV_abs / ghiN_abs (optional, NULL to skip): per gradient entry, the sum of
  * the magnitudes of the terms that the adjoint adds into it (through the
  * vertex-normal chain, a componentwise bound of the same), the scale to which
- * a floating-point evaluation of the sums is accurate. */
+ * a floating-point evaluation of the sums is accurate.
+ *
+ * bnoise / ghiN_sens (optional, NULL to skip): given per ray a bound bnoise[r]
+ * on the perturbation of the hit weights beta1, beta2 (so beta0 = 1 - beta1 -
+ * beta2 moves by at most twice that), ghiN_sens receives per entry of dL/dhi_N
+ * the summed first-order bound of how far its terms beta_k h_bar move:
+ *   |d(beta_k h_bar)| <= |d beta_k| |h_bar| + |beta_k| |d h_bar|,
+ *   |d h_bar| <= 3 |n_bar| |d h| / |h|^2,  |d h| <= bnoise (|N1 - N0| + |N2 - N0|)
+ * (h_bar = (I - n n^T) n_bar / |h|, n = h / |h|: dn = (I - n n^T) dh / |h| and
+ * d|h| = n . dh contribute |n_bar| |dh| / |h|^2 twice and once). */
 int orc_adjoint(const float *loV, int64_t nlv, const int32_t *loF, int64_t nlf, const float *UV,
                 int32_t res, const float *hiV, int64_t nhv, const int32_t *hiF, const float *hiN, int64_t n,
                 const int32_t *face, const double *bary, const int32_t *g, const int8_t *hf,
-                const double *gout, double *gloV, double *ghiN, double *gloV_abs, double *ghiN_abs) {
+                const double *gout, double *gloV, double *ghiN, double *gloV_abs, double *ghiN_abs,
+                const double *bnoise, double *ghiN_sens) {
     double *s = (double *)malloc(sizeof(double) * (size_t)(3 * (nlv > 0 ? nlv : 1)));
     double *nrm = (double *)malloc(sizeof(double) * (size_t)(3 * (nlv > 0 ? nlv : 1)));
     double *nbar = (double *)calloc((size_t)(3 * (nlv > 0 ? nlv : 1)), sizeof(double));
@@ -1297,6 +1307,7 @@ int orc_adjoint(const float *loV, int64_t nlv, const int32_t *loF, int64_t nlf, 
     for (int64_t i = 0; i < 3 * nhv; ++i) ghiN[i] = 0;
     if (gloV_abs) for (int64_t i = 0; i < 3 * nlv; ++i) gloV_abs[i] = 0;
     if (ghiN_abs) for (int64_t i = 0; i < 3 * nhv; ++i) ghiN_abs[i] = 0;
+    if (ghiN_sens) for (int64_t i = 0; i < 3 * nhv; ++i) ghiN_sens[i] = 0;
     for (int64_t r = 0; r < n; ++r) {
         rstate S;
         ray_forward(loV, loF, nrm, UV, res, hiV, hiF, hiN, face[r], bary + 3 * r, g[r], hf[r], &S);
@@ -1317,6 +1328,16 @@ int orc_adjoint(const float *loV, int64_t nlv, const int32_t *loF, int64_t nlf, 
         for (int k = 0; k < 3; ++k) {
             st3d(ghiN, S.hv[k], add(ld3d(ghiN, S.hv[k]), scl(hb, beta[k])));
             acc_abs(ghiN_abs, S.hv[k], scl(hb, beta[k]));
+        }
+        if (ghiN_sens && bnoise) {
+            double db = bnoise[r];
+            double dh = db * (norm(sub(S.N[1], S.N[0])) + norm(sub(S.N[2], S.N[0])));
+            double dhb = 3.0 * norm(nb) * dh / (S.lh * S.lh);
+            for (int k = 0; k < 3; ++k) {
+                double dbk = k == 0 ? 2.0 * db : db;
+                v3 e = add(scl(vabs(hb), dbk), scl(mk(1, 1, 1), fabs(beta[k]) * dhb));
+                st3d(ghiN_sens, S.hv[k], add(ld3d(ghiN_sens, S.hv[k]), e));
+            }
         }
         double b1b = dot(hb, sub(S.N[1], S.N[0])), b2b = dot(hb, sub(S.N[2], S.N[0]));
         /* [-d | e1 | e2] (t, b1, b2) = p - A: w = M^-T (0, b1b, b2b) */

@@ -192,3 +192,41 @@ def test_first_hits_planted_leak_fails(oracle_lib, sphere_rays):
     g = ids.copy()
     g[r] = back[0]
     assert not check_first_hits(oracle_lib, V, F, P, D, g, ids, t, 5.0).ok()
+
+
+def _patch_beside_texel_column(dx):
+    """A high-poly quad at z = 0.05 over x in [0.1, x1], y in [0.1, 0.9] whose
+    boundary edge x = x1 lies dx short of the texel column x = 8.5 / 16 of a
+    16^2 flat low-poly (rays along +z)."""
+    from planes import plane_asset
+    x1 = np.float32(8.5 / 16 - dx)
+    V = np.array([[0.1, 0.1, 0.05], [x1, 0.1, 0.05], [x1, 0.9, 0.05], [0.1, 0.9, 0.05]], np.float32)
+    F = np.array([[0, 1, 2], [0, 2, 3]], np.int32)
+    # tilted normals, so a hit bakes a normal other than the miss value (0,0,1)
+    N = np.tile(np.float32([0.3, 0, 1]), (4, 1))
+    return plane_asset(V, F, N, res=16, lo_n=2, max_dist=0.25)
+
+
+def test_hit_grazing_a_boundary_edge_is_a_plain_tie(oracle_lib):
+    """Rays passing 5e-7 (about 8 FP32 ulps) outside a boundary edge of the
+    high-poly: the plain rule misses, the robust rule's edge tolerance admits
+    the triangle (as the GPU does).  Against the plain rule such a hit is a tie
+    (the ray grazes the triangle); the same hit planted on rays 0.1 away from
+    the edge is not."""
+    a = _patch_beside_texel_column(5e-7)
+    ob = oracle_lib.bake(a, dilate_passes=0)
+    obp = oracle_lib.bake(a, rule="plain", dilate_passes=0)
+    graze = (ob.hit >= 0) & (obp.hit < 0)
+    assert graze.sum() >= 10, int(graze.sum())
+    gm, gh = _as_gpu(ob)
+    rp = compare_plain(oracle_lib, a, obp, gm, gh)
+    print(rp)
+    assert rp.ok() and rp.n_disagree == int(graze.sum()) and rp.max_delta_ulp <= 32
+    assert rp.max_angle > 10  # the grazing hits' normals are not the miss value
+    # planted: the triangle reported on rays of the column 0.1 farther out
+    far = np.nonzero((obp.hit < 0) & np.isclose(obp.P[:, 0], 10.5 / 16))[0]
+    assert far.size > 0
+    gh2 = gh.copy()
+    gh2[obp.texels[far[0]]] = 0
+    rp2 = compare_plain(oracle_lib, a, obp, gm, gh2)
+    assert not rp2.ok()

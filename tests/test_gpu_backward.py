@@ -5,10 +5,21 @@ selection (the GPU's hit ids per texel; the texel -> face assignment and the
 barycentrics are the rasteriser's exact integers, bit-identical on both
 sides), with the same upstream gradient the GPU received.  Every entry of
 dL/dlo_V and dL/dhi_N is compared, with no exclusions: relative L2 <= 1e-4
-overall, and per entry |gpu - adjoint| <= 1e-3 |adjoint| + 1e-6 max|adjoint|.
-The report also gives the largest error in units of u = 2^-24 times the
-entry's summed term magnitudes (the scale an FP32 evaluation of the sums is
-accurate to).
+overall, and per entry |gpu - adjoint| <= 1e-3 |adjoint| + 1e-6 max|adjoint|
+(+ for dL/dhi_N the FP32 noise term below).
+
+The FP64 adjoint recomputes the hit weights beta of the selected triangle
+exactly; the GPU's come from its FP32 forward, which moves them by up to the
+comparator's weight noise bound (tests/compare.py, ``weight_slack``: the ray's
+origin and direction rounding and the watertight test's arithmetic, divided by
+the hit triangle's smallest altitude: ~1e-4 on the 1.3M-triangle noise
+sphere, whose triangles are 3e-3 across at unit coordinates).  A hi_N term
+beta_k h_bar with a small beta_k carries that absolute error, whatever the
+backward's own arithmetic, so per entry of dL/dhi_N the tolerance adds the
+oracle's first-order bound of how far its terms move under that perturbation
+(oracle.c, orc_adjoint: bnoise / ghiN_sens).  The report also gives the
+largest error in units of u = 2^-24 times the entry's summed term magnitudes
+(the scale an FP32 evaluation of the sums is accurate to).
 """
 import sys
 
@@ -19,10 +30,10 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
+import compare as CMP  # noqa: E402
 from synth import Asset, make_config  # noqa: E402
 from synth import meshes as M  # noqa: E402
 
-U32 = 2.0 ** -24
 
 
 @pytest.fixture(scope="module")
@@ -39,23 +50,6 @@ def say(*a):
     sys.stdout.flush()
 
 
-def _compare_grads(name, g_gpu, g_orc, mag):
-    g_gpu = np.asarray(g_gpu, np.float64)
-    err = np.abs(g_gpu - g_orc)
-    rel_l2 = np.linalg.norm(g_gpu - g_orc) / max(np.linalg.norm(g_orc), 1e-30)
-    tol = 1e-3 * np.abs(g_orc) + 1e-6 * np.abs(g_orc).max()
-    ratio = err / np.maximum(tol, 1e-300)
-    worst = float(ratio.max()) if err.size else 0.0
-    in_u = float((err / np.maximum(U32 * mag, 1e-300)).max()) if err.size else 0.0
-    k = np.unravel_index(np.argmax(ratio), ratio.shape) if err.size else None
-    say(f"[gpu] grad {name}: {g_orc.size} entries, rel L2 {rel_l2:.2e}, worst err/tol {worst:.3f}"
-        f" (entry {k}: gpu {g_gpu[k]:.6e} adjoint {g_orc[k]:.6e} magnitude {mag[k]:.3e}),"
-        f" max err / (u magnitude) {in_u:.1f}")
-    assert rel_l2 <= 1e-4, rel_l2
-    assert worst <= 1.0, worst
-    return rel_l2
-
-
 def _run(B, a, grad_map_np=None, target=None):
     t = B.to_device(a)
     r = B.bake_normals(*t, a.res, a.max_dist, save=True, dilate_passes=0)
@@ -70,9 +64,12 @@ def _run(B, a, grad_map_np=None, target=None):
 
 def _adjoint_at_gpu_selection(oracle_lib, a, r, gm):
     """The oracle's adjoint at the GPU's hit ids, fed the GPU's upstream
-    gradient (float32 values widened exactly)."""
+    gradient (float32 values widened exactly): (lo_V, hi_N, their term
+    magnitudes, hi_N's weight-noise bound)."""
     g = gm.detach().cpu().numpy() if torch.is_tensor(gm) else np.asarray(gm, np.float32)
-    return oracle_lib.adjoint_at(a, r.hit.cpu().numpy(), g.astype(np.float64).reshape(-1, 3), magnitudes=True)
+    hit = r.hit.cpu().numpy()
+    return oracle_lib.adjoint_at(a, hit, g.astype(np.float64).reshape(-1, 3), magnitudes=True,
+                                 bnoise=CMP.weight_noise(a, hit))
 
 
 def test_backward_matches_oracle_adjoint_ripple(B, oracle_lib):
@@ -80,9 +77,9 @@ def test_backward_matches_oracle_adjoint_ripple(B, oracle_lib):
     rng = np.random.default_rng(3)
     gm = rng.normal(size=(a.res, a.res, 3)).astype(np.float32)
     r, t, gmt, glo, ghi = _run(B, a, gm)
-    olo, ohi, mlo, mhi = _adjoint_at_gpu_selection(oracle_lib, a, r, gmt)
-    _compare_grads("lo_V", glo, olo, mlo)
-    _compare_grads("hi_N", ghi, ohi, mhi)
+    olo, ohi, mlo, mhi, shi = _adjoint_at_gpu_selection(oracle_lib, a, r, gmt)
+    CMP.compare_grads("lo_V", glo, olo, mlo)
+    CMP.compare_grads("hi_N", ghi, ohi, mhi, shi)
     assert np.abs(ohi).sum() > 0 and np.abs(olo).sum() > 0
 
 
@@ -162,9 +159,9 @@ def test_differentiation_workload_full_size(B, oracle_lib):
     r, t, gm_t, glo, ghi = _run(B, a, target=tgt)
     assert glo.shape == (10242, 3) and ghi.shape == (655362, 3)
     say("[gpu] cfg4: oracle adjoint at the GPU's selection")
-    olo, ohi, mlo, mhi = _adjoint_at_gpu_selection(oracle_lib, a, r, gm_t)
-    _compare_grads("lo_V", glo, olo, mlo)
-    _compare_grads("hi_N", ghi, ohi, mhi)
+    olo, ohi, mlo, mhi, shi = _adjoint_at_gpu_selection(oracle_lib, a, r, gm_t)
+    CMP.compare_grads("lo_V", glo, olo, mlo)
+    CMP.compare_grads("hi_N", ghi, ohi, mhi, shi)
 
 
 def _large_asset(uv_zero, seed=9):

@@ -121,3 +121,52 @@ def test_bake_adjoint_ignores_non_hits(oracle_lib):
     gm2[nonhit] = 1e6  # non-hit texels are constants: no effect
     glo2, ghi2 = oracle_lib.bake_adjoint(a, ob, gm2)
     assert np.array_equal(glo, glo2) and np.array_equal(ghi, ghi2)
+
+
+def test_weight_noise_bound_dominates_the_change(oracle_lib, setup):
+    """The hi_N sensitivity output (orc_adjoint's bnoise / ghiN_sens) bounds
+    the change of dL/dhi_N when the hit weights move.  The weights are moved
+    through the geometry: each hit triangle is shifted within its own plane by
+    a small random offset (the crossing point, and so beta, moves; the hit
+    normals and the upstream gradient do not), and the change of every entry
+    must stay within the bound computed with the largest weight change seen
+    on that ray.  Brute force over the 64 sampled rays, one ray at a time (so
+    a triangle shared by two rays is moved for one of them only)."""
+    import copy
+    a, ob, sel, tex, face, bary, g, hf = setup
+    rng = np.random.default_rng(21)
+    gout = rng.normal(size=(face.size, 3))
+    worst = 0.0
+    for r in range(face.size):
+        sl = slice(r, r + 1)
+        _, ghi0 = oracle_lib.adjoint(a, face[sl], bary[sl], g[sl], hf[sl], gout[sl])
+        _, tb0 = oracle_lib.frozen_forward(a, face[sl], bary[sl], g[sl], hf[sl])
+        T = a.hi_V[a.hi_F[g[r]]].astype(np.float64)
+        e1, e2 = T[1] - T[0], T[2] - T[0]
+        u = e1 / np.linalg.norm(e1)
+        w = np.cross(np.cross(e1, e2), u)
+        w /= np.linalg.norm(w)
+        for _ in range(3):
+            # an in-plane shift of about 1e-3 of the triangle's size: the
+            # float32 vertices round, so the shift is not exactly in-plane,
+            # which only changes beta (and t) a little more
+            s = (rng.normal() * u + rng.normal() * w) * 1e-3 * np.linalg.norm(e1)
+            b = copy.copy(a)
+            hv = a.hi_V.copy()
+            for j in a.hi_F[g[r]]:
+                hv[j] = (hv[j].astype(np.float64) + s).astype(np.float32)
+            b.hi_V = hv
+            _, ghi1 = oracle_lib.adjoint(b, face[sl], bary[sl], g[sl], hf[sl], gout[sl])
+            _, tb1 = oracle_lib.frozen_forward(b, face[sl], bary[sl], g[sl], hf[sl])
+            db = float(np.abs(tb1[0, 1:] - tb0[0, 1:]).max())
+            assert db > 0
+            _, _, _, _, sens = oracle_lib.adjoint(a, face[sl], bary[sl], g[sl], hf[sl], gout[sl],
+                                                  magnitudes=True, bnoise=np.array([db]))
+            change = np.abs(ghi1 - ghi0)
+            # first order: allow 1 % for the second-order terms at this shift
+            assert np.all(change <= 1.01 * sens + 1e-15), (r, change.max(), sens.max())
+            touched = np.abs(ghi0).sum(1) > 0
+            worst = max(worst, float((change[touched] / np.maximum(sens[touched], 1e-300)).max()))
+    # the bound is not vacuous: some entry uses a good part of it
+    print(f"largest change / bound: {worst:.3f}")
+    assert worst > 0.05, worst
