@@ -481,6 +481,8 @@ def main():
     ap.add_argument("--trav-block", type=int, default=0)
     ap.add_argument("--trav-stack", type=int, default=0)
     ap.add_argument("--trav-mode", type=int, default=-1)
+    ap.add_argument("--one-queue", action="store_true",
+                    help="traversal items from one work queue instead of one per XCD")
     ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3),
                     help="workload: 2 = the headline 1.3M -> 20k triangle bake (default); 1 = the small "
                          "ripple bake; 3 = the large 5.2M-triangle bake")
@@ -543,7 +545,7 @@ def main():
         V = np.asarray(asset.hi_V, np.float64)
         md = 0.01 * float(np.linalg.norm(V.max(0) - V.min(0)))
     trav = dict(trav_block=args.trav_block, trav_stack=args.trav_stack, trav_mode=args.trav_mode,
-                query=args.query)
+                query=args.query, one_queue=args.one_queue)
     # loss target: the map baked (by this library, untimed) from a second noise seed
     tgt_asset = make_config(args.config, seed=1)
     target = B.bake_normals(*B.to_device(tgt_asset, dev), res, md).map.clone()

@@ -84,9 +84,15 @@ extern "C" {
                                (bake_read_counter 1 and 2); slower, same results */
 #define BAKE_FLAG_ONE_STREAM 8u /* run every stage on the caller's stream: no second
                                    stream for the low-poly work beside the BVH build
-                                   (forward) and the high-poly sort (backward); the
+                                   (forward) and the high-poly sums (backward); the
                                    backward of a saved forward follows the forward's
                                    choice.  Same results bit for bit.              */
+#define BAKE_FLAG_ONE_QUEUE 16u /* the ray traversal's persistent waves take their
+                                   (asset, 64-ray batch) items from one work queue
+                                   in face order, instead of the default of one
+                                   queue per XCD over a contiguous part of the items
+                                   (the waves sharing an L2 then trace one region of
+                                   the surface).  Same results bit for bit.         */
 
 typedef struct bake_options {
     int32_t dilate_passes; /* chart dilation passes, 0..64 (default 2)                    */

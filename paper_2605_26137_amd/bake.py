@@ -43,6 +43,7 @@ BAKE_FLAG_SAVE = 1
 BAKE_FLAG_TIMING = 2
 BAKE_FLAG_COUNT = 4
 BAKE_FLAG_ONE_STREAM = 8
+BAKE_FLAG_ONE_QUEUE = 16
 
 (VIEW_RAYS, VIEW_HITS, VIEW_FACEMAP, VIEW_LO_N, VIEW_SORTED, VIEW_NODES, VIEW_LEAVES, VIEW_FACE_T,
  VIEW_SORTED_IDX) = range(9)
@@ -162,12 +163,14 @@ def _check(rc: int):
 
 
 def make_options(dilate_passes=2, save=False, timing=False, rgb8_ptr=0, trav_block=0,
-                 trav_stack=0, trav_mode=-1, count=False, query="ray", one_stream=False) -> BakeOptions:
+                 trav_stack=0, trav_mode=-1, count=False, query="ray", one_stream=False,
+                 one_queue=False) -> BakeOptions:
     o = BakeOptions()
     lib().bake_default_options(C.byref(o))
     o.dilate_passes = int(dilate_passes)
     o.flags = ((BAKE_FLAG_SAVE if save else 0) | (BAKE_FLAG_TIMING if timing else 0)
-               | (BAKE_FLAG_COUNT if count else 0) | (BAKE_FLAG_ONE_STREAM if one_stream else 0))
+               | (BAKE_FLAG_COUNT if count else 0) | (BAKE_FLAG_ONE_STREAM if one_stream else 0)
+               | (BAKE_FLAG_ONE_QUEUE if one_queue else 0))
     o.out_rgb8 = rgb8_ptr or None
     o.trav_block = int(trav_block)
     o.trav_stack = int(trav_stack)
@@ -257,7 +260,8 @@ def bake_normals(hi_V, hi_F, hi_N, lo_V, lo_F, lo_UV, res: int, max_dist: float,
                  dilate_passes: int = 2, rgb8: bool = False, save: bool = False,
                  timing: bool = False, trav_block: int = 0, trav_stack: int = 0,
                  trav_mode: int = -1, count: bool = False, query: str = "ray",
-                 one_stream: bool = False, workspace: Optional[torch.Tensor] = None,
+                 one_stream: bool = False, one_queue: bool = False,
+                 workspace: Optional[torch.Tensor] = None,
                  out_map: Optional[torch.Tensor] = None, out_hit: Optional[torch.Tensor] = None,
                  stream=None) -> BakeResult:
     """Bake a tangent-space normal map of the high-poly onto the low-poly's UV
@@ -281,7 +285,7 @@ def bake_normals(hi_V, hi_F, hi_N, lo_V, lo_F, lo_UV, res: int, max_dist: float,
     sizes = (hi_V.shape[0], hi_F.shape[0], lo_V.shape[0], lo_F.shape[0], int(res))
     rgb = torch.empty((res, res, 3), dtype=torch.uint8, device=dev) if rgb8 else None
     opts = make_options(dilate_passes, save, timing, rgb.data_ptr() if rgb is not None else 0,
-                        trav_block, trav_stack, trav_mode, count, query, one_stream)
+                        trav_block, trav_stack, trav_mode, count, query, one_stream, one_queue)
     nbytes = workspace_size(*sizes, opts)
     if workspace is None or workspace.numel() < nbytes:
         workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
@@ -378,7 +382,7 @@ class BakeBatch:
     Every asset's results are bitwise those of a single bake_normals call."""
 
     def __init__(self, assets, *, save=False, dilate_passes=2, rgb8=False, trav_block=0,
-                 trav_stack=0, trav_mode=-1, need_lo=True, need_hi=True, query="ray"):
+                 trav_stack=0, trav_mode=-1, need_lo=True, need_hi=True, query="ray", one_queue=False):
         if not assets:
             raise ValueError("empty batch")
         self.inputs = []
@@ -427,7 +431,7 @@ class BakeBatch:
             e.grad_hi_N = ghi.data_ptr() if ghi is not None else None
         self.device = self.inputs[0][0].device
         self.opts = make_options(dilate_passes, save, False, 0, trav_block, trav_stack, trav_mode,
-                                 query=query)
+                                 query=query, one_queue=one_queue)
         b = C.c_size_t(0)
         _check(lib().bake_batch_workspace_size(self._arr, self.n, C.byref(self.opts), C.byref(b)))
         self.workspace = torch.empty(b.value, dtype=torch.uint8, device=self.device)

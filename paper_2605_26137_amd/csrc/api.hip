@@ -65,7 +65,8 @@ int32_t parse_opts(const bake_options* o, Opts* out) {
     if (o->dilate_passes < 0 || o->dilate_passes > 64)
         return fail(BAKE_E_INVALID_ARG, "dilate_passes %d outside [0, 64]", o->dilate_passes);
     out->dilate = o->dilate_passes;
-    if (o->flags & ~(uint32_t)(BAKE_FLAG_SAVE | BAKE_FLAG_TIMING | BAKE_FLAG_COUNT | BAKE_FLAG_ONE_STREAM))
+    if (o->flags & ~(uint32_t)(BAKE_FLAG_SAVE | BAKE_FLAG_TIMING | BAKE_FLAG_COUNT | BAKE_FLAG_ONE_STREAM |
+                               BAKE_FLAG_ONE_QUEUE))
         return fail(BAKE_E_INVALID_ARG, "unknown flag bits 0x%x", o->flags);
     out->flags = o->flags;
     out->rgb8 = o->out_rgb8;
@@ -524,6 +525,7 @@ int32_t run_forward(Plan& P, const Opts& o, void* workspace, hipStream_t s) {
     HIP_OR_FAIL(tim_record(tim, 3, s));
     TravConfig tc = o.trav;
     tc.count = (o.flags & BAKE_FLAG_COUNT) != 0;
+    tc.xcd = (o.flags & BAKE_FLAG_ONE_QUEUE) == 0;
     HIP_OR_FAIL(launch_traverse(H, tc, s));
     HIP_OR_FAIL(tim_record(tim, 4, s));
     HIP_OR_FAIL(launch_dilate(H, o.dilate, s));

@@ -170,7 +170,10 @@ constexpr int kCntSlots = 16;
 // Batch counter slots.
 constexpr int kGcQueue = 0;  // traversal work queue head
 constexpr int kGcSeal = 1;   // nonce of the last completed forward (0 while one runs)
-constexpr int kGcSlots = 16;
+constexpr int kXcds = 8;         // XCDs of an MI355X: each has its own L2
+constexpr int kXcdStride = 32;   // one 128-byte line per XCD queue head
+constexpr int kGcXcdQueue = 32;  // kXcds traversal queue heads, kXcdStride apart
+constexpr int kGcSlots = kGcXcdQueue + kXcds * kXcdStride;
 
 // What every kernel receives: the asset table and the batch-wide tables.
 struct Batch {
@@ -259,6 +262,7 @@ struct TravConfig {
                   // 3: 64-ray batches, balanced all-node / all-leaf trips
     bool count = false;    // instrumented variant: count box and triangle tests
     bool closest = false;  // closest-point query instead of the ray query
+    bool xcd = true;       // wave batches: one work queue per XCD (traverse.hip)
 };
 
 // ---------------------------------------------------------------------------

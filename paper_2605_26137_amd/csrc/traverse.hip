@@ -291,6 +291,7 @@ struct TravArgs {
     Hit* hits;             // optional, by global ray index
     int32_t* spill;        // [kMaxDepth][spill_lanes]
     int64_t spill_lanes;
+    int32_t xcd_split;     // wave batches: per-XCD work queues (next_item)
 };
 
 // What the inner loop needs of an asset.
@@ -574,6 +575,53 @@ __device__ __forceinline__ int32_t tri_step(const TreeView& tv, int32_t node, co
     else return leaf_step<BLOCK, STACK, COUNT, Q == kQFirst>(tv, node, R, best, st, tid, c_tri);
 }
 
+// The XCD (0..7) whose compute unit runs the calling wave, from the hardware
+// register that names it.
+__device__ __forceinline__ int wave_xcd() {
+    return (int)(__builtin_amdgcn_s_getreg((3 << 11) | 20) & (kXcds - 1));  // hwreg(HW_REG_XCC_ID, 0, 4)
+}
+
+// The work queue of the wave batches: the wave's next (asset, 64-ray batch)
+// item of the n in face order, n when none is left.  With one queue every
+// wave takes the next item, so the waves in flight (about 7,000 on 256 CUs)
+// cover a window of about 40 % of a 1M-ray bake, spread over all eight XCDs.
+// With the XCD split the items are cut into kXcds contiguous ranges and a
+// wave takes from its own XCD's range first: the waves that share an L2 then
+// trace one region of the surface, whose nodes and leaves stay in that L2.
+// A wave whose range is done moves on to the next XCD's range (cur, left: the
+// range it takes from and how many ranges it has yet to find empty); a range
+// once found empty stays empty, so every wave ends after at most kXcds
+// empty answers and every item is handed out exactly once.
+struct ItemQueue {
+    int cur, left;
+};
+
+__device__ __forceinline__ ItemQueue item_queue_init(bool split) {
+    ItemQueue iq;
+    iq.cur = split ? wave_xcd() : 0;
+    iq.left = split ? kXcds : 1;
+    return iq;
+}
+
+__device__ __forceinline__ uint32_t next_item(const Batch& B, uint32_t n, bool split, int lane, ItemQueue& iq) {
+    for (;;) {
+        if (iq.left == 0) return n;
+        uint32_t lo = 0, len = n;
+        uint32_t* head = &B.gcnt[kGcQueue];
+        if (split) {
+            lo = (uint32_t)(((uint64_t)n * (uint32_t)iq.cur) / kXcds);
+            len = (uint32_t)(((uint64_t)n * (uint32_t)(iq.cur + 1)) / kXcds) - lo;
+            head = &B.gcnt[kGcXcdQueue + kXcdStride * iq.cur];
+        }
+        uint32_t k = 0;
+        if (lane == 0) k = atomicAdd(head, 1u);
+        k = __builtin_amdgcn_readfirstlane(__shfl(k, 0, 64));
+        if (k < len) return lo + k;
+        --iq.left;
+        iq.cur = iq.cur + 1 == kXcds ? 0 : iq.cur + 1;
+    }
+}
+
 // Loop shapes of the wave batches (TravConfig::mode):
 constexpr int kLoopSingle = 0;    // every trip: each lane one step of its own kind
 constexpr int kLoopPhased = 2;    // internal-node trips until every lane is at a leaf, then one leaf trip
@@ -601,10 +649,10 @@ __global__ __launch_bounds__(BLOCK) void traverse_batch_kernel(TravArgs a) {
     st.spill = a.spill;
     st.stride = a.spill_lanes;
     st.col = (int64_t)blockIdx.x * BLOCK + tid;
+    const bool split = a.xcd_split != 0;
+    ItemQueue iq = item_queue_init(split);
     for (;;) {
-        uint32_t q = 0;
-        if (lane == 0) q = atomicAdd(&B.gcnt[kGcQueue], 1u);
-        q = __builtin_amdgcn_readfirstlane(__shfl(q, 0, 64));
+        const uint32_t q = next_item(B, nbatches, split, lane, iq);
         if (q >= nbatches) break;
         const int ai = upper_asset(B.rb_pf, B.n, q);
         const AssetDev& As = B.A[ai];
@@ -1040,6 +1088,7 @@ hipError_t launch_visibility_rays(const BatchHost& H, const VisRun& v, hipStream
     a.t.hits = nullptr;
     a.t.spill = v.spill;
     a.t.spill_lanes = v.spill_lanes;
+    a.t.xcd_split = 0;
     a.eyes = v.eyes;
     a.target = make_float3(v.target[0], v.target[1], v.target[2]);
     a.tan_half = v.tan_half;
@@ -1079,6 +1128,7 @@ hipError_t launch_view_maps(const BatchHost& H, const MapRun& m, hipStream_t s) 
     a.t.hits = nullptr;
     a.t.spill = nullptr;
     a.t.spill_lanes = 0;
+    a.t.xcd_split = 0;
     a.eyes = m.eyes;
     a.target = make_float3(m.target[0], m.target[1], m.target[2]);
     a.tan_half = m.tan_half;
@@ -1097,8 +1147,10 @@ hipError_t launch_view_maps(const BatchHost& H, const MapRun& m, hipStream_t s) 
 hipError_t launch_traverse(const BatchHost& H, const TravConfig& cfg, hipStream_t s) {
     const Layout& L = H.L;
     char* ws = H.ws;
+    // the queue heads (the single queue and the per-XCD ones) start at zero
     hipError_t e = fill_u32(H.dev.gcnt + kGcQueue, 0, 1, s);
     if (e != hipSuccess) return e;
+    if ((e = fill_u32(H.dev.gcnt + kGcXcdQueue, 0, kXcds * kXcdStride, s)) != hipSuccess) return e;
     if (L.t_tex == 0) return hipSuccess;
     TravArgs a;
     a.B = H.dev;
@@ -1111,6 +1163,7 @@ hipError_t launch_traverse(const BatchHost& H, const TravConfig& cfg, hipStream_
     a.hits = L.save ? (Hit*)(ws + L.hits) : nullptr;
     a.spill = (int32_t*)(ws + L.spill);
     a.spill_lanes = L.spill_lanes;
+    a.xcd_split = cfg.xcd ? 1 : 0;
     int64_t lanes = L.spill_lanes;
     if (cfg.count) return launch_mode<256, 16, true>(a, cfg.mode, cfg.closest, s, lanes);
 #define BAKE_TRAV_CASE(B, S) \
