@@ -84,7 +84,7 @@ extern "C" {
                                (bake_read_counter 1 and 2); slower, same results */
 #define BAKE_FLAG_ONE_STREAM 8u /* run every stage on the caller's stream: no second
                                    stream for the low-poly work beside the BVH build
-                                   (forward) and the high-poly sums (backward); the
+                                   (forward) and the high-poly sort (backward); the
                                    backward of a saved forward follows the forward's
                                    choice.  Same results bit for bit.              */
 #define BAKE_FLAG_ONE_QUEUE 16u /* the ray traversal's persistent waves take their
@@ -167,6 +167,37 @@ int32_t bake_normals_backward(const float *hi_V, int64_t n_hi_v, const int32_t *
                               float max_dist, const float *grad_map, float *grad_lo_V,
                               float *grad_hi_N, void *workspace, size_t workspace_bytes,
                               void *stream);
+
+/* ---- the forward bake without a workspace -------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * forward bake as bake_normals, same arguments minus the workspace, with the
+ * scratch memory taken from a fixed array of BAKE_NOALLOC_BYTES inside the
+ * library's device code, one per GPU, held until the process ends.  The call
+ * allocates no device memory (no hipMalloc / hipFree and no library routine
+ * that allocates device memory; host-side planning uses small host
+ * containers).  Its results are bitwise those of bake_normals on the same
+ * inputs and options.
+ *   - Limit: a bake whose bake_workspace_size exceeds BAKE_NOALLOC_BYTES fails
+ *     with BAKE_E_WORKSPACE before anything is enqueued (128 MiB holds, e.g.,
+ *     a 512^2 atlas over a 327,680-triangle high-poly; use bake_normals for
+ *     larger bakes).
+ *   - opt->flags may not hold BAKE_FLAG_SAVE, BAKE_FLAG_TIMING or
+ *     BAKE_FLAG_COUNT (BAKE_E_INVALID_ARG): the saved state, the counters and
+ *     the status word stay in the shared array, which no other entry point
+ *     can name.  Every stage runs on `stream` (BAKE_FLAG_ONE_STREAM implied).
+ *   - All calls on one GPU share that GPU's array and it keeps the last
+ *     call's contents; each call clears what must start at zero.  Calls that
+ *     overlap on one GPU (other streams, other threads) RACE: serialise them.
+ *   - The first call on a device resolves the array's device address (a
+ *     runtime query, made once per device with that device current).
+ * Bad index data does not fault (as for bake_normals), but the device status
+ * word is not readable from here. */
+#define BAKE_NOALLOC_BYTES (128u << 20)
+int32_t bake_normals_noalloc(const float *hi_V, int64_t n_hi_v, const int32_t *hi_F, int64_t n_hi_f,
+                             const float *hi_N, const float *lo_V, int64_t n_lo_v, const int32_t *lo_F,
+                             int64_t n_lo_f, const float *lo_UV, int32_t res, float max_dist,
+                             float *out_map, int32_t *out_hit, const bake_options *opt, void *stream);
 
 /* ---- hidden-face removal (Sec. 6.2) ------------------------------------ */
 /* Visibility rays from viewpoints around a mesh, then a flood fill that

@@ -95,6 +95,10 @@ _EXPORTS = {
                                  C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                                  C.c_int32, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_size_t, C.c_void_p]),
+    "bake_normals_noalloc": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
+                                         C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
+                                         C.c_int32, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_void_p]),
     "bake_normals_backward": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                                           C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                                           C.c_int32, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -300,6 +304,42 @@ def bake_normals(hi_V, hi_F, hi_N, lo_V, lo_F, lo_UV, res: int, max_dist: float,
     r = BakeResult(out_map, out_hit, rgb, workspace, opts, sizes)
     r.max_dist = float(max_dist)
     return r
+
+
+NOALLOC_BYTES = 128 << 20  # BAKE_NOALLOC_BYTES
+
+
+def bake_normals_noalloc(hi_V, hi_F, hi_N, lo_V, lo_F, lo_UV, res: int, max_dist: float,
+                         out_map: torch.Tensor, out_hit: torch.Tensor, *, dilate_passes: int = 2,
+                         out_rgb8: Optional[torch.Tensor] = None, trav_block: int = 0, trav_stack: int = 0,
+                         trav_mode: int = -1, query: str = "ray", stream=None) -> None:
+    """bake_normals into caller-allocated out_map [res,res,3] f32 and out_hit
+    [res,res] i32 (and optionally out_rgb8 [res,res,3] u8) with no device
+    allocation at all: the library's fixed per-GPU scratch array stands in
+    for the workspace (include/bake.h, bake_normals_noalloc: its size limit,
+    and calls that overlap on one GPU race)."""
+    hi_V = _dev_tensor(hi_V, torch.float32, "hi_V", (3,))
+    hi_F = _dev_tensor(hi_F, torch.int32, "hi_F", (3,))
+    hi_N = _dev_tensor(hi_N, torch.float32, "hi_N", (3,))
+    lo_V = _dev_tensor(lo_V, torch.float32, "lo_V", (3,))
+    lo_F = _dev_tensor(lo_F, torch.int32, "lo_F", (3,))
+    lo_UV = _dev_tensor(lo_UV, torch.float32, "lo_UV", (3, 2))
+    out_map = _dev_tensor(out_map, torch.float32, "out_map")
+    out_hit = _dev_tensor(out_hit, torch.int32, "out_hit")
+    if tuple(out_map.shape) != (res, res, 3) or tuple(out_hit.shape) != (res, res):
+        raise ValueError(f"out_map must be [{res},{res},3] and out_hit [{res},{res}]")
+    if out_rgb8 is not None:
+        out_rgb8 = _dev_tensor(out_rgb8, torch.uint8, "out_rgb8")
+        if tuple(out_rgb8.shape) != (res, res, 3):
+            raise ValueError(f"out_rgb8 must be [{res},{res},3]")
+    if hi_N.shape[0] != hi_V.shape[0] or lo_UV.shape[0] != lo_F.shape[0]:
+        raise ValueError("hi_N / hi_V or lo_UV / lo_F row counts differ")
+    opts = make_options(dilate_passes, False, False, out_rgb8.data_ptr() if out_rgb8 is not None else 0,
+                        trav_block, trav_stack, trav_mode, False, query, True)
+    _check(lib().bake_normals_noalloc(
+        _ptr(hi_V), hi_V.shape[0], _ptr(hi_F), hi_F.shape[0], _ptr(hi_N), _ptr(lo_V), lo_V.shape[0],
+        _ptr(lo_F), lo_F.shape[0], _ptr(lo_UV), int(res), float(max_dist), _ptr(out_map), _ptr(out_hit),
+        C.byref(opts), _stream_handle(stream)))
 
 
 def bake_normals_backward(result: BakeResult, inputs, grad_map, need_lo=True, need_hi=True,

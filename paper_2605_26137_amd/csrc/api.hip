@@ -602,6 +602,36 @@ int32_t read_counter_at(const void* workspace, int32_t asset, int32_t which, voi
     return BAKE_OK;
 }
 
+// ---- the scratch array of bake_normals_noalloc ------------------------------
+// For callers that cannot allocate device memory, the bake's workspace is a
+// fixed array in the library's own device memory, one per GPU (the runtime
+// places it with the code object; it lives until the process ends).  Host
+// code must never use the array's name as a device address: the device
+// address is resolved once per device with hipGetSymbolAddress, with that
+// device current, on the entry point's first call there, and every launch and
+// fill takes that address.  Calls on one GPU share the array: the bake
+// clears what must start at zero (its status block and counters) at the start
+// of every call, and calls that overlap on one GPU race.
+constexpr size_t kNoAllocBytes = (size_t)BAKE_NOALLOC_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+void* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+int32_t noalloc_scratch(void** out) {
+    int dev = -1;
+    HIP_OR_FAIL(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(BAKE_E_UNSUPPORTED, "device %d beyond the %d supported", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIP_OR_FAIL(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || ((uintptr_t)p & 255) != 0) return fail(BAKE_E_HIP, "scratch array address %p unusable", p);
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return BAKE_OK;
+}
+
 // ---- hidden-face removal (Sec. 6.2) ----------------------------------------
 // The workspace of a visibility pass: the batch-of-one plan whose asset has
 // the mesh as its high-poly and no low-poly (its BVH build is the bake's),
@@ -750,6 +780,38 @@ int32_t bake_normals(const float* hi_V, int64_t n_hi_v, const int32_t* hi_F, int
     if ((rc = check_workspace(workspace, workspace_bytes, P.L))) return rc;
     fill_pointers(&a, &P);
     return run_forward(P, o, workspace, (hipStream_t)stream);
+}
+
+int32_t bake_normals_noalloc(const float* hi_V, int64_t n_hi_v, const int32_t* hi_F, int64_t n_hi_f,
+                             const float* hi_N, const float* lo_V, int64_t n_lo_v, const int32_t* lo_F,
+                             int64_t n_lo_f, const float* lo_UV, int32_t res, float max_dist, float* out_map,
+                             int32_t* out_hit, const bake_options* opt, void* stream) {
+    g_err[0] = 0;
+    Opts o;
+    int32_t rc = parse_opts(opt, &o);
+    if (rc) return rc;
+    if (o.flags & (BAKE_FLAG_SAVE | BAKE_FLAG_TIMING | BAKE_FLAG_COUNT))
+        return fail(BAKE_E_INVALID_ARG,
+                    "bake_normals_noalloc takes no BAKE_FLAG_SAVE, BAKE_FLAG_TIMING or BAKE_FLAG_COUNT");
+    o.flags |= BAKE_FLAG_ONE_STREAM;  // the second stream and its events would be created on first use
+    bake_asset a = single_asset(hi_V, n_hi_v, hi_F, n_hi_f, hi_N, lo_V, n_lo_v, lo_F, n_lo_f, lo_UV, res,
+                                max_dist);
+    a.out_map = out_map;
+    a.out_hit = out_hit;
+    a.out_rgb8 = o.rgb8;
+    Plan P;
+    if ((rc = plan_batch(&a, 1, o.flags, &P))) return rc;
+    if ((rc = validate_asset(a, 0))) return rc;
+    if (!out_map || !out_hit) return fail(BAKE_E_INVALID_ARG, "out_map / out_hit is NULL");
+    if (P.L.total > kNoAllocBytes)
+        return fail(BAKE_E_WORKSPACE,
+                    "this bake needs %zu bytes of scratch; bake_normals_noalloc holds %zu (BAKE_NOALLOC_BYTES): "
+                    "use bake_normals with a workspace",
+                    P.L.total, kNoAllocBytes);
+    void* ws = nullptr;
+    if ((rc = noalloc_scratch(&ws))) return rc;
+    fill_pointers(&a, &P);
+    return run_forward(P, o, ws, (hipStream_t)stream);
 }
 
 int32_t bake_normals_backward(const float* hi_V, int64_t n_hi_v, const int32_t* hi_F,

@@ -319,3 +319,21 @@ def test_qem_workspace_size(B):
         B.qem_workspace_size(-1, 5)
     with pytest.raises(B.BakeError):
         B.qem_workspace_size(10, 1 << 28)
+
+
+def _noalloc(B, nhv, nhf, nlv, nlf, res, opt=None):
+    fake = C.c_void_p(0x1000)
+    return B.lib().bake_normals_noalloc(fake, nhv, fake, nhf, fake, fake, nlv, fake, nlf, fake, res,
+                                        C.c_float(0.1), fake, fake, opt, None)
+
+
+def test_noalloc_host_checks(B):
+    """bake_normals_noalloc refuses, before touching the device, a bake larger
+    than its scratch array and the flags whose state it could not hand back."""
+    assert B.NOALLOC_BYTES == 128 << 20
+    assert _noalloc(B, 655362, 1310720, 10242, 20480, 2048) == B.BAKE_E_WORKSPACE
+    assert b"BAKE_NOALLOC_BYTES" in B.lib().bake_last_error()
+    for kw in (dict(save=True), dict(timing=True), dict(count=True)):
+        o = B.make_options(**kw)
+        assert _noalloc(B, 2562, 5120, 42, 80, 128, C.byref(o)) == B.BAKE_E_INVALID_ARG
+    assert _noalloc(B, 2562, 5120, 42, 80, 100) == B.BAKE_E_UNSUPPORTED
