@@ -445,7 +445,12 @@ def bench_batch(B, assets, steps, warmup, trav, log):
         torch.cuda.synchronize()
         return (time.perf_counter() - t) * 1e3 / k
 
+    # the phases below are separated by idle gaps of 50 ms, so a kernel trace
+    # of this run can be cut into them (outside every timed region)
+    torch.cuda.synchronize()
+    time.sleep(0.05)
     seq_ms = timed(seq_step, steps)
+    time.sleep(0.05)
     # the sequential results equal the batch's, bitwise
     same = all(torch.equal(outs[i][0].view(torch.int32), batch.maps[i].view(torch.int32))
                and torch.equal(outs[i][1], batch.hits[i])
@@ -458,7 +463,10 @@ def bench_batch(B, assets, steps, warmup, trav, log):
         batch.backward()
 
     eager_ms = timed(eager, steps)
+    time.sleep(0.05)
     graph = batch.capture()
+    torch.cuda.synchronize()
+    time.sleep(0.05)
     graph_ms = timed(graph.replay, steps)
     log(f"[bench] batch: sequential {seq_ms:.2f} ms, batched eager {eager_ms:.2f} ms, graph {graph_ms:.2f} ms")
     return {"assets": n_assets, "hi_tris": int(sum(a.hi_F.shape[0] for a in assets)),
@@ -493,6 +501,8 @@ def main():
     ap.add_argument("--batch-assets", type=int, default=0, metavar="N",
                     help="also measure an N-asset batch (64 = the uneven batch workload)")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--batch-only", action="store_true",
+                    help="with --batch-assets: measure only the batch (no headline step, no oracle baseline)")
     ap.add_argument("--eager", action="store_true",
                     help="time plain per-step API calls only (default: also record the step into a HIP graph "
                          "and report the replayed step)")
@@ -536,6 +546,11 @@ def main():
         return
     if args.query == "viewmaps":
         print(json.dumps(bench_view_maps(args, B, log)), flush=True)
+        return
+    if args.batch_only and batch_assets:
+        trav = dict(trav_block=args.trav_block, trav_stack=args.trav_stack, trav_mode=args.trav_mode,
+                    one_queue=args.one_queue)
+        print(json.dumps({"batch": bench_batch(B, batch_assets, args.batch_steps, 1, trav, log)}), flush=True)
         return
     asset = make_config(args.config)
     t = B.to_device(asset, dev)

@@ -254,10 +254,13 @@ int32_t make_plan(const Sizes* z, int n, uint32_t flags, Plan* P) {
     L.node_range = take(8 * (size_t)L.t_node);
     L.frontier = take(4 * (size_t)L.t_tl);
     L.treelets = take(16 * (size_t)L.t_tl);
+    L.top = take(8 * (size_t)L.t_tl);
+    L.child = take(4 * (size_t)L.t_node);
     L.spill = take(4 * (size_t)kMaxDepth * (size_t)L.spill_lanes);
     if (L.save) {
         const size_t items = 3 * (size_t)L.t_tex;
-        L.bwd_ray = take(48 * (size_t)L.t_tex);
+        L.bwd_ray = take(36 * (size_t)L.t_tex);
+        L.bwd_hterm = take(32 * (size_t)L.t_tex);
         L.bwd_k0 = take(4 * items);
         L.bwd_v0 = take(4 * items);
         L.bwd_k1 = take(4 * items);

@@ -49,9 +49,17 @@ __device__ __forceinline__ float3 unit_adj(float3 xb, float3 u, float len) {
     return mul3(sub3(xb, mul3(u, dot3(xb, u))), 1.0f / len);
 }
 
-struct RayGrad {  // 48 B per ray
-    float3 pb, mb, tfb, hb;
+struct RayGrad {  // 36 B per ray: what the low-poly chain needs
+    float3 pb, mb, tfb;
 };
+
+// What the high-poly sums need of a ray, in one 32-B record: h_bar and the
+// hit weights beta1, beta2 (beta0 = 1 - beta1 - beta2).
+struct alignas(16) HiTerm {
+    float4 a;  // h_bar.xyz, beta1
+    float4 b;  // beta2, -, -, -
+};
+static_assert(sizeof(HiTerm) == 32, "HiTerm is 32 B");
 
 // The (asset, 64-ray batch) item q: the asset and the wave's global ray
 // (invalid when past the asset's rays).
@@ -80,8 +88,8 @@ __global__ __launch_bounds__(256) void bwd_ray_kernel(Batch B, const Ray* __rest
                                                       const Hit* __restrict__ hits,
                                                       const float4* __restrict__ lo_n_all,
                                                       const float4* __restrict__ face_t_all,
-                                                      RayGrad* __restrict__ rg, uint32_t* __restrict__ keys,
-                                                      uint32_t* __restrict__ vals) {
+                                                      RayGrad* __restrict__ rg, HiTerm* __restrict__ ht,
+                                                      uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
     if (!sealed(B)) return;
     const int lane = threadIdx.x & 63;
     const uint32_t nb = B.rb_pf[B.n];
@@ -96,7 +104,10 @@ __global__ __launch_bounds__(256) void bwd_ray_kernel(Batch B, const Ray* __rest
         const Ray ray = rays[r];
         const Hit hit = hits[r];
         RayGrad g;
-        g.pb = g.mb = g.tfb = g.hb = f3(0.f, 0.f, 0.f);
+        g.pb = g.mb = g.tfb = f3(0.f, 0.f, 0.f);
+        HiTerm term;
+        term.a = make_float4(0.f, 0.f, 0.f, 0.f);
+        term.b = make_float4(0.f, 0.f, 0.f, 0.f);
         uint32_t kv[3] = {(uint32_t)nhv, (uint32_t)nhv, (uint32_t)nhv};
         const float* grad_map = B.G[it.a].grad_map;  // NULL: the asset wants no gradient
         if (hit.id >= 0 && grad_map) {
@@ -153,12 +164,14 @@ __global__ __launch_bounds__(256) void bwd_ray_kernel(Batch B, const Ray* __rest
             g.pb = w;
             g.mb = unit_adj(db, d, lm);
             g.tfb = Tfb;
-            g.hb = hb;
+            term.a = make_float4(hb.x, hb.y, hb.z, be1);
+            term.b = make_float4(be2, 0.f, 0.f, 0.f);
             kv[0] = (uint32_t)j0;
             kv[1] = (uint32_t)j1;
             kv[2] = (uint32_t)j2;
         }
         rg[r] = g;
+        ht[r] = term;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             keys[3 * r + k] = kv[k];
@@ -335,13 +348,13 @@ __global__ __launch_bounds__(256) void zero_grad_hi_kernel(Batch B) {
 
 // The term of sorted pair j: the hit's barycentric weight of corner k times
 // the ray's adjoint of the interpolated high-poly normal (item = 3 ray + k).
-__device__ __forceinline__ float3 hiN_term(const uint32_t* __restrict__ vals, const Hit* __restrict__ hits,
-                                           const RayGrad* __restrict__ rg, int64_t j) {
+__device__ __forceinline__ float3 hiN_term(const uint32_t* __restrict__ vals, const HiTerm* __restrict__ ht,
+                                           int64_t j) {
     const uint32_t item = vals[j];
     const uint32_t r = item / 3, k = item - 3 * r;
-    const Hit h = hits[r];
-    const float beta = k == 0 ? 1.0f - h.beta1 - h.beta2 : (k == 1 ? h.beta1 : h.beta2);
-    return mul3(rg[r].hb, beta);
+    const HiTerm h = ht[r];
+    const float beta = k == 0 ? 1.0f - h.a.w - h.b.x : (k == 1 ? h.a.w : h.b.x);
+    return mul3(f3(h.a.x, h.a.y, h.a.z), beta);
 }
 
 // Sorted (vertex, item) pairs of an asset, 64 at a time per wave: each lane
@@ -353,8 +366,7 @@ __device__ __forceinline__ float3 hiN_term(const uint32_t* __restrict__ vals, co
 // (asset, 64-ray batch) items: 192 pairs each.
 __global__ __launch_bounds__(256) void bwd_hiN_kernel(Batch B, const uint32_t* __restrict__ keys,
                                                       const uint32_t* __restrict__ vals,
-                                                      const Hit* __restrict__ hits,
-                                                      const RayGrad* __restrict__ rg) {
+                                                      const HiTerm* __restrict__ ht) {
     if (!sealed(B)) return;
     const int lane = threadIdx.x & 63;
     const uint32_t nb = B.rb_pf[B.n];
@@ -378,7 +390,7 @@ __global__ __launch_bounds__(256) void bwd_hiN_kernel(Batch B, const uint32_t* _
             const int64_t i = i0 + lane;
             const bool in = i < hi;  // false for every lane past the batch's pairs
             keyv[k3] = in ? keys[i] : 0xFFFFFFFFu;  // past the end: a run of its own
-            gv[k3] = in ? hiN_term(vals, hits, rg, i) : f3(0.f, 0.f, 0.f);
+            gv[k3] = in ? hiN_term(vals, ht, i) : f3(0.f, 0.f, 0.f);
             contv[k3] = i0 < hi && i0 > lo && keys[i0 - 1] == keys[i0];
         }
         for (int k3 = 0; k3 < 3; ++k3) {
@@ -410,7 +422,7 @@ __global__ __launch_bounds__(256) void bwd_hiN_kernel(Batch B, const uint32_t* _
             if (!in || key >= nhv || !run_end) continue;
             if (lane < first_change && cont_in) continue;  // an earlier wave's run
             if (lane == 63) {
-                for (int64_t j = i0 + 64; j < hi && keys[j] == key; ++j) g = add3(g, hiN_term(vals, hits, rg, j));
+                for (int64_t j = i0 + 64; j < hi && keys[j] == key; ++j) g = add3(g, hiN_term(vals, ht, j));
             }
             st3(grad_hi_N, key, g);
         }
@@ -469,6 +481,7 @@ hipError_t launch_backward(const BatchHost& H, bool any_lo, bool any_hi, hipStre
     const Ray* rays = (const Ray*)(ws + L.rays);
     const Hit* hits = (const Hit*)(ws + L.hits);
     RayGrad* rg = (RayGrad*)(ws + L.bwd_ray);
+    HiTerm* ht = (HiTerm*)(ws + L.bwd_hterm);
     // persistent waves over the (asset, 64-ray batch) items: enough for the
     // largest possible ray count, capped
     int64_t cap_batches = 0;
@@ -476,7 +489,7 @@ hipError_t launch_backward(const BatchHost& H, bool any_lo, bool any_hi, hipStre
     const unsigned ray_grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((cap_batches + 3) / 4, 4096));
     if (L.t_tex > 0) {
         hipLaunchKernelGGL(bwd_ray_kernel, dim3(ray_grid), dim3(256), 0, s, H.dev, rays, hits,
-                           (const float4*)(ws + L.lo_n), (const float4*)(ws + L.face_t), rg,
+                           (const float4*)(ws + L.lo_n), (const float4*)(ws + L.face_t), rg, ht,
                            (uint32_t*)(ws + L.bwd_k0), (uint32_t*)(ws + L.bwd_v0));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
@@ -535,7 +548,7 @@ hipError_t launch_backward(const BatchHost& H, bool any_lo, bool any_hi, hipStre
             if (beside && (e = hipStreamWaitEvent(s, join, 0)) != hipSuccess) return e;
             hipLaunchKernelGGL(bwd_hiN_kernel, dim3(ray_grid), dim3(256), 0, s, H.dev,
                                (const uint32_t*)(ws + (in1 ? L.bwd_k1 : L.bwd_k0)),
-                               (const uint32_t*)(ws + (in1 ? L.bwd_v1 : L.bwd_v0)), hits, (const RayGrad*)rg);
+                               (const uint32_t*)(ws + (in1 ? L.bwd_v1 : L.bwd_v0)), (const HiTerm*)ht);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
     }

@@ -166,6 +166,7 @@ constexpr int kCntTriLo = 4;     // u64 triangle tests (FLAG_COUNT), slots 4-5
 constexpr int kCntFrontier = 6;  // refit frontier length
 constexpr int kCntTreelets = 7;  // refit treelets
 constexpr int kCntIterLo = 8;    // u64 traversal loop trips of whole waves (FLAG_COUNT), slots 8-9
+constexpr int kCntTop = 10;      // refit top nodes (internal nodes above the treelets)
 constexpr int kCntSlots = 16;
 // Batch counter slots.
 constexpr int kGcQueue = 0;  // traversal work queue head
@@ -231,10 +232,11 @@ struct Layout {
     size_t rays, hits;                            // per ray
     size_t bounds_part, bounds;                   // centroid bounds: per sort tile, per asset
     size_t keys0, keys1, vals0, vals1, hist, sup; // radix sort of the BVH keys
-    size_t nodes, nodes_c, leaves, node_parent, leaf_parent, refit_cnt, node_range, frontier, treelets;
+    size_t nodes, nodes_c, leaves, node_parent, leaf_parent, refit_cnt, node_range, frontier, treelets, top, child;
     size_t spill;                                 // traversal stack spill
     // backward scratch (BAKE_FLAG_SAVE only)
-    size_t bwd_ray, bwd_k0, bwd_v0, bwd_k1, bwd_v1, bwd_hist, bwd_sup, bwd_face1, bwd_face2, bwd_sbar, bwd_vbar;
+    size_t bwd_ray, bwd_hterm, bwd_k0, bwd_v0, bwd_k1, bwd_v1, bwd_hist, bwd_sup, bwd_face1, bwd_face2, bwd_sbar,
+        bwd_vbar;
     size_t total;
     // batch totals
     int n;

@@ -418,49 +418,119 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(Batch Bt, con
 // 4. Karras hierarchy
 // ---------------------------------------------------------------------------
 
-// Common-prefix length of sorted keys i and j, extended by the indices on
-// equal keys; -1 outside [0, n).
-__device__ __forceinline__ int cprefix(const uint32_t* __restrict__ k, int64_t n, int64_t i,
-                                       int64_t j) {
-    if (j < 0 || j >= n) return -1;
-    uint32_t a = k[i], b = k[j];
-    if (a == b) return 32 + __clz((uint32_t)i ^ (uint32_t)j);
-    return __clz(a ^ b);
+// Per-thread search reach: a node's range and split are searched by its own
+// thread in the wave's LDS window of sorted keys when the range spans at most
+// kKarrasReach keys; longer ranges (the few nodes near the top) are searched
+// by the whole wave together, 64 probes per step.
+constexpr int kKarrasReach = 64;
+
+// The largest x in [lo, hi) with pred(x), given pred(lo) and not pred(hi)
+// (pred monotone: true up to some point, false after it); the wave searches
+// 64 candidates per step.  Wave-uniform arguments.
+template <typename Pred>
+__device__ __forceinline__ int64_t wave_last_true(int64_t lo, int64_t hi, int lane, Pred pred) {
+    while (hi - lo > 1) {
+        const int64_t step = (hi - lo + 63) / 64;
+        const int64_t x = lo + (int64_t)lane * step;
+        const bool ok = lane > 0 && x < hi && pred(x);
+        const uint64_t m = __ballot(ok) | 1ull;
+        const int last = 63 - __clzll((long long)m);
+        lo += (int64_t)last * step;
+        hi = min(hi, lo + step);
+    }
+    return lo;
 }
 
 __global__ __launch_bounds__(kBlock) void karras_kernel(Batch Bt, const uint32_t* __restrict__ keys_all,
-                                                        BvhNodeC* __restrict__ nodes_all,
+                                                        uint32_t* __restrict__ child_all,
                                                         int32_t* __restrict__ np_all,
                                                         int32_t* __restrict__ lp_all,
                                                         int2* __restrict__ range_all) {
+    // each wave's window: keys [i0 - 64, i0 + 128) around its nodes [i0, i0 + 64)
+    __shared__ uint32_t s_win[kBlock / 64][3 * 64];
     int64_t lb;
     const AssetDev& As = Bt.A[block_asset(Bt, kGNode, blockIdx.x, &lb)];
     const int64_t n = As.nhf;
-    const int64_t i = lb * kBlock + threadIdx.x;
-    if (i >= n - 1) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t i0 = lb * kBlock + wave * 64;
+    const int64_t i = i0 + lane;
     const uint32_t* __restrict__ keys = keys_all + As.hf;
-    BvhNodeC* __restrict__ nodes = nodes_all + As.node;
+    uint32_t* win = s_win[wave];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const int64_t q = i0 - 64 + 64 * r + lane;
+        if (q >= 0 && q < n) win[64 * r + lane] = keys[q];
+    }
+    __syncthreads();
+    if (i0 >= n - 1) return;  // the whole wave is past the asset's nodes
+    // common-prefix length of keys a and b (b within the window of a's wave;
+    // extended by the indices on equal keys), -1 outside [0, n)
+    auto cpw = [&](int64_t a, int64_t b) -> int {
+        if (b < 0 || b >= n) return -1;
+        const uint32_t x = win[a - i0 + 64], y = win[b - i0 + 64];
+        return x == y ? 32 + __clz((uint32_t)a ^ (uint32_t)b) : __clz(x ^ y);
+    };
+    const bool live = i < n - 1;
+    int d = 1, dmin = 0, dnode = 0;
+    int64_t l = 0, sp = 0;
+    bool big = false;
+    if (live) {
+        d = (cpw(i, i + 1) - cpw(i, i - 1)) >= 0 ? 1 : -1;
+        dmin = cpw(i, i - d);
+        int64_t lmax = 2;
+        while (lmax <= kKarrasReach && cpw(i, i + lmax * d) > dmin) lmax <<= 1;
+        if (lmax > kKarrasReach) {
+            big = true;
+        } else {
+            for (int64_t t = lmax >> 1; t >= 1; t >>= 1)
+                if (cpw(i, i + (l + t) * d) > dmin) l += t;
+            dnode = cpw(i, i + l * d);
+            int64_t t = l;
+            do {
+                t = (t + 1) >> 1;
+                if (cpw(i, i + (sp + t) * d) > dnode) sp += t;
+            } while (t > 1);
+        }
+    }
+    // the wave's long ranges, one at a time: range end by probing the powers
+    // of two, then 64-way refinement; the split likewise
+    uint64_t bm = __ballot(big);
+    while (bm) {
+        const int src = __ffsll((long long)bm) - 1;
+        bm &= bm - 1;
+        const int64_t bi = __shfl(i, src, 64);
+        const int bd = __shfl(d, src, 64), bdmin = __shfl(dmin, src, 64);
+        const uint32_t kb = keys[bi];
+        auto cpg = [&](int64_t b) -> int {
+            if (b < 0 || b >= n) return -1;
+            const uint32_t y = keys[b];
+            return kb == y ? 32 + __clz((uint32_t)bi ^ (uint32_t)b) : __clz(kb ^ y);
+        };
+        // 2^k for k <= 6 is known to lie in the range (the per-thread search
+        // found 64 in it); lanes 7..40 probe 2^lane
+        const bool okp = lane > 6 && lane <= 40 && cpg(bi + ((int64_t)1 << lane) * bd) > bdmin;
+        const uint64_t m = __ballot(okp) | 0x7Full;
+        const int K = 63 - __clzll((long long)m);
+        const int64_t L = wave_last_true((int64_t)1 << K, (int64_t)1 << (K + 1), lane,
+                                         [&](int64_t x) { return cpg(bi + x * bd) > bdmin; });
+        const int bdnode = cpg(bi + L * bd);
+        const int64_t S = wave_last_true(0, L, lane, [&](int64_t x) { return cpg(bi + x * bd) > bdnode; });
+        if (lane == src) {
+            l = L;
+            dnode = bdnode;
+            sp = S;
+        }
+    }
+    if (!live) return;
     int32_t* __restrict__ node_parent = np_all + As.node;
     int32_t* __restrict__ leaf_parent = lp_all + As.hf;
-    int d = (cprefix(keys, n, i, i + 1) - cprefix(keys, n, i, i - 1)) >= 0 ? 1 : -1;
-    int dmin = cprefix(keys, n, i, i - d);
-    int64_t lmax = 2;
-    while (cprefix(keys, n, i, i + lmax * d) > dmin) lmax <<= 1;
-    int64_t l = 0;
-    for (int64_t t = lmax >> 1; t >= 1; t >>= 1)
-        if (cprefix(keys, n, i, i + (l + t) * d) > dmin) l += t;
-    int64_t j = i + l * d;
-    int dnode = cprefix(keys, n, i, j);
-    int64_t s = 0, t = l;
-    do {
-        t = (t + 1) >> 1;
-        if (cprefix(keys, n, i, i + (s + t) * d) > dnode) s += t;
-    } while (t > 1);
-    int64_t gamma = i + s * d + (d < 0 ? -1 : 0);
-    int64_t lo = i < j ? i : j, hi = i < j ? j : i;
-    int32_t left = lo == gamma ? ~(int32_t)gamma : (int32_t)gamma;
-    int32_t right = hi == gamma + 1 ? ~(int32_t)(gamma + 1) : (int32_t)(gamma + 1);
-    nodes[i].q.w = (uint32_t)gamma | (left < 0 ? kChildLeafL : 0u) | (right < 0 ? kChildLeafR : 0u);
+    const int64_t j = i + l * d;
+    (void)dnode;
+    const int64_t gamma = i + sp * d + (d < 0 ? -1 : 0);
+    const int64_t lo = i < j ? i : j, hi = i < j ? j : i;
+    const int32_t left = lo == gamma ? ~(int32_t)gamma : (int32_t)gamma;
+    const int32_t right = hi == gamma + 1 ? ~(int32_t)(gamma + 1) : (int32_t)(gamma + 1);
+    child_all[As.node + i] = (uint32_t)gamma | (left < 0 ? kChildLeafL : 0u) | (right < 0 ? kChildLeafR : 0u);
     range_all[As.node + i] = make_int2((int32_t)lo, (int32_t)hi);
     if (left < 0) leaf_parent[gamma] = (int32_t)(i << 1);
     else node_parent[gamma] = (int32_t)(i << 1);
@@ -543,9 +613,9 @@ __device__ __forceinline__ uint32_t quantise_axis(float lL, float hL, float lR, 
     return e;
 }
 
-// Writes the frame and child planes of node p (its child word is the
-// hierarchy kernel's).
-__device__ __forceinline__ void write_compressed(BvhNodeC* node, const float L[6], const float R[6]) {
+// Writes node p whole: its frame, child planes and child word (the
+// hierarchy kernel's), two 16-B stores.
+__device__ __forceinline__ void write_compressed(BvhNodeC* node, uint32_t child, const float L[6], const float R[6]) {
     float o[3];
     uint32_t q[3][4], e[3];
 #pragma unroll
@@ -557,10 +627,7 @@ __device__ __forceinline__ void write_compressed(BvhNodeC* node, const float L[6
 #pragma unroll
     for (int i = 0; i < 3; ++i) w[i] = b[4 * i] | (b[4 * i + 1] << 8) | (b[4 * i + 2] << 16) | (b[4 * i + 3] << 24);
     node->a = make_float4(o[0], o[1], o[2], __uint_as_float(e[0] | (e[1] << 8) | (e[2] << 16)));
-    uint32_t* qw = reinterpret_cast<uint32_t*>(&node->q);
-    qw[0] = w[0];
-    qw[1] = w[1];
-    qw[2] = w[2];
+    node->q = make_uint4(w[0], w[1], w[2], child);
 }
 
 __global__ __launch_bounds__(kBlock) void leaf_pack_kernel(Batch Bt, const uint32_t* __restrict__ sorted_idx,
@@ -601,41 +668,76 @@ __device__ __forceinline__ void leaf_box(const Leaf& L, float box[6]) {
 // Treelet roots: nodes (internal i < n-1, or leaf ~k) of at most kTreelet
 // leaves whose parent has more (or that are the root).  Entries are
 // asset-local (ref, lo, hi, parent link).
+// Also lists the top nodes (internal nodes of more than kTreelet leaves: the
+// nodes above the treelets) with their parent links, for refit_top_kernel.
+// Appends, for every lane with want set, one slot of the per-asset list whose
+// length counter is *counter: one atomic per wave (the wave's asset is
+// uniform), slots in lane order.  Returns the lane's slot.
+__device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool want) {
+    const uint64_t m = __ballot(want);
+    if (m == 0) return 0;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)m) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
+    base = __shfl(base, leader, 64);
+    return base + (uint32_t)__popcll(m & __lanemask_lt());
+}
+
+// Also lists the top nodes (internal nodes of more than kTreelet leaves: the
+// nodes above the treelets) with their parent links, for refit_top_kernel,
+// and clears the arrival counters its fallback path uses.
 __global__ __launch_bounds__(kBlock) void treelet_find_kernel(Batch Bt, const int2* __restrict__ range_all,
                                                               const int32_t* __restrict__ np_all,
                                                               const int32_t* __restrict__ lp_all,
-                                                              int4* __restrict__ list_all) {
+                                                              int4* __restrict__ list_all,
+                                                              int2* __restrict__ top_all,
+                                                              uint32_t* __restrict__ cnt_all) {
     int64_t lb;
     const int a = block_asset(Bt, kGAllNode, blockIdx.x, &lb);
     const AssetDev& As = Bt.A[a];
     const int64_t n = As.nhf;
     const int64_t x = lb * kBlock + threadIdx.x;
-    if (x >= 2 * n - 1) return;
+    const bool valid = x < 2 * n - 1;
     const int2* __restrict__ node_range = range_all + As.node;
-    int32_t ref, lo, hi, pp;
-    if (x < n - 1) {
+    int32_t ref = 0, lo = 0, hi = -1, pp = -1;
+    if (valid && x < n - 1) {
         int2 r = node_range[x];
         ref = (int32_t)x; lo = r.x; hi = r.y;
         pp = np_all[As.node + x];
-    } else {
+        cnt_all[As.node + x] = 0u;
+    } else if (valid) {
         int32_t k = (int32_t)(x - (n - 1));
         ref = ~k; lo = hi = k;
         pp = n > 1 ? lp_all[As.hf + k] : -1;
     }
-    if (hi - lo + 1 > kTreelet) return;
-    if (pp >= 0) {
-        int2 pr = node_range[pp >> 1];
-        if (pr.y - pr.x + 1 <= kTreelet) return;
+    const bool big = valid && hi - lo + 1 > kTreelet;
+    bool root = false;
+    if (valid && !big) {
+        root = true;
+        if (pp >= 0) {
+            int2 pr = node_range[pp >> 1];
+            root = pr.y - pr.x + 1 > kTreelet;
+        }
     }
-    uint32_t e = atomicAdd(&Bt.cnt[(int64_t)a * kCntSlots + kCntTreelets], 1u);
-    if (e < (uint32_t)treelet_cap(n)) list_all[As.tl + e] = make_int4(ref, lo, hi, pp);
-    else set_status(Bt, kStInternal);
+    const uint32_t cap = (uint32_t)treelet_cap(n);
+    const uint32_t et = wave_append(&Bt.cnt[(int64_t)a * kCntSlots + kCntTop], big);
+    if (big) {
+        if (et < cap) top_all[As.tl + et] = make_int2(ref, pp);
+        else set_status(Bt, kStInternal);
+    }
+    const uint32_t e = wave_append(&Bt.cnt[(int64_t)a * kCntSlots + kCntTreelets], root);
+    if (root) {
+        if (e < cap) list_all[As.tl + e] = make_int4(ref, lo, hi, pp);
+        else set_status(Bt, kStInternal);
+    }
 }
 
 // Workgroups take the batch's treelets in turn (the treelet prefix over the
 // assets is known on the device only).
 __global__ __launch_bounds__(kRefitBlock) void treelet_refit_kernel(
     Batch Bt, const Leaf* __restrict__ leaves_all, BvhNode* nodes_all, BvhNodeC* __restrict__ nodes_c_all,
+    const uint32_t* __restrict__ child_all,
     const int32_t* __restrict__ np_all,
     const int32_t* __restrict__ lp_all, const int4* __restrict__ list_all, int32_t* __restrict__ frontier_all) {
     __shared__ int32_t s_np[kTreelet];      // parent link of internal node lo + i
@@ -650,6 +752,7 @@ __global__ __launch_bounds__(kRefitBlock) void treelet_refit_kernel(
         const Leaf* __restrict__ leaves = leaves_all + As.hf;
         BvhNode* nodes = nodes_all + As.node;
         BvhNodeC* __restrict__ nodes_c = nodes_c_all + As.node;
+        const uint32_t* __restrict__ child = child_all + As.node;
         const int32_t* __restrict__ node_parent = np_all + As.node;
         const int32_t* __restrict__ leaf_parent = lp_all + As.hf;
         uint32_t* nfront = &Bt.cnt[(int64_t)a * kCntSlots + kCntFrontier];
@@ -712,7 +815,7 @@ __global__ __launch_bounds__(kRefitBlock) void treelet_refit_kernel(
         // the treelet's internal nodes (both children arrived) from their LDS
         // slots, in parallel
         for (int i = threadIdx.x; i < sz; i += kRefitBlock)
-            if (s_cnt[i] == 2u) write_compressed(&nodes_c[lo + i], s_box[i][0], s_box[i][1]);
+            if (s_cnt[i] == 2u) write_compressed(&nodes_c[lo + i], child[lo + i], s_box[i][0], s_box[i][1]);
         __syncthreads();
     }
 }
@@ -720,26 +823,149 @@ __global__ __launch_bounds__(kRefitBlock) void treelet_refit_kernel(
 // Top pass: one workgroup per asset climbs from its frontier through the nodes
 // above the treelets.  Each frontier entry says: child `side` of node p is
 // complete and its box is in p's slot.
+//
+// When the asset has at most kTopLds top nodes, the climb runs in LDS: the
+// top nodes (listed by treelet_find_kernel) get LDS slots through an LDS
+// hash of their indices, each learns its parent's slot, the frontier's boxes
+// are copied into their parents' LDS box slots, and the climb's arrival
+// counters, parent links and boxes are LDS accesses only.  Otherwise the
+// nodes' global box slots and counters serve.
+constexpr int kTopLds = 2048;
+constexpr int kTopHash = 4096;  // open addressing, linear probing (load <= 1/2)
+
+__device__ __forceinline__ uint32_t top_hash(int32_t p) { return ((uint32_t)p * 2654435761u) >> 20; }
+
+__device__ __forceinline__ int top_slot(const int32_t* hkey, const int16_t* hval, int32_t p) {
+    uint32_t h = top_hash(p) & (kTopHash - 1);
+    for (int probe = 0; probe < kTopHash; ++probe) {
+        const int32_t k = hkey[h];
+        if (k == p) return hval[h];
+        if (k == -1) return -1;
+        h = (h + 1) & (kTopHash - 1);
+    }
+    return -1;
+}
+
+struct TopLds {
+    int32_t hkey[kTopHash];
+    int16_t hval[kTopHash];
+    int32_t node[kTopLds];      // top node of slot e
+    int32_t up[kTopLds];        // parent slot link (slot << 1 | side), -1 at the root
+    uint32_t cnt[kTopLds];      // arrivals
+    float box[kTopLds][2][6];   // child boxes, by side
+};
+
+__device__ void refit_top_lds(Batch Bt, const AssetDev& As, BvhNode* nodes, BvhNodeC* __restrict__ nodes_c,
+                              const uint32_t* __restrict__ child, const int32_t* __restrict__ frontier, uint32_t nf,
+                              const int2* __restrict__ top, uint32_t nt, TopLds& S) {
+    int32_t* s_hkey = S.hkey;
+    int16_t* s_hval = S.hval;
+    int32_t* s_node = S.node;
+    int32_t* s_up = S.up;
+    uint32_t* s_cnt = S.cnt;
+    float(*s_box)[2][6] = S.box;
+    const int tid = threadIdx.x;
+    for (int h = tid; h < kTopHash; h += kTopBlock) s_hkey[h] = -1;
+    __syncthreads();
+    for (uint32_t e = tid; e < nt; e += kTopBlock) {
+        const int2 t = top[e];
+        s_node[e] = t.x;
+        s_cnt[e] = 0;
+        uint32_t h = top_hash(t.x) & (kTopHash - 1);
+        for (int probe = 0; probe < kTopHash; ++probe) {
+            if (atomicCAS(&s_hkey[h], -1, t.x) == -1) {
+                s_hval[h] = (int16_t)e;
+                break;
+            }
+            h = (h + 1) & (kTopHash - 1);
+        }
+    }
+    __syncthreads();
+    for (uint32_t e = tid; e < nt; e += kTopBlock) {
+        const int32_t pp = top[e].y;
+        int32_t up = -1;
+        if (pp >= 0) {
+            const int ps = top_slot(s_hkey, s_hval, pp >> 1);
+            if (ps < 0) set_status(Bt, kStInternal);  // a top node's parent is a top node
+            else up = (ps << 1) | (pp & 1);
+        }
+        s_up[e] = up;
+    }
+    // the treelet roots' boxes, from their parents' global slots
+    for (uint32_t f = tid; f < nf; f += kTopBlock) {
+        const int32_t pp = frontier[f];
+        const int ps = top_slot(s_hkey, s_hval, pp >> 1);
+        if (ps < 0) {
+            set_status(Bt, kStInternal);
+            continue;
+        }
+        const float* g = reinterpret_cast<const float*>(&nodes[pp >> 1]) + 6 * (pp & 1);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) s_box[ps][pp & 1][q] = g[q];
+    }
+    __syncthreads();
+    for (uint32_t f = tid; f < nf; f += kTopBlock) {
+        const int32_t pp0 = frontier[f];
+        int e = top_slot(s_hkey, s_hval, pp0 >> 1);
+        for (int level = 0; e >= 0; ++level) {
+            if (level > 2 * kMaxDepth) {  // only a malformed hierarchy gets here
+                set_status(Bt, kStInternal);
+                break;
+            }
+            const uint32_t old = __hip_atomic_fetch_add(&s_cnt[e], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (old == 0) break;
+            float box[6];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) box[q] = fminf(s_box[e][0][q], s_box[e][1][q]);
+#pragma unroll
+            for (int q = 3; q < 6; ++q) box[q] = fmaxf(s_box[e][0][q], s_box[e][1][q]);
+            const int32_t up = s_up[e];
+            if (up < 0) break;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) s_box[up >> 1][up & 1][q] = box[q];
+            e = up >> 1;
+        }
+    }
+    __syncthreads();
+    for (uint32_t e = tid; e < nt; e += kTopBlock) {
+        if (s_cnt[e] == 2u) write_compressed(&nodes_c[s_node[e]], child[s_node[e]], s_box[e][0], s_box[e][1]);
+        else set_status(Bt, kStInternal);
+    }
+}
+
 __global__ __launch_bounds__(kTopBlock) void refit_top_kernel(Batch Bt, BvhNode* nodes_all,
                                                              BvhNodeC* __restrict__ nodes_c_all,
+                                                             const uint32_t* __restrict__ child_all,
                                                              const int32_t* __restrict__ np_all,
                                                              const int32_t* __restrict__ frontier_all,
+                                                             const int2* __restrict__ top_all,
                                                              uint32_t* cnt_all) {
-    // nodes completed by the climb, compressed in parallel after it (beyond
-    // the list's capacity a node is compressed where it completes)
-    __shared__ int32_t s_done[kTopList];
+    // global path: nodes completed by the climb, compressed in parallel after
+    // it (beyond the list's capacity a node is compressed where it completes)
+    union TopMem {
+        TopLds lds;
+        int32_t done[kTopList];
+    };
+    __shared__ TopMem s_mem;
     __shared__ uint32_t s_ndone;
+    int32_t* s_done = s_mem.done;
     const int a = blockIdx.x;
     const AssetDev& As = Bt.A[a];
     if (As.nhf <= 1) return;
-    if (threadIdx.x == 0) s_ndone = 0;
-    __syncthreads();
     BvhNode* nodes = nodes_all + As.node;
     BvhNodeC* __restrict__ nodes_c = nodes_c_all + As.node;
+    const uint32_t* __restrict__ child = child_all + As.node;
     const int32_t* __restrict__ node_parent = np_all + As.node;
     const int32_t* __restrict__ frontier = frontier_all + As.tl;
     uint32_t* cnt = cnt_all + As.node;
     const uint32_t m = min(Bt.cnt[(int64_t)a * kCntSlots + kCntFrontier], (uint32_t)treelet_cap(As.nhf));
+    const uint32_t nt = Bt.cnt[(int64_t)a * kCntSlots + kCntTop];
+    if (nt > 0 && nt <= min((uint32_t)kTopLds, (uint32_t)treelet_cap(As.nhf))) {
+        refit_top_lds(Bt, As, nodes, nodes_c, child, frontier, m, top_all + As.tl, nt, s_mem.lds);
+        return;
+    }
+    if (threadIdx.x == 0) s_ndone = 0;
+    __syncthreads();
     for (uint32_t e = threadIdx.x; e < m; e += kTopBlock) {
         int32_t pp = frontier[e];
         for (int level = 0; pp >= 0; ++level) {
@@ -760,7 +986,7 @@ __global__ __launch_bounds__(kTopBlock) void refit_top_kernel(Batch Bt, BvhNode*
             }
             const uint32_t slot = atomicAdd(&s_ndone, 1u);
             if (slot < (uint32_t)kTopList) s_done[slot] = p;
-            else write_compressed(&nodes_c[p], bl, br);
+            else write_compressed(&nodes_c[p], child[p], bl, br);
 #pragma unroll
             for (int q = 0; q < 3; ++q) box[q] = fminf(bl[q], br[q]);
 #pragma unroll
@@ -780,7 +1006,7 @@ __global__ __launch_bounds__(kTopBlock) void refit_top_kernel(Batch Bt, BvhNode*
             bl[q] = f[q];
             br[q] = f[6 + q];
         }
-        write_compressed(&nodes_c[p], bl, br);
+        write_compressed(&nodes_c[p], child[p], bl, br);
     }
 }
 
@@ -849,6 +1075,8 @@ hipError_t launch_bvh_build(const BatchHost& H, hipStream_t s) {
     int2* range = (int2*)(ws + L.node_range);
     int32_t* frontier = (int32_t*)(ws + L.frontier);
     int4* tlist = (int4*)(ws + L.treelets);
+    int2* top = (int2*)(ws + L.top);
+    uint32_t* child = (uint32_t*)(ws + L.child);
 
     hipLaunchKernelGGL(bounds_part_kernel, dim3((unsigned)(H.blocks(kGSort) * kBoundsSplit)), dim3(kBlock), 0, s,
                        H.dev, part);
@@ -863,13 +1091,12 @@ hipError_t launch_bvh_build(const BatchHost& H, hipStream_t s) {
     // 30-bit keys take four 8-bit passes: the sorted arrays are back in keys0 / vals0
     if (H.blocks(kGNode) > 0) {
         hipLaunchKernelGGL(karras_kernel, dim3((unsigned)H.blocks(kGNode)), dim3(kBlock), 0, s, H.dev,
-                           (const uint32_t*)k0, nodes_c, np, lp, range);
-        if ((e = fill_u32(cnt, 0, L.t_node, s)) != hipSuccess) return e;
+                           (const uint32_t*)k0, child, np, lp, range);
     }
     hipLaunchKernelGGL(leaf_pack_kernel, dim3((unsigned)H.blocks(kGHiF)), dim3(kBlock), 0, s, H.dev,
                        (const uint32_t*)v0, leaves);
     hipLaunchKernelGGL(treelet_find_kernel, dim3((unsigned)H.blocks(kGAllNode)), dim3(kBlock), 0, s, H.dev,
-                       (const int2*)range, (const int32_t*)np, (const int32_t*)lp, tlist);
+                       (const int2*)range, (const int32_t*)np, (const int32_t*)lp, tlist, top, cnt);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (L.t_node > 0) {
         if ((e = launch_treelet_space(H, s)) != hipSuccess) return e;
@@ -879,10 +1106,12 @@ hipError_t launch_bvh_build(const BatchHost& H, hipStream_t s) {
         for (int a = 0; a < L.n; ++a) grid += H.A[a].nhf / (kTreelet / 2) + 1;
         grid = std::min<int64_t>(grid, 2048);
         hipLaunchKernelGGL(treelet_refit_kernel, dim3((unsigned)grid), dim3(kRefitBlock), 0, s, H.dev,
-                           (const Leaf*)leaves, nodes, nodes_c, (const int32_t*)np, (const int32_t*)lp,
+                           (const Leaf*)leaves, nodes, nodes_c, (const uint32_t*)child, (const int32_t*)np,
+                           (const int32_t*)lp,
                            (const int4*)tlist, frontier);
         hipLaunchKernelGGL(refit_top_kernel, dim3((unsigned)L.n), dim3(kTopBlock), 0, s, H.dev, nodes, nodes_c,
-                           (const int32_t*)np, (const int32_t*)frontier, cnt);
+                           (const uint32_t*)child, (const int32_t*)np, (const int32_t*)frontier, (const int2*)top,
+                           cnt);
     }
     return hipGetLastError();
 }

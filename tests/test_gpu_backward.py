@@ -222,3 +222,31 @@ def test_backward_with_no_covered_texel_on_two_streams(B):
     r, _, _, glo, ghi = _run(B, a, gm)
     assert r.ray_count() == 0
     assert not glo.any() and not ghi.any()
+
+
+def test_non_finite_upstream_gradient_stays_in_its_vertices(B):
+    """An infinite upstream gradient at one hit texel makes exactly the three
+    vertices of its hit triangle NaN in dL/dhi_N; every other entry is bitwise
+    what it is when that texel's gradient is 0 (each vertex sums only its own
+    run of the sorted pairs)."""
+    a = make_config(1)
+    rng = np.random.default_rng(14)
+    gm = rng.normal(size=(a.res, a.res, 3)).astype(np.float32)
+    t = B.to_device(a)
+    r = B.bake_normals(*t, a.res, a.max_dist, save=True, dilate_passes=0)
+    hit = r.hit.cpu().numpy().reshape(-1)
+    tex = int(np.nonzero(hit >= 0)[0][100])
+    g0 = gm.copy().reshape(-1, 3)
+    g0[tex] = 0.0
+    ginf = gm.copy().reshape(-1, 3)
+    ginf[tex] = [np.inf, 0.0, 0.0]
+    out = []
+    for g in (g0, ginf):
+        _, ghi = B.bake_normals_backward(r, t, torch.from_numpy(g.reshape(a.res, a.res, 3)).cuda(), need_lo=False)
+        torch.cuda.synchronize()
+        out.append(ghi.cpu().numpy())
+    tri = a.hi_F[hit[tex]]
+    nan_rows = np.nonzero(np.isnan(out[1]).any(1))[0]
+    assert set(nan_rows.tolist()) == set(int(v) for v in tri), (nan_rows, tri)
+    keep = np.setdiff1d(np.arange(a.hi_V.shape[0]), tri)
+    assert np.array_equal(out[0][keep].view(np.uint32), out[1][keep].view(np.uint32))
