@@ -163,25 +163,28 @@ __device__ __forceinline__ void tri_test(const RayT& r, const Leaf& L, float max
     float V = edge_fn(A.x, A.y, C.x, C.y);
     float W = edge_fn(B.x, B.y, A.x, A.y);
     float det = U + V + W;
-    if (det == 0.f) return;
-    if (det < 0.f) {
-        U = -U; V = -V; W = -W; det = -det;
-    }
-    if (fminf(fminf(U, V), W) < -kEdgeEps * det) return;
-    float T = U * A.z + V * B.z + W * C.z;
+    // written without branches (the lanes of a leaf trip take one path; a
+    // zero det gives a non-finite t, which the range test rejects)
+    const bool neg = det < 0.f;
+    U = neg ? -U : U;
+    V = neg ? -V : V;
+    W = neg ? -W : W;
+    det = neg ? -det : det;
+    const bool inside = det != 0.f && !(fminf(fminf(U, V), W) < -kEdgeEps * det);
+    // T accumulated in this order, each product fused into the next sum
+    const float T = fmaf(W, C.z, fmaf(V, B.z, U * A.z));
     float rdet = 1.0f / det;
     float t = T * rdet;
     float at = fabsf(t);
-    if (ONE ? !(t > 0.f && t <= max_dist) : !(at <= max_dist)) return;
-    uint32_t key = (uint32_t)(at * inv_w);
-    if (key < b->key || (key == b->key && id < b->id)) {
-        b->key = key;
-        b->id = id;
-        b->t = t;
-        b->b1 = V * rdet;
-        b->b2 = W * rdet;
-        b->bound = (float)(key + 1u) * w * (1.0f + kPad);
-    }
+    const bool in_range = ONE ? (t > 0.f && t <= max_dist) : (at <= max_dist);
+    const uint32_t key = in_range ? (uint32_t)(at * inv_w) : 0xFFFFFFFFu;
+    const bool better = inside && in_range && (key < b->key || (key == b->key && id < b->id));
+    b->key = better ? key : b->key;
+    b->id = better ? id : b->id;
+    b->t = better ? t : b->t;
+    b->b1 = better ? V * rdet : b->b1;
+    b->b2 = better ? W * rdet : b->b2;
+    b->bound = better ? (float)(key + 1u) * w * (1.0f + kPad) : b->bound;
 }
 
 // Point-to-box distance test: true when the box may hold a point within
@@ -314,6 +317,10 @@ __device__ __forceinline__ TreeView tree_view(const TravArgs& t, const AssetDev&
     v.step_cap = (int32_t)min((int64_t)4 * As.nhf + 1024, (int64_t)INT32_MAX);
     return v;
 }
+
+// Node `node` (>= 0) and leaf ~node (node < 0) of a tree.
+__device__ __forceinline__ const BvhNodeC* node_at(const TreeView& tv, int32_t node) { return tv.nodes + node; }
+__device__ __forceinline__ const Leaf* leaf_at(const TreeView& tv, int32_t node) { return tv.leaves + ~node; }
 
 // Ray setup from the G-buffer record: world position p, interpolated smooth
 // normal d, tangent T' orthogonalised against d, UV handedness.  rel = false
@@ -470,7 +477,7 @@ template <int BLOCK, int STACK, bool COUNT, bool ONE = false>
 __device__ __forceinline__ int32_t inner_step(const TreeView& tv, uint32_t* status, int32_t node,
                                               const RayT& R, const Best& best, LaneStack<BLOCK, STACK>& st,
                                               int tid, unsigned long long& c_box) {
-    const NodeBoxes nb = load_node(tv.nodes + node);
+    const NodeBoxes nb = load_node(node_at(tv, node));
     const int4 ref = make_int4(nb.left, nb.right, 0, 0);
     float mL, mR;
     bool hL = box_test<ONE>(R, nb.llo, nb.lhi, best.bound, &mL);
@@ -494,7 +501,7 @@ __device__ __forceinline__ int32_t inner_step(const TreeView& tv, uint32_t* stat
 template <int BLOCK, int STACK, bool COUNT, bool ONE = false>
 __device__ __forceinline__ int32_t leaf_step(const TreeView& tv, int32_t node, const RayT& R, Best& best,
                                              LaneStack<BLOCK, STACK>& st, int tid, unsigned long long& c_tri) {
-    const Leaf L = tv.leaves[~node];
+    const Leaf L = *leaf_at(tv, node);
     tri_test<ONE>(R, L, tv.max_dist, tv.inv_w, tv.w, &best);
     if (COUNT) c_tri += 1;
     return st.pop(tid);
@@ -505,7 +512,7 @@ template <int BLOCK, int STACK, bool COUNT>
 __device__ __forceinline__ int32_t inner_step_pt(const TreeView& tv, uint32_t* status, int32_t node,
                                                  float3 p, const Best& best, LaneStack<BLOCK, STACK>& st,
                                                  int tid, unsigned long long& c_box) {
-    const NodeBoxes nb = load_node(tv.nodes + node);
+    const NodeBoxes nb = load_node(node_at(tv, node));
     const int4 ref = make_int4(nb.left, nb.right, 0, 0);
     float dL, dR;
     bool hL = box_dist_test(p, nb.llo, nb.lhi, best.bound, &dL);
@@ -528,7 +535,7 @@ __device__ __forceinline__ int32_t inner_step_pt(const TreeView& tv, uint32_t* s
 template <int BLOCK, int STACK, bool COUNT>
 __device__ __forceinline__ int32_t leaf_step_pt(const TreeView& tv, int32_t node, float3 p, Best& best,
                                                 LaneStack<BLOCK, STACK>& st, int tid, unsigned long long& c_tri) {
-    const Leaf L = tv.leaves[~node];
+    const Leaf L = *leaf_at(tv, node);
     tri_closest_test(p, L, tv.max_dist, tv.inv_w, tv.w, &best);
     if (COUNT) c_tri += 1;
     return st.pop(tid);
