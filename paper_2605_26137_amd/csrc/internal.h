@@ -148,7 +148,7 @@ constexpr int kSuper = 32;       // sort tiles per super-tile (digit counts summ
 // Super-tile rows of a sort over `tiles` tiles of `n` assets (asset a's rows
 // start at its first tile / kSuper + a).
 __host__ __device__ inline int64_t sort_super_rows(int64_t tiles, int64_t n) { return tiles / kSuper + n + 1; }
-constexpr int kFinishTile = 32;  // texel tile side of the fused fill + dilation
+constexpr int kFinishTile = 56;  // texel tile side of the fused fill + dilation (tile + 2 halos <= 64)
 constexpr int kMaxFusedPasses = 4;  // more dilation passes run one launch per pass
 
 // Treelet and frontier capacity per asset.  Treelet roots are the small

@@ -321,6 +321,18 @@ __global__ __launch_bounds__(256) void fill_uncovered_kernel(Batch Bt, const uin
     }
 }
 
+// The uncovered texels alone (no dilation): (0,0,1) and the uncovered status.
+__global__ __launch_bounds__(256) void uncovered_kernel(Batch Bt, const uint32_t* __restrict__ facemap) {
+    int64_t lb;
+    const AssetDev& As = Bt.A[block_asset(Bt, kGTex, blockIdx.x, &lb)];
+    const int64_t t = lb * 256 + threadIdx.x;
+    if (t >= (int64_t)As.res * As.res || facemap[As.tex + t] != 0x7FFFFFFFu) return;
+    As.out_map[3 * t] = 0.f;
+    As.out_map[3 * t + 1] = 0.f;
+    As.out_map[3 * t + 2] = 1.f;
+    As.out_hit[t] = kUncovered;
+}
+
 // Pass k: a still-empty texel takes the normalised sum of its 8 neighbours
 // that had a value before this pass (level < k).  Texels written in this pass
 // are never read in it, so the map is updated in place.
@@ -362,112 +374,131 @@ __global__ __launch_bounds__(256) void dilate_kernel(Batch Bt, int pass, uint8_t
     level[t] = (uint8_t)pass;
 }
 
-// Uncovered fill and k <= kMaxFusedPasses dilation passes in one launch: a
-// workgroup loads its kFinishTile^2 tile plus a k-texel halo into LDS
-// (covered texels with their traced value, uncovered ones as (0,0,1)), runs
-// the passes there with the pass rule of dilate_kernel, and writes the tile's
-// uncovered texels.  A value at distance d from the region's edge is exact
-// through pass d, so the tile (d >= k) is exact after k passes: the result is
-// bitwise that of the fill + per-pass launches.
-constexpr int kFinishBlock = 256;
-constexpr uint8_t kOutside = 254;  // outside the image: never read, never filled
+// Uncovered fill and 1 <= k <= kMaxFusedPasses dilation passes in one launch.
+// A workgroup takes a kFinishTile^2 texel tile plus a k-texel halo, R = tile
+// + 2k <= 64 texels a side: one wave per region row at a time, one lane per
+// column.  The region's values go to LDS (covered texels with their traced
+// value, uncovered ones as (0,0,1)) and its rows to 64-bit masks: inside the
+// image, and has a value before the pass (covered, or filled in an earlier
+// pass).  A pass fills, with the pass rule of dilate_kernel, only the empty
+// texels that the masks show to have a valued neighbour; the others read
+// nothing.  A value at distance d from the region's edge is exact through
+// pass d, so the tile (d >= k) is exact after k passes: the result is bitwise
+// that of the fill + per-pass launches (same neighbours, same order of sums).
+constexpr int kFinishBlock = 512;
+constexpr int kFinishWaves = kFinishBlock / 64;
+static_assert(kFinishTile + 2 * kMaxFusedPasses <= 64, "a region row fits one wave");
 
 template <int PASSES>
 __global__ __launch_bounds__(kFinishBlock) void finish_kernel(Batch Bt, const uint32_t* __restrict__ facemap_all) {
-    constexpr int passes = PASSES;
-    constexpr int32_t R = kFinishTile + 2 * PASSES;  // region side: divisions by it are by a constant
-    __shared__ float s_map[R * R][3];
-    __shared__ uint8_t s_lvl[R * R];
+    static_assert(PASSES >= 1 && PASSES <= kMaxFusedPasses, "fused pass count");
+    constexpr int R = kFinishTile + 2 * PASSES;                // region side
+    constexpr int kRows = (R + kFinishWaves - 1) / kFinishWaves;  // region rows per wave
+    __shared__ float s_map[R][64][3];
+    __shared__ uint64_t s_in[R], s_val[2][R];
     int64_t lt;
     const AssetDev& As = Bt.A[block_asset(Bt, kGTile, blockIdx.x, &lt)];
     const int32_t res = As.res;
     const int32_t tiles_x = (res + kFinishTile - 1) / kFinishTile;
-    const int32_t ti = (int32_t)(lt / tiles_x) * kFinishTile, tj = (int32_t)(lt % tiles_x) * kFinishTile;
-    const int32_t oi = ti - passes, oj = tj - passes;  // region origin
+    const int32_t oi = (int32_t)(lt / tiles_x) * kFinishTile - PASSES;  // region origin
+    const int32_t oj = (int32_t)(lt % tiles_x) * kFinishTile - PASSES;
     const uint32_t* __restrict__ facemap = facemap_all + As.tex;
-    const float* __restrict__ map = As.out_map;
-    // The region's loads, kU per thread and trip, are issued together: first
-    // the coverage of kU texels, then the map values of those covered (two
-    // load latencies per trip instead of two per texel).
-    constexpr int kU = (R * R + kFinishBlock - 1) / kFinishBlock < 8 ? (R * R + kFinishBlock - 1) / kFinishBlock : 8;
-    for (int x0 = threadIdx.x; x0 < R * R; x0 += kU * kFinishBlock) {
-        int64_t t[kU];
-        bool in[kU], cov[kU];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int32_t j = oj + lane;
+    const bool col_in = lane < R && j >= 0 && j < res;
+    // Loads of all the wave's rows first: coverage, then the map values of
+    // the covered texels (two load latencies per wave).
+    int32_t t[kRows];
+    bool cov[kRows];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int x = x0 + u * kFinishBlock;
-            const int32_t i = oi + x / R, j = oj + x % R;
-            in[u] = x < R * R && i >= 0 && j >= 0 && i < res && j < res;
-            t[u] = in[u] ? (int64_t)i * res + j : 0;
-            cov[u] = in[u] && facemap[t[u]] != 0x7FFFFFFFu;
+    for (int u = 0; u < kRows; ++u) {
+        const int r = wave + u * kFinishWaves;
+        const int32_t i = oi + r;
+        const bool in = r < R && col_in && i >= 0 && i < res;
+        t[u] = in ? i * res + j : -1;
+        cov[u] = in && facemap[t[u]] != 0x7FFFFFFFu;
+    }
+    float m0[kRows], m1[kRows], m2[kRows];
+#pragma unroll
+    for (int u = 0; u < kRows; ++u) {
+        m0[u] = 0.f;
+        m1[u] = 0.f;
+        m2[u] = 1.f;
+        if (cov[u]) {
+            m0[u] = As.out_map[3 * t[u]];
+            m1[u] = As.out_map[3 * t[u] + 1];
+            m2[u] = As.out_map[3 * t[u] + 2];
         }
-        float m0[kU], m1[kU], m2[kU];
+    }
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            m0[u] = 0.f;
-            m1[u] = 0.f;
-            m2[u] = 1.f;
-            if (cov[u]) {
-                m0[u] = map[3 * t[u]];
-                m1[u] = map[3 * t[u] + 1];
-                m2[u] = map[3 * t[u] + 2];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int x = x0 + u * kFinishBlock;
-            if (x >= R * R) continue;
-            s_lvl[x] = !in[u] ? kOutside : (cov[u] ? 0 : 255);
-            s_map[x][0] = m0[u];
-            s_map[x][1] = m1[u];
-            s_map[x][2] = m2[u];
+    for (int u = 0; u < kRows; ++u) {
+        const int r = wave + u * kFinishWaves;
+        if (r >= R) break;  // wave-uniform
+        s_map[r][lane][0] = m0[u];
+        s_map[r][lane][1] = m1[u];
+        s_map[r][lane][2] = m2[u];
+        const uint64_t bin = __ballot(t[u] >= 0), bcov = __ballot(cov[u]);
+        if (lane == 0) {
+            s_in[r] = bin;
+            s_val[0][r] = bcov;
         }
     }
     __syncthreads();
-    for (int pass = 1; pass <= passes; ++pass) {
-        // texels filled in this pass get level `pass` and are never read in it
-        for (int x = threadIdx.x; x < R * R; x += kFinishBlock) {
-            if (s_lvl[x] != 255) continue;
-            const int32_t ri = x / R, rj = x % R;
-            float sx = 0.f, sy = 0.f, sz = 0.f;
-            int cnt = 0;
+    for (int pass = 1; pass <= PASSES; ++pass) {
+        const uint64_t* cur = s_val[(pass - 1) & 1];
+        uint64_t* nxt = s_val[pass & 1];
 #pragma unroll
-            for (int di = -1; di <= 1; ++di) {
+        for (int u = 0; u < kRows; ++u) {
+            const int r = wave + u * kFinishWaves;
+            if (r >= R) break;  // wave-uniform
+            const uint64_t vu = r > 0 ? cur[r - 1] : 0ull, vc = cur[r], vd = r + 1 < R ? cur[r + 1] : 0ull;
+            const uint64_t vm = vu | vc | vd;
+            const uint64_t cand = (vm | (vm << 1) | (vm >> 1)) & s_in[r] & ~vc;
+            bool filled = false;
+            if ((cand >> lane) & 1ull) {
+                float sx = 0.f, sy = 0.f, sz = 0.f;
 #pragma unroll
-                for (int dj = -1; dj <= 1; ++dj) {
-                    if (di == 0 && dj == 0) continue;
-                    const int32_t ii = ri + di, jj = rj + dj;
-                    if (ii < 0 || jj < 0 || ii >= R || jj >= R) continue;
-                    const int u = ii * R + jj;
-                    if (s_lvl[u] < pass) {
-                        sx += s_map[u][0];
-                        sy += s_map[u][1];
-                        sz += s_map[u][2];
-                        ++cnt;
+                for (int di = -1; di <= 1; ++di) {
+                    const uint64_t row = di < 0 ? vu : (di == 0 ? vc : vd);
+#pragma unroll
+                    for (int dj = -1; dj <= 1; ++dj) {
+                        if (di == 0 && dj == 0) continue;
+                        const int ii = r + di, jj = lane + dj;
+                        if (ii < 0 || jj < 0 || ii >= R || jj >= R) continue;
+                        if ((row >> jj) & 1ull) {
+                            sx += s_map[ii][jj][0];
+                            sy += s_map[ii][jj][1];
+                            sz += s_map[ii][jj][2];
+                        }
                     }
                 }
+                // at least one neighbour had a value (the candidate mask)
+                const float l2 = sx * sx + sy * sy + sz * sz;
+                if (l2 > 0.f) {
+                    const float inv = 1.0f / sqrtf(l2);
+                    s_map[r][lane][0] = sx * inv;
+                    s_map[r][lane][1] = sy * inv;
+                    s_map[r][lane][2] = sz * inv;
+                    filled = true;
+                }
             }
-            if (cnt == 0) continue;
-            float l2 = sx * sx + sy * sy + sz * sz;
-            if (!(l2 > 0.f)) continue;
-            float r = 1.0f / sqrtf(l2);
-            s_map[x][0] = sx * r;
-            s_map[x][1] = sy * r;
-            s_map[x][2] = sz * r;
-            s_lvl[x] = (uint8_t)pass;
+            // texels filled in this pass are read by no one in it: the pass
+            // reads the masks of `cur` and writes those of `nxt`
+            const uint64_t bf = __ballot(filled);
+            if (lane == 0) nxt[r] = vc | bf;
         }
         __syncthreads();
     }
-    for (int x = threadIdx.x; x < kFinishTile * kFinishTile; x += kFinishBlock) {
-        const int32_t i = ti + x / kFinishTile, j = tj + x % kFinishTile;
-        if (i >= res || j >= res) continue;
-        const int u = (i - oi) * R + (j - oj);
-        if (s_lvl[u] == 0) continue;  // covered: the traversal's value stays
-        const int64_t t = (int64_t)i * res + j;
-        As.out_map[3 * t] = s_map[u][0];
-        As.out_map[3 * t + 1] = s_map[u][1];
-        As.out_map[3 * t + 2] = s_map[u][2];
-        As.out_hit[t] = kUncovered;
+    // the tile's uncovered texels, filled or (0,0,1)
+    const bool col_tile = lane >= PASSES && lane < PASSES + kFinishTile;
+#pragma unroll
+    for (int u = 0; u < kRows; ++u) {
+        const int r = wave + u * kFinishWaves;
+        if (r < PASSES || r >= PASSES + kFinishTile || !col_tile || t[u] < 0 || cov[u]) continue;
+        As.out_map[3 * t[u]] = s_map[r][lane][0];
+        As.out_map[3 * t[u] + 1] = s_map[r][lane][1];
+        As.out_map[3 * t[u] + 2] = s_map[r][lane][2];
+        As.out_hit[t[u]] = kUncovered;
     }
 }
 
@@ -553,12 +584,16 @@ hipError_t launch_fill_uncovered(const BatchHost& H, hipStream_t s) {
 
 // After the traversal: uncovered fill and dilation, fused for few passes.
 hipError_t launch_dilate(const BatchHost& H, int passes, hipStream_t s) {
+    const uint32_t* fm = (const uint32_t*)(H.ws + H.L.facemap);
+    if (passes == 0) {
+        if (H.blocks(kGTex) == 0) return hipSuccess;
+        hipLaunchKernelGGL(uncovered_kernel, dim3((unsigned)H.blocks(kGTex)), dim3(256), 0, s, H.dev, fm);
+        return hipGetLastError();
+    }
     if (passes <= kMaxFusedPasses) {
         if (H.blocks(kGTile) == 0) return hipSuccess;
         const dim3 grid((unsigned)H.blocks(kGTile)), block(kFinishBlock);
-        const uint32_t* fm = (const uint32_t*)(H.ws + H.L.facemap);
         switch (passes) {
-            case 0: hipLaunchKernelGGL(finish_kernel<0>, grid, block, 0, s, H.dev, fm); break;
             case 1: hipLaunchKernelGGL(finish_kernel<1>, grid, block, 0, s, H.dev, fm); break;
             case 2: hipLaunchKernelGGL(finish_kernel<2>, grid, block, 0, s, H.dev, fm); break;
             case 3: hipLaunchKernelGGL(finish_kernel<3>, grid, block, 0, s, H.dev, fm); break;

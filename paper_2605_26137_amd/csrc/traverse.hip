@@ -17,11 +17,16 @@
 //   * lane refill: lanes whose ray finished are refilled from a ray queue over
 //     the concatenated lists while the rest continue (wave-level compaction
 //     after Aila & Laine 2009); lanes may then work on different assets;
-//   * conservative slab test: near/far planes picked by the sign of the
-//     direction, t widened outward by a relative 1e-6 (after Ize 2013); a zero
-//     direction component gives +-inf slab ends (kept infinite by the
-//     widening), or NaN for a ray lying in a slab plane, which the
-//     NaN-ignoring min3/max3 treat as an unbounded slab;
+//   * conservative slab test on the compressed node itself: a child plane is
+//     o + q s (frame origin o, power-of-two step s, byte q), so its crossing
+//     is t = q (s/d) + (o - p)/d, one fma per plane from three per-node
+//     products, with the near / far bytes of both children picked by a byte
+//     permute whose selector follows the signs of d.  The slabs are widened
+//     outward by an absolute per-ray margin that bounds the FP32 rounding of
+//     that evaluation (the error analysis, after Ize 2013, is at make_rayt);
+//     a zero direction component takes 1/d = 2^64 instead of infinity, which
+//     the margin turns into an unbounded slab for a ray inside it and a
+//     rejected box for a ray outside;
 //   * hit rule: a triangle is hit when the crossing's barycentric weights are
 //     all >= -kEdgeEps (relative edge tolerance) and |t| <= max_dist; the
 //     winner minimises (floor(|t| / w), index) with the quantum w = max_dist
@@ -80,17 +85,54 @@ __device__ __forceinline__ float edge_fn(float xa, float ya, float xb, float yb)
 // Ray state for the slab and triangle tests.
 struct RayT {
     float3 p;
-    float3 invd;    // 1/d with +inf for a zero component
-    uint32_t sgn;   // bit k set: d_k < 0 (near plane is the box max)
+    float3 invd;    // 1/d, magnitudes clamped to 2^64 (2^64 for a zero component)
+    float3 E;       // per-axis slab margin, in units of t
+    uint32_t seln;  // byte-permute selector of the left child's near planes
     float3x3 S;     // rows of the shear: (Ax, Ay, Az) = S (v - p)
 };
 
-__device__ __forceinline__ RayT make_rayt(float3 p, float3 d) {
+constexpr float kInvdMax = 18446744073709551616.0f;  // 2^64
+constexpr float kSlabRel = 1.0f / 1048576.0f;        // 2^-20
+
+// The slab margin.  A compressed child plane is the exact value o + q s,
+// which the build places on the outer side of the child's box up to half an
+// ulp of the coordinate (it checks the once-rounded fmaf(q, s, o)); the test
+// evaluates t = fma(q, A, B) with A = s c exact (c the stored 1/d, s a power
+// of two), B = fl(fl(o - p) c -+ E).  With u = 2^-24, X = the largest
+// coordinate magnitude of the root box and M1 = the largest distance from p
+// to it (every frame origin and plane lies in the root box, 255 s is at most
+// twice the node's extent), the errors are at most 2uX|c| (plane), uM1|c|
+// (o - p), u(M1|c| + E) (B), and, where a slab end can decide the test (|t|
+// within about twice the bound b <= max_dist), 2ub for the final rounding and
+// 2ub for c against 1/d: in all below E / 4 with E = 2^-20 ((M1 + X)|c| +
+// max_dist).  In space that widens every box by about 1e-6 of (scene extent +
+// coordinate magnitude).  A clamped c (|d| < 2^-64) scales the slab ends
+// towards zero, but only for planes within E / |c| of p, which the margin
+// already makes unbounded.  A non-finite root frame gives a NaN margin: every
+// slab is then unbounded (the NaN-ignoring min3 / max3).
+__device__ __forceinline__ RayT make_rayt(float3 p, float3 d, const BvhNodeC* root, float max_dist) {
     RayT r;
     r.p = p;
-    r.invd = f3(d.x == 0.f ? INFINITY : 1.0f / d.x, d.y == 0.f ? INFINITY : 1.0f / d.y,
-                d.z == 0.f ? INFINITY : 1.0f / d.z);
-    r.sgn = (d.x < 0.f ? 1u : 0u) | (d.y < 0.f ? 2u : 0u) | (d.z < 0.f ? 4u : 0u);
+    auto inv = [](float x) {
+        const float c = x == 0.f ? kInvdMax : 1.0f / x;
+        return fabsf(c) > kInvdMax ? copysignf(kInvdMax, c) : c;
+    };
+    r.invd = f3(inv(d.x), inv(d.y), inv(d.z));
+    // near byte of the left child per axis: lo (bytes 0, 1, 2) for d >= 0,
+    // hi (bytes 3, 4, 5) for d < 0; byte 3 of the selector yields zero
+    r.seln = (d.x < 0.f ? 3u : 0u) | ((d.y < 0.f ? 4u : 1u) << 8) | ((d.z < 0.f ? 5u : 2u) << 16) | (0x0Cu << 24);
+    r.E = f3(0.f, 0.f, 0.f);
+    if (root) {
+        const float4 a = root->a;
+        const uint32_t meta = __float_as_uint(a.w);
+        auto margin = [&](float o, uint32_t e, float pc, float c) {
+            const float hi = fmaf(255.f, __uint_as_float(e << 23), o);
+            const float m1 = fmaxf(fabsf(o - pc), fabsf(hi - pc)), x = fmaxf(fabsf(o), fabsf(hi));
+            return kSlabRel * fmaf(m1 + x, fabsf(c), max_dist);
+        };
+        r.E = f3(margin(a.x, meta & 0xFFu, p.x, r.invd.x), margin(a.y, (meta >> 8) & 0xFFu, p.y, r.invd.y),
+                 margin(a.z, (meta >> 16) & 0xFFu, p.z, r.invd.z));
+    }
     float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
     int kz = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
     int kx = kz == 2 ? 0 : kz + 1;
@@ -115,33 +157,6 @@ __device__ __forceinline__ float3 shear(const RayT& r, float3 v) {
     return f3(fmaf(r.S.r0.z, a.z, fmaf(r.S.r0.y, a.y, r.S.r0.x * a.x)),
               fmaf(r.S.r1.z, a.z, fmaf(r.S.r1.y, a.y, r.S.r1.x * a.x)),
               fmaf(r.S.r2.z, a.z, fmaf(r.S.r2.y, a.y, r.S.r2.x * a.x)));
-}
-
-// Slab test of box [lo, hi]; on overlap with [-bound, bound] (ONE: with
-// [0, bound], the half-line) returns true and the smallest |t| of the
-// (widened) overlap in *mint.
-template <bool ONE = false>
-__device__ __forceinline__ bool box_test(const RayT& r, float3 lo, float3 hi, float bound,
-                                         float* mint) {
-    float nx = (r.sgn & 1u) ? hi.x : lo.x, fx = (r.sgn & 1u) ? lo.x : hi.x;
-    float ny = (r.sgn & 2u) ? hi.y : lo.y, fy = (r.sgn & 2u) ? lo.y : hi.y;
-    float nz = (r.sgn & 4u) ? hi.z : lo.z, fz = (r.sgn & 4u) ? lo.z : hi.z;
-    float t0x = (nx - r.p.x) * r.invd.x, t1x = (fx - r.p.x) * r.invd.x;
-    float t0y = (ny - r.p.y) * r.invd.y, t1y = (fy - r.p.y) * r.invd.y;
-    float t0z = (nz - r.p.z) * r.invd.z, t1z = (fz - r.p.z) * r.invd.z;
-    float t0 = fmaxf(fmaxf(t0x, t0y), t0z);
-    float t1 = fminf(fminf(t1x, t1y), t1z);
-    // widen outward by a relative kPad.  An infinite end (a direction
-    // component of zero, or a slab distance that overflows) stays infinite:
-    // the fma gives inf - inf = NaN there, which the NaN-ignoring min / max
-    // drop, so a ray running outside a slab parallel to it rejects the box
-    // instead of keeping every box it meets.
-    t0 = fminf(t0, fmaf(-kPad, fabsf(t0), t0));
-    t1 = fmaxf(t1, fmaf(kPad, fabsf(t1), t1));
-    t0 = fmaxf(t0, ONE ? 0.f : -bound);
-    t1 = fminf(t1, bound);
-    *mint = fmaxf(fmaxf(t0, -t1), 0.f);  // nearest |t| of [t0, t1]
-    return t0 <= t1;
 }
 
 struct Best {
@@ -470,6 +485,23 @@ __device__ __forceinline__ NodeBoxes load_node(const BvhNodeC* nd) {
     return n;
 }
 
+// Slab test of one child from its near and far plane bytes (bytes 0-2 of the
+// permuted words, x y z): on overlap of the widened slabs with [-bound, bound]
+// (ONE: with [0, bound], the half-line) returns true and the smallest |t| of
+// the overlap in *mint.
+template <bool ONE>
+__device__ __forceinline__ bool child_test(uint32_t nw, uint32_t fw, float3 A, float3 Bn, float3 Bf, float bound,
+                                           float* mint) {
+    const float t0x = fmaf((float)(nw & 0xFFu), A.x, Bn.x), t1x = fmaf((float)(fw & 0xFFu), A.x, Bf.x);
+    const float t0y = fmaf((float)((nw >> 8) & 0xFFu), A.y, Bn.y), t1y = fmaf((float)((fw >> 8) & 0xFFu), A.y, Bf.y);
+    const float t0z = fmaf((float)((nw >> 16) & 0xFFu), A.z, Bn.z),
+                t1z = fmaf((float)((fw >> 16) & 0xFFu), A.z, Bf.z);
+    const float t0 = fmaxf(fmaxf(fmaxf(t0x, t0y), t0z), ONE ? 0.f : -bound);
+    const float t1 = fminf(fminf(fminf(t1x, t1y), t1z), bound);
+    *mint = fmaxf(fmaxf(t0, -t1), 0.f);  // nearest |t| of [t0, t1]
+    return t0 <= t1;
+}
+
 // One traversal step of a lane at an internal node: test both child boxes, go
 // to the nearer hit and push the other, or pop when neither is hit.  Returns
 // the next node (internal, leaf, or kEmpty: the ray is done).
@@ -477,11 +509,28 @@ template <int BLOCK, int STACK, bool COUNT, bool ONE = false>
 __device__ __forceinline__ int32_t inner_step(const TreeView& tv, uint32_t* status, int32_t node,
                                               const RayT& R, const Best& best, LaneStack<BLOCK, STACK>& st,
                                               int tid, unsigned long long& c_box) {
-    const NodeBoxes nb = load_node(node_at(tv, node));
-    const int4 ref = make_int4(nb.left, nb.right, 0, 0);
+    const BvhNodeC* nd = node_at(tv, node);
+    const float4 a = nd->a;
+    const uint4 q = nd->q;
+    const uint32_t meta = __float_as_uint(a.w);
+    // per axis: A = s / d (exact), Bn / Bf = (o - p) / d -/+ the margin
+    const float3 A = f3(__uint_as_float((meta & 0xFFu) << 23) * R.invd.x,
+                        __uint_as_float(((meta >> 8) & 0xFFu) << 23) * R.invd.y,
+                        __uint_as_float(((meta >> 16) & 0xFFu) << 23) * R.invd.z);
+    const float dx = a.x - R.p.x, dy = a.y - R.p.y, dz = a.z - R.p.z;
+    const float3 Bn = f3(fmaf(dx, R.invd.x, -R.E.x), fmaf(dy, R.invd.y, -R.E.y), fmaf(dz, R.invd.z, -R.E.z));
+    const float3 Bf = f3(fmaf(dx, R.invd.x, R.E.x), fmaf(dy, R.invd.y, R.E.y), fmaf(dz, R.invd.z, R.E.z));
+    // plane bytes: left child = bytes 0-5 of (q.x, q.y), right = bytes 2-7 of
+    // (q.y, q.z); far selector = near with lo / hi swapped per axis
+    const uint32_t selF = R.seln ^ 0x00070503u;
+    const uint32_t nL = __builtin_amdgcn_perm(q.y, q.x, R.seln), fL = __builtin_amdgcn_perm(q.y, q.x, selF);
+    const uint32_t nR = __builtin_amdgcn_perm(q.z, q.y, R.seln + 0x00020202u),
+                   fR = __builtin_amdgcn_perm(q.z, q.y, selF + 0x00020202u);
+    const int32_t g = (int32_t)(q.w & kChildIndex);
+    const int4 ref = make_int4((q.w & kChildLeafL) ? ~g : g, (q.w & kChildLeafR) ? ~(g + 1) : g + 1, 0, 0);
     float mL, mR;
-    bool hL = box_test<ONE>(R, nb.llo, nb.lhi, best.bound, &mL);
-    bool hR = box_test<ONE>(R, nb.rlo, nb.rhi, best.bound, &mR);
+    bool hL = child_test<ONE>(nL, fL, A, Bn, Bf, best.bound, &mL);
+    bool hR = child_test<ONE>(nR, fR, A, Bn, Bf, best.bound, &mR);
     if (COUNT) c_box += 2;
     int32_t next = kEmpty;
     if (hL && hR) {
@@ -645,7 +694,7 @@ constexpr int kLoopBalanced = 3;  // each trip is all-leaf or all-internal: a le
 // early wait through the rest of the internal-node phase; the balanced shape
 // never mixes them and lets no more than half of the busy lanes wait.
 template <int BLOCK, int STACK, bool COUNT, int LOOP, bool CLOSEST>
-__global__ __launch_bounds__(BLOCK) void traverse_batch_kernel(TravArgs a) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(COUNT ? 1 : 7))) void traverse_batch_kernel(TravArgs a) {
     __shared__ int32_t stk[STACK][BLOCK];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -677,7 +726,7 @@ __global__ __launch_bounds__(BLOCK) void traverse_batch_kernel(TravArgs a) {
             const RaySetup rs = setup_ray(a, As, a.rays[r]);
             if (rs.rel) {
                 if constexpr (CLOSEST) R.p = rs.p;
-                else R = make_rayt(rs.p, rs.d);
+                else R = make_rayt(rs.p, rs.d, tv.root >= 0 ? tv.nodes : nullptr, tv.max_dist);
                 node = tv.root;
             }
         }
@@ -828,7 +877,7 @@ __global__ __launch_bounds__(BLOCK) void visibility_kernel(VisArgs a) {
         {
             float3 e, d, f;
             pixel_ray(a, v, p, &e, &d, &f);
-            R = make_rayt(e, d);
+            R = make_rayt(e, d, tv.root >= 0 ? tv.nodes : nullptr, tv.max_dist);
         }
         int32_t node = valid ? tv.root : kEmpty;
         Best best;
@@ -1005,7 +1054,7 @@ __global__ __launch_bounds__(BLOCK) void traverse_refill_kernel(TravArgs a) {
                     node = rs.rel ? tv.root : kEmpty;
                     st.sp = st.lo = 0;
                     steps = 0;
-                    if (rs.rel) R = make_rayt(rs.p, rs.d);
+                    if (rs.rel) R = make_rayt(rs.p, rs.d, tv.root >= 0 ? tv.nodes : nullptr, tv.max_dist);
                     active = node != kEmpty;
                     if (!active) finish_ray(a, As, k, rs, best);
                 }

@@ -190,6 +190,27 @@ def test_noise_multi_tile_brute(B, oracle_lib, hi_level, lo_level, res):
     check(oracle_lib, a, r, method="brute")
 
 
+@pytest.mark.parametrize("passes", [0, 1, 3, 4, 6])
+def test_dilation_passes(B, oracle_lib, passes):
+    """Every dilation depth against the oracle's (Sec. 6.4 gutters): the fused
+    launch (1 to 4 passes, 56-texel tiles with the halo; 256^2 leaves a ragged
+    32-texel tail), the per-pass launches (6) and no dilation (0)."""
+    a = _noise_asset(6, 3, 256, seed=7)
+    r = run(B, a, dilate_passes=passes)
+    ob = oracle_lib.bake(a, method="bvh", dilate_passes=passes)
+    check(oracle_lib, a, r, ob=ob)
+    gm, gh = np_out(r)
+    unc = gh == -3
+    filled = unc & np.any(gm != np.array([0.0, 0.0, 1.0], np.float32), axis=1)
+    o_filled = unc & np.any(ob.map != np.array([0.0, 0.0, 1.0]), axis=1)
+    say(f"[gpu] passes={passes}: uncovered {int(unc.sum())}, filled {int(filled.sum())} (oracle {int(o_filled.sum())})")
+    assert np.array_equal(filled, o_filled)
+    if passes == 0:
+        assert not filled.any()
+    else:
+        assert filled.any()
+
+
 # ---------------------------------------------------------------------------
 # configuration invariance, determinism
 # ---------------------------------------------------------------------------
