@@ -506,14 +506,17 @@ int32_t run_forward(Plan& P, const Opts& o, void* workspace, hipStream_t s) {
     std::unique_lock<std::mutex> side_lock(g_side_mu);
     Side* side = L.t_hf >= kSideMinFaces && !one_stream ? side_stream(s) : nullptr;
     if (side) {
+        // the build, the longer chain, is enqueued first: kernels are handed
+        // to the device one by one in the order they were enqueued (also on
+        // a graph replay), so the chain enqueued second starts late
         HIP_OR_FAIL(hipEventRecord(side->fork, s));
+        HIP_OR_FAIL(launch_bvh_build(H, s));
         HIP_OR_FAIL(hipStreamWaitEvent(side->s, side->fork, 0));
         HIP_OR_FAIL(launch_lo_prep(H, side->s));
         HIP_OR_FAIL(tim_record(tim, 1, side->s));
         HIP_OR_FAIL(launch_raster(H, side->s));
         HIP_OR_FAIL(tim_record(tim, 2, side->s));
         HIP_OR_FAIL(hipEventRecord(side->join, side->s));
-        HIP_OR_FAIL(launch_bvh_build(H, s));
         HIP_OR_FAIL(hipStreamWaitEvent(s, side->join, 0));
     } else {
         side_lock.unlock();
