@@ -234,11 +234,16 @@ __global__ __launch_bounds__(kSortBlock) void radix_hist_kernel(Batch Bt, const 
     if (threadIdx.x < 256) h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = T.lt * kSortTile;
+    // all rounds' keys are loaded before the first count (one load latency)
+    uint32_t k[kSortRounds];
 #pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
-        int64_t i = base + (int64_t)r * kSortBlock + threadIdx.x;
-        if (i < T.count) atomicAdd(&h[(keys[T.start + i] >> shift) & 255u], 1u);
+        const int64_t i = base + (int64_t)r * kSortBlock + threadIdx.x;
+        k[r] = i < T.count ? keys[T.start + i] : 0u;
     }
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r)
+        if (base + (int64_t)r * kSortBlock + threadIdx.x < T.count) atomicAdd(&h[(k[r] >> shift) & 255u], 1u);
     __syncthreads();
     if (threadIdx.x < 256) {
         const uint32_t c = h[threadIdx.x];
@@ -295,15 +300,32 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(Batch Bt, con
         // per digit, in four parts: the asset's count (all super-tile rows)
         // and the count before this tile (earlier super-tiles, then the
         // earlier tiles of its own super-tile)
+        // (the loads of a group are all issued before their sums: one load
+        // latency per group instead of one per row)
         const int d = tid & 255, part = tid >> 8;
         const int64_t S = T.lt / kSuper, nS = ceil_div(ceil_div(T.count, kSortTile), kSuper);
         uint32_t tot = 0, before = 0;
-        for (int64_t x = part; x < nS; x += 4) {
-            const uint32_t v = sup[T.sbase + 256 * x + d];
-            tot += v;
-            if (x < S) before += v;
+        uint32_t hv[kSuper / 4];
+#pragma unroll
+        for (int j = 0; j < kSuper / 4; ++j) {
+            const int64_t t = S * kSuper + part + 4 * j;
+            hv[j] = t < T.lt ? hist[T.hbase + 256 * t + d] : 0u;
         }
-        for (int64_t t = S * kSuper + part; t < T.lt; t += 4) before += hist[T.hbase + 256 * t + d];
+        for (int64_t x0 = part; x0 < nS; x0 += 4 * 8) {
+            uint32_t v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int64_t x = x0 + 4 * j;
+                v[j] = x < nS ? sup[T.sbase + 256 * x + d] : 0u;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                tot += v[j];
+                if (x0 + 4 * j < S) before += v[j];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kSuper / 4; ++j) before += hv[j];
         scratch[part][d] = tot;
         scratch[4 + part][d] = before;
     }
