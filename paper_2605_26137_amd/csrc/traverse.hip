@@ -756,18 +756,25 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(COUNT ? 1
                 }
             }
         } else if constexpr (LOOP == kLoopBalanced) {
+            // internal-node trips while more busy lanes are at an internal
+            // node than at a leaf, then one leaf trip; the node trips leave
+            // the best hit untouched, so their loop keeps it in place
             for (;;) {
-                const uint64_t at_node = __ballot(node >= 0);
-                const uint64_t at_leaf = __ballot(node < 0 && node != kEmpty);
-                if ((at_node | at_leaf) == 0) break;
-                if (COUNT) ++c_iter;
-                if (__popcll(at_leaf) >= __popcll(at_node)) {
-                    if (node < 0 && node != kEmpty) {
-                        node = tri_step<BLOCK, STACK, COUNT, CLOSEST ? kQPoint : kQRay>(tv, node, R, best, st, tid, c_tri);
+                uint64_t at_leaf;
+                for (;;) {
+                    const uint64_t at_node = __ballot(node >= 0);
+                    at_leaf = __ballot(node < 0 && node != kEmpty);
+                    if (__popcll(at_leaf) >= __popcll(at_node)) break;
+                    if (COUNT) ++c_iter;
+                    if (node >= 0) {
+                        node = node_step<BLOCK, STACK, COUNT, CLOSEST ? kQPoint : kQRay>(tv, B.status, node, R, best, st, tid, c_box);
                         capped();
                     }
-                } else if (node >= 0) {
-                    node = node_step<BLOCK, STACK, COUNT, CLOSEST ? kQPoint : kQRay>(tv, B.status, node, R, best, st, tid, c_box);
+                }
+                if (at_leaf == 0) break;  // and no lane at a node: the batch is done
+                if (COUNT) ++c_iter;
+                if (node < 0 && node != kEmpty) {
+                    node = tri_step<BLOCK, STACK, COUNT, CLOSEST ? kQPoint : kQRay>(tv, node, R, best, st, tid, c_tri);
                     capped();
                 }
             }
