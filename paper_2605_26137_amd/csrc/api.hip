@@ -118,7 +118,6 @@ int64_t grid_blocks(int g, const Sizes& z) {
         case kGHiV: return cdiv(z.nhv, 256);
         case kGHiF: return cdiv(z.nhf, 256);
         case kGNode: return cdiv(std::max<int64_t>(z.nhf - 1, 0), 256);
-        case kGAllNode: return cdiv(std::max<int64_t>(2 * z.nhf - 1, 0), 256);
         case kGSort: return cdiv(z.nhf, kSortTile);
         case kGTex: return cdiv(tex, 256);
         case kGTex3: return cdiv(3 * tex, 256);
@@ -251,7 +250,6 @@ int32_t make_plan(const Sizes* z, int n, uint32_t flags, Plan* P) {
     L.node_parent = take(4 * (size_t)L.t_node);
     L.leaf_parent = take(4 * (size_t)L.t_hf);
     L.refit_cnt = take(4 * (size_t)L.t_node);
-    L.node_range = take(8 * (size_t)L.t_node);
     L.frontier = take(4 * (size_t)L.t_tl);
     L.treelets = take(16 * (size_t)L.t_tl);
     L.top = take(8 * (size_t)L.t_tl);

@@ -132,7 +132,6 @@ enum GridId : int {
     kGHiV,      // hi vertices, 256 per block
     kGHiF,      // hi triangles, 256 per block
     kGNode,     // internal nodes, 256 per block
-    kGAllNode,  // internal nodes + leaves, 256 per block
     kGSort,     // BVH sort tiles (kSortTile keys per block)
     kGTex,      // texels, 256 per block
     kGTex3,     // texel channels, 256 per block
@@ -232,7 +231,7 @@ struct Layout {
     size_t rays, hits;                            // per ray
     size_t bounds_part, bounds;                   // centroid bounds: per sort tile, per asset
     size_t keys0, keys1, vals0, vals1, hist, sup; // radix sort of the BVH keys
-    size_t nodes, nodes_c, leaves, node_parent, leaf_parent, refit_cnt, node_range, frontier, treelets, top, child;
+    size_t nodes, nodes_c, leaves, node_parent, leaf_parent, refit_cnt, frontier, treelets, top, child;
     size_t spill;                                 // traversal stack spill
     // backward scratch (BAKE_FLAG_SAVE only)
     size_t bwd_ray, bwd_hterm, bwd_k0, bwd_v0, bwd_k1, bwd_v1, bwd_hist, bwd_sup, bwd_face1, bwd_face2, bwd_sbar,

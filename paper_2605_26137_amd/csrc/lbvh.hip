@@ -445,6 +445,8 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(Batch Bt, con
 // kKarrasReach keys; longer ranges (the few nodes near the top) are searched
 // by the whole wave together, 64 probes per step.
 constexpr int kKarrasReach = 64;
+// Leaves per refit treelet (section 5): the hierarchy kernel lists the treelets.
+constexpr int kTreelet = 2048;
 
 // The largest x in [lo, hi) with pred(x), given pred(lo) and not pred(hi)
 // (pred monotone: true up to some point, false after it); the wave searches
@@ -463,15 +465,37 @@ __device__ __forceinline__ int64_t wave_last_true(int64_t lo, int64_t hi, int la
     return lo;
 }
 
+// Appends, for every lane with want set, one slot of the per-asset list whose
+// length counter is *counter: one atomic per wave (the wave's asset is
+// uniform), slots in lane order.  Returns the lane's slot.
+__device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool want) {
+    const uint64_t m = __ballot(want);
+    if (m == 0) return 0;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)m) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
+    base = __shfl(base, leader, 64);
+    return base + (uint32_t)__popcll(m & __lanemask_lt());
+}
+
+// Also lists the refit's work (see section 5): a node of more than kTreelet
+// leaves is a top node, listed with its parent link (by its parent, or by
+// itself at the root); a child of at most kTreelet leaves of a top node, or
+// a root of at most kTreelet leaves, roots a treelet, listed with its range
+// and parent link.  Clears the arrival counters of the refit's fallback.
 __global__ __launch_bounds__(kBlock) void karras_kernel(Batch Bt, const uint32_t* __restrict__ keys_all,
                                                         uint32_t* __restrict__ child_all,
                                                         int32_t* __restrict__ np_all,
                                                         int32_t* __restrict__ lp_all,
-                                                        int2* __restrict__ range_all) {
+                                                        int4* __restrict__ list_all,
+                                                        int2* __restrict__ top_all,
+                                                        uint32_t* __restrict__ cnt_all) {
     // each wave's window: keys [i0 - 64, i0 + 128) around its nodes [i0, i0 + 64)
     __shared__ uint32_t s_win[kBlock / 64][3 * 64];
     int64_t lb;
-    const AssetDev& As = Bt.A[block_asset(Bt, kGNode, blockIdx.x, &lb)];
+    const int a = block_asset(Bt, kGNode, blockIdx.x, &lb);
+    const AssetDev& As = Bt.A[a];
     const int64_t n = As.nhf;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t i0 = lb * kBlock + wave * 64;
@@ -553,12 +577,41 @@ __global__ __launch_bounds__(kBlock) void karras_kernel(Batch Bt, const uint32_t
     const int32_t left = lo == gamma ? ~(int32_t)gamma : (int32_t)gamma;
     const int32_t right = hi == gamma + 1 ? ~(int32_t)(gamma + 1) : (int32_t)(gamma + 1);
     child_all[As.node + i] = (uint32_t)gamma | (left < 0 ? kChildLeafL : 0u) | (right < 0 ? kChildLeafR : 0u);
-    range_all[As.node + i] = make_int2((int32_t)lo, (int32_t)hi);
     if (left < 0) leaf_parent[gamma] = (int32_t)(i << 1);
     else node_parent[gamma] = (int32_t)(i << 1);
     if (right < 0) leaf_parent[gamma + 1] = (int32_t)((i << 1) | 1);
     else node_parent[gamma + 1] = (int32_t)((i << 1) | 1);
     if (i == 0) node_parent[0] = -1;
+    // the refit's lists
+    cnt_all[As.node + i] = 0u;
+    const bool top = hi - lo + 1 > kTreelet;
+    const uint32_t cap = (uint32_t)treelet_cap(n);
+    uint32_t* ntop = &Bt.cnt[(int64_t)a * kCntSlots + kCntTop];
+    uint32_t* ntl = &Bt.cnt[(int64_t)a * kCntSlots + kCntTreelets];
+    const int32_t cref[2] = {left, right};
+    const int32_t clo[2] = {(int32_t)lo, (int32_t)(gamma + 1)}, chi[2] = {(int32_t)gamma, (int32_t)hi};
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const int32_t pp = (int32_t)((i << 1) | side);
+        const bool cbig = chi[side] - clo[side] + 1 > kTreelet;
+        const uint32_t et = wave_append(ntop, cbig);
+        if (cbig) {
+            if (et < cap) top_all[As.tl + et] = make_int2(cref[side], pp);
+            else set_status(Bt, kStInternal);
+        }
+        const bool root = top && !cbig;
+        const uint32_t e = wave_append(ntl, root);
+        if (root) {
+            if (e < cap) list_all[As.tl + e] = make_int4(cref[side], clo[side], chi[side], pp);
+            else set_status(Bt, kStInternal);
+        }
+    }
+    const uint32_t er = wave_append(top ? ntop : ntl, i == 0);
+    if (i == 0) {
+        if (er >= cap) set_status(Bt, kStInternal);
+        else if (top) top_all[As.tl + er] = make_int2(0, -1);
+        else list_all[As.tl + er] = make_int4(0, 0, (int32_t)(n - 1), -1);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -581,7 +634,6 @@ __global__ __launch_bounds__(kBlock) void karras_kernel(Batch Bt, const uint32_t
 //  d. one workgroup finishes the few nodes above the treelets from the
 //     frontier (global counters that only this workgroup touches).
 
-constexpr int kTreelet = 2048;
 constexpr int kRefitBlock = 1024;  // 16 waves: the LDS footprint allows one workgroup per CU
 constexpr int kTopBlock = 1024;
 constexpr int kTopList = 8192;
@@ -687,74 +739,6 @@ __device__ __forceinline__ void leaf_box(const Leaf& L, float box[6]) {
     }
 }
 
-// Treelet roots: nodes (internal i < n-1, or leaf ~k) of at most kTreelet
-// leaves whose parent has more (or that are the root).  Entries are
-// asset-local (ref, lo, hi, parent link).
-// Also lists the top nodes (internal nodes of more than kTreelet leaves: the
-// nodes above the treelets) with their parent links, for refit_top_kernel.
-// Appends, for every lane with want set, one slot of the per-asset list whose
-// length counter is *counter: one atomic per wave (the wave's asset is
-// uniform), slots in lane order.  Returns the lane's slot.
-__device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool want) {
-    const uint64_t m = __ballot(want);
-    if (m == 0) return 0;
-    const int lane = threadIdx.x & 63;
-    const int leader = __ffsll((long long)m) - 1;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
-    base = __shfl(base, leader, 64);
-    return base + (uint32_t)__popcll(m & __lanemask_lt());
-}
-
-// Also lists the top nodes (internal nodes of more than kTreelet leaves: the
-// nodes above the treelets) with their parent links, for refit_top_kernel,
-// and clears the arrival counters its fallback path uses.
-__global__ __launch_bounds__(kBlock) void treelet_find_kernel(Batch Bt, const int2* __restrict__ range_all,
-                                                              const int32_t* __restrict__ np_all,
-                                                              const int32_t* __restrict__ lp_all,
-                                                              int4* __restrict__ list_all,
-                                                              int2* __restrict__ top_all,
-                                                              uint32_t* __restrict__ cnt_all) {
-    int64_t lb;
-    const int a = block_asset(Bt, kGAllNode, blockIdx.x, &lb);
-    const AssetDev& As = Bt.A[a];
-    const int64_t n = As.nhf;
-    const int64_t x = lb * kBlock + threadIdx.x;
-    const bool valid = x < 2 * n - 1;
-    const int2* __restrict__ node_range = range_all + As.node;
-    int32_t ref = 0, lo = 0, hi = -1, pp = -1;
-    if (valid && x < n - 1) {
-        int2 r = node_range[x];
-        ref = (int32_t)x; lo = r.x; hi = r.y;
-        pp = np_all[As.node + x];
-        cnt_all[As.node + x] = 0u;
-    } else if (valid) {
-        int32_t k = (int32_t)(x - (n - 1));
-        ref = ~k; lo = hi = k;
-        pp = n > 1 ? lp_all[As.hf + k] : -1;
-    }
-    const bool big = valid && hi - lo + 1 > kTreelet;
-    bool root = false;
-    if (valid && !big) {
-        root = true;
-        if (pp >= 0) {
-            int2 pr = node_range[pp >> 1];
-            root = pr.y - pr.x + 1 > kTreelet;
-        }
-    }
-    const uint32_t cap = (uint32_t)treelet_cap(n);
-    const uint32_t et = wave_append(&Bt.cnt[(int64_t)a * kCntSlots + kCntTop], big);
-    if (big) {
-        if (et < cap) top_all[As.tl + et] = make_int2(ref, pp);
-        else set_status(Bt, kStInternal);
-    }
-    const uint32_t e = wave_append(&Bt.cnt[(int64_t)a * kCntSlots + kCntTreelets], root);
-    if (root) {
-        if (e < cap) list_all[As.tl + e] = make_int4(ref, lo, hi, pp);
-        else set_status(Bt, kStInternal);
-    }
-}
-
 // Workgroups take the batch's treelets in turn (the treelet prefix over the
 // assets is known on the device only).
 __global__ __launch_bounds__(kRefitBlock) void treelet_refit_kernel(
@@ -847,7 +831,7 @@ __global__ __launch_bounds__(kRefitBlock) void treelet_refit_kernel(
 // complete and its box is in p's slot.
 //
 // When the asset has at most kTopLds top nodes, the climb runs in LDS: the
-// top nodes (listed by treelet_find_kernel) get LDS slots through an LDS
+// top nodes (listed by karras_kernel) get LDS slots through an LDS
 // hash of their indices, each learns its parent's slot, the frontier's boxes
 // are copied into their parents' LDS box slots, and the climb's arrival
 // counters, parent links and boxes are LDS accesses only.  Otherwise the
@@ -1094,7 +1078,6 @@ hipError_t launch_bvh_build(const BatchHost& H, hipStream_t s) {
     int32_t* np = (int32_t*)(ws + L.node_parent);
     int32_t* lp = (int32_t*)(ws + L.leaf_parent);
     uint32_t* cnt = (uint32_t*)(ws + L.refit_cnt);
-    int2* range = (int2*)(ws + L.node_range);
     int32_t* frontier = (int32_t*)(ws + L.frontier);
     int4* tlist = (int4*)(ws + L.treelets);
     int2* top = (int2*)(ws + L.top);
@@ -1113,12 +1096,10 @@ hipError_t launch_bvh_build(const BatchHost& H, hipStream_t s) {
     // 30-bit keys take four 8-bit passes: the sorted arrays are back in keys0 / vals0
     if (H.blocks(kGNode) > 0) {
         hipLaunchKernelGGL(karras_kernel, dim3((unsigned)H.blocks(kGNode)), dim3(kBlock), 0, s, H.dev,
-                           (const uint32_t*)k0, child, np, lp, range);
+                           (const uint32_t*)k0, child, np, lp, tlist, top, cnt);
     }
     hipLaunchKernelGGL(leaf_pack_kernel, dim3((unsigned)H.blocks(kGHiF)), dim3(kBlock), 0, s, H.dev,
                        (const uint32_t*)v0, leaves);
-    hipLaunchKernelGGL(treelet_find_kernel, dim3((unsigned)H.blocks(kGAllNode)), dim3(kBlock), 0, s, H.dev,
-                       (const int2*)range, (const int32_t*)np, (const int32_t*)lp, tlist, top, cnt);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (L.t_node > 0) {
         if ((e = launch_treelet_space(H, s)) != hipSuccess) return e;
