@@ -216,6 +216,8 @@ int32_t make_plan(const Sizes* z, int n, uint32_t flags, Plan* P) {
     L.status = take(4);  // the status block is 256 bytes: counters start at 256
     L.counters = take(4 * (size_t)kCntSlots * n);
     L.gcnt = take(4 * (size_t)kGcSlots);
+    // the BVH sort's super-tile rows: zeroed with the counters before the table
+    L.sup = take(4 * 256 * (size_t)kSortPasses * (size_t)sort_super_rows(L.t_stile, n));
     L.table = take(sizeof(AssetDev) * (size_t)n + 4 * (size_t)kGridCount * (n + 1));
     L.gpf = L.table + sizeof(AssetDev) * (size_t)n;
     L.grads = take(sizeof(AssetGrad) * (size_t)n);
@@ -243,7 +245,6 @@ int32_t make_plan(const Sizes* z, int n, uint32_t flags, Plan* P) {
     L.keys1 = take(4 * (size_t)L.t_hf);
     L.vals1 = take(4 * (size_t)L.t_hf);
     L.hist = take(4 * 256 * (size_t)L.t_stile);
-    L.sup = take(4 * 256 * (size_t)kSortPasses * (size_t)sort_super_rows(L.t_stile, n));
     L.nodes = take(64 * (size_t)L.t_node);
     L.nodes_c = take(32 * (size_t)L.t_node);
     L.leaves = take(48 * (size_t)L.t_hf);

@@ -1036,7 +1036,8 @@ hipError_t launch_sort(const BatchHost& H, int which, int bits, bool* result_in_
     uint32_t* sup = (uint32_t*)(H.ws + (bwd ? L.bwd_sup : L.sup));
     const int64_t sup_pass = sort_super_rows(bwd ? L.t_btile : L.t_stile, L.n) * 256;
     if (passes > kSortPasses) return hipErrorInvalidValue;
-    hipError_t e = fill_u32(sup, 0, sup_pass * passes, s);
+    // the BVH sort's rows lie in the region every forward zeroes first
+    hipError_t e = bwd ? fill_u32(sup, 0, sup_pass * passes, s) : hipSuccess;
     if (e != hipSuccess) return e;
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;

@@ -1210,10 +1210,9 @@ hipError_t launch_view_maps(const BatchHost& H, const MapRun& m, hipStream_t s) 
 hipError_t launch_traverse(const BatchHost& H, const TravConfig& cfg, hipStream_t s) {
     const Layout& L = H.L;
     char* ws = H.ws;
-    // the queue heads (the single queue and the per-XCD ones) start at zero
-    hipError_t e = fill_u32(H.dev.gcnt + kGcQueue, 0, 1, s);
-    if (e != hipSuccess) return e;
-    if ((e = fill_u32(H.dev.gcnt + kGcXcdQueue, 0, kXcds * kXcdStride, s)) != hipSuccess) return e;
+    // the queue heads (the single queue and the per-XCD ones) start at zero:
+    // the forward zeroes every counter before its first launch, and the
+    // traversal is its only user of them
     if (L.t_tex == 0) return hipSuccess;
     TravArgs a;
     a.B = H.dev;
