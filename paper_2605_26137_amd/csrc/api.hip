@@ -117,7 +117,6 @@ int64_t grid_blocks(int g, const Sizes& z) {
         case kGLoV: return cdiv(z.nlv, 256);
         case kGHiV: return cdiv(z.nhv, 256);
         case kGHiF: return cdiv(z.nhf, 256);
-        case kGNode: return cdiv(std::max<int64_t>(z.nhf - 1, 0), 256);
         case kGSort: return cdiv(z.nhf, kSortTile);
         case kGTex: return cdiv(tex, 256);
         case kGTex3: return cdiv(3 * tex, 256);

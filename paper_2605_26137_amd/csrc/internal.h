@@ -131,7 +131,6 @@ enum GridId : int {
     kGLoV,      // lo vertices, 256 per block
     kGHiV,      // hi vertices, 256 per block
     kGHiF,      // hi triangles, 256 per block
-    kGNode,     // internal nodes, 256 per block
     kGSort,     // BVH sort tiles (kSortTile keys per block)
     kGTex,      // texels, 256 per block
     kGTex3,     // texel channels, 256 per block

@@ -479,12 +479,16 @@ __device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool want) {
     return base + (uint32_t)__popcll(m & __lanemask_lt());
 }
 
-// Also lists the refit's work (see section 5): a node of more than kTreelet
+// Also packs leaf i (its triangle's corners and index, in sorted order: the
+// leaves are independent of the hierarchy) and lists the refit's work (see
+// section 5): a node of more than kTreelet
 // leaves is a top node, listed with its parent link (by its parent, or by
 // itself at the root); a child of at most kTreelet leaves of a top node, or
 // a root of at most kTreelet leaves, roots a treelet, listed with its range
 // and parent link.  Clears the arrival counters of the refit's fallback.
 __global__ __launch_bounds__(kBlock) void karras_kernel(Batch Bt, const uint32_t* __restrict__ keys_all,
+                                                        const uint32_t* __restrict__ sorted_idx,
+                                                        Leaf* __restrict__ leaves,
                                                         uint32_t* __restrict__ child_all,
                                                         int32_t* __restrict__ np_all,
                                                         int32_t* __restrict__ lp_all,
@@ -494,12 +498,23 @@ __global__ __launch_bounds__(kBlock) void karras_kernel(Batch Bt, const uint32_t
     // each wave's window: keys [i0 - 64, i0 + 128) around its nodes [i0, i0 + 64)
     __shared__ uint32_t s_win[kBlock / 64][3 * 64];
     int64_t lb;
-    const int a = block_asset(Bt, kGNode, blockIdx.x, &lb);
+    const int a = block_asset(Bt, kGHiF, blockIdx.x, &lb);
     const AssetDev& As = Bt.A[a];
     const int64_t n = As.nhf;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t i0 = lb * kBlock + wave * 64;
     const int64_t i = i0 + lane;
+    if (i < n) {
+        const uint32_t g = sorted_idx[As.hf + i];
+        bool bad;
+        const int3 t = tri_idx(As.hi_F, g, As.nhv, &bad);
+        const float3 va = ldv(As.hi_V, t.x), vb = ldv(As.hi_V, t.y), vc = ldv(As.hi_V, t.z);
+        Leaf lf;
+        lf.a = make_float4(va.x, va.y, va.z, vb.x);
+        lf.b = make_float4(vb.y, vb.z, vc.x, vc.y);
+        lf.c = make_float4(vc.z, __int_as_float((int32_t)g), 0.f, 0.f);
+        leaves[As.hf + i] = lf;
+    }
     const uint32_t* __restrict__ keys = keys_all + As.hf;
     uint32_t* win = s_win[wave];
 #pragma unroll
@@ -704,22 +719,6 @@ __device__ __forceinline__ void write_compressed(BvhNodeC* node, uint32_t child,
     node->q = make_uint4(w[0], w[1], w[2], child);
 }
 
-__global__ __launch_bounds__(kBlock) void leaf_pack_kernel(Batch Bt, const uint32_t* __restrict__ sorted_idx,
-                                                           Leaf* __restrict__ leaves) {
-    int64_t lb;
-    const AssetDev& As = Bt.A[block_asset(Bt, kGHiF, blockIdx.x, &lb)];
-    const int64_t k = lb * kBlock + threadIdx.x;
-    if (k >= As.nhf) return;
-    uint32_t g = sorted_idx[As.hf + k];
-    bool bad;
-    int3 t = tri_idx(As.hi_F, g, As.nhv, &bad);
-    float3 a = ldv(As.hi_V, t.x), b = ldv(As.hi_V, t.y), c = ldv(As.hi_V, t.z);
-    Leaf lf;
-    lf.a = make_float4(a.x, a.y, a.z, b.x);
-    lf.b = make_float4(b.y, b.z, c.x, c.y);
-    lf.c = make_float4(c.z, __int_as_float((int32_t)g), 0.f, 0.f);
-    leaves[As.hf + k] = lf;
-}
 
 // Box of a leaf triangle, widened for the hit rule's edge tolerance: weights
 // down to -kLeafEps put the crossing inside the triangle scaled by (1 + 3
@@ -1095,12 +1094,10 @@ hipError_t launch_bvh_build(const BatchHost& H, hipStream_t s) {
     bool in1 = false;
     if ((e = launch_sort(H, kSortBvh, 30, &in1, s)) != hipSuccess) return e;
     // 30-bit keys take four 8-bit passes: the sorted arrays are back in keys0 / vals0
-    if (H.blocks(kGNode) > 0) {
-        hipLaunchKernelGGL(karras_kernel, dim3((unsigned)H.blocks(kGNode)), dim3(kBlock), 0, s, H.dev,
-                           (const uint32_t*)k0, child, np, lp, tlist, top, cnt);
+    if (H.blocks(kGHiF) > 0) {
+        hipLaunchKernelGGL(karras_kernel, dim3((unsigned)H.blocks(kGHiF)), dim3(kBlock), 0, s, H.dev,
+                           (const uint32_t*)k0, (const uint32_t*)v0, leaves, child, np, lp, tlist, top, cnt);
     }
-    hipLaunchKernelGGL(leaf_pack_kernel, dim3((unsigned)H.blocks(kGHiF)), dim3(kBlock), 0, s, H.dev,
-                       (const uint32_t*)v0, leaves);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (L.t_node > 0) {
         if ((e = launch_treelet_space(H, s)) != hipSuccess) return e;
