@@ -496,8 +496,9 @@ int32_t run_forward(Plan& P, const Opts& o, void* workspace, hipStream_t s) {
     std::vector<char> blob(L.grads - L.table, 0);
     memcpy(blob.data(), P.A.data(), sizeof(AssetDev) * (size_t)L.n);
     memcpy(blob.data() + (L.gpf - L.table), P.gpf.data(), 4 * P.gpf.size());
-    HIP_OR_FAIL(write_table(ws + L.table, blob.data(), (L.gpf - L.table) + 4 * P.gpf.size(), s));
-    HIP_OR_FAIL(fill_u32((uint32_t*)ws, 0, (int64_t)(L.table / 4), s));
+    // the table, and the status, counters and BVH sort rows before it zeroed
+    HIP_OR_FAIL(write_table(ws + L.table, blob.data(), (L.gpf - L.table) + 4 * P.gpf.size(), s, (uint32_t*)ws,
+                            (int64_t)(L.table / 4)));
     // small bakes run on one stream: there the fork and join cost more than
     // the overlap saves
     const bool one_stream = (o.flags & BAKE_FLAG_ONE_STREAM) != 0;
@@ -558,7 +559,9 @@ int32_t run_backward(Plan& P, void* workspace, uint32_t nonce, bool one_stream, 
         any_hi = any_hi || P.G[a].grad_hi_N != nullptr;
     }
     if (!any_lo && !any_hi) return BAKE_OK;
-    HIP_OR_FAIL(write_table(ws + P.L.grads, P.G.data(), sizeof(AssetGrad) * (size_t)P.L.n, s));
+    // the gradient table, and the backward sort's super-tile rows zeroed
+    HIP_OR_FAIL(write_table(ws + P.L.grads, P.G.data(), sizeof(AssetGrad) * (size_t)P.L.n, s,
+                            (uint32_t*)(ws + P.L.bwd_sup), bwd_sort_zero_words(P.L)));
     std::lock_guard<std::mutex> side_lock(g_side_mu);
     Side* side = P.L.t_hf >= kSideMinFaces && !one_stream ? side_stream(s) : nullptr;
     if (side) {
@@ -979,8 +982,9 @@ int32_t bake_visibility(const float* V, const int32_t* F, int64_t n_v, int64_t n
     std::vector<char> blob(L.grads - L.table, 0);
     memcpy(blob.data(), P.A.data(), sizeof(AssetDev));
     memcpy(blob.data() + (L.gpf - L.table), P.gpf.data(), 4 * P.gpf.size());
-    HIP_OR_FAIL(write_table(ws + L.table, blob.data(), (L.gpf - L.table) + 4 * P.gpf.size(), s));
-    HIP_OR_FAIL(fill_u32((uint32_t*)ws, 0, (int64_t)(L.table / 4), s));
+    // the table, and the status, counters and BVH sort rows before it zeroed
+    HIP_OR_FAIL(write_table(ws + L.table, blob.data(), (L.gpf - L.table) + 4 * P.gpf.size(), s, (uint32_t*)ws,
+                            (int64_t)(L.table / 4)));
     forget_saved(workspace);
     HIP_OR_FAIL(tim_record(tim, 1, s));
     HIP_OR_FAIL(launch_bvh_build(H, s));
@@ -1072,8 +1076,9 @@ int32_t bake_view_maps(const float* V, const int32_t* F, const float* UV, int64_
     std::vector<char> blob(L.grads - L.table, 0);
     memcpy(blob.data(), P.A.data(), sizeof(AssetDev));
     memcpy(blob.data() + (L.gpf - L.table), P.gpf.data(), 4 * P.gpf.size());
-    HIP_OR_FAIL(write_table(ws + L.table, blob.data(), (L.gpf - L.table) + 4 * P.gpf.size(), s));
-    HIP_OR_FAIL(fill_u32((uint32_t*)ws, 0, (int64_t)(L.table / 4), s));
+    // the table, and the status, counters and BVH sort rows before it zeroed
+    HIP_OR_FAIL(write_table(ws + L.table, blob.data(), (L.gpf - L.table) + 4 * P.gpf.size(), s, (uint32_t*)ws,
+                            (int64_t)(L.table / 4)));
     forget_saved(workspace);
     HIP_OR_FAIL(launch_lo_prep(H, s));
     HIP_OR_FAIL(launch_raster(H, s));

@@ -279,7 +279,11 @@ hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint
 
 // Copies `bytes` host bytes to device memory through by-value kernel
 // arguments (no host-to-device copy, so it can be recorded in a graph).
-hipError_t write_table(void* dst, const void* src, size_t bytes, hipStream_t s);
+// With zero_words > 0, the first launch also zeroes zero[0, zero_words).
+hipError_t write_table(void* dst, const void* src, size_t bytes, hipStream_t s, uint32_t* zero = nullptr,
+                       int64_t zero_words = 0);
+// The backward sort's super-tile rows, which its caller zeroes before the sort.
+int64_t bwd_sort_zero_words(const Layout& L);
 
 // Per-asset ray starts and 64-ray batch prefix (after the raster); treelet
 // prefix (after the treelet search).

@@ -1019,6 +1019,10 @@ inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b
 
 }  // namespace
 
+int64_t bwd_sort_zero_words(const Layout& L) {
+    return L.save ? sort_super_rows(L.t_btile, L.n) * 256 * (int64_t)kSortPasses : 0;
+}
+
 hipError_t launch_sort(const BatchHost& H, int which, int bits, bool* result_in_1, hipStream_t s,
                        hipEvent_t after_first) {
     const Layout& L = H.L;
@@ -1035,9 +1039,10 @@ hipError_t launch_sort(const BatchHost& H, int which, int bits, bool* result_in_
     uint32_t* sup = (uint32_t*)(H.ws + (bwd ? L.bwd_sup : L.sup));
     const int64_t sup_pass = sort_super_rows(bwd ? L.t_btile : L.t_stile, L.n) * 256;
     if (passes > kSortPasses) return hipErrorInvalidValue;
-    // the BVH sort's rows lie in the region every forward zeroes first
-    hipError_t e = bwd ? fill_u32(sup, 0, sup_pass * passes, s) : hipSuccess;
-    if (e != hipSuccess) return e;
+    // the super-tile rows start at zero: the BVH sort's lie in the region
+    // every forward zeroes first, the backward's are zeroed with the
+    // backward's gradient table (bwd_sort_zero_words)
+    hipError_t e = hipSuccess;
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
         uint32_t* sp = sup + sup_pass * p;
