@@ -352,19 +352,25 @@ int g_saved_next = 0;
 uint32_t g_nonce = 0;
 
 // Registers a saved forward and returns the nonce it leaves in the workspace.
-uint32_t remember_saved(const void* ws, uint64_t sig, bool one_stream) {
+// The nonce of a forward about to be enqueued (never 0).
+uint32_t reserve_nonce() {
     std::lock_guard<std::mutex> lk(g_saved_mu);
-    if (++g_nonce == 0) g_nonce = 1;  // 0 marks a forward in flight
+    if (++g_nonce == 0) g_nonce = 1;  // 0: no saved forward
+    return g_nonce;
+}
+
+// After the forward with `nonce` has been enqueued whole.
+void remember_saved(const void* ws, uint64_t sig, bool one_stream, uint32_t nonce) {
+    std::lock_guard<std::mutex> lk(g_saved_mu);
     for (int i = 0; i < kSavedSlots; ++i)
         if (g_saved[i].ws == ws) {
             g_saved[i].sig = sig;
-            g_saved[i].nonce = g_nonce;
+            g_saved[i].nonce = nonce;
             g_saved[i].one_stream = one_stream;
-            return g_nonce;
+            return;
         }
-    g_saved[g_saved_next] = Saved{ws, sig, g_nonce, one_stream};
+    g_saved[g_saved_next] = Saved{ws, sig, nonce, one_stream};
     g_saved_next = (g_saved_next + 1) % kSavedSlots;
-    return g_nonce;
 }
 
 void forget_saved(const void* ws) {
@@ -496,9 +502,14 @@ int32_t run_forward(Plan& P, const Opts& o, void* workspace, hipStream_t s) {
     std::vector<char> blob(L.grads - L.table, 0);
     memcpy(blob.data(), P.A.data(), sizeof(AssetDev) * (size_t)L.n);
     memcpy(blob.data() + (L.gpf - L.table), P.gpf.data(), 4 * P.gpf.size());
-    // the table, and the status, counters and BVH sort rows before it zeroed
+    // the table, and the status, counters and BVH sort rows before it zeroed;
+    // with BAKE_FLAG_SAVE the seal takes this forward's nonce in the same
+    // launch (the backward checks it on the device: any later forward on the
+    // workspace overwrites it, and the stream orders it before the backward)
+    const bool save = (o.flags & BAKE_FLAG_SAVE) != 0;
+    const uint32_t nonce = save ? reserve_nonce() : 0u;
     HIP_OR_FAIL(write_table(ws + L.table, blob.data(), (L.gpf - L.table) + 4 * P.gpf.size(), s, (uint32_t*)ws,
-                            (int64_t)(L.table / 4)));
+                            (int64_t)(L.table / 4), save ? (int64_t)(L.gcnt / 4 + kGcSeal) : -1, nonce));
     // small bakes run on one stream: there the fork and join cost more than
     // the overlap saves
     const bool one_stream = (o.flags & BAKE_FLAG_ONE_STREAM) != 0;
@@ -537,13 +548,8 @@ int32_t run_forward(Plan& P, const Opts& o, void* workspace, hipStream_t s) {
     bool any_rgb8 = false;
     for (int a = 0; a < L.n; ++a) any_rgb8 = any_rgb8 || P.A[a].out_rgb8 != nullptr;
     if (any_rgb8) HIP_OR_FAIL(launch_rgb8(H, s));
-    if (o.flags & BAKE_FLAG_SAVE) {
-        // seal the saved state: the backward checks this nonce on the device
-        const uint32_t nonce = remember_saved(workspace, P.sig, one_stream);
-        HIP_OR_FAIL(fill_u32(H.dev.gcnt + kGcSeal, nonce, 1, s));
-    } else {
-        forget_saved(workspace);
-    }
+    if (save) remember_saved(workspace, P.sig, one_stream, nonce);
+    else forget_saved(workspace);
     HIP_OR_FAIL(tim_record(tim, 5, s));
     tim_commit(tim);
     return BAKE_OK;

@@ -168,7 +168,7 @@ constexpr int kCntTop = 10;      // refit top nodes (internal nodes above the tr
 constexpr int kCntSlots = 16;
 // Batch counter slots.
 constexpr int kGcQueue = 0;  // traversal work queue head
-constexpr int kGcSeal = 1;   // nonce of the last completed forward (0 while one runs)
+constexpr int kGcSeal = 1;   // nonce of the last forward with BAKE_FLAG_SAVE (written as it starts; 0 after one without)
 constexpr int kXcds = 8;         // XCDs of an MI355X: each has its own L2
 constexpr int kXcdStride = 32;   // one 128-byte line per XCD queue head
 constexpr int kGcXcdQueue = 32;  // kXcds traversal queue heads, kXcdStride apart
@@ -279,9 +279,10 @@ hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint
 
 // Copies `bytes` host bytes to device memory through by-value kernel
 // arguments (no host-to-device copy, so it can be recorded in a graph).
-// With zero_words > 0, the first launch also zeroes zero[0, zero_words).
+// With zero_words > 0, the first launch also zeroes zero[0, zero_words),
+// except word set_idx, which takes set_val.
 hipError_t write_table(void* dst, const void* src, size_t bytes, hipStream_t s, uint32_t* zero = nullptr,
-                       int64_t zero_words = 0);
+                       int64_t zero_words = 0, int64_t set_idx = -1, uint32_t set_val = 0);
 // The backward sort's super-tile rows, which its caller zeroes before the sort.
 int64_t bwd_sort_zero_words(const Layout& L);
 

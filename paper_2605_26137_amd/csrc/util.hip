@@ -166,11 +166,14 @@ __global__ __launch_bounds__(256) void table_chunk_kernel(uint32_t* dst, TableCh
     for (uint32_t i = threadIdx.x; i < c.words; i += 256) dst[i] = c.w[i];
 }
 
-// The first chunk, and zeroes of a region beside it (one launch for both).
-__global__ __launch_bounds__(256) void table_zero_kernel(uint32_t* dst, TableChunk c, uint32_t* z, int64_t zwords) {
+// The first chunk, and zeroes of a region beside it (one launch for both):
+// word set_idx of the region takes set_val instead.
+__global__ __launch_bounds__(256) void table_zero_kernel(uint32_t* dst, TableChunk c, uint32_t* z, int64_t zwords,
+                                                         int64_t set_idx, uint32_t set_val) {
     if (blockIdx.x == 0)
         for (uint32_t i = threadIdx.x; i < c.words; i += 256) dst[i] = c.w[i];
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < zwords; i += (int64_t)gridDim.x * 256) z[i] = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < zwords; i += (int64_t)gridDim.x * 256)
+        z[i] = i == set_idx ? set_val : 0u;
 }
 
 // Exclusive prefix over the assets of a per-asset value, by one workgroup of
@@ -287,7 +290,8 @@ hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint
     return hipGetLastError();
 }
 
-hipError_t write_table(void* dst, const void* src, size_t bytes, hipStream_t s, uint32_t* zero, int64_t zero_words) {
+hipError_t write_table(void* dst, const void* src, size_t bytes, hipStream_t s, uint32_t* zero, int64_t zero_words,
+                       int64_t set_idx, uint32_t set_val) {
     const uint32_t* w = (const uint32_t*)src;
     const size_t words = (bytes + 3) / 4;  // callers pass 4-byte multiples
     for (size_t o = 0; o < words || (o == 0 && zero_words > 0); o += kChunkWords) {
@@ -297,7 +301,8 @@ hipError_t write_table(void* dst, const void* src, size_t bytes, hipStream_t s, 
         memcpy(c.w, w + o, 4 * (size_t)c.words);
         if (o == 0 && zero_words > 0) {
             const unsigned g = (unsigned)std::min<int64_t>((zero_words + 255) / 256, 1024);
-            hipLaunchKernelGGL(table_zero_kernel, dim3(g), dim3(256), 0, s, (uint32_t*)dst, c, zero, zero_words);
+            hipLaunchKernelGGL(table_zero_kernel, dim3(g), dim3(256), 0, s, (uint32_t*)dst, c, zero, zero_words, set_idx,
+                               set_val);
         } else {
             hipLaunchKernelGGL(table_chunk_kernel, dim3(1), dim3(256), 0, s, (uint32_t*)dst + o, c);
         }
