@@ -127,6 +127,19 @@ def test_sq_loss(B):
     assert np.array_equal(grad.cpu().numpy(), (2.0 * (m - tg)).astype(np.float32))
 
 
+@pytest.mark.parametrize("n,off", [(12289, 0), (4097, 0), (3, 0), (8195, 1), (4096 * 5 + 2, 2)])
+def test_sq_loss_ragged_and_unaligned(B, n, off):
+    """Counts that are not a multiple of 4 or of the 4096-value block tile, and
+    arrays that start off a 16-byte boundary (the 4-byte path)."""
+    rng = np.random.default_rng(n)
+    m = rng.normal(size=n + off).astype(np.float32)
+    tg = rng.normal(size=n + off).astype(np.float32)
+    loss, grad = B.sq_loss(torch.from_numpy(m).cuda()[off:], torch.from_numpy(tg).cuda()[off:])
+    d = m[off:].astype(np.float64) - tg[off:]
+    assert abs(float(loss.item()) - (d * d).sum()) <= 1e-5 * (d * d).sum()
+    assert np.array_equal(grad.cpu().numpy(), (2.0 * (m[off:] - tg[off:])).astype(np.float32))
+
+
 def test_autograd_function(B):
     a = make_config(1)
     hi_V, hi_F, hi_N, lo_V, lo_F, lo_UV = B.to_device(a)
