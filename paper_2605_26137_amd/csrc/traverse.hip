@@ -809,9 +809,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(COUNT ? 1
 // up u = r x f; pixel (i, j) of
 // the res x res image looks along normalise(f + x r + y u) with x = ((j +
 // 1/2) 2 / res - 1) tan_half and y = (1 - (i + 1/2) 2 / res) tan_half.  Each
-// wave takes 64 consecutive pixels of one view (grid-stride over the
-// (view, 64-pixel batch) items), finds every ray's first hit on the half-line
-// (0, t_far] with the bake's hit rule and flags the hit face visible.
+// wave takes an 8 x 8 pixel tile of one view (grid-stride over the (view,
+// tile) items; lanes past the image edge idle), so its 64 rays leave the eye
+// in a square bundle and walk similar paths, finds every ray's first hit on
+// the half-line (0, t_far] with the bake's hit rule and flags the hit face
+// visible.
 struct VisArgs {
     TravArgs t;
     const float* eyes;
@@ -872,14 +874,17 @@ __global__ __launch_bounds__(BLOCK) void visibility_kernel(VisArgs a) {
     st.stride = a.t.spill_lanes;
     st.col = (int64_t)blockIdx.x * BLOCK + tid;
     const int64_t px = (int64_t)a.res * a.res;
-    const int64_t bpv = (px + 63) / 64;
-    const int64_t items = bpv * a.n_views;
+    const int64_t tpr = ((int64_t)a.res + 7) / 8;  // 8 x 8 tiles per image row
+    const int64_t tpv = tpr * tpr;                 // tiles per view
+    const int64_t items = tpv * a.n_views;
     const int64_t nwaves = ((int64_t)gridDim.x * BLOCK) >> 6;
     unsigned long long c_box = 0, c_tri = 0, c_iter = 0;
     for (int64_t it = ((int64_t)blockIdx.x * BLOCK + tid) >> 6; it < items; it += nwaves) {
-        const int32_t v = (int32_t)(it / bpv);
-        const int64_t p = (it - (int64_t)v * bpv) * 64 + lane;
-        const bool valid = p < px;
+        const int32_t v = (int32_t)(it / tpv);
+        const int64_t t = it - (int64_t)v * tpv, ty = t / tpr, tx = t - ty * tpr;
+        const int64_t row = ty * 8 + (lane >> 3), col = tx * 8 + (lane & 7);
+        const bool valid = row < a.res && col < a.res;
+        const int64_t p = valid ? row * a.res + col : 0;
         RayT R;
         {
             float3 e, d, f;
@@ -1166,8 +1171,8 @@ hipError_t launch_visibility_rays(const BatchHost& H, const VisRun& v, hipStream
     if (e != hipSuccess) return e;
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
     if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kBlk, 0)) != hipSuccess) return e;
-    const int64_t px = (int64_t)v.res * v.res;
-    const int64_t waves = ((px + 63) / 64) * v.n_views;
+    const int64_t tpr = ((int64_t)v.res + 7) / 8;
+    const int64_t waves = tpr * tpr * v.n_views;  // one 8 x 8 pixel tile per wave item
     int64_t blocks = (int64_t)cus * std::max(per, 1);
     blocks = std::min(blocks, (waves + kBlk / 64 - 1) / (kBlk / 64));  // no block without an item
     blocks = std::min(blocks, v.spill_lanes / kBlk);                    // every lane has a spill column
