@@ -896,23 +896,33 @@ __global__ __launch_bounds__(BLOCK) void visibility_kernel(VisArgs a) {
         reset_best(best, tv.max_dist);
         st.sp = st.lo = 0;
         int32_t steps = 0;
-        for (;;) {
-            const uint64_t at_node = __ballot(node >= 0);
-            const uint64_t at_leaf = __ballot(node < 0 && node != kEmpty);
-            if ((at_node | at_leaf) == 0) break;
-            if (COUNT) ++c_iter;
-            if (__popcll(at_leaf) >= __popcll(at_node)) {
-                if (node < 0 && node != kEmpty)
-                    node = tri_step<BLOCK, STACK, COUNT, kQFirst>(tv, node, R, best, st, tid, c_tri);
-                else continue;
-            } else if (node >= 0) {
-                node = node_step<BLOCK, STACK, COUNT, kQFirst>(tv, B.status, node, R, best, st, tid, c_box);
-            } else {
-                continue;
-            }
+        // a lane past the step bound (only a malformed tree gets there) stops
+        auto capped = [&]() {
             if (++steps > tv.step_cap) {
                 set_status(B, kStInternal);
                 node = kEmpty;
+            }
+        };
+        // the balanced loop as nested loops, as in the bake's wave batches:
+        // internal-node trips while more busy lanes are at an internal node
+        // than at a leaf, then one leaf trip
+        for (;;) {
+            uint64_t at_leaf;
+            for (;;) {
+                const uint64_t at_node = __ballot(node >= 0);
+                at_leaf = __ballot(node < 0 && node != kEmpty);
+                if (__popcll(at_leaf) >= __popcll(at_node)) break;
+                if (COUNT) ++c_iter;
+                if (node >= 0) {
+                    node = node_step<BLOCK, STACK, COUNT, kQFirst>(tv, B.status, node, R, best, st, tid, c_box);
+                    capped();
+                }
+            }
+            if (at_leaf == 0) break;  // and no lane at a node: the tile is done
+            if (COUNT) ++c_iter;
+            if (node < 0 && node != kEmpty) {
+                node = tri_step<BLOCK, STACK, COUNT, kQFirst>(tv, node, R, best, st, tid, c_tri);
+                capped();
             }
         }
         if (valid) {
