@@ -862,7 +862,7 @@ __device__ __forceinline__ void pixel_ray(const VisArgs& a, int32_t v, int64_t p
 }
 
 template <int BLOCK, int STACK, bool COUNT>
-__global__ __launch_bounds__(BLOCK) void visibility_kernel(VisArgs a) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(COUNT ? 1 : 7))) void visibility_kernel(VisArgs a) {
     __shared__ int32_t stk[STACK][BLOCK];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
