@@ -287,7 +287,7 @@ hipError_t write_table(void* dst, const void* src, size_t bytes, hipStream_t s, 
 int64_t bwd_sort_zero_words(const Layout& L);
 
 // Per-asset ray starts and 64-ray batch prefix (after the raster); treelet
-// prefix (after the treelet search).
+// prefix (after the hierarchy kernel has listed the treelets).
 hipError_t launch_ray_spaces(const BatchHost& H, hipStream_t s);
 hipError_t launch_treelet_space(const BatchHost& H, hipStream_t s);
 

@@ -6,14 +6,16 @@
 //   3. stable LSD radix sort of (code, index), 8-bit digits, LDS-ranked with
 //      wave64 ballots, so equal codes keep ascending index order,
 //   4. Karras hierarchy: every internal node finds its key range and split
-//      from common-prefix lengths (code, extended by the index on equal codes),
-//   5. leaf packing (vertices copied bit-exactly, original index kept) and a
-//      bottom-up refit: per internal node an arrival counter; the second
-//      arriving child unions both boxes and continues upward.  min/max is
-//      exact, so the boxes do not depend on arrival order.
+//      from common-prefix lengths (code, extended by the index on equal codes);
+//      the same kernel packs the leaves (vertices copied bit-exactly, original
+//      index kept) and lists the refit's treelets and the nodes above them,
+//   5. bottom-up refit in LDS, treelet by treelet, then the nodes above the
+//      treelets: the second arriving child of a node unions both boxes and
+//      continues upward (min/max is exact, so the boxes do not depend on
+//      arrival order); the nodes are then written compressed (32 B each).
 // In a batch every asset gets its own tree over its own bounds; sort tiles
-// never straddle two assets, and one batch-wide scan of the digit counts
-// (asset-major) gives every key its place in the concatenated key arrays.
+// never straddle two assets, and each tile places its keys from its asset's
+// per-tile and per-super-tile digit counts (section 3).
 #include <algorithm>
 #include <utility>
 
@@ -636,18 +638,19 @@ __global__ __launch_bounds__(kBlock) void karras_kernel(Batch Bt, const uint32_t
 // The refit avoids device-scope ordering per node (an acquire/release at
 // device scope costs an L2 write-back and invalidation across the XCDs, and
 // chains of them serialise the upper levels):
-//  a. leaf packing: one thread per sorted leaf;
-//  b. treelets: the maximal subtrees with at most kTreelet leaves.  A Karras
-//     node covers a contiguous leaf range [lo, hi] and its index lies in that
-//     range, so a treelet's internal nodes have indices in [lo, hi] too;
-//  c. one workgroup per treelet loads the parent links of [lo, hi] into LDS
+//  a. treelets: the maximal subtrees with at most kTreelet leaves (listed by
+//     the hierarchy kernel).  A Karras node covers a contiguous leaf range
+//     [lo, hi] and its index lies in that range, so a treelet's internal
+//     nodes have indices in [lo, hi] too;
+//  b. one workgroup per treelet loads the parent links of [lo, hi] into LDS
 //     and refits bottom-up: each child leaves its box in its own LDS slot of
 //     the parent (one slot per side) and counts its arrival in LDS; the second
-//     arrival reads the sibling's slot, writes the node and continues.  The
-//     treelet root's box goes to its parent's slot and the parent is appended
-//     to a frontier;
-//  d. one workgroup finishes the few nodes above the treelets from the
-//     frontier (global counters that only this workgroup touches).
+//     arrival reads the sibling's slot and continues.  The treelet root's box
+//     goes to its parent's slot and the parent is appended to a frontier; the
+//     workgroup then writes the treelet's nodes compressed, in parallel;
+//  c. one workgroup per asset finishes the nodes above the treelets from the
+//     frontier: in LDS when there are at most kTopLds of them, else with
+//     global counters that only this workgroup touches.
 
 constexpr int kRefitBlock = 1024;  // 16 waves: the LDS footprint allows one workgroup per CU
 constexpr int kTopBlock = 1024;

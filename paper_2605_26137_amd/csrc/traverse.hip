@@ -7,8 +7,9 @@
 //
 // Traversal (two launch shapes, same per-ray arithmetic and results):
 //   * wave batches (default): persistent waves take (asset, 64-ray batch)
-//     items of the batch's face-ordered ray lists from one device work queue,
-//     trace the 64 rays together in a tight loop and encode when the whole
+//     items of the batch's face-ordered ray lists from device work queues
+//     (one per XCD, each over a contiguous eighth of the items first: see
+//     next_item), trace the 64 rays together in a tight loop and encode when the whole
 //     batch is done: neighbouring texels of one face walk nearly the same
 //     nodes, and the asset is uniform across the wave.  The loop's trips are
 //     all-internal-node or all-leaf, a leaf trip being taken once at least
