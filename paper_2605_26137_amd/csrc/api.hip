@@ -223,6 +223,7 @@ int32_t make_plan(const Sizes* z, int n, uint32_t flags, Plan* P) {
     L.ray_pf = take(4 * (size_t)(n + 1));
     L.rb_pf = take(4 * (size_t)(n + 1));
     L.tl_pf = take(4 * (size_t)(n + 1));
+    L.bt_pf = take(4 * (size_t)(n + 1));
     L.lo_n = take(16 * (size_t)L.t_lv);
     L.lo_deg = take(4 * (size_t)L.t_lv);
     L.lo_off = take(4 * (size_t)(L.t_lv + 1));
@@ -327,6 +328,7 @@ BatchHost host_view(const Plan& P, char* ws) {
     H.dev.ray_pf = (const uint32_t*)(ws + L.ray_pf);
     H.dev.rb_pf = (const uint32_t*)(ws + L.rb_pf);
     H.dev.tl_pf = (const uint32_t*)(ws + L.tl_pf);
+    H.dev.bt_pf = (const uint32_t*)(ws + L.bt_pf);
     H.dev.cnt = (uint32_t*)(ws + L.counters);
     H.dev.gcnt = (uint32_t*)(ws + L.gcnt);
     H.dev.status = (uint32_t*)(ws + L.status);

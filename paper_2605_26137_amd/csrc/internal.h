@@ -169,6 +169,7 @@ constexpr int kCntSlots = 16;
 // Batch counter slots.
 constexpr int kGcQueue = 0;  // traversal work queue head
 constexpr int kGcSeal = 1;   // nonce of the last forward with BAKE_FLAG_SAVE (written as it starts; 0 after one without)
+constexpr int kGcBwdTiles = 2;  // backward sort tiles that hold pairs, over the batch (written after the raster)
 constexpr int kXcds = 8;         // XCDs of an MI355X: each has its own L2
 constexpr int kXcdStride = 32;   // one 128-byte line per XCD queue head
 constexpr int kGcXcdQueue = 32;  // kXcds traversal queue heads, kXcdStride apart
@@ -182,6 +183,7 @@ struct Batch {
     const uint32_t* ray_pf; // [n + 1] first ray of each asset (written after the raster)
     const uint32_t* rb_pf;  // [n + 1] 64-ray batches before each asset
     const uint32_t* tl_pf;  // [n + 1] treelets before each asset
+    const uint32_t* bt_pf;  // [n + 1] backward sort tiles holding pairs before each asset (after the raster)
     uint32_t* cnt;          // [n][kCntSlots]
     uint32_t* gcnt;         // [kGcSlots]
     uint32_t* status;       // status word, OR over the batch
@@ -222,7 +224,7 @@ __device__ __forceinline__ void set_status(const Batch& B, uint32_t bits) { atom
 // Host description of a batch: asset table, grid prefix tables and the
 // workspace layout.
 struct Layout {
-    size_t status, counters, gcnt, table, grads, gpf, ray_pf, rb_pf, tl_pf;
+    size_t status, counters, gcnt, table, grads, gpf, ray_pf, rb_pf, tl_pf, bt_pf;
     size_t lo_n, lo_deg, lo_off, lo_cur, lo_adj;  // lo vertex normals + vertex->face CSR
     size_t face_t, face_uv, face_cnt, face_off;   // per lo face
     size_t scan_tmp;                              // block sums of the scans
@@ -286,8 +288,9 @@ hipError_t write_table(void* dst, const void* src, size_t bytes, hipStream_t s, 
 // The backward sort's super-tile rows, which its caller zeroes before the sort.
 int64_t bwd_sort_zero_words(const Layout& L);
 
-// Per-asset ray starts and 64-ray batch prefix (after the raster); treelet
-// prefix (after the hierarchy kernel has listed the treelets).
+// Per-asset ray starts, 64-ray batch prefix and backward sort tile prefix
+// (after the raster); treelet prefix (after the hierarchy kernel has listed
+// the treelets).
 hipError_t launch_ray_spaces(const BatchHost& H, hipStream_t s);
 hipError_t launch_treelet_space(const BatchHost& H, hipStream_t s);
 

@@ -207,10 +207,19 @@ struct SortTile {
     int64_t start, count, hbase, sbase, lt;
 };
 
+// BWD blocks map onto the tiles that hold pairs (the prefix the forward wrote
+// after its raster); the grid covers the capacity, and its blocks past the
+// pairs' tiles have exited already (bwd_block_idle).
 template <bool BWD>
 __device__ __forceinline__ SortTile sort_tile(const Batch& Bt, int64_t blk) {
     SortTile T;
-    const int a = block_asset(Bt, BWD ? kGBwdSort : kGSort, blk, &T.lt);
+    int a;
+    if (BWD) {
+        a = upper_asset(Bt.bt_pf, Bt.n, blk);
+        T.lt = blk - Bt.bt_pf[a];
+    } else {
+        a = block_asset(Bt, kGSort, blk, &T.lt);
+    }
     const AssetDev& As = Bt.A[a];
     const int64_t tile_base = BWD ? As.btile : As.stile;
     if (BWD) {
@@ -225,12 +234,20 @@ __device__ __forceinline__ SortTile sort_tile(const Batch& Bt, int64_t blk) {
     return T;
 }
 
+// A backward sort block with nothing to do: a workspace no longer holding the
+// saved forward, or a block past the tiles that hold pairs.  Both words lie
+// in one line of the batch counters, so an idle block exits after one load
+// latency.
+__device__ __forceinline__ bool bwd_block_idle(const Batch& Bt) {
+    return !sealed(Bt) || blockIdx.x >= Bt.gcnt[kGcBwdTiles];
+}
+
 template <bool BWD>
 __global__ __launch_bounds__(kSortBlock) void radix_hist_kernel(Batch Bt, const uint32_t* __restrict__ keys,
                                                                 int shift, uint32_t* __restrict__ hist,
                                                                 uint32_t* __restrict__ sup) {
     __shared__ uint32_t h[256];
-    if (BWD && !sealed(Bt)) return;
+    if (BWD && bwd_block_idle(Bt)) return;
     const SortTile T = sort_tile<BWD>(Bt, blockIdx.x);
     if (T.lt * kSortTile >= T.count) return;  // an empty capacity tile (uniform)
     if (threadIdx.x < 256) h[threadIdx.x] = 0;
@@ -283,7 +300,7 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter_kernel(Batch Bt, con
     __shared__ uint16_t wcnt[kSortRounds][kSortWaves][256];
     static_assert(kSortTile <= 65535, "tile positions are kept in 16 bits");
     static_assert(kSortBlock == 4 * 256 && kSortRounds * kSortWaves == 64, "one scan thread per (round, digit)");
-    if (BWD && !sealed(Bt)) return;
+    if (BWD && bwd_block_idle(Bt)) return;
     const SortTile T = sort_tile<BWD>(Bt, blockIdx.x);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t base = T.lt * kSortTile;

@@ -206,28 +206,36 @@ __device__ void asset_prefix(uint32_t v, int a, int n, uint32_t* out, uint32_t* 
 // After the raster: the ray list is the concatenation of the assets' face-
 // ordered lists, and the exclusive scan of the per-face counts (total at
 // index t_lf) gives every face's first ray.
+// Also the prefix of the backward sort's tiles that will hold pairs (three
+// per ray, kSortTile per tile) and their total beside the seal: the backward
+// sort's grid covers every asset's capacity, and its blocks past the total
+// exit on that one word.
 __global__ __launch_bounds__(kPrefixBlock) void ray_spaces_kernel(Batch B, const uint32_t* face_off,
                                                                  int64_t t_lf, uint32_t* ray_pf,
-                                                                 uint32_t* rb_pf) {
+                                                                 uint32_t* rb_pf, uint32_t* bt_pf) {
     __shared__ uint32_t lw[kPrefixBlock / 64];
-    __shared__ uint32_t carry;
-    if (threadIdx.x == 0) carry = 0;
+    __shared__ uint32_t carry, carry_t;
+    if (threadIdx.x == 0) carry = carry_t = 0;
     __syncthreads();
     for (int c = 0; c < B.n; c += kPrefixBlock) {
         const int a = c + threadIdx.x;
-        uint32_t nb = 0;
+        uint32_t nb = 0, nt = 0;
         if (a < B.n) {
             const AssetDev& A = B.A[a];
             const uint32_t start = face_off[A.lf], end = face_off[A.lf + A.nlf];
             ray_pf[a] = start;
             B.cnt[(int64_t)a * kCntSlots + kCntRays] = end - start;
             nb = (end - start + 63u) / 64u;
+            nt = (uint32_t)((3 * (uint64_t)(end - start) + kSortTile - 1) / kSortTile);
         }
         asset_prefix(nb, a, B.n, rb_pf, &carry, lw);
+        asset_prefix(nt, a, B.n, bt_pf, &carry_t, lw);
     }
     if (threadIdx.x == 0) {
         ray_pf[B.n] = face_off[t_lf];
         rb_pf[B.n] = carry;
+        bt_pf[B.n] = carry_t;
+        B.gcnt[kGcBwdTiles] = carry_t;
     }
 }
 
@@ -316,7 +324,7 @@ hipError_t launch_ray_spaces(const BatchHost& H, hipStream_t s) {
     const Layout& L = H.L;
     hipLaunchKernelGGL(ray_spaces_kernel, dim3(1), dim3(kPrefixBlock), 0, s, H.dev,
                        (const uint32_t*)(H.ws + L.face_off), L.t_lf, (uint32_t*)(H.ws + L.ray_pf),
-                       (uint32_t*)(H.ws + L.rb_pf));
+                       (uint32_t*)(H.ws + L.rb_pf), (uint32_t*)(H.ws + L.bt_pf));
     return hipGetLastError();
 }
 
