@@ -50,6 +50,13 @@ def _empty_hi_asset():
                  res=64, max_dist=0.1)
 
 
+def _rayless_asset():
+    """A low-poly triangle whose UV triangle covers no texel centre: no rays."""
+    a = _single_triangle_asset()
+    uv = np.array([[[0.501, 0.501], [0.503, 0.501], [0.501, 0.503]]], np.float32)
+    return Asset("noray", a.hi_V, a.hi_F, a.hi_N, a.lo_V, a.lo_F, uv, res=32, max_dist=0.1)
+
+
 def _mixed_assets():
     """Uneven small batch: generated assets of different sizes and atlases,
     the ripple sphere, a single triangle and an asset without high-poly."""
@@ -120,6 +127,34 @@ def test_batch_backward_equals_single(B):
     torch.cuda.synchronize()
     _check_batch_equals_single(B, batch, assets, singles, grads=True)
     assert any(np.abs(s["glo"]).sum() > 0 for s in singles)
+
+
+def test_batch_backward_with_rayless_assets(B):
+    """Assets without a single ray before, between and after assets with rays:
+    the per-asset prefix of the backward sort's tiles has empty ranges, and
+    the sort's grid (sized for every asset's capacity) is mostly idle blocks.
+    Forward and backward equal the single bakes bit for bit."""
+    gen = make_batch_assets(3, seed=13, hi_range=(2_000, 30_000), lo_range=(80, 800),
+                            res_choices=(64, 128), max_dist=0.1)
+    assets = [_rayless_asset(), gen[0], _rayless_asset(), _rayless_asset(), gen[1], _rayless_asset(), gen[2],
+              _rayless_asset()]
+    rng = np.random.default_rng(12)
+    gms = [torch.from_numpy(rng.normal(size=(a.res, a.res, 3)).astype(np.float32)).cuda() for a in assets]
+    singles = [_single(B, a, dilate=0, save=True, grad_map=g) for a, g in zip(assets, gms)]
+    assert [s["rays"] == 0 for s in singles] == [a.name == "noray" for a in assets]
+    batch = B.BakeBatch([_inputs(B, a) for a in assets], save=True, dilate_passes=0, rgb8=True)
+    for i, g in enumerate(gms):
+        batch.grad_maps[i].copy_(g)
+    batch.forward()
+    batch.backward()
+    torch.cuda.synchronize()
+    assert batch.status() == 0
+    _check_batch_equals_single(B, batch, assets, singles, grads=True)
+    for a, s in zip(assets, singles):
+        if a.name == "noray":
+            assert not np.any(s["glo"]) and not np.any(s["ghi"])
+        else:
+            assert np.abs(s["glo"]).sum() > 0
 
 
 def test_batch_order_does_not_matter(B):
