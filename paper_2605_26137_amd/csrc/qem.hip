@@ -1083,8 +1083,13 @@ hipError_t qem_simplify_run(const QemLayout& L, char* ws, const float* V, const 
         QEM_TRY(hipEventRecord(tev[2], s));
     }
     QEM_TRY(set_up(L, p, V, F, s));
-    uint32_t h[kQcSlots];
-    QEM_TRY(hipMemcpyAsync(h, p.cnt, sizeof h, hipMemcpyDeviceToHost, s));
+    // the round counts come back every round: into pinned host memory (one
+    // buffer per calling thread, kept for the process), which the copy
+    // reaches directly instead of through a staging buffer
+    static thread_local uint32_t* h = nullptr;
+    if (!h) QEM_TRY(hipHostMalloc((void**)&h, 4 * (kQcSlots + 1), hipHostMallocDefault));
+    constexpr size_t kCountBytes = 4 * kQcSlots;
+    QEM_TRY(hipMemcpyAsync(h, p.cnt, kCountBytes, hipMemcpyDeviceToHost, s));
     QEM_TRY(hipStreamSynchronize(s));
     *status = h[kQcStatus];
     if (h[kQcStatus]) return hipSuccess;
@@ -1128,7 +1133,7 @@ hipError_t qem_simplify_run(const QemLayout& L, char* ws, const float* V, const 
         hipLaunchKernelGGL(qem_face_scatter_kernel, dim3(blocks_for(live)), dim3(kQB), 0, s, p.F2, live, p.keep,
                            p.koff, p.F);
         QEM_TRY(hipGetLastError());
-        QEM_TRY(hipMemcpyAsync(h, p.cnt, sizeof h, hipMemcpyDeviceToHost, s));
+        QEM_TRY(hipMemcpyAsync(h, p.cnt, kCountBytes, hipMemcpyDeviceToHost, s));
         QEM_TRY(hipStreamSynchronize(s));
         live = h[kQcOut];
         if (times_ms) {
@@ -1158,10 +1163,9 @@ hipError_t qem_simplify_run(const QemLayout& L, char* ws, const float* V, const 
             QEM_TRY(hipGetLastError());
             hipLaunchKernelGGL(qem_frenum_kernel, dim3(blocks_for(live)), dim3(kQB), 0, s, p.F, live, vid);
             QEM_TRY(hipGetLastError());
-            uint32_t nvn = 0;
-            QEM_TRY(hipMemcpyAsync(&nvn, p.cnt + kQcVerts, 4, hipMemcpyDeviceToHost, s));
+            QEM_TRY(hipMemcpyAsync(h + kQcSlots, p.cnt + kQcVerts, 4, hipMemcpyDeviceToHost, s));
             QEM_TRY(hipStreamSynchronize(s));
-            nv = nvn;
+            nv = h[kQcSlots];
             std::swap(p.P, p.P2);
             std::swap(p.Q, p.Q2);
         }
@@ -1178,7 +1182,7 @@ hipError_t qem_simplify_run(const QemLayout& L, char* ws, const float* V, const 
     QEM_TRY(hipGetLastError());
     hipLaunchKernelGGL(qem_fout_kernel, dim3(blocks_for(live)), dim3(kQB), 0, s, p.F, live, vid, F_out);
     QEM_TRY(hipGetLastError());
-    QEM_TRY(hipMemcpyAsync(h, p.cnt, sizeof h, hipMemcpyDeviceToHost, s));
+    QEM_TRY(hipMemcpyAsync(h, p.cnt, kCountBytes, hipMemcpyDeviceToHost, s));
     if (times_ms) QEM_TRY(hipEventRecord(tev[3], s));
     QEM_TRY(hipStreamSynchronize(s));
     if (times_ms) QEM_TRY(hipEventElapsedTime(&times_ms[1], tev[2], tev[3]));
