@@ -27,7 +27,7 @@ quantum w = max_dist 2^-20, winner min (floor(|t| / w), index)).
 
 ``compare_plain`` measures the GPU against the plain rule and reports it:
 the agreement rate, and every disagreement must be a tie in the sense of
-the benchmark spec's accuracy bar: |t| within 1e-6 max_dist of the plain nearest hit,
+the bake's accuracy bar: |t| within 1e-6 max_dist of the plain nearest hit,
 the GPU's triangle crossed within 32 FP32 ulps of the crossing point, and the
 baked normals within 0.05 degrees (a GPU miss only at the range end).
 

@@ -10,7 +10,7 @@ robust: every weight >= -EDGE_EPS; the winner minimises (floor(|t| / w), index)
 
 The tolerance and the quantum are a convention, not a reading of the paper's
 nearest-hit query (Sec. 6.4): the workloads test that the robust rule departs
-from the plain one only by ties in the benchmark spec's sense -- |t| within
+from the plain one only by ties in the accuracy bar's sense -- |t| within
 1e-6 max_dist and the same baked normal within 0.05 degrees.
 """
 import math
